@@ -1,0 +1,259 @@
+"""Seeded synthetic lidar-like workloads (inputs only; none of the method's arithmetic).
+
+The paper's datasets (ToySim, Intel Map, EviLOG; Sec. IV, dataset summary table) are not
+available, so every workload here is generated: a square world with axis-aligned rectangles and
+circles, one or more sensor poses, beams at evenly spaced angles, ranges ray-cast exactly and
+perturbed by Gaussian noise.  Beam end points are labelled occupied (psi = 1) and points drawn
+uniformly along each beam are labelled empty (psi = 0), the labelling heuristic of Sec. III-B
+(data format and preprocessing).
+
+The phase basis Theta is also drawn here: it is the one random draw the method makes
+(initialisation of the axis vectors, Sec. III-B), so it is passed to both the oracle and the GPU
+library as an input.  Theta[k] = theta_k / l with theta_k ~ U[-pi, pi] per axis for
+k = 1..D/2-1, mirrored as Theta[D-k] = -Theta[k], and Theta[0] = Theta[D/2] = 0 so that every
+fractional power of the axis spectra is the spectrum of a real vector.
+
+Every array comes from ``numpy.random.default_rng(SeedSequence([2408, config_id, stream]))``
+with streams 0: Theta, 1: world, 2: poses, 3: range noise, 4: empty samples, 5: request stream.
+"""
+from __future__ import annotations
+
+import dataclasses
+import hashlib
+import math
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+STREAM_THETA, STREAM_WORLD, STREAM_POSES, STREAM_NOISE, STREAM_EMPTY, STREAM_REQUESTS = range(6)
+
+
+def rng_for(config_id: int, stream: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([2408, int(config_id), int(stream)]))
+
+
+def make_theta(D: int, ell: float, rng: np.random.Generator) -> np.ndarray:
+    """Conjugate-symmetric phase basis, float64 [D][2] in rad/m (already divided by l)."""
+    if D < 4 or D % 2:
+        raise ValueError("D must be even and >= 4")
+    h = D // 2
+    th = np.zeros((D, 2), dtype=np.float64)
+    ph = rng.uniform(-np.pi, np.pi, size=(h - 1, 2))
+    th[1:h] = ph
+    th[h + 1:] = -ph[::-1]
+    return th / float(ell)
+
+
+@dataclasses.dataclass
+class World:
+    half: float                      # world is [-half, half]^2, its boundary is a wall
+    rects: np.ndarray                # [nr][4] xmin, ymin, xmax, ymax
+    circles: np.ndarray              # [nc][3] cx, cy, radius
+
+
+def _dist_to_obstacles(p: np.ndarray, w: World) -> float:
+    d = math.inf
+    for xmn, ymn, xmx, ymx in w.rects:
+        dx = max(xmn - p[0], 0.0, p[0] - xmx)
+        dy = max(ymn - p[1], 0.0, p[1] - ymx)
+        d = min(d, math.hypot(dx, dy))
+    for cx, cy, r in w.circles:
+        d = min(d, math.hypot(p[0] - cx, p[1] - cy) - r)
+    return d
+
+
+def make_world(half: float, n_rect: int, n_circ: int, rect_side: Tuple[float, float],
+               circ_radius: Tuple[float, float], keep_clear: np.ndarray, clearance: float,
+               rng: np.random.Generator) -> World:
+    rects: List[List[float]] = []
+    circles: List[List[float]] = []
+    tries = 0
+    while len(rects) < n_rect:
+        tries += 1
+        if tries > 100000:
+            raise RuntimeError("could not place rectangles")
+        sx, sy = rng.uniform(rect_side[0], rect_side[1], size=2)
+        cx, cy = rng.uniform(-half + sx / 2, half - sx / 2), rng.uniform(-half + sy / 2, half - sy / 2)
+        r = [cx - sx / 2, cy - sy / 2, cx + sx / 2, cy + sy / 2]
+        ok = True
+        for p in keep_clear:
+            dx = max(r[0] - p[0], 0.0, p[0] - r[2])
+            dy = max(r[1] - p[1], 0.0, p[1] - r[3])
+            if math.hypot(dx, dy) < clearance:
+                ok = False
+                break
+        if ok:
+            rects.append(r)
+    tries = 0
+    while len(circles) < n_circ:
+        tries += 1
+        if tries > 100000:
+            raise RuntimeError("could not place circles")
+        rad = rng.uniform(circ_radius[0], circ_radius[1])
+        cx, cy = rng.uniform(-half + rad, half - rad, size=2)
+        if all(math.hypot(cx - p[0], cy - p[1]) - rad >= clearance for p in keep_clear):
+            circles.append([cx, cy, rad])
+    return World(half, np.array(rects, dtype=np.float64).reshape(-1, 4),
+                 np.array(circles, dtype=np.float64).reshape(-1, 3))
+
+
+def random_walk(world: World, n: int, start: np.ndarray, rng: np.random.Generator,
+                step=(0.5, 1.5), margin: float = 0.5) -> np.ndarray:
+    poses = [np.asarray(start, dtype=np.float64)]
+    heading = rng.uniform(-np.pi, np.pi)
+    tries = 0
+    while len(poses) < n:
+        tries += 1
+        if tries > 200000:
+            raise RuntimeError("random walk got stuck")
+        heading += rng.normal(0.0, 0.6)
+        s = rng.uniform(*step)
+        q = poses[-1] + s * np.array([math.cos(heading), math.sin(heading)])
+        if np.any(np.abs(q) > world.half - 1.0) or _dist_to_obstacles(q, world) < margin:
+            heading += rng.uniform(-np.pi, np.pi)
+            continue
+        poses.append(q)
+    return np.stack(poses)
+
+
+def raycast(world: World, pose: np.ndarray, angles: np.ndarray) -> np.ndarray:
+    """Exact range from pose along each angle to the first wall, rectangle or circle."""
+    dx, dy = np.cos(angles), np.sin(angles)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        # world boundary (ray starts inside): exit distance
+        tx = np.where(dx > 0, (world.half - pose[0]) / dx, np.where(dx < 0, (-world.half - pose[0]) / dx, np.inf))
+        ty = np.where(dy > 0, (world.half - pose[1]) / dy, np.where(dy < 0, (-world.half - pose[1]) / dy, np.inf))
+        t = np.minimum(tx, ty)
+        for xmn, ymn, xmx, ymx in world.rects:
+            t1x = np.where(dx != 0, (xmn - pose[0]) / dx, np.where(pose[0] >= xmn, -np.inf, np.inf))
+            t2x = np.where(dx != 0, (xmx - pose[0]) / dx, np.where(pose[0] <= xmx, np.inf, -np.inf))
+            t1y = np.where(dy != 0, (ymn - pose[1]) / dy, np.where(pose[1] >= ymn, -np.inf, np.inf))
+            t2y = np.where(dy != 0, (ymx - pose[1]) / dy, np.where(pose[1] <= ymx, np.inf, -np.inf))
+            tmin = np.maximum(np.minimum(t1x, t2x), np.minimum(t1y, t2y))
+            tmax = np.minimum(np.maximum(t1x, t2x), np.maximum(t1y, t2y))
+            hit = (tmax >= tmin) & (tmin > 0)
+            t = np.where(hit & (tmin < t), tmin, t)
+        for cx, cy, r in world.circles:
+            ox, oy = pose[0] - cx, pose[1] - cy
+            b = ox * dx + oy * dy
+            c = ox * ox + oy * oy - r * r
+            disc = b * b - c
+            tc = -b - np.sqrt(np.maximum(disc, 0.0))
+            hit = (disc >= 0) & (tc > 0)
+            t = np.where(hit & (tc < t), tc, t)
+    return t
+
+
+def scan_points(world: World, poses: np.ndarray, beams: int, empties_per_beam: int,
+                sigma: float, rng_noise: np.random.Generator,
+                rng_empty: np.random.Generator) -> Tuple[np.ndarray, np.ndarray]:
+    """Occupied beam end points then empty samples along the beams, pose by pose."""
+    ang = 2.0 * np.pi * np.arange(beams) / beams
+    dirs = np.stack([np.cos(ang), np.sin(ang)], axis=1)
+    xs, ls = [], []
+    for p in poses:
+        r = raycast(world, p, ang) + rng_noise.normal(0.0, sigma, size=beams)
+        r = np.maximum(r, 0.0)
+        hits = p[None, :] + r[:, None] * dirs
+        u = rng_empty.uniform(0.0, 1.0, size=(beams, empties_per_beam))
+        emp = p[None, None, :] + (u * r[:, None])[:, :, None] * dirs[:, None, :]
+        xs.append(hits)
+        ls.append(np.ones(beams, dtype=np.uint8))
+        xs.append(emp.reshape(-1, 2))
+        ls.append(np.zeros(beams * empties_per_beam, dtype=np.uint8))
+    return (np.concatenate(xs).astype(np.float32), np.concatenate(ls))
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    D: int
+    ell: float
+    theta: np.ndarray            # float64 [D][2], rad/m
+    layout: Tuple[float, float, float, float]   # x0, y0, x1, y1 of the tile layout
+    tiles: Tuple[int, int]
+    grid: Tuple[float, float, float]            # x0, y0, res
+    nx: int
+    ny: int
+    xy: np.ndarray               # float32 [n][2], world metres
+    label: np.ndarray            # uint8 [n], 1 = occupied
+    r_occ: int
+    r_emp: int
+    rho: float = 0.0
+    poses: Optional[np.ndarray] = None
+
+    @property
+    def n(self) -> int:
+        return int(self.xy.shape[0])
+
+    def digest(self) -> Dict[str, str]:
+        return {k: hashlib.sha256(np.ascontiguousarray(v).tobytes()).hexdigest()
+                for k, v in (("theta", self.theta), ("xy", self.xy), ("label", self.label))}
+
+
+@dataclasses.dataclass
+class ScanRecipe:
+    config_id: int
+    name: str
+    half: float
+    n_rect: int
+    n_circ: int
+    rect_side: Tuple[float, float]
+    circ_radius: Tuple[float, float]
+    n_poses: int
+    beams: int
+    empties: int
+    D: int
+    ell: float
+    tiles: Tuple[int, int]
+    res: float
+    nx: int
+    ny: int
+    r: int
+    sigma: float = 0.02
+    grid_origin: Optional[Tuple[float, float]] = None
+
+
+# Workload recipes.  "toy_room" and "world40" are the plain-method configurations (a single
+# 360-beam scan in a 12.8 m room; 50 scans of 1080 beams in a 40 m world at D = 8192);
+# the small ones are multi-tile and ragged variants sized for the oracle.
+RECIPES: Dict[str, ScanRecipe] = {
+    "toy_room": ScanRecipe(1, "toy_room", 6.4, 6, 0, (0.5, 2.5), (0.25, 1.5), 1, 360, 5,
+                           1024, 0.2, (1, 1), 0.1, 128, 128, 2),
+    "world40": ScanRecipe(2, "world40", 20.0, 20, 20, (0.5, 4.0), (0.25, 1.5), 50, 1080, 10,
+                          8192, 0.1, (4, 4), 0.05, 800, 800, 3),
+    "world40_d1": ScanRecipe(2, "world40_d1", 20.0, 20, 20, (0.5, 4.0), (0.25, 1.5), 50, 1080, 10,
+                             8192, 0.1, (1, 1), 0.05, 800, 800, 3),
+    "mini4x4": ScanRecipe(11, "mini4x4", 8.0, 8, 6, (0.5, 2.0), (0.25, 1.0), 8, 360, 5,
+                          2048, 0.2, (4, 4), 0.1, 160, 160, 3),
+    "ragged3x3": ScanRecipe(12, "ragged3x3", 7.5, 6, 4, (0.5, 2.0), (0.25, 1.0), 5, 300, 4,
+                            1000, 0.2, (3, 3), 0.1, 150, 130, 2, grid_origin=(-7.5, -6.5)),
+}
+
+
+def build(recipe: ScanRecipe) -> Workload:
+    rt = rng_for(recipe.config_id, STREAM_THETA)
+    theta = make_theta(recipe.D, recipe.ell, rt)
+    rw = rng_for(recipe.config_id, STREAM_WORLD)
+    start = np.zeros(2)
+    world = make_world(recipe.half, recipe.n_rect, recipe.n_circ, recipe.rect_side,
+                       recipe.circ_radius, start[None, :], 1.0, rw)
+    if recipe.n_poses == 1:
+        poses = start[None, :]
+    else:
+        poses = random_walk(world, recipe.n_poses, start, rng_for(recipe.config_id, STREAM_POSES))
+    xy, label = scan_points(world, poses, recipe.beams, recipe.empties, recipe.sigma,
+                            rng_for(recipe.config_id, STREAM_NOISE),
+                            rng_for(recipe.config_id, STREAM_EMPTY))
+    if recipe.grid_origin is None:
+        gx0 = gy0 = -recipe.half
+    else:
+        gx0, gy0 = recipe.grid_origin
+    layout = (gx0, gy0, gx0 + recipe.nx * recipe.res, gy0 + recipe.ny * recipe.res)
+    return Workload(recipe.name, recipe.D, recipe.ell, theta, layout, recipe.tiles,
+                    (gx0, gy0, recipe.res), recipe.nx, recipe.ny, xy, label,
+                    recipe.r, recipe.r, 0.0, poses)
+
+
+def workload(name: str) -> Workload:
+    return build(RECIPES[name])
