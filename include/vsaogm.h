@@ -1,0 +1,183 @@
+/*
+ * vsaogm.h -- C ABI of the MI355X (gfx950) VSA-OGM hot path.
+ *
+ * VSA-OGM (arXiv 2408.09066) builds an occupancy grid map from labelled 2-D
+ * points with Spatial Semantic Pointers.  The operations exposed here are:
+ *
+ *   vsaogm_encode    Sec. III-B "Encoding Point Clouds": every point is
+ *                    fractionally bound (2-D encoding equation) and bundled
+ *                    (eq. bundling) into the memory of its nearest tile and
+ *                    its class (Algorithm 1).
+ *   vsaogm_decode    Sec. III-B "Decoding": memory normalisation (eq.
+ *                    vector-normalization) and similarity against the
+ *                    location vectors of every grid cell (eq. loc-query),
+ *                    plus the per-class maximum used by eq. non-linearities.
+ *   vsaogm_classify  Sec. III-B: (P/max P)^2 (eq. non-linearities), local
+ *                    Shannon entropy over a disk mask (Algorithm 2 and the
+ *                    entropy / mask equations), softmax (eq. softmax),
+ *                    probabilistic signed difference (eq. psd) and the
+ *                    threshold rho (eq. classification).
+ *   vsaogm_fuse      Sec. III-B "Multi-Map Fusion" (Algorithm 3).
+ *   vsaogm_submit /  a request loop that runs whole map updates
+ *   vsaogm_poll      (encode + decode + classify) for many maps at once.
+ *
+ * Representation.  A real D-dimensional SSP is kept as its discrete Fourier
+ * spectrum.  The axis vectors have unit-modulus, conjugate-symmetric spectra
+ * exp(i*theta_k); the caller passes Theta[k] = theta_k / l (radians per
+ * metre, length scale l already applied) for both axes.  Fractional binding
+ * of (x, y) is then the spectrum exp(i*(Theta[k][0]*x + Theta[k][1]*y)).
+ * Because the spectra are conjugate-symmetric only bins 0..D/2 are stored.
+ *
+ * Tiles (Sec. III-B "Vector Discretization") split the layout rectangle
+ * [x0,x1] x [y0,y1] into tiles_x * tiles_y equal tiles, numbered row-major
+ * beta = ty*tiles_x + tx.  Memory 2*beta+psi holds class psi of tile beta
+ * (psi = 1 occupied, 0 empty).  A point or a grid cell belongs to the tile
+ * whose centre is nearest (double-precision squared distance, lowest index on
+ * an exact tie); points outside the rectangle go to the nearest tile.
+ *
+ * Conventions for every function:
+ *   - the return value is a vsaogm_status; no C++ exception crosses the ABI;
+ *   - "dev" pointers are HIP device pointers on the map's device, "host"
+ *     pointers are ordinary host memory; the caller owns every pointer it
+ *     passes, the library owns maps, servers and their internal buffers;
+ *   - calls that take a stream only enqueue work on it (they return before the
+ *     GPU finishes); the caller must keep inputs alive and outputs untouched
+ *     until the stream reaches that point;
+ *   - a map is not thread-safe; a server is safe for concurrent submit/poll.
+ */
+#ifndef VSAOGM_H
+#define VSAOGM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VSAOGM_OK = 0,
+    VSAOGM_EINVAL = -1,   /* invalid argument (message in vsaogm_last_error) */
+    VSAOGM_ENOMEM = -2,   /* device allocation failed */
+    VSAOGM_EDEVICE = -3,  /* a HIP call failed */
+    VSAOGM_EAGAIN = -4,   /* vsaogm_poll: request not finished yet */
+    VSAOGM_EBUSY = -5,    /* vsaogm_submit: admission refused (queue or memory budget full) */
+    VSAOGM_ENOTFOUND = -6 /* unknown ticket or map id */
+} vsaogm_status;
+
+/* Arithmetic of the similarity contraction (Sec. III-B eq. loc-query). */
+typedef enum {
+    VSAOGM_FP32 = 0,    /* fp32 operands, fp32 accumulation (MFMA f32) */
+    VSAOGM_BF16 = 1,    /* bf16 operands, fp32 accumulation */
+    VSAOGM_FP16 = 2,    /* fp16 operands, fp32 accumulation */
+    VSAOGM_BF16X3 = 3   /* bf16 hi+lo split of both operands, 3 products, fp32 accumulation */
+} vsaogm_precision;
+
+typedef struct vsaogm_map vsaogm_map;
+typedef struct vsaogm_server vsaogm_server;
+typedef void* vsaogm_stream; /* a hipStream_t; NULL means the device's null stream */
+
+typedef struct {
+    int32_t dim;            /* D: even, >= 4 (the paper's vector dimensionality d) */
+    const double* theta;    /* host [D][2] Theta in rad/m; Theta[0] = Theta[D/2] = 0 and
+                               Theta[D-k] = -Theta[k] exactly, else EINVAL; copied */
+    double x0, y0, x1, y1;  /* tile layout rectangle (metres), x1 > x0, y1 > y0 */
+    int32_t tiles_x, tiles_y; /* delta per axis, 1..64 each */
+    int32_t device;         /* HIP device ordinal */
+} vsaogm_map_desc;
+
+/* Query grid: cell (i, j), 0 <= i < nx, 0 <= j < ny, has centre
+   (x0 + (i + 0.5) * res, y0 + (j + 0.5) * res).  Maps are [ny][nx] row-major. */
+typedef struct {
+    double x0, y0, res;
+    int32_t nx, ny;
+} vsaogm_grid_desc;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int32_t vsaogm_version(void);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char* vsaogm_last_error(void);
+
+/* Create a map with all memories zero.  *out receives the handle. */
+int vsaogm_map_create(const vsaogm_map_desc* desc, vsaogm_map** out);
+
+/* Destroy a map (synchronises its device first).  NULL is a no-op. */
+int vsaogm_map_destroy(vsaogm_map* map);
+
+/* Number of memories (2 * tiles_x * tiles_y) and the dimension D. */
+int vsaogm_map_info(const vsaogm_map* map, int64_t* n_memories, int32_t* dim);
+
+/* Set every memory back to zero (async on stream). */
+int vsaogm_map_reset(vsaogm_map* map, vsaogm_stream stream);
+
+/*
+ * Algorithm 1: bundle n labelled points into the map's memories.
+ *   xy    dev float32 [n][2], world metres
+ *   label dev uint8 [n], 1 = occupied, 0 = empty; any other value is not
+ *         bundled and is counted (see vsaogm_map_take_rejected)
+ * Memories accumulate across calls.  n == 0 is a no-op.  Returns EINVAL for
+ * n < 0 or NULL pointers with n > 0.  Work buffers grow on demand (a growth
+ * synchronises the stream once).
+ */
+int vsaogm_encode(vsaogm_map* map, const float* xy, const uint8_t* label, int64_t n,
+                  vsaogm_stream stream);
+
+/*
+ * Synchronise the stream and return (and clear) the number of points that
+ * encode calls rejected for a label outside {0, 1} since the last call.
+ */
+int vsaogm_map_take_rejected(vsaogm_map* map, vsaogm_stream stream, int64_t* n_rejected);
+
+/*
+ * Eqs. vector-normalization and loc-query over a grid:
+ *   heat dev float32 [2][ny][nx]; heat[psi][j][i] = normalised memory
+ *        2*beta(c)+psi dotted with the location vector of cell c, 0 where
+ *        that memory is empty;
+ *   hmax dev float32 [2]; hmax[psi] = max over the grid of heat[psi]
+ *        (the maximum of eq. non-linearities).
+ * precision selects the contraction arithmetic (vsaogm_precision).  The
+ * per-grid location tables are built on first use and cached in the map
+ * (a new grid synchronises the stream once).  Returns EINVAL for nx, ny < 1,
+ * res <= 0, or a grid whose cells cannot be split into per-tile row and
+ * column ranges.
+ */
+int vsaogm_decode(vsaogm_map* map, const vsaogm_grid_desc* grid, int32_t precision,
+                  float* heat, float* hmax, vsaogm_stream stream);
+
+/*
+ * Post-processing of Sec. III-B on the device:
+ *   Q = (heat / hmax)^2 per class (Q = 0 for a class whose hmax <= 0),
+ *   H_psi(c) = sum of -Q ln Q over grid cells within Euclidean distance r_psi
+ *   (integer cell offsets, inclusive; cells outside the grid are not summed),
+ *   ogm = softmax(H)_1 - softmax(H)_0 = tanh((H_1 - H_0) / 2),
+ *   label = 1 (occupied) where ogm >= rho, else 0.
+ *   heat dev float32 [2][ny][nx] (index 1 = occupied), hmax dev float32 [2],
+ *   ogm  dev float32 [ny][nx] or NULL, label dev uint8 [ny][nx].
+ * r_occ is the disk radius of class 1, r_emp of class 0; 0 <= r <= 24.
+ * Only grid->nx and grid->ny are used.  device selects the HIP device.
+ */
+int vsaogm_classify(const vsaogm_grid_desc* grid, const float* heat, const float* hmax,
+                    int32_t r_occ, int32_t r_emp, float rho, float* ogm, uint8_t* label,
+                    int32_t device, vsaogm_stream stream);
+
+/*
+ * Read the memories back in the paper's frame: out dev float32
+ * [2R][D/2+1][2] (re, im), out[key][k] = sum over the key's points of
+ * exp(i*(Theta[k][0]*x + Theta[k][1]*y)), k = 0..D/2 (the other bins are the
+ * complex conjugates, bin D-k = conj(bin k)).
+ */
+int vsaogm_memories(const vsaogm_map* map, float* out, vsaogm_stream stream);
+
+/*
+ * Algorithm 3 for two maps: dst's memories += src's memories, key by key.
+ * Both maps must have the same Theta (bitwise), D, layout rectangle, tiling
+ * and device (EINVAL otherwise).  Async on stream; src must not be encoded
+ * into concurrently.
+ */
+int vsaogm_fuse(vsaogm_map* dst, const vsaogm_map* src, vsaogm_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VSAOGM_H */

@@ -1,0 +1,89 @@
+// Entropy-based classification (Sec. III-B: eq. non-linearities, Algorithm 2 with the
+// local Shannon entropy and disk-mask equations, eqs. softmax, psd and classification).
+//
+// One block covers TX x TY cells.  The entropy terms g = -Q ln Q, Q = (P / max P)^2, of the
+// block and a halo of R = max(r_occ, r_emp) cells are computed once into LDS (zero outside
+// the grid, which excludes those neighbours), then each cell sums its disk of integer
+// offsets dx^2 + dy^2 <= r^2 per class, and the softmax of the two entropies minus each other
+// is tanh((H1 - H0) / 2).  The heatmaps are read once and the map written once.
+#include "internal.h"
+
+namespace vsaogm {
+namespace {
+
+constexpr int TX = 64, TY = 16;
+
+__global__ __launch_bounds__(256) void k_classify(const float* __restrict__ heat,
+                                                  const float* __restrict__ hmax, int nx, int ny,
+                                                  int r_occ, int r_emp, float rho,
+                                                  float* __restrict__ ogm,
+                                                  uint8_t* __restrict__ label) {
+    extern __shared__ float sg[];
+    const int R = max(r_occ, r_emp);
+    const int W = TX + 2 * R, H = TY + 2 * R;
+    __shared__ int half_w[2][2 * kMaxRadius + 1];
+    const int bx = blockIdx.x * TX, by = blockIdx.y * TY;
+    if (threadIdx.x < 2 * (2 * kMaxRadius + 1)) {
+        const int p = threadIdx.x / (2 * kMaxRadius + 1);
+        const int dy = threadIdx.x % (2 * kMaxRadius + 1) - kMaxRadius;
+        const int r = p ? r_occ : r_emp;
+        int w = -1;  // no cell in this row of the disk
+        if (dy >= -r && dy <= r) {
+            w = 0;
+            while ((w + 1) * (w + 1) + dy * dy <= r * r) ++w;
+        }
+        half_w[p][dy + kMaxRadius] = w;
+    }
+    const float m0 = hmax[0], m1 = hmax[1];
+    const size_t plane = (size_t)nx * ny;
+    for (int idx = threadIdx.x; idx < 2 * W * H; idx += 256) {
+        const int p = idx / (W * H);
+        const int rem = idx - p * W * H;
+        const int yy = rem / W, xx = rem - yy * W;
+        const int gx = bx - R + xx, gy = by - R + yy;
+        const float m = p ? m1 : m0;
+        float v = 0.f;
+        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && m > 0.f) {
+            const float r = heat[p * plane + (size_t)gy * nx + gx] / m;
+            const float q = r * r;
+            v = (q > 0.f) ? -q * logf(q) : 0.f;
+        }
+        sg[idx] = v;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < TX * TY; c += 256) {
+        const int cx = c % TX, cy = c / TX;
+        const int gx = bx + cx, gy = by + cy;
+        if (gx >= nx || gy >= ny) continue;
+        float h[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int r = p ? r_occ : r_emp;
+            const float* base = sg + p * W * H;
+            float s = 0.f;
+            for (int dy = -r; dy <= r; ++dy) {
+                const int w = half_w[p][dy + kMaxRadius];
+                const float* row = base + (cy + R + dy) * W + (cx + R);
+                for (int dx = -w; dx <= w; ++dx) s += row[dx];
+            }
+            h[p] = s;
+        }
+        const float o = tanhf(0.5f * (h[1] - h[0]));
+        const size_t off = (size_t)gy * nx + gx;
+        if (ogm) ogm[off] = o;
+        label[off] = (o >= rho) ? 1 : 0;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_classify(const float* heat, const float* hmax, int nx, int ny, int r_occ,
+                           int r_emp, float rho, float* ogm, uint8_t* label, hipStream_t s) {
+    const int R = r_occ > r_emp ? r_occ : r_emp;
+    const size_t lds = 2 * (size_t)(TX + 2 * R) * (TY + 2 * R) * sizeof(float);
+    hipLaunchKernelGGL(k_classify, dim3((nx + TX - 1) / TX, (ny + TY - 1) / TY), dim3(256), lds, s,
+                       heat, hmax, nx, ny, r_occ, r_emp, rho, ogm, label);
+    return hipGetLastError();
+}
+
+}  // namespace vsaogm

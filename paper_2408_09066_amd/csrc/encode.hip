@@ -1,0 +1,464 @@
+// Encoding and bundling (Sec. III-B "Encoding Point Clouds", Algorithm 1) on gfx950.
+//
+// A point gamma_i with class psi_i is fractionally bound (2-D encoding equation) into the
+// spectrum exp(i*Theta[k].gamma_i) and added (eq. bundling) to memory 2*beta+psi_i of its
+// nearest tile beta.  Memories are kept in tile-local coordinates,
+//   Omega_local[key][k] = sum_i exp(i*Theta[k].(gamma_i - mu_beta)),
+// which is exp(-i*Theta[k].mu_beta) times the paper's memory; the decode queries cells in
+// the same local frame, so the factor cancels exactly in every similarity, while the phases
+// stay small enough for single precision.
+//
+// Pipeline (all on the stream, no host synchronisation):
+//   k_assign   nearest tile (exact double-precision argmin, lowest index on ties), key,
+//              label check, per-chunk key histogram
+//   k_scan     per-key totals and exclusive bases, encode work table
+//   k_scatter  stable counting sort of the local coordinates by key (one wavefront per chunk)
+//   k_encode   per (work item, block of bins): sum of exp(2*pi*i*t) with t in revolutions,
+//              hardware v_sin/v_cos, two points per step:
+//                exp(i a) + exp(i b) = 2 cos((a-b)/2) exp(i (a+b)/2)
+//   k_reduce   fixed-order sum of the work items' partial spectra into the memories
+#include "internal.h"
+
+namespace vsaogm {
+namespace {
+
+__device__ inline int nearest_tile(double x, double y, const LayoutDev& L) {
+    // Guess by the per-axis floor, then evaluate the exact squared distances of the 3x3
+    // neighbourhood in increasing tile order (row-major), keeping the first strict minimum.
+    double gx = fmin(fmax((x - L.x0) * L.inv_wx, -1.0), (double)L.tiles_x);
+    double gy = fmin(fmax((y - L.y0) * L.inv_wy, -1.0), (double)L.tiles_y);
+    int ex = (int)floor(gx), ey = (int)floor(gy);
+    int i0 = max(ex - 1, 0), i1 = min(ex + 1, L.tiles_x - 1);
+    int j0 = max(ey - 1, 0), j1 = min(ey + 1, L.tiles_y - 1);
+    int best = -1;
+    double bd = INFINITY;
+    for (int j = j0; j <= j1; ++j) {
+        double dy = __dsub_rn(y, L.cy[j]);
+        double dy2 = __dmul_rn(dy, dy);
+        for (int i = i0; i <= i1; ++i) {
+            double dx = __dsub_rn(x, L.cx[i]);
+            double d2 = __dadd_rn(__dmul_rn(dx, dx), dy2);
+            if (d2 < bd) {
+                bd = d2;
+                best = j * L.tiles_x + i;
+            }
+        }
+    }
+    return best;
+}
+
+__global__ __launch_bounds__(256) void k_assign(const float2* __restrict__ xy,
+                                                const uint8_t* __restrict__ label, int64_t n,
+                                                LayoutDev L, int nkeys, int* __restrict__ key_out,
+                                                int* __restrict__ hist,
+                                                unsigned long long* __restrict__ n_bad) {
+    extern __shared__ int sh_hist[];
+    for (int k = threadIdx.x; k < nkeys; k += blockDim.x) sh_hist[k] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kAssignChunk;
+    int bad = 0;
+    for (int q = threadIdx.x; q < kAssignChunk; q += blockDim.x) {
+        int64_t i = base + q;
+        if (i >= n) break;
+        float2 p = xy[i];
+        unsigned l = label[i];
+        int key = -1;
+        if (l <= 1u) {
+            int b = nearest_tile((double)p.x, (double)p.y, L);
+            if (b >= 0) key = 2 * b + (int)l;
+        }
+        if (key < 0) {
+            ++bad;
+        } else {
+            atomicAdd(&sh_hist[key], 1);
+        }
+        key_out[i] = key;
+    }
+    if (bad) atomicAdd(n_bad, (unsigned long long)bad);
+    __syncthreads();
+    for (int k = threadIdx.x; k < nkeys; k += blockDim.x)
+        hist[(size_t)blockIdx.x * nkeys + k] = sh_hist[k];
+}
+
+// Exclusive scan of v[0..n) in shared memory by one block of blockDim.x threads.
+// tmp must hold blockDim.x ints.  Returns the total.
+__device__ int block_exclusive_scan(int* v, int n, int* tmp) {
+    const int T = blockDim.x;
+    const int per = (n + T - 1) / T;
+    const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
+    int s = 0;
+    for (int i = lo; i < hi; ++i) s += v[i];
+    tmp[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < T; off <<= 1) {
+        int add = (int)threadIdx.x >= off ? tmp[threadIdx.x - off] : 0;
+        __syncthreads();
+        tmp[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int run = tmp[threadIdx.x] - s;  // exclusive prefix of this thread's segment
+    for (int i = lo; i < hi; ++i) {
+        int x = v[i];
+        v[i] = run;
+        run += x;
+    }
+    int total = tmp[T - 1];
+    __syncthreads();
+    return total;
+}
+
+// One block of 1024 threads.  hist[c][k] (counts) becomes the global destination base of
+// chunk c's points of key k; the encode work table and per-key bookkeeping are written.
+__global__ __launch_bounds__(1024) void k_scan(int* __restrict__ hist, int nchunks, int nkeys,
+                                               int echunk, EChunk* __restrict__ table,
+                                               int* __restrict__ meta) {
+    extern __shared__ int sh[];
+    int* tot = sh;                 // [nkeys] totals, then key starts
+    int* nec = sh + nkeys;         // [nkeys] work items per key, then their first index
+    int* tmp = sh + 2 * nkeys;     // [blockDim.x]
+    for (int k = threadIdx.x; k < nkeys; k += blockDim.x) {
+        int run = 0;
+        for (int c = 0; c < nchunks; ++c) {
+            int* h = hist + (size_t)c * nkeys + k;
+            int x = *h;
+            *h = run;
+            run += x;
+        }
+        tot[k] = run;
+        nec[k] = (run + echunk - 1) / echunk;
+        meta[1 + 2 * nkeys + k] = run;  // key_count
+    }
+    __syncthreads();
+    int n_ec = block_exclusive_scan(nec, nkeys, tmp);
+    block_exclusive_scan(tot, nkeys, tmp);
+    if (threadIdx.x == 0) meta[0] = n_ec;
+    for (int k = threadIdx.x; k < nkeys; k += blockDim.x) {
+        int start = tot[k];
+        int cnt = meta[1 + 2 * nkeys + k];
+        int e0 = nec[k];
+        int ne = (cnt + echunk - 1) / echunk;
+        meta[1 + k] = e0;
+        meta[1 + nkeys + k] = ne;
+        for (int j = 0; j < ne; ++j) {
+            EChunk e;
+            e.key = k;
+            e.start = start + j * echunk;
+            e.len = min(echunk, cnt - j * echunk);
+            e.pad = 0;
+            table[e0 + j] = e;
+        }
+        for (int c = 0; c < nchunks; ++c) hist[(size_t)c * nkeys + k] += start;
+    }
+}
+
+// Stable counting-sort scatter: one wavefront per chunk of kAssignChunk points, in order.
+// A point's slot is its key's running base plus the number of earlier lanes of the same
+// round with the same key (lanes are matched bit by bit with ballots).
+__global__ __launch_bounds__(64) void k_scatter(const float2* __restrict__ xy,
+                                                const int* __restrict__ key, int64_t n,
+                                                LayoutDev L, int nkeys, int key_bits,
+                                                const int* __restrict__ base,
+                                                float2* __restrict__ sorted,
+                                                float2* __restrict__ sorted_lo) {
+    extern __shared__ int run[];
+    const int lane = threadIdx.x;
+    for (int k = lane; k < nkeys; k += 64) run[k] = base[(size_t)blockIdx.x * nkeys + k];
+    __syncthreads();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t c0 = (int64_t)blockIdx.x * kAssignChunk;
+    for (int r = 0; r < kAssignChunk / 64; ++r) {
+        const int64_t i = c0 + r * 64 + lane;
+        const int k = (i < n) ? key[i] : -1;
+        const unsigned uk = (k < 0) ? (unsigned)nkeys : (unsigned)k;
+        uint64_t same = ~0ull;
+        for (int b = 0; b < key_bits; ++b) {
+            const bool bit = (uk >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            same &= bit ? m : ~m;
+        }
+        if (k >= 0) {
+            const int rank = __popcll(same & lt_mask);
+            const int dest = run[k] + rank;
+            const int beta = k >> 1;
+            const int tx = beta % L.tiles_x, ty = beta / L.tiles_x;
+            const float2 p = xy[i];
+            const double lx = (double)p.x - L.cx[tx];
+            const double ly = (double)p.y - L.cy[ty];
+            const float fx = (float)lx, fy = (float)ly;
+            sorted[dest] = make_float2(fx, fy);
+            sorted_lo[dest] = make_float2((float)(lx - (double)fx), (float)(ly - (double)fy));
+            if ((same & lt_mask) == 0) run[k] += __popcll(same);
+        }
+        __syncthreads();
+    }
+}
+
+// Partial spectra of one work item for one block of bins.  Thread t owns bins
+// b0 + t + j*256, j < BPT; the points are read as wave-uniform (scalar) loads.
+template <int BPT>
+__global__ __launch_bounds__(kEncodeThreads) void k_encode(
+    const float2* __restrict__ sorted, const float2* __restrict__ sorted_lo,
+    const EChunk* __restrict__ table, const int* __restrict__ meta,
+    const float2* __restrict__ rev, const double2* __restrict__ rev_d, float max_rev_x,
+    float max_rev_y, int halfp, float2* __restrict__ partial) {
+    const int c = blockIdx.x;
+    if (c >= meta[0]) return;
+    const EChunk e = table[c];
+    const int b0 = blockIdx.y * (kEncodeThreads * BPT) + threadIdx.x;
+    const float2* __restrict__ p = sorted + e.start;
+
+    // Largest phase (revolutions) any bin can reach on this work item's points.
+    __shared__ float sh_max[kEncodeThreads / 64];
+    float bound = 0.f;
+    for (int q = threadIdx.x; q < e.len; q += kEncodeThreads) {
+        float2 v = p[q];
+        bound = fmaxf(bound, fabsf(v.x) * max_rev_x + fabsf(v.y) * max_rev_y);
+    }
+    for (int off = 32; off > 0; off >>= 1) bound = fmaxf(bound, __shfl_xor(bound, off));
+    if ((threadIdx.x & 63) == 0) sh_max[threadIdx.x >> 6] = bound;
+    __syncthreads();
+    float wmax = 0.f;
+#pragma unroll
+    for (int w = 0; w < kEncodeThreads / 64; ++w) wmax = fmaxf(wmax, sh_max[w]);
+
+    float re[BPT], im[BPT];
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) re[j] = im[j] = 0.f;
+
+    if (wmax <= kWidePhaseRev) {
+        float ax[BPT], ay[BPT];
+#pragma unroll
+        for (int j = 0; j < BPT; ++j) {
+            const int k = b0 + j * kEncodeThreads;
+            float2 t = (k < halfp) ? rev[k] : make_float2(0.f, 0.f);
+            ax[j] = t.x;
+            ay[j] = t.y;
+        }
+        const int npairs = e.len >> 1;
+        for (int q = 0; q < npairs; ++q) {
+            const float2 a = p[2 * q];
+            const float2 b = p[2 * q + 1];
+            const float mx = 0.5f * (a.x + b.x), my = 0.5f * (a.y + b.y);
+            const float dx = 0.5f * (a.x - b.x), dy = 0.5f * (a.y - b.y);
+#pragma unroll
+            for (int j = 0; j < BPT; ++j) {
+                const float tm = __builtin_fmaf(ax[j], mx, ay[j] * my);
+                const float td = __builtin_fmaf(ax[j], dx, ay[j] * dy);
+                const float cd = __builtin_amdgcn_cosf(td);
+                re[j] = __builtin_fmaf(cd, __builtin_amdgcn_cosf(tm), re[j]);
+                im[j] = __builtin_fmaf(cd, __builtin_amdgcn_sinf(tm), im[j]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < BPT; ++j) {
+            re[j] *= 2.f;
+            im[j] *= 2.f;
+        }
+        if (e.len & 1) {
+            const float2 a = p[e.len - 1];
+#pragma unroll
+            for (int j = 0; j < BPT; ++j) {
+                const float t = __builtin_fmaf(ax[j], a.x, ay[j] * a.y);
+                re[j] += __builtin_amdgcn_cosf(t);
+                im[j] += __builtin_amdgcn_sinf(t);
+            }
+        }
+    } else {
+        // Large arguments: the phase is formed and wrapped to [-1/2, 1/2] revolutions in
+        // double precision, from the double-float local coordinates.
+        double ax[BPT], ay[BPT];
+#pragma unroll
+        for (int j = 0; j < BPT; ++j) {
+            const int k = b0 + j * kEncodeThreads;
+            double2 t = (k < halfp) ? rev_d[k] : make_double2(0.0, 0.0);
+            ax[j] = t.x;
+            ay[j] = t.y;
+        }
+        const float2* __restrict__ plo = sorted_lo + e.start;
+        for (int q = 0; q < e.len; ++q) {
+            const float2 a = p[q], al = plo[q];
+            const double x = (double)a.x + (double)al.x, y = (double)a.y + (double)al.y;
+#pragma unroll
+            for (int j = 0; j < BPT; ++j) {
+                const double t = __fma_rn(ax[j], x, ay[j] * y);
+                const float r = (float)(t - rint(t));
+                re[j] += __builtin_amdgcn_cosf(r);
+                im[j] += __builtin_amdgcn_sinf(r);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+        const int k = b0 + j * kEncodeThreads;
+        if (k < halfp) partial[(size_t)c * halfp + k] = make_float2(re[j], im[j]);
+    }
+}
+
+// omega[key][k] += sum over the key's work items, in work-item order (deterministic).
+__global__ __launch_bounds__(256) void k_reduce(const float2* __restrict__ partial,
+                                                const int* __restrict__ meta, int nkeys, int half,
+                                                int halfp, float2* __restrict__ omega) {
+    const int key = blockIdx.y;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= half) return;
+    const int e0 = meta[1 + key], ne = meta[1 + nkeys + key];
+    if (ne == 0) return;
+    float sr = 0.f, si = 0.f;
+    for (int c = e0; c < e0 + ne; ++c) {
+        float2 v = partial[(size_t)c * halfp + k];
+        sr += v.x;
+        si += v.y;
+    }
+    float2* o = omega + (size_t)key * halfp + k;
+    float2 w = *o;
+    *o = make_float2(w.x + sr, w.y + si);
+}
+
+// scale[key] = 2 / (D * ||w||) with ||w||^2 = (2/D) sum_{k < D/2} |Omega_k|^2 (Parseval over
+// the conjugate-symmetric spectrum; bins 0 and D/2 both equal the point count), 0 for an
+// empty memory (eq. vector-normalization).
+__global__ __launch_bounds__(256) void k_norm(const float2* __restrict__ omega, int half,
+                                              int halfp, int D, float* __restrict__ scale) {
+    const int key = blockIdx.x;
+    const float2* w = omega + (size_t)key * halfp;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < half; k += 256) {
+        double re = w[k].x, im = w[k].y;
+        s += re * re + im * im;
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    __shared__ double sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0] + sh[1] + sh[2] + sh[3];
+        double nrm = sqrt(2.0 * t / (double)D);
+        scale[key] = (nrm > 0.0) ? (float)(2.0 / ((double)D * nrm)) : 0.f;
+    }
+}
+
+// Paper-frame export: out[key][k] = exp(i*Theta[k].mu_beta) * Omega_local[key][k] for
+// k < D/2, and out[key][D/2] = Omega_local[key][0] (the point count; Theta[D/2] = 0).
+__global__ __launch_bounds__(256) void k_export(const float2* __restrict__ omega,
+                                                const double* __restrict__ theta_rad,
+                                                LayoutDev L, int half, int halfp,
+                                                float* __restrict__ out) {
+    const int key = blockIdx.y;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k > half) return;
+    const int beta = key >> 1;
+    const double mx = L.cx[beta % L.tiles_x], my = L.cy[beta / L.tiles_x];
+    const float2* w = omega + (size_t)key * halfp;
+    float* o = out + ((size_t)key * (half + 1) + k) * 2;
+    if (k == half) {
+        o[0] = w[0].x;
+        o[1] = w[0].y;
+        return;
+    }
+    double ph = theta_rad[2 * k] * mx + theta_rad[2 * k + 1] * my;
+    double s, c;
+    sincos(ph, &s, &c);
+    double re = w[k].x, im = w[k].y;
+    o[0] = (float)(c * re - s * im);
+    o[1] = (float)(s * re + c * im);
+}
+
+__global__ __launch_bounds__(256) void k_add(float2* __restrict__ dst,
+                                             const float2* __restrict__ src, size_t n) {
+    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) {
+        float2 a = dst[i], b = src[i];
+        dst[i] = make_float2(a.x + b.x, a.y + b.y);
+    }
+}
+
+int bits_for(int v) {
+    int b = 0;
+    while ((1 << b) <= v) ++b;
+    return b;
+}
+
+}  // namespace
+
+EncodePlan encode_plan(int64_t n, int halfp, int nkeys) {
+    EncodePlan p;
+    p.nchunks = (int)((n + kAssignChunk - 1) / kAssignChunk);
+    p.bpt = 1;
+    while (p.bpt < kEncodeBpt && kEncodeThreads * p.bpt < halfp) p.bpt *= 2;
+    p.binblocks = (halfp + kEncodeThreads * p.bpt - 1) / (kEncodeThreads * p.bpt);
+    int64_t ec = (n * p.binblocks + 1023) / 1024;
+    ec = ec < 64 ? 64 : (ec > kEncodeChunk ? kEncodeChunk : ec);
+    ec += ec & 1;
+    p.echunk = (int)ec;
+    p.max_echunks = (int)((n + ec - 1) / ec) + nkeys;
+    return p;
+}
+
+hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const LayoutDev& L,
+                         int nkeys, const float2* theta_rev, const double* theta_rev_d,
+                         float max_rev_x, float max_rev_y, int half, int halfp,
+                         const EncodeWork& w, float2* omega, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const EncodePlan p = encode_plan(n, halfp, nkeys);
+    const float2* xy2 = reinterpret_cast<const float2*>(xy);
+    hipLaunchKernelGGL(k_assign, dim3(p.nchunks), dim3(256), nkeys * sizeof(int), s, xy2, label,
+                       n, L, nkeys, w.key, w.hist, w.n_bad);
+    const size_t scan_lds = (2 * (size_t)nkeys + 1024) * sizeof(int);
+    if (scan_lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)scan_lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), scan_lds, s, w.hist,
+                       p.nchunks, nkeys, p.echunk, w.table, w.meta);
+    hipLaunchKernelGGL(k_scatter, dim3(p.nchunks), dim3(64), nkeys * sizeof(int), s, xy2, w.key,
+                       n, L, nkeys, bits_for(nkeys), w.hist, w.sorted, w.sorted_lo);
+    const double2* rev_d = reinterpret_cast<const double2*>(theta_rev_d);
+    const dim3 eg(p.max_echunks, p.binblocks);
+    switch (p.bpt) {
+        case 1:
+            hipLaunchKernelGGL(k_encode<1>, eg, dim3(kEncodeThreads), 0, s, w.sorted, w.sorted_lo,
+                               w.table, w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp,
+                               w.partial);
+            break;
+        case 2:
+            hipLaunchKernelGGL(k_encode<2>, eg, dim3(kEncodeThreads), 0, s, w.sorted, w.sorted_lo,
+                               w.table, w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp,
+                               w.partial);
+            break;
+        case 4:
+            hipLaunchKernelGGL(k_encode<4>, eg, dim3(kEncodeThreads), 0, s, w.sorted, w.sorted_lo,
+                               w.table, w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp,
+                               w.partial);
+            break;
+        default:
+            hipLaunchKernelGGL(k_encode<8>, eg, dim3(kEncodeThreads), 0, s, w.sorted, w.sorted_lo,
+                               w.table, w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp,
+                               w.partial);
+            break;
+    }
+    hipLaunchKernelGGL(k_reduce, dim3((half + 255) / 256, nkeys), dim3(256), 0, s, w.partial,
+                       w.meta, nkeys, half, halfp, omega);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm(const float2* omega, int nkeys, int half, int halfp, int D, float* scale,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_norm, dim3(nkeys), dim3(256), 0, s, omega, half, halfp, D, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_memories_export(const float2* omega, const double* theta_rad, const LayoutDev& L,
+                                  int nkeys, int half, int halfp, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_export, dim3((half + 1 + 255) / 256, nkeys), dim3(256), 0, s, omega,
+                       theta_rad, L, half, halfp, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_add(float2* dst, const float2* src, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+}  // namespace vsaogm

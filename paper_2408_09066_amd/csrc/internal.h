@@ -1,0 +1,102 @@
+// Internal declarations of the gfx950 VSA-OGM library: launch helpers and the
+// small structs the kernels share.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace vsaogm {
+
+constexpr int kMaxTilesPerAxis = 64;
+constexpr int kMaxKeys = 2 * kMaxTilesPerAxis * kMaxTilesPerAxis;  // 8192 memories
+constexpr int kAssignChunk = 2048;   // points per histogram / stable-scatter chunk
+constexpr int kEncodeChunk = 1024;   // points per encode work item (even, so pairs never straddle)
+constexpr int kEncodeThreads = 256;
+constexpr int kEncodeBpt = 8;        // spectrum bins per encode thread
+constexpr int kBinPad = 64;          // stored half spectra are padded to a multiple of this
+constexpr int kMaxRadius = 24;       // largest disk radius of the entropy filter
+// A phase bound (revolutions) above which a chunk is encoded with double-precision
+// phases; below it single precision keeps the phase error under ~4e-6 revolutions.
+constexpr float kWidePhaseRev = 64.0f;
+
+// Tile layout as the kernels see it.  Centres are computed on the host in double
+// precision, cx[tx] = x0 + (tx + 0.5) * (x1 - x0) / tiles_x.
+struct LayoutDev {
+    double x0, y0;
+    double inv_wx, inv_wy;  // used only to guess the nearest tile before the exact check
+    int tiles_x, tiles_y;
+    const double* cx;       // [tiles_x]
+    const double* cy;       // [tiles_y]
+};
+
+// One encode work item: a run of points of one memory (key) in the sorted buffer.
+struct EChunk {
+    int key;
+    int start;
+    int len;
+    int pad;
+};
+
+// One decode tile: a TM x TN block of one tile's cells, both classes.
+struct DTile {
+    int beta;
+    int r0, c0;       // first row / column of the block
+    int rend, cend;   // one past the last row / column of the tile's cells
+    int pad[3];
+};
+
+// ---- encode (encode.hip) -----------------------------------------------------------
+struct EncodeWork {
+    int* key;            // [cap_n]
+    float2* sorted;      // [cap_n] tile-local coordinates, grouped by key
+    float2* sorted_lo;   // [cap_n] rounding residuals of the local coordinates
+    int* hist;           // [cap_chunks][nkeys] per-chunk key counts, then bases
+    EChunk* table;       // [cap_echunks]
+    int* meta;           // [1 + 3 * nkeys]: n_echunks, key_ec_start[nkeys], key_ec_count[nkeys], key_count[nkeys]
+    float2* partial;     // [cap_echunks][halfp]
+    unsigned long long* n_bad;
+};
+
+// Launch geometry of one encode, shared by the host (buffer sizing) and the launcher.
+struct EncodePlan {
+    int nchunks;      // histogram / scatter chunks of kAssignChunk points
+    int bpt;          // bins per encode thread
+    int binblocks;    // bin blocks of kEncodeThreads * bpt bins
+    int echunk;       // points per encode work item (even)
+    int max_echunks;  // upper bound on work items: ceil(n / echunk) + nkeys
+};
+EncodePlan encode_plan(int64_t n, int halfp, int nkeys);
+
+hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const LayoutDev& L,
+                         int nkeys, const float2* theta_rev, const double* theta_rev_d,
+                         float max_rev_x, float max_rev_y, int half, int halfp,
+                         const EncodeWork& w, float2* omega, hipStream_t s);
+
+hipError_t launch_norm(const float2* omega, int nkeys, int half, int halfp, int D, float* scale,
+                       hipStream_t s);
+
+hipError_t launch_memories_export(const float2* omega, const double* theta_rad, const LayoutDev& L,
+                                  int nkeys, int half, int halfp, float* out, hipStream_t s);
+
+hipError_t launch_add(float2* dst, const float2* src, size_t n, hipStream_t s);
+
+// ---- decode (decode.hip) -----------------------------------------------------------
+// Location tables: tab[c][k] = exp(i * Theta_axis[k] * local[c]) for k < half, 0 for
+// half <= k < halfp; computed in double precision.  Stored as fp32 complex pairs.
+hipError_t launch_table_f32(const double* theta_rad, int axis, const double* local, int ncells,
+                            int half, int halfp, float2* tab, hipStream_t s);
+// Same table split into bf16 (or fp16) hi and lo parts: [c][2*halfp] hi, then lo.
+hipError_t launch_table_split(const double* theta_rad, int axis, const double* local, int ncells,
+                              int half, int halfp, bool fp16, void* hi, void* lo, hipStream_t s);
+
+hipError_t launch_decode(int precision, const DTile* tiles, int ntiles, const void* ex_hi,
+                         const void* ex_lo, const void* ey_hi, const void* ey_lo,
+                         const float2* omega, const float* scale, int halfp, int nx, int ny,
+                         float* heat, unsigned* hmax_u, float* hmax, hipStream_t s);
+
+// ---- classify (classify.hip) -------------------------------------------------------
+hipError_t launch_classify(const float* heat, const float* hmax, int nx, int ny, int r_occ,
+                           int r_emp, float rho, float* ogm, uint8_t* label, hipStream_t s);
+
+}  // namespace vsaogm

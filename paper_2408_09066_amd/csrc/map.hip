@@ -1,0 +1,538 @@
+// Host side of the C ABI (include/vsaogm.h): map objects, validation, buffer management and
+// the order of launches.  Every entry point catches C++ exceptions and returns a status.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "internal.h"
+#include "vsaogm.h"
+
+using namespace vsaogm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw Error(code, msg); }
+
+void hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return;
+    if (e == hipErrorOutOfMemory) fail(VSAOGM_ENOMEM, std::string(what) + ": out of device memory");
+    fail(VSAOGM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class F>
+int guarded(F&& f) {
+    try {
+        g_last_error.clear();
+        f();
+        return VSAOGM_OK;
+    } catch (const Error& e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return VSAOGM_ENOMEM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return VSAOGM_EDEVICE;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return VSAOGM_EDEVICE;
+    }
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        hip_check(hipGetDevice(&prev), "hipGetDevice");
+        if (prev != dev) hip_check(hipSetDevice(dev), "hipSetDevice");
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void alloc(size_t count, const char* what) {
+        release();
+        void* q = nullptr;
+        hip_check(hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)), what);
+        p = static_cast<T*>(q);
+        n = count;
+    }
+};
+
+__global__ void k_zero_words(unsigned* p, size_t n) {
+    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+void zero_async(void* p, size_t bytes, hipStream_t s) {
+    size_t words = bytes / 4;
+    if (words == 0) return;
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s,
+                       static_cast<unsigned*>(p), words);
+    hip_check(hipGetLastError(), "zero kernel");
+}
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+struct GridKey {
+    double x0, y0, res;
+    int nx, ny;
+    bool operator<(const GridKey& o) const {
+        return std::tie(x0, y0, res, nx, ny) < std::tie(o.x0, o.y0, o.res, o.nx, o.ny);
+    }
+};
+
+// Per-grid decode state: cell-to-tile split, local coordinates, tile list, tables.
+struct GridCache {
+    int nx = 0, ny = 0;
+    DevBuf<double> local_x, local_y;
+    DevBuf<DTile> tiles;
+    int ntiles = 0;
+    DevBuf<float2> ex32, ey32;  // FP32 tables [n][halfp]
+};
+
+}  // namespace
+
+struct vsaogm_map {
+    int device = 0;
+    int D = 0, half = 0, halfp = 0;
+    int tiles_x = 1, tiles_y = 1, nkeys = 2;
+    double x0 = 0, y0 = 0, x1 = 0, y1 = 0;
+    std::vector<double> theta;          // host copy [D][2]
+    std::vector<double> cx, cy;         // tile centres
+    float max_rev_x = 0.f, max_rev_y = 0.f;
+
+    DevBuf<double> d_cx, d_cy;
+    DevBuf<float2> d_rev;               // [halfp] Theta / (2 pi), fp32
+    DevBuf<double> d_rev_d;             // [halfp][2] Theta / (2 pi), fp64
+    DevBuf<double> d_theta;             // [half][2] Theta, rad/m
+    DevBuf<float2> d_omega;             // [nkeys][halfp] local-frame memories
+    DevBuf<float> d_scale;              // [nkeys]
+    DevBuf<unsigned> d_hmax_u;          // [2]
+    DevBuf<unsigned long long> d_bad;   // [1]
+
+    // encode workspace
+    int64_t cap_n = 0;
+    int cap_chunks = 0, cap_echunks = 0;
+    DevBuf<int> w_key, w_hist, w_meta;
+    DevBuf<float2> w_sorted, w_sorted_lo, w_partial;
+    DevBuf<EChunk> w_table;
+
+    std::map<GridKey, std::unique_ptr<GridCache>> grids;
+
+    LayoutDev layout() const {
+        LayoutDev L;
+        L.x0 = x0;
+        L.y0 = y0;
+        L.inv_wx = (double)tiles_x / (x1 - x0);
+        L.inv_wy = (double)tiles_y / (y1 - y0);
+        L.tiles_x = tiles_x;
+        L.tiles_y = tiles_y;
+        L.cx = d_cx.p;
+        L.cy = d_cy.p;
+        return L;
+    }
+};
+
+namespace {
+
+#pragma clang fp contract(off)
+// Tile centres exactly as written: x0 + (t + 0.5) * ((x1 - x0) / tiles), in double.
+std::vector<double> centres(double a0, double a1, int tiles) {
+    std::vector<double> c(tiles);
+    const double w = (a1 - a0) / (double)tiles;
+    for (int t = 0; t < tiles; ++t) c[t] = a0 + ((double)t + 0.5) * w;
+    return c;
+}
+
+double sq_dist(double x, double y, double mx, double my) {
+    const double dx = x - mx, dy = y - my;
+    return dx * dx + dy * dy;
+}
+#pragma clang fp contract(on)
+
+// Nearest centre along one axis (strict <, lowest index on ties).
+int nearest_1d(const std::vector<double>& c, double v) {
+    int best = 0;
+    double bd = INFINITY;
+    for (int t = 0; t < (int)c.size(); ++t) {
+        const double d = (v - c[t]) * (v - c[t]);
+        if (d < bd) {
+            bd = d;
+            best = t;
+        }
+    }
+    return best;
+}
+
+void ensure_encode_workspace(vsaogm_map* m, int64_t n, hipStream_t s) {
+    const EncodePlan p = encode_plan(n, m->halfp, m->nkeys);
+    if (n <= m->cap_n && p.nchunks <= m->cap_chunks && p.max_echunks <= m->cap_echunks) return;
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    const int64_t cap = std::max<int64_t>(n + n / 4, 4096);
+    const EncodePlan q = encode_plan(cap, m->halfp, m->nkeys);
+    const int chunks = std::max(q.nchunks, p.nchunks);
+    const int echunks = std::max(q.max_echunks, p.max_echunks);
+    m->w_key.alloc(cap, "encode keys");
+    m->w_sorted.alloc(cap, "encode sorted");
+    m->w_sorted_lo.alloc(cap, "encode sorted residuals");
+    m->w_hist.alloc((size_t)chunks * m->nkeys, "encode histogram");
+    m->w_table.alloc(echunks, "encode table");
+    m->w_partial.alloc((size_t)echunks * m->halfp, "encode partial spectra");
+    if (!m->w_meta.p) m->w_meta.alloc(1 + 3 * (size_t)m->nkeys, "encode meta");
+    m->cap_n = cap;
+    m->cap_chunks = chunks;
+    m->cap_echunks = echunks;
+}
+
+GridCache* grid_cache(vsaogm_map* m, const vsaogm_grid_desc* g, hipStream_t s) {
+    GridKey key{g->x0, g->y0, g->res, g->nx, g->ny};
+    auto it = m->grids.find(key);
+    if (it != m->grids.end()) return it->second.get();
+
+    // Columns and rows of each tile: every cell belongs to the tile with the nearest
+    // centre.  Along one axis the nearest centre is non-decreasing in the cell index, so
+    // each tile owns a contiguous range of columns and of rows.
+    std::vector<int> tcol(g->nx), trow(g->ny);
+    std::vector<double> lx(g->nx), ly(g->ny);
+    std::vector<char> near_tie_col(g->nx, 0), near_tie_row(g->ny, 0);
+    auto axis = [&](int ncell, double o, const std::vector<double>& c, std::vector<int>& t,
+                    std::vector<double>& loc, std::vector<char>& tie) {
+        for (int i = 0; i < ncell; ++i) {
+            const double v = o + ((double)i + 0.5) * g->res;
+            t[i] = nearest_1d(c, v);
+            loc[i] = v - c[t[i]];
+            if (i > 0 && t[i] < t[i - 1]) fail(VSAOGM_EINVAL, "grid cells are not ordered along an axis");
+            for (int u = 0; u < (int)c.size(); ++u) {
+                if (u == t[i]) continue;
+                const double d1 = (v - c[t[i]]) * (v - c[t[i]]), d2 = (v - c[u]) * (v - c[u]);
+                if (std::fabs(d2 - d1) <= 1e-9 * (d1 + d2) + 1e-300) tie[i] = 1;
+            }
+        }
+    };
+    axis(g->nx, g->x0, m->cx, tcol, lx, near_tie_col);
+    axis(g->ny, g->y0, m->cy, trow, ly, near_tie_row);
+    // Where an axis is close to a tie, confirm that the two-dimensional argmin (the
+    // definition) agrees with the per-axis split for every affected cell.
+    for (int j = 0; j < g->ny; ++j)
+        for (int i = 0; i < g->nx; ++i) {
+            if (!near_tie_col[i] && !near_tie_row[j]) continue;
+            const double x = g->x0 + ((double)i + 0.5) * g->res;
+            const double y = g->y0 + ((double)j + 0.5) * g->res;
+            int best = 0;
+            double bd = INFINITY;
+            for (int b = 0; b < m->tiles_x * m->tiles_y; ++b) {
+                const double d = sq_dist(x, y, m->cx[b % m->tiles_x], m->cy[b / m->tiles_x]);
+                if (d < bd) {
+                    bd = d;
+                    best = b;
+                }
+            }
+            if (best != trow[j] * m->tiles_x + tcol[i])
+                fail(VSAOGM_EINVAL, "a grid cell centre lies on a tile boundary in a way that "
+                                    "does not split into per-tile rows and columns");
+        }
+
+    auto gc = std::make_unique<GridCache>();
+    gc->nx = g->nx;
+    gc->ny = g->ny;
+    std::vector<DTile> tl;
+    constexpr int TM = 64, TN = 64;
+    for (int ty = 0; ty < m->tiles_y; ++ty) {
+        const int r0 = (int)(std::lower_bound(trow.begin(), trow.end(), ty) - trow.begin());
+        const int r1 = (int)(std::upper_bound(trow.begin(), trow.end(), ty) - trow.begin());
+        if (r0 >= r1) continue;
+        for (int tx = 0; tx < m->tiles_x; ++tx) {
+            const int c0 = (int)(std::lower_bound(tcol.begin(), tcol.end(), tx) - tcol.begin());
+            const int c1 = (int)(std::upper_bound(tcol.begin(), tcol.end(), tx) - tcol.begin());
+            if (c0 >= c1) continue;
+            for (int r = r0; r < r1; r += TM)
+                for (int c = c0; c < c1; c += TN) {
+                    DTile d{};
+                    d.beta = ty * m->tiles_x + tx;
+                    d.r0 = r;
+                    d.c0 = c;
+                    d.rend = r1;
+                    d.cend = c1;
+                    tl.push_back(d);
+                }
+        }
+    }
+    gc->ntiles = (int)tl.size();
+    gc->tiles.alloc(tl.size(), "decode tile list");
+    gc->local_x.alloc(g->nx, "local x");
+    gc->local_y.alloc(g->ny, "local y");
+    gc->ex32.alloc((size_t)g->nx * m->halfp, "x location table");
+    gc->ey32.alloc((size_t)g->ny * m->halfp, "y location table");
+    hip_check(hipMemcpy(gc->tiles.p, tl.data(), tl.size() * sizeof(DTile), hipMemcpyHostToDevice),
+              "copy tile list");
+    hip_check(hipMemcpy(gc->local_x.p, lx.data(), lx.size() * sizeof(double), hipMemcpyHostToDevice),
+              "copy local x");
+    hip_check(hipMemcpy(gc->local_y.p, ly.data(), ly.size() * sizeof(double), hipMemcpyHostToDevice),
+              "copy local y");
+    hip_check(launch_table_f32(m->d_theta.p, 0, gc->local_x.p, g->nx, m->half, m->halfp, gc->ex32.p, s),
+              "x table");
+    hip_check(launch_table_f32(m->d_theta.p, 1, gc->local_y.p, g->ny, m->half, m->halfp, gc->ey32.p, s),
+              "y table");
+    GridCache* raw = gc.get();
+    m->grids.emplace(key, std::move(gc));
+    return raw;
+}
+
+void check_grid(const vsaogm_grid_desc* g) {
+    if (!g) fail(VSAOGM_EINVAL, "grid is NULL");
+    if (g->nx < 1 || g->ny < 1) fail(VSAOGM_EINVAL, "grid nx and ny must be >= 1");
+    if ((int64_t)g->nx * g->ny > (int64_t)1 << 31) fail(VSAOGM_EINVAL, "grid too large");
+    if (!is_finite(g->x0) || !is_finite(g->y0) || !is_finite(g->res) || !(g->res > 0))
+        fail(VSAOGM_EINVAL, "grid origin must be finite and res > 0");
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t vsaogm_version(void) { return 100; }
+
+const char* vsaogm_last_error(void) { return g_last_error.c_str(); }
+
+int vsaogm_map_create(const vsaogm_map_desc* d, vsaogm_map** out) {
+    return guarded([&] {
+        if (!d || !out) fail(VSAOGM_EINVAL, "desc and out must not be NULL");
+        *out = nullptr;
+        const int D = d->dim;
+        if (D < 4 || (D & 1)) fail(VSAOGM_EINVAL, "dim must be even and >= 4");
+        if (D > (1 << 22)) fail(VSAOGM_EINVAL, "dim too large");
+        if (!d->theta) fail(VSAOGM_EINVAL, "theta is NULL");
+        if (d->tiles_x < 1 || d->tiles_y < 1 || d->tiles_x > kMaxTilesPerAxis ||
+            d->tiles_y > kMaxTilesPerAxis)
+            fail(VSAOGM_EINVAL, "tiles per axis must be in 1..64");
+        if (!is_finite(d->x0) || !is_finite(d->x1) || !is_finite(d->y0) || !is_finite(d->y1) ||
+            !(d->x1 > d->x0) || !(d->y1 > d->y0))
+            fail(VSAOGM_EINVAL, "layout rectangle must be finite with x1 > x0 and y1 > y0");
+        int ndev = 0;
+        hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+        if (d->device < 0 || d->device >= ndev) fail(VSAOGM_EINVAL, "no such device");
+        const double* th = d->theta;
+        for (int k = 0; k < 2 * D; ++k)
+            if (!is_finite(th[k])) fail(VSAOGM_EINVAL, "theta must be finite");
+        const int half = D / 2;
+        if (th[0] != 0.0 || th[1] != 0.0 || th[2 * half] != 0.0 || th[2 * half + 1] != 0.0)
+            fail(VSAOGM_EINVAL, "theta[0] and theta[D/2] must be zero");
+        for (int k = 1; k < half; ++k)
+            for (int a = 0; a < 2; ++a)
+                if (th[2 * (D - k) + a] != -th[2 * k + a])
+                    fail(VSAOGM_EINVAL, "theta must be conjugate-symmetric: theta[D-k] = -theta[k]");
+
+        auto m = std::make_unique<vsaogm_map>();
+        m->device = d->device;
+        m->D = D;
+        m->half = half;
+        m->halfp = (half + kBinPad - 1) / kBinPad * kBinPad;
+        m->tiles_x = d->tiles_x;
+        m->tiles_y = d->tiles_y;
+        m->nkeys = 2 * d->tiles_x * d->tiles_y;
+        m->x0 = d->x0;
+        m->y0 = d->y0;
+        m->x1 = d->x1;
+        m->y1 = d->y1;
+        m->theta.assign(th, th + 2 * (size_t)D);
+        m->cx = centres(d->x0, d->x1, d->tiles_x);
+        m->cy = centres(d->y0, d->y1, d->tiles_y);
+
+        std::vector<float2> rev(m->halfp, make_float2(0.f, 0.f));
+        std::vector<double> rev_d(2 * (size_t)m->halfp, 0.0);
+        const double inv2pi = 1.0 / (2.0 * M_PI);
+        for (int k = 0; k < half; ++k) {
+            const double a = th[2 * k] * inv2pi, b = th[2 * k + 1] * inv2pi;
+            rev[k] = make_float2((float)a, (float)b);
+            rev_d[2 * k] = a;
+            rev_d[2 * k + 1] = b;
+            m->max_rev_x = std::max(m->max_rev_x, std::fabs(rev[k].x));
+            m->max_rev_y = std::max(m->max_rev_y, std::fabs(rev[k].y));
+        }
+
+        DeviceGuard guard(m->device);
+        m->d_cx.alloc(m->tiles_x, "tile centres x");
+        m->d_cy.alloc(m->tiles_y, "tile centres y");
+        m->d_rev.alloc(m->halfp, "theta (rev, fp32)");
+        m->d_rev_d.alloc(2 * (size_t)m->halfp, "theta (rev, fp64)");
+        m->d_theta.alloc(2 * (size_t)half, "theta (rad)");
+        m->d_omega.alloc((size_t)m->nkeys * m->halfp, "memories");
+        m->d_scale.alloc(m->nkeys, "memory scales");
+        m->d_hmax_u.alloc(2, "class maxima");
+        m->d_bad.alloc(1, "rejected-label counter");
+        hip_check(hipMemcpy(m->d_cx.p, m->cx.data(), m->cx.size() * 8, hipMemcpyHostToDevice), "copy");
+        hip_check(hipMemcpy(m->d_cy.p, m->cy.data(), m->cy.size() * 8, hipMemcpyHostToDevice), "copy");
+        hip_check(hipMemcpy(m->d_rev.p, rev.data(), rev.size() * sizeof(float2), hipMemcpyHostToDevice),
+                  "copy");
+        hip_check(hipMemcpy(m->d_rev_d.p, rev_d.data(), rev_d.size() * 8, hipMemcpyHostToDevice), "copy");
+        hip_check(hipMemcpy(m->d_theta.p, th, 2 * (size_t)half * 8, hipMemcpyHostToDevice), "copy");
+        zero_async(m->d_omega.p, m->d_omega.n * sizeof(float2), nullptr);
+        zero_async(m->d_bad.p, sizeof(unsigned long long), nullptr);
+        hip_check(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
+        *out = m.release();
+    });
+}
+
+int vsaogm_map_destroy(vsaogm_map* m) {
+    if (!m) return VSAOGM_OK;
+    return guarded([&] {
+        DeviceGuard guard(m->device);
+        (void)hipDeviceSynchronize();
+        delete m;
+    });
+}
+
+int vsaogm_map_info(const vsaogm_map* m, int64_t* n_memories, int32_t* dim) {
+    return guarded([&] {
+        if (!m) fail(VSAOGM_EINVAL, "map is NULL");
+        if (n_memories) *n_memories = m->nkeys;
+        if (dim) *dim = m->D;
+    });
+}
+
+int vsaogm_map_reset(vsaogm_map* m, vsaogm_stream stream) {
+    return guarded([&] {
+        if (!m) fail(VSAOGM_EINVAL, "map is NULL");
+        DeviceGuard guard(m->device);
+        zero_async(m->d_omega.p, m->d_omega.n * sizeof(float2), (hipStream_t)stream);
+    });
+}
+
+int vsaogm_encode(vsaogm_map* m, const float* xy, const uint8_t* label, int64_t n,
+                  vsaogm_stream stream) {
+    return guarded([&] {
+        if (!m) fail(VSAOGM_EINVAL, "map is NULL");
+        if (n < 0) fail(VSAOGM_EINVAL, "n must be >= 0");
+        if (n == 0) return;
+        if (!xy || !label) fail(VSAOGM_EINVAL, "xy and label must not be NULL");
+        if (n > ((int64_t)1 << 31) - (int64_t)kAssignChunk * 2)
+            fail(VSAOGM_EINVAL, "n too large for one call");
+        DeviceGuard guard(m->device);
+        hipStream_t s = (hipStream_t)stream;
+        ensure_encode_workspace(m, n, s);
+        EncodeWork w;
+        w.key = m->w_key.p;
+        w.sorted = m->w_sorted.p;
+        w.sorted_lo = m->w_sorted_lo.p;
+        w.hist = m->w_hist.p;
+        w.table = m->w_table.p;
+        w.meta = m->w_meta.p;
+        w.partial = m->w_partial.p;
+        w.n_bad = m->d_bad.p;
+        hip_check(launch_encode(xy, label, n, m->layout(), m->nkeys, m->d_rev.p, m->d_rev_d.p,
+                                m->max_rev_x, m->max_rev_y, m->half, m->halfp, w, m->d_omega.p, s),
+                  "encode launch");
+    });
+}
+
+int vsaogm_map_take_rejected(vsaogm_map* m, vsaogm_stream stream, int64_t* n_rejected) {
+    return guarded([&] {
+        if (!m || !n_rejected) fail(VSAOGM_EINVAL, "map and n_rejected must not be NULL");
+        DeviceGuard guard(m->device);
+        hipStream_t s = (hipStream_t)stream;
+        unsigned long long v = 0;
+        hip_check(hipMemcpyAsync(&v, m->d_bad.p, sizeof(v), hipMemcpyDeviceToHost, s), "read counter");
+        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+        zero_async(m->d_bad.p, sizeof(v), s);
+        *n_rejected = (int64_t)v;
+    });
+}
+
+int vsaogm_decode(vsaogm_map* m, const vsaogm_grid_desc* g, int32_t precision, float* heat,
+                  float* hmax, vsaogm_stream stream) {
+    return guarded([&] {
+        if (!m) fail(VSAOGM_EINVAL, "map is NULL");
+        check_grid(g);
+        if (!heat || !hmax) fail(VSAOGM_EINVAL, "heat and hmax must not be NULL");
+        if (precision != VSAOGM_FP32) fail(VSAOGM_EINVAL, "precision not available");
+        DeviceGuard guard(m->device);
+        hipStream_t s = (hipStream_t)stream;
+        GridCache* gc = grid_cache(m, g, s);
+        hip_check(launch_norm(m->d_omega.p, m->nkeys, m->half, m->halfp, m->D, m->d_scale.p, s),
+                  "norm launch");
+        hip_check(launch_decode(precision, gc->tiles.p, gc->ntiles, gc->ex32.p, nullptr, gc->ey32.p,
+                                nullptr, m->d_omega.p, m->d_scale.p, m->halfp, g->nx, g->ny, heat,
+                                m->d_hmax_u.p, hmax, s),
+                  "decode launch");
+    });
+}
+
+int vsaogm_classify(const vsaogm_grid_desc* g, const float* heat, const float* hmax, int32_t r_occ,
+                    int32_t r_emp, float rho, float* ogm, uint8_t* label, int32_t device,
+                    vsaogm_stream stream) {
+    return guarded([&] {
+        if (!g || g->nx < 1 || g->ny < 1) fail(VSAOGM_EINVAL, "grid nx and ny must be >= 1");
+        if (!heat || !hmax || !label) fail(VSAOGM_EINVAL, "heat, hmax and label must not be NULL");
+        if (r_occ < 0 || r_emp < 0 || r_occ > kMaxRadius || r_emp > kMaxRadius)
+            fail(VSAOGM_EINVAL, "disk radii must be in 0..24");
+        if (!std::isfinite(rho)) fail(VSAOGM_EINVAL, "rho must be finite");
+        int ndev = 0;
+        hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+        if (device < 0 || device >= ndev) fail(VSAOGM_EINVAL, "no such device");
+        DeviceGuard guard(device);
+        hip_check(launch_classify(heat, hmax, g->nx, g->ny, r_occ, r_emp, rho, ogm, label,
+                                  (hipStream_t)stream),
+                  "classify launch");
+    });
+}
+
+int vsaogm_memories(const vsaogm_map* m, float* out, vsaogm_stream stream) {
+    return guarded([&] {
+        if (!m || !out) fail(VSAOGM_EINVAL, "map and out must not be NULL");
+        DeviceGuard guard(m->device);
+        hip_check(launch_memories_export(m->d_omega.p, m->d_theta.p, m->layout(), m->nkeys, m->half,
+                                         m->halfp, out, (hipStream_t)stream),
+                  "export launch");
+    });
+}
+
+int vsaogm_fuse(vsaogm_map* dst, const vsaogm_map* src, vsaogm_stream stream) {
+    return guarded([&] {
+        if (!dst || !src) fail(VSAOGM_EINVAL, "maps must not be NULL");
+        if (dst == src) fail(VSAOGM_EINVAL, "cannot fuse a map into itself");
+        if (dst->device != src->device) fail(VSAOGM_EINVAL, "maps live on different devices");
+        if (dst->D != src->D || dst->theta != src->theta)
+            fail(VSAOGM_EINVAL, "maps must share the axis vectors (same Theta)");
+        if (dst->tiles_x != src->tiles_x || dst->tiles_y != src->tiles_y || dst->x0 != src->x0 ||
+            dst->y0 != src->y0 || dst->x1 != src->x1 || dst->y1 != src->y1)
+            fail(VSAOGM_EINVAL, "maps must share the tiling of the global frame");
+        DeviceGuard guard(dst->device);
+        hip_check(launch_add(dst->d_omega.p, src->d_omega.p, dst->d_omega.n, (hipStream_t)stream),
+                  "fuse launch");
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,185 @@
+"""ctypes binding of ``libvsaogm.so`` (the C ABI in include/vsaogm.h).
+
+Argument marshalling only: torch tensors provide device memory and the current HIP stream;
+every step of the path runs in the library's kernels.  Loading fails loudly when the built
+library is missing -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libvsaogm.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16x3": 3}
+
+EXPORTED = [
+    "vsaogm_version", "vsaogm_last_error", "vsaogm_map_create", "vsaogm_map_destroy",
+    "vsaogm_map_info", "vsaogm_map_reset", "vsaogm_encode", "vsaogm_map_take_rejected",
+    "vsaogm_decode", "vsaogm_classify", "vsaogm_memories", "vsaogm_fuse",
+]
+
+
+class VsaogmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"vsaogm error {code}: {msg}")
+        self.code = code
+
+
+class MapDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("theta", ctypes.c_void_p),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double),
+                ("x1", ctypes.c_double), ("y1", ctypes.c_double),
+                ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32),
+                ("device", ctypes.c_int32)]
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double), ("res", ctypes.c_double),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2408_09066_amd.build.build()")
+    L = ctypes.CDLL(path)
+    P, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    L.vsaogm_version.restype = i32
+    L.vsaogm_last_error.restype = ctypes.c_char_p
+    L.vsaogm_map_create.argtypes = [ctypes.POINTER(MapDesc), ctypes.POINTER(P)]
+    L.vsaogm_map_destroy.argtypes = [P]
+    L.vsaogm_map_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    L.vsaogm_map_reset.argtypes = [P, P]
+    L.vsaogm_encode.argtypes = [P, P, P, i64, P]
+    L.vsaogm_map_take_rejected.argtypes = [P, P, ctypes.POINTER(i64)]
+    L.vsaogm_decode.argtypes = [P, ctypes.POINTER(GridDesc), i32, P, P, P]
+    L.vsaogm_classify.argtypes = [ctypes.POINTER(GridDesc), P, P, i32, i32, f32, P, P, i32, P]
+    L.vsaogm_memories.argtypes = [P, P, P]
+    L.vsaogm_fuse.argtypes = [P, P, P]
+    for name in EXPORTED:
+        if name not in ("vsaogm_version", "vsaogm_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(rc: int):
+    if rc != OK:
+        msg = load().vsaogm_last_error().decode(errors="replace")
+        raise VsaogmError(rc, msg)
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr() if t is not None else 0)
+
+
+def grid_desc(grid: Tuple[float, float, float], nx: int, ny: int) -> GridDesc:
+    return GridDesc(float(grid[0]), float(grid[1]), float(grid[2]), int(nx), int(ny))
+
+
+class Map:
+    """A set of 2*tiles_x*tiles_y memory vectors on one GPU (Sec. III-B)."""
+
+    def __init__(self, theta: np.ndarray, layout: Sequence[float], tiles: Sequence[int],
+                 device: int = 0):
+        L = load()
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        self.D = int(th.shape[0])
+        self.tiles = (int(tiles[0]), int(tiles[1]))
+        self.device = int(device)
+        d = MapDesc(self.D, th.ctypes.data, float(layout[0]), float(layout[1]), float(layout[2]),
+                    float(layout[3]), self.tiles[0], self.tiles[1], self.device)
+        h = ctypes.c_void_p()
+        check(L.vsaogm_map_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.n_memories = 2 * self.tiles[0] * self.tiles[1]
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().vsaogm_map_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset(self, stream=None):
+        check(load().vsaogm_map_reset(self._h, _stream(stream)))
+
+    def encode(self, xy, label, stream=None):
+        """xy: float32 [n][2] cuda tensor, label: uint8 [n] cuda tensor."""
+        n = int(xy.shape[0])
+        assert xy.is_cuda and label.is_cuda and xy.is_contiguous() and label.is_contiguous()
+        assert str(xy.dtype) == "torch.float32" and str(label.dtype) == "torch.uint8"
+        assert tuple(xy.shape) == (n, 2) and tuple(label.shape) == (n,)
+        check(load().vsaogm_encode(self._h, _ptr(xy), _ptr(label), n, _stream(stream)))
+
+    def take_rejected(self, stream=None) -> int:
+        v = ctypes.c_int64()
+        check(load().vsaogm_map_take_rejected(self._h, _stream(stream), ctypes.byref(v)))
+        return int(v.value)
+
+    def decode(self, grid, nx: int, ny: int, precision: str = "fp32", heat=None, hmax=None,
+               stream=None):
+        import torch
+        dev = torch.device("cuda", self.device)
+        if heat is None:
+            heat = torch.empty((2, ny, nx), dtype=torch.float32, device=dev)
+        if hmax is None:
+            hmax = torch.empty(2, dtype=torch.float32, device=dev)
+        assert heat.is_contiguous() and tuple(heat.shape) == (2, ny, nx)
+        g = grid_desc(grid, nx, ny)
+        check(load().vsaogm_decode(self._h, ctypes.byref(g), PRECISIONS[precision], _ptr(heat),
+                                   _ptr(hmax), _stream(stream)))
+        return heat, hmax
+
+    def memories(self, out=None, stream=None):
+        """Paper-frame memories, float32 [2R][D/2+1][2]."""
+        import torch
+        if out is None:
+            out = torch.empty((self.n_memories, self.D // 2 + 1, 2), dtype=torch.float32,
+                              device=torch.device("cuda", self.device))
+        check(load().vsaogm_memories(self._h, _ptr(out), _stream(stream)))
+        return out
+
+    def fuse_from(self, other: "Map", stream=None):
+        check(load().vsaogm_fuse(self._h, other._h, _stream(stream)))
+
+
+def classify(heat, hmax, r_occ: int, r_emp: int, rho: float = 0.0, ogm=None, label=None,
+             device: int = 0, stream=None):
+    import torch
+    _, ny, nx = heat.shape
+    dev = heat.device
+    if label is None:
+        label = torch.empty((ny, nx), dtype=torch.uint8, device=dev)
+    if ogm is None:
+        ogm = torch.empty((ny, nx), dtype=torch.float32, device=dev)
+    g = GridDesc(0.0, 0.0, 1.0, int(nx), int(ny))
+    check(load().vsaogm_classify(ctypes.byref(g), _ptr(heat), _ptr(hmax), int(r_occ), int(r_emp),
+                                 float(rho), _ptr(ogm), _ptr(label), int(device), _stream(stream)))
+    return ogm, label
