@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Benchmark of the VSA-OGM hot path on one MI355X.
+
+One step is one full map update of the "world40" workload, with every input already resident
+in HBM: 50 lidar scans of 1080 beams in a 40 m x 40 m world, 54 000 occupied beam ends and
+540 000 empty samples (594 000 points), D = 8192, l = 0.1 m, 4 x 4 tiles (32 memories),
+an 800 x 800 grid at 0.05 m and disk radius 3.  The step resets the memories, encodes and
+bundles every point, decodes both class heatmaps (fp32 similarity GEMM) and classifies the
+grid (entropy, softmax difference, threshold).
+
+Printed: one JSON line with the whole-step throughput (heatmap cells decoded per second),
+points encoded per second, per-update latency percentiles, the roofline of the dominant
+kernel and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_MFMA_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0}
+# Issue-limited complex-exponential rate of the encode kernel: 256 CUs x 2.4 GHz x 64 lanes
+# per clock, over 6 issue slots per complex exponential (per pair of points and bin: 4 phase
+# FMA/MUL, 2 accumulate FMA, 3 half-rate transcendentals of 2 slots each = 12 slots).
+PEAK_CEXP_TPS = 256 * 2.4e9 * 64 / 6 / 1e12
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
+
+
+def cpu_baseline(w, budget_s: float):
+    """Time the FP64 oracle on a bounded sample of the workload and scale to cells/s."""
+    import oracle
+    oracle.lib()
+    rng = np.random.default_rng(np.random.SeedSequence([2408, 99]))
+    # encode: a prefix of the points, sized from a short probe to about budget/2 seconds
+    probe = 500
+    t = time.perf_counter()
+    oracle.encode(w.theta, w.layout, w.tiles, w.xy[:probe], w.label[:probe])
+    dt = max(time.perf_counter() - t, 1e-6)
+    n_enc = int(min(w.n, max(probe, probe * (0.5 * budget_s) / dt)))
+    t = time.perf_counter()
+    omega, _ = oracle.encode(w.theta, w.layout, w.tiles, w.xy[:n_enc], w.label[:n_enc])
+    t_enc = time.perf_counter() - t
+    # decode: random cells, sized to about budget/3 seconds
+    ncell = w.nx * w.ny
+    cells = rng.choice(ncell, size=64, replace=False)
+    t = time.perf_counter()
+    oracle.similarity_cells(w.theta, w.layout, w.tiles, omega, w.grid, w.nx, cells)
+    dt = max(time.perf_counter() - t, 1e-6)
+    n_dec = int(min(ncell, max(64, 64 * (budget_s / 3) / dt)))
+    cells = rng.choice(ncell, size=n_dec, replace=False)
+    t = time.perf_counter()
+    oracle.similarity_cells(w.theta, w.layout, w.tiles, omega, w.grid, w.nx, cells)
+    t_dec = time.perf_counter() - t
+    # post-processing: a 200 x 200 sub-grid of synthetic similarity values
+    sub = 200
+    P = rng.normal(0.0, 0.1, size=(2, sub, sub))
+    t = time.perf_counter()
+    oracle.postprocess(P, w.r_occ, w.r_emp, w.rho)
+    t_cls = time.perf_counter() - t
+    step = t_enc * (w.n / n_enc) + t_dec * (ncell / n_dec) + t_cls * (ncell / (sub * sub))
+    return {
+        "value": ncell / step,
+        "unit": "cells/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"encode of the first {n_enc} of {w.n} points ({t_enc:.2f} s), similarity at "
+                   f"{n_dec} random cells of {ncell} ({t_dec:.2f} s), entropy/softmax/threshold on a "
+                   f"{sub}x{sub} sub-grid ({t_cls:.2f} s); scaled to one full update "
+                   f"({step:.1f} s)"),
+        "points_per_s": n_enc / t_enc,
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="world40")
+    ap.add_argument("--precision", default="fp32", choices=["fp32"])
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of oracle work for the CPU baseline (0 disables it)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the hot path here is the single-GPU kernel set)", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2408_09066_amd import native, synth
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    native.load()
+    torch.cuda.set_device(0)
+    w = synth.workload(args.workload)
+    dev = torch.device("cuda", 0)
+    xy = torch.from_numpy(w.xy).to(dev)
+    lab = torch.from_numpy(w.label).to(dev)
+    heat = torch.empty((2, w.ny, w.nx), dtype=torch.float32, device=dev)
+    hmax = torch.empty(2, dtype=torch.float32, device=dev)
+    ogm = torch.empty((w.ny, w.nx), dtype=torch.float32, device=dev)
+    out_lab = torch.empty((w.ny, w.nx), dtype=torch.uint8, device=dev)
+    m = native.Map(w.theta, w.layout, w.tiles, device=0)
+
+    def step():
+        m.reset()
+        m.encode(xy, lab)
+        m.decode(w.grid, w.nx, w.ny, args.precision, heat=heat, hmax=hmax)
+        native.classify(heat, hmax, w.r_occ, w.r_emp, w.rho, ogm=ogm, label=out_lab)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    E = torch.cuda.Event
+    step_ev = [(E(enable_timing=True), E(enable_timing=True)) for _ in range(K)]
+    stage_ev = {s: [(E(enable_timing=True), E(enable_timing=True)) for _ in range(K)]
+                for s in native.STAGES}
+    # torch creates an event on its first record; record each once so that its handle
+    # exists before the library records it around the stage's kernel
+    for evs in stage_ev.values():
+        for a, b in evs:
+            a.record()
+            b.record()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        for s in native.STAGES:
+            native.profile_events(s, *stage_ev[s][i])
+        step_ev[i][0].record()
+        step()
+        step_ev[i][1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for s in native.STAGES:
+        native.profile_events(s, None, None)
+
+    elapsed = t1 - t0
+    ms_step = elapsed / K * 1e3
+    lat = [a.elapsed_time(b) for a, b in step_ev]
+    stage_ms = {s: float(np.mean([a.elapsed_time(b) for a, b in stage_ev[s]])) for s in native.STAGES}
+    ncell = w.nx * w.ny
+    half = w.D // 2
+    enc_cexp = w.n * (half - 1)
+    dec_flop = 4.0 * w.D * ncell
+    cls_bytes = 13.0 * ncell
+    stages = {
+        "encode": {"bound": "alu", "achieved": enc_cexp / (stage_ms["encode"] * 1e-3) / 1e12,
+                   "peak": PEAK_CEXP_TPS, "unit": "Tcexp/s", "ms": stage_ms["encode"]},
+        "decode": {"bound": "mfma", "achieved": dec_flop / (stage_ms["decode"] * 1e-3) / 1e12,
+                   "peak": PEAK_MFMA_TFLOPS[args.precision], "unit": "TFLOP/s",
+                   "ms": stage_ms["decode"]},
+        "classify": {"bound": "hbm", "achieved": cls_bytes / (stage_ms["classify"] * 1e-3) / 1e9,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "ms": stage_ms["classify"]},
+    }
+    for v in stages.values():
+        v["frac"] = v["achieved"] / v["peak"]
+    dom = max(stages, key=lambda s: stages[s]["ms"])
+    d = stages[dom]
+    roof = {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
+            "frac": d["frac"], "traffic": None, "kernel": dom}
+
+    result = {
+        "metric": "heatmap cells decoded/sec + points encoded/sec; p50/p99 map-update latency",
+        "value": ncell * K / elapsed,
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{w.name}: {w.n} points ({int(w.label.sum())} occupied), D={w.D}, "
+                         f"l={w.ell} m, {w.tiles[0]}x{w.tiles[1]} tiles, {w.nx}x{w.ny} grid at "
+                         f"{w.grid[2]} m, disk r={w.r_occ}"),
+            "precision": args.precision,
+        },
+        "points_per_s": w.n * K / elapsed,
+        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
+        "stages": stages,
+        "roofline": roof,
+    }
+    m.close()
+    if args.cpu_budget > 0:
+        result["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -176,6 +176,17 @@ int vsaogm_memories(const vsaogm_map* map, float* out, vsaogm_stream stream);
  */
 int vsaogm_fuse(vsaogm_map* dst, const vsaogm_map* src, vsaogm_stream stream);
 
+/*
+ * Profiling hook: record the given HIP events (hipEvent_t) immediately before and
+ * after every launch of one stage's main kernel, on the stream it is launched on:
+ *   stage 0  encode: the sin/cos-and-accumulate kernel,
+ *   stage 1  decode: the similarity GEMM,
+ *   stage 2  classify: the entropy / softmax / threshold kernel.
+ * Passing NULL events turns the stage's recording off.  Process-wide; not for use
+ * while other threads launch the same stage.
+ */
+int vsaogm_profile_events(int32_t stage, void* begin_event, void* end_event);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,8 +81,10 @@ hipError_t launch_classify(const float* heat, const float* hmax, int nx, int ny,
                            int r_emp, float rho, float* ogm, uint8_t* label, hipStream_t s) {
     const int R = r_occ > r_emp ? r_occ : r_emp;
     const size_t lds = 2 * (size_t)(TX + 2 * R) * (TY + 2 * R) * sizeof(float);
+    profile_begin(kStageClassify, s);
     hipLaunchKernelGGL(k_classify, dim3((nx + TX - 1) / TX, (ny + TY - 1) / TY), dim3(256), lds, s,
                        heat, hmax, nx, ny, r_occ, r_emp, rho, ogm, label);
+    profile_end(kStageClassify, s);
     return hipGetLastError();
 }
 

@@ -209,9 +209,11 @@ hipError_t launch_decode(int precision, const DTile* tiles, int ntiles, const vo
     (void)ey_lo;
     if (precision != 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_hmax_init, dim3(1), dim3(64), 0, s, hmax_u);
+    profile_begin(kStageDecode, s);
     hipLaunchKernelGGL(k_decode_f32, dim3(ntiles), dim3(256), 0, s, tiles,
                        static_cast<const float2*>(ex_hi), static_cast<const float2*>(ey_hi),
                        omega, scale, halfp, nx, ny, heat, hmax_u);
+    profile_end(kStageDecode, s);
     hipLaunchKernelGGL(k_hmax_final, dim3(1), dim3(64), 0, s, hmax_u, hmax);
     return hipGetLastError();
 }

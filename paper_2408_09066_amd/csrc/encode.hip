@@ -415,6 +415,7 @@ hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const
                        n, L, nkeys, bits_for(nkeys), w.hist, w.sorted, w.sorted_lo);
     const double2* rev_d = reinterpret_cast<const double2*>(theta_rev_d);
     const dim3 eg(p.max_echunks, p.binblocks);
+    profile_begin(kStageEncode, s);
     switch (p.bpt) {
         case 1:
             hipLaunchKernelGGL(k_encode<1>, eg, dim3(kEncodeThreads), 0, s, w.sorted, w.sorted_lo,
@@ -437,6 +438,7 @@ hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const
                                w.partial);
             break;
     }
+    profile_end(kStageEncode, s);
     hipLaunchKernelGGL(k_reduce, dim3((half + 255) / 256, nkeys), dim3(256), 0, s, w.partial,
                        w.meta, nkeys, half, halfp, omega);
     return hipGetLastError();

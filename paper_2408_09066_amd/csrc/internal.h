@@ -46,6 +46,11 @@ struct DTile {
     int pad[3];
 };
 
+// ---- profiling hook (map.hip) --------------------------------------------------------
+enum ProfileStage { kStageEncode = 0, kStageDecode = 1, kStageClassify = 2, kNumStages = 3 };
+void profile_begin(int stage, hipStream_t s);
+void profile_end(int stage, hipStream_t s);
+
 // ---- encode (encode.hip) -----------------------------------------------------------
 struct EncodeWork {
     int* key;            // [cap_n]

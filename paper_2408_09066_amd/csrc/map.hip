@@ -123,7 +123,21 @@ struct GridCache {
     DevBuf<float2> ex32, ey32;  // FP32 tables [n][halfp]
 };
 
+struct ProfileSlot {
+    hipEvent_t begin = nullptr, end = nullptr;
+};
+ProfileSlot g_profile[kNumStages];
+
 }  // namespace
+
+namespace vsaogm {
+void profile_begin(int stage, hipStream_t s) {
+    if (g_profile[stage].begin) (void)hipEventRecord(g_profile[stage].begin, s);
+}
+void profile_end(int stage, hipStream_t s) {
+    if (g_profile[stage].end) (void)hipEventRecord(g_profile[stage].end, s);
+}
+}  // namespace vsaogm
 
 struct vsaogm_map {
     int device = 0;
@@ -532,6 +546,14 @@ int vsaogm_fuse(vsaogm_map* dst, const vsaogm_map* src, vsaogm_stream stream) {
         DeviceGuard guard(dst->device);
         hip_check(launch_add(dst->d_omega.p, src->d_omega.p, dst->d_omega.n, (hipStream_t)stream),
                   "fuse launch");
+    });
+}
+
+int vsaogm_profile_events(int32_t stage, void* begin_event, void* end_event) {
+    return guarded([&] {
+        if (stage < 0 || stage >= kNumStages) fail(VSAOGM_EINVAL, "unknown stage");
+        g_profile[stage].begin = static_cast<hipEvent_t>(begin_event);
+        g_profile[stage].end = static_cast<hipEvent_t>(end_event);
     });
 }
 

@@ -22,6 +22,7 @@ EXPORTED = [
     "vsaogm_version", "vsaogm_last_error", "vsaogm_map_create", "vsaogm_map_destroy",
     "vsaogm_map_info", "vsaogm_map_reset", "vsaogm_encode", "vsaogm_map_take_rejected",
     "vsaogm_decode", "vsaogm_classify", "vsaogm_memories", "vsaogm_fuse",
+    "vsaogm_profile_events",
 ]
 
 
@@ -68,6 +69,7 @@ def load(path: str = LIB_PATH):
     L.vsaogm_classify.argtypes = [ctypes.POINTER(GridDesc), P, P, i32, i32, f32, P, P, i32, P]
     L.vsaogm_memories.argtypes = [P, P, P]
     L.vsaogm_fuse.argtypes = [P, P, P]
+    L.vsaogm_profile_events.argtypes = [i32, P, P]
     for name in EXPORTED:
         if name not in ("vsaogm_version", "vsaogm_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -183,3 +185,13 @@ def classify(heat, hmax, r_occ: int, r_emp: int, rho: float = 0.0, ogm=None, lab
     check(load().vsaogm_classify(ctypes.byref(g), _ptr(heat), _ptr(hmax), int(r_occ), int(r_emp),
                                  float(rho), _ptr(ogm), _ptr(label), int(device), _stream(stream)))
     return ogm, label
+
+
+STAGES = {"encode": 0, "decode": 1, "classify": 2}
+
+
+def profile_events(stage: str, begin=None, end=None):
+    """Record torch.cuda.Event objects around every launch of a stage's main kernel."""
+    b = ctypes.c_void_p(begin.cuda_event if begin is not None else 0)
+    e = ctypes.c_void_p(end.cuda_event if end is not None else 0)
+    check(load().vsaogm_profile_events(STAGES[stage], b, e))
