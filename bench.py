@@ -90,7 +90,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="world40")
-    ap.add_argument("--precision", default="fp32", choices=["fp32"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16", "bf16x3"])
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle work for the CPU baseline (0 disables it)")
     args = ap.parse_args()
@@ -188,7 +188,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.precision == "fp32" else f"f32 ({args.precision} decode operands)",
         "data": "synthetic",
         "config": {
             "workload": (f"{w.name}: {w.n} points ({int(w.label.sum())} occupied), D={w.D}, "

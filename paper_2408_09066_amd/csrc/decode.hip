@@ -5,23 +5,42 @@
 // per axis: exp(i*Theta_x[k]*x) * exp(i*Theta_y[k]*y).  In tile-local coordinates, and
 // using the conjugate symmetry of the spectra, the similarity of cell (row y, column x)
 // of tile beta with memory key = 2*beta+psi is
-//   P[psi][y][x] = scale[key] * sum_{k < D/2} Re( conj(Omega[key][k]) Ex[x][k] Ey[y][k] )
-// with scale = 2 / (D ||w||).  Written over real and imaginary parts this is a real
-// contraction of length D:
-//   L[y][2k] = Re Ey[y][k],           L[y][2k+1] = Im Ey[y][k]
-//   R[x][2k] = Re(conj(Om) Ex[x][k]), R[x][2k+1] = -Im(conj(Om) Ex[x][k])
-//   P = scale * L . R^T
-// so every tile is a dense GEMM (rows x columns x D) run on MFMA.  The per-axis tables Ex,
-// Ey (the paper's precomputed location vectors, factored) are built once per grid in double
-// precision; the memory factor conj(Omega) is applied to R while it is staged into LDS.
-// The GEMM epilogue applies the scale, stores the heatmap and folds each class's maximum
-// into an order-preserving unsigned atomic (the maximum of eq. non-linearities).
+//   P[psi][y][x] = (2/D) * sum_{k < D/2} Re( conj(Omega[key][k]) / ||w_key|| * Ex[x][k] * Ey[y][k] )
+// Written over real and imaginary parts this is a real contraction of length D:
+//   L[y][2k] = Re Ey[y][k],  L[y][2k+1] = Im Ey[y][k]
+//   R[x][2k] = Re(conj(Om) Ex[x][k]) / ||w||,  R[x][2k+1] = -Im(conj(Om) Ex[x][k]) / ||w||
+//   P = (2/D) * L . R^T
+// so the heatmaps are dense GEMMs run on MFMA.  The per-axis tables Ex, Ey (the paper's
+// precomputed location vectors, factored) are built once per grid in double precision; the
+// memory factor conj(Omega)/||w|| is applied to R while it is staged into LDS, which also
+// keeps R of order one for the 16-bit formats.
+//
+// Work layout.  Rows of one tile band (cells sharing a tile row) are grouped in blocks of
+// 16; a work tile is up to kRowBlocks row blocks of one band by 64 consecutive grid columns
+// (the columns may belong to different tiles: each column stages its own memory).  Each of
+// the 4 waves owns one 16-column block and all row blocks, for both classes.  The K loop
+// (the spectrum) is split "stream-K" style: the (tile, K step) iteration space is cut into
+// equal contiguous ranges, one per workgroup, so every CU gets the same work however few
+// tiles there are.  A tile finished by one workgroup is stored from registers; a tile split
+// across workgroups is written as partial sums and the last workgroup to finish it adds
+// them in workgroup order (deterministic) and stores it.  Every store folds the class
+// maxima (eq. non-linearities) into order-preserving unsigned atomics.
 #include "internal.h"
 
 namespace vsaogm {
 namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kRowBlocks = kDecodeRowBlocks;
+constexpr int kTileRows = 16 * kRowBlocks;
+constexpr int kTileCols = 64;
+constexpr int kRowPitchBytes = 144;  // LDS row: 128 data bytes + 16 padding
 
 __global__ __launch_bounds__(256) void k_table_f32(const double* __restrict__ theta_rad, int axis,
                                                    const double* __restrict__ local, int half,
@@ -38,6 +57,41 @@ __global__ __launch_bounds__(256) void k_table_f32(const double* __restrict__ th
     tab[(size_t)c * halfp + k] = v;
 }
 
+__device__ inline uint16_t bf16_bits(float f) {  // round to nearest even (finite inputs)
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_value(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ inline uint16_t f16_bits(float f) {
+    _Float16 h = (_Float16)f;
+    return __builtin_bit_cast(uint16_t, h);
+}
+
+// 16-bit tables [c][2*halfp] (re, im per bin); lo holds the rounding residual (split form).
+__global__ __launch_bounds__(256) void k_table_16(const double* __restrict__ theta_rad, int axis,
+                                                  const double* __restrict__ local, int half,
+                                                  int halfp, int fp16, uint16_t* __restrict__ hi,
+                                                  uint16_t* __restrict__ lo) {
+    const int c = blockIdx.y;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= halfp) return;
+    double v[2] = {0.0, 0.0};
+    if (k < half) sincos(theta_rad[2 * k + axis] * local[c], &v[1], &v[0]);
+    for (int q = 0; q < 2; ++q) {
+        const size_t o = (size_t)c * 2 * halfp + 2 * k + q;
+        if (fp16) {
+            const uint16_t h = f16_bits((float)v[q]);
+            hi[o] = h;
+            if (lo) lo[o] = f16_bits((float)(v[q] - (double)__builtin_bit_cast(_Float16, h)));
+        } else {
+            const uint16_t h = bf16_bits((float)v[q]);
+            hi[o] = h;
+            if (lo) lo[o] = bf16_bits((float)(v[q] - (double)bf16_value(h)));
+        }
+    }
+}
+
 // Monotone map float -> unsigned so that unsigned max = float max.
 __device__ inline unsigned order_key(float f) {
     unsigned u = __float_as_uint(f);
@@ -47,148 +101,342 @@ __device__ inline float order_value(unsigned u) {
     return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
 }
 
-__global__ void k_hmax_init(unsigned* hmax_u) {
-    if (threadIdx.x < 2) hmax_u[threadIdx.x] = 0u;
-}
-__global__ void k_hmax_final(const unsigned* hmax_u, float* hmax) {
-    if (threadIdx.x < 2) hmax[threadIdx.x] = order_value(hmax_u[threadIdx.x]);
-}
+struct DecodeArgs {
+    const DTile* tiles;
+    int ntiles;
+    const int* col_tx;         // [nx] tile column of every grid column
+    const float2* ex;          // [nx][halfp] fp32
+    const void* ey;            // fp32 [ny][halfp] or 16-bit [ny][2*halfp]
+    const void* ey_lo;         // 16-bit residual (split form) or null
+    const float2* omega;       // [nkeys][halfp]
+    const float* inv_norm;     // [nkeys] 1/||w||, 0 for an empty memory
+    int halfp, nx, ny, tiles_x;
+    float out_scale;           // 2 / D
+    float* heat;               // [2][ny][nx]
+    unsigned* hmax_u;          // [3]: ordered maxima, finished-tile counter
+    float* hmax;               // [2]
+    int* tile_cnt;             // [ntiles] segments finished per tile (reset by the last)
+    float* partial;            // [grid][2][2][kTileRows][kTileCols]
+    int ksteps;                // K steps per tile
+    int steps_per_wg;          // L
+    long long total_steps;     // ntiles * ksteps
+};
 
-constexpr int TM = 64, TN = 64;   // cells per block (rows x columns)
-constexpr int KB = 16;            // complex bins per K step (32 reals)
-constexpr int LDA = 2 * KB + 4;   // padded LDS row (floats)
+// Operand formats: FP32 (0), BF16 (1), FP16 (2), BF16 hi+lo (3).
+template <int PREC>
+struct Fmt {
+    static constexpr bool kSplit = (PREC == 3);
+    static constexpr bool k16 = (PREC != 0);
+    static constexpr int KB = k16 ? 32 : 16;  // complex bins per K step (128-byte rows)
+};
 
-// FP32 operands, MFMA v_mfma_f32_16x16x4_f32.  256 threads = 4 waves in a 2 x 2 layout,
-// each wave a 32 x 32 block of both classes.  Within a K step lane group g = lane/16 owns
-// reals 8g..8g+7 and feeds them to eight MFMAs (the order of a sum is immaterial).
-__global__ __launch_bounds__(256) void k_decode_f32(const DTile* __restrict__ tiles,
-                                                    const float2* __restrict__ ex,
-                                                    const float2* __restrict__ ey,
-                                                    const float2* __restrict__ omega,
-                                                    const float* __restrict__ scale, int halfp,
-                                                    int nx, int ny, float* __restrict__ heat,
-                                                    unsigned* __restrict__ hmax_u) {
-    __shared__ float As[TM * LDA];
-    __shared__ float Bs[2 * TN * LDA];
-    const DTile t = tiles[blockIdx.x];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+__device__ inline void store_tile(const DecodeArgs& a, const DTile& t, int wave, int lane,
+                                  const v4f (&acc)[2][kRowBlocks]) {
     const int g = lane >> 4, i16 = lane & 15;
-
-    // staging assignment: two float4 (= 2 complex bins each) of L and of Ex per thread
-    int lrow[2], lpart[2];
-    const float2* ey_p[2];
-    const float2* ex_p[2];
-    const float2* om_p[2][2];
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        const int idx = tid + 256 * s;
-        lrow[s] = idx >> 3;
-        lpart[s] = idx & 7;
-        const int gr = min(t.r0 + lrow[s], t.rend - 1);
-        const int gc = min(t.c0 + lrow[s], t.cend - 1);
-        ey_p[s] = ey + (size_t)gr * halfp + 2 * lpart[s];
-        ex_p[s] = ex + (size_t)gc * halfp + 2 * lpart[s];
-        om_p[s][0] = omega + (size_t)(2 * t.beta) * halfp + 2 * lpart[s];
-        om_p[s][1] = omega + (size_t)(2 * t.beta + 1) * halfp + 2 * lpart[s];
-    }
-
-    float4 rl[2], rx[2], ro[2][2];
-    auto gload = [&](int kb) {
-        const int off = kb * KB;
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            rl[s] = *reinterpret_cast<const float4*>(ey_p[s] + off);
-            rx[s] = *reinterpret_cast<const float4*>(ex_p[s] + off);
-            ro[s][0] = *reinterpret_cast<const float4*>(om_p[s][0] + off);
-            ro[s][1] = *reinterpret_cast<const float4*>(om_p[s][1] + off);
-        }
-    };
-
-    v4f acc[2][2][2];
-#pragma unroll
-    for (int p = 0; p < 2; ++p)
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) acc[p][a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-
-    const int nk = halfp / KB;
-    gload(0);
-    for (int kb = 0; kb < nk; ++kb) {
-        __syncthreads();
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            *reinterpret_cast<float4*>(&As[lrow[s] * LDA + 4 * lpart[s]]) = rl[s];
-            const float4 e = rx[s];
-#pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                const float4 o = ro[s][p];
-                float4 r;
-                r.x = o.x * e.x + o.y * e.y;
-                r.y = o.y * e.x - o.x * e.y;
-                r.z = o.z * e.z + o.w * e.w;
-                r.w = o.w * e.z - o.z * e.w;
-                *reinterpret_cast<float4*>(&Bs[(p * TN + lrow[s]) * LDA + 4 * lpart[s]]) = r;
-            }
-        }
-        __syncthreads();
-        if (kb + 1 < nk) gload(kb + 1);
-
-        float a[2][8], b[2][2][8];
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb) {
-            const float* src = &As[(wm * 32 + rb * 16 + i16) * LDA + 8 * g];
-            const float4 u = *reinterpret_cast<const float4*>(src);
-            const float4 v = *reinterpret_cast<const float4*>(src + 4);
-            a[rb][0] = u.x; a[rb][1] = u.y; a[rb][2] = u.z; a[rb][3] = u.w;
-            a[rb][4] = v.x; a[rb][5] = v.y; a[rb][6] = v.z; a[rb][7] = v.w;
-        }
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-                const float* src = &Bs[(p * TN + wn * 32 + cb * 16 + i16) * LDA + 8 * g];
-                const float4 u = *reinterpret_cast<const float4*>(src);
-                const float4 v = *reinterpret_cast<const float4*>(src + 4);
-                b[p][cb][0] = u.x; b[p][cb][1] = u.y; b[p][cb][2] = u.z; b[p][cb][3] = u.w;
-                b[p][cb][4] = v.x; b[p][cb][5] = v.y; b[p][cb][6] = v.z; b[p][cb][7] = v.w;
-            }
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-#pragma unroll
-            for (int p = 0; p < 2; ++p)
-#pragma unroll
-                for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                    for (int cb = 0; cb < 2; ++cb)
-                        acc[p][rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                            a[rb][s], b[p][cb][s], acc[p][rb][cb], 0, 0, 0);
-    }
-
-    // epilogue: scale, store, per-class maximum
+    const int col = t.col0 + 16 * wave + i16;
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
-        const float sc = scale[2 * t.beta + p];
         float mx = -INFINITY;
-        float* out = heat + (size_t)p * nx * ny;
+        float* out = a.heat + (size_t)p * a.nx * a.ny;
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
+        for (int rb = 0; rb < kRowBlocks; ++rb) {
+            if (rb < t.nrb) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const int row = t.r0 + wm * 32 + rb * 16 + 4 * g + j;
-                    const int col = t.c0 + wn * 32 + cb * 16 + i16;
-                    if (row < t.rend && col < t.cend) {
-                        const float v = acc[p][rb][cb][j] * sc;
-                        out[(size_t)row * nx + col] = v;
+                    const int row = t.row0 + 16 * rb + 4 * g + j;
+                    if (row < t.row_end && col < a.nx) {
+                        const float v = acc[p][rb][j] * a.out_scale;
+                        out[(size_t)row * a.nx + col] = v;
                         mx = fmaxf(mx, v);
                     }
                 }
+            }
+        }
         for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
-        if (lane == 0 && mx > -INFINITY) atomicMax(hmax_u + p, order_key(mx));
+        if (lane == 0 && mx > -INFINITY) atomicMax(a.hmax_u + p, order_key(mx));
+    }
+}
+
+// After a tile is stored: count it; the last tile of the grid writes the float maxima.
+__device__ inline void tile_done(const DecodeArgs& a) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned prev = atomicAdd(a.hmax_u + 2, 1u);
+        if (prev == (unsigned)a.ntiles - 1) {
+            __threadfence();
+            a.hmax[0] = order_value(atomicOr(a.hmax_u + 0, 0u));
+            a.hmax[1] = order_value(atomicOr(a.hmax_u + 1, 0u));
+        }
+    }
+}
+
+// Workgroups resident per CU: two for the single-product formats; the split form needs more
+// registers than two waves per SIMD allow, so it runs one.
+template <int PREC>
+constexpr int kDecodeOccupancy = (PREC == 3) ? 1 : 2;
+
+template <int PREC>
+__global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeArgs a) {
+    using F = Fmt<PREC>;
+    constexpr int KB = F::KB;
+    constexpr int NSPLIT = F::kSplit ? 2 : 1;
+    // LDS: A rows [kTileRows], B rows [2 classes][kTileCols], each kRowPitchBytes, hi (+lo)
+    __shared__ __attribute__((aligned(16))) unsigned char smem[NSPLIT * (kTileRows + 2 * kTileCols) * kRowPitchBytes];
+    __shared__ int sh_flag;
+    unsigned char* As = smem;
+    unsigned char* Bs = smem + NSPLIT * kTileRows * kRowPitchBytes;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, i16 = lane & 15;
+    const long long it0 = (long long)blockIdx.x * a.steps_per_wg;
+    const long long it1 = min(it0 + a.steps_per_wg, a.total_steps);
+    const int first_tile = (int)(it0 / a.ksteps);
+
+    long long it = it0;
+    while (it < it1) {
+        const int ti = (int)(it / a.ksteps);
+        const int kb0 = (int)(it - (long long)ti * a.ksteps);
+        const int kb1 = (int)min((long long)a.ksteps, it1 - (long long)ti * a.ksteps);
+        it = (long long)ti * a.ksteps + kb1;
+        const DTile t = a.tiles[ti];
+        const int nrows = 16 * t.nrb;
+
+        // ---- staging assignment
+        // A: nrows rows of 128 bytes = 8 units of 16 bytes per row
+        constexpr int A_UNITS_MAX = kTileRows * 8;
+        constexpr int A_PER_T = (A_UNITS_MAX + 255) / 256;
+        // B: 64 columns x KB complex, units of 2 complex (one float4 of Ex)
+        constexpr int B_UNITS = kTileCols * KB / 2;
+        constexpr int B_PER_T = B_UNITS / 256;
+        const int ty = t.ty;
+
+        u32x4 ra[A_PER_T * NSPLIT];
+        f32x4 rx[B_PER_T], ro[B_PER_T][2];
+        float rs[B_PER_T][2];
+
+        // Global loads of one K step into registers.  Rows past the tile's last row block (but
+        // inside the kTileRows LDS rows) load a clamped valid row that the MFMAs never read.
+        auto gload = [&](int kb) {
+#pragma unroll
+            for (int u = 0; u < A_PER_T; ++u) {
+                const int idx = tid + 256 * u;
+                if (idx >= A_UNITS_MAX) break;  // only the last unit round is partial
+                const int r = idx >> 3, part = idx & 7;
+                const int grow = min(t.row0 + min(r, nrows - 1), t.row_end - 1);
+                if (PREC == 0) {
+                    const float2* src = static_cast<const float2*>(a.ey) + (size_t)grow * a.halfp +
+                                        (size_t)kb * KB + 2 * part;
+                    ra[u * NSPLIT] = *reinterpret_cast<const u32x4*>(src);
+                } else {
+                    const size_t off = (size_t)grow * 2 * a.halfp + (size_t)kb * KB * 2 + 8 * part;
+                    ra[u * NSPLIT] = *reinterpret_cast<const u32x4*>(static_cast<const uint16_t*>(a.ey) + off);
+                    if (F::kSplit)
+                        ra[u * NSPLIT + NSPLIT - 1] =
+                            *reinterpret_cast<const u32x4*>(static_cast<const uint16_t*>(a.ey_lo) + off);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < B_PER_T; ++u) {
+                const int idx = tid + 256 * u;
+                const int c = idx / (KB / 2), part = idx % (KB / 2);
+                const int gcol = min(t.col0 + c, a.nx - 1);
+                const int key0 = 2 * (ty * a.tiles_x + a.col_tx[gcol]);
+                const size_t boff = (size_t)kb * KB + 2 * part;
+                rx[u] = *reinterpret_cast<const f32x4*>(a.ex + (size_t)gcol * a.halfp + boff);
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    ro[u][p] = *reinterpret_cast<const f32x4*>(a.omega + (size_t)(key0 + p) * a.halfp + boff);
+                    rs[u][p] = a.inv_norm[key0 + p];
+                }
+            }
+        };
+
+        auto lstore = [&]() {
+#pragma unroll
+            for (int u = 0; u < A_PER_T; ++u) {
+                const int idx = tid + 256 * u;
+                if (idx >= A_UNITS_MAX) break;  // LDS rows stop at kTileRows
+                const int r = idx >> 3, part = idx & 7;
+#pragma unroll
+                for (int h = 0; h < NSPLIT; ++h)
+                    *reinterpret_cast<u32x4*>(As + (h * kTileRows + r) * kRowPitchBytes + 16 * part) = ra[u * NSPLIT + h];
+            }
+#pragma unroll
+            for (int u = 0; u < B_PER_T; ++u) {
+                const int idx = tid + 256 * u;
+                const int c = idx / (KB / 2), part = idx % (KB / 2);
+                const f32x4 e = rx[u];
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    const f32x4 o = ro[u][p];
+                    const float s = rs[u][p];
+                    // conj(o) * e / ||w||, stored as (Re, -Im)
+                    const float r0 = (o.x * e.x + o.y * e.y) * s;
+                    const float r1 = (o.y * e.x - o.x * e.y) * s;
+                    const float r2 = (o.z * e.z + o.w * e.w) * s;
+                    const float r3 = (o.w * e.z - o.z * e.w) * s;
+                    unsigned char* dst = Bs + (p * kTileCols + c) * kRowPitchBytes;
+                    if (PREC == 0) {
+                        *reinterpret_cast<f32x4*>(dst + 16 * part) = f32x4{r0, r1, r2, r3};
+                    } else if (PREC == 2) {
+                        const u32x2 v = {(uint32_t)f16_bits(r0) | ((uint32_t)f16_bits(r1) << 16),
+                                         (uint32_t)f16_bits(r2) | ((uint32_t)f16_bits(r3) << 16)};
+                        *reinterpret_cast<u32x2*>(dst + 8 * part) = v;
+                    } else {
+                        const uint16_t h0 = bf16_bits(r0), h1 = bf16_bits(r1), h2 = bf16_bits(r2),
+                                       h3 = bf16_bits(r3);
+                        const u32x2 v = {(uint32_t)h0 | ((uint32_t)h1 << 16),
+                                         (uint32_t)h2 | ((uint32_t)h3 << 16)};
+                        *reinterpret_cast<u32x2*>(dst + 8 * part) = v;
+                        if (F::kSplit) {
+                            const u32x2 l = {(uint32_t)bf16_bits(r0 - bf16_value(h0)) |
+                                                 ((uint32_t)bf16_bits(r1 - bf16_value(h1)) << 16),
+                                             (uint32_t)bf16_bits(r2 - bf16_value(h2)) |
+                                                 ((uint32_t)bf16_bits(r3 - bf16_value(h3)) << 16)};
+                            *reinterpret_cast<u32x2*>(dst + 2 * kTileCols * kRowPitchBytes + 8 * part) = l;
+                        }
+                    }
+                }
+            }
+        };
+
+        v4f acc[2][kRowBlocks];
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int rb = 0; rb < kRowBlocks; ++rb) acc[p][rb] = v4f{0.f, 0.f, 0.f, 0.f};
+
+        gload(kb0);
+        for (int kb = kb0; kb < kb1; ++kb) {
+            __syncthreads();
+            lstore();
+            __syncthreads();
+            if (kb + 1 < kb1) gload(kb + 1);
+            const int bcol = 16 * wave + i16;
+            // MFMAs are issued with the row-block loop innermost so that consecutive
+            // instructions update different accumulators (no back-to-back dependency).
+            if (PREC == 0) {
+                float b[2][8];
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    const f32x4* src = reinterpret_cast<const f32x4*>(Bs + (p * kTileCols + bcol) * kRowPitchBytes + 32 * g);
+                    const f32x4 u = src[0], v = src[1];
+                    b[p][0] = u.x; b[p][1] = u.y; b[p][2] = u.z; b[p][3] = u.w;
+                    b[p][4] = v.x; b[p][5] = v.y; b[p][6] = v.z; b[p][7] = v.w;
+                }
+                float av[kRowBlocks][8];
+#pragma unroll
+                for (int rb = 0; rb < kRowBlocks; ++rb) {
+                    if (rb < t.nrb) {
+                        const f32x4* src = reinterpret_cast<const f32x4*>(As + (16 * rb + i16) * kRowPitchBytes + 32 * g);
+                        const f32x4 u = src[0], v = src[1];
+                        av[rb][0] = u.x; av[rb][1] = u.y; av[rb][2] = u.z; av[rb][3] = u.w;
+                        av[rb][4] = v.x; av[rb][5] = v.y; av[rb][6] = v.z; av[rb][7] = v.w;
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < 8; ++s)
+#pragma unroll
+                    for (int rb = 0; rb < kRowBlocks; ++rb)
+                        if (rb < t.nrb)
+#pragma unroll
+                            for (int p = 0; p < 2; ++p)
+                                acc[p][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rb][s], b[p][s], acc[p][rb], 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int ch = 0; ch < 2; ++ch) {  // two 32-real halves of the 64-real K step
+                    u32x4 bh[2], bl[2];
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) {
+                        const unsigned char* src = Bs + (p * kTileCols + bcol) * kRowPitchBytes + 64 * ch + 16 * g;
+                        bh[p] = *reinterpret_cast<const u32x4*>(src);
+                        if (F::kSplit) bl[p] = *reinterpret_cast<const u32x4*>(src + 2 * kTileCols * kRowPitchBytes);
+                    }
+                    u32x4 ah[kRowBlocks], al[kRowBlocks];
+#pragma unroll
+                    for (int rb = 0; rb < kRowBlocks; ++rb) {
+                        if (rb < t.nrb) {
+                            const unsigned char* src = As + (16 * rb + i16) * kRowPitchBytes + 64 * ch + 16 * g;
+                            ah[rb] = *reinterpret_cast<const u32x4*>(src);
+                            if (F::kSplit) al[rb] = *reinterpret_cast<const u32x4*>(src + kTileRows * kRowPitchBytes);
+                        }
+                    }
+                    constexpr int NTERM = F::kSplit ? 3 : 1;
+#pragma unroll
+                    for (int term = 0; term < NTERM; ++term)
+#pragma unroll
+                        for (int rb = 0; rb < kRowBlocks; ++rb)
+                            if (rb < t.nrb)
+#pragma unroll
+                                for (int p = 0; p < 2; ++p) {
+                                    const u32x4 x = (term == 2) ? al[rb] : ah[rb];
+                                    const u32x4 y = (term == 1) ? bl[p] : bh[p];
+                                    if (PREC == 2)
+                                        acc[p][rb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                            __builtin_bit_cast(v8h, x), __builtin_bit_cast(v8h, y), acc[p][rb], 0, 0, 0);
+                                    else
+                                        acc[p][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                            __builtin_bit_cast(v8bf, x), __builtin_bit_cast(v8bf, y), acc[p][rb], 0, 0, 0);
+                                }
+                }
+            }
+        }
+
+        const bool whole = (kb0 == 0 && kb1 == a.ksteps);
+        if (whole) {
+            store_tile(a, t, wave, lane, acc);
+            tile_done(a);
+            continue;
+        }
+        // partial tile: slot 0 if this is the workgroup's first tile, else slot 1
+        const int slot = (ti == first_tile) ? 0 : 1;
+        float* part = a.partial + ((size_t)blockIdx.x * 2 + slot) * 2 * kTileRows * kTileCols;
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int rb = 0; rb < kRowBlocks; ++rb)
+                if (rb < t.nrb)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        part[((size_t)p * kTileRows + 16 * rb + 4 * g + j) * kTileCols + 16 * wave + i16] = acc[p][rb][j];
+        const int w_first = (int)(((long long)ti * a.ksteps) / a.steps_per_wg);
+        const int w_last = (int)(((long long)ti * a.ksteps + a.ksteps - 1) / a.steps_per_wg);
+        // every wave publishes its partial sums device-wide before the tile's counter moves
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) {
+            const int prev = atomicAdd(a.tile_cnt + ti, 1);
+            const int last = (prev == w_last - w_first) ? 1 : 0;
+            if (last) {
+                a.tile_cnt[ti] = 0;  // ready for the next decode
+                __threadfence();
+            }
+            sh_flag = last;
+        }
+        __syncthreads();
+        if (!sh_flag) continue;
+        __threadfence();  // acquire the other segments' partial sums
+        // last segment: add every segment's partial sums in workgroup order
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int rb = 0; rb < kRowBlocks; ++rb) acc[p][rb] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int w = w_first; w <= w_last; ++w) {
+            const int wslot = ((int)(((long long)w * a.steps_per_wg) / a.ksteps) == ti) ? 0 : 1;
+            const float* src = a.partial + ((size_t)w * 2 + wslot) * 2 * kTileRows * kTileCols;
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int rb = 0; rb < kRowBlocks; ++rb)
+                    if (rb < t.nrb)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            acc[p][rb][j] += __builtin_nontemporal_load(
+                                src + ((size_t)p * kTileRows + 16 * rb + 4 * g + j) * kTileCols + 16 * wave + i16);
+        }
+        store_tile(a, t, wave, lane, acc);
+        tile_done(a);
     }
 }
 
@@ -201,20 +449,63 @@ hipError_t launch_table_f32(const double* theta_rad, int axis, const double* loc
     return hipGetLastError();
 }
 
-hipError_t launch_decode(int precision, const DTile* tiles, int ntiles, const void* ex_hi,
-                         const void* ex_lo, const void* ey_hi, const void* ey_lo,
-                         const float2* omega, const float* scale, int halfp, int nx, int ny,
-                         float* heat, unsigned* hmax_u, float* hmax, hipStream_t s) {
-    (void)ex_lo;
-    (void)ey_lo;
-    if (precision != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_hmax_init, dim3(1), dim3(64), 0, s, hmax_u);
+hipError_t launch_table_split(const double* theta_rad, int axis, const double* local, int ncells,
+                              int half, int halfp, bool fp16, void* hi, void* lo, hipStream_t s) {
+    hipLaunchKernelGGL(k_table_16, dim3((halfp + 255) / 256, ncells), dim3(256), 0, s, theta_rad,
+                       axis, local, half, halfp, fp16 ? 1 : 0, static_cast<uint16_t*>(hi),
+                       static_cast<uint16_t*>(lo));
+    return hipGetLastError();
+}
+
+DecodePlan decode_plan(int precision, int ntiles, int halfp, int num_cus) {
+    DecodePlan p;
+    const int kb = precision == 0 ? 16 : 32;
+    p.ksteps = halfp / kb;
+    const long long total = (long long)ntiles * p.ksteps;
+    const int slots = (precision == 3 ? kDecodeOccupancy<3> : kDecodeOccupancy<0>) * num_cus;
+    long long L = (total + slots - 1) / slots;
+    if (L < 4) L = 4;
+    p.steps_per_wg = (int)L;
+    p.grid = (int)((total + L - 1) / L);
+    p.total_steps = total;
+    return p;
+}
+
+size_t decode_partial_floats(int grid) { return (size_t)grid * 2 * 2 * kTileRows * kTileCols; }
+
+hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
+    DecodeArgs a;
+    a.tiles = d.tiles;
+    a.ntiles = d.ntiles;
+    a.col_tx = d.col_tx;
+    a.ex = d.ex;
+    a.ey = d.ey;
+    a.ey_lo = d.ey_lo;
+    a.omega = d.omega;
+    a.inv_norm = d.inv_norm;
+    a.halfp = d.halfp;
+    a.nx = d.nx;
+    a.ny = d.ny;
+    a.tiles_x = d.tiles_x;
+    a.out_scale = d.out_scale;
+    a.heat = d.heat;
+    a.hmax_u = d.hmax_u;
+    a.hmax = d.hmax;
+    a.tile_cnt = d.tile_cnt;
+    a.partial = d.partial;
+    a.ksteps = d.plan.ksteps;
+    a.steps_per_wg = d.plan.steps_per_wg;
+    a.total_steps = d.plan.total_steps;
+    const dim3 grid(d.plan.grid), block(256);
     profile_begin(kStageDecode, s);
-    hipLaunchKernelGGL(k_decode_f32, dim3(ntiles), dim3(256), 0, s, tiles,
-                       static_cast<const float2*>(ex_hi), static_cast<const float2*>(ey_hi),
-                       omega, scale, halfp, nx, ny, heat, hmax_u);
+    switch (precision) {
+        case 0: hipLaunchKernelGGL(k_decode<0>, grid, block, 0, s, a); break;
+        case 1: hipLaunchKernelGGL(k_decode<1>, grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_decode<2>, grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL(k_decode<3>, grid, block, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
     profile_end(kStageDecode, s);
-    hipLaunchKernelGGL(k_hmax_final, dim3(1), dim3(64), 0, s, hmax_u, hmax);
     return hipGetLastError();
 }
 

@@ -47,108 +47,127 @@ __device__ inline int nearest_tile(double x, double y, const LayoutDev& L) {
     return best;
 }
 
-__global__ __launch_bounds__(256) void k_assign(const float2* __restrict__ xy,
-                                                const uint8_t* __restrict__ label, int64_t n,
-                                                LayoutDev L, int nkeys, int* __restrict__ key_out,
-                                                int* __restrict__ hist,
-                                                unsigned long long* __restrict__ n_bad) {
+// One point per thread; blocks of kAssignChunk points.  hist is key-major:
+// hist[key][chunk] = number of the chunk's points with that key.
+__global__ __launch_bounds__(kAssignChunk) void k_assign(const float2* __restrict__ xy,
+                                                         const uint8_t* __restrict__ label,
+                                                         int64_t n, LayoutDev L, int nkeys,
+                                                         int nchunks, int* __restrict__ key_out,
+                                                         int* __restrict__ hist,
+                                                         unsigned long long* __restrict__ n_bad) {
     extern __shared__ int sh_hist[];
     for (int k = threadIdx.x; k < nkeys; k += blockDim.x) sh_hist[k] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kAssignChunk;
-    int bad = 0;
-    for (int q = threadIdx.x; q < kAssignChunk; q += blockDim.x) {
-        int64_t i = base + q;
-        if (i >= n) break;
-        float2 p = xy[i];
-        unsigned l = label[i];
+    const int64_t i = (int64_t)blockIdx.x * kAssignChunk + threadIdx.x;
+    if (i < n) {
+        const float2 p = xy[i];
+        const unsigned l = label[i];
         int key = -1;
         if (l <= 1u) {
-            int b = nearest_tile((double)p.x, (double)p.y, L);
+            const int b = nearest_tile((double)p.x, (double)p.y, L);
             if (b >= 0) key = 2 * b + (int)l;
         }
-        if (key < 0) {
-            ++bad;
-        } else {
+        if (key < 0)
+            atomicAdd(n_bad, 1ull);
+        else
             atomicAdd(&sh_hist[key], 1);
-        }
         key_out[i] = key;
     }
-    if (bad) atomicAdd(n_bad, (unsigned long long)bad);
     __syncthreads();
     for (int k = threadIdx.x; k < nkeys; k += blockDim.x)
-        hist[(size_t)blockIdx.x * nkeys + k] = sh_hist[k];
+        hist[(size_t)k * nchunks + blockIdx.x] = sh_hist[k];
 }
 
-// Exclusive scan of v[0..n) in shared memory by one block of blockDim.x threads.
-// tmp must hold blockDim.x ints.  Returns the total.
-__device__ int block_exclusive_scan(int* v, int n, int* tmp) {
-    const int T = blockDim.x;
-    const int per = (n + T - 1) / T;
-    const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
-    int s = 0;
-    for (int i = lo; i < hi; ++i) s += v[i];
-    tmp[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 1; off < T; off <<= 1) {
-        int add = (int)threadIdx.x >= off ? tmp[threadIdx.x - off] : 0;
-        __syncthreads();
-        tmp[threadIdx.x] += add;
-        __syncthreads();
+// Exclusive scan across a block of kScanThreads threads; returns the block total in *total.
+constexpr int kScanThreads = 1024;
+__device__ int block_scan_excl(int v, int* sh_w, int* total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
     }
-    int run = tmp[threadIdx.x] - s;  // exclusive prefix of this thread's segment
-    for (int i = lo; i < hi; ++i) {
-        int x = v[i];
-        v[i] = run;
-        run += x;
-    }
-    int total = tmp[T - 1];
+    if (lane == 63) sh_w[wv] = x;
     __syncthreads();
-    return total;
+    if (wv == 0) {
+        int t = (lane < kScanThreads / 64) ? sh_w[lane] : 0;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(t, off);
+            if (lane >= off) t += y;
+        }
+        if (lane < kScanThreads / 64) sh_w[lane] = t;
+    }
+    __syncthreads();
+    const int before = (wv > 0) ? sh_w[wv - 1] : 0;
+    *total = sh_w[kScanThreads / 64 - 1];
+    __syncthreads();
+    return before + x - v;
 }
 
-// One block of 1024 threads.  hist[c][k] (counts) becomes the global destination base of
-// chunk c's points of key k; the encode work table and per-key bookkeeping are written.
-__global__ __launch_bounds__(1024) void k_scan(int* __restrict__ hist, int nchunks, int nkeys,
-                                               int echunk, EChunk* __restrict__ table,
-                                               int* __restrict__ meta) {
-    extern __shared__ int sh[];
-    int* tot = sh;                 // [nkeys] totals, then key starts
-    int* nec = sh + nkeys;         // [nkeys] work items per key, then their first index
-    int* tmp = sh + 2 * nkeys;     // [blockDim.x]
-    for (int k = threadIdx.x; k < nkeys; k += blockDim.x) {
-        int run = 0;
-        for (int c = 0; c < nchunks; ++c) {
-            int* h = hist + (size_t)c * nkeys + k;
-            int x = *h;
-            *h = run;
-            run += x;
+// One block.  The key-major histogram becomes, by one flat exclusive scan, the destination
+// base of every (key, chunk) -- the stable counting sort's offsets.  Then per key: point
+// count, encode work items and their table.
+__global__ __launch_bounds__(kScanThreads) void k_scan(int* __restrict__ hist, int nchunks,
+                                                       int nkeys, int echunk,
+                                                       EChunk* __restrict__ table,
+                                                       int* __restrict__ meta) {
+    __shared__ int sh_w[kScanThreads / 64];
+    extern __shared__ int key_start[];   // [nkeys]
+    const int64_t N = (int64_t)nkeys * nchunks;
+    constexpr int V = 4;
+    int carry = 0;
+    for (int64_t base = 0; base < N; base += (int64_t)kScanThreads * V) {
+        const int64_t j0 = base + (int64_t)threadIdx.x * V;
+        int v[V];
+        int sum = 0;
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            v[u] = (j0 + u < N) ? hist[j0 + u] : 0;
+            sum += v[u];
         }
-        tot[k] = run;
-        nec[k] = (run + echunk - 1) / echunk;
-        meta[1 + 2 * nkeys + k] = run;  // key_count
+        int total;
+        int run = carry + block_scan_excl(sum, sh_w, &total);
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            if (j0 + u < N) {
+                hist[j0 + u] = run;
+                if ((j0 + u) % nchunks == 0) key_start[(j0 + u) / nchunks] = run;
+            }
+            run += v[u];
+        }
+        carry += total;
     }
     __syncthreads();
-    int n_ec = block_exclusive_scan(nec, nkeys, tmp);
-    block_exclusive_scan(tot, nkeys, tmp);
-    if (threadIdx.x == 0) meta[0] = n_ec;
-    for (int k = threadIdx.x; k < nkeys; k += blockDim.x) {
-        int start = tot[k];
-        int cnt = meta[1 + 2 * nkeys + k];
-        int e0 = nec[k];
-        int ne = (cnt + echunk - 1) / echunk;
-        meta[1 + k] = e0;
-        meta[1 + nkeys + k] = ne;
-        for (int j = 0; j < ne; ++j) {
-            EChunk e;
-            e.key = k;
-            e.start = start + j * echunk;
-            e.len = min(echunk, cnt - j * echunk);
-            e.pad = 0;
-            table[e0 + j] = e;
+    const int n_valid = carry;
+    // per-key counts and work items (keys in slices of kScanThreads, scanned in order)
+    int ec_carry = 0;
+    for (int k0 = 0; k0 < nkeys; k0 += kScanThreads) {
+        const int k = k0 + threadIdx.x;
+        int start = 0, cnt = 0, ne = 0;
+        if (k < nkeys) {
+            start = key_start[k];
+            const int next = (k + 1 < nkeys) ? key_start[k + 1] : n_valid;
+            cnt = next - start;
+            ne = (cnt + echunk - 1) / echunk;
         }
-        for (int c = 0; c < nchunks; ++c) hist[(size_t)c * nkeys + k] += start;
+        int total;
+        const int e0 = ec_carry + block_scan_excl(ne, sh_w, &total);
+        if (k < nkeys) {
+            meta[1 + k] = e0;
+            meta[1 + nkeys + k] = ne;
+            meta[1 + 2 * nkeys + k] = cnt;
+            for (int j = 0; j < ne; ++j) {
+                EChunk e;
+                e.key = k;
+                e.start = start + j * echunk;
+                e.len = min(echunk, cnt - j * echunk);
+                e.pad = 0;
+                table[e0 + j] = e;
+            }
+        }
+        ec_carry += total;
     }
+    if (threadIdx.x == 0) meta[0] = ec_carry;
 }
 
 // Stable counting-sort scatter: one wavefront per chunk of kAssignChunk points, in order.
@@ -156,19 +175,28 @@ __global__ __launch_bounds__(1024) void k_scan(int* __restrict__ hist, int nchun
 // round with the same key (lanes are matched bit by bit with ballots).
 __global__ __launch_bounds__(64) void k_scatter(const float2* __restrict__ xy,
                                                 const int* __restrict__ key, int64_t n,
-                                                LayoutDev L, int nkeys, int key_bits,
+                                                LayoutDev L, int nkeys, int nchunks, int key_bits,
                                                 const int* __restrict__ base,
                                                 float2* __restrict__ sorted,
                                                 float2* __restrict__ sorted_lo) {
     extern __shared__ int run[];
+    constexpr int R = kAssignChunk / 64;
     const int lane = threadIdx.x;
-    for (int k = lane; k < nkeys; k += 64) run[k] = base[(size_t)blockIdx.x * nkeys + k];
+    const int64_t c0 = (int64_t)blockIdx.x * kAssignChunk;
+    int kk[R];
+    float2 pp[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = c0 + r * 64 + lane;
+        kk[r] = (i < n) ? key[i] : -1;
+        pp[r] = (i < n) ? xy[i] : make_float2(0.f, 0.f);
+    }
+    for (int k = lane; k < nkeys; k += 64) run[k] = base[(size_t)k * nchunks + blockIdx.x];
     __syncthreads();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t c0 = (int64_t)blockIdx.x * kAssignChunk;
-    for (int r = 0; r < kAssignChunk / 64; ++r) {
-        const int64_t i = c0 + r * 64 + lane;
-        const int k = (i < n) ? key[i] : -1;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int k = kk[r];
         const unsigned uk = (k < 0) ? (unsigned)nkeys : (unsigned)k;
         uint64_t same = ~0ull;
         for (int b = 0; b < key_bits; ++b) {
@@ -181,9 +209,8 @@ __global__ __launch_bounds__(64) void k_scatter(const float2* __restrict__ xy,
             const int dest = run[k] + rank;
             const int beta = k >> 1;
             const int tx = beta % L.tiles_x, ty = beta / L.tiles_x;
-            const float2 p = xy[i];
-            const double lx = (double)p.x - L.cx[tx];
-            const double ly = (double)p.y - L.cy[ty];
+            const double lx = (double)pp[r].x - L.cx[tx];
+            const double ly = (double)pp[r].y - L.cy[ty];
             const float fx = (float)lx, fy = (float)ly;
             sorted[dest] = make_float2(fx, fy);
             sorted_lo[dest] = make_float2((float)(lx - (double)fx), (float)(ly - (double)fy));
@@ -303,23 +330,39 @@ __global__ __launch_bounds__(256) void k_reduce(const float2* __restrict__ parti
     if (k >= half) return;
     const int e0 = meta[1 + key], ne = meta[1 + nkeys + key];
     if (ne == 0) return;
+    const float2* p = partial + (size_t)e0 * halfp + k;
     float sr = 0.f, si = 0.f;
-    for (int c = e0; c < e0 + ne; ++c) {
-        float2 v = partial[(size_t)c * halfp + k];
+    int c = 0;
+    for (; c + 8 <= ne; c += 8) {
+        float2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(size_t)(c + u) * halfp];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            sr += v[u].x;
+            si += v[u].y;
+        }
+    }
+    for (; c < ne; ++c) {
+        const float2 v = p[(size_t)c * halfp];
         sr += v.x;
         si += v.y;
     }
     float2* o = omega + (size_t)key * halfp + k;
-    float2 w = *o;
+    const float2 w = *o;
     *o = make_float2(w.x + sr, w.y + si);
 }
 
-// scale[key] = 2 / (D * ||w||) with ||w||^2 = (2/D) sum_{k < D/2} |Omega_k|^2 (Parseval over
-// the conjugate-symmetric spectrum; bins 0 and D/2 both equal the point count), 0 for an
-// empty memory (eq. vector-normalization).
+// scale[key] = 1 / ||w|| with ||w||^2 = (2/D) sum_{k < D/2} |Omega_k|^2 (Parseval over the
+// conjugate-symmetric spectrum; bins 0 and D/2 both equal the point count), 0 for an empty
+// memory (eq. vector-normalization).
 __global__ __launch_bounds__(256) void k_norm(const float2* __restrict__ omega, int half,
-                                              int halfp, int D, float* __restrict__ scale) {
+                                              int halfp, int D, float* __restrict__ scale,
+                                              unsigned* __restrict__ hmax_u) {
     const int key = blockIdx.x;
+    // the following similarity GEMM folds its maxima into hmax_u[0..1] and counts finished
+    // blocks in hmax_u[2]; they start from zero here
+    if (key == 0 && threadIdx.x < 3) hmax_u[threadIdx.x] = 0u;
     const float2* w = omega + (size_t)key * halfp;
     double s = 0.0;
     for (int k = threadIdx.x; k < half; k += 256) {
@@ -333,7 +376,7 @@ __global__ __launch_bounds__(256) void k_norm(const float2* __restrict__ omega, 
     if (threadIdx.x == 0) {
         double t = sh[0] + sh[1] + sh[2] + sh[3];
         double nrm = sqrt(2.0 * t / (double)D);
-        scale[key] = (nrm > 0.0) ? (float)(2.0 / ((double)D * nrm)) : 0.f;
+        scale[key] = (nrm > 0.0) ? (float)(1.0 / nrm) : 0.f;
     }
 }
 
@@ -401,18 +444,12 @@ hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const
     if (n <= 0) return hipSuccess;
     const EncodePlan p = encode_plan(n, halfp, nkeys);
     const float2* xy2 = reinterpret_cast<const float2*>(xy);
-    hipLaunchKernelGGL(k_assign, dim3(p.nchunks), dim3(256), nkeys * sizeof(int), s, xy2, label,
-                       n, L, nkeys, w.key, w.hist, w.n_bad);
-    const size_t scan_lds = (2 * (size_t)nkeys + 1024) * sizeof(int);
-    if (scan_lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)scan_lds);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), scan_lds, s, w.hist,
-                       p.nchunks, nkeys, p.echunk, w.table, w.meta);
+    hipLaunchKernelGGL(k_assign, dim3(p.nchunks), dim3(kAssignChunk), nkeys * sizeof(int), s, xy2,
+                       label, n, L, nkeys, p.nchunks, w.key, w.hist, w.n_bad);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), nkeys * sizeof(int), s, w.hist, p.nchunks, nkeys,
+                       p.echunk, w.table, w.meta);
     hipLaunchKernelGGL(k_scatter, dim3(p.nchunks), dim3(64), nkeys * sizeof(int), s, xy2, w.key,
-                       n, L, nkeys, bits_for(nkeys), w.hist, w.sorted, w.sorted_lo);
+                       n, L, nkeys, p.nchunks, bits_for(nkeys), w.hist, w.sorted, w.sorted_lo);
     const double2* rev_d = reinterpret_cast<const double2*>(theta_rev_d);
     const dim3 eg(p.max_echunks, p.binblocks);
     profile_begin(kStageEncode, s);
@@ -445,8 +482,8 @@ hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const
 }
 
 hipError_t launch_norm(const float2* omega, int nkeys, int half, int halfp, int D, float* scale,
-                       hipStream_t s) {
-    hipLaunchKernelGGL(k_norm, dim3(nkeys), dim3(256), 0, s, omega, half, halfp, D, scale);
+                       unsigned* hmax_u, hipStream_t s) {
+    hipLaunchKernelGGL(k_norm, dim3(nkeys), dim3(256), 0, s, omega, half, halfp, D, scale, hmax_u);
     return hipGetLastError();
 }
 

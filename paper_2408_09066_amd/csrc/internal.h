@@ -10,7 +10,7 @@ namespace vsaogm {
 
 constexpr int kMaxTilesPerAxis = 64;
 constexpr int kMaxKeys = 2 * kMaxTilesPerAxis * kMaxTilesPerAxis;  // 8192 memories
-constexpr int kAssignChunk = 2048;   // points per histogram / stable-scatter chunk
+constexpr int kAssignChunk = 1024;   // points per histogram / stable-scatter chunk
 constexpr int kEncodeChunk = 1024;   // points per encode work item (even, so pairs never straddle)
 constexpr int kEncodeThreads = 256;
 constexpr int kEncodeBpt = 8;        // spectrum bins per encode thread
@@ -38,11 +38,15 @@ struct EChunk {
     int pad;
 };
 
-// One decode tile: a TM x TN block of one tile's cells, both classes.
+// One decode work tile: up to kDecodeRowBlocks blocks of 16 rows of one tile band (rows
+// whose cells share a tile row) by 64 consecutive grid columns, both classes.
+constexpr int kDecodeRowBlocks = 7;
 struct DTile {
-    int beta;
-    int r0, c0;       // first row / column of the block
-    int rend, cend;   // one past the last row / column of the tile's cells
+    int ty;           // tile row of the band
+    int row0;         // first grid row of the block
+    int row_end;      // one past the band's last row
+    int nrb;          // row blocks of 16 in this tile (1..kDecodeRowBlocks)
+    int col0;         // first grid column (multiple of 64)
     int pad[3];
 };
 
@@ -56,7 +60,7 @@ struct EncodeWork {
     int* key;            // [cap_n]
     float2* sorted;      // [cap_n] tile-local coordinates, grouped by key
     float2* sorted_lo;   // [cap_n] rounding residuals of the local coordinates
-    int* hist;           // [cap_chunks][nkeys] per-chunk key counts, then bases
+    int* hist;           // [nkeys][cap_chunks] per-chunk key counts, then bases
     EChunk* table;       // [cap_echunks]
     int* meta;           // [1 + 3 * nkeys]: n_echunks, key_ec_start[nkeys], key_ec_count[nkeys], key_count[nkeys]
     float2* partial;     // [cap_echunks][halfp]
@@ -78,8 +82,10 @@ hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const
                          float max_rev_x, float max_rev_y, int half, int halfp,
                          const EncodeWork& w, float2* omega, hipStream_t s);
 
-hipError_t launch_norm(const float2* omega, int nkeys, int half, int halfp, int D, float* scale,
-                       hipStream_t s);
+// inv_norm[key] = 1/||w_key|| (0 for an empty memory).  Also zeroes hmax_u[0..2] (class
+// maxima and finished-tile counter of the decode that follows).
+hipError_t launch_norm(const float2* omega, int nkeys, int half, int halfp, int D, float* inv_norm,
+                       unsigned* hmax_u, hipStream_t s);
 
 hipError_t launch_memories_export(const float2* omega, const double* theta_rad, const LayoutDev& L,
                                   int nkeys, int half, int halfp, float* out, hipStream_t s);
@@ -95,10 +101,36 @@ hipError_t launch_table_f32(const double* theta_rad, int axis, const double* loc
 hipError_t launch_table_split(const double* theta_rad, int axis, const double* local, int ncells,
                               int half, int halfp, bool fp16, void* hi, void* lo, hipStream_t s);
 
-hipError_t launch_decode(int precision, const DTile* tiles, int ntiles, const void* ex_hi,
-                         const void* ex_lo, const void* ey_hi, const void* ey_lo,
-                         const float2* omega, const float* scale, int halfp, int nx, int ny,
-                         float* heat, unsigned* hmax_u, float* hmax, hipStream_t s);
+// Stream-K launch geometry of the similarity GEMM.
+struct DecodePlan {
+    int ksteps;            // K steps per tile
+    int steps_per_wg;      // contiguous (tile, K step) iterations per workgroup
+    int grid;              // workgroups
+    long long total_steps; // tiles * ksteps
+};
+DecodePlan decode_plan(int precision, int ntiles, int halfp, int num_cus);
+size_t decode_partial_floats(int grid);
+
+struct DecodeLaunch {
+    const DTile* tiles;
+    int ntiles;
+    const int* col_tx;
+    const float2* ex;       // fp32 [nx][halfp]
+    const void* ey;         // fp32 [ny][halfp] (FP32) or 16-bit [ny][2*halfp]
+    const void* ey_lo;      // bf16 residual table (BF16X3) or null
+    const float2* omega;
+    const float* inv_norm;
+    int halfp, nx, ny, tiles_x;
+    float out_scale;        // 2 / D
+    float* heat;
+    unsigned* hmax_u;       // zeroed by launch_norm
+    float* hmax;
+    int* tile_cnt;          // [ntiles], zero between launches
+    float* partial;         // decode_partial_floats(plan.grid)
+    DecodePlan plan;
+};
+// Similarity GEMM over the tile list (precision: 0 fp32, 1 bf16, 2 fp16, 3 bf16 hi+lo).
+hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s);
 
 // ---- classify (classify.hip) -------------------------------------------------------
 hipError_t launch_classify(const float* heat, const float* hmax, int nx, int ny, int r_occ,

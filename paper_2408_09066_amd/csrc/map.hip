@@ -114,13 +114,16 @@ struct GridKey {
     }
 };
 
-// Per-grid decode state: cell-to-tile split, local coordinates, tile list, tables.
+// Per-grid decode state: cell-to-tile split, local coordinates, work tiles, tables.
 struct GridCache {
     int nx = 0, ny = 0;
     DevBuf<double> local_x, local_y;
     DevBuf<DTile> tiles;
     int ntiles = 0;
-    DevBuf<float2> ex32, ey32;  // FP32 tables [n][halfp]
+    DevBuf<int> col_tx;              // [nx] tile column of every grid column
+    DevBuf<int> tile_cnt;            // [ntiles] stream-K segment counters (zero at rest)
+    DevBuf<float2> ex32, ey32;       // fp32 tables [n][halfp]
+    DevBuf<uint16_t> ey_bf, ey_bf_lo, ey_h;  // 16-bit y tables [ny][2*halfp], built on first use
 };
 
 struct ProfileSlot {
@@ -153,8 +156,10 @@ struct vsaogm_map {
     DevBuf<double> d_rev_d;             // [halfp][2] Theta / (2 pi), fp64
     DevBuf<double> d_theta;             // [half][2] Theta, rad/m
     DevBuf<float2> d_omega;             // [nkeys][halfp] local-frame memories
-    DevBuf<float> d_scale;              // [nkeys]
-    DevBuf<unsigned> d_hmax_u;          // [2]
+    DevBuf<float> d_scale;              // [nkeys] 1/||w||
+    DevBuf<float> d_partial;            // stream-K partial sums of the decode
+    int num_cus = 0;
+    DevBuf<unsigned> d_hmax_u;          // [3] ordered class maxima, finished-block counter
     DevBuf<unsigned long long> d_bad;   // [1]
 
     // encode workspace
@@ -282,47 +287,82 @@ GridCache* grid_cache(vsaogm_map* m, const vsaogm_grid_desc* g, hipStream_t s) {
     auto gc = std::make_unique<GridCache>();
     gc->nx = g->nx;
     gc->ny = g->ny;
+    // Work tiles: per tile band, its rows in blocks of 16 split evenly into groups of at most
+    // kDecodeRowBlocks blocks, times the grid's columns in slices of 64.
     std::vector<DTile> tl;
-    constexpr int TM = 64, TN = 64;
     for (int ty = 0; ty < m->tiles_y; ++ty) {
         const int r0 = (int)(std::lower_bound(trow.begin(), trow.end(), ty) - trow.begin());
         const int r1 = (int)(std::upper_bound(trow.begin(), trow.end(), ty) - trow.begin());
         if (r0 >= r1) continue;
-        for (int tx = 0; tx < m->tiles_x; ++tx) {
-            const int c0 = (int)(std::lower_bound(tcol.begin(), tcol.end(), tx) - tcol.begin());
-            const int c1 = (int)(std::upper_bound(tcol.begin(), tcol.end(), tx) - tcol.begin());
-            if (c0 >= c1) continue;
-            for (int r = r0; r < r1; r += TM)
-                for (int c = c0; c < c1; c += TN) {
-                    DTile d{};
-                    d.beta = ty * m->tiles_x + tx;
-                    d.r0 = r;
-                    d.c0 = c;
-                    d.rend = r1;
-                    d.cend = c1;
-                    tl.push_back(d);
-                }
+        const int nblocks = (r1 - r0 + 15) / 16;
+        const int ngroups = (nblocks + kDecodeRowBlocks - 1) / kDecodeRowBlocks;
+        int b0 = 0;
+        for (int gi = 0; gi < ngroups; ++gi) {
+            const int nb = nblocks / ngroups + (gi < nblocks % ngroups ? 1 : 0);
+            for (int c = 0; c < g->nx; c += 64) {
+                DTile d{};
+                d.ty = ty;
+                d.row0 = r0 + 16 * b0;
+                d.row_end = r1;
+                d.nrb = nb;
+                d.col0 = c;
+                tl.push_back(d);
+            }
+            b0 += nb;
         }
     }
     gc->ntiles = (int)tl.size();
     gc->tiles.alloc(tl.size(), "decode tile list");
+    gc->tile_cnt.alloc(tl.size(), "decode tile counters");
+    gc->col_tx.alloc(g->nx, "column tiles");
     gc->local_x.alloc(g->nx, "local x");
     gc->local_y.alloc(g->ny, "local y");
     gc->ex32.alloc((size_t)g->nx * m->halfp, "x location table");
-    gc->ey32.alloc((size_t)g->ny * m->halfp, "y location table");
     hip_check(hipMemcpy(gc->tiles.p, tl.data(), tl.size() * sizeof(DTile), hipMemcpyHostToDevice),
               "copy tile list");
+    hip_check(hipMemcpy(gc->col_tx.p, tcol.data(), tcol.size() * sizeof(int), hipMemcpyHostToDevice),
+              "copy column tiles");
     hip_check(hipMemcpy(gc->local_x.p, lx.data(), lx.size() * sizeof(double), hipMemcpyHostToDevice),
               "copy local x");
     hip_check(hipMemcpy(gc->local_y.p, ly.data(), ly.size() * sizeof(double), hipMemcpyHostToDevice),
               "copy local y");
+    hip_check(hipMemset(gc->tile_cnt.p, 0, tl.size() * sizeof(int)), "clear tile counters");
     hip_check(launch_table_f32(m->d_theta.p, 0, gc->local_x.p, g->nx, m->half, m->halfp, gc->ex32.p, s),
               "x table");
-    hip_check(launch_table_f32(m->d_theta.p, 1, gc->local_y.p, g->ny, m->half, m->halfp, gc->ey32.p, s),
-              "y table");
     GridCache* raw = gc.get();
     m->grids.emplace(key, std::move(gc));
     return raw;
+}
+
+// The y table in the operand format of the requested precision (built on first use).
+const void* y_table(vsaogm_map* m, GridCache* gc, int precision, const void** lo, hipStream_t s) {
+    *lo = nullptr;
+    const size_t n16 = (size_t)gc->ny * 2 * m->halfp;
+    switch (precision) {
+        case VSAOGM_FP32:
+            if (!gc->ey32.p) {
+                gc->ey32.alloc((size_t)gc->ny * m->halfp, "y location table");
+                hip_check(launch_table_f32(m->d_theta.p, 1, gc->local_y.p, gc->ny, m->half, m->halfp,
+                                           gc->ey32.p, s), "y table");
+            }
+            return gc->ey32.p;
+        case VSAOGM_FP16:
+            if (!gc->ey_h.p) {
+                gc->ey_h.alloc(n16, "y location table (fp16)");
+                hip_check(launch_table_split(m->d_theta.p, 1, gc->local_y.p, gc->ny, m->half, m->halfp,
+                                             true, gc->ey_h.p, nullptr, s), "y table");
+            }
+            return gc->ey_h.p;
+        default:
+            if (!gc->ey_bf.p || !gc->ey_bf_lo.p) {
+                gc->ey_bf.alloc(n16, "y location table (bf16)");
+                gc->ey_bf_lo.alloc(n16, "y location table (bf16 residual)");
+                hip_check(launch_table_split(m->d_theta.p, 1, gc->local_y.p, gc->ny, m->half, m->halfp,
+                                             false, gc->ey_bf.p, gc->ey_bf_lo.p, s), "y table");
+            }
+            if (precision == VSAOGM_BF16X3) *lo = gc->ey_bf_lo.p;
+            return gc->ey_bf.p;
+    }
 }
 
 void check_grid(const vsaogm_grid_desc* g) {
@@ -398,6 +438,9 @@ int vsaogm_map_create(const vsaogm_map_desc* d, vsaogm_map** out) {
         }
 
         DeviceGuard guard(m->device);
+        hip_check(hipDeviceGetAttribute(&m->num_cus, hipDeviceAttributeMultiprocessorCount, m->device),
+                  "device attribute");
+        if (m->num_cus < 1) m->num_cus = 1;
         m->d_cx.alloc(m->tiles_x, "tile centres x");
         m->d_cy.alloc(m->tiles_y, "tile centres y");
         m->d_rev.alloc(m->halfp, "theta (rev, fp32)");
@@ -405,7 +448,7 @@ int vsaogm_map_create(const vsaogm_map_desc* d, vsaogm_map** out) {
         m->d_theta.alloc(2 * (size_t)half, "theta (rad)");
         m->d_omega.alloc((size_t)m->nkeys * m->halfp, "memories");
         m->d_scale.alloc(m->nkeys, "memory scales");
-        m->d_hmax_u.alloc(2, "class maxima");
+        m->d_hmax_u.alloc(3, "class maxima");
         m->d_bad.alloc(1, "rejected-label counter");
         hip_check(hipMemcpy(m->d_cx.p, m->cx.data(), m->cx.size() * 8, hipMemcpyHostToDevice), "copy");
         hip_check(hipMemcpy(m->d_cy.p, m->cy.data(), m->cy.size() * 8, hipMemcpyHostToDevice), "copy");
@@ -491,16 +534,41 @@ int vsaogm_decode(vsaogm_map* m, const vsaogm_grid_desc* g, int32_t precision, f
         if (!m) fail(VSAOGM_EINVAL, "map is NULL");
         check_grid(g);
         if (!heat || !hmax) fail(VSAOGM_EINVAL, "heat and hmax must not be NULL");
-        if (precision != VSAOGM_FP32) fail(VSAOGM_EINVAL, "precision not available");
+        if (precision < VSAOGM_FP32 || precision > VSAOGM_BF16X3) fail(VSAOGM_EINVAL, "unknown precision");
         DeviceGuard guard(m->device);
         hipStream_t s = (hipStream_t)stream;
         GridCache* gc = grid_cache(m, g, s);
-        hip_check(launch_norm(m->d_omega.p, m->nkeys, m->half, m->halfp, m->D, m->d_scale.p, s),
+        const void* ey_lo = nullptr;
+        const void* ey = y_table(m, gc, precision, &ey_lo, s);
+        DecodeLaunch d;
+        d.plan = decode_plan(precision, gc->ntiles, m->halfp, m->num_cus);
+        const size_t need = decode_partial_floats(d.plan.grid);
+        if (m->d_partial.n < need) {
+            hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+            m->d_partial.alloc(need, "decode partial sums");
+        }
+        hip_check(launch_norm(m->d_omega.p, m->nkeys, m->half, m->halfp, m->D, m->d_scale.p,
+                              m->d_hmax_u.p, s),
                   "norm launch");
-        hip_check(launch_decode(precision, gc->tiles.p, gc->ntiles, gc->ex32.p, nullptr, gc->ey32.p,
-                                nullptr, m->d_omega.p, m->d_scale.p, m->halfp, g->nx, g->ny, heat,
-                                m->d_hmax_u.p, hmax, s),
-                  "decode launch");
+        d.tiles = gc->tiles.p;
+        d.ntiles = gc->ntiles;
+        d.col_tx = gc->col_tx.p;
+        d.ex = gc->ex32.p;
+        d.ey = ey;
+        d.ey_lo = ey_lo;
+        d.omega = m->d_omega.p;
+        d.inv_norm = m->d_scale.p;
+        d.halfp = m->halfp;
+        d.nx = g->nx;
+        d.ny = g->ny;
+        d.tiles_x = m->tiles_x;
+        d.out_scale = (float)(2.0 / (double)m->D);
+        d.heat = heat;
+        d.hmax_u = m->d_hmax_u.p;
+        d.hmax = hmax;
+        d.tile_cnt = gc->tile_cnt.p;
+        d.partial = m->d_partial.p;
+        hip_check(launch_decode(precision, d, s), "decode launch");
     });
 }
 

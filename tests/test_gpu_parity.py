@@ -78,26 +78,38 @@ def check_labels(lab_gpu, lab_ref, ogm_ref, rho):
     assert worst < MARGIN
 
 
+# Single-rounding 16-bit operands are reported, not held to the fp32 bar: their heatmap
+# error is bounded by a few units of their 8- or 11-bit mantissa.
+LOOSE_TOL = {"bf16": 2e-2, "fp16": 3e-3}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "bf16", "fp16"])
 @pytest.mark.parametrize("name", ["toy_room", "mini4x4", "ragged3x3"])
-def test_pipeline_matches_oracle(torch_cuda, name):
-    say(f"[gpu] pipeline parity {name}")
+def test_pipeline_matches_oracle(torch_cuda, name, precision):
+    say(f"[gpu] pipeline parity {name} {precision}")
     w, (om, P, m, H, ogm, lab) = oracle_result(name)
-    g = gpu_run(torch_cuda, w)
+    g = gpu_run(torch_cuda, w, precision)
     assert g["rejected"] == 0
     half = w.D // 2
     ref_mem = om[:, :half + 1, :]
     for key in range(om.shape[0]):
         e = rel_l2(g["mem"][key], ref_mem[key])
         assert e <= MEM_TOL, (key, e)
+    tol = LOOSE_TOL.get(precision, HEAT_TOL)
     for psi in range(2):
         e = rel_l2(g["heat"][psi], P[psi])
         mab = float(np.max(np.abs(g["heat"][psi] - P[psi])))
         say(f"  heat[{psi}] rel-L2 {e:.3e} max-abs {mab:.3e}; max {g['hmax'][psi]:.6f} vs {m[psi]:.6f}")
-        assert e <= HEAT_TOL
-        assert abs(g["hmax"][psi] - m[psi]) <= HEAT_TOL * max(abs(m[psi]), 1e-30)
+        assert e <= tol
+        assert abs(g["hmax"][psi] - m[psi]) <= 2 * tol * max(abs(m[psi]), 1e-30)
         assert g["hmax"][psi] == np.max(g["heat"][psi])
     say(f"  ogm max-abs {np.max(np.abs(g['ogm'] - ogm)):.3e}")
-    check_labels(g["label"], lab, ogm, w.rho)
+    if precision in LOOSE_TOL:
+        agree = float(np.mean(g["label"] == lab))
+        say(f"  labels agree {agree * 100:.4f}% (reported)")
+        assert agree >= 0.98
+    else:
+        check_labels(g["label"], lab, ogm, w.rho)
 
 
 @pytest.mark.parametrize("name", ["toy_room", "mini4x4"])
