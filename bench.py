@@ -84,6 +84,106 @@ def cpu_baseline(w, budget_s: float):
     }
 
 
+def serving_benchmark(n_requests: int = 256, slots: int = 8, precision: str = "bf16x3"):
+    """256 map updates of 16 uneven maps: plain per-request fp32 path vs the request loop.
+
+    Plain path: one update at a time through the map API (copy in, encode, fp32 decode,
+    classify, copy the labels out, synchronise).  Request loop: the server with `slots`
+    execution slots and the bf16 hi+lo decode (fp32-level accuracy).  Throughput is measured
+    with every request queued at once; latency percentiles with Poisson arrivals at 0.5x, 1x and
+    2x the plain path's throughput (for the plain path from its measured service times)."""
+    import torch
+    from paper_2408_09066_amd import native, synth
+
+    maps, reqs = synth.serving_stream(n_requests=n_requests)
+    dev = torch.device("cuda", 0)
+    R = 3
+
+    # ---- plain per-request path
+    objs = [native.Map(m.theta, m.layout, m.tiles) for m in maps]
+    for m, o in zip(maps, objs):   # location tables built before timing
+        o.decode(m.grid, m.side, m.side, "fp32")
+    torch.cuda.synchronize()
+    service, plain_labels = [], []
+    t_all = time.perf_counter()
+    for q in reqs:
+        spec, o = maps[q.map_id], objs[q.map_id]
+        t0 = time.perf_counter()
+        xy = torch.from_numpy(q.xy).to(dev)
+        lb = torch.from_numpy(q.label).to(dev)
+        o.encode(xy, lb)
+        heat, hmax = o.decode(spec.grid, spec.side, spec.side, "fp32")
+        _, lab = native.classify(heat, hmax, R, R, 0.0)
+        plain_labels.append(lab.cpu().numpy())
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t0)
+    plain_total = time.perf_counter() - t_all
+    for o in objs:
+        o.close()
+    plain_ups = len(reqs) / plain_total
+
+    def new_server():
+        srv = native.Server(max_inflight=slots)
+        ids = [srv.add_map(m.theta, m.layout, m.tiles) for m in maps]
+        warm = [srv.submit(i, np.zeros((0, 2), np.float32), np.zeros(0, np.uint8), m.grid, m.side,
+                           m.side, R, R, 0.0, precision)[0] for i, m in zip(ids, maps)]
+        for t in warm:
+            srv.wait(t)
+        return srv, ids
+
+    # ---- request loop, everything queued at once
+    srv, ids = new_server()
+    t0 = time.perf_counter()
+    tk = [srv.submit(ids[q.map_id], q.xy, q.label, maps[q.map_id].grid, maps[q.map_id].side,
+                     maps[q.map_id].side, R, R, 0.0, precision) for q in reqs]
+    res = [srv.wait(t) for t, _ in tk]
+    served_total = time.perf_counter() - t0
+    agree = min(float(np.mean(out["label"] == pl)) for (_, out), pl in zip(tk, plain_labels))
+    assert all(r["status"] == 0 for r in res)
+    stats = srv.stats()
+    srv.close()
+    served_ups = len(reqs) / served_total
+
+    # ---- latency under Poisson arrivals
+    arrivals = np.array([q.arrival_s for q in reqs])
+    lat = {}
+    for mult in (0.5, 1.0, 2.0):
+        qps = mult * plain_ups
+        arr = arrivals / qps
+        # plain path: one server queue with the measured service times
+        fin, last = [], 0.0
+        for a, sv in zip(arr, service):
+            last = max(a, last) + sv
+            fin.append(last - a)
+        srv, ids = new_server()
+        t0 = time.perf_counter()
+        tk = []
+        for q, a in zip(reqs, arr):
+            while time.perf_counter() - t0 < a:
+                pass
+            tk.append(srv.submit(ids[q.map_id], q.xy, q.label, maps[q.map_id].grid,
+                                 maps[q.map_id].side, maps[q.map_id].side, R, R, 0.0, precision)[0])
+        rs = [srv.wait(t) for t in tk]
+        srv.close()
+        ls = [(r["t_done_ns"] - r["t_submit_ns"]) * 1e-6 for r in rs]
+        lat[f"{mult}x"] = {"qps": qps,
+                           "serving_ms": {"p50": percentile(ls, 50), "p99": percentile(ls, 99)},
+                           "plain_ms": {"p50": percentile(fin, 50) * 1e3, "p99": percentile(fin, 99) * 1e3}}
+    return {
+        "workload": (f"{len(reqs)} updates of {len(maps)} maps: D in {{2048,4096,8192}}, 1-16 tiles, "
+                     f"grid sides {min(m.side for m in maps)}-{max(m.side for m in maps)} at 0.05 m, "
+                     f"{min(q.xy.shape[0] for q in reqs)}-{max(q.xy.shape[0] for q in reqs)} points"),
+        "slots": slots,
+        "precision": precision,
+        "updates_per_s": served_ups,
+        "plain_fp32_updates_per_s": plain_ups,
+        "speedup": served_ups / plain_ups,
+        "label_agreement_min": agree,
+        "peak_budget_bytes": stats["peak_bytes"],
+        "latency": lat,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +193,8 @@ def main() -> int:
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16", "bf16x3"])
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle work for the CPU baseline (0 disables it)")
+    ap.add_argument("--serving", type=int, default=1,
+                    help="also run the request-loop benchmark (256 updates of 16 maps)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -202,6 +304,8 @@ def main() -> int:
         "roofline": roof,
     }
     m.close()
+    if args.serving:
+        result["serving"] = serving_benchmark()
     if args.cpu_budget > 0:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(result), flush=True)

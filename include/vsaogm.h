@@ -176,6 +176,90 @@ int vsaogm_memories(const vsaogm_map* map, float* out, vsaogm_stream stream);
  */
 int vsaogm_fuse(vsaogm_map* dst, const vsaogm_map* src, vsaogm_stream stream);
 
+/* ---------------------------------------------------------------------------
+ * Serving: a request loop for map updates of many maps.
+ *
+ * A server owns a set of maps (their memories stay resident on the device)
+ * and runs whole map updates -- encode the request's points into its map,
+ * decode the request's grid, classify it -- for requests that arrive while
+ * others are on the GPU.  Requests are admitted as execution slots (one HIP
+ * stream each) and device memory budget free up; the updates of different
+ * maps overlap on the device, while updates of one map run in submission
+ * order (memories are state).  A request's result does not depend on which
+ * other requests share the device with it.
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+    int64_t hbm_budget_bytes; /* device bytes for in-flight request buffers;
+                                 <= 0 means a quarter of the free memory */
+    int32_t max_inflight;     /* execution slots (streams), 1..32 */
+    int32_t max_queue;        /* pending requests before submit returns EBUSY */
+    int32_t device;           /* HIP device ordinal */
+} vsaogm_server_desc;
+
+typedef struct {
+    int32_t map_id;           /* from vsaogm_server_add_map */
+    const float* xy;          /* host [n][2] world metres (copied by submit) */
+    const uint8_t* label;     /* host [n] point classes (copied by submit) */
+    int64_t n;                /* points, >= 0 */
+    vsaogm_grid_desc grid;    /* grid to decode after the update */
+    int32_t precision;        /* vsaogm_precision of the similarity contraction */
+    int32_t r_occ, r_emp;     /* disk radii (classify) */
+    float rho;                /* decision threshold */
+    float* ogm;               /* host [ny][nx] signed difference, or NULL */
+    uint8_t* label_out;       /* host [ny][nx] occupancy labels, or NULL */
+    float* heat;              /* host [2][ny][nx] similarity maps, or NULL */
+} vsaogm_request;
+
+typedef struct {
+    int32_t status;           /* VSAOGM_OK, or the error the update hit */
+    int32_t slot;             /* execution slot that ran it */
+    int64_t t_submit_ns;      /* steady-clock time stamps (ns) */
+    int64_t t_start_ns;       /* admitted and launched */
+    int64_t t_done_ns;        /* outputs written to the caller's buffers */
+    float hmax[2];            /* per-class maxima of the decoded grid */
+} vsaogm_result;
+
+/* Create a server on a device.  *out receives the handle. */
+int vsaogm_server_create(const vsaogm_server_desc* desc, vsaogm_server** out);
+
+/* Finish every admitted request, then destroy the server and its maps. */
+int vsaogm_server_destroy(vsaogm_server* server);
+
+/* Create a map owned by the server (desc->device is ignored: the server's
+   device is used).  *map_id receives its id (0, 1, ...). */
+int vsaogm_server_add_map(vsaogm_server* server, const vsaogm_map_desc* desc, int32_t* map_id);
+
+/* The server-owned map (for vsaogm_memories / vsaogm_fuse after vsaogm_server_drain).
+   Not to be encoded into or destroyed by the caller. */
+int vsaogm_server_get_map(vsaogm_server* server, int32_t map_id, vsaogm_map** out);
+
+/*
+ * Queue one map update.  Inputs are copied before returning; output buffers
+ * must stay valid until the ticket completes.  Returns EBUSY when max_queue
+ * requests are pending (nothing is queued), ENOTFOUND for an unknown map,
+ * EINVAL for invalid arguments (also when the request alone exceeds the
+ * memory budget).  Thread-safe.
+ */
+int vsaogm_submit(vsaogm_server* server, const vsaogm_request* req, uint64_t* ticket);
+
+/*
+ * Non-blocking: VSAOGM_EAGAIN while the ticket runs; otherwise fills *result,
+ * retires the ticket and returns VSAOGM_OK (the update's own status is in
+ * result->status).  ENOTFOUND for an unknown or already retired ticket.
+ */
+int vsaogm_poll(vsaogm_server* server, uint64_t ticket, vsaogm_result* result);
+
+/* Blocking variant of vsaogm_poll. */
+int vsaogm_wait(vsaogm_server* server, uint64_t ticket, vsaogm_result* result);
+
+/* Block until every submitted request has completed. */
+int vsaogm_server_drain(vsaogm_server* server);
+
+/* Counters: requests completed, peak bytes of the budget in use, budget. */
+int vsaogm_server_stats(vsaogm_server* server, int64_t* completed, int64_t* peak_bytes,
+                        int64_t* budget_bytes);
+
 /*
  * Profiling hook: record the given HIP events (hipEvent_t) immediately before and
  * after every launch of one stage's main kernel, on the stream it is launched on:

@@ -22,9 +22,12 @@
 // (the spectrum) is split "stream-K" style: the (tile, K step) iteration space is cut into
 // equal contiguous ranges, one per workgroup, so every CU gets the same work however few
 // tiles there are.  A tile finished by one workgroup is stored from registers; a tile split
-// across workgroups is written as partial sums and the last workgroup to finish it adds
-// them in workgroup order (deterministic) and stores it.  Every store folds the class
-// maxima (eq. non-linearities) into order-preserving unsigned atomics.
+// across workgroups is written as partial sums that a second kernel adds in workgroup order
+// (deterministic) and stores.  Nothing in the GEMM waits on another workgroup: a device-scope
+// fence on this multi-XCD part writes back and invalidates the whole L2 of the XCD, which
+// would evict the location tables of every resident workgroup.  Every store folds the class
+// maxima (eq. non-linearities) into order-preserving unsigned atomics; a one-block kernel
+// converts them once all stores are done.
 #include "internal.h"
 
 namespace vsaogm {
@@ -36,6 +39,22 @@ typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+// Two floats to packed bf16 / fp16 (round to nearest even; v_cvt_pk_* on gfx950).
+__device__ inline uint32_t pack_bf16(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
+}
+__device__ inline uint32_t pack_f16(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, f16x2));
+}
+// The residuals a - bf16(a), b - bf16(b) of a packed pair, packed again.
+__device__ inline uint32_t pack_bf16_lo(float a, float b, uint32_t hi) {
+    const float ha = __uint_as_float(hi << 16), hb = __uint_as_float(hi & 0xffff0000u);
+    return pack_bf16(a - ha, b - hb);
+}
 
 constexpr int kRowBlocks = kDecodeRowBlocks;
 constexpr int kTileRows = 16 * kRowBlocks;
@@ -108,14 +127,11 @@ struct DecodeArgs {
     const float2* ex;          // [nx][halfp] fp32
     const void* ey;            // fp32 [ny][halfp] or 16-bit [ny][2*halfp]
     const void* ey_lo;         // 16-bit residual (split form) or null
-    const float2* omega;       // [nkeys][halfp]
-    const float* inv_norm;     // [nkeys] 1/||w||, 0 for an empty memory
+    const float2* omega_s;     // [nkeys][halfp] conj(Omega) / ||w|| (0 for an empty memory)
     int halfp, nx, ny, tiles_x;
     float out_scale;           // 2 / D
     float* heat;               // [2][ny][nx]
-    unsigned* hmax_u;          // [3]: ordered maxima, finished-tile counter
-    float* hmax;               // [2]
-    int* tile_cnt;             // [ntiles] segments finished per tile (reset by the last)
+    unsigned* hmax_u;          // [2] ordered maxima (zeroed by the norm kernel)
     float* partial;            // [grid][2][2][kTileRows][kTileCols]
     int ksteps;                // K steps per tile
     int steps_per_wg;          // L
@@ -157,20 +173,6 @@ __device__ inline void store_tile(const DecodeArgs& a, const DTile& t, int wave,
     }
 }
 
-// After a tile is stored: count it; the last tile of the grid writes the float maxima.
-__device__ inline void tile_done(const DecodeArgs& a) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(a.hmax_u + 2, 1u);
-        if (prev == (unsigned)a.ntiles - 1) {
-            __threadfence();
-            a.hmax[0] = order_value(atomicOr(a.hmax_u + 0, 0u));
-            a.hmax[1] = order_value(atomicOr(a.hmax_u + 1, 0u));
-        }
-    }
-}
-
 // Workgroups resident per CU: two for the single-product formats; the split form needs more
 // registers than two waves per SIMD allow, so it runs one.
 template <int PREC>
@@ -181,17 +183,22 @@ __global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeAr
     using F = Fmt<PREC>;
     constexpr int KB = F::KB;
     constexpr int NSPLIT = F::kSplit ? 2 : 1;
-    // LDS: A rows [kTileRows], B rows [2 classes][kTileCols], each kRowPitchBytes, hi (+lo)
-    __shared__ __attribute__((aligned(16))) unsigned char smem[NSPLIT * (kTileRows + 2 * kTileCols) * kRowPitchBytes];
-    __shared__ int sh_flag;
-    unsigned char* As = smem;
-    unsigned char* Bs = smem + NSPLIT * kTileRows * kRowPitchBytes;
+    // LDS, two stages: A rows [kTileRows], B rows [2 classes][kTileCols], each
+    // kRowPitchBytes, hi (+ lo).
+    constexpr int STAGE = NSPLIT * (kTileRows + 2 * kTileCols) * kRowPitchBytes;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[2 * STAGE];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, i16 = lane & 15;
     const long long it0 = (long long)blockIdx.x * a.steps_per_wg;
     const long long it1 = min(it0 + a.steps_per_wg, a.total_steps);
     const int first_tile = (int)(it0 / a.ksteps);
+
+    // A: 128-byte rows, 8 units of 16 bytes; B: 64 columns x KB complex, units of 2 complex
+    constexpr int A_UNITS_MAX = kTileRows * 8;
+    constexpr int A_PER_T = (A_UNITS_MAX + 255) / 256;
+    constexpr int B_UNITS = kTileCols * KB / 2;
+    constexpr int B_PER_T = B_UNITS / 256;
 
     long long it = it0;
     while (it < it1) {
@@ -201,19 +208,24 @@ __global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeAr
         it = (long long)ti * a.ksteps + kb1;
         const DTile t = a.tiles[ti];
         const int nrows = 16 * t.nrb;
-
-        // ---- staging assignment
-        // A: nrows rows of 128 bytes = 8 units of 16 bytes per row
-        constexpr int A_UNITS_MAX = kTileRows * 8;
-        constexpr int A_PER_T = (A_UNITS_MAX + 255) / 256;
-        // B: 64 columns x KB complex, units of 2 complex (one float4 of Ex)
-        constexpr int B_UNITS = kTileCols * KB / 2;
-        constexpr int B_PER_T = B_UNITS / 256;
         const int ty = t.ty;
 
         u32x4 ra[A_PER_T * NSPLIT];
         f32x4 rx[B_PER_T], ro[B_PER_T][2];
-        float rs[B_PER_T][2];
+        // per-tile column data, hoisted out of the K loop: every load of a K step then has a
+        // ready address and the first wait on them comes after the step's MFMAs
+        const f32x4* ex_row[B_PER_T];
+        const f32x4* om_row[B_PER_T];
+#pragma unroll
+        for (int u = 0; u < B_PER_T; ++u) {
+            const int idx = tid + 256 * u;
+            const int c = idx / (KB / 2), part = idx % (KB / 2);
+            const int gcol = min(t.col0 + c, a.nx - 1);
+            const int key0 = 2 * (ty * a.tiles_x + a.col_tx[gcol]);
+            ex_row[u] = reinterpret_cast<const f32x4*>(a.ex + (size_t)gcol * a.halfp + 2 * part);
+            om_row[u] = reinterpret_cast<const f32x4*>(a.omega_s + (size_t)key0 * a.halfp + 2 * part);
+        }
+        const size_t om_class = (size_t)a.halfp / 2;  // one key further, in f32x4 units
 
         // Global loads of one K step into registers.  Rows past the tile's last row block (but
         // inside the kTileRows LDS rows) load a clamped valid row that the MFMAs never read.
@@ -238,21 +250,18 @@ __global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeAr
             }
 #pragma unroll
             for (int u = 0; u < B_PER_T; ++u) {
-                const int idx = tid + 256 * u;
-                const int c = idx / (KB / 2), part = idx % (KB / 2);
-                const int gcol = min(t.col0 + c, a.nx - 1);
-                const int key0 = 2 * (ty * a.tiles_x + a.col_tx[gcol]);
-                const size_t boff = (size_t)kb * KB + 2 * part;
-                rx[u] = *reinterpret_cast<const f32x4*>(a.ex + (size_t)gcol * a.halfp + boff);
-#pragma unroll
-                for (int p = 0; p < 2; ++p) {
-                    ro[u][p] = *reinterpret_cast<const f32x4*>(a.omega + (size_t)(key0 + p) * a.halfp + boff);
-                    rs[u][p] = a.inv_norm[key0 + p];
-                }
+                const size_t boff = (size_t)kb * (KB / 2);  // f32x4 = two complex bins
+                rx[u] = ex_row[u][boff];
+                ro[u][0] = om_row[u][boff];
+                ro[u][1] = om_row[u][boff + om_class];
             }
         };
 
-        auto lstore = [&]() {
+        // Registers of one K step into LDS stage `st`; the column operand becomes
+        // conj(Omega)/||w|| * Ex written as (Re, -Im), rounded to the operand format.
+        auto lstore = [&](int st) {
+            unsigned char* As = smem + st * STAGE;
+            unsigned char* Bs = As + NSPLIT * kTileRows * kRowPitchBytes;
 #pragma unroll
             for (int u = 0; u < A_PER_T; ++u) {
                 const int idx = tid + 256 * u;
@@ -270,32 +279,22 @@ __global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeAr
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
                     const f32x4 o = ro[u][p];
-                    const float s = rs[u][p];
-                    // conj(o) * e / ||w||, stored as (Re, -Im)
-                    const float r0 = (o.x * e.x + o.y * e.y) * s;
-                    const float r1 = (o.y * e.x - o.x * e.y) * s;
-                    const float r2 = (o.z * e.z + o.w * e.w) * s;
-                    const float r3 = (o.w * e.z - o.z * e.w) * s;
+                    // (o.x + i o.y)(e.x + i e.y) -> (Re, -Im)
+                    const float r0 = __builtin_fmaf(o.x, e.x, -o.y * e.y);
+                    const float r1 = -__builtin_fmaf(o.x, e.y, o.y * e.x);
+                    const float r2 = __builtin_fmaf(o.z, e.z, -o.w * e.w);
+                    const float r3 = -__builtin_fmaf(o.z, e.w, o.w * e.z);
                     unsigned char* dst = Bs + (p * kTileCols + c) * kRowPitchBytes;
                     if (PREC == 0) {
                         *reinterpret_cast<f32x4*>(dst + 16 * part) = f32x4{r0, r1, r2, r3};
                     } else if (PREC == 2) {
-                        const u32x2 v = {(uint32_t)f16_bits(r0) | ((uint32_t)f16_bits(r1) << 16),
-                                         (uint32_t)f16_bits(r2) | ((uint32_t)f16_bits(r3) << 16)};
-                        *reinterpret_cast<u32x2*>(dst + 8 * part) = v;
+                        *reinterpret_cast<u32x2*>(dst + 8 * part) = u32x2{pack_f16(r0, r1), pack_f16(r2, r3)};
                     } else {
-                        const uint16_t h0 = bf16_bits(r0), h1 = bf16_bits(r1), h2 = bf16_bits(r2),
-                                       h3 = bf16_bits(r3);
-                        const u32x2 v = {(uint32_t)h0 | ((uint32_t)h1 << 16),
-                                         (uint32_t)h2 | ((uint32_t)h3 << 16)};
-                        *reinterpret_cast<u32x2*>(dst + 8 * part) = v;
-                        if (F::kSplit) {
-                            const u32x2 l = {(uint32_t)bf16_bits(r0 - bf16_value(h0)) |
-                                                 ((uint32_t)bf16_bits(r1 - bf16_value(h1)) << 16),
-                                             (uint32_t)bf16_bits(r2 - bf16_value(h2)) |
-                                                 ((uint32_t)bf16_bits(r3 - bf16_value(h3)) << 16)};
-                            *reinterpret_cast<u32x2*>(dst + 2 * kTileCols * kRowPitchBytes + 8 * part) = l;
-                        }
+                        const uint32_t h01 = pack_bf16(r0, r1), h23 = pack_bf16(r2, r3);
+                        *reinterpret_cast<u32x2*>(dst + 8 * part) = u32x2{h01, h23};
+                        if (F::kSplit)
+                            *reinterpret_cast<u32x2*>(dst + 2 * kTileCols * kRowPitchBytes + 8 * part) =
+                                u32x2{pack_bf16_lo(r0, r1, h01), pack_bf16_lo(r2, r3, h23)};
                     }
                 }
             }
@@ -307,12 +306,18 @@ __global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeAr
 #pragma unroll
             for (int rb = 0; rb < kRowBlocks; ++rb) acc[p][rb] = v4f{0.f, 0.f, 0.f, 0.f};
 
+        // Pipeline: stage k+1 is loaded and written to the other LDS stage while the MFMAs
+        // of stage k run; one barrier per K step.
+        __syncthreads();  // the previous tile's last reads of both stages are done
         gload(kb0);
+        lstore(0);
+        __syncthreads();
         for (int kb = kb0; kb < kb1; ++kb) {
-            __syncthreads();
-            lstore();
-            __syncthreads();
-            if (kb + 1 < kb1) gload(kb + 1);
+            const int st = (kb - kb0) & 1;
+            const bool more = kb + 1 < kb1;
+            if (more) gload(kb + 1);
+            const unsigned char* As = smem + st * STAGE;
+            const unsigned char* Bs = As + NSPLIT * kTileRows * kRowPitchBytes;
             const int bcol = 16 * wave + i16;
             // MFMAs are issued with the row-block loop innermost so that consecutive
             // instructions update different accumulators (no back-to-back dependency).
@@ -381,15 +386,16 @@ __global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeAr
                                 }
                 }
             }
+            if (more) lstore(st ^ 1);
+            __syncthreads();
         }
 
-        const bool whole = (kb0 == 0 && kb1 == a.ksteps);
-        if (whole) {
+        if (kb0 == 0 && kb1 == a.ksteps) {  // the whole tile: store it
             store_tile(a, t, wave, lane, acc);
-            tile_done(a);
             continue;
         }
-        // partial tile: slot 0 if this is the workgroup's first tile, else slot 1
+        // a tile split across workgroups: store this segment's partial sums (slot 0 if the
+        // tile is the workgroup's first, else slot 1); k_decode_fix adds the segments
         const int slot = (ti == first_tile) ? 0 : 1;
         float* part = a.partial + ((size_t)blockIdx.x * 2 + slot) * 2 * kTileRows * kTileCols;
 #pragma unroll
@@ -400,44 +406,63 @@ __global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeAr
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
                         part[((size_t)p * kTileRows + 16 * rb + 4 * g + j) * kTileCols + 16 * wave + i16] = acc[p][rb][j];
-        const int w_first = (int)(((long long)ti * a.ksteps) / a.steps_per_wg);
-        const int w_last = (int)(((long long)ti * a.ksteps + a.ksteps - 1) / a.steps_per_wg);
-        // every wave publishes its partial sums device-wide before the tile's counter moves
-        __threadfence();
-        __syncthreads();
-        if (tid == 0) {
-            const int prev = atomicAdd(a.tile_cnt + ti, 1);
-            const int last = (prev == w_last - w_first) ? 1 : 0;
-            if (last) {
-                a.tile_cnt[ti] = 0;  // ready for the next decode
-                __threadfence();
-            }
-            sh_flag = last;
-        }
-        __syncthreads();
-        if (!sh_flag) continue;
-        __threadfence();  // acquire the other segments' partial sums
-        // last segment: add every segment's partial sums in workgroup order
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int rb = 0; rb < kRowBlocks; ++rb) acc[p][rb] = v4f{0.f, 0.f, 0.f, 0.f};
-        for (int w = w_first; w <= w_last; ++w) {
-            const int wslot = ((int)(((long long)w * a.steps_per_wg) / a.ksteps) == ti) ? 0 : 1;
-            const float* src = a.partial + ((size_t)w * 2 + wslot) * 2 * kTileRows * kTileCols;
-#pragma unroll
-            for (int p = 0; p < 2; ++p)
-#pragma unroll
-                for (int rb = 0; rb < kRowBlocks; ++rb)
-                    if (rb < t.nrb)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j)
-                            acc[p][rb][j] += __builtin_nontemporal_load(
-                                src + ((size_t)p * kTileRows + 16 * rb + 4 * g + j) * kTileCols + 16 * wave + i16);
-        }
-        store_tile(a, t, wave, lane, acc);
-        tile_done(a);
     }
+}
+
+// Split tiles: add the segments' partial sums in workgroup order (deterministic), scale, store,
+// fold the maxima.  Block (tile, eighth): 7 elements per thread, all loads of a thread in
+// flight together; one atomic per block and class.  Tiles finished whole by one workgroup are
+// skipped.  Runs after the GEMM, so the kernel boundary makes the partial sums visible.
+constexpr int kFixParts = 8;
+constexpr int kFixPer = 2 * kTileRows * kTileCols / kFixParts / 256;  // elements per thread
+static_assert(kFixPer * 256 * kFixParts == 2 * kTileRows * kTileCols, "fix-up split");
+
+__global__ __launch_bounds__(256) void k_decode_fix(DecodeArgs a) {
+    constexpr int PER_TILE = 2 * kTileRows * kTileCols;
+    const int ti = blockIdx.x / kFixParts, part8 = blockIdx.x % kFixParts;
+    const long long t0 = (long long)ti * a.ksteps;
+    const int w_first = (int)(t0 / a.steps_per_wg);
+    const int w_last = (int)((t0 + a.ksteps - 1) / a.steps_per_wg);
+    if (w_first == w_last) return;  // whole tile, stored by the GEMM
+    const DTile t = a.tiles[ti];
+    float sum[kFixPer];
+#pragma unroll
+    for (int j = 0; j < kFixPer; ++j) sum[j] = 0.f;
+    for (int w = w_first; w <= w_last; ++w) {
+        const int slot = ((long long)w * a.steps_per_wg / a.ksteps == ti) ? 0 : 1;
+        const float* src = a.partial + ((size_t)w * 2 + slot) * PER_TILE + part8 * (PER_TILE / kFixParts);
+#pragma unroll
+        for (int j = 0; j < kFixPer; ++j) sum[j] += src[threadIdx.x + 256 * j];
+    }
+    float mx[2] = {-INFINITY, -INFINITY};
+#pragma unroll
+    for (int j = 0; j < kFixPer; ++j) {
+        const int rem = part8 * (PER_TILE / kFixParts) + threadIdx.x + 256 * j;
+        const int p = rem / (kTileRows * kTileCols);
+        const int r = (rem / kTileCols) % kTileRows, c = rem % kTileCols;
+        const int row = t.row0 + r, col = t.col0 + c;
+        if (r < 16 * t.nrb && row < t.row_end && col < a.nx) {
+            const float v = sum[j] * a.out_scale;
+            a.heat[(size_t)p * a.nx * a.ny + (size_t)row * a.nx + col] = v;
+            mx[p] = fmaxf(mx[p], v);
+        }
+    }
+    __shared__ float sh[2][4];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        float m = mx[q];
+        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+        if ((threadIdx.x & 63) == 0) sh[q][threadIdx.x >> 6] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        const float m = fmaxf(fmaxf(sh[threadIdx.x][0], sh[threadIdx.x][1]), fmaxf(sh[threadIdx.x][2], sh[threadIdx.x][3]));
+        if (m > -INFINITY) atomicMax(a.hmax_u + threadIdx.x, order_key(m));
+    }
+}
+
+__global__ void k_hmax_final(const unsigned* __restrict__ hmax_u, float* __restrict__ hmax) {
+    if (threadIdx.x < 2) hmax[threadIdx.x] = order_value(hmax_u[threadIdx.x]);
 }
 
 }  // namespace
@@ -481,8 +506,7 @@ hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
     a.ex = d.ex;
     a.ey = d.ey;
     a.ey_lo = d.ey_lo;
-    a.omega = d.omega;
-    a.inv_norm = d.inv_norm;
+    a.omega_s = d.omega_s;
     a.halfp = d.halfp;
     a.nx = d.nx;
     a.ny = d.ny;
@@ -490,8 +514,6 @@ hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
     a.out_scale = d.out_scale;
     a.heat = d.heat;
     a.hmax_u = d.hmax_u;
-    a.hmax = d.hmax;
-    a.tile_cnt = d.tile_cnt;
     a.partial = d.partial;
     a.ksteps = d.plan.ksteps;
     a.steps_per_wg = d.plan.steps_per_wg;
@@ -505,7 +527,10 @@ hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
         case 3: hipLaunchKernelGGL(k_decode<3>, grid, block, 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
+    if (d.plan.steps_per_wg % d.plan.ksteps != 0 || d.plan.steps_per_wg < d.plan.ksteps)
+        hipLaunchKernelGGL(k_decode_fix, dim3((unsigned)d.ntiles * kFixParts), dim3(256), 0, s, a);
     profile_end(kStageDecode, s);
+    hipLaunchKernelGGL(k_hmax_final, dim3(1), dim3(64), 0, s, d.hmax_u, d.hmax);
     return hipGetLastError();
 }
 

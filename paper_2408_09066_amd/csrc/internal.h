@@ -50,6 +50,9 @@ struct DTile {
     int pad[3];
 };
 
+// ---- error text shared by every entry point (map.hip) -------------------------------
+void set_last_error(const char* msg);
+
 // ---- profiling hook (map.hip) --------------------------------------------------------
 enum ProfileStage { kStageEncode = 0, kStageDecode = 1, kStageClassify = 2, kNumStages = 3 };
 void profile_begin(int stage, hipStream_t s);
@@ -82,10 +85,10 @@ hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const
                          float max_rev_x, float max_rev_y, int half, int halfp,
                          const EncodeWork& w, float2* omega, hipStream_t s);
 
-// inv_norm[key] = 1/||w_key|| (0 for an empty memory).  Also zeroes hmax_u[0..2] (class
-// maxima and finished-tile counter of the decode that follows).
+// inv_norm[key] = 1/||w_key|| (0 for an empty memory) and omega_s = conj(Omega) * inv_norm.
+// Also zeroes hmax_u[0..2] (class maxima and finished-tile counter of the decode that follows).
 hipError_t launch_norm(const float2* omega, int nkeys, int half, int halfp, int D, float* inv_norm,
-                       unsigned* hmax_u, hipStream_t s);
+                       float2* omega_s, unsigned* hmax_u, hipStream_t s);
 
 hipError_t launch_memories_export(const float2* omega, const double* theta_rad, const LayoutDev& L,
                                   int nkeys, int half, int halfp, float* out, hipStream_t s);
@@ -118,14 +121,12 @@ struct DecodeLaunch {
     const float2* ex;       // fp32 [nx][halfp]
     const void* ey;         // fp32 [ny][halfp] (FP32) or 16-bit [ny][2*halfp]
     const void* ey_lo;      // bf16 residual table (BF16X3) or null
-    const float2* omega;
-    const float* inv_norm;
+    const float2* omega_s;  // conj(Omega) / ||w||, [nkeys][halfp]
     int halfp, nx, ny, tiles_x;
     float out_scale;        // 2 / D
     float* heat;
     unsigned* hmax_u;       // zeroed by launch_norm
     float* hmax;
-    int* tile_cnt;          // [ntiles], zero between launches
     float* partial;         // decode_partial_floats(plan.grid)
     DecodePlan plan;
 };

@@ -89,6 +89,17 @@ struct DevBuf {
         p = static_cast<T*>(q);
         n = count;
     }
+    // Stream-ordered replacement: the old block is released and the new one obtained in the
+    // order of stream s, so growing a buffer never synchronises the device.
+    void alloc_async(size_t count, hipStream_t s, const char* what) {
+        if (p) hip_check(hipFreeAsync(p, s), what);
+        p = nullptr;
+        n = 0;
+        void* q = nullptr;
+        hip_check(hipMallocAsync(&q, std::max<size_t>(count, 1) * sizeof(T), s), what);
+        p = static_cast<T*>(q);
+        n = count;
+    }
 };
 
 __global__ void k_zero_words(unsigned* p, size_t n) {
@@ -121,7 +132,6 @@ struct GridCache {
     DevBuf<DTile> tiles;
     int ntiles = 0;
     DevBuf<int> col_tx;              // [nx] tile column of every grid column
-    DevBuf<int> tile_cnt;            // [ntiles] stream-K segment counters (zero at rest)
     DevBuf<float2> ex32, ey32;       // fp32 tables [n][halfp]
     DevBuf<uint16_t> ey_bf, ey_bf_lo, ey_h;  // 16-bit y tables [ny][2*halfp], built on first use
 };
@@ -134,6 +144,7 @@ ProfileSlot g_profile[kNumStages];
 }  // namespace
 
 namespace vsaogm {
+void set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
 void profile_begin(int stage, hipStream_t s) {
     if (g_profile[stage].begin) (void)hipEventRecord(g_profile[stage].begin, s);
 }
@@ -157,6 +168,7 @@ struct vsaogm_map {
     DevBuf<double> d_theta;             // [half][2] Theta, rad/m
     DevBuf<float2> d_omega;             // [nkeys][halfp] local-frame memories
     DevBuf<float> d_scale;              // [nkeys] 1/||w||
+    DevBuf<float2> d_omega_s;           // [nkeys][halfp] conj(Omega)/||w|| for the decode
     DevBuf<float> d_partial;            // stream-K partial sums of the decode
     int num_cus = 0;
     DevBuf<unsigned> d_hmax_u;          // [3] ordered class maxima, finished-block counter
@@ -219,18 +231,17 @@ int nearest_1d(const std::vector<double>& c, double v) {
 void ensure_encode_workspace(vsaogm_map* m, int64_t n, hipStream_t s) {
     const EncodePlan p = encode_plan(n, m->halfp, m->nkeys);
     if (n <= m->cap_n && p.nchunks <= m->cap_chunks && p.max_echunks <= m->cap_echunks) return;
-    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-    const int64_t cap = std::max<int64_t>(n + n / 4, 4096);
+    const int64_t cap = std::max<int64_t>(n + n / 2, 4096);
     const EncodePlan q = encode_plan(cap, m->halfp, m->nkeys);
     const int chunks = std::max(q.nchunks, p.nchunks);
     const int echunks = std::max(q.max_echunks, p.max_echunks);
-    m->w_key.alloc(cap, "encode keys");
-    m->w_sorted.alloc(cap, "encode sorted");
-    m->w_sorted_lo.alloc(cap, "encode sorted residuals");
-    m->w_hist.alloc((size_t)chunks * m->nkeys, "encode histogram");
-    m->w_table.alloc(echunks, "encode table");
-    m->w_partial.alloc((size_t)echunks * m->halfp, "encode partial spectra");
-    if (!m->w_meta.p) m->w_meta.alloc(1 + 3 * (size_t)m->nkeys, "encode meta");
+    m->w_key.alloc_async(cap, s, "encode keys");
+    m->w_sorted.alloc_async(cap, s, "encode sorted");
+    m->w_sorted_lo.alloc_async(cap, s, "encode sorted residuals");
+    m->w_hist.alloc_async((size_t)chunks * m->nkeys, s, "encode histogram");
+    m->w_table.alloc_async(echunks, s, "encode table");
+    m->w_partial.alloc_async((size_t)echunks * m->halfp, s, "encode partial spectra");
+    if (!m->w_meta.p) m->w_meta.alloc_async(1 + 3 * (size_t)m->nkeys, s, "encode meta");
     m->cap_n = cap;
     m->cap_chunks = chunks;
     m->cap_echunks = echunks;
@@ -313,7 +324,6 @@ GridCache* grid_cache(vsaogm_map* m, const vsaogm_grid_desc* g, hipStream_t s) {
     }
     gc->ntiles = (int)tl.size();
     gc->tiles.alloc(tl.size(), "decode tile list");
-    gc->tile_cnt.alloc(tl.size(), "decode tile counters");
     gc->col_tx.alloc(g->nx, "column tiles");
     gc->local_x.alloc(g->nx, "local x");
     gc->local_y.alloc(g->ny, "local y");
@@ -326,7 +336,6 @@ GridCache* grid_cache(vsaogm_map* m, const vsaogm_grid_desc* g, hipStream_t s) {
               "copy local x");
     hip_check(hipMemcpy(gc->local_y.p, ly.data(), ly.size() * sizeof(double), hipMemcpyHostToDevice),
               "copy local y");
-    hip_check(hipMemset(gc->tile_cnt.p, 0, tl.size() * sizeof(int)), "clear tile counters");
     hip_check(launch_table_f32(m->d_theta.p, 0, gc->local_x.p, g->nx, m->half, m->halfp, gc->ex32.p, s),
               "x table");
     GridCache* raw = gc.get();
@@ -448,6 +457,7 @@ int vsaogm_map_create(const vsaogm_map_desc* d, vsaogm_map** out) {
         m->d_theta.alloc(2 * (size_t)half, "theta (rad)");
         m->d_omega.alloc((size_t)m->nkeys * m->halfp, "memories");
         m->d_scale.alloc(m->nkeys, "memory scales");
+        m->d_omega_s.alloc((size_t)m->nkeys * m->halfp, "scaled memories");
         m->d_hmax_u.alloc(3, "class maxima");
         m->d_bad.alloc(1, "rejected-label counter");
         hip_check(hipMemcpy(m->d_cx.p, m->cx.data(), m->cx.size() * 8, hipMemcpyHostToDevice), "copy");
@@ -543,12 +553,9 @@ int vsaogm_decode(vsaogm_map* m, const vsaogm_grid_desc* g, int32_t precision, f
         DecodeLaunch d;
         d.plan = decode_plan(precision, gc->ntiles, m->halfp, m->num_cus);
         const size_t need = decode_partial_floats(d.plan.grid);
-        if (m->d_partial.n < need) {
-            hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-            m->d_partial.alloc(need, "decode partial sums");
-        }
+        if (m->d_partial.n < need) m->d_partial.alloc_async(need, s, "decode partial sums");
         hip_check(launch_norm(m->d_omega.p, m->nkeys, m->half, m->halfp, m->D, m->d_scale.p,
-                              m->d_hmax_u.p, s),
+                              m->d_omega_s.p, m->d_hmax_u.p, s),
                   "norm launch");
         d.tiles = gc->tiles.p;
         d.ntiles = gc->ntiles;
@@ -556,8 +563,7 @@ int vsaogm_decode(vsaogm_map* m, const vsaogm_grid_desc* g, int32_t precision, f
         d.ex = gc->ex32.p;
         d.ey = ey;
         d.ey_lo = ey_lo;
-        d.omega = m->d_omega.p;
-        d.inv_norm = m->d_scale.p;
+        d.omega_s = m->d_omega_s.p;
         d.halfp = m->halfp;
         d.nx = g->nx;
         d.ny = g->ny;
@@ -566,7 +572,6 @@ int vsaogm_decode(vsaogm_map* m, const vsaogm_grid_desc* g, int32_t precision, f
         d.heat = heat;
         d.hmax_u = m->d_hmax_u.p;
         d.hmax = hmax;
-        d.tile_cnt = gc->tile_cnt.p;
         d.partial = m->d_partial.p;
         hip_check(launch_decode(precision, d, s), "decode launch");
     });

@@ -22,7 +22,9 @@ EXPORTED = [
     "vsaogm_version", "vsaogm_last_error", "vsaogm_map_create", "vsaogm_map_destroy",
     "vsaogm_map_info", "vsaogm_map_reset", "vsaogm_encode", "vsaogm_map_take_rejected",
     "vsaogm_decode", "vsaogm_classify", "vsaogm_memories", "vsaogm_fuse",
-    "vsaogm_profile_events",
+    "vsaogm_profile_events", "vsaogm_server_create", "vsaogm_server_destroy",
+    "vsaogm_server_add_map", "vsaogm_server_get_map", "vsaogm_submit", "vsaogm_poll",
+    "vsaogm_wait", "vsaogm_server_drain", "vsaogm_server_stats",
 ]
 
 
@@ -43,6 +45,24 @@ class MapDesc(ctypes.Structure):
 class GridDesc(ctypes.Structure):
     _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double), ("res", ctypes.c_double),
                 ("nx", ctypes.c_int32), ("ny", ctypes.c_int32)]
+
+
+class ServerDesc(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("max_queue", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("map_id", ctypes.c_int32), ("xy", ctypes.c_void_p), ("label", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("grid", GridDesc), ("precision", ctypes.c_int32),
+                ("r_occ", ctypes.c_int32), ("r_emp", ctypes.c_int32), ("rho", ctypes.c_float),
+                ("ogm", ctypes.c_void_p), ("label_out", ctypes.c_void_p), ("heat", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("t_submit_ns", ctypes.c_int64), ("t_start_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64), ("hmax", ctypes.c_float * 2)]
 
 
 _lib = None
@@ -70,6 +90,15 @@ def load(path: str = LIB_PATH):
     L.vsaogm_memories.argtypes = [P, P, P]
     L.vsaogm_fuse.argtypes = [P, P, P]
     L.vsaogm_profile_events.argtypes = [i32, P, P]
+    L.vsaogm_server_create.argtypes = [ctypes.POINTER(ServerDesc), ctypes.POINTER(P)]
+    L.vsaogm_server_destroy.argtypes = [P]
+    L.vsaogm_server_add_map.argtypes = [P, ctypes.POINTER(MapDesc), ctypes.POINTER(i32)]
+    L.vsaogm_server_get_map.argtypes = [P, i32, ctypes.POINTER(P)]
+    L.vsaogm_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    L.vsaogm_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
+    L.vsaogm_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
+    L.vsaogm_server_drain.argtypes = [P]
+    L.vsaogm_server_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     for name in EXPORTED:
         if name not in ("vsaogm_version", "vsaogm_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -195,3 +224,113 @@ def profile_events(stage: str, begin=None, end=None):
     b = ctypes.c_void_p(begin.cuda_event if begin is not None else 0)
     e = ctypes.c_void_p(end.cuda_event if end is not None else 0)
     check(load().vsaogm_profile_events(STAGES[stage], b, e))
+
+
+class ServerMap:
+    """A map owned by a Server (read-only view for memories / fusion)."""
+
+    def __init__(self, handle, D, n_memories, device):
+        self._h, self.D, self.n_memories, self.device = handle, D, n_memories, device
+
+    def memories(self, out=None, stream=None):
+        return Map.memories(self, out, stream)
+
+
+class Server:
+    """The request loop of the C ABI: submit map updates, poll for their results."""
+
+    def __init__(self, device: int = 0, max_inflight: int = 4, max_queue: int = 1024,
+                 hbm_budget_bytes: int = 0):
+        L = load()
+        d = ServerDesc(int(hbm_budget_bytes), int(max_inflight), int(max_queue), int(device))
+        h = ctypes.c_void_p()
+        check(L.vsaogm_server_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.device = int(device)
+        self._keep = {}
+        self._maps = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().vsaogm_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_map(self, theta, layout, tiles) -> int:
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        d = MapDesc(int(th.shape[0]), th.ctypes.data, float(layout[0]), float(layout[1]),
+                    float(layout[2]), float(layout[3]), int(tiles[0]), int(tiles[1]), self.device)
+        mid = ctypes.c_int32()
+        check(load().vsaogm_server_add_map(self._h, ctypes.byref(d), ctypes.byref(mid)))
+        self._maps[mid.value] = (int(th.shape[0]), 2 * int(tiles[0]) * int(tiles[1]))
+        return int(mid.value)
+
+    def get_map(self, map_id: int) -> ServerMap:
+        h = ctypes.c_void_p()
+        check(load().vsaogm_server_get_map(self._h, int(map_id), ctypes.byref(h)))
+        D, nmem = self._maps[map_id]
+        return ServerMap(h, D, nmem, self.device)
+
+    def submit(self, map_id: int, xy: np.ndarray, label: np.ndarray, grid, nx: int, ny: int,
+               r_occ: int, r_emp: int, rho: float = 0.0, precision: str = "fp32",
+               want=("label",), block_when_busy: bool = True):
+        """Queue one update; returns (ticket, outputs dict of numpy arrays filled on completion)."""
+        import time
+        xy = np.ascontiguousarray(xy, dtype=np.float32).reshape(-1, 2)
+        label = np.ascontiguousarray(label, dtype=np.uint8).reshape(-1)
+        out = {}
+        if "label" in want:
+            out["label"] = np.empty((ny, nx), dtype=np.uint8)
+        if "ogm" in want:
+            out["ogm"] = np.empty((ny, nx), dtype=np.float32)
+        if "heat" in want:
+            out["heat"] = np.empty((2, ny, nx), dtype=np.float32)
+        req = Request(int(map_id), xy.ctypes.data, label.ctypes.data, int(xy.shape[0]),
+                      grid_desc(grid, nx, ny), PRECISIONS[precision], int(r_occ), int(r_emp),
+                      float(rho),
+                      out["ogm"].ctypes.data if "ogm" in out else None,
+                      out["label"].ctypes.data if "label" in out else None,
+                      out["heat"].ctypes.data if "heat" in out else None)
+        t = ctypes.c_uint64()
+        while True:
+            rc = load().vsaogm_submit(self._h, ctypes.byref(req), ctypes.byref(t))
+            if rc == EBUSY and block_when_busy:
+                time.sleep(50e-6)
+                continue
+            check(rc)
+            break
+        self._keep[t.value] = out
+        return int(t.value), out
+
+    def poll(self, ticket: int):
+        """None while running; else a dict with status, slot, times (ns) and maxima."""
+        r = Result()
+        rc = load().vsaogm_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(r))
+        if rc == EAGAIN:
+            return None
+        check(rc)
+        self._keep.pop(ticket, None)
+        return {"status": r.status, "slot": r.slot, "t_submit_ns": r.t_submit_ns,
+                "t_start_ns": r.t_start_ns, "t_done_ns": r.t_done_ns,
+                "hmax": (r.hmax[0], r.hmax[1])}
+
+    def wait(self, ticket: int):
+        r = Result()
+        check(load().vsaogm_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(r)))
+        self._keep.pop(ticket, None)
+        return {"status": r.status, "slot": r.slot, "t_submit_ns": r.t_submit_ns,
+                "t_start_ns": r.t_start_ns, "t_done_ns": r.t_done_ns,
+                "hmax": (r.hmax[0], r.hmax[1])}
+
+    def drain(self):
+        check(load().vsaogm_server_drain(self._h))
+
+    def stats(self):
+        c, p, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        check(load().vsaogm_server_stats(self._h, ctypes.byref(c), ctypes.byref(p), ctypes.byref(b)))
+        return {"completed": c.value, "peak_bytes": p.value, "budget_bytes": b.value}

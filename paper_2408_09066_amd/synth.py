@@ -257,3 +257,65 @@ def build(recipe: ScanRecipe) -> Workload:
 
 def workload(name: str) -> Workload:
     return build(RECIPES[name])
+
+
+@dataclasses.dataclass
+class MapSpec:
+    D: int
+    ell: float
+    theta: np.ndarray
+    tiles: Tuple[int, int]
+    side: int                  # grid cells per axis
+    res: float
+    layout: Tuple[float, float, float, float]
+    grid: Tuple[float, float, float]
+    world: World
+
+
+@dataclasses.dataclass
+class UpdateRequest:
+    map_id: int
+    xy: np.ndarray
+    label: np.ndarray
+    arrival_s: float           # Poisson arrival offset (seconds) at unit rate
+
+
+def serving_stream(n_maps: int = 16, n_requests: int = 256, config_id: int = 4,
+                   beams=(360, 4320), empties: int = 10, grid_side=(64, 1024), res: float = 0.05,
+                   dims=(2048, 4096, 8192), ell: float = 0.1, max_tiles: int = 4):
+    """Maps of uneven size and a Poisson stream of lidar updates to random maps.
+
+    Each map draws D from dims, tiles per axis from 1..max_tiles (1..max_tiles^2 regions) and a
+    grid side log-uniform in grid_side rounded to a multiple of the tiles, at res m.  Its world
+    is the grid's square with 2 + side/40 rectangles and circles.  Each request picks a map
+    uniformly, a pose by a short random walk, a beam count log-uniform in beams and `empties`
+    samples per beam; arrivals are exponential gaps of mean 1 (scale by 1/QPS)."""
+    rr = rng_for(config_id, STREAM_REQUESTS)
+    maps: List[MapSpec] = []
+    for m in range(n_maps):
+        D = int(rr.choice(dims))
+        t = int(rr.integers(1, max_tiles + 1))
+        side = int(round(math.exp(rr.uniform(math.log(grid_side[0]), math.log(grid_side[1])))))
+        side = max(t, side - side % t)
+        half = side * res / 2.0
+        theta = make_theta(D, ell, rng_for(1000 + 16 * config_id + m, STREAM_THETA))
+        nob = 2 + side // 40
+        world = make_world(half, nob // 2 + 1, nob // 2, (0.3, min(4.0, half / 2)), (0.2, min(1.5, half / 4)),
+                           np.zeros((1, 2)), min(1.0, half / 4), rr)
+        maps.append(MapSpec(D, ell, theta, (t, t), side, res, (-half, -half, half, half),
+                            (-half, -half, res), world))
+    reqs: List[UpdateRequest] = []
+    tnow = 0.0
+    poses = [np.zeros(2) for _ in range(n_maps)]
+    for _ in range(n_requests):
+        m = int(rr.integers(0, n_maps))
+        spec = maps[m]
+        B = int(round(math.exp(rr.uniform(math.log(beams[0]), math.log(beams[1])))))
+        step = rr.normal(0.0, 0.3 * spec.world.half / 4, size=2)
+        p = np.clip(poses[m] + step, -0.8 * spec.world.half, 0.8 * spec.world.half)
+        if _dist_to_obstacles(p, spec.world) > 0.2:
+            poses[m] = p
+        xy, lab = scan_points(spec.world, poses[m][None, :], B, empties, 0.02, rr, rr)
+        tnow += float(rr.exponential(1.0))
+        reqs.append(UpdateRequest(m, xy, lab, tnow))
+    return maps, reqs

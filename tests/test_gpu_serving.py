@@ -1,0 +1,159 @@
+"""The request loop (vsaogm_submit / vsaogm_poll) on the GPU.
+
+Every update a server runs must equal the same update run alone through the map API (same
+kernels, same per-map order), bit for bit, whatever else shares the device; and it must match
+the FP64 oracle within the fp32 bars.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_09066_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2408_09066_amd import native
+    native.load()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def stream():
+    maps, reqs = synth.serving_stream(n_maps=4, n_requests=24, config_id=41, beams=(120, 600),
+                                      grid_side=(40, 200), dims=(1024, 2048))
+    return maps, reqs
+
+
+def direct(torch, maps, reqs, precision):
+    """Each request through the map API, in submission order."""
+    from paper_2408_09066_amd import native
+    objs = [native.Map(m.theta, m.layout, m.tiles) for m in maps]
+    outs = []
+    for q in reqs:
+        spec = maps[q.map_id]
+        mo = objs[q.map_id]
+        mo.encode(torch.from_numpy(q.xy).cuda(), torch.from_numpy(q.label).cuda())
+        heat, hmax = mo.decode(spec.grid, spec.side, spec.side, precision)
+        ogm, lab = native.classify(heat, hmax, 3, 3, 0.0)
+        torch.cuda.synchronize()
+        outs.append({"heat": heat.cpu().numpy(), "ogm": ogm.cpu().numpy(), "label": lab.cpu().numpy()})
+    for mo in objs:
+        mo.close()
+    return outs
+
+
+def served(maps, reqs, precision, only_map=None, max_inflight=4, budget=0):
+    from paper_2408_09066_amd import native
+    srv = native.Server(max_inflight=max_inflight, hbm_budget_bytes=budget)
+    ids = [srv.add_map(m.theta, m.layout, m.tiles) for m in maps]
+    tickets = []
+    for i, q in enumerate(reqs):
+        if only_map is not None and q.map_id != only_map:
+            continue
+        spec = maps[q.map_id]
+        t, out = srv.submit(ids[q.map_id], q.xy, q.label, spec.grid, spec.side, spec.side, 3, 3,
+                            0.0, precision, want=("label", "ogm", "heat"))
+        tickets.append((i, t, out))
+    results = {}
+    for i, t, out in tickets:
+        r = srv.wait(t)
+        assert r["status"] == 0, r
+        results[i] = (out, r)
+    st = srv.stats()
+    srv.close()
+    return results, st
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_server_equals_direct_path(torch_cuda, stream, precision):
+    say(f"[gpu] server vs direct path {precision}")
+    maps, reqs = stream
+    ref = direct(torch_cuda, maps, reqs, precision)
+    res, st = served(maps, reqs, precision)
+    assert st["completed"] == len(reqs)
+    assert st["peak_bytes"] <= st["budget_bytes"]
+    slots = set()
+    for i, (out, r) in res.items():
+        slots.add(r["slot"])
+        for k in ("heat", "ogm", "label"):
+            assert np.array_equal(out[k], ref[i][k]), (i, k)
+        assert r["hmax"][1] == pytest.approx(float(ref[i]["heat"][1].max()), abs=0.0)
+    say(f"  {len(res)} updates bitwise equal to the direct path, slots used {sorted(slots)}")
+
+
+def test_alone_and_in_the_mix_agree(torch_cuda, stream):
+    """A map's updates give the same bits alone on the server and mixed with other maps'."""
+    say("[gpu] alone vs in the mix")
+    maps, reqs = stream
+    mix, _ = served(maps, reqs, "bf16x3", max_inflight=8)
+    for mid in range(len(maps)):
+        alone, _ = served(maps, reqs, "bf16x3", only_map=mid, max_inflight=1)
+        for i, (out, r) in alone.items():
+            for k in ("heat", "ogm", "label"):
+                assert np.array_equal(out[k], mix[i][0][k]), (mid, i, k)
+
+
+def test_tight_budget_still_completes(torch_cuda, stream):
+    """Admission waits for memory: a budget for about one request at a time still finishes."""
+    say("[gpu] tight budget")
+    maps, reqs = stream
+    from paper_2408_09066_amd import native
+    big = max(q.xy.shape[0] for q in reqs)
+    side = max(m.side for m in maps)
+    budget = big * 29 + side * side * 13 + 8 + 512 * 2 * 2 * 112 * 64 * 4 + (big // 64 + 1024) * 1024 * 8 + 4096
+    res, st = served(maps, reqs[:12], "fp32", max_inflight=4, budget=budget)
+    assert st["completed"] == 12
+    assert st["peak_bytes"] <= budget
+
+
+def test_served_update_matches_oracle(torch_cuda):
+    say("[gpu] served update vs oracle")
+    from paper_2408_09066_amd import native
+    w = synth.workload("mini4x4")
+    srv = native.Server(max_inflight=2)
+    mid = srv.add_map(w.theta, w.layout, w.tiles)
+    t, out = srv.submit(mid, w.xy, w.label, w.grid, w.nx, w.ny, w.r_occ, w.r_emp, 0.0, "bf16x3",
+                        want=("heat", "label"))
+    r = srv.wait(t)
+    assert r["status"] == 0
+    _, P, m, H, ogm, lab = oracle.pipeline(w)
+    for p in range(2):
+        e = np.linalg.norm(out["heat"][p] - P[p]) / np.linalg.norm(P[p])
+        assert e < 1e-4
+    assert np.mean(out["label"] == lab) >= 0.999
+    srv.close()
+
+
+def test_server_errors(torch_cuda):
+    say("[gpu] server errors")
+    from paper_2408_09066_amd import native
+    srv = native.Server(max_inflight=1, hbm_budget_bytes=64 << 20)
+    w = synth.workload("toy_room")
+    mid = srv.add_map(w.theta, w.layout, w.tiles)
+    with pytest.raises(native.VsaogmError) as e:
+        srv.submit(mid + 7, w.xy, w.label, w.grid, w.nx, w.ny, 2, 2)
+    assert e.value.code == native.ENOTFOUND
+    with pytest.raises(native.VsaogmError) as e:
+        srv.submit(mid, w.xy, w.label, w.grid, 20000, 20000, 2, 2)   # beyond the budget
+    assert e.value.code == native.EINVAL
+    with pytest.raises(native.VsaogmError):
+        srv.submit(mid, w.xy, w.label, w.grid, w.nx, w.ny, 30, 2)
+    t, _ = srv.submit(mid, w.xy, w.label, w.grid, w.nx, w.ny, 2, 2)
+    srv.wait(t)
+    with pytest.raises(native.VsaogmError) as e:
+        srv.poll(t)                                                     # retired
+    assert e.value.code == native.ENOTFOUND
+    srv.close()
