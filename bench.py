@@ -89,9 +89,11 @@ def serving_benchmark(n_requests: int = 256, slots: int = 8, precision: str = "b
 
     Plain path: one update at a time through the map API (copy in, encode, fp32 decode,
     classify, copy the labels out, synchronise).  Request loop: the server with `slots`
-    execution slots and the bf16 hi+lo decode (fp32-level accuracy).  Throughput is measured
-    with every request queued at once; latency percentiles with Poisson arrivals at 0.5x, 1x and
-    2x the plain path's throughput (for the plain path from its measured service times)."""
+    execution slots and the bf16 hi+lo decode (fp32-level accuracy).  Both paths first run the
+    whole stream once untimed (location tables and work buffers reach their sizes), then the
+    timed pass.  Throughput is measured with every request queued at once; latency percentiles
+    with Poisson arrivals at 0.5x, 1x and 2x the plain path's throughput (for the plain path
+    from its measured per-request service times, one queue)."""
     import torch
     from paper_2408_09066_amd import native, synth
 
@@ -101,47 +103,52 @@ def serving_benchmark(n_requests: int = 256, slots: int = 8, precision: str = "b
 
     # ---- plain per-request path
     objs = [native.Map(m.theta, m.layout, m.tiles) for m in maps]
-    for m, o in zip(maps, objs):   # location tables built before timing
-        o.decode(m.grid, m.side, m.side, "fp32")
-    torch.cuda.synchronize()
-    service, plain_labels = [], []
-    t_all = time.perf_counter()
-    for q in reqs:
-        spec, o = maps[q.map_id], objs[q.map_id]
-        t0 = time.perf_counter()
-        xy = torch.from_numpy(q.xy).to(dev)
-        lb = torch.from_numpy(q.label).to(dev)
-        o.encode(xy, lb)
-        heat, hmax = o.decode(spec.grid, spec.side, spec.side, "fp32")
-        _, lab = native.classify(heat, hmax, R, R, 0.0)
-        plain_labels.append(lab.cpu().numpy())
-        torch.cuda.synchronize()
-        service.append(time.perf_counter() - t0)
-    plain_total = time.perf_counter() - t_all
+
+    def plain_pass():
+        service, labels = [], []
+        t_all = time.perf_counter()
+        for q in reqs:
+            spec, o = maps[q.map_id], objs[q.map_id]
+            t0 = time.perf_counter()
+            xy = torch.from_numpy(q.xy).to(dev)
+            lb = torch.from_numpy(q.label).to(dev)
+            o.encode(xy, lb)
+            heat, hmax = o.decode(spec.grid, spec.side, spec.side, "fp32")
+            _, lab = native.classify(heat, hmax, R, R, 0.0)
+            labels.append(lab.cpu().numpy())
+            torch.cuda.synchronize()
+            service.append(time.perf_counter() - t0)
+        return time.perf_counter() - t_all, service, labels
+
+    plain_pass()
+    plain_total, service, plain_labels = plain_pass()
     for o in objs:
         o.close()
     plain_ups = len(reqs) / plain_total
 
-    def new_server():
-        srv = native.Server(max_inflight=slots)
-        ids = [srv.add_map(m.theta, m.layout, m.tiles) for m in maps]
-        warm = [srv.submit(i, np.zeros((0, 2), np.float32), np.zeros(0, np.uint8), m.grid, m.side,
-                           m.side, R, R, 0.0, precision)[0] for i, m in zip(ids, maps)]
-        for t in warm:
-            srv.wait(t)
-        return srv, ids
+    # ---- request loop
+    srv = native.Server(max_inflight=slots)
+    ids = [srv.add_map(m.theta, m.layout, m.tiles) for m in maps]
 
-    # ---- request loop, everything queued at once
-    srv, ids = new_server()
-    t0 = time.perf_counter()
-    tk = [srv.submit(ids[q.map_id], q.xy, q.label, maps[q.map_id].grid, maps[q.map_id].side,
-                     maps[q.map_id].side, R, R, 0.0, precision) for q in reqs]
-    res = [srv.wait(t) for t, _ in tk]
-    served_total = time.perf_counter() - t0
-    agree = min(float(np.mean(out["label"] == pl)) for (_, out), pl in zip(tk, plain_labels))
-    assert all(r["status"] == 0 for r in res)
-    stats = srv.stats()
-    srv.close()
+    def submit(q):
+        spec = maps[q.map_id]
+        return srv.submit(ids[q.map_id], q.xy, q.label, spec.grid, spec.side, spec.side, R, R, 0.0,
+                          precision)
+
+    items = [{"map_id": ids[q.map_id], "xy": q.xy, "label": q.label, "grid": maps[q.map_id].grid,
+              "nx": maps[q.map_id].side, "ny": maps[q.map_id].side, "r_occ": R, "r_emp": R,
+              "precision": precision} for q in reqs]
+
+    def saturated():
+        t0 = time.perf_counter()
+        tk = srv.submit_many(items)
+        res = [srv.wait(t) for t, _ in tk]
+        assert all(r["status"] == 0 for r in res)
+        return time.perf_counter() - t0, [out["label"] for _, out in tk]
+
+    saturated()
+    served_total, served_labels = saturated()
+    agree = min(float(np.mean(a == b)) for a, b in zip(served_labels, plain_labels))
     served_ups = len(reqs) / served_total
 
     # ---- latency under Poisson arrivals
@@ -150,25 +157,23 @@ def serving_benchmark(n_requests: int = 256, slots: int = 8, precision: str = "b
     for mult in (0.5, 1.0, 2.0):
         qps = mult * plain_ups
         arr = arrivals / qps
-        # plain path: one server queue with the measured service times
         fin, last = [], 0.0
-        for a, sv in zip(arr, service):
-            last = max(a, last) + sv
-            fin.append(last - a)
-        srv, ids = new_server()
+        for a_, sv in zip(arr, service):
+            last = max(a_, last) + sv
+            fin.append(last - a_)
         t0 = time.perf_counter()
         tk = []
-        for q, a in zip(reqs, arr):
-            while time.perf_counter() - t0 < a:
+        for q, a_ in zip(reqs, arr):
+            while time.perf_counter() - t0 < a_:
                 pass
-            tk.append(srv.submit(ids[q.map_id], q.xy, q.label, maps[q.map_id].grid,
-                                 maps[q.map_id].side, maps[q.map_id].side, R, R, 0.0, precision)[0])
+            tk.append(submit(q)[0])
         rs = [srv.wait(t) for t in tk]
-        srv.close()
         ls = [(r["t_done_ns"] - r["t_submit_ns"]) * 1e-6 for r in rs]
         lat[f"{mult}x"] = {"qps": qps,
                            "serving_ms": {"p50": percentile(ls, 50), "p99": percentile(ls, 99)},
                            "plain_ms": {"p50": percentile(fin, 50) * 1e3, "p99": percentile(fin, 99) * 1e3}}
+    stats = srv.stats()
+    srv.close()
     return {
         "workload": (f"{len(reqs)} updates of {len(maps)} maps: D in {{2048,4096,8192}}, 1-16 tiles, "
                      f"grid sides {min(m.side for m in maps)}-{max(m.side for m in maps)} at 0.05 m, "

@@ -244,6 +244,15 @@ int vsaogm_server_get_map(vsaogm_server* server, int32_t map_id, vsaogm_map** ou
 int vsaogm_submit(vsaogm_server* server, const vsaogm_request* req, uint64_t* ticket);
 
 /*
+ * Queue count requests in order, as count calls of vsaogm_submit would, with one lock
+ * acquisition.  Stops at the first request that fails; *n_queued receives how many were
+ * queued (tickets[0..*n_queued) are valid) and the return value is that request's status
+ * (VSAOGM_OK when all were queued).
+ */
+int vsaogm_submit_many(vsaogm_server* server, const vsaogm_request* reqs, int32_t count,
+                       uint64_t* tickets, int32_t* n_queued);
+
+/*
  * Non-blocking: VSAOGM_EAGAIN while the ticket runs; otherwise fills *result,
  * retires the ticket and returns VSAOGM_OK (the update's own status is in
  * result->status).  ENOTFOUND for an unknown or already retired ticket.

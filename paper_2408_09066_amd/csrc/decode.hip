@@ -120,6 +120,14 @@ __device__ inline float order_value(unsigned u) {
     return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
 }
 
+// Logical index of workgroup b of n when consecutive hardware indices land on different XCDs
+// (round-robin over kXcds): XCD x receives the logical range [x*n/kXcds, (x+1)*n/kXcds).
+constexpr int kXcds = 8;
+__device__ inline int xcd_local_index(int b, int n) {
+    if (n % kXcds != 0) return b;
+    return (b % kXcds) * (n / kXcds) + b / kXcds;
+}
+
 struct DecodeArgs {
     const DTile* tiles;
     int ntiles;
@@ -190,7 +198,11 @@ __global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeAr
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, i16 = lane & 15;
-    const long long it0 = (long long)blockIdx.x * a.steps_per_wg;
+    // Workgroups are dispatched round-robin over the XCDs; give each XCD a contiguous share of
+    // the iteration space, so that its resident workgroups work on neighbouring tiles (the
+    // same row group of a band) and share those rows' table lines in the XCD's L2.
+    const int wg = xcd_local_index(blockIdx.x, gridDim.x);
+    const long long it0 = (long long)wg * a.steps_per_wg;
     const long long it1 = min(it0 + a.steps_per_wg, a.total_steps);
     const int first_tile = (int)(it0 / a.ksteps);
 
@@ -397,7 +409,7 @@ __global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeAr
         // a tile split across workgroups: store this segment's partial sums (slot 0 if the
         // tile is the workgroup's first, else slot 1); k_decode_fix adds the segments
         const int slot = (ti == first_tile) ? 0 : 1;
-        float* part = a.partial + ((size_t)blockIdx.x * 2 + slot) * 2 * kTileRows * kTileCols;
+        float* part = a.partial + ((size_t)wg * 2 + slot) * 2 * kTileRows * kTileCols;
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll

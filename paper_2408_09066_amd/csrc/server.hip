@@ -1,8 +1,9 @@
 // Request server for map updates (vsaogm_server_* / vsaogm_submit / vsaogm_poll).
 //
-// One worker thread owns the device side.  Each execution slot is a HIP stream with its own
-// device and pinned host buffers; a request admitted to a slot runs its whole update there:
-// host-to-device copy of the points, encode into its map (Algorithm 1), decode of its grid
+// Worker threads (up to four) own the device side, each a share of the execution slots.  Each
+// slot is a HIP stream with its own device and pinned host buffers; a request admitted to a
+// slot runs its whole update there:
+// one host-to-device copy of the points (staged by submit in pooled pinned memory), encode into its map (Algorithm 1), decode of its grid
 // (eqs. vector-normalization, loc-query), classification (Algorithm 2, eqs. softmax, psd,
 // classification) and device-to-host copies of the outputs, closed by an event.  Slots run
 // concurrently, so updates of different maps overlap on the GPU; a map is bound to at most one
@@ -103,22 +104,71 @@ struct HostMem {
     }
 };
 
+// Pinned host blocks of power-of-two sizes, reused across requests (allocating pinned memory
+// per request would cost more than the request's copies).
+struct PinnedPool {
+    std::mutex mu;
+    std::vector<std::pair<size_t, void*>> free_blocks;
+    std::vector<void*> all;
+    std::pair<void*, size_t> get(size_t need) {
+        size_t cap = 1 << 16;
+        while (cap < need) cap *= 2;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (size_t i = 0; i < free_blocks.size(); ++i)
+                if (free_blocks[i].first == cap) {
+                    void* p = free_blocks[i].second;
+                    free_blocks[i] = free_blocks.back();
+                    free_blocks.pop_back();
+                    return {p, cap};
+                }
+        }
+        void* p = nullptr;
+        check_hip(hipHostMalloc(&p, cap, hipHostMallocDefault), "pinned request buffer");
+        std::lock_guard<std::mutex> lk(mu);
+        all.push_back(p);
+        return {p, cap};
+    }
+    void put(void* p, size_t cap) {
+        std::lock_guard<std::mutex> lk(mu);
+        free_blocks.emplace_back(cap, p);
+    }
+    ~PinnedPool() {
+        for (void* p : all) (void)hipHostFree(p);
+    }
+};
+
 struct Request {
     uint64_t ticket = 0;
     vsaogm_request r{};
-    std::vector<float> xy;
-    std::vector<uint8_t> label;
+    void* in = nullptr;       // pinned [n][2] float32 points, then [n] labels
+    size_t in_cap = 0;
     int64_t footprint = 0;
     vsaogm_result res{};
     bool done = false;
+};
+
+// Output block on the device and in pinned memory: maxima, labels, map, heatmaps, each
+// 256-byte aligned; one copy brings back the prefix holding what the request asked for.
+struct OutLayout {
+    size_t lab, ogm, heat, end_lab, end_ogm, end_heat;
+    explicit OutLayout(int64_t cells) {
+        auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+        lab = 256;
+        ogm = up(lab + cells);
+        heat = up(ogm + cells * 4);
+        end_lab = lab + cells;
+        end_ogm = ogm + cells * 4;
+        end_heat = heat + cells * 8;
+    }
 };
 
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     Request* req = nullptr;
-    DevMem d_xy, d_label, d_heat, d_hmax, d_ogm, d_lab;
-    HostMem h_xy, h_label, h_heat, h_hmax, h_ogm, h_lab;
+    DevMem d_in, d_out;
+    HostMem h_out;
 };
 
 // Bytes a request holds while it runs: its inputs and outputs on the device plus the map's
@@ -147,13 +197,16 @@ struct vsaogm_server {
     std::vector<Slot> slots;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
-    std::thread worker;
     bool stop = false;
     uint64_t next_ticket = 1;
     int64_t completed = 0;
     int inflight = 0;
 
-    void run();
+    int nworkers = 1;
+    std::vector<std::thread> workers;
+    PinnedPool pool;
+
+    void run(int w);
     void launch(Slot& s, int slot_index);
     void finish(Slot& s);
 };
@@ -166,42 +219,26 @@ void vsaogm_server::launch(Slot& s, int slot_index) {
     int rc = VSAOGM_OK;
     try {
         const int64_t n = r.n, cells = (int64_t)r.grid.nx * r.grid.ny;
-        s.d_xy.ensure(std::max<int64_t>(n, 1) * 8, s.stream, "slot points");
-        s.d_label.ensure(std::max<int64_t>(n, 1), s.stream, "slot labels");
-        s.d_heat.ensure(cells * 8, s.stream, "slot heatmaps");
-        s.d_hmax.ensure(8, s.stream, "slot maxima");
-        s.d_ogm.ensure(cells * 4, s.stream, "slot map");
-        s.d_lab.ensure(cells, s.stream, "slot labels");
-        s.h_xy.ensure(std::max<int64_t>(n, 1) * 8, "slot pinned points");
-        s.h_label.ensure(std::max<int64_t>(n, 1), "slot pinned labels");
-        s.h_hmax.ensure(8, "slot pinned maxima");
-        if (r.heat) s.h_heat.ensure(cells * 8, "slot pinned heatmaps");
-        if (r.ogm) s.h_ogm.ensure(cells * 4, "slot pinned map");
-        if (r.label_out) s.h_lab.ensure(cells, "slot pinned labels");
-        if (n > 0) {
-            std::memcpy(s.h_xy.p, q->xy.data(), n * 8);
-            std::memcpy(s.h_label.p, q->label.data(), n);
-            check_hip(hipMemcpyAsync(s.d_xy.p, s.h_xy.p, n * 8, hipMemcpyHostToDevice, s.stream), "copy points");
-            check_hip(hipMemcpyAsync(s.d_label.p, s.h_label.p, n, hipMemcpyHostToDevice, s.stream), "copy labels");
-        }
+        const OutLayout L(cells);
+        const size_t back = r.heat ? L.end_heat : (r.ogm ? L.end_ogm : (r.label_out ? L.end_lab : 8));
+        s.d_in.ensure(std::max<int64_t>(n, 1) * 9, s.stream, "slot inputs");
+        s.d_out.ensure(L.end_heat, s.stream, "slot outputs");
+        s.h_out.ensure(back, "slot pinned outputs");
+        unsigned char* din = static_cast<unsigned char*>(s.d_in.p);
+        unsigned char* dout = static_cast<unsigned char*>(s.d_out.p);
+        if (n > 0)
+            check_hip(hipMemcpyAsync(din, q->in, n * 9, hipMemcpyHostToDevice, s.stream), "copy inputs");
         vsaogm_map* m = maps[r.map_id];
         auto call = [&](int code) {
             if (code != VSAOGM_OK) throw Fail(code, vsaogm_last_error());
         };
-        call(vsaogm_encode(m, static_cast<float*>(s.d_xy.p), static_cast<uint8_t*>(s.d_label.p), n, s.stream));
-        call(vsaogm_decode(m, &r.grid, r.precision, static_cast<float*>(s.d_heat.p),
-                           static_cast<float*>(s.d_hmax.p), s.stream));
-        call(vsaogm_classify(&r.grid, static_cast<float*>(s.d_heat.p), static_cast<float*>(s.d_hmax.p), r.r_occ,
-                             r.r_emp, r.rho, static_cast<float*>(s.d_ogm.p), static_cast<uint8_t*>(s.d_lab.p),
-                             device, s.stream));
-        check_hip(hipMemcpyAsync(s.h_hmax.p, s.d_hmax.p, 8, hipMemcpyDeviceToHost, s.stream), "copy maxima");
-        if (r.heat)
-            check_hip(hipMemcpyAsync(s.h_heat.p, s.d_heat.p, cells * 8, hipMemcpyDeviceToHost, s.stream),
-                      "copy heatmaps");
-        if (r.ogm)
-            check_hip(hipMemcpyAsync(s.h_ogm.p, s.d_ogm.p, cells * 4, hipMemcpyDeviceToHost, s.stream), "copy map");
-        if (r.label_out)
-            check_hip(hipMemcpyAsync(s.h_lab.p, s.d_lab.p, cells, hipMemcpyDeviceToHost, s.stream), "copy labels");
+        float* hmax = reinterpret_cast<float*>(dout);
+        float* heat = reinterpret_cast<float*>(dout + L.heat);
+        call(vsaogm_encode(m, reinterpret_cast<float*>(din), din + n * 8, n, s.stream));
+        call(vsaogm_decode(m, &r.grid, r.precision, heat, hmax, s.stream));
+        call(vsaogm_classify(&r.grid, heat, hmax, r.r_occ, r.r_emp, r.rho,
+                             reinterpret_cast<float*>(dout + L.ogm), dout + L.lab, device, s.stream));
+        check_hip(hipMemcpyAsync(s.h_out.p, dout, back, hipMemcpyDeviceToHost, s.stream), "copy outputs");
     } catch (const Fail& e) {
         rc = e.code;
     } catch (const std::exception&) {
@@ -217,22 +254,27 @@ void vsaogm_server::finish(Slot& s) {
     const vsaogm_request& r = q->r;
     if (q->res.status == VSAOGM_OK) {
         const int64_t cells = (int64_t)r.grid.nx * r.grid.ny;
-        std::memcpy(q->res.hmax, s.h_hmax.p, 8);
-        if (r.heat) std::memcpy(r.heat, s.h_heat.p, cells * 8);
-        if (r.ogm) std::memcpy(r.ogm, s.h_ogm.p, cells * 4);
-        if (r.label_out) std::memcpy(r.label_out, s.h_lab.p, cells);
+        const OutLayout L(cells);
+        const unsigned char* h = static_cast<const unsigned char*>(s.h_out.p);
+        std::memcpy(q->res.hmax, h, 8);
+        if (r.label_out) std::memcpy(r.label_out, h + L.lab, cells);
+        if (r.ogm) std::memcpy(r.ogm, h + L.ogm, cells * 4);
+        if (r.heat) std::memcpy(r.heat, h + L.heat, cells * 8);
     }
+    if (q->in) pool.put(q->in, q->in_cap);
+    q->in = nullptr;
     q->res.t_done_ns = now_ns();
 }
 
-void vsaogm_server::run() {
+void vsaogm_server::run(int w) {
     (void)hipSetDevice(device);
     std::vector<int> free_slots;
-    for (int i = (int)slots.size() - 1; i >= 0; --i) free_slots.push_back(i);
+    for (int i = (int)slots.size() - 1; i >= 0; --i)
+        if (i % nworkers == w) free_slots.push_back(i);
     for (;;) {
         bool progressed = false;
-        // completions
-        for (int i = 0; i < (int)slots.size(); ++i) {
+        // completions of this worker's slots
+        for (int i = w; i < (int)slots.size(); i += nworkers) {
             Slot& s = slots[i];
             if (!s.req) continue;
             const hipError_t e = hipEventQuery(s.done);
@@ -248,6 +290,7 @@ void vsaogm_server::run() {
                 --inflight;
             }
             cv_done.notify_all();
+            cv_work.notify_all();  // a map or budget freed up for the other workers
             s.req = nullptr;
             free_slots.push_back(i);
             progressed = true;
@@ -279,9 +322,11 @@ void vsaogm_server::run() {
                 it = pending.erase(it);
             }
             if (to_launch.empty() && !progressed) {
-                // nothing to do right now: sleep until a submit or a short timeout (running
-                // slots are polled every 20 microseconds)
-                cv_work.wait_for(lk, std::chrono::microseconds(inflight > 0 ? 20 : 2000));
+                // nothing to do right now: sleep until a submit or a completion, or a short
+                // timeout while this worker's slots run (they are polled every 20 us)
+                bool mine = false;
+                for (int i = w; i < (int)slots.size(); i += nworkers) mine = mine || slots[i].req;
+                cv_work.wait_for(lk, std::chrono::microseconds(mine ? 20 : 2000));
                 continue;
             }
         }
@@ -317,7 +362,8 @@ int vsaogm_server_create(const vsaogm_server_desc* d, vsaogm_server** out) {
             check_hip(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming), "create event");
         }
         vsaogm_server* raw = s.get();
-        raw->worker = std::thread([raw] { raw->run(); });
+        raw->nworkers = std::min(d->max_inflight, 4);
+        for (int w = 0; w < raw->nworkers; ++w) raw->workers.emplace_back([raw, w] { raw->run(w); });
         *out = s.release();
     });
 }
@@ -330,7 +376,8 @@ int vsaogm_server_destroy(vsaogm_server* s) {
             s->stop = true;
         }
         s->cv_work.notify_all();
-        if (s->worker.joinable()) s->worker.join();
+        for (auto& t : s->workers)
+            if (t.joinable()) t.join();
         (void)hipSetDevice(s->device);
         for (auto& sl : s->slots) {
             if (sl.stream) (void)hipStreamSynchronize(sl.stream);
@@ -369,43 +416,110 @@ int vsaogm_server_get_map(vsaogm_server* s, int32_t map_id, vsaogm_map** out) {
     });
 }
 
+}  // extern "C"
+
+namespace {
+
+// Validate one request and stage its inputs in pinned memory (no server lock held).
+std::unique_ptr<Request> prepare(vsaogm_server* s, const vsaogm_request* r) {
+    if (!r) throw Fail(VSAOGM_EINVAL, "request must not be NULL");
+    if (r->n < 0) throw Fail(VSAOGM_EINVAL, "n must be >= 0");
+    if (r->n > 0 && (!r->xy || !r->label)) throw Fail(VSAOGM_EINVAL, "xy and label must not be NULL");
+    if (r->grid.nx < 1 || r->grid.ny < 1 || !(r->grid.res > 0)) throw Fail(VSAOGM_EINVAL, "invalid grid");
+    if (r->precision < VSAOGM_FP32 || r->precision > VSAOGM_BF16X3) throw Fail(VSAOGM_EINVAL, "unknown precision");
+    if (r->r_occ < 0 || r->r_emp < 0 || r->r_occ > 24 || r->r_emp > 24)
+        throw Fail(VSAOGM_EINVAL, "disk radii must be in 0..24");
+    auto q = std::make_unique<Request>();
+    q->r = *r;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (r->map_id < 0 || r->map_id >= (int32_t)s->maps.size()) throw Fail(VSAOGM_ENOTFOUND, "unknown map");
+        q->footprint = footprint_of(*r, s->map_dim[r->map_id]);
+    }
+    if (q->footprint > s->budget) throw Fail(VSAOGM_EINVAL, "request exceeds the memory budget");
+    if (r->n > 0) {
+        auto blk = s->pool.get((size_t)r->n * 9);
+        q->in = blk.first;
+        q->in_cap = blk.second;
+        std::memcpy(q->in, r->xy, (size_t)r->n * 8);
+        std::memcpy(static_cast<unsigned char*>(q->in) + r->n * 8, r->label, (size_t)r->n);
+    }
+    q->r.xy = nullptr;
+    q->r.label = nullptr;
+    q->res.status = VSAOGM_EAGAIN;
+    q->res.slot = -1;
+    return q;
+}
+
+// Queue a prepared request (server lock held); false when the queue is full.
+bool enqueue_locked(vsaogm_server* s, std::unique_ptr<Request>& q, uint64_t* ticket) {
+    if ((int)s->pending.size() >= s->max_queue) return false;
+    q->ticket = s->next_ticket++;
+    q->res.t_submit_ns = now_ns();
+    *ticket = q->ticket;
+    s->pending.push_back(q.get());
+    s->tickets.emplace(q->ticket, std::move(q));
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
 int vsaogm_submit(vsaogm_server* s, const vsaogm_request* r, uint64_t* ticket) {
     return guard([&] {
         if (!s || !r || !ticket) throw Fail(VSAOGM_EINVAL, "server, request and ticket must not be NULL");
-        if (r->n < 0) throw Fail(VSAOGM_EINVAL, "n must be >= 0");
-        if (r->n > 0 && (!r->xy || !r->label)) throw Fail(VSAOGM_EINVAL, "xy and label must not be NULL");
-        if (r->grid.nx < 1 || r->grid.ny < 1 || !(r->grid.res > 0)) throw Fail(VSAOGM_EINVAL, "invalid grid");
-        if (r->precision < VSAOGM_FP32 || r->precision > VSAOGM_BF16X3) throw Fail(VSAOGM_EINVAL, "unknown precision");
-        if (r->r_occ < 0 || r->r_emp < 0 || r->r_occ > 24 || r->r_emp > 24)
-            throw Fail(VSAOGM_EINVAL, "disk radii must be in 0..24");
-        auto q = std::make_unique<Request>();
-        q->r = *r;
+        auto q = prepare(s, r);
+        bool ok;
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            if (r->map_id < 0 || r->map_id >= (int32_t)s->maps.size()) throw Fail(VSAOGM_ENOTFOUND, "unknown map");
-            q->footprint = footprint_of(*r, s->map_dim[r->map_id]);
-            if (q->footprint > s->budget) throw Fail(VSAOGM_EINVAL, "request exceeds the memory budget");
-            if ((int)s->pending.size() >= s->max_queue) throw Fail(VSAOGM_EBUSY, "queue full");
+            ok = enqueue_locked(s, q, ticket);
         }
-        if (r->n > 0) {
-            q->xy.assign(r->xy, r->xy + 2 * r->n);
-            q->label.assign(r->label, r->label + r->n);
-        }
-        q->r.xy = nullptr;
-        q->r.label = nullptr;
-        q->res.status = VSAOGM_EAGAIN;
-        q->res.slot = -1;
-        q->res.t_submit_ns = now_ns();
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            if ((int)s->pending.size() >= s->max_queue) throw Fail(VSAOGM_EBUSY, "queue full");
-            q->ticket = s->next_ticket++;
-            *ticket = q->ticket;
-            s->pending.push_back(q.get());
-            s->tickets.emplace(q->ticket, std::move(q));
+        if (!ok) {
+            if (q->in) s->pool.put(q->in, q->in_cap);
+            throw Fail(VSAOGM_EBUSY, "queue full");
         }
         s->cv_work.notify_all();
     });
+}
+
+int vsaogm_submit_many(vsaogm_server* s, const vsaogm_request* reqs, int32_t count, uint64_t* tickets,
+                       int32_t* n_queued) {
+    int32_t queued = 0;
+    const int rc = guard([&] {
+        if (!s || (!reqs && count > 0) || (!tickets && count > 0))
+            throw Fail(VSAOGM_EINVAL, "server, requests and tickets must not be NULL");
+        std::vector<std::unique_ptr<Request>> qs;
+        qs.reserve(count > 0 ? count : 0);
+        int err = VSAOGM_OK;
+        std::string msg;
+        for (int32_t i = 0; i < count; ++i) {
+            try {
+                qs.push_back(prepare(s, reqs + i));
+            } catch (const Fail& e) {
+                err = e.code;
+                msg = e.what();
+                break;
+            }
+        }
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (auto& q : qs) {
+                if (!enqueue_locked(s, q, tickets + queued)) {
+                    err = VSAOGM_EBUSY;
+                    msg = "queue full";
+                    break;
+                }
+                ++queued;
+            }
+        }
+        for (auto& q : qs)
+            if (q && q->in) s->pool.put(q->in, q->in_cap);  // the ones not queued
+        if (queued) s->cv_work.notify_all();
+        if (err != VSAOGM_OK) throw Fail(err, msg);
+    });
+    if (n_queued) *n_queued = queued;
+    return rc;
 }
 
 static int poll_locked(vsaogm_server* s, uint64_t ticket, vsaogm_result* out) {

@@ -24,7 +24,7 @@ EXPORTED = [
     "vsaogm_decode", "vsaogm_classify", "vsaogm_memories", "vsaogm_fuse",
     "vsaogm_profile_events", "vsaogm_server_create", "vsaogm_server_destroy",
     "vsaogm_server_add_map", "vsaogm_server_get_map", "vsaogm_submit", "vsaogm_poll",
-    "vsaogm_wait", "vsaogm_server_drain", "vsaogm_server_stats",
+    "vsaogm_wait", "vsaogm_server_drain", "vsaogm_server_stats", "vsaogm_submit_many",
 ]
 
 
@@ -96,6 +96,8 @@ def load(path: str = LIB_PATH):
     L.vsaogm_server_get_map.argtypes = [P, i32, ctypes.POINTER(P)]
     L.vsaogm_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
     L.vsaogm_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
+    L.vsaogm_submit_many.argtypes = [P, ctypes.POINTER(Request), i32, ctypes.POINTER(ctypes.c_uint64),
+                                     ctypes.POINTER(i32)]
     L.vsaogm_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
     L.vsaogm_server_drain.argtypes = [P]
     L.vsaogm_server_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -306,6 +308,41 @@ class Server:
             break
         self._keep[t.value] = out
         return int(t.value), out
+
+    def submit_many(self, items, want=("label",)):
+        """Queue a list of requests with one call.  items: dicts with keys map_id, xy, label,
+        grid, nx, ny, r_occ, r_emp and optionally rho, precision.  Returns [(ticket, outputs)]."""
+        n = len(items)
+        arr = (Request * n)()
+        keep, outs = [], []
+        for i, it in enumerate(items):
+            xy = np.ascontiguousarray(it["xy"], dtype=np.float32).reshape(-1, 2)
+            lab = np.ascontiguousarray(it["label"], dtype=np.uint8).reshape(-1)
+            nx, ny = int(it["nx"]), int(it["ny"])
+            out = {}
+            if "label" in want:
+                out["label"] = np.empty((ny, nx), dtype=np.uint8)
+            if "ogm" in want:
+                out["ogm"] = np.empty((ny, nx), dtype=np.float32)
+            if "heat" in want:
+                out["heat"] = np.empty((2, ny, nx), dtype=np.float32)
+            keep.append((xy, lab))
+            outs.append(out)
+            arr[i] = Request(int(it["map_id"]), xy.ctypes.data, lab.ctypes.data, int(xy.shape[0]),
+                             grid_desc(it["grid"], nx, ny), PRECISIONS[it.get("precision", "fp32")],
+                             int(it["r_occ"]), int(it["r_emp"]), float(it.get("rho", 0.0)),
+                             out["ogm"].ctypes.data if "ogm" in out else None,
+                             out["label"].ctypes.data if "label" in out else None,
+                             out["heat"].ctypes.data if "heat" in out else None)
+        tk = (ctypes.c_uint64 * n)()
+        nq = ctypes.c_int32()
+        rc = load().vsaogm_submit_many(self._h, arr, n, tk, ctypes.byref(nq))
+        res = []
+        for i in range(nq.value):
+            self._keep[int(tk[i])] = outs[i]
+            res.append((int(tk[i]), outs[i]))
+        check(rc)
+        return res
 
     def poll(self, ticket: int):
         """None while running; else a dict with status, slot, times (ns) and maxima."""

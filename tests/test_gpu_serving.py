@@ -157,3 +157,27 @@ def test_server_errors(torch_cuda):
         srv.poll(t)                                                     # retired
     assert e.value.code == native.ENOTFOUND
     srv.close()
+
+
+def test_submit_many_matches_single_submits(torch_cuda, stream):
+    say("[gpu] submit_many")
+    from paper_2408_09066_amd import native
+    maps, reqs = stream
+    ref, _ = served(maps, reqs, "fp32")
+    srv = native.Server(max_inflight=4)
+    ids = [srv.add_map(m.theta, m.layout, m.tiles) for m in maps]
+    items = [{"map_id": ids[q.map_id], "xy": q.xy, "label": q.label, "grid": maps[q.map_id].grid,
+              "nx": maps[q.map_id].side, "ny": maps[q.map_id].side, "r_occ": 3, "r_emp": 3,
+              "precision": "fp32"} for q in reqs]
+    tk = srv.submit_many(items, want=("label", "ogm", "heat"))
+    assert len(tk) == len(reqs)
+    for i, (t, out) in enumerate(tk):
+        assert srv.wait(t)["status"] == 0
+        for k in ("heat", "ogm", "label"):
+            assert np.array_equal(out[k], ref[i][0][k])
+    # a bad request stops the batch; the ones before it are queued
+    bad = dict(items[0], map_id=99)
+    with pytest.raises(native.VsaogmError):
+        srv.submit_many([items[0], bad, items[1]])
+    srv.drain()
+    srv.close()
