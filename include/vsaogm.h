@@ -160,6 +160,26 @@ int vsaogm_classify(const vsaogm_grid_desc* grid, const float* heat, const float
                     int32_t r_occ, int32_t r_emp, float rho, float* ogm, uint8_t* label,
                     int32_t device, vsaogm_stream stream);
 
+/* Activation of the decoding ablation (Sec. IV-B, decoding methodology). */
+typedef enum {
+    VSAOGM_ACT_ENTROPY = 0,  /* local Shannon entropy over the disks (the decoding of Sec. III-B) */
+    VSAOGM_ACT_RELU = 1,     /* max(q, 0) per cell */
+    VSAOGM_ACT_TANH = 2,     /* tanh(q) per cell */
+    VSAOGM_ACT_SIGMOID = 3   /* 1 / (1 + exp(-q)) per cell */
+} vsaogm_activation;
+
+/*
+ * vsaogm_classify with the toggles of the decoding ablation of Sec. IV-B: the value fed to
+ * the softmax is act(nl(n(P))) with n(P) = P / max P if normalize (0 for a class whose
+ * maximum is <= 0), nl(q) = q^2 if square, and act from vsaogm_activation (the entropy term
+ * -q ln q is 0 for q <= 0; per-cell activations ignore the radii).  vsaogm_classify is this
+ * call with normalize = square = 1 and VSAOGM_ACT_ENTROPY.
+ */
+int vsaogm_classify_ex(const vsaogm_grid_desc* grid, const float* heat, const float* hmax,
+                       int32_t r_occ, int32_t r_emp, float rho, int32_t normalize, int32_t square,
+                       int32_t activation, float* ogm, uint8_t* label, int32_t device,
+                       vsaogm_stream stream);
+
 /*
  * Read the memories back in the paper's frame: out dev float32
  * [2R][D/2+1][2] (re, im), out[key][k] = sum over the key's points of

@@ -55,6 +55,7 @@ def lib():
         L.vo_postprocess.argtypes = [P, i32, i32, i32, i32, f64, P, P, P, P]
         L.vo_postprocess_cells.argtypes = [P, P, i64, i32, i32, P, f64, P, P, P]
         L.vo_fuse.argtypes = [i32, i64, i32, P, P, P, P]
+        L.vo_postprocess_ex.argtypes = [P, i32, i32, i32, i32, f64, i32, i32, i32, P, P, P, P]
         L.vo_num_threads.restype = i32
         _lib = L
     return _lib
@@ -160,6 +161,23 @@ def postprocess(P: np.ndarray, r_occ: int, r_emp: int, rho: float):
     lib().vo_postprocess(_p(P), nx, ny, int(r_occ), int(r_emp), float(rho), _p(m), _p(H),
                          _p(ogm), _p(lab))
     return m, H, ogm, lab
+
+
+ACTIVATIONS = {"entropy": 0, "relu": 1, "tanh": 2, "sigmoid": 3}
+
+
+def postprocess_ex(P: np.ndarray, r_occ: int, r_emp: int, rho: float, normalize: bool = True,
+                   square: bool = True, act: str = "entropy"):
+    """Decoding ablation (Sec. IV-B): (m[2], A[2][ny][nx] pre-softmax values, ogm, label)."""
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    _, ny, nx = P.shape
+    m = np.empty(2, dtype=np.float64)
+    A = np.empty((2, ny, nx), dtype=np.float64)
+    ogm = np.empty((ny, nx), dtype=np.float64)
+    lab = np.empty((ny, nx), dtype=np.uint8)
+    lib().vo_postprocess_ex(_p(P), nx, ny, int(r_occ), int(r_emp), float(rho), int(bool(normalize)),
+                            int(bool(square)), ACTIVATIONS[act], _p(m), _p(A), _p(ogm), _p(lab))
+    return m, A, ogm, lab
 
 
 def postprocess_cells(nb: np.ndarray, valid: np.ndarray, r_occ: int, r_emp: int,

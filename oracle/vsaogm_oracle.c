@@ -307,6 +307,68 @@ void vo_postprocess_cells(const double* nb, const uint8_t* valid, int64_t ncells
 }
 
 /*
+ * The decoding ablation of Sec. IV-B (decoding methodology): the intermediate value before the
+ * softmax is act(nl(n(P))) with toggles for the normalisation n(P) = P / max P (per class, over
+ * the whole map), the non-linearity nl(Q) = Q^2, and the activation act, one of
+ * 0 = local Shannon entropy over the disk of radius r_psi (Algorithm 2), 1 = ReLU, 2 = tanh,
+ * 3 = sigmoid, applied per cell.  The two classes' values then go through the softmax, the
+ * signed difference and the threshold as in the default decoding (normalise on, square on,
+ * entropy).  Readings: with normalisation off the raw P is used; a class whose maximum is
+ * <= 0 has n(P) = 0; the entropy term -Q ln Q is 0 for Q <= 0.
+ */
+static double ablation_value(double p, double m, int normalize, int square)
+{
+    double q = p;
+    if (normalize) q = (m > 0.0) ? p / m : 0.0;
+    if (square) q = q * q;
+    return q;
+}
+
+void vo_postprocess_ex(const double* P, int32_t nx, int32_t ny, int32_t r_occ, int32_t r_emp,
+                       double rho, int32_t normalize, int32_t square, int32_t act,
+                       double* m, double* A, double* ogm, uint8_t* label)
+{
+    int64_t nc = (int64_t)nx * ny;
+    for (int32_t psi = 0; psi < 2; ++psi) {
+        double mx = -INFINITY;
+        for (int64_t c = 0; c < nc; ++c)
+            if (P[psi * nc + c] > mx) mx = P[psi * nc + c];
+        m[psi] = mx;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        int64_t i = c % nx, j = c / nx;
+        double a[2];
+        for (int32_t psi = 0; psi < 2; ++psi) {
+            const double* Pp = P + psi * nc;
+            if (act == 0) {
+                int32_t r = psi ? r_occ : r_emp;
+                double h = 0.0;
+                for (int32_t dy = -r; dy <= r; ++dy)
+                    for (int32_t dx = -r; dx <= r; ++dx) {
+                        if ((int64_t)dx * dx + (int64_t)dy * dy > (int64_t)r * r) continue;
+                        int64_t ii = i + dx, jj = j + dy;
+                        if (ii < 0 || jj < 0 || ii >= nx || jj >= ny) continue;
+                        double q = ablation_value(Pp[jj * nx + ii], m[psi], normalize, square);
+                        if (q > 0.0) h += -q * log(q);
+                    }
+                a[psi] = h;
+            } else {
+                double q = ablation_value(Pp[c], m[psi], normalize, square);
+                if (act == 1) a[psi] = q > 0.0 ? q : 0.0;
+                else if (act == 2) a[psi] = tanh(q);
+                else a[psi] = 1.0 / (1.0 + exp(-q));
+            }
+        }
+        if (A) { A[c] = a[0]; A[nc + c] = a[1]; }
+        double e0 = exp(a[0]), e1 = exp(a[1]);
+        double o = e1 / (e0 + e1) - e0 / (e0 + e1);
+        if (ogm) ogm[c] = o;
+        if (label) label[c] = (o >= rho) ? 1 : 0;
+    }
+}
+
+/*
  * Algorithm 3 (multi-map fusion): agents that share axis vectors, classes and
  * tiling hold memories with the same indices; the global set starts empty and
  * each agent's memory j is added to global memory j (created as zero when

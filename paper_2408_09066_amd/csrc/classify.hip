@@ -5,7 +5,9 @@
 // block and a halo of R = max(r_occ, r_emp) cells are computed once into LDS (zero outside
 // the grid, which excludes those neighbours), then each cell sums its disk of integer
 // offsets dx^2 + dy^2 <= r^2 per class, and the softmax of the two entropies minus each other
-// is tanh((H1 - H0) / 2).  The heatmaps are read once and the map written once.
+// is tanh((H1 - H0) / 2).  The heatmaps are read once and the map written once.  The ablation
+// variants (normalisation / square off, per-cell ReLU, tanh or sigmoid in place of the
+// entropy) change only the per-cell value and use a radius of 0.
 #include "internal.h"
 
 namespace vsaogm {
@@ -13,9 +15,25 @@ namespace {
 
 constexpr int TX = 64, TY = 16;
 
+// Pre-softmax value of one cell of one class (decoding of Sec. III-B and its ablation of
+// Sec. IV-B): q = P (/ max P if normalising) (squared if squaring), then -q ln q (entropy, to be
+// summed over the disk; 0 for q <= 0) or the per-cell activation ReLU / tanh / sigmoid.
+__device__ inline float cell_value(float p, float m, int normalize, int square, int act) {
+    float q = p;
+    if (normalize) q = (m > 0.f) ? p / m : 0.f;
+    if (square) q = q * q;
+    switch (act) {
+        case 0: return (q > 0.f) ? -q * logf(q) : 0.f;
+        case 1: return fmaxf(q, 0.f);
+        case 2: return tanhf(q);
+        default: return 1.f / (1.f + expf(-q));
+    }
+}
+
 __global__ __launch_bounds__(256) void k_classify(const float* __restrict__ heat,
                                                   const float* __restrict__ hmax, int nx, int ny,
-                                                  int r_occ, int r_emp, float rho,
+                                                  int r_occ, int r_emp, float rho, int normalize,
+                                                  int square, int act,
                                                   float* __restrict__ ogm,
                                                   uint8_t* __restrict__ label) {
     extern __shared__ float sg[];
@@ -43,11 +61,8 @@ __global__ __launch_bounds__(256) void k_classify(const float* __restrict__ heat
         const int gx = bx - R + xx, gy = by - R + yy;
         const float m = p ? m1 : m0;
         float v = 0.f;
-        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && m > 0.f) {
-            const float r = heat[p * plane + (size_t)gy * nx + gx] / m;
-            const float q = r * r;
-            v = (q > 0.f) ? -q * logf(q) : 0.f;
-        }
+        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny)
+            v = cell_value(heat[p * plane + (size_t)gy * nx + gx], m, normalize, square, act);
         sg[idx] = v;
     }
     __syncthreads();
@@ -78,12 +93,14 @@ __global__ __launch_bounds__(256) void k_classify(const float* __restrict__ heat
 }  // namespace
 
 hipError_t launch_classify(const float* heat, const float* hmax, int nx, int ny, int r_occ,
-                           int r_emp, float rho, float* ogm, uint8_t* label, hipStream_t s) {
+                           int r_emp, float rho, int normalize, int square, int act, float* ogm,
+                           uint8_t* label, hipStream_t s) {
+    if (act != 0) r_occ = r_emp = 0;  // per-cell activations: the "disk" is the cell itself
     const int R = r_occ > r_emp ? r_occ : r_emp;
     const size_t lds = 2 * (size_t)(TX + 2 * R) * (TY + 2 * R) * sizeof(float);
     profile_begin(kStageClassify, s);
     hipLaunchKernelGGL(k_classify, dim3((nx + TX - 1) / TX, (ny + TY - 1) / TY), dim3(256), lds, s,
-                       heat, hmax, nx, ny, r_occ, r_emp, rho, ogm, label);
+                       heat, hmax, nx, ny, r_occ, r_emp, rho, normalize, square, act, ogm, label);
     profile_end(kStageClassify, s);
     return hipGetLastError();
 }

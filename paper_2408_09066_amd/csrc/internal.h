@@ -134,7 +134,9 @@ struct DecodeLaunch {
 hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s);
 
 // ---- classify (classify.hip) -------------------------------------------------------
+// act: 0 entropy (disk radii used), 1 ReLU, 2 tanh, 3 sigmoid (per cell)
 hipError_t launch_classify(const float* heat, const float* hmax, int nx, int ny, int r_occ,
-                           int r_emp, float rho, float* ogm, uint8_t* label, hipStream_t s);
+                           int r_emp, float rho, int normalize, int square, int act, float* ogm,
+                           uint8_t* label, hipStream_t s);
 
 }  // namespace vsaogm

@@ -577,23 +577,33 @@ int vsaogm_decode(vsaogm_map* m, const vsaogm_grid_desc* g, int32_t precision, f
     });
 }
 
-int vsaogm_classify(const vsaogm_grid_desc* g, const float* heat, const float* hmax, int32_t r_occ,
-                    int32_t r_emp, float rho, float* ogm, uint8_t* label, int32_t device,
-                    vsaogm_stream stream) {
+int vsaogm_classify_ex(const vsaogm_grid_desc* g, const float* heat, const float* hmax,
+                       int32_t r_occ, int32_t r_emp, float rho, int32_t normalize, int32_t square,
+                       int32_t activation, float* ogm, uint8_t* label, int32_t device,
+                       vsaogm_stream stream) {
     return guarded([&] {
         if (!g || g->nx < 1 || g->ny < 1) fail(VSAOGM_EINVAL, "grid nx and ny must be >= 1");
         if (!heat || !hmax || !label) fail(VSAOGM_EINVAL, "heat, hmax and label must not be NULL");
         if (r_occ < 0 || r_emp < 0 || r_occ > kMaxRadius || r_emp > kMaxRadius)
             fail(VSAOGM_EINVAL, "disk radii must be in 0..24");
         if (!std::isfinite(rho)) fail(VSAOGM_EINVAL, "rho must be finite");
+        if (activation < VSAOGM_ACT_ENTROPY || activation > VSAOGM_ACT_SIGMOID)
+            fail(VSAOGM_EINVAL, "unknown activation");
         int ndev = 0;
         hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
         if (device < 0 || device >= ndev) fail(VSAOGM_EINVAL, "no such device");
         DeviceGuard guard(device);
-        hip_check(launch_classify(heat, hmax, g->nx, g->ny, r_occ, r_emp, rho, ogm, label,
-                                  (hipStream_t)stream),
+        hip_check(launch_classify(heat, hmax, g->nx, g->ny, r_occ, r_emp, rho, normalize ? 1 : 0,
+                                  square ? 1 : 0, activation, ogm, label, (hipStream_t)stream),
                   "classify launch");
     });
+}
+
+int vsaogm_classify(const vsaogm_grid_desc* g, const float* heat, const float* hmax, int32_t r_occ,
+                    int32_t r_emp, float rho, float* ogm, uint8_t* label, int32_t device,
+                    vsaogm_stream stream) {
+    return vsaogm_classify_ex(g, heat, hmax, r_occ, r_emp, rho, 1, 1, VSAOGM_ACT_ENTROPY, ogm, label,
+                              device, stream);
 }
 
 int vsaogm_memories(const vsaogm_map* m, float* out, vsaogm_stream stream) {

@@ -25,7 +25,9 @@ EXPORTED = [
     "vsaogm_profile_events", "vsaogm_server_create", "vsaogm_server_destroy",
     "vsaogm_server_add_map", "vsaogm_server_get_map", "vsaogm_submit", "vsaogm_poll",
     "vsaogm_wait", "vsaogm_server_drain", "vsaogm_server_stats", "vsaogm_submit_many",
+    "vsaogm_classify_ex",
 ]
+ACTIVATIONS = {"entropy": 0, "relu": 1, "tanh": 2, "sigmoid": 3}
 
 
 class VsaogmError(RuntimeError):
@@ -88,6 +90,8 @@ def load(path: str = LIB_PATH):
     L.vsaogm_decode.argtypes = [P, ctypes.POINTER(GridDesc), i32, P, P, P]
     L.vsaogm_classify.argtypes = [ctypes.POINTER(GridDesc), P, P, i32, i32, f32, P, P, i32, P]
     L.vsaogm_memories.argtypes = [P, P, P]
+    L.vsaogm_classify_ex.argtypes = [ctypes.POINTER(GridDesc), P, P, i32, i32, f32, i32, i32, i32,
+                                     P, P, i32, P]
     L.vsaogm_fuse.argtypes = [P, P, P]
     L.vsaogm_profile_events.argtypes = [i32, P, P]
     L.vsaogm_server_create.argtypes = [ctypes.POINTER(ServerDesc), ctypes.POINTER(P)]
@@ -204,7 +208,8 @@ class Map:
 
 
 def classify(heat, hmax, r_occ: int, r_emp: int, rho: float = 0.0, ogm=None, label=None,
-             device: int = 0, stream=None):
+             device: int = 0, stream=None, normalize: bool = True, square: bool = True,
+             act: str = "entropy"):
     import torch
     _, ny, nx = heat.shape
     dev = heat.device
@@ -213,8 +218,15 @@ def classify(heat, hmax, r_occ: int, r_emp: int, rho: float = 0.0, ogm=None, lab
     if ogm is None:
         ogm = torch.empty((ny, nx), dtype=torch.float32, device=dev)
     g = GridDesc(0.0, 0.0, 1.0, int(nx), int(ny))
-    check(load().vsaogm_classify(ctypes.byref(g), _ptr(heat), _ptr(hmax), int(r_occ), int(r_emp),
-                                 float(rho), _ptr(ogm), _ptr(label), int(device), _stream(stream)))
+    if normalize and square and act == "entropy":
+        check(load().vsaogm_classify(ctypes.byref(g), _ptr(heat), _ptr(hmax), int(r_occ),
+                                     int(r_emp), float(rho), _ptr(ogm), _ptr(label), int(device),
+                                     _stream(stream)))
+    else:
+        check(load().vsaogm_classify_ex(ctypes.byref(g), _ptr(heat), _ptr(hmax), int(r_occ),
+                                        int(r_emp), float(rho), int(bool(normalize)),
+                                        int(bool(square)), ACTIVATIONS[act], _ptr(ogm), _ptr(label),
+                                        int(device), _stream(stream)))
     return ogm, label
 
 

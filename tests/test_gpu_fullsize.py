@@ -1,0 +1,97 @@
+"""Full-size parity (the benchmark's workload and launch configuration) on sampled outputs.
+
+The oracle cannot decode 640 000 cells at D = 8192 in seconds, so it evaluates:
+  * the similarity at 1 500 seeded random cells and at the GPU's 64 highest cells per class
+    (the latter only choose where to look; every expected value is the oracle's own);
+  * the class maxima as the oracle's maximum over those cells, which contain the true argmax
+    whenever the GPU heatmap is within its bar;
+  * entropy, softmax and threshold at 150 seeded cells from their disk neighbourhoods.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_09066_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2408_09066_amd import native
+    native.load()
+    return torch
+
+
+@pytest.mark.parametrize("name,precision", [("world40", "fp32"), ("world40_d1", "bf16x3")])
+def test_fullsize_sampled(torch_cuda, name, precision):
+    say(f"[gpu] full-size sampled parity {name} {precision}")
+    from paper_2408_09066_amd import native
+    torch = torch_cuda
+    w = synth.workload(name)
+    m = native.Map(w.theta, w.layout, w.tiles)
+    m.reset()
+    m.encode(torch.from_numpy(w.xy).cuda(), torch.from_numpy(w.label).cuda())
+    heat, hmax = m.decode(w.grid, w.nx, w.ny, precision)
+    ogm, lab = native.classify(heat, hmax, w.r_occ, w.r_emp, w.rho)
+    torch.cuda.synchronize()
+    heat = heat.cpu().numpy().astype(np.float64)
+    hmax = hmax.cpu().numpy().astype(np.float64)
+    ogm = ogm.cpu().numpy().astype(np.float64)
+    lab = lab.cpu().numpy()
+    m.close()
+
+    omega, bad = oracle.encode(w.theta, w.layout, w.tiles, w.xy, w.label)
+    assert bad == 0
+    rng = np.random.default_rng(np.random.SeedSequence([2408, 7, len(name)]))
+    ncell = w.nx * w.ny
+    cells = rng.choice(ncell, size=1500, replace=False)
+    P = oracle.similarity_cells(w.theta, w.layout, w.tiles, omega, w.grid, w.nx, cells)
+    for p in range(2):
+        g = heat[p].reshape(-1)[cells]
+        e = np.linalg.norm(g - P[p]) / np.linalg.norm(P[p])
+        say(f"  heat[{p}] sampled rel-L2 {e:.3e} max-abs {np.max(np.abs(g - P[p])):.3e}")
+        assert e <= 1e-4
+    # class maxima
+    top = np.unique(np.concatenate([np.argsort(heat[p].reshape(-1))[-64:] for p in range(2)]))
+    Ptop = oracle.similarity_cells(w.theta, w.layout, w.tiles, omega, w.grid, w.nx, top)
+    m_ref = Ptop.max(axis=1)
+    for p in range(2):
+        say(f"  max[{p}] {hmax[p]:.7f} vs oracle {m_ref[p]:.7f}")
+        assert abs(hmax[p] - m_ref[p]) <= 1e-4 * abs(m_ref[p])
+        assert hmax[p] == heat[p].max()
+        assert np.all(P[p] <= m_ref[p] + 1e-4 * abs(m_ref[p]))
+    # entropy / softmax / threshold at sampled cells from their neighbourhoods
+    R = max(w.r_occ, w.r_emp)
+    wd = 2 * R + 1
+    sc = rng.choice(ncell, size=150, replace=False)
+    nb_idx, valid = [], np.zeros((len(sc), wd, wd), np.uint8)
+    for q, c in enumerate(sc):
+        i, j = c % w.nx, c // w.nx
+        for dy in range(-R, R + 1):
+            for dx in range(-R, R + 1):
+                ii, jj = i + dx, j + dy
+                ok = 0 <= ii < w.nx and 0 <= jj < w.ny
+                valid[q, dy + R, dx + R] = ok
+                nb_idx.append(jj * w.nx + ii if ok else 0)
+    nb_idx = np.array(nb_idx)
+    uniq, inv = np.unique(nb_idx, return_inverse=True)
+    Pn = oracle.similarity_cells(w.theta, w.layout, w.tiles, omega, w.grid, w.nx, uniq)
+    nb = Pn[:, inv].reshape(2, len(sc), wd, wd).transpose(1, 0, 2, 3)
+    H, ogm_ref, lab_ref = oracle.postprocess_cells(nb, valid, w.r_occ, w.r_emp, m_ref, w.rho)
+    g_ogm = ogm.reshape(-1)[sc]
+    g_lab = lab.reshape(-1)[sc]
+    say(f"  ogm sampled max-abs {np.max(np.abs(g_ogm - ogm_ref)):.3e}")
+    assert np.max(np.abs(g_ogm - ogm_ref)) < 1e-3
+    flips = g_lab != lab_ref
+    assert not flips.any() or np.max(np.abs(ogm_ref[flips] - w.rho)) < 1e-3

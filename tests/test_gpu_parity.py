@@ -258,3 +258,27 @@ def test_wide_phase_path(torch_cuda):
         e = rel_l2(g["heat"][psi], P[psi])
         say(f"  heat[{psi}] rel-L2 {e:.3e}")
         assert e <= HEAT_TOL
+
+
+@pytest.mark.parametrize("act", ["entropy", "relu", "tanh", "sigmoid"])
+@pytest.mark.parametrize("normalize,square", [(True, True), (True, False), (False, True), (False, False)])
+def test_decoding_ablation_variants(torch_cuda, act, normalize, square):
+    """The toggles of the decoding ablation (Sec. IV-B) on the oracle's similarity maps."""
+    say(f"[gpu] ablation {act} normalize={normalize} square={square}")
+    from paper_2408_09066_amd import native
+    torch = torch_cuda
+    w, (om, P, m, H, ogm, lab) = oracle_result("mini4x4")
+    P32 = P.astype(np.float32)
+    r_occ, r_emp = 3, 2
+    m_ref, A_ref, ogm_ref, lab_ref = oracle.postprocess_ex(P32.astype(np.float64), r_occ, r_emp, 0.0,
+                                                           normalize, square, act)
+    heat = torch.from_numpy(P32).cuda()
+    hmax = torch.from_numpy(m_ref.astype(np.float32)).cuda()
+    ogm_g, lab_g = native.classify(heat, hmax, r_occ, r_emp, 0.0, normalize=normalize,
+                                   square=square, act=act)
+    torch.cuda.synchronize()
+    ogm_g = ogm_g.cpu().numpy().astype(np.float64)
+    lab_g = lab_g.cpu().numpy()
+    assert np.max(np.abs(ogm_g - ogm_ref)) < 1e-4
+    bad = lab_g != lab_ref
+    assert not bad.any() or np.max(np.abs(ogm_ref[bad])) < 1e-5

@@ -354,3 +354,53 @@ def test_generator_is_deterministic_and_symmetric():
     assert np.all(th[0] == 0) and np.all(th[D // 2] == 0)
     assert np.array_equal(th[D - np.arange(1, D // 2)], -th[np.arange(1, D // 2)])
     assert np.max(np.abs(th)) <= math.pi / a.ell
+
+
+# ---------------------------------------------------------------- decoding ablation (Sec. IV-B)
+
+def test_ablation_default_is_the_decoding():
+    """Normalise + square + entropy is the decoding of Sec. III-B."""
+    rng = np.random.default_rng(21)
+    P = rng.normal(0.05, 0.2, size=(2, 14, 19))
+    m, H, ogm, lab = oracle.postprocess(P, 3, 2, 0.1)
+    m2, A, ogm2, lab2 = oracle.postprocess_ex(P, 3, 2, 0.1, True, True, "entropy")
+    assert np.array_equal(m, m2) and np.max(np.abs(A - H)) < 1e-14
+    assert np.max(np.abs(ogm - ogm2)) < 1e-14 and np.array_equal(lab, lab2)
+
+
+def test_ablation_activation_special_values():
+    """Per-cell activations at hand-computed points: Q = 1 at the class maximum, Q = 0 where
+    the class is 0, Q = 1/4 where P is half the maximum (normalise, square)."""
+    P = np.zeros((2, 1, 3))
+    P[1, 0, 0] = 2.0            # class 1 max: Q1 = 1 at cell 0
+    P[1, 0, 1] = 1.0            # Q1 = 1/4 at cell 1
+    P[0, 0, 2] = 5.0            # class 0 max at cell 2: Q0 = 1
+    expect = {
+        # cell 0: (Q0, Q1) = (0, 1); cell 1: (0, 1/4); cell 2: (1, 0)
+        "relu": [math.tanh(0.5), math.tanh(0.125), -math.tanh(0.5)],
+        "tanh": [math.tanh(0.7615941559557649 / 2), math.tanh(0.24491866240370913 / 2),
+                 -math.tanh(0.7615941559557649 / 2)],
+        "sigmoid": [math.tanh((0.7310585786300049 - 0.5) / 2), math.tanh((0.5621765008857981 - 0.5) / 2),
+                    math.tanh((0.5 - 0.7310585786300049) / 2)],
+    }
+    for act, vals in expect.items():
+        _, _, ogm, lab = oracle.postprocess_ex(P, 1, 1, 0.0, True, True, act)
+        assert np.max(np.abs(ogm[0] - np.array(vals))) < 1e-12, act
+        assert list(lab[0]) == [1, 1, 0]
+
+
+def test_ablation_toggles():
+    """Without normalisation the raw similarity is used; without squaring negative values
+    survive (ReLU clips them, tanh keeps the sign); an entropy term of Q <= 0 is 0."""
+    P = np.array([[[-0.5, 0.2]], [[0.4, -0.3]]])   # class 0 row, class 1 row
+    _, A, _, _ = oracle.postprocess_ex(P, 0, 0, 0.0, False, False, "relu")
+    assert np.allclose(A[:, 0, :], [[0.0, 0.2], [0.4, 0.0]])
+    _, A, _, _ = oracle.postprocess_ex(P, 0, 0, 0.0, False, False, "tanh")
+    assert np.allclose(A[:, 0, :], np.tanh(P[:, 0, :]))
+    _, A, _, _ = oracle.postprocess_ex(P, 0, 0, 0.0, True, False, "relu")
+    assert np.allclose(A[:, 0, :], [[0.0, 1.0], [1.0, 0.0]])   # P / max, clipped
+    _, A, _, _ = oracle.postprocess_ex(P, 0, 0, 0.0, False, True, "entropy")
+    q = P[:, 0, :] ** 2
+    assert np.allclose(A[:, 0, :], -q * np.log(q))            # r = 0: the cell itself
+    _, A, _, _ = oracle.postprocess_ex(P, 0, 0, 0.0, False, False, "entropy")
+    assert A[0, 0, 0] == 0.0 and A[1, 0, 1] == 0.0            # negative Q contributes 0
