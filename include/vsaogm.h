@@ -145,6 +145,18 @@ int vsaogm_decode(vsaogm_map* map, const vsaogm_grid_desc* grid, int32_t precisi
                   float* heat, float* hmax, vsaogm_stream stream);
 
 /*
+ * Localized decoding (Sec. III-A: each tile's cells read only that tile's memories): like
+ * vsaogm_decode, but only the cells of tiles whose memories changed since the last
+ * incremental decode of this grid, into this same heat buffer at this same precision, are
+ * recomputed; the other cells keep their values (heat must be that buffer, unchanged
+ * since).  The first call for a grid, or a call with another heat buffer or precision,
+ * decodes every cell.  hmax is the maximum over all cells (the map keeps per-tile maxima).
+ * Synchronises the stream once, to read which memories changed.  Errors as vsaogm_decode.
+ */
+int vsaogm_decode_incremental(vsaogm_map* map, const vsaogm_grid_desc* grid, int32_t precision,
+                              float* heat, float* hmax, vsaogm_stream stream);
+
+/*
  * Post-processing of Sec. III-B on the device:
  *   Q = (heat / hmax)^2 per class (Q = 0 for a class whose hmax <= 0),
  *   H_psi(c) = sum of -Q ln Q over grid cells within Euclidean distance r_psi

@@ -177,7 +177,7 @@ __device__ inline void store_tile(const DecodeArgs& a, const DTile& t, int wave,
             }
         }
         for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
-        if (lane == 0 && mx > -INFINITY) atomicMax(a.hmax_u + p, order_key(mx));
+        if (lane == 0 && mx > -INFINITY && a.hmax_u) atomicMax(a.hmax_u + p, order_key(mx));
     }
 }
 
@@ -467,10 +467,54 @@ __global__ __launch_bounds__(256) void k_decode_fix(DecodeArgs a) {
         if ((threadIdx.x & 63) == 0) sh[q][threadIdx.x >> 6] = m;
     }
     __syncthreads();
-    if (threadIdx.x < 2) {
+    if (threadIdx.x < 2 && a.hmax_u) {
         const float m = fmaxf(fmaxf(sh[threadIdx.x][0], sh[threadIdx.x][1]), fmaxf(sh[threadIdx.x][2], sh[threadIdx.x][3]));
         if (m > -INFINITY) atomicMax(a.hmax_u + threadIdx.x, order_key(m));
     }
+}
+
+// One block per listed region: maxima of both classes over the region's cells.
+__global__ __launch_bounds__(256) void k_region_max(const float* __restrict__ heat, int nx, int ny,
+                                                    const RegionBox* __restrict__ boxes,
+                                                    float* __restrict__ region_max) {
+    const RegionBox b = boxes[blockIdx.x];
+    const int w = b.col1 - b.col0, h = b.row1 - b.row0;
+    float mx[2] = {-INFINITY, -INFINITY};
+    for (int e = threadIdx.x; e < w * h; e += 256) {
+        const int r = b.row0 + e / w, c = b.col0 + e % w;
+#pragma unroll
+        for (int p = 0; p < 2; ++p) mx[p] = fmaxf(mx[p], heat[(size_t)p * nx * ny + (size_t)r * nx + c]);
+    }
+    __shared__ float sh[2][4];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        float m = mx[p];
+        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+        if ((threadIdx.x & 63) == 0) sh[p][threadIdx.x >> 6] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2)
+        region_max[2 * b.beta + threadIdx.x] =
+            fmaxf(fmaxf(sh[threadIdx.x][0], sh[threadIdx.x][1]), fmaxf(sh[threadIdx.x][2], sh[threadIdx.x][3]));
+}
+
+__global__ __launch_bounds__(256) void k_region_final(const float* __restrict__ region_max, int nregions,
+                                                      float* __restrict__ hmax) {
+    float mx[2] = {-INFINITY, -INFINITY};
+    for (int i = threadIdx.x; i < nregions; i += 256) {
+        mx[0] = fmaxf(mx[0], region_max[2 * i]);
+        mx[1] = fmaxf(mx[1], region_max[2 * i + 1]);
+    }
+    __shared__ float sh[2][4];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        float m = mx[p];
+        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+        if ((threadIdx.x & 63) == 0) sh[p][threadIdx.x >> 6] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2)
+        hmax[threadIdx.x] = fmaxf(fmaxf(sh[threadIdx.x][0], sh[threadIdx.x][1]), fmaxf(sh[threadIdx.x][2], sh[threadIdx.x][3]));
 }
 
 __global__ void k_hmax_final(const unsigned* __restrict__ hmax_u, float* __restrict__ hmax) {
@@ -510,6 +554,14 @@ DecodePlan decode_plan(int precision, int ntiles, int halfp, int num_cus) {
 
 size_t decode_partial_floats(int grid) { return (size_t)grid * 2 * 2 * kTileRows * kTileCols; }
 
+hipError_t launch_region_max(const float* heat, int nx, int ny, const RegionBox* boxes, int nboxes,
+                             float* region_max, int nregions, float* hmax, hipStream_t s) {
+    if (nboxes > 0)
+        hipLaunchKernelGGL(k_region_max, dim3(nboxes), dim3(256), 0, s, heat, nx, ny, boxes, region_max);
+    hipLaunchKernelGGL(k_region_final, dim3(1), dim3(256), 0, s, region_max, nregions, hmax);
+    return hipGetLastError();
+}
+
 hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
     DecodeArgs a;
     a.tiles = d.tiles;
@@ -542,7 +594,7 @@ hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
     if (d.plan.steps_per_wg % d.plan.ksteps != 0 || d.plan.steps_per_wg < d.plan.ksteps)
         hipLaunchKernelGGL(k_decode_fix, dim3((unsigned)d.ntiles * kFixParts), dim3(256), 0, s, a);
     profile_end(kStageDecode, s);
-    hipLaunchKernelGGL(k_hmax_final, dim3(1), dim3(64), 0, s, d.hmax_u, d.hmax);
+    if (d.hmax_u) hipLaunchKernelGGL(k_hmax_final, dim3(1), dim3(64), 0, s, d.hmax_u, d.hmax);
     return hipGetLastError();
 }
 

@@ -110,7 +110,8 @@ __device__ int block_scan_excl(int v, int* sh_w, int* total) {
 __global__ __launch_bounds__(kScanThreads) void k_scan(int* __restrict__ hist, int nchunks,
                                                        int nkeys, int echunk,
                                                        EChunk* __restrict__ table,
-                                                       int* __restrict__ meta) {
+                                                       int* __restrict__ meta,
+                                                       unsigned* __restrict__ version) {
     __shared__ int sh_w[kScanThreads / 64];
     extern __shared__ int key_start[];   // [nkeys]
     const int64_t N = (int64_t)nkeys * nchunks;
@@ -156,6 +157,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int* __restrict__ hist, i
             meta[1 + k] = e0;
             meta[1 + nkeys + k] = ne;
             meta[1 + 2 * nkeys + k] = cnt;
+            if (cnt > 0) version[k] += 1u;  // the memory changes: decodes of it are stale
             for (int j = 0; j < ne; ++j) {
                 EChunk e;
                 e.key = k;
@@ -415,6 +417,11 @@ __global__ __launch_bounds__(256) void k_export(const float2* __restrict__ omega
     o[1] = (float)(s * re + c * im);
 }
 
+__global__ __launch_bounds__(256) void k_bump(unsigned* __restrict__ version, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) version[i] += 1u;
+}
+
 __global__ __launch_bounds__(256) void k_add(float2* __restrict__ dst,
                                              const float2* __restrict__ src, size_t n) {
     size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -456,7 +463,7 @@ hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const
     hipLaunchKernelGGL(k_assign, dim3(p.nchunks), dim3(kAssignChunk), nkeys * sizeof(int), s, xy2,
                        label, n, L, nkeys, p.nchunks, w.key, w.hist, w.n_bad);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), nkeys * sizeof(int), s, w.hist, p.nchunks, nkeys,
-                       p.echunk, w.table, w.meta);
+                       p.echunk, w.table, w.meta, w.version);
     hipLaunchKernelGGL(k_scatter, dim3(p.nchunks), dim3(64), nkeys * sizeof(int), s, xy2, w.key,
                        n, L, nkeys, p.nchunks, bits_for(nkeys), w.hist, w.sorted, w.sorted_lo);
     const double2* rev_d = reinterpret_cast<const double2*>(theta_rev_d);
@@ -501,6 +508,11 @@ hipError_t launch_memories_export(const float2* omega, const double* theta_rad, 
                                   int nkeys, int half, int halfp, float* out, hipStream_t s) {
     hipLaunchKernelGGL(k_export, dim3((half + 1 + 255) / 256, nkeys), dim3(256), 0, s, omega,
                        theta_rad, L, half, halfp, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_bump_versions(unsigned* version, int nkeys, hipStream_t s) {
+    hipLaunchKernelGGL(k_bump, dim3((nkeys + 255) / 256), dim3(256), 0, s, version, nkeys);
     return hipGetLastError();
 }
 

@@ -68,6 +68,7 @@ struct EncodeWork {
     int* meta;           // [1 + 3 * nkeys]: n_echunks, key_ec_start[nkeys], key_ec_count[nkeys], key_count[nkeys]
     float2* partial;     // [cap_echunks][halfp]
     unsigned long long* n_bad;
+    unsigned* version;   // [nkeys] bumped for every memory that receives points
 };
 
 // Launch geometry of one encode, shared by the host (buffer sizing) and the launcher.
@@ -94,6 +95,7 @@ hipError_t launch_memories_export(const float2* omega, const double* theta_rad, 
                                   int nkeys, int half, int halfp, float* out, hipStream_t s);
 
 hipError_t launch_add(float2* dst, const float2* src, size_t n, hipStream_t s);
+hipError_t launch_bump_versions(unsigned* version, int nkeys, hipStream_t s);
 
 // ---- decode (decode.hip) -----------------------------------------------------------
 // Location tables: tab[c][k] = exp(i * Theta_axis[k] * local[c]) for k < half, 0 for
@@ -131,7 +133,17 @@ struct DecodeLaunch {
     DecodePlan plan;
 };
 // Similarity GEMM over the tile list (precision: 0 fp32, 1 bf16, 2 fp16, 3 bf16 hi+lo).
+// With hmax_u == nullptr no class maxima are folded and hmax is not written.
 hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s);
+
+// Per-region class maxima of a heatmap: region_max[beta][psi] = max over the region's cells
+// (rows [row0, row1) x cols [col0, col1) of each listed region; -inf if it has none), then
+// hmax[psi] = max over all nregions regions.
+struct RegionBox {
+    int beta, row0, row1, col0, col1, pad[3];
+};
+hipError_t launch_region_max(const float* heat, int nx, int ny, const RegionBox* boxes, int nboxes,
+                             float* region_max, int nregions, float* hmax, hipStream_t s);
 
 // ---- classify (classify.hip) -------------------------------------------------------
 // act: 0 entropy (disk radii used), 1 ReLU, 2 tanh, 3 sigmoid (per cell)

@@ -134,6 +134,19 @@ struct GridCache {
     DevBuf<int> col_tx;              // [nx] tile column of every grid column
     DevBuf<float2> ex32, ey32;       // fp32 tables [n][halfp]
     DevBuf<uint16_t> ey_bf, ey_bf_lo, ey_h;  // 16-bit y tables [ny][2*halfp], built on first use
+    // incremental decoding state
+    std::vector<DTile> host_tiles;
+    std::vector<int> tcol;                   // tile column of every grid column
+    std::vector<RegionBox> boxes;            // [tiles] cell range of every tile (row0 == row1: none)
+    std::vector<unsigned> seen;              // memory versions at the last incremental decode
+    const float* inc_heat = nullptr;         // heat buffer of that decode
+    int inc_precision = -1;                  // and its operand precision
+    bool inc_valid = false;
+    DevBuf<float> region_max;                // [tiles][2]
+    DevBuf<DTile> inc_tiles;
+    DevBuf<RegionBox> inc_boxes;
+    std::vector<DTile> inc_tiles_host;
+    std::vector<RegionBox> inc_boxes_host;
 };
 
 struct ProfileSlot {
@@ -173,6 +186,8 @@ struct vsaogm_map {
     int num_cus = 0;
     DevBuf<unsigned> d_hmax_u;          // [3] ordered class maxima, finished-block counter
     DevBuf<unsigned long long> d_bad;   // [1]
+    DevBuf<unsigned> d_version;         // [nkeys] change counters of the memories
+    unsigned* h_version = nullptr;      // pinned read-back of d_version
 
     // encode workspace
     int64_t cap_n = 0;
@@ -323,6 +338,21 @@ GridCache* grid_cache(vsaogm_map* m, const vsaogm_grid_desc* g, hipStream_t s) {
         }
     }
     gc->ntiles = (int)tl.size();
+    gc->host_tiles = tl;
+    gc->tcol = tcol;
+    gc->boxes.resize((size_t)m->tiles_x * m->tiles_y);
+    for (int ty = 0; ty < m->tiles_y; ++ty)
+        for (int tx = 0; tx < m->tiles_x; ++tx) {
+            RegionBox b{};
+            b.beta = ty * m->tiles_x + tx;
+            b.row0 = (int)(std::lower_bound(trow.begin(), trow.end(), ty) - trow.begin());
+            b.row1 = (int)(std::upper_bound(trow.begin(), trow.end(), ty) - trow.begin());
+            b.col0 = (int)(std::lower_bound(tcol.begin(), tcol.end(), tx) - tcol.begin());
+            b.col1 = (int)(std::upper_bound(tcol.begin(), tcol.end(), tx) - tcol.begin());
+            if (b.row0 >= b.row1 || b.col0 >= b.col1) b.row0 = b.row1 = b.col0 = b.col1 = 0;
+            gc->boxes[b.beta] = b;
+        }
+    gc->seen.assign(m->nkeys, 0u);
     gc->tiles.alloc(tl.size(), "decode tile list");
     gc->col_tx.alloc(g->nx, "column tiles");
     gc->local_x.alloc(g->nx, "local x");
@@ -460,6 +490,9 @@ int vsaogm_map_create(const vsaogm_map_desc* d, vsaogm_map** out) {
         m->d_omega_s.alloc((size_t)m->nkeys * m->halfp, "scaled memories");
         m->d_hmax_u.alloc(3, "class maxima");
         m->d_bad.alloc(1, "rejected-label counter");
+        m->d_version.alloc(m->nkeys, "memory versions");
+        hip_check(hipHostMalloc((void**)&m->h_version, sizeof(unsigned) * m->nkeys, hipHostMallocDefault),
+                  "pinned versions");
         hip_check(hipMemcpy(m->d_cx.p, m->cx.data(), m->cx.size() * 8, hipMemcpyHostToDevice), "copy");
         hip_check(hipMemcpy(m->d_cy.p, m->cy.data(), m->cy.size() * 8, hipMemcpyHostToDevice), "copy");
         hip_check(hipMemcpy(m->d_rev.p, rev.data(), rev.size() * sizeof(float2), hipMemcpyHostToDevice),
@@ -468,6 +501,7 @@ int vsaogm_map_create(const vsaogm_map_desc* d, vsaogm_map** out) {
         hip_check(hipMemcpy(m->d_theta.p, th, 2 * (size_t)half * 8, hipMemcpyHostToDevice), "copy");
         zero_async(m->d_omega.p, m->d_omega.n * sizeof(float2), nullptr);
         zero_async(m->d_bad.p, sizeof(unsigned long long), nullptr);
+        zero_async(m->d_version.p, sizeof(unsigned) * m->nkeys, nullptr);
         hip_check(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
         *out = m.release();
     });
@@ -478,6 +512,7 @@ int vsaogm_map_destroy(vsaogm_map* m) {
     return guarded([&] {
         DeviceGuard guard(m->device);
         (void)hipDeviceSynchronize();
+        if (m->h_version) (void)hipHostFree(m->h_version);
         delete m;
     });
 }
@@ -495,6 +530,7 @@ int vsaogm_map_reset(vsaogm_map* m, vsaogm_stream stream) {
         if (!m) fail(VSAOGM_EINVAL, "map is NULL");
         DeviceGuard guard(m->device);
         zero_async(m->d_omega.p, m->d_omega.n * sizeof(float2), (hipStream_t)stream);
+        hip_check(launch_bump_versions(m->d_version.p, m->nkeys, (hipStream_t)stream), "versions");
     });
 }
 
@@ -519,6 +555,7 @@ int vsaogm_encode(vsaogm_map* m, const float* xy, const uint8_t* label, int64_t 
         w.meta = m->w_meta.p;
         w.partial = m->w_partial.p;
         w.n_bad = m->d_bad.p;
+        w.version = m->d_version.p;
         hip_check(launch_encode(xy, label, n, m->layout(), m->nkeys, m->d_rev.p, m->d_rev_d.p,
                                 m->max_rev_x, m->max_rev_y, m->half, m->halfp, w, m->d_omega.p, s),
                   "encode launch");
@@ -577,6 +614,89 @@ int vsaogm_decode(vsaogm_map* m, const vsaogm_grid_desc* g, int32_t precision, f
     });
 }
 
+int vsaogm_decode_incremental(vsaogm_map* m, const vsaogm_grid_desc* g, int32_t precision, float* heat,
+                              float* hmax, vsaogm_stream stream) {
+    return guarded([&] {
+        if (!m) fail(VSAOGM_EINVAL, "map is NULL");
+        check_grid(g);
+        if (!heat || !hmax) fail(VSAOGM_EINVAL, "heat and hmax must not be NULL");
+        if (precision < VSAOGM_FP32 || precision > VSAOGM_BF16X3) fail(VSAOGM_EINVAL, "unknown precision");
+        DeviceGuard guard(m->device);
+        hipStream_t s = (hipStream_t)stream;
+        GridCache* gc = grid_cache(m, g, s);
+        const void* ey_lo = nullptr;
+        const void* ey = y_table(m, gc, precision, &ey_lo, s);
+        const int nregions = m->tiles_x * m->tiles_y;
+        if (!gc->region_max.p) gc->region_max.alloc_async(2 * (size_t)nregions, s, "region maxima");
+        // which memories changed since this grid was last decoded incrementally
+        hip_check(hipMemcpyAsync(m->h_version, m->d_version.p, sizeof(unsigned) * m->nkeys,
+                                 hipMemcpyDeviceToHost, s),
+                  "read versions");
+        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+        std::vector<char> dirty(nregions, 0);
+        const bool all = !gc->inc_valid || gc->inc_heat != heat || gc->inc_precision != precision;
+        for (int b = 0; b < nregions; ++b)
+            dirty[b] = all || m->h_version[2 * b] != gc->seen[2 * b] ||
+                       m->h_version[2 * b + 1] != gc->seen[2 * b + 1];
+        std::copy(m->h_version, m->h_version + m->nkeys, gc->seen.begin());
+        gc->inc_valid = true;
+        gc->inc_heat = heat;
+        gc->inc_precision = precision;
+        std::vector<DTile>& tl = gc->inc_tiles_host;
+        std::vector<RegionBox>& bx = gc->inc_boxes_host;
+        tl.clear();
+        bx.clear();
+        for (const DTile& t : gc->host_tiles) {
+            const int tx0 = gc->tcol[t.col0], tx1 = gc->tcol[std::min(t.col0 + 63, g->nx - 1)];
+            bool d = false;
+            for (int tx = tx0; tx <= tx1 && !d; ++tx) d = dirty[t.ty * m->tiles_x + tx];
+            if (d) tl.push_back(t);
+        }
+        for (int b = 0; b < nregions; ++b)
+            if (dirty[b]) bx.push_back(gc->boxes[b]);
+        if (gc->inc_tiles.n < tl.size()) gc->inc_tiles.alloc_async(gc->host_tiles.size(), s, "incremental tiles");
+        if (gc->inc_boxes.n < bx.size()) gc->inc_boxes.alloc_async(nregions, s, "incremental regions");
+        // the host vectors stay untouched until this stream passes the copies: the next
+        // incremental decode of this grid synchronises the stream before refilling them
+        if (!tl.empty())
+            hip_check(hipMemcpyAsync(gc->inc_tiles.p, tl.data(), tl.size() * sizeof(DTile), hipMemcpyHostToDevice, s),
+                      "copy tiles");
+        if (!bx.empty())
+            hip_check(hipMemcpyAsync(gc->inc_boxes.p, bx.data(), bx.size() * sizeof(RegionBox),
+                                     hipMemcpyHostToDevice, s),
+                      "copy regions");
+        if (!tl.empty()) {
+            DecodeLaunch d;
+            d.plan = decode_plan(precision, (int)tl.size(), m->halfp, m->num_cus);
+            const size_t need = decode_partial_floats(d.plan.grid);
+            if (m->d_partial.n < need) m->d_partial.alloc_async(need, s, "decode partial sums");
+            hip_check(launch_norm(m->d_omega.p, m->nkeys, m->half, m->halfp, m->D, m->d_scale.p,
+                                  m->d_omega_s.p, m->d_hmax_u.p, s),
+                      "norm launch");
+            d.tiles = gc->inc_tiles.p;
+            d.ntiles = (int)tl.size();
+            d.col_tx = gc->col_tx.p;
+            d.ex = gc->ex32.p;
+            d.ey = ey;
+            d.ey_lo = ey_lo;
+            d.omega_s = m->d_omega_s.p;
+            d.halfp = m->halfp;
+            d.nx = g->nx;
+            d.ny = g->ny;
+            d.tiles_x = m->tiles_x;
+            d.out_scale = (float)(2.0 / (double)m->D);
+            d.heat = heat;
+            d.hmax_u = nullptr;
+            d.hmax = hmax;
+            d.partial = m->d_partial.p;
+            hip_check(launch_decode(precision, d, s), "decode launch");
+        }
+        hip_check(launch_region_max(heat, g->nx, g->ny, gc->inc_boxes.p, (int)bx.size(), gc->region_max.p,
+                                    nregions, hmax, s),
+                  "region maxima");
+    });
+}
+
 int vsaogm_classify_ex(const vsaogm_grid_desc* g, const float* heat, const float* hmax,
                        int32_t r_occ, int32_t r_emp, float rho, int32_t normalize, int32_t square,
                        int32_t activation, float* ogm, uint8_t* label, int32_t device,
@@ -629,6 +749,7 @@ int vsaogm_fuse(vsaogm_map* dst, const vsaogm_map* src, vsaogm_stream stream) {
         DeviceGuard guard(dst->device);
         hip_check(launch_add(dst->d_omega.p, src->d_omega.p, dst->d_omega.n, (hipStream_t)stream),
                   "fuse launch");
+        hip_check(launch_bump_versions(dst->d_version.p, dst->nkeys, (hipStream_t)stream), "versions");
     });
 }
 

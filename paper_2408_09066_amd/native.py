@@ -25,7 +25,7 @@ EXPORTED = [
     "vsaogm_profile_events", "vsaogm_server_create", "vsaogm_server_destroy",
     "vsaogm_server_add_map", "vsaogm_server_get_map", "vsaogm_submit", "vsaogm_poll",
     "vsaogm_wait", "vsaogm_server_drain", "vsaogm_server_stats", "vsaogm_submit_many",
-    "vsaogm_classify_ex",
+    "vsaogm_classify_ex", "vsaogm_decode_incremental",
 ]
 ACTIVATIONS = {"entropy": 0, "relu": 1, "tanh": 2, "sigmoid": 3}
 
@@ -88,6 +88,7 @@ def load(path: str = LIB_PATH):
     L.vsaogm_encode.argtypes = [P, P, P, i64, P]
     L.vsaogm_map_take_rejected.argtypes = [P, P, ctypes.POINTER(i64)]
     L.vsaogm_decode.argtypes = [P, ctypes.POINTER(GridDesc), i32, P, P, P]
+    L.vsaogm_decode_incremental.argtypes = [P, ctypes.POINTER(GridDesc), i32, P, P, P]
     L.vsaogm_classify.argtypes = [ctypes.POINTER(GridDesc), P, P, i32, i32, f32, P, P, i32, P]
     L.vsaogm_memories.argtypes = [P, P, P]
     L.vsaogm_classify_ex.argtypes = [ctypes.POINTER(GridDesc), P, P, i32, i32, f32, i32, i32, i32,
@@ -192,6 +193,18 @@ class Map:
         g = grid_desc(grid, nx, ny)
         check(load().vsaogm_decode(self._h, ctypes.byref(g), PRECISIONS[precision], _ptr(heat),
                                    _ptr(hmax), _stream(stream)))
+        return heat, hmax
+
+    def decode_incremental(self, grid, nx: int, ny: int, heat, precision: str = "fp32", hmax=None,
+                           stream=None):
+        """Recompute only the tiles whose memories changed since the last call with this heat."""
+        import torch
+        if hmax is None:
+            hmax = torch.empty(2, dtype=torch.float32, device=torch.device("cuda", self.device))
+        assert heat.is_contiguous() and tuple(heat.shape) == (2, ny, nx)
+        g = grid_desc(grid, nx, ny)
+        check(load().vsaogm_decode_incremental(self._h, ctypes.byref(g), PRECISIONS[precision],
+                                               _ptr(heat), _ptr(hmax), _stream(stream)))
         return heat, hmax
 
     def memories(self, out=None, stream=None):
