@@ -189,6 +189,89 @@ def serving_benchmark(n_requests: int = 256, slots: int = 8, precision: str = "b
     }
 
 
+def stress_generate(n_updates: int, workers: int):
+    """The large-map scenario and its first n_updates updates (host arrays), made before any
+    GPU use: generation forks worker processes."""
+    from paper_2408_09066_amd import synth
+    sc = synth.stress_scenario()
+    t = time.perf_counter()
+    ups = sc.updates(n_updates, workers=workers)
+    return sc, ups, time.perf_counter() - t
+
+
+def stress_benchmark(sc, ups, precision: str = "bf16x3", load: float = 0.8):
+    """Large-map stress: one map of 16 x 16 tiles at D = 16384 and a 4000 x 4000 grid, updated
+    through the request loop, one request per 10 poses (118 800 points), each returning the
+    grid's labels.  Passes, each on a fresh map: (1) every update queued at once with
+    localized decoding (only tiles whose memories changed), (2) the same with full decodes,
+    (3) Poisson arrivals at `load` x the throughput of (1), for the sustained latency."""
+    import torch
+    from paper_2408_09066_amd import native
+
+    R = sc.r
+    cells = sc.nx * sc.ny
+
+    def run(srv, batch, local, arrivals=None):
+        mid = srv.add_map(sc.theta, sc.layout, sc.tiles)
+        items = [{"map_id": mid, "xy": xy, "label": lb, "grid": sc.grid, "nx": sc.nx, "ny": sc.ny,
+                  "r_occ": R, "r_emp": R, "precision": precision, "local": local} for xy, lb in batch]
+        t0 = time.perf_counter()
+        if arrivals is None:
+            tk = srv.submit_many(items)
+        else:
+            tk = []
+            for it, a_ in zip(items, arrivals):
+                while time.perf_counter() - t0 < a_:
+                    pass
+                tk.extend(srv.submit_many([it]))
+        res = [srv.wait(t) for t, _ in tk]
+        total_s = time.perf_counter() - t0
+        assert all(r["status"] == 0 for r in res)
+        lat = [(r["t_done_ns"] - r["t_submit_ns"]) * 1e-6 for r in res]
+        svc = [(r["t_done_ns"] - r["t_start_ns"]) * 1e-6 for r in res]
+        return total_s, lat, svc, tk[-1][1]["label"]
+
+    # untimed, on a server of its own: kernels loaded
+    warm = native.Server(max_inflight=2)
+    run(warm, ups[:2], True)
+    warm.close()
+    torch.cuda.synchronize()
+    free0, total = torch.cuda.mem_get_info()
+    srv = native.Server(max_inflight=2)
+    t_loc, _, svc_loc, lab_loc = run(srv, ups, True)
+    free1, _ = torch.cuda.mem_get_info()
+    t_full, _, svc_full, lab_full = run(srv, ups, False)
+    rate = load * len(ups) / t_loc
+    gaps = np.random.default_rng(np.random.SeedSequence([2408, 5, 5])).exponential(1.0 / rate, size=len(ups))
+    t_open, lat_open, _, _ = run(srv, ups, True, np.cumsum(gaps))
+    stats = srv.stats()
+    srv.close()
+    npts = sum(len(xy) for xy, _ in ups)
+    steady = svc_loc[1:] if len(svc_loc) > 1 else svc_loc
+    return {
+        "workload": (f"{sc.name}: 200 m x 200 m world, {len(sc.world.rects)} rectangles + "
+                     f"{len(sc.world.circles)} circles, {len(ups)} updates of "
+                     f"{sc.poses_per_update} poses x {sc.beams} beams x (1 + {sc.empties}) = "
+                     f"{sc.points_per_update} points, D={sc.D}, {sc.tiles[0]}x{sc.tiles[1]} tiles, "
+                     f"{sc.nx}x{sc.ny} grid at {sc.grid[2]} m, r={R}, {precision} decode, "
+                     "labels returned per update"),
+        "updates": len(ups),
+        "points": npts,
+        "updates_per_s": len(ups) / t_loc,
+        "points_per_s": npts / t_loc,
+        "cells_per_s": cells * len(ups) / t_loc,
+        "full_decode_updates_per_s": len(ups) / t_full,
+        "label_agreement_full_decode": float(np.mean(lab_loc == lab_full)),
+        "service_ms": {"first": svc_loc[0], "p50": percentile(steady, 50), "p99": percentile(steady, 99)},
+        "full_decode_service_ms": {"p50": percentile(svc_full[1:], 50), "p99": percentile(svc_full[1:], 99)},
+        "open_loop": {"load": load, "qps": rate, "latency_ms": {"p50": percentile(lat_open, 50),
+                                                                "p99": percentile(lat_open, 99)}},
+        "hbm_bytes_in_use": int(free0 - free1),   # one map, its tables and the server's buffers
+        "hbm_total_bytes": int(total),
+        "peak_budget_bytes": stats["peak_bytes"],
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,12 +283,18 @@ def main() -> int:
                     help="seconds of oracle work for the CPU baseline (0 disables it)")
     ap.add_argument("--serving", type=int, default=1,
                     help="also run the request-loop benchmark (256 updates of 16 maps)")
+    ap.add_argument("--stress", type=int, default=200,
+                    help="updates of the large-map stress run through the request loop (0 disables it)")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="processes that generate the stress scans")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the hot path here is the single-GPU kernel set)", file=sys.stderr)
         return 2
+
+    stress_in = stress_generate(args.stress, args.workers) if args.stress > 0 else None
 
     import torch
     from paper_2408_09066_amd import native, synth
@@ -311,6 +400,10 @@ def main() -> int:
     m.close()
     if args.serving:
         result["serving"] = serving_benchmark()
+    if stress_in is not None:
+        sc, ups, gen_s = stress_in
+        result["stress"] = stress_benchmark(sc, ups)
+        result["stress"]["generation_s"] = gen_s
     if args.cpu_budget > 0:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(result), flush=True)

@@ -151,6 +151,8 @@ int vsaogm_decode(vsaogm_map* map, const vsaogm_grid_desc* grid, int32_t precisi
  * recomputed; the other cells keep their values (heat must be that buffer, unchanged
  * since).  The first call for a grid, or a call with another heat buffer or precision,
  * decodes every cell.  hmax is the maximum over all cells (the map keeps per-tile maxima).
+ * A recomputed cell equals vsaogm_decode's value up to the order of the fp32 accumulation
+ * (the reduction over frequencies is split among workgroups by the number of tiles decoded).
  * Synchronises the stream once, to read which memories changed.  Errors as vsaogm_decode.
  */
 int vsaogm_decode_incremental(vsaogm_map* map, const vsaogm_grid_desc* grid, int32_t precision,
@@ -241,7 +243,13 @@ typedef struct {
     float* ogm;               /* host [ny][nx] signed difference, or NULL */
     uint8_t* label_out;       /* host [ny][nx] occupancy labels, or NULL */
     float* heat;              /* host [2][ny][nx] similarity maps, or NULL */
+    int32_t flags;            /* 0, or VSAOGM_REQUEST_LOCAL */
 } vsaogm_request;
+
+/* Request flag: decode with vsaogm_decode_incremental into a heat buffer the server keeps
+   for the map (one grid per map; a request with another grid or precision decodes in full
+   and replaces it).  That buffer (8 bytes per cell) is map state, outside the budget. */
+enum { VSAOGM_REQUEST_LOCAL = 1 };
 
 typedef struct {
     int32_t status;           /* VSAOGM_OK, or the error the update hit */
@@ -262,7 +270,7 @@ int vsaogm_server_destroy(vsaogm_server* server);
    device is used).  *map_id receives its id (0, 1, ...). */
 int vsaogm_server_add_map(vsaogm_server* server, const vsaogm_map_desc* desc, int32_t* map_id);
 
-/* The server-owned map (for vsaogm_memories / vsaogm_fuse after vsaogm_server_drain).
+/* The server-owned map (for vsaogm_memories, vsaogm_decode or vsaogm_fuse after vsaogm_server_drain).
    Not to be encoded into or destroyed by the caller. */
 int vsaogm_server_get_map(vsaogm_server* server, int32_t map_id, vsaogm_map** out);
 

@@ -192,6 +192,12 @@ struct vsaogm_server {
     std::vector<vsaogm_map*> maps;
     std::vector<int32_t> map_dim;
     std::vector<char> map_busy;
+    // heat kept per map for VSAOGM_REQUEST_LOCAL (only the map's own running request uses it)
+    struct LocalHeat {
+        DevMem heat;
+        vsaogm_grid_desc grid{};
+    };
+    std::vector<std::unique_ptr<LocalHeat>> local_heat;
     std::deque<Request*> pending;
     std::unordered_map<uint64_t, std::unique_ptr<Request>> tickets;
     std::vector<Slot> slots;
@@ -235,7 +241,27 @@ void vsaogm_server::launch(Slot& s, int slot_index) {
         float* hmax = reinterpret_cast<float*>(dout);
         float* heat = reinterpret_cast<float*>(dout + L.heat);
         call(vsaogm_encode(m, reinterpret_cast<float*>(din), din + n * 8, n, s.stream));
-        call(vsaogm_decode(m, &r.grid, r.precision, heat, hmax, s.stream));
+        if (r.flags & VSAOGM_REQUEST_LOCAL) {
+            LocalHeat& lh = *local_heat[r.map_id];
+            const bool same = lh.heat.p && lh.grid.nx == r.grid.nx && lh.grid.ny == r.grid.ny &&
+                              lh.grid.x0 == r.grid.x0 && lh.grid.y0 == r.grid.y0 && lh.grid.res == r.grid.res;
+            if (!same) {
+                lh.heat.ensure(cells * 8, s.stream, "map heat");
+                lh.grid = r.grid;
+            }
+            float* mheat = static_cast<float*>(lh.heat.p);
+            // a buffer that held another grid is decoded in full: its address alone cannot tell
+            // the localized decode that its contents changed
+            if (same)
+                call(vsaogm_decode_incremental(m, &r.grid, r.precision, mheat, hmax, s.stream));
+            else
+                call(vsaogm_decode(m, &r.grid, r.precision, mheat, hmax, s.stream));
+            if (r.heat)
+                check_hip(hipMemcpyAsync(heat, mheat, cells * 8, hipMemcpyDeviceToDevice, s.stream), "copy heat");
+            heat = mheat;
+        } else {
+            call(vsaogm_decode(m, &r.grid, r.precision, heat, hmax, s.stream));
+        }
         call(vsaogm_classify(&r.grid, heat, hmax, r.r_occ, r.r_emp, r.rho,
                              reinterpret_cast<float*>(dout + L.ogm), dout + L.lab, device, s.stream));
         check_hip(hipMemcpyAsync(s.h_out.p, dout, back, hipMemcpyDeviceToHost, s.stream), "copy outputs");
@@ -403,6 +429,7 @@ int vsaogm_server_add_map(vsaogm_server* s, const vsaogm_map_desc* d, int32_t* m
         s->maps.push_back(m);
         s->map_dim.push_back(dd.dim);
         s->map_busy.push_back(0);
+        s->local_heat.push_back(std::make_unique<vsaogm_server::LocalHeat>());
         *map_id = (int32_t)s->maps.size() - 1;
     });
 }

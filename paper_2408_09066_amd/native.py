@@ -58,7 +58,11 @@ class Request(ctypes.Structure):
     _fields_ = [("map_id", ctypes.c_int32), ("xy", ctypes.c_void_p), ("label", ctypes.c_void_p),
                 ("n", ctypes.c_int64), ("grid", GridDesc), ("precision", ctypes.c_int32),
                 ("r_occ", ctypes.c_int32), ("r_emp", ctypes.c_int32), ("rho", ctypes.c_float),
-                ("ogm", ctypes.c_void_p), ("label_out", ctypes.c_void_p), ("heat", ctypes.c_void_p)]
+                ("ogm", ctypes.c_void_p), ("label_out", ctypes.c_void_p), ("heat", ctypes.c_void_p),
+                ("flags", ctypes.c_int32)]
+
+
+REQUEST_LOCAL = 1
 
 
 class Result(ctypes.Structure):
@@ -254,13 +258,17 @@ def profile_events(stage: str, begin=None, end=None):
 
 
 class ServerMap:
-    """A map owned by a Server (read-only view for memories / fusion)."""
+    """A map owned by a Server (a view for memories, decoding and fusion once the server is
+    drained)."""
 
     def __init__(self, handle, D, n_memories, device):
         self._h, self.D, self.n_memories, self.device = handle, D, n_memories, device
 
     def memories(self, out=None, stream=None):
         return Map.memories(self, out, stream)
+
+    def decode(self, grid, nx: int, ny: int, precision: str = "fp32", heat=None, hmax=None, stream=None):
+        return Map.decode(self, grid, nx, ny, precision, heat, hmax, stream)
 
 
 class Server:
@@ -305,8 +313,9 @@ class Server:
 
     def submit(self, map_id: int, xy: np.ndarray, label: np.ndarray, grid, nx: int, ny: int,
                r_occ: int, r_emp: int, rho: float = 0.0, precision: str = "fp32",
-               want=("label",), block_when_busy: bool = True):
-        """Queue one update; returns (ticket, outputs dict of numpy arrays filled on completion)."""
+               want=("label",), block_when_busy: bool = True, local: bool = False):
+        """Queue one update; returns (ticket, outputs dict of numpy arrays filled on completion).
+        local: decode only the tiles whose memories changed, into a heat buffer the server keeps."""
         import time
         xy = np.ascontiguousarray(xy, dtype=np.float32).reshape(-1, 2)
         label = np.ascontiguousarray(label, dtype=np.uint8).reshape(-1)
@@ -322,7 +331,8 @@ class Server:
                       float(rho),
                       out["ogm"].ctypes.data if "ogm" in out else None,
                       out["label"].ctypes.data if "label" in out else None,
-                      out["heat"].ctypes.data if "heat" in out else None)
+                      out["heat"].ctypes.data if "heat" in out else None,
+                      REQUEST_LOCAL if local else 0)
         t = ctypes.c_uint64()
         while True:
             rc = load().vsaogm_submit(self._h, ctypes.byref(req), ctypes.byref(t))
@@ -336,7 +346,7 @@ class Server:
 
     def submit_many(self, items, want=("label",)):
         """Queue a list of requests with one call.  items: dicts with keys map_id, xy, label,
-        grid, nx, ny, r_occ, r_emp and optionally rho, precision.  Returns [(ticket, outputs)]."""
+        grid, nx, ny, r_occ, r_emp and optionally rho, precision, local.  Returns [(ticket, outputs)]."""
         n = len(items)
         arr = (Request * n)()
         keep, outs = [], []
@@ -358,7 +368,8 @@ class Server:
                              int(it["r_occ"]), int(it["r_emp"]), float(it.get("rho", 0.0)),
                              out["ogm"].ctypes.data if "ogm" in out else None,
                              out["label"].ctypes.data if "label" in out else None,
-                             out["heat"].ctypes.data if "heat" in out else None)
+                             out["heat"].ctypes.data if "heat" in out else None,
+                             REQUEST_LOCAL if it.get("local") else 0)
         tk = (ctypes.c_uint64 * n)()
         nq = ctypes.c_int32()
         rc = load().vsaogm_submit_many(self._h, arr, n, tk, ctypes.byref(nq))

@@ -119,28 +119,32 @@ def random_walk(world: World, n: int, start: np.ndarray, rng: np.random.Generato
 def raycast(world: World, pose: np.ndarray, angles: np.ndarray) -> np.ndarray:
     """Exact range from pose along each angle to the first wall, rectangle or circle."""
     dx, dy = np.cos(angles), np.sin(angles)
+    px, py = float(pose[0]), float(pose[1])
     with np.errstate(divide="ignore", invalid="ignore"):
         # world boundary (ray starts inside): exit distance
-        tx = np.where(dx > 0, (world.half - pose[0]) / dx, np.where(dx < 0, (-world.half - pose[0]) / dx, np.inf))
-        ty = np.where(dy > 0, (world.half - pose[1]) / dy, np.where(dy < 0, (-world.half - pose[1]) / dy, np.inf))
+        tx = np.where(dx > 0, (world.half - px) / dx, np.where(dx < 0, (-world.half - px) / dx, np.inf))
+        ty = np.where(dy > 0, (world.half - py) / dy, np.where(dy < 0, (-world.half - py) / dy, np.inf))
         t = np.minimum(tx, ty)
-        for xmn, ymn, xmx, ymx in world.rects:
-            t1x = np.where(dx != 0, (xmn - pose[0]) / dx, np.where(pose[0] >= xmn, -np.inf, np.inf))
-            t2x = np.where(dx != 0, (xmx - pose[0]) / dx, np.where(pose[0] <= xmx, np.inf, -np.inf))
-            t1y = np.where(dy != 0, (ymn - pose[1]) / dy, np.where(pose[1] >= ymn, -np.inf, np.inf))
-            t2y = np.where(dy != 0, (ymx - pose[1]) / dy, np.where(pose[1] <= ymx, np.inf, -np.inf))
+        if len(world.rects):
+            # slab test, obstacles x beams at once
+            xmn, ymn, xmx, ymx = (world.rects[:, i:i + 1] for i in range(4))
+            DX, DY = dx[None, :], dy[None, :]
+            t1x = np.where(DX != 0, (xmn - px) / DX, np.where(px >= xmn, -np.inf, np.inf))
+            t2x = np.where(DX != 0, (xmx - px) / DX, np.where(px <= xmx, np.inf, -np.inf))
+            t1y = np.where(DY != 0, (ymn - py) / DY, np.where(py >= ymn, -np.inf, np.inf))
+            t2y = np.where(DY != 0, (ymx - py) / DY, np.where(py <= ymx, np.inf, -np.inf))
             tmin = np.maximum(np.minimum(t1x, t2x), np.minimum(t1y, t2y))
             tmax = np.minimum(np.maximum(t1x, t2x), np.maximum(t1y, t2y))
             hit = (tmax >= tmin) & (tmin > 0)
-            t = np.where(hit & (tmin < t), tmin, t)
-        for cx, cy, r in world.circles:
-            ox, oy = pose[0] - cx, pose[1] - cy
-            b = ox * dx + oy * dy
-            c = ox * ox + oy * oy - r * r
+            t = np.minimum(t, np.where(hit, tmin, np.inf).min(axis=0))
+        if len(world.circles):
+            ox, oy = px - world.circles[:, 0:1], py - world.circles[:, 1:2]
+            b = ox * dx[None, :] + oy * dy[None, :]
+            c = ox * ox + oy * oy - world.circles[:, 2:3] ** 2
             disc = b * b - c
             tc = -b - np.sqrt(np.maximum(disc, 0.0))
             hit = (disc >= 0) & (tc > 0)
-            t = np.where(hit & (tc < t), tc, t)
+            t = np.minimum(t, np.where(hit, tc, np.inf).min(axis=0))
     return t
 
 
@@ -319,3 +323,63 @@ def serving_stream(n_maps: int = 16, n_requests: int = 256, config_id: int = 4,
         tnow += float(rr.exponential(1.0))
         reqs.append(UpdateRequest(m, xy, lab, tnow))
     return maps, reqs
+
+
+@dataclasses.dataclass
+class StressScenario:
+    """A large map updated in scan groups: one long random walk, an update every few poses."""
+    name: str
+    D: int
+    ell: float
+    theta: np.ndarray
+    layout: Tuple[float, float, float, float]
+    tiles: Tuple[int, int]
+    grid: Tuple[float, float, float]
+    nx: int
+    ny: int
+    r: int
+    world: World
+    poses: np.ndarray
+    beams: int
+    empties: int
+    poses_per_update: int
+    config_id: int
+    sigma: float = 0.02
+
+    @property
+    def n_updates(self) -> int:
+        return -(-len(self.poses) // self.poses_per_update)
+
+    @property
+    def points_per_update(self) -> int:
+        return self.poses_per_update * self.beams * (1 + self.empties)
+
+    def update(self, u: int) -> Tuple[np.ndarray, np.ndarray]:
+        """(xy float32 [n][2], label uint8 [n]) of update u (its own noise and empty streams)."""
+        ps = self.poses[u * self.poses_per_update:(u + 1) * self.poses_per_update]
+        rn = np.random.default_rng(np.random.SeedSequence([2408, self.config_id, STREAM_NOISE, u]))
+        re = np.random.default_rng(np.random.SeedSequence([2408, self.config_id, STREAM_EMPTY, u]))
+        return scan_points(self.world, ps, self.beams, self.empties, self.sigma, rn, re)
+
+    def updates(self, limit: Optional[int] = None, workers: int = 1) -> List[Tuple[np.ndarray, np.ndarray]]:
+        """The first `limit` updates in walk order, generated by `workers` processes."""
+        n = self.n_updates if limit is None else min(limit, self.n_updates)
+        if workers <= 1 or n <= 1:
+            return [self.update(u) for u in range(n)]
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(workers, n)) as pool:
+            return pool.map(self.update, range(n), chunksize=1)
+
+
+def stress_scenario(n_poses: int = 2000, config_id: int = 5) -> StressScenario:
+    """200 m square world, 200 rectangles + 200 circles, 1080 beams and 10 empties per beam,
+    D = 16384, l = 0.1 m, 16 x 16 tiles, a 4000 x 4000 grid at 0.05 m, r = 3, and one update per
+    10 poses (118 800 points)."""
+    half, D, ell = 100.0, 16384, 0.1
+    theta = make_theta(D, ell, rng_for(config_id, STREAM_THETA))
+    start = np.zeros(2)
+    world = make_world(half, 200, 200, (0.5, 4.0), (0.25, 1.5), start[None, :], 1.0,
+                       rng_for(config_id, STREAM_WORLD))
+    poses = random_walk(world, n_poses, start, rng_for(config_id, STREAM_POSES))
+    return StressScenario("stress200", D, ell, theta, (-half, -half, half, half), (16, 16),
+                          (-half, -half, 0.05), 4000, 4000, 3, world, poses, 1080, 10, 10, config_id)

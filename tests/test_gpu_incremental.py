@@ -2,8 +2,9 @@
 
 Each cell reads only its own tile's memories (Sec. III-A), so after an update confined to a
 few tiles the cells of every other tile keep their values.  Bars: the incremental heat and
-maxima equal a full decode bit for bit (the same kernels compute every recomputed cell, and
-a maximum is exact); cells of untouched tiles are provably not rewritten (a planted sentinel
+maxima equal a full decode up to the order of the fp32 accumulation (the frequency reduction
+is split among workgroups according to how many tiles are decoded): max-abs difference
+<= ORDER_TOL; cells of untouched tiles are provably not rewritten (a planted sentinel
 survives); and the result meets the fp32 oracle bar (relative L2 <= 1e-4).
 """
 import sys
@@ -18,6 +19,20 @@ pytestmark = pytest.mark.gpu
 
 HEAT_TOL = 1e-4
 SENTINEL = -7.0
+# The absolute values of a cell's K terms sum to at most 1 (each memory is divided by its norm,
+# and by Cauchy-Schwarz sum|Omega_k| <= (D/2) ||omega||), so the partial sums stay below 1 and
+# a different split of the K-reduction moves a cell by a few ulps of them per split point
+# (about 1e-6 measured at D = 16384 and a 4000 x 4000 grid).
+ORDER_TOL = 1e-5
+
+
+def same(a, b):
+    """Equal up to accumulation order."""
+    return bool(torch_max_abs(a, b) <= ORDER_TOL)
+
+
+def torch_max_abs(a, b):
+    return float((a - b).abs().max()) if a.numel() else 0.0
 
 
 def say(*a):
@@ -88,7 +103,7 @@ def test_incremental_equals_full(torch_cuda, name, precision):
     m.decode_incremental(w.grid, w.nx, w.ny, heat, precision, hmax)
     ref, ref_max = full()
     torch.cuda.synchronize()
-    assert torch.equal(heat, ref) and torch.equal(hmax, ref_max)
+    assert same(heat, ref) and same(hmax, ref_max)
 
     # an update inside one tile: a cell of the first tile is not rewritten
     r, c = cell_in(w, tile_box(w, 0, 0, 0.3))
@@ -102,14 +117,14 @@ def test_incremental_equals_full(torch_cuda, name, precision):
     torch.cuda.synchronize()
     assert torch.all(heat[:, r, c] == SENTINEL)
     heat[:, r, c] = keep
-    assert torch.equal(heat, ref) and torch.equal(hmax, ref_max)
-    assert not torch.equal(heat[:, ur, uc], before_u)  # the updated tile did change
+    assert same(heat, ref) and same(hmax, ref_max)
+    assert torch_max_abs(heat[:, ur, uc], before_u) > 1e-4  # the updated tile did change
 
     # nothing changed: nothing is recomputed, maxima stay
     heat[:, ur, uc] = SENTINEL
     m.decode_incremental(w.grid, w.nx, w.ny, heat, precision, hmax)
     torch.cuda.synchronize()
-    assert torch.all(heat[:, ur, uc] == SENTINEL) and torch.equal(hmax, ref_max)
+    assert torch.all(heat[:, ur, uc] == SENTINEL) and same(hmax, ref_max)
     heat[:, ur, uc] = ref[:, ur, uc]
 
     # the full point set against the oracle (fp32 bar)
@@ -132,12 +147,12 @@ def test_incremental_equals_full(torch_cuda, name, precision):
     m.decode_incremental(w.grid, w.nx, w.ny, heat, precision, hmax)
     ref, ref_max = full()
     torch.cuda.synchronize()
-    assert torch.equal(heat, ref) and torch.equal(hmax, ref_max)
+    assert same(heat, ref) and same(hmax, ref_max)
 
     # another heat buffer decodes every cell
     heat2 = torch.full_like(heat, float("nan"))
     m.decode_incremental(w.grid, w.nx, w.ny, heat2, precision, hmax)
     torch.cuda.synchronize()
-    assert torch.equal(heat2, ref) and torch.equal(hmax, ref_max)
+    assert same(heat2, ref) and same(hmax, ref_max)
     other.close()
     m.close()

@@ -55,7 +55,7 @@ def direct(torch, maps, reqs, precision):
     return outs
 
 
-def served(maps, reqs, precision, only_map=None, max_inflight=4, budget=0):
+def served(maps, reqs, precision, only_map=None, max_inflight=4, budget=0, local=False):
     from paper_2408_09066_amd import native
     srv = native.Server(max_inflight=max_inflight, hbm_budget_bytes=budget)
     ids = [srv.add_map(m.theta, m.layout, m.tiles) for m in maps]
@@ -65,7 +65,7 @@ def served(maps, reqs, precision, only_map=None, max_inflight=4, budget=0):
             continue
         spec = maps[q.map_id]
         t, out = srv.submit(ids[q.map_id], q.xy, q.label, spec.grid, spec.side, spec.side, 3, 3,
-                            0.0, precision, want=("label", "ogm", "heat"))
+                            0.0, precision, want=("label", "ogm", "heat"), local=local)
         tickets.append((i, t, out))
     results = {}
     for i, t, out in tickets:
@@ -180,4 +180,60 @@ def test_submit_many_matches_single_submits(torch_cuda, stream):
     with pytest.raises(native.VsaogmError):
         srv.submit_many([items[0], bad, items[1]])
     srv.drain()
+    srv.close()
+
+
+# Localized and full decodes differ only in the order of the fp32 K-reduction: heat by at most
+# ORDER_TOL (absolute), the OGM derived from it by at most the OGM bar used against the oracle,
+# and labels only where the OGM lies within that bar of the threshold 0.
+ORDER_TOL = 1e-5
+OGM_TOL = 1e-3
+
+
+def check_local(out, ref, tag):
+    for k, tol in (("heat", ORDER_TOL), ("ogm", OGM_TOL)):
+        d = float(np.max(np.abs(out[k] - ref[k]))) if out[k].size else 0.0
+        assert d <= tol, (tag, k, d)
+    flips = out["label"] != ref["label"]
+    assert not flips.any() or float(np.max(np.abs(ref["ogm"][flips]))) <= OGM_TOL, tag
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_local_requests_equal_full_ones(torch_cuda, stream, precision):
+    """Requests flagged local (map-kept heat, only changed tiles decoded) match full decodes up
+    to the accumulation order of the similarity reduction (labels may differ only where the
+    OGM is within that of the threshold 0)."""
+    say(f"[gpu] local requests {precision}")
+    maps, reqs = stream
+    ref = direct(torch_cuda, maps, reqs, precision)
+    got, _ = served(maps, reqs, precision, local=True)
+    for i in range(len(reqs)):
+        out, _ = got[i]
+        check_local(out, ref[i], i)
+
+
+def test_local_requests_switching_grids(torch_cuda):
+    """One map, local requests alternating between two grids, against full decodes."""
+    say("[gpu] local requests, two grids")
+    from paper_2408_09066_amd import native
+    torch = torch_cuda
+    w = synth.workload("mini4x4")
+    grids = [(w.grid, w.nx, w.ny), ((w.grid[0] + 0.35, w.grid[1] + 0.15, 0.1), 120, 96)]
+    parts = np.array_split(np.arange(w.n), 6)
+    srv = native.Server(max_inflight=2)
+    mid = srv.add_map(w.theta, w.layout, w.tiles)
+    ref_map = native.Map(w.theta, w.layout, w.tiles)
+    for j, idx in enumerate(parts):
+        g, nx, ny = grids[(j // 2) % 2]
+        t, out = srv.submit(mid, w.xy[idx], w.label[idx], g, nx, ny, 3, 3, 0.0, "fp32",
+                            want=("label", "ogm", "heat"), local=True)
+        assert srv.wait(t)["status"] == 0
+        ref_map.encode(torch.from_numpy(np.ascontiguousarray(w.xy[idx])).cuda(),
+                       torch.from_numpy(np.ascontiguousarray(w.label[idx])).cuda())
+        heat, hmax = ref_map.decode(g, nx, ny)
+        ogm, lab = native.classify(heat, hmax, 3, 3, 0.0)
+        torch.cuda.synchronize()
+        check_local(out, {"heat": heat.cpu().numpy(), "ogm": ogm.cpu().numpy(),
+                          "label": lab.cpu().numpy()}, j)
+    ref_map.close()
     srv.close()
