@@ -287,7 +287,20 @@ def main() -> int:
                     help="updates of the large-map stress run through the request loop (0 disables it)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
                     help="processes that generate the stress scans")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 512 MiB device to device three times (reference for HBM byte counters)")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        n = 512 << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}), flush=True)
+        return 0
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "

@@ -28,6 +28,8 @@
 // would evict the location tables of every resident workgroup.  Every store folds the class
 // maxima (eq. non-linearities) into order-preserving unsigned atomics; a one-block kernel
 // converts them once all stores are done.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace vsaogm {
@@ -56,7 +58,7 @@ __device__ inline uint32_t pack_bf16_lo(float a, float b, uint32_t hi) {
     return pack_bf16(a - ha, b - hb);
 }
 
-constexpr int kRowBlocks = kDecodeRowBlocks;
+constexpr int kRowBlocks = kDecodeSetRowBlocks[0];
 constexpr int kTileRows = 16 * kRowBlocks;
 constexpr int kTileCols = 64;
 constexpr int kRowPitchBytes = 144;  // LDS row: 128 data bytes + 16 padding
@@ -421,39 +423,290 @@ __global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeAr
     }
 }
 
+// 16-bit operand formats.  Work tiles of 4*RBW row blocks x 64 columns x 2 classes.  The
+// waves split the rows (wave w owns row blocks w, w+4, ...) and read their row operand -- the
+// location table, already in the MFMA input format -- straight from global memory into
+// registers, DEPTH K steps ahead; only the column operand, which needs the memory factor
+// applied, goes through LDS (its sources are loaded one step ahead), where all four waves read
+// it.  So LDS carries one operand instead of two, and each wave reads only its own rows' table
+// data.  256-row tiles, one workgroup per CU (the accumulators take the AGPRs).
+template <int PREC>
+struct Wide {
+    static constexpr bool kSplit = (PREC == 3);
+    static constexpr int RBW = 4;                       // row blocks per wave
+    static constexpr int OCC = 1;                       // workgroups per CU
+    static constexpr int TR = 64 * RBW;                 // tile rows
+    static constexpr int NS = kSplit ? 2 : 1;           // hi (+ lo) parts
+    static constexpr int DEPTH = 1;                     // K steps the row operand is loaded ahead
+    static constexpr int NSETS = DEPTH + 1;             // register sets in rotation
+    static constexpr int KB = 32;                       // complex bins per K step
+    static constexpr int BROWS = 2 * kTileCols;         // LDS rows: class-major columns
+    static constexpr int BSTAGE = NS * BROWS * kRowPitchBytes;
+    static constexpr int B_PER_T = kTileCols * KB / 2 / 256;  // f32x4 units per thread
+    static constexpr int OSTAGE = 2 * 2 * KB;           // float2: [key slot][class][bin]
+};
+
+static_assert(Wide<1>::TR == 16 * kDecodeSetRowBlocks[1] && Wide<3>::TR == 16 * kDecodeSetRowBlocks[2],
+              "tile sets match the kernels");
+
+template <int PREC>
+__global__ __launch_bounds__(256, Wide<PREC>::OCC) void k_decode16(DecodeArgs a) {
+    using W = Wide<PREC>;
+    constexpr int NS = W::NS, NSETS = W::NSETS, DEPTH = W::DEPTH, KB = W::KB, RBW = W::RBW, TR = W::TR;
+    constexpr int B_PER_T = W::B_PER_T;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[2 * W::BSTAGE];
+    __shared__ __attribute__((aligned(16))) float2 om_lds[2][W::OSTAGE];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, i16 = lane & 15;
+    const int wg = xcd_local_index(blockIdx.x, gridDim.x);
+    const long long it0 = (long long)wg * a.steps_per_wg;
+    const long long it1 = min(it0 + a.steps_per_wg, a.total_steps);
+    const int first_tile = (int)(it0 / a.ksteps);
+    const uint16_t* ey_hi = static_cast<const uint16_t*>(a.ey);
+    const uint16_t* ey_lo = static_cast<const uint16_t*>(a.ey_lo);
+    const size_t pitch = 2 * (size_t)a.halfp;  // 16-bit elements per table row
+
+    long long it = it0;
+    while (it < it1) {
+        const int ti = (int)(it / a.ksteps);
+        const int kb0 = (int)(it - (long long)ti * a.ksteps);
+        const int kb1 = (int)min((long long)a.ksteps, it1 - (long long)ti * a.ksteps);
+        it = (long long)ti * a.ksteps + kb1;
+        const DTile t = a.tiles[ti];
+        const int n = kb1 - kb0;
+        // row blocks of this wave present in the tile (wave-uniform, kept in a scalar register)
+        const int wv = __builtin_amdgcn_readfirstlane(wave);
+        const int nj = __builtin_amdgcn_readfirstlane((t.nrb > wv) ? min((t.nrb - wv + 3) / 4, RBW) : 0);
+
+        // row operand addresses: row i16 of each owned block, K offset 8*g within a 32-real chunk
+        size_t arow[RBW];
+#pragma unroll
+        for (int j = 0; j < RBW; ++j) {
+            const int row = min(t.row0 + 16 * (wave + 4 * j) + i16, t.row_end - 1);
+            arow[j] = (size_t)row * pitch + 8 * g;
+        }
+        // column operand sources: the x table per column; the memories of the (at most two)
+        // tile columns of the slice are staged in LDS, two K steps ahead, by the first wave
+        const f32x4* ex_row[B_PER_T];
+        int oslot[B_PER_T];
+        const int part16 = tid % (KB / 2);
+#pragma unroll
+        for (int u = 0; u < B_PER_T; ++u) {
+            const int c = (tid + 256 * u) / (KB / 2);
+            const int gcol = min(t.col0 + c, a.nx - 1);
+            ex_row[u] = reinterpret_cast<const f32x4*>(a.ex + (size_t)gcol * a.halfp + 2 * part16);
+            oslot[u] = min(max(a.col_tx[gcol] - t.tx0, 0), 1);
+        }
+        const int oks = (lane >> 5) & 1, ocls = (lane >> 4) & 1;  // this lane's staging item
+        const f32x4* om_src = reinterpret_cast<const f32x4*>(
+            a.omega_s + (size_t)(2 * (t.ty * a.tiles_x + min(t.tx0 + oks, a.tiles_x - 1)) + ocls) * a.halfp +
+            2 * part16);
+        f32x4 OM;
+        auto load_om = [&](int kk) { OM = om_src[(size_t)(kb0 + min(kk, n - 1)) * (KB / 2)]; };
+        auto store_om = [&](int st) {
+            if (wave == 0)
+                *reinterpret_cast<f32x4*>(&om_lds[st][(oks * 2 + ocls) * KB + 2 * part16]) = OM;
+        };
+
+        u32x4 A[NSETS][RBW][2][NS];     // [set][block][32-real chunk][hi, lo]
+        f32x4 BX[B_PER_T];
+
+        // Loads are issued without branches (blocks past the tile's last one reload a clamped row,
+        // steps past the segment's last one reload its last step), so that the compiler can count
+        // them exactly and waits only for the data a step actually consumes.
+        auto load_a = [&](auto SET, int kk) {  // row operand of K step kb0 + kk into set SET
+            constexpr int S = decltype(SET)::value;
+            const int kb = kb0 + min(kk, n - 1);
+#pragma unroll
+            for (int j = 0; j < RBW; ++j)
+#pragma unroll
+                    for (int ch = 0; ch < 2; ++ch) {
+                        const size_t off = arow[j] + (size_t)kb * (2 * KB) + 32 * ch;
+                        A[S][j][ch][0] = *reinterpret_cast<const u32x4*>(ey_hi + off);
+                        if (W::kSplit) A[S][j][ch][NS - 1] = *reinterpret_cast<const u32x4*>(ey_lo + off);
+                    }
+        };
+        auto load_b = [&](int kk) {  // column operand sources of K step kb0 + kk
+            const size_t boff = (size_t)(kb0 + min(kk, n - 1)) * (KB / 2);
+#pragma unroll
+            for (int u = 0; u < B_PER_T; ++u) BX[u] = ex_row[u][boff];
+        };
+        // column operand into LDS stage st: conj(Omega)/||w|| * Ex as (Re, -Im)
+        auto bstore = [&](int st) {
+            unsigned char* Bs = smem + st * W::BSTAGE;
+#pragma unroll
+            for (int u = 0; u < B_PER_T; ++u) {
+                const int idx = tid + 256 * u;
+                const int c = idx / (KB / 2), part = idx % (KB / 2);
+                const f32x4 e = BX[u];
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    const f32x4 o = *reinterpret_cast<const f32x4*>(&om_lds[st][(oslot[u] * 2 + p) * KB + 2 * part]);
+                    const float r0 = __builtin_fmaf(o.x, e.x, -o.y * e.y);
+                    const float r1 = -__builtin_fmaf(o.x, e.y, o.y * e.x);
+                    const float r2 = __builtin_fmaf(o.z, e.z, -o.w * e.w);
+                    const float r3 = -__builtin_fmaf(o.z, e.w, o.w * e.z);
+                    unsigned char* dst = Bs + (p * kTileCols + c) * kRowPitchBytes + 8 * part;
+                    if (PREC == 2) {
+                        *reinterpret_cast<u32x2*>(dst) = u32x2{pack_f16(r0, r1), pack_f16(r2, r3)};
+                    } else {
+                        const uint32_t h01 = pack_bf16(r0, r1), h23 = pack_bf16(r2, r3);
+                        *reinterpret_cast<u32x2*>(dst) = u32x2{h01, h23};
+                        if (W::kSplit)
+                            *reinterpret_cast<u32x2*>(dst + W::BROWS * kRowPitchBytes) =
+                                u32x2{pack_bf16_lo(r0, r1, h01), pack_bf16_lo(r2, r3, h23)};
+                    }
+                }
+            }
+        };
+
+        v4f acc[RBW][2][4];
+#pragma unroll
+        for (int j = 0; j < RBW; ++j)
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) acc[j][p][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+
+        // one K step from register set SET: loads for step kk + DEPTH go out first, then the
+        // MFMAs of step kk (column operand from LDS stage kk & 1), then step kk + 1's column
+        // operand is written to the other stage; one barrier per step
+        auto step = [&](auto SET, int kk) {
+            constexpr int S = decltype(SET)::value;
+            load_b(kk + 1);  // first: the wait for it at the end of the step leaves the row loads in flight
+            load_om(kk + 2);
+            load_a(std::integral_constant<int, (S + DEPTH) % NSETS>{}, kk + DEPTH);
+            const unsigned char* Bs = smem + (kk & 1) * W::BSTAGE;
+#pragma unroll
+            for (int ch = 0; ch < 2; ++ch) {
+                u32x4 bh[4][2], bl[4][2];
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) {
+                        const unsigned char* src = Bs + (p * kTileCols + 16 * cb + i16) * kRowPitchBytes + 64 * ch + 16 * g;
+                        bh[cb][p] = *reinterpret_cast<const u32x4*>(src);
+                        if (W::kSplit) bl[cb][p] = *reinterpret_cast<const u32x4*>(src + W::BROWS * kRowPitchBytes);
+                    }
+                constexpr int NTERM = W::kSplit ? 3 : 1;
+#pragma unroll
+                for (int term = 0; term < NTERM; ++term)
+#pragma unroll
+                    for (int j = 0; j < RBW; ++j)
+                        if (j < nj)
+#pragma unroll
+                            for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                                for (int p = 0; p < 2; ++p) {
+                                    const u32x4 x = (term == 2) ? A[S][j][ch][NS - 1] : A[S][j][ch][0];
+                                    const u32x4 y = (term == 1) ? bl[cb][p] : bh[cb][p];
+                                    if (PREC == 2)
+                                        acc[j][p][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                            __builtin_bit_cast(v8h, x), __builtin_bit_cast(v8h, y), acc[j][p][cb], 0, 0, 0);
+                                    else
+                                        acc[j][p][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                            __builtin_bit_cast(v8bf, x), __builtin_bit_cast(v8bf, y), acc[j][p][cb], 0, 0, 0);
+                                }
+            }
+            bstore((kk + 1) & 1);  // past the segment's end: a stage nobody reads
+            store_om(kk & 1);      // memories of step kk + 2, into the stage step kk's used
+            __syncthreads();
+        };
+
+        __syncthreads();  // the previous tile's reads of every LDS stage are done
+        load_om(0);
+        store_om(0);
+        load_om(1);
+        store_om(1);
+        load_b(0);
+        load_a(std::integral_constant<int, 0>{}, 0);
+        if (DEPTH > 1) load_a(std::integral_constant<int, 1 % NSETS>{}, 1);
+        __syncthreads();
+        bstore(0);
+        __syncthreads();
+        int kk = 0;
+        for (; kk + NSETS <= n; kk += NSETS) {  // straight-line bodies
+            step(std::integral_constant<int, 0>{}, kk);
+            step(std::integral_constant<int, 1>{}, kk + 1);
+            if (NSETS > 2) step(std::integral_constant<int, 2 % NSETS>{}, kk + 2);
+        }
+        if (kk < n) step(std::integral_constant<int, 0>{}, kk);
+        if (NSETS > 2 && kk + 1 < n) step(std::integral_constant<int, 1>{}, kk + 1);
+
+        const bool whole = (kb0 == 0 && kb1 == a.ksteps);
+        const int slot = (ti == first_tile) ? 0 : 1;
+        float* part = a.partial + ((size_t)wg * 2 + slot) * 2 * TR * kTileCols;
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            float mx = -INFINITY;
+            float* out = a.heat + (size_t)p * a.nx * a.ny;
+#pragma unroll
+            for (int j = 0; j < RBW; ++j)
+                if (j < nj)
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int r = 16 * (wave + 4 * j) + 4 * g + e, c = 16 * cb + i16;
+                            if (whole) {
+                                const int row = t.row0 + r, col = t.col0 + c;
+                                if (row < t.row_end && c < t.ncol) {
+                                    const float v = acc[j][p][cb][e] * a.out_scale;
+                                    out[(size_t)row * a.nx + col] = v;
+                                    mx = fmaxf(mx, v);
+                                }
+                            } else {
+                                part[((size_t)p * TR + r) * kTileCols + c] = acc[j][p][cb][e];
+                            }
+                        }
+            if (whole) {
+                for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+                if (lane == 0 && mx > -INFINITY && a.hmax_u) atomicMax(a.hmax_u + p, order_key(mx));
+            }
+        }
+    }
+}
+
 // Split tiles: add the segments' partial sums in workgroup order (deterministic), scale, store,
-// fold the maxima.  Block (tile, eighth): 7 elements per thread, all loads of a thread in
+// fold the maxima.  Block (tile, part): about 8 elements per thread, all loads of a thread in
 // flight together; one atomic per block and class.  Tiles finished whole by one workgroup are
 // skipped.  Runs after the GEMM, so the kernel boundary makes the partial sums visible.
-constexpr int kFixParts = 8;
-constexpr int kFixPer = 2 * kTileRows * kTileCols / kFixParts / 256;  // elements per thread
-static_assert(kFixPer * 256 * kFixParts == 2 * kTileRows * kTileCols, "fix-up split");
+template <int TR>
+struct Fix {
+    static constexpr int PER_TILE = 2 * TR * kTileCols;
+    static constexpr int PARTS = PER_TILE / 256 / 8 > 0 ? PER_TILE / (256 * 8) : 1;  // ~8 elements per thread
+    static constexpr int PER = PER_TILE / PARTS / 256;
+    static_assert(PER * 256 * PARTS == PER_TILE, "fix-up split");
+};
 
+template <int TR>
 __global__ __launch_bounds__(256) void k_decode_fix(DecodeArgs a) {
-    constexpr int PER_TILE = 2 * kTileRows * kTileCols;
-    const int ti = blockIdx.x / kFixParts, part8 = blockIdx.x % kFixParts;
+    using X = Fix<TR>;
+    constexpr int PER_TILE = X::PER_TILE, PARTS = X::PARTS, PER = X::PER;
+    const int ti = blockIdx.x / PARTS, partk = blockIdx.x % PARTS;
     const long long t0 = (long long)ti * a.ksteps;
     const int w_first = (int)(t0 / a.steps_per_wg);
     const int w_last = (int)((t0 + a.ksteps - 1) / a.steps_per_wg);
     if (w_first == w_last) return;  // whole tile, stored by the GEMM
     const DTile t = a.tiles[ti];
-    float sum[kFixPer];
+    float sum[PER];
 #pragma unroll
-    for (int j = 0; j < kFixPer; ++j) sum[j] = 0.f;
+    for (int j = 0; j < PER; ++j) sum[j] = 0.f;
     for (int w = w_first; w <= w_last; ++w) {
         const int slot = ((long long)w * a.steps_per_wg / a.ksteps == ti) ? 0 : 1;
-        const float* src = a.partial + ((size_t)w * 2 + slot) * PER_TILE + part8 * (PER_TILE / kFixParts);
+        const float* src = a.partial + ((size_t)w * 2 + slot) * PER_TILE + partk * (PER_TILE / PARTS);
 #pragma unroll
-        for (int j = 0; j < kFixPer; ++j) sum[j] += src[threadIdx.x + 256 * j];
+        for (int j = 0; j < PER; ++j) sum[j] += src[threadIdx.x + 256 * j];
     }
     float mx[2] = {-INFINITY, -INFINITY};
 #pragma unroll
-    for (int j = 0; j < kFixPer; ++j) {
-        const int rem = part8 * (PER_TILE / kFixParts) + threadIdx.x + 256 * j;
-        const int p = rem / (kTileRows * kTileCols);
-        const int r = (rem / kTileCols) % kTileRows, c = rem % kTileCols;
+    for (int j = 0; j < PER; ++j) {
+        const int rem = partk * (PER_TILE / PARTS) + threadIdx.x + 256 * j;
+        const int p = rem / (TR * kTileCols);
+        const int r = (rem / kTileCols) % TR, c = rem % kTileCols;
         const int row = t.row0 + r, col = t.col0 + c;
-        if (r < 16 * t.nrb && row < t.row_end && col < a.nx) {
+        if (r < 16 * t.nrb && row < t.row_end && c < t.ncol) {
             const float v = sum[j] * a.out_scale;
             a.heat[(size_t)p * a.nx * a.ny + (size_t)row * a.nx + col] = v;
             mx[p] = fmaxf(mx[p], v);
@@ -543,7 +796,17 @@ DecodePlan decode_plan(int precision, int ntiles, int halfp, int num_cus) {
     const int kb = precision == 0 ? 16 : 32;
     p.ksteps = halfp / kb;
     const long long total = (long long)ntiles * p.ksteps;
-    const int slots = (precision == 3 ? kDecodeOccupancy<3> : kDecodeOccupancy<0>) * num_cus;
+    const int occ = precision == 0 ? kDecodeOccupancy<0> : Wide<1>::OCC;
+    const int slots = occ * num_cus;
+    const long long rounds = (ntiles + slots - 1) / slots;
+    if (precision != 0 && ntiles >= slots && (double)ntiles >= 0.9 * (double)(rounds * slots)) {
+        // whole tiles per workgroup: every workgroup walks K from the start, in step with the
+        // others on its XCD, and no tile needs a fix-up (grid padded to a multiple of the XCDs)
+        p.steps_per_wg = p.ksteps;
+        p.grid = (ntiles + kXcds - 1) / kXcds * kXcds;
+        p.total_steps = total;
+        return p;
+    }
     long long L = (total + slots - 1) / slots;
     if (L < 4) L = 4;
     p.steps_per_wg = (int)L;
@@ -552,7 +815,11 @@ DecodePlan decode_plan(int precision, int ntiles, int halfp, int num_cus) {
     return p;
 }
 
-size_t decode_partial_floats(int grid) { return (size_t)grid * 2 * 2 * kTileRows * kTileCols; }
+size_t decode_partial_floats(int precision, const DecodePlan& p) {
+    if (p.steps_per_wg % p.ksteps == 0 && p.steps_per_wg >= p.ksteps) return 0;  // no split tile
+    const int tr = precision == 0 ? kTileRows : Wide<1>::TR;
+    return (size_t)p.grid * 2 * 2 * tr * kTileCols;
+}
 
 hipError_t launch_region_max(const float* heat, int nx, int ny, const RegionBox* boxes, int nboxes,
                              float* region_max, int nregions, float* hmax, hipStream_t s) {
@@ -586,13 +853,19 @@ hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
     profile_begin(kStageDecode, s);
     switch (precision) {
         case 0: hipLaunchKernelGGL(k_decode<0>, grid, block, 0, s, a); break;
-        case 1: hipLaunchKernelGGL(k_decode<1>, grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL(k_decode<2>, grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL(k_decode<3>, grid, block, 0, s, a); break;
+        case 1: hipLaunchKernelGGL(k_decode16<1>, grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_decode16<2>, grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL(k_decode16<3>, grid, block, 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
-    if (d.plan.steps_per_wg % d.plan.ksteps != 0 || d.plan.steps_per_wg < d.plan.ksteps)
-        hipLaunchKernelGGL(k_decode_fix, dim3((unsigned)d.ntiles * kFixParts), dim3(256), 0, s, a);
+    if (d.plan.steps_per_wg % d.plan.ksteps != 0 || d.plan.steps_per_wg < d.plan.ksteps) {
+        if (precision == 0)
+            hipLaunchKernelGGL(k_decode_fix<kTileRows>, dim3((unsigned)d.ntiles * Fix<kTileRows>::PARTS), dim3(256), 0, s, a);
+        else if (precision == 3)
+            hipLaunchKernelGGL(k_decode_fix<Wide<3>::TR>, dim3((unsigned)d.ntiles * Fix<Wide<3>::TR>::PARTS), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL(k_decode_fix<Wide<1>::TR>, dim3((unsigned)d.ntiles * Fix<Wide<1>::TR>::PARTS), dim3(256), 0, s, a);
+    }
     profile_end(kStageDecode, s);
     if (d.hmax_u) hipLaunchKernelGGL(k_hmax_final, dim3(1), dim3(64), 0, s, d.hmax_u, d.hmax);
     return hipGetLastError();

@@ -38,16 +38,21 @@ struct EChunk {
     int pad;
 };
 
-// One decode work tile: up to kDecodeRowBlocks blocks of 16 rows of one tile band (rows
-// whose cells share a tile row) by 64 consecutive grid columns, both classes.
-constexpr int kDecodeRowBlocks = 7;
+// One decode work tile: up to kDecodeSetRowBlocks[decode_tile_set(precision)] blocks of 16 rows
+// of one tile band (rows whose cells share a tile row) by 64 consecutive grid columns, both
+// classes.  Tile sets: 0 fp32 operands, 1 bf16 / fp16, 2 bf16 hi+lo.
+constexpr int kDecodeTileSets = 3;
+constexpr int kDecodeSetRowBlocks[kDecodeTileSets] = {7, 16, 16};
+inline int decode_tile_set(int precision) { return precision == 0 ? 0 : (precision == 3 ? 2 : 1); }
 struct DTile {
     int ty;           // tile row of the band
     int row0;         // first grid row of the block
     int row_end;      // one past the band's last row
-    int nrb;          // row blocks of 16 in this tile (1..kDecodeRowBlocks)
-    int col0;         // first grid column (multiple of 64)
-    int pad[3];
+    int nrb;          // row blocks of 16 in this tile (1..kDecodeSetRowBlocks of its set)
+    int col0;         // first grid column
+    int ncol;         // columns of this tile (1..64)
+    int tx0;          // tile column of its first column; 16-bit tiles span at most tx0, tx0 + 1
+    int pad;
 };
 
 // ---- error text shared by every entry point (map.hip) -------------------------------
@@ -114,7 +119,7 @@ struct DecodePlan {
     long long total_steps; // tiles * ksteps
 };
 DecodePlan decode_plan(int precision, int ntiles, int halfp, int num_cus);
-size_t decode_partial_floats(int grid);
+size_t decode_partial_floats(int precision, const DecodePlan& plan);  // 0 when no tile is split
 
 struct DecodeLaunch {
     const DTile* tiles;
@@ -129,7 +134,7 @@ struct DecodeLaunch {
     float* heat;
     unsigned* hmax_u;       // zeroed by launch_norm
     float* hmax;
-    float* partial;         // decode_partial_floats(plan.grid)
+    float* partial;         // decode_partial_floats(precision, plan) floats
     DecodePlan plan;
 };
 // Similarity GEMM over the tile list (precision: 0 fp32, 1 bf16, 2 fp16, 3 bf16 hi+lo).

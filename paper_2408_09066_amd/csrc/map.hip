@@ -129,13 +129,14 @@ struct GridKey {
 struct GridCache {
     int nx = 0, ny = 0;
     DevBuf<double> local_x, local_y;
-    DevBuf<DTile> tiles;
-    int ntiles = 0;
+    // work tiles of each tile set (decode_tile_set)
+    DevBuf<DTile> tiles[kDecodeTileSets];
+    int ntiles[kDecodeTileSets] = {};
+    std::vector<DTile> host_tiles[kDecodeTileSets];
     DevBuf<int> col_tx;              // [nx] tile column of every grid column
     DevBuf<float2> ex32, ey32;       // fp32 tables [n][halfp]
     DevBuf<uint16_t> ey_bf, ey_bf_lo, ey_h;  // 16-bit y tables [ny][2*halfp], built on first use
     // incremental decoding state
-    std::vector<DTile> host_tiles;
     std::vector<int> tcol;                   // tile column of every grid column
     std::vector<RegionBox> boxes;            // [tiles] cell range of every tile (row0 == row1: none)
     std::vector<unsigned> seen;              // memory versions at the last incremental decode
@@ -314,31 +315,54 @@ GridCache* grid_cache(vsaogm_map* m, const vsaogm_grid_desc* g, hipStream_t s) {
     gc->nx = g->nx;
     gc->ny = g->ny;
     // Work tiles: per tile band, its rows in blocks of 16 split evenly into groups of at most
-    // kDecodeRowBlocks blocks, times the grid's columns in slices of 64.
-    std::vector<DTile> tl;
-    for (int ty = 0; ty < m->tiles_y; ++ty) {
-        const int r0 = (int)(std::lower_bound(trow.begin(), trow.end(), ty) - trow.begin());
-        const int r1 = (int)(std::upper_bound(trow.begin(), trow.end(), ty) - trow.begin());
-        if (r0 >= r1) continue;
-        const int nblocks = (r1 - r0 + 15) / 16;
-        const int ngroups = (nblocks + kDecodeRowBlocks - 1) / kDecodeRowBlocks;
-        int b0 = 0;
-        for (int gi = 0; gi < ngroups; ++gi) {
-            const int nb = nblocks / ngroups + (gi < nblocks % ngroups ? 1 : 0);
-            for (int c = 0; c < g->nx; c += 64) {
+    // kDecodeSetRowBlocks blocks, times the grid's columns in slices of up to 64.
+    for (int set = 0; set < kDecodeTileSets; ++set) {
+        const int maxrb = kDecodeSetRowBlocks[set];
+        // column slices (the same for every band): 64 columns; for 16-bit operands cut short
+        // where a slice would reach a third tile column (its kernel stages two tiles' memories)
+        std::vector<std::pair<int, int>> slices;
+        for (int c = 0; c < g->nx;) {
+            int end = std::min(c + 64, g->nx);
+            if (set > 0 && tcol[end - 1] > tcol[c] + 1)
+                end = (int)(std::lower_bound(tcol.begin(), tcol.end(), tcol[c] + 2) - tcol.begin());
+            slices.emplace_back(c, end);
+            c = end;
+        }
+        std::vector<DTile> groups;  // row groups, columns unset
+        for (int ty = 0; ty < m->tiles_y; ++ty) {
+            const int r0 = (int)(std::lower_bound(trow.begin(), trow.end(), ty) - trow.begin());
+            const int r1 = (int)(std::upper_bound(trow.begin(), trow.end(), ty) - trow.begin());
+            if (r0 >= r1) continue;
+            const int nblocks = (r1 - r0 + 15) / 16;
+            const int ngroups = (nblocks + maxrb - 1) / maxrb;
+            int b0 = 0;
+            for (int gi = 0; gi < ngroups; ++gi) {
+                const int nb = nblocks / ngroups + (gi < nblocks % ngroups ? 1 : 0);
                 DTile d{};
                 d.ty = ty;
                 d.row0 = r0 + 16 * b0;
                 d.row_end = r1;
                 d.nrb = nb;
-                d.col0 = c;
-                tl.push_back(d);
+                groups.push_back(d);
+                b0 += nb;
             }
-            b0 += nb;
         }
+        // order: blocks of kBlockRows row groups x kBlockCols slices, so that the workgroups
+        // resident on one XCD at a time work on tiles that share rows and columns
+        constexpr int kBlockRows = 4, kBlockCols = 8;
+        std::vector<DTile>& tl = gc->host_tiles[set];
+        for (size_t gb = 0; gb < groups.size(); gb += kBlockRows)
+            for (size_t sb = 0; sb < slices.size(); sb += kBlockCols)
+                for (size_t gi = gb; gi < std::min(groups.size(), gb + kBlockRows); ++gi)
+                    for (size_t si = sb; si < std::min(slices.size(), sb + kBlockCols); ++si) {
+                        DTile d = groups[gi];
+                        d.col0 = slices[si].first;
+                        d.ncol = slices[si].second - slices[si].first;
+                        d.tx0 = tcol[d.col0];
+                        tl.push_back(d);
+                    }
+        gc->ntiles[set] = (int)tl.size();
     }
-    gc->ntiles = (int)tl.size();
-    gc->host_tiles = tl;
     gc->tcol = tcol;
     gc->boxes.resize((size_t)m->tiles_x * m->tiles_y);
     for (int ty = 0; ty < m->tiles_y; ++ty)
@@ -353,13 +377,16 @@ GridCache* grid_cache(vsaogm_map* m, const vsaogm_grid_desc* g, hipStream_t s) {
             gc->boxes[b.beta] = b;
         }
     gc->seen.assign(m->nkeys, 0u);
-    gc->tiles.alloc(tl.size(), "decode tile list");
+    for (int set = 0; set < kDecodeTileSets; ++set)
+        gc->tiles[set].alloc(gc->host_tiles[set].size(), "decode tile list");
     gc->col_tx.alloc(g->nx, "column tiles");
     gc->local_x.alloc(g->nx, "local x");
     gc->local_y.alloc(g->ny, "local y");
     gc->ex32.alloc((size_t)g->nx * m->halfp, "x location table");
-    hip_check(hipMemcpy(gc->tiles.p, tl.data(), tl.size() * sizeof(DTile), hipMemcpyHostToDevice),
-              "copy tile list");
+    for (int set = 0; set < kDecodeTileSets; ++set)
+        hip_check(hipMemcpy(gc->tiles[set].p, gc->host_tiles[set].data(),
+                            gc->host_tiles[set].size() * sizeof(DTile), hipMemcpyHostToDevice),
+                  "copy tile list");
     hip_check(hipMemcpy(gc->col_tx.p, tcol.data(), tcol.size() * sizeof(int), hipMemcpyHostToDevice),
               "copy column tiles");
     hip_check(hipMemcpy(gc->local_x.p, lx.data(), lx.size() * sizeof(double), hipMemcpyHostToDevice),
@@ -587,15 +614,16 @@ int vsaogm_decode(vsaogm_map* m, const vsaogm_grid_desc* g, int32_t precision, f
         GridCache* gc = grid_cache(m, g, s);
         const void* ey_lo = nullptr;
         const void* ey = y_table(m, gc, precision, &ey_lo, s);
+        const int set = decode_tile_set(precision);
         DecodeLaunch d;
-        d.plan = decode_plan(precision, gc->ntiles, m->halfp, m->num_cus);
-        const size_t need = decode_partial_floats(d.plan.grid);
+        d.plan = decode_plan(precision, gc->ntiles[set], m->halfp, m->num_cus);
+        const size_t need = decode_partial_floats(precision, d.plan);
         if (m->d_partial.n < need) m->d_partial.alloc_async(need, s, "decode partial sums");
         hip_check(launch_norm(m->d_omega.p, m->nkeys, m->half, m->halfp, m->D, m->d_scale.p,
                               m->d_omega_s.p, m->d_hmax_u.p, s),
                   "norm launch");
-        d.tiles = gc->tiles.p;
-        d.ntiles = gc->ntiles;
+        d.tiles = gc->tiles[set].p;
+        d.ntiles = gc->ntiles[set];
         d.col_tx = gc->col_tx.p;
         d.ex = gc->ex32.p;
         d.ey = ey;
@@ -646,15 +674,17 @@ int vsaogm_decode_incremental(vsaogm_map* m, const vsaogm_grid_desc* g, int32_t 
         std::vector<RegionBox>& bx = gc->inc_boxes_host;
         tl.clear();
         bx.clear();
-        for (const DTile& t : gc->host_tiles) {
-            const int tx0 = gc->tcol[t.col0], tx1 = gc->tcol[std::min(t.col0 + 63, g->nx - 1)];
+        const int set = decode_tile_set(precision);
+        for (const DTile& t : gc->host_tiles[set]) {
+            const int tx0 = gc->tcol[t.col0], tx1 = gc->tcol[t.col0 + t.ncol - 1];
             bool d = false;
             for (int tx = tx0; tx <= tx1 && !d; ++tx) d = dirty[t.ty * m->tiles_x + tx];
             if (d) tl.push_back(t);
         }
         for (int b = 0; b < nregions; ++b)
             if (dirty[b]) bx.push_back(gc->boxes[b]);
-        if (gc->inc_tiles.n < tl.size()) gc->inc_tiles.alloc_async(gc->host_tiles.size(), s, "incremental tiles");
+        if (gc->inc_tiles.n < tl.size())
+            gc->inc_tiles.alloc_async(gc->host_tiles[set].size(), s, "incremental tiles");
         if (gc->inc_boxes.n < bx.size()) gc->inc_boxes.alloc_async(nregions, s, "incremental regions");
         // the host vectors stay untouched until this stream passes the copies: the next
         // incremental decode of this grid synchronises the stream before refilling them
@@ -668,7 +698,7 @@ int vsaogm_decode_incremental(vsaogm_map* m, const vsaogm_grid_desc* g, int32_t 
         if (!tl.empty()) {
             DecodeLaunch d;
             d.plan = decode_plan(precision, (int)tl.size(), m->halfp, m->num_cus);
-            const size_t need = decode_partial_floats(d.plan.grid);
+            const size_t need = decode_partial_floats(precision, d.plan);
             if (m->d_partial.n < need) m->d_partial.alloc_async(need, s, "decode partial sums");
             hip_check(launch_norm(m->d_omega.p, m->nkeys, m->half, m->halfp, m->D, m->d_scale.p,
                                   m->d_omega_s.p, m->d_hmax_u.p, s),

@@ -179,7 +179,7 @@ int64_t footprint_of(const vsaogm_request& r, int32_t dim) {
     const int64_t inputs = n * 9;
     const int64_t outputs = cells * 13 + 8;
     const int64_t encode_ws = n * 20 + (n / 64 + 1024) * halfp * 8;
-    const int64_t decode_ws = 512 * 2 * 2 * 112 * 64 * 4;  // stream-K partial sums (upper bound)
+    const int64_t decode_ws = (int64_t)256 * 2 * 2 * 256 * 64 * 4;  // stream-K partial sums (upper bound)
     return inputs + outputs + encode_ws + decode_ws;
 }
 

@@ -1,0 +1,108 @@
+"""Precision variants of the similarity contraction against the FP64 oracle.
+
+(i) the single-scan room at every operand format, in full; (ii) the 40 m world decoded with
+one tile (an 800 x 800 x D=8192 contraction per class, local phases up to about 1 250 rad) at
+1 500 seeded cells.  For each format the test prints max-abs and relative-L2 error per
+heatmap, label agreement and the decode time relative to fp32, and holds fp32 and the bf16
+hi+lo split to the fp32 bar (relative L2 <= 1e-4); single-rounding bf16 / fp16 are held to the
+bounds their 8- / 11-bit mantissas allow.
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_09066_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+BAR = {"fp32": 1e-4, "bf16x3": 1e-4, "bf16": 2e-2, "fp16": 3e-3}
+PRECISIONS = ["fp32", "bf16x3", "bf16", "fp16"]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2408_09066_amd import native
+    native.load()
+    return torch
+
+
+def decode_ms(torch, m, w, precision, reps=5):
+    heat = torch.empty((2, w.ny, w.nx), dtype=torch.float32, device="cuda")
+    hmax = torch.empty(2, dtype=torch.float32, device="cuda")
+    m.decode(w.grid, w.nx, w.ny, precision, heat=heat, hmax=hmax)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        m.decode(w.grid, w.nx, w.ny, precision, heat=heat, hmax=hmax)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps, heat, hmax
+
+
+@functools.lru_cache(maxsize=None)
+def room_oracle():
+    w = synth.workload("toy_room")
+    return w, oracle.pipeline(w)
+
+
+def test_precision_room(torch_cuda):
+    from paper_2408_09066_amd import native
+    torch = torch_cuda
+    w, (om, P, mref, H, ogm, lab) = room_oracle()
+    m = native.Map(w.theta, w.layout, w.tiles)
+    m.encode(torch.from_numpy(w.xy).cuda(), torch.from_numpy(w.label).cuda())
+    say("\n[gpu] precision report, single-scan room (128 x 128, D = 1024)")
+    t32 = None
+    for prec in PRECISIONS:
+        ms, heat, hmax = decode_ms(torch, m, w, prec)
+        t32 = t32 or ms
+        _, lb = native.classify(heat, hmax, w.r_occ, w.r_emp, w.rho)
+        torch.cuda.synchronize()
+        h = heat.cpu().numpy().astype(np.float64)
+        errs = [(float(np.max(np.abs(h[p] - P[p]))), float(np.linalg.norm(h[p] - P[p]) / np.linalg.norm(P[p])))
+                for p in range(2)]
+        agree = float(np.mean(lb.cpu().numpy() == lab))
+        say(f"  {prec:7s} max-abs {max(e[0] for e in errs):.2e}  rel-L2 {max(e[1] for e in errs):.2e}  "
+            f"labels {agree * 100:.3f}%  decode {ms * 1e3:.1f} us ({t32 / ms:.2f}x fp32)")
+        assert max(e[1] for e in errs) <= BAR[prec]
+        if BAR[prec] <= 1e-4:
+            bad = lb.cpu().numpy() != lab
+            assert not bad.any() or np.max(np.abs(ogm[bad] - w.rho)) < 1e-3
+    m.close()
+
+
+def test_precision_one_tile_world(torch_cuda):
+    from paper_2408_09066_amd import native
+    torch = torch_cuda
+    w = synth.workload("world40_d1")
+    m = native.Map(w.theta, w.layout, w.tiles)
+    m.encode(torch.from_numpy(w.xy).cuda(), torch.from_numpy(w.label).cuda())
+    omega, bad = oracle.encode(w.theta, w.layout, w.tiles, w.xy, w.label)
+    assert bad == 0
+    rng = np.random.default_rng(np.random.SeedSequence([2408, 3, 2]))
+    cells = rng.choice(w.nx * w.ny, size=1500, replace=False)
+    P = oracle.similarity_cells(w.theta, w.layout, w.tiles, omega, w.grid, w.nx, cells)
+    say("\n[gpu] precision report, one-tile 40 m world (800 x 800, D = 8192), 1 500 cells")
+    t32 = None
+    for prec in PRECISIONS:
+        ms, heat, _ = decode_ms(torch, m, w, prec)
+        t32 = t32 or ms
+        h = heat.cpu().numpy().astype(np.float64).reshape(2, -1)[:, cells]
+        errs = [(float(np.max(np.abs(h[p] - P[p]))), float(np.linalg.norm(h[p] - P[p]) / np.linalg.norm(P[p])))
+                for p in range(2)]
+        flop = 4.0 * w.D * w.nx * w.ny
+        say(f"  {prec:7s} max-abs {max(e[0] for e in errs):.2e}  rel-L2 {max(e[1] for e in errs):.2e}  "
+            f"decode {ms * 1e3:.1f} us ({t32 / ms:.2f}x fp32, {flop / ms / 1e9:.0f} TFLOP/s useful)")
+        assert max(e[1] for e in errs) <= BAR[prec]
+    m.close()
