@@ -309,6 +309,10 @@ int vsaogm_server_drain(vsaogm_server* server);
 int vsaogm_server_stats(vsaogm_server* server, int64_t* completed, int64_t* peak_bytes,
                         int64_t* budget_bytes);
 
+/* Device bytes a request holds from admission to completion (what admission checks against
+   the budget).  ENOTFOUND for an unknown map. */
+int vsaogm_request_bytes(vsaogm_server* server, const vsaogm_request* req, int64_t* bytes);
+
 /*
  * Profiling hook: record the given HIP events (hipEvent_t) immediately before and
  * after every launch of one stage's main kernel, on the stream it is launched on:

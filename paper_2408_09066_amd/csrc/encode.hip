@@ -115,29 +115,39 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int* __restrict__ hist, i
     __shared__ int sh_w[kScanThreads / 64];
     extern __shared__ int key_start[];   // [nkeys]
     const int64_t N = (int64_t)nkeys * nchunks;
-    constexpr int V = 4;
+    // coalesced passes of kScanThreads * V entries; the next pass's loads are issued before
+    // the current pass is scanned
+    constexpr int V = 16;
+    constexpr int64_t PASS = (int64_t)kScanThreads * V;
     int carry = 0;
-    for (int64_t base = 0; base < N; base += (int64_t)kScanThreads * V) {
+    int nxt[V];
+    auto load_pass = [&](int64_t base) {
         const int64_t j0 = base + (int64_t)threadIdx.x * V;
+#pragma unroll
+        for (int u = 0; u < V; ++u) nxt[u] = (j0 + u < N) ? hist[j0 + u] : 0;
+    };
+    load_pass(0);
+    for (int64_t base = 0; base < N; base += PASS) {
         int v[V];
         int sum = 0;
 #pragma unroll
         for (int u = 0; u < V; ++u) {
-            v[u] = (j0 + u < N) ? hist[j0 + u] : 0;
+            v[u] = nxt[u];
             sum += v[u];
         }
+        if (base + PASS < N) load_pass(base + PASS);
         int total;
         int run = carry + block_scan_excl(sum, sh_w, &total);
+        const int64_t j0 = base + (int64_t)threadIdx.x * V;
 #pragma unroll
         for (int u = 0; u < V; ++u) {
-            if (j0 + u < N) {
-                hist[j0 + u] = run;
-                if ((j0 + u) % nchunks == 0) key_start[(j0 + u) / nchunks] = run;
-            }
+            if (j0 + u < N) hist[j0 + u] = run;
             run += v[u];
         }
         carry += total;
     }
+    __syncthreads();  // the bases written above are visible to the whole block
+    for (int k = threadIdx.x; k < nkeys; k += kScanThreads) key_start[k] = hist[(int64_t)k * nchunks];
     __syncthreads();
     const int n_valid = carry;
     // per-key counts and work items (keys in slices of kScanThreads, scanned in order)
@@ -238,6 +248,7 @@ __global__ __launch_bounds__(kEncodeThreads) void k_encode(
 
     // Largest phase (revolutions) any bin can reach on this work item's points.
     __shared__ float sh_max[kEncodeThreads / 64];
+    __shared__ float4 sh_pair[kEncodeChunk / 2];
     float bound = 0.f;
     for (int q = threadIdx.x; q < e.len; q += kEncodeThreads) {
         float2 v = p[q];
@@ -263,12 +274,18 @@ __global__ __launch_bounds__(kEncodeThreads) void k_encode(
             ax[j] = t.x;
             ay[j] = t.y;
         }
+        // pair mid-points and half-differences, formed once per pair for all bins
         const int npairs = e.len >> 1;
+        for (int q = threadIdx.x; q < npairs; q += kEncodeThreads) {
+            const float2 a = p[2 * q], b = p[2 * q + 1];
+            sh_pair[q] = make_float4(0.5f * (a.x + b.x), 0.5f * (a.y + b.y), 0.5f * (a.x - b.x),
+                                     0.5f * (a.y - b.y));
+        }
+        __syncthreads();
+#pragma unroll 2
         for (int q = 0; q < npairs; ++q) {
-            const float2 a = p[2 * q];
-            const float2 b = p[2 * q + 1];
-            const float mx = 0.5f * (a.x + b.x), my = 0.5f * (a.y + b.y);
-            const float dx = 0.5f * (a.x - b.x), dy = 0.5f * (a.y - b.y);
+            const float4 pq = sh_pair[q];
+            const float mx = pq.x, my = pq.y, dx = pq.z, dy = pq.w;
 #pragma unroll
             for (int j = 0; j < BPT; ++j) {
                 const float tm = __builtin_fmaf(ax[j], mx, ay[j] * my);

@@ -593,4 +593,12 @@ int vsaogm_server_stats(vsaogm_server* s, int64_t* completed, int64_t* peak_byte
     return VSAOGM_OK;
 }
 
+int vsaogm_request_bytes(vsaogm_server* s, const vsaogm_request* r, int64_t* bytes) {
+    if (!s || !r || !bytes) return VSAOGM_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (r->map_id < 0 || r->map_id >= (int32_t)s->maps.size()) return VSAOGM_ENOTFOUND;
+    *bytes = footprint_of(*r, s->map_dim[r->map_id]);
+    return VSAOGM_OK;
+}
+
 }  // extern "C"

@@ -25,7 +25,7 @@ EXPORTED = [
     "vsaogm_profile_events", "vsaogm_server_create", "vsaogm_server_destroy",
     "vsaogm_server_add_map", "vsaogm_server_get_map", "vsaogm_submit", "vsaogm_poll",
     "vsaogm_wait", "vsaogm_server_drain", "vsaogm_server_stats", "vsaogm_submit_many",
-    "vsaogm_classify_ex", "vsaogm_decode_incremental",
+    "vsaogm_classify_ex", "vsaogm_decode_incremental", "vsaogm_request_bytes",
 ]
 ACTIVATIONS = {"entropy": 0, "relu": 1, "tanh": 2, "sigmoid": 3}
 
@@ -110,6 +110,7 @@ def load(path: str = LIB_PATH):
     L.vsaogm_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
     L.vsaogm_server_drain.argtypes = [P]
     L.vsaogm_server_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.vsaogm_request_bytes.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(i64)]
     for name in EXPORTED:
         if name not in ("vsaogm_version", "vsaogm_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -402,6 +403,14 @@ class Server:
 
     def drain(self):
         check(load().vsaogm_server_drain(self._h))
+
+    def request_bytes(self, map_id: int, n_points: int, grid, nx: int, ny: int) -> int:
+        """Device bytes admission reserves for such a request."""
+        req = Request(int(map_id), None, None, int(n_points), grid_desc(grid, nx, ny), 0, 0, 0, 0.0,
+                      None, None, None, 0)
+        b = ctypes.c_int64()
+        check(load().vsaogm_request_bytes(self._h, ctypes.byref(req), ctypes.byref(b)))
+        return int(b.value)
 
     def stats(self):
         c, p, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()

@@ -111,9 +111,11 @@ def test_tight_budget_still_completes(torch_cuda, stream):
     say("[gpu] tight budget")
     maps, reqs = stream
     from paper_2408_09066_amd import native
-    big = max(q.xy.shape[0] for q in reqs)
-    side = max(m.side for m in maps)
-    budget = big * 29 + side * side * 13 + 8 + 512 * 2 * 2 * 112 * 64 * 4 + (big // 64 + 1024) * 1024 * 8 + 4096
+    probe = native.Server(max_inflight=1)
+    ids = [probe.add_map(m.theta, m.layout, m.tiles) for m in maps]
+    budget = max(probe.request_bytes(ids[q.map_id], q.xy.shape[0], maps[q.map_id].grid, maps[q.map_id].side,
+                                     maps[q.map_id].side) for q in reqs[:12]) + 4096
+    probe.close()
     res, st = served(maps, reqs[:12], "fp32", max_inflight=4, budget=budget)
     assert st["completed"] == 12
     assert st["peak_bytes"] <= budget
@@ -140,7 +142,7 @@ def test_served_update_matches_oracle(torch_cuda):
 def test_server_errors(torch_cuda):
     say("[gpu] server errors")
     from paper_2408_09066_amd import native
-    srv = native.Server(max_inflight=1, hbm_budget_bytes=64 << 20)
+    srv = native.Server(max_inflight=1, hbm_budget_bytes=128 << 20)
     w = synth.workload("toy_room")
     mid = srv.add_map(w.theta, w.layout, w.tiles)
     with pytest.raises(native.VsaogmError) as e:
