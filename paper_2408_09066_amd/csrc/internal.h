@@ -13,7 +13,7 @@ constexpr int kMaxKeys = 2 * kMaxTilesPerAxis * kMaxTilesPerAxis;  // 8192 memor
 constexpr int kAssignChunk = 1024;   // points per histogram / stable-scatter chunk
 constexpr int kEncodeChunk = 1024;   // points per encode work item (even, so pairs never straddle)
 constexpr int kEncodeThreads = 256;
-constexpr int kEncodeBpt = 8;        // spectrum bins per encode thread
+constexpr int kEncodeBpt = 4;        // spectrum bins per encode thread
 constexpr int kBinPad = 64;          // stored half spectra are padded to a multiple of this
 constexpr int kMaxRadius = 24;       // largest disk radius of the entropy filter
 // A phase bound (revolutions) above which a chunk is encoded with double-precision
