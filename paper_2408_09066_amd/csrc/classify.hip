@@ -15,6 +15,36 @@ namespace {
 
 constexpr int TX = 64, TY = 16;
 
+// Disk sum around the LDS element at `centre` (row pitch W) for a radius known at compile
+// time: straight-line reads at constant offsets within each row.
+template <int R>
+__device__ inline float disk_sum(const float* centre, int W) {
+    float s = 0.f;
+#pragma unroll
+    for (int dy = -R; dy <= R; ++dy) {
+        const float* row = centre + dy * W;
+#pragma unroll
+        for (int dx = -R; dx <= R; ++dx)
+            if (dx * dx + dy * dy <= R * R) s += row[dx];
+    }
+    return s;
+}
+
+// Radii up to kFastRadius use the unrolled sums; larger ones the table-driven loop.
+constexpr int kFastRadius = 6;
+
+__device__ inline float disk_sum_fast(int r, const float* centre, int W) {
+    switch (r) {
+        case 0: return disk_sum<0>(centre, W);
+        case 1: return disk_sum<1>(centre, W);
+        case 2: return disk_sum<2>(centre, W);
+        case 3: return disk_sum<3>(centre, W);
+        case 4: return disk_sum<4>(centre, W);
+        case 5: return disk_sum<5>(centre, W);
+        default: return disk_sum<6>(centre, W);
+    }
+}
+
 // Pre-softmax value of one cell of one class (decoding of Sec. III-B and its ablation of
 // Sec. IV-B): q = P (/ max P if normalising) (squared if squaring), then -q ln q (entropy, to be
 // summed over the disk; 0 for q <= 0) or the per-cell activation ReLU / tanh / sigmoid.
@@ -23,7 +53,7 @@ __device__ inline float cell_value(float p, float m, int normalize, int square, 
     if (normalize) q = (m > 0.f) ? p / m : 0.f;
     if (square) q = q * q;
     switch (act) {
-        case 0: return (q > 0.f) ? -q * logf(q) : 0.f;
+        case 0: return (q > 0.f) ? -q * __logf(q) : 0.f;
         case 1: return fmaxf(q, 0.f);
         case 2: return tanhf(q);
         default: return 1.f / (1.f + expf(-q));
@@ -76,10 +106,14 @@ __global__ __launch_bounds__(256) void k_classify(const float* __restrict__ heat
             const int r = p ? r_occ : r_emp;
             const float* base = sg + p * W * H;
             float s = 0.f;
-            for (int dy = -r; dy <= r; ++dy) {
-                const int w = half_w[p][dy + kMaxRadius];
-                const float* row = base + (cy + R + dy) * W + (cx + R);
-                for (int dx = -w; dx <= w; ++dx) s += row[dx];
+            if (r <= kFastRadius) {
+                s = disk_sum_fast(r, base + (cy + R) * W + (cx + R), W);
+            } else {
+                for (int dy = -r; dy <= r; ++dy) {
+                    const int w = half_w[p][dy + kMaxRadius];
+                    const float* row = base + (cy + R + dy) * W + (cx + R);
+                    for (int dx = -w; dx <= w; ++dx) s += row[dx];
+                }
             }
             h[p] = s;
         }

@@ -693,11 +693,28 @@ __global__ __launch_bounds__(256) void k_decode_fix(DecodeArgs a) {
     float sum[PER];
 #pragma unroll
     for (int j = 0; j < PER; ++j) sum[j] = 0.f;
-    for (int w = w_first; w <= w_last; ++w) {
+    // segments in workgroup order, two at a time so that both segments' loads are in flight
+    auto seg = [&](int w) {
         const int slot = ((long long)w * a.steps_per_wg / a.ksteps == ti) ? 0 : 1;
-        const float* src = a.partial + ((size_t)w * 2 + slot) * PER_TILE + partk * (PER_TILE / PARTS);
+        return a.partial + ((size_t)w * 2 + slot) * PER_TILE + partk * (PER_TILE / PARTS);
+    };
+    int w = w_first;
+    for (; w + 1 <= w_last; w += 2) {
+        const float* s0 = seg(w);
+        const float* s1 = seg(w + 1);
+        float v0[PER], v1[PER];
 #pragma unroll
-        for (int j = 0; j < PER; ++j) sum[j] += src[threadIdx.x + 256 * j];
+        for (int j = 0; j < PER; ++j) {
+            v0[j] = s0[threadIdx.x + 256 * j];
+            v1[j] = s1[threadIdx.x + 256 * j];
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) sum[j] = (sum[j] + v0[j]) + v1[j];
+    }
+    if (w <= w_last) {
+        const float* s0 = seg(w);
+#pragma unroll
+        for (int j = 0; j < PER; ++j) sum[j] += s0[threadIdx.x + 256 * j];
     }
     float mx[2] = {-INFINITY, -INFINITY};
 #pragma unroll

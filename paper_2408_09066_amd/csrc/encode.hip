@@ -12,7 +12,7 @@
 //   k_assign   nearest tile (exact double-precision argmin, lowest index on ties), key,
 //              label check, per-chunk key histogram
 //   k_scan     per-key totals and exclusive bases, encode work table
-//   k_scatter  stable counting sort of the local coordinates by key (one wavefront per chunk)
+//   k_scatter  stable counting sort of the local coordinates by key (four wavefronts per chunk)
 //   k_encode   per (work item, block of bins): sum of exp(2*pi*i*t) with t in revolutions,
 //              hardware v_sin/v_cos, two points per step:
 //                exp(i a) + exp(i b) = 2 cos((a-b)/2) exp(i (a+b)/2)
@@ -115,34 +115,34 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int* __restrict__ hist, i
     __shared__ int sh_w[kScanThreads / 64];
     extern __shared__ int key_start[];   // [nkeys]
     const int64_t N = (int64_t)nkeys * nchunks;
-    // coalesced passes of kScanThreads * V entries; the next pass's loads are issued before
-    // the current pass is scanned
-    constexpr int V = 16;
-    constexpr int64_t PASS = (int64_t)kScanThreads * V;
+    // coalesced passes of kScanThreads * 4 entries (one aligned group of four per thread; the
+    // histogram buffer is padded so the last group stays in bounds); the next pass's group is
+    // loaded before the current pass is scanned
+    constexpr int64_t PASS = (int64_t)kScanThreads * 4;
     int carry = 0;
-    int nxt[V];
-    auto load_pass = [&](int64_t base) {
-        const int64_t j0 = base + (int64_t)threadIdx.x * V;
-#pragma unroll
-        for (int u = 0; u < V; ++u) nxt[u] = (j0 + u < N) ? hist[j0 + u] : 0;
-    };
-    load_pass(0);
+    typedef int i32x4 __attribute__((ext_vector_type(4)));
+    i32x4 nxt = *reinterpret_cast<const i32x4*>(hist + min((int64_t)threadIdx.x * 4, N - 1) / 4 * 4);
     for (int64_t base = 0; base < N; base += PASS) {
-        int v[V];
-        int sum = 0;
+        const int64_t j0 = base + (int64_t)threadIdx.x * 4;
+        i32x4 v = nxt;
 #pragma unroll
-        for (int u = 0; u < V; ++u) {
-            v[u] = nxt[u];
-            sum += v[u];
-        }
-        if (base + PASS < N) load_pass(base + PASS);
+        for (int u = 0; u < 4; ++u)
+            if (j0 + u >= N) v[u] = 0;
+        if (base + PASS < N) nxt = *reinterpret_cast<const i32x4*>(hist + min(j0 + PASS, N - 1) / 4 * 4);
         int total;
-        int run = carry + block_scan_excl(sum, sh_w, &total);
-        const int64_t j0 = base + (int64_t)threadIdx.x * V;
+        int run = carry + block_scan_excl(v[0] + v[1] + v[2] + v[3], sh_w, &total);
+        i32x4 out;
 #pragma unroll
-        for (int u = 0; u < V; ++u) {
-            if (j0 + u < N) hist[j0 + u] = run;
+        for (int u = 0; u < 4; ++u) {
+            out[u] = run;
             run += v[u];
+        }
+        if (j0 + 3 < N) {
+            *reinterpret_cast<i32x4*>(hist + j0) = out;
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (j0 + u < N) hist[j0 + u] = out[u];
         }
         carry += total;
     }
@@ -182,28 +182,47 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int* __restrict__ hist, i
     if (threadIdx.x == 0) meta[0] = ec_carry;
 }
 
-// Stable counting-sort scatter: one wavefront per chunk of kAssignChunk points, in order.
-// A point's slot is its key's running base plus the number of earlier lanes of the same
+// Stable counting-sort scatter: one block of WAVES wavefronts per chunk of kAssignChunk points,
+// wave w taking the chunk's w-th part in order (four waves; one when the per-wave key tables
+// would not fit the LDS of a workgroup).  The waves' key counts give each wave its
+// own running base per key (the chunk's base plus the counts of the earlier quarters); within a
+// wave, a point's slot is its key's running base plus the number of earlier lanes of the same
 // round with the same key (lanes are matched bit by bit with ballots).
-__global__ __launch_bounds__(64) void k_scatter(const float2* __restrict__ xy,
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_scatter(const float2* __restrict__ xy,
                                                 const int* __restrict__ key, int64_t n,
                                                 LayoutDev L, int nkeys, int nchunks, int key_bits,
                                                 const int* __restrict__ base,
                                                 float2* __restrict__ sorted,
                                                 float2* __restrict__ sorted_lo) {
-    extern __shared__ int run[];
-    constexpr int R = kAssignChunk / 64;
-    const int lane = threadIdx.x;
-    const int64_t c0 = (int64_t)blockIdx.x * kAssignChunk;
+    extern __shared__ int run[];  // [WAVES][nkeys]
+    constexpr int Q = kAssignChunk / WAVES;           // points per wave
+    constexpr int R = Q / 64;                         // rounds per wave
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t q0 = (int64_t)blockIdx.x * kAssignChunk + (int64_t)wave * Q;
     int kk[R];
     float2 pp[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int64_t i = c0 + r * 64 + lane;
+        const int64_t i = q0 + r * 64 + lane;
         kk[r] = (i < n) ? key[i] : -1;
         pp[r] = (i < n) ? xy[i] : make_float2(0.f, 0.f);
     }
-    for (int k = lane; k < nkeys; k += 64) run[k] = base[(size_t)k * nchunks + blockIdx.x];
+    for (int k = threadIdx.x; k < WAVES * nkeys; k += blockDim.x) run[k] = 0;
+    __syncthreads();
+    int* my = run + wave * nkeys;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (kk[r] >= 0) atomicAdd(&my[kk[r]], 1);
+    __syncthreads();
+    for (int k = threadIdx.x; k < nkeys; k += blockDim.x) {  // counts -> per-wave bases
+        int acc = base[(size_t)k * nchunks + blockIdx.x];
+        for (int w = 0; w < WAVES; ++w) {
+            const int c = run[w * nkeys + k];
+            run[w * nkeys + k] = acc;
+            acc += c;
+        }
+    }
     __syncthreads();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
@@ -218,7 +237,7 @@ __global__ __launch_bounds__(64) void k_scatter(const float2* __restrict__ xy,
         }
         if (k >= 0) {
             const int rank = __popcll(same & lt_mask);
-            const int dest = run[k] + rank;
+            const int dest = my[k] + rank;
             const int beta = k >> 1;
             const int tx = beta % L.tiles_x, ty = beta / L.tiles_x;
             const double lx = (double)pp[r].x - L.cx[tx];
@@ -226,7 +245,7 @@ __global__ __launch_bounds__(64) void k_scatter(const float2* __restrict__ xy,
             const float fx = (float)lx, fy = (float)ly;
             sorted[dest] = make_float2(fx, fy);
             sorted_lo[dest] = make_float2((float)(lx - (double)fx), (float)(ly - (double)fy));
-            if ((same & lt_mask) == 0) run[k] += __popcll(same);
+            if ((same & lt_mask) == 0) my[k] += __popcll(same);
         }
         __syncthreads();
     }
@@ -481,8 +500,12 @@ hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const
                        label, n, L, nkeys, p.nchunks, w.key, w.hist, w.n_bad);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), nkeys * sizeof(int), s, w.hist, p.nchunks, nkeys,
                        p.echunk, w.table, w.meta, w.version);
-    hipLaunchKernelGGL(k_scatter, dim3(p.nchunks), dim3(64), nkeys * sizeof(int), s, xy2, w.key,
-                       n, L, nkeys, p.nchunks, bits_for(nkeys), w.hist, w.sorted, w.sorted_lo);
+    if (4 * nkeys * (int)sizeof(int) <= 65536)
+        hipLaunchKernelGGL(k_scatter<4>, dim3(p.nchunks), dim3(256), 4 * nkeys * sizeof(int), s, xy2, w.key,
+                           n, L, nkeys, p.nchunks, bits_for(nkeys), w.hist, w.sorted, w.sorted_lo);
+    else
+        hipLaunchKernelGGL(k_scatter<1>, dim3(p.nchunks), dim3(64), nkeys * sizeof(int), s, xy2, w.key,
+                           n, L, nkeys, p.nchunks, bits_for(nkeys), w.hist, w.sorted, w.sorted_lo);
     const double2* rev_d = reinterpret_cast<const double2*>(theta_rev_d);
     const dim3 eg(p.max_echunks, p.binblocks);
     profile_begin(kStageEncode, s);

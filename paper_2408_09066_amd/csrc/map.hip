@@ -254,7 +254,8 @@ void ensure_encode_workspace(vsaogm_map* m, int64_t n, hipStream_t s) {
     m->w_key.alloc_async(cap, s, "encode keys");
     m->w_sorted.alloc_async(cap, s, "encode sorted");
     m->w_sorted_lo.alloc_async(cap, s, "encode sorted residuals");
-    m->w_hist.alloc_async((size_t)chunks * m->nkeys, s, "encode histogram");
+    // + 4: the scan reads the histogram in aligned groups of four
+    m->w_hist.alloc_async((size_t)chunks * m->nkeys + 4, s, "encode histogram");
     m->w_table.alloc_async(echunks, s, "encode table");
     m->w_partial.alloc_async((size_t)echunks * m->halfp, s, "encode partial spectra");
     if (!m->w_meta.p) m->w_meta.alloc_async(1 + 3 * (size_t)m->nkeys, s, "encode meta");
