@@ -215,6 +215,22 @@ def serving_benchmark(n_requests: int = 256, slots: int = 8, precision: str = "b
     }
 
 
+def heldout_accuracy(w, precision):
+    """AUC / NLL of the held-out 20 % of the points under a map of the other 80 % (untimed)."""
+    import torch
+    from paper_2408_09066_amd import metrics, native
+    tr, te = metrics.split_points(w.n, 0.8, np.random.default_rng(np.random.SeedSequence([2408, 2, 6])))
+    m = native.Map(w.theta, w.layout, w.tiles)
+    m.encode(torch.from_numpy(np.ascontiguousarray(w.xy[tr])).cuda(),
+             torch.from_numpy(np.ascontiguousarray(w.label[tr])).cuda())
+    heat, hmax = m.decode(w.grid, w.nx, w.ny, precision)
+    ogm, _ = native.classify(heat, hmax, w.r_occ, w.r_emp, w.rho)
+    r = metrics.evaluate(ogm.cpu().numpy(), w.grid, w.xy[te], w.label[te])
+    m.close()
+    r["split"] = "80/20 of the labelled points"
+    return r
+
+
 def stress_generate(n_updates: int, workers: int):
     """The large-map scenario and its first n_updates updates (host arrays), made before any
     GPU use: generation forks worker processes."""
@@ -441,6 +457,7 @@ def main() -> int:
         "roofline": roof,
     }
     m.close()
+    result["accuracy"] = heldout_accuracy(w, args.precision)
     if args.serving:
         result["serving"] = serving_benchmark()
     if stress_in is not None:
