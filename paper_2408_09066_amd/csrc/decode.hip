@@ -693,28 +693,25 @@ __global__ __launch_bounds__(256) void k_decode_fix(DecodeArgs a) {
     float sum[PER];
 #pragma unroll
     for (int j = 0; j < PER; ++j) sum[j] = 0.f;
-    // segments in workgroup order, two at a time so that both segments' loads are in flight
+    // segments in workgroup order, four at a time so that their loads are in flight together
+    // (a segment past the last one reloads the last and adds nothing)
     auto seg = [&](int w) {
         const int slot = ((long long)w * a.steps_per_wg / a.ksteps == ti) ? 0 : 1;
         return a.partial + ((size_t)w * 2 + slot) * PER_TILE + partk * (PER_TILE / PARTS);
     };
-    int w = w_first;
-    for (; w + 1 <= w_last; w += 2) {
-        const float* s0 = seg(w);
-        const float* s1 = seg(w + 1);
-        float v0[PER], v1[PER];
+    for (int w = w_first; w <= w_last; w += 4) {
+        float v[4][PER];
 #pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            v0[j] = s0[threadIdx.x + 256 * j];
-            v1[j] = s1[threadIdx.x + 256 * j];
+        for (int q = 0; q < 4; ++q) {
+            const float* src = seg(min(w + q, w_last));
+#pragma unroll
+            for (int j = 0; j < PER; ++j) v[q][j] = src[threadIdx.x + 256 * j];
         }
 #pragma unroll
-        for (int j = 0; j < PER; ++j) sum[j] = (sum[j] + v0[j]) + v1[j];
-    }
-    if (w <= w_last) {
-        const float* s0 = seg(w);
+        for (int q = 0; q < 4; ++q)
+            if (w + q <= w_last)
 #pragma unroll
-        for (int j = 0; j < PER; ++j) sum[j] += s0[threadIdx.x + 256 * j];
+                for (int j = 0; j < PER; ++j) sum[j] += v[q][j];
     }
     float mx[2] = {-INFINITY, -INFINITY};
 #pragma unroll

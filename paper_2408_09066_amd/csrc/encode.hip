@@ -394,7 +394,8 @@ __global__ __launch_bounds__(256) void k_reduce(const float2* __restrict__ parti
 // scale[key] = 1 / ||w|| with ||w||^2 = (2/D) sum_{k < D/2} |Omega_k|^2 (Parseval over the
 // conjugate-symmetric spectrum; bins 0 and D/2 both equal the point count), 0 for an empty
 // memory (eq. vector-normalization); omega_s[key] = conj(Omega[key]) * scale[key].
-__global__ __launch_bounds__(256) void k_norm(const float2* __restrict__ omega, int half,
+constexpr int kNormThreads = 1024;
+__global__ __launch_bounds__(kNormThreads) void k_norm(const float2* __restrict__ omega, int half,
                                               int halfp, int D, float* __restrict__ scale,
                                               float2* __restrict__ omega_s,
                                               unsigned* __restrict__ hmax_u) {
@@ -404,17 +405,18 @@ __global__ __launch_bounds__(256) void k_norm(const float2* __restrict__ omega, 
     if (key == 0 && threadIdx.x < 3) hmax_u[threadIdx.x] = 0u;
     const float2* w = omega + (size_t)key * halfp;
     double s = 0.0;
-    for (int k = threadIdx.x; k < half; k += 256) {
+    for (int k = threadIdx.x; k < half; k += kNormThreads) {
         double re = w[k].x, im = w[k].y;
         s += re * re + im * im;
     }
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    __shared__ double sh[4];
+    __shared__ double sh[kNormThreads / 64];
     __shared__ float sh_inv;
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double t = sh[0] + sh[1] + sh[2] + sh[3];
+        double t = 0.0;
+        for (int i = 0; i < kNormThreads / 64; ++i) t += sh[i];
         double nrm = sqrt(2.0 * t / (double)D);
         const float inv = (nrm > 0.0) ? (float)(1.0 / nrm) : 0.f;
         scale[key] = inv;
@@ -424,7 +426,7 @@ __global__ __launch_bounds__(256) void k_norm(const float2* __restrict__ omega, 
     // conj(Omega) / ||w|| for the similarity GEMM (padding bins stay zero)
     const float inv = sh_inv;
     float2* o = omega_s + (size_t)key * halfp;
-    for (int k = threadIdx.x; k < halfp; k += 256) o[k] = make_float2(w[k].x * inv, -w[k].y * inv);
+    for (int k = threadIdx.x; k < halfp; k += kNormThreads) o[k] = make_float2(w[k].x * inv, -w[k].y * inv);
 }
 
 // Paper-frame export: out[key][k] = exp(i*Theta[k].mu_beta) * Omega_local[key][k] for
@@ -539,7 +541,7 @@ hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const
 
 hipError_t launch_norm(const float2* omega, int nkeys, int half, int halfp, int D, float* scale,
                        float2* omega_s, unsigned* hmax_u, hipStream_t s) {
-    hipLaunchKernelGGL(k_norm, dim3(nkeys), dim3(256), 0, s, omega, half, halfp, D, scale, omega_s,
+    hipLaunchKernelGGL(k_norm, dim3(nkeys), dim3(kNormThreads), 0, s, omega, half, halfp, D, scale, omega_s,
                        hmax_u);
     return hipGetLastError();
 }

@@ -107,6 +107,13 @@ __global__ void k_zero_words(unsigned* p, size_t n) {
     if (i < n) p[i] = 0u;
 }
 
+// Reset of a map in one launch: zero the memories and bump every memory's version.
+__global__ void k_reset_map(unsigned* words, size_t n, unsigned* version, int nkeys) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) words[i] = 0u;
+    if (i < (size_t)nkeys) version[i] += 1u;
+}
+
 void zero_async(void* p, size_t bytes, hipStream_t s) {
     size_t words = bytes / 4;
     if (words == 0) return;
@@ -557,8 +564,11 @@ int vsaogm_map_reset(vsaogm_map* m, vsaogm_stream stream) {
     return guarded([&] {
         if (!m) fail(VSAOGM_EINVAL, "map is NULL");
         DeviceGuard guard(m->device);
-        zero_async(m->d_omega.p, m->d_omega.n * sizeof(float2), (hipStream_t)stream);
-        hip_check(launch_bump_versions(m->d_version.p, m->nkeys, (hipStream_t)stream), "versions");
+        const size_t words = m->d_omega.n * 2;
+        const size_t n = std::max(words, (size_t)m->nkeys);
+        hipLaunchKernelGGL(k_reset_map, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                           reinterpret_cast<unsigned*>(m->d_omega.p), words, m->d_version.p, m->nkeys);
+        hip_check(hipGetLastError(), "reset kernel");
     });
 }
 
