@@ -57,6 +57,16 @@ def lib():
         L.vo_fuse.argtypes = [i32, i64, i32, P, P, P, P]
         L.vo_postprocess_ex.argtypes = [P, i32, i32, i32, i32, f64, i32, i32, i32, P, P, P, P]
         L.vo_num_threads.restype = i32
+        L.vo3_tile_center.argtypes = [P, P, i32, P, P, P]
+        L.vo3_assign_tile.argtypes = [P, P, f64, f64, f64]
+        L.vo3_assign_tile.restype = i32
+        L.vo3_assign_tiles.argtypes = [P, P, P, i64, P]
+        L.vo3_encode.argtypes = [i32, P, P, P, P, P, i64, P]
+        L.vo3_encode.restype = i64
+        L.vo3_similarity_cells.argtypes = [i32, P, P, P, P, P, i32, i32, P, i64, P]
+        L.vo3_ball_count.argtypes = [i32]
+        L.vo3_ball_count.restype = i64
+        L.vo3_postprocess.argtypes = [P, i32, i32, i32, i32, i32, f64, P, P, P, P]
         _lib = L
     return _lib
 
@@ -218,4 +228,83 @@ def pipeline(w, P_only: bool = False):
     if P_only:
         return omega, P
     m, H, ogm, lab = postprocess(P, w.r_occ, w.r_emp, w.rho)
+    return omega, P, m, H, ogm, lab
+
+
+# ---- three dimensions (the 3-D extension: Sec. III with a third axis) -----------------
+
+def num_memories3(tiles) -> int:
+    return 2 * int(tiles[0]) * int(tiles[1]) * int(tiles[2])
+
+
+def tile_center3(layout, tiles, beta: int):
+    lay, t = _lay(layout, tiles)
+    out = [ctypes.c_double(), ctypes.c_double(), ctypes.c_double()]
+    lib().vo3_tile_center(_p(lay), _p(t), int(beta), *[ctypes.byref(o) for o in out])
+    return tuple(o.value for o in out)
+
+
+def assign_tiles3(layout, tiles, xyz: np.ndarray) -> np.ndarray:
+    lay, t = _lay(layout, tiles)
+    pts = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    out = np.empty(pts.shape[0], dtype=np.int32)
+    lib().vo3_assign_tiles(_p(lay), _p(t), _p(pts), pts.shape[0], _p(out))
+    return out
+
+
+def encode3(theta: np.ndarray, layout, tiles, xyz: np.ndarray, label: np.ndarray,
+            omega: Optional[np.ndarray] = None):
+    """Algorithm 1 in 3-D: memories float64 [2R][D][2] (accumulated into omega if given)."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    D = th.shape[0]
+    lay, t = _lay(layout, tiles)
+    if omega is None:
+        omega = np.zeros((num_memories3(tiles), D, 2), dtype=np.float64)
+    p = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
+    lab = np.ascontiguousarray(label, dtype=np.uint8).reshape(-1)
+    bad = lib().vo3_encode(D, _p(th), _p(lay), _p(t), _p(p), _p(lab), p.shape[0], _p(omega))
+    return omega, int(bad)
+
+
+def similarity3_cells(theta, layout, tiles, omega, grid, nx: int, ny: int, cells: np.ndarray) -> np.ndarray:
+    """Eq. loc-query at flat voxel indices (l*ny + j)*nx + i: float64 [2][ncells]."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    lay, t = _lay(layout, tiles)
+    g = np.ascontiguousarray(grid, dtype=np.float64)
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    c = np.ascontiguousarray(cells, dtype=np.int64).reshape(-1)
+    P = np.empty((2, c.shape[0]), dtype=np.float64)
+    lib().vo3_similarity_cells(th.shape[0], _p(th), _p(lay), _p(t), _p(om), _p(g), int(nx), int(ny),
+                               _p(c), c.shape[0], _p(P))
+    return P
+
+
+def similarity3(theta, layout, tiles, omega, grid, nx: int, ny: int, nz: int) -> np.ndarray:
+    """Similarity of every voxel: float64 [2][nz][ny][nx]."""
+    P = similarity3_cells(theta, layout, tiles, omega, grid, nx, ny, np.arange(nx * ny * nz))
+    return P.reshape(2, nz, ny, nx)
+
+
+def ball_count(r: int) -> int:
+    return int(lib().vo3_ball_count(int(r)))
+
+
+def postprocess3(P: np.ndarray, r_occ: int, r_emp: int, rho: float):
+    """(m[2], H[2][nz][ny][nx], ogm[nz][ny][nx], label[nz][ny][nx]) of a whole volume."""
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    _, nz, ny, nx = P.shape
+    m = np.empty(2, dtype=np.float64)
+    H = np.empty_like(P)
+    ogm = np.empty((nz, ny, nx), dtype=np.float64)
+    lab = np.empty((nz, ny, nx), dtype=np.uint8)
+    lib().vo3_postprocess(_p(P), nx, ny, nz, int(r_occ), int(r_emp), float(rho), _p(m), _p(H), _p(ogm), _p(lab))
+    return m, H, ogm, lab
+
+
+def pipeline3(v):
+    """Whole 3-D decode of a synth.Volume workload: (omega, P, m, H, ogm, label)."""
+    omega, bad = encode3(v.theta, v.layout, v.tiles, v.xyz, v.label)
+    assert bad == 0
+    P = similarity3(v.theta, v.layout, v.tiles, omega, v.grid, v.nx, v.ny, v.nz)
+    m, H, ogm, lab = postprocess3(P, v.r_occ, v.r_emp, v.rho)
     return omega, P, m, H, ogm, lab

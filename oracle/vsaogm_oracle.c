@@ -401,3 +401,162 @@ int32_t vo_num_threads(void)
     return 1;
 #endif
 }
+
+/*
+ * ---------------------------------------------------------------------------
+ * Three dimensions (the 3-D extension named as future work in Sec. V; the
+ * method of Sec. III with a third axis).  Readings: the fractional binding of
+ * Sec. III-A takes one axis vector per dimension, so the spectrum of the point
+ * (x, y, z) is exp(i*(Theta[k][0] x + Theta[k][1] y + Theta[k][2] z)); tiles
+ * are delta_x x delta_y x delta_z boxes numbered beta = (tz*ty_n + ty)*tx_n + tx;
+ * voxel centres are (x0 + (i+1/2) res, y0 + (j+1/2) res, z0 + (l+1/2) res); the
+ * entropy mask is the ball of integer offsets dx^2 + dy^2 + dz^2 <= r^2.
+ * Everything else (normalisation, maxima, squaring, entropy, softmax, signed
+ * difference, threshold) is unchanged.  theta is [D][3], lay is
+ * {x0, y0, z0, x1, y1, z1}, tiles is {tx_n, ty_n, tz_n}.
+ * ---------------------------------------------------------------------------
+ */
+void vo3_tile_center(const double* lay, const int32_t* tiles, int32_t beta,
+                     double* mx, double* my, double* mz)
+{
+    int32_t tx = beta % tiles[0];
+    int32_t ty = (beta / tiles[0]) % tiles[1];
+    int32_t tz = beta / (tiles[0] * tiles[1]);
+    *mx = lay[0] + ((double)tx + 0.5) * ((lay[3] - lay[0]) / (double)tiles[0]);
+    *my = lay[1] + ((double)ty + 0.5) * ((lay[4] - lay[1]) / (double)tiles[1]);
+    *mz = lay[2] + ((double)tz + 0.5) * ((lay[5] - lay[2]) / (double)tiles[2]);
+}
+
+int32_t vo3_assign_tile(const double* lay, const int32_t* tiles, double x, double y, double z)
+{
+    int32_t n = tiles[0] * tiles[1] * tiles[2];
+    int32_t best = 0;
+    double best_d2 = INFINITY;
+    for (int32_t b = 0; b < n; ++b) {
+        double mx, my, mz;
+        vo3_tile_center(lay, tiles, b, &mx, &my, &mz);
+        double dx = x - mx, dy = y - my, dz = z - mz;
+        double d2 = dx * dx + dy * dy + dz * dz;
+        if (d2 < best_d2) { best_d2 = d2; best = b; }
+    }
+    return best;
+}
+
+void vo3_assign_tiles(const double* lay, const int32_t* tiles, const double* xyz, int64_t n,
+                      int32_t* beta_out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        beta_out[i] = vo3_assign_tile(lay, tiles, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+}
+
+/* Algorithm 1 in 3-D: omega [2R][D][2] accumulated in place; returns rejected labels. */
+int64_t vo3_encode(int32_t D, const double* theta, const double* lay, const int32_t* tiles,
+                   const float* xyz, const uint8_t* label, int64_t n, double* omega)
+{
+    int64_t bad = 0;
+    int32_t* key = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        if (label[i] > 1) { key[i] = -1; ++bad; continue; }
+        int32_t beta = vo3_assign_tile(lay, tiles, (double)xyz[3 * i], (double)xyz[3 * i + 1],
+                                       (double)xyz[3 * i + 2]);
+        key[i] = 2 * beta + (int32_t)label[i];
+    }
+#pragma omp parallel for schedule(static)
+    for (int32_t k = 0; k < D; ++k) {
+        for (int64_t i = 0; i < n; ++i) {
+            if (key[i] < 0) continue;
+            double ph = theta[3 * k] * (double)xyz[3 * i] + theta[3 * k + 1] * (double)xyz[3 * i + 1] +
+                        theta[3 * k + 2] * (double)xyz[3 * i + 2];
+            double* w = omega + ((size_t)key[i] * D + k) * 2;
+            w[0] += cos(ph);
+            w[1] += sin(ph);
+        }
+    }
+    free(key);
+    return bad;
+}
+
+static double similarity3_at(int32_t D, const double* theta, const double* w, double nrm,
+                             double cx, double cy, double cz)
+{
+    if (nrm == 0.0) return 0.0;
+    double s = 0.0;
+    for (int32_t k = 0; k < D; ++k) {
+        double ph = theta[3 * k] * cx + theta[3 * k + 1] * cy + theta[3 * k + 2] * cz;
+        s += w[2 * k] * cos(ph) + w[2 * k + 1] * sin(ph);
+    }
+    return s / ((double)D * nrm);
+}
+
+/* grid {x0, y0, z0, res}; voxels listed by flat index (l*ny + j)*nx + i; P is [2][ncells]. */
+void vo3_similarity_cells(int32_t D, const double* theta, const double* lay, const int32_t* tiles,
+                          const double* omega, const double* grid, int32_t nx, int32_t ny,
+                          const int64_t* cells, int64_t ncells, double* P)
+{
+    int64_t nmem = 2 * (int64_t)tiles[0] * tiles[1] * tiles[2];
+    double* nrm = (double*)malloc(sizeof(double) * (size_t)nmem);
+    for (int64_t m = 0; m < nmem; ++m) nrm[m] = vo_norm(D, omega + (size_t)m * D * 2);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < ncells; ++q) {
+        int64_t i = cells[q] % nx, j = (cells[q] / nx) % ny, l = cells[q] / ((int64_t)nx * ny);
+        double cx = grid[0] + ((double)i + 0.5) * grid[3];
+        double cy = grid[1] + ((double)j + 0.5) * grid[3];
+        double cz = grid[2] + ((double)l + 0.5) * grid[3];
+        int32_t beta = vo3_assign_tile(lay, tiles, cx, cy, cz);
+        for (int32_t psi = 0; psi < 2; ++psi) {
+            int32_t key = 2 * beta + psi;
+            P[(size_t)psi * ncells + q] =
+                similarity3_at(D, theta, omega + (size_t)key * D * 2, nrm[key], cx, cy, cz);
+        }
+    }
+    free(nrm);
+}
+
+int64_t vo3_ball_count(int32_t r)
+{
+    int64_t c = 0;
+    for (int32_t dz = -r; dz <= r; ++dz)
+        for (int32_t dy = -r; dy <= r; ++dy)
+            for (int32_t dx = -r; dx <= r; ++dx)
+                if ((int64_t)dx * dx + (int64_t)dy * dy + (int64_t)dz * dz <= (int64_t)r * r) ++c;
+    return c;
+}
+
+static double local_entropy3(const double* P, double m, int32_t nx, int32_t ny, int32_t nz,
+                             int64_t i, int64_t j, int64_t l, int32_t r)
+{
+    double h = 0.0;
+    for (int32_t dz = -r; dz <= r; ++dz)
+        for (int32_t dy = -r; dy <= r; ++dy)
+            for (int32_t dx = -r; dx <= r; ++dx) {
+                if ((int64_t)dx * dx + (int64_t)dy * dy + (int64_t)dz * dz > (int64_t)r * r) continue;
+                int64_t ii = i + dx, jj = j + dy, ll = l + dz;
+                if (ii < 0 || jj < 0 || ll < 0 || ii >= nx || jj >= ny || ll >= nz) continue;
+                h += entropy_term(P[(ll * ny + jj) * nx + ii], m);
+            }
+    return h;
+}
+
+/* Decoding stages after similarity over a whole volume; P, H are [2][nz][ny][nx]. */
+void vo3_postprocess(const double* P, int32_t nx, int32_t ny, int32_t nz, int32_t r_occ,
+                     int32_t r_emp, double rho, double* m, double* H, double* ogm, uint8_t* label)
+{
+    int64_t nc = (int64_t)nx * ny * nz;
+    for (int32_t psi = 0; psi < 2; ++psi) {
+        double mx = -INFINITY;
+        for (int64_t c = 0; c < nc; ++c)
+            if (P[psi * nc + c] > mx) mx = P[psi * nc + c];
+        m[psi] = mx;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        int64_t i = c % nx, j = (c / nx) % ny, l = c / ((int64_t)nx * ny);
+        double h0 = local_entropy3(P, m[0], nx, ny, nz, i, j, l, r_emp);
+        double h1 = local_entropy3(P + nc, m[1], nx, ny, nz, i, j, l, r_occ);
+        if (H) { H[c] = h0; H[nc + c] = h1; }
+        double e0 = exp(h0), e1 = exp(h1);
+        double o = e1 / (e0 + e1) - e0 / (e0 + e1);
+        if (ogm) ogm[c] = o;
+        if (label) label[c] = (o >= rho) ? 1 : 0;
+    }
+}

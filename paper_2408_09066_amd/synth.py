@@ -383,3 +383,140 @@ def stress_scenario(n_poses: int = 2000, config_id: int = 5) -> StressScenario:
     poses = random_walk(world, n_poses, start, rng_for(config_id, STREAM_POSES))
     return StressScenario("stress200", D, ell, theta, (-half, -half, half, half), (16, 16),
                           (-half, -half, 0.05), 4000, 4000, 3, world, poses, 1080, 10, 10, config_id)
+
+
+# ---- three dimensions -------------------------------------------------------------------
+
+def make_theta3(D: int, ell: float, rng: np.random.Generator) -> np.ndarray:
+    """Conjugate-symmetric phase basis for three axes, float64 [D][3] in rad/m."""
+    if D < 4 or D % 2:
+        raise ValueError("D must be even and >= 4")
+    h = D // 2
+    th = np.zeros((D, 3), dtype=np.float64)
+    ph = rng.uniform(-np.pi, np.pi, size=(h - 1, 3))
+    th[1:h] = ph
+    th[h + 1:] = -ph[::-1]
+    return th / float(ell)
+
+
+@dataclasses.dataclass
+class World3:
+    half: Tuple[float, float, float]   # the room is [-hx, hx] x [-hy, hy] x [0, 2 hz]; walls, floor, ceiling
+    boxes: np.ndarray                  # [nb][6] xmin, ymin, zmin, xmax, ymax, zmax
+
+
+def raycast3(world: World3, pose: np.ndarray, dirs: np.ndarray) -> np.ndarray:
+    """Exact range from pose along each unit direction to the first wall, floor, ceiling or box."""
+    lo = np.array([-world.half[0], -world.half[1], 0.0])
+    hi = np.array([world.half[0], world.half[1], 2.0 * world.half[2]])
+    with np.errstate(divide="ignore", invalid="ignore"):
+        tb = np.where(dirs > 0, (hi - pose) / dirs, np.where(dirs < 0, (lo - pose) / dirs, np.inf))
+        t = tb.min(axis=1)
+        for b in world.boxes:
+            t1 = np.where(dirs != 0, (b[:3] - pose) / dirs, np.where(pose >= b[:3], -np.inf, np.inf))
+            t2 = np.where(dirs != 0, (b[3:] - pose) / dirs, np.where(pose <= b[3:], np.inf, -np.inf))
+            tmin = np.minimum(t1, t2).max(axis=1)
+            tmax = np.maximum(t1, t2).min(axis=1)
+            hit = (tmax >= tmin) & (tmin > 0)
+            t = np.where(hit & (tmin < t), tmin, t)
+    return t
+
+
+def sphere_directions(n: int) -> np.ndarray:
+    """n near-uniform unit directions (Fibonacci sphere)."""
+    i = np.arange(n) + 0.5
+    z = 1.0 - 2.0 * i / n
+    r = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    a = np.pi * (3.0 - np.sqrt(5.0)) * i
+    return np.stack([r * np.cos(a), r * np.sin(a), z], axis=1)
+
+
+@dataclasses.dataclass
+class Volume:
+    name: str
+    D: int
+    ell: float
+    theta: np.ndarray                                # float64 [D][3]
+    layout: Tuple[float, float, float, float, float, float]
+    tiles: Tuple[int, int, int]
+    grid: Tuple[float, float, float, float]          # x0, y0, z0, res
+    nx: int
+    ny: int
+    nz: int
+    xyz: np.ndarray                                  # float32 [n][3]
+    label: np.ndarray                                # uint8 [n]
+    r_occ: int
+    r_emp: int
+    rho: float = 0.0
+
+    @property
+    def n(self) -> int:
+        return int(self.xyz.shape[0])
+
+
+@dataclasses.dataclass
+class VolumeRecipe:
+    config_id: int
+    name: str
+    half: Tuple[float, float, float]
+    n_boxes: int
+    box_side: Tuple[float, float]
+    n_poses: int
+    beams: int
+    empties: int
+    D: int
+    ell: float
+    tiles: Tuple[int, int, int]
+    res: float
+    r: int
+    sigma: float = 0.02
+
+
+# "room3d" is small enough for the FP64 oracle over every voxel; "hall3d" is the 3-D benchmark.
+VOLUME_RECIPES: Dict[str, VolumeRecipe] = {
+    "room3d": VolumeRecipe(31, "room3d", (3.2, 3.2, 1.6), 5, (0.4, 1.2), 3, 600, 3, 512, 0.3,
+                           (2, 2, 1), 0.2, 1),
+    "hall3d": VolumeRecipe(32, "hall3d", (6.4, 6.4, 1.6), 24, (0.4, 1.6), 20, 4000, 5, 4096, 0.2,
+                           (2, 2, 1), 0.1, 2),
+}
+
+
+def volume(name: str) -> Volume:
+    rc = VOLUME_RECIPES[name]
+    theta = make_theta3(rc.D, rc.ell, rng_for(rc.config_id, STREAM_THETA))
+    rw = rng_for(rc.config_id, STREAM_WORLD)
+    hx, hy, hz = rc.half
+    boxes = []
+    while len(boxes) < rc.n_boxes:
+        s = rw.uniform(rc.box_side[0], rc.box_side[1], size=3)
+        c = np.array([rw.uniform(-hx + s[0] / 2, hx - s[0] / 2), rw.uniform(-hy + s[1] / 2, hy - s[1] / 2),
+                      s[2] / 2])  # standing on the floor
+        b = np.r_[c - s / 2, c + s / 2]
+        if np.all(np.abs(c[:2]) > 0.0) and not (b[0] < 0.8 and b[3] > -0.8 and b[1] < 0.8 and b[4] > -0.8):
+            boxes.append(b)   # keeps the centre column clear for the sensor
+    world = World3((hx, hy, hz), np.array(boxes, dtype=np.float64).reshape(-1, 6))
+    rp = rng_for(rc.config_id, STREAM_POSES)
+    poses = []
+    for _ in range(rc.n_poses):
+        while True:
+            q = np.array([rp.uniform(-hx + 0.5, hx - 0.5), rp.uniform(-hy + 0.5, hy - 0.5), rp.uniform(0.8, 1.4)])
+            inside = any(np.all(q >= b[:3] - 0.3) and np.all(q <= b[3:] + 0.3) for b in world.boxes)
+            if not inside:
+                poses.append(q)
+                break
+    dirs = sphere_directions(rc.beams)
+    rn, re = rng_for(rc.config_id, STREAM_NOISE), rng_for(rc.config_id, STREAM_EMPTY)
+    xs, ls = [], []
+    for q in poses:
+        r = np.maximum(raycast3(world, q, dirs) + rn.normal(0.0, rc.sigma, size=rc.beams), 0.0)
+        xs.append(q[None, :] + r[:, None] * dirs)
+        ls.append(np.ones(rc.beams, np.uint8))
+        u = re.uniform(0.0, 1.0, size=(rc.beams, rc.empties))
+        xs.append((q[None, None, :] + (u * r[:, None])[:, :, None] * dirs[:, None, :]).reshape(-1, 3))
+        ls.append(np.zeros(rc.beams * rc.empties, np.uint8))
+    xyz = np.concatenate(xs).astype(np.float32)
+    label = np.concatenate(ls)
+    nx, ny, nz = int(round(2 * hx / rc.res)), int(round(2 * hy / rc.res)), int(round(2 * hz / rc.res))
+    layout = (-hx, -hy, 0.0, hx, hy, 2 * hz)
+    return Volume(rc.name, rc.D, rc.ell, theta, layout, rc.tiles, (-hx, -hy, 0.0, rc.res), nx, ny, nz,
+                  xyz, label, rc.r, rc.r)
