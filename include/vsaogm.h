@@ -74,6 +74,7 @@ typedef enum {
 
 typedef struct vsaogm_map vsaogm_map;
 typedef struct vsaogm_server vsaogm_server;
+typedef struct vsaogm_volume vsaogm_volume;
 typedef void* vsaogm_stream; /* a hipStream_t; NULL means the device's null stream */
 
 typedef struct {
@@ -323,6 +324,56 @@ int vsaogm_request_bytes(vsaogm_server* server, const vsaogm_request* req, int64
  * while other threads launch the same stage.
  */
 int vsaogm_profile_events(int32_t stage, void* begin_event, void* end_event);
+
+/* ---------------------------------------------------------------------------
+ * Volumes: the method in three dimensions (Sec. III with a third axis; the 3-D
+ * mapping named as future work in Sec. V).  A point's spectrum is
+ * exp(i Theta[k].(x, y, z)); tiles are tiles_x x tiles_y x tiles_z boxes numbered
+ * beta = (tz * tiles_y + ty) * tiles_x + tx, memory 2*beta + psi; a voxel queries its
+ * own nearest tile; the entropy window is the ball of integer voxel offsets
+ * dx^2 + dy^2 + dz^2 <= r^2.  Normalisation, maxima, squaring, softmax, signed
+ * difference and threshold are those of the plane map.
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t dim;              /* D: even, >= 4 */
+    const double* theta;      /* host [D][3] rad/m, conjugate-symmetric per axis, copied */
+    double x0, y0, z0, x1, y1, z1;   /* layout box, m */
+    int32_t tiles_x, tiles_y, tiles_z;   /* 1..64 each, at most 4096 tiles */
+    int32_t device;
+} vsaogm_volume_desc;
+
+typedef struct {
+    double x0, y0, z0, res;   /* voxel (i,j,l) centre = (x0+(i+.5)res, y0+(j+.5)res, z0+(l+.5)res) */
+    int32_t nx, ny, nz;
+} vsaogm_grid3_desc;
+
+/* Create / destroy a volume (memories zero).  EINVAL for invalid descriptors. */
+int vsaogm_volume_create(const vsaogm_volume_desc* desc, vsaogm_volume** out);
+int vsaogm_volume_destroy(vsaogm_volume* vol);
+
+/* Algorithm 1 in 3-D: bundle n points (device float [n][3] world metres, device uint8 labels
+   0/1) into the memories; labels other than 0/1 are counted and skipped.  Asynchronous. */
+int vsaogm_volume_encode(vsaogm_volume* vol, const float* xyz, const uint8_t* label, int64_t n,
+                         vsaogm_stream stream);
+
+/* Labels rejected since the last call (synchronises the stream). */
+int vsaogm_volume_take_rejected(vsaogm_volume* vol, vsaogm_stream stream, int64_t* n_rejected);
+
+/* Similarity of every voxel with its tile's normalised memories (eq. loc-query in 3-D):
+   heat device float [2][nz][ny][nx] (class 1 = occupied), hmax device float [2] the
+   per-class maxima.  precision: VSAOGM_BF16, VSAOGM_FP16 or VSAOGM_BF16X3 (the hi+lo
+   split reaches fp32 accuracy); EINVAL for VSAOGM_FP32 and for grids whose voxels do
+   not split into per-tile slabs along each axis. */
+int vsaogm_volume_decode(vsaogm_volume* vol, const vsaogm_grid3_desc* grid, int32_t precision,
+                         float* heat, float* hmax, vsaogm_stream stream);
+
+/* Entropy classification of a volume (Algorithm 2 with a ball mask of radius r_occ for
+   class 1 and r_emp for class 0, 0..24): ogm device float [nz][ny][nx] (or NULL), label
+   device uint8 [nz][ny][nx]. */
+int vsaogm_classify3(const vsaogm_grid3_desc* grid, const float* heat, const float* hmax,
+                     int32_t r_occ, int32_t r_emp, float rho, float* ogm, uint8_t* label,
+                     int32_t device, vsaogm_stream stream);
 
 #ifdef __cplusplus
 }

@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libvsaogm.so")
 ARCH = "gfx950"
 
-SOURCES = ["encode.hip", "decode.hip", "classify.hip", "map.hip", "server.hip"]
+SOURCES = ["encode.hip", "decode.hip", "classify.hip", "map.hip", "server.hip", "volume.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

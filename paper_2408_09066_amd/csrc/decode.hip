@@ -140,7 +140,10 @@ struct DecodeArgs {
     const float2* omega_s;     // [nkeys][halfp] conj(Omega) / ||w|| (0 for an empty memory)
     int halfp, nx, ny, tiles_x;
     float out_scale;           // 2 / D
-    float* heat;               // [2][ny][nx]
+    float* heat;               // [2][slices][ny][nx]: class planes class_stride apart, a tile's
+                               // slice (DTile::pad) nx*ny further
+    size_t class_stride;
+    const float2* ez;          // [slices][halfp] third-axis table (volumes), else null
     unsigned* hmax_u;          // [2] ordered maxima (zeroed by the norm kernel)
     float* partial;            // [grid][2][2][kTileRows][kTileCols]
     int ksteps;                // K steps per tile
@@ -163,7 +166,7 @@ __device__ inline void store_tile(const DecodeArgs& a, const DTile& t, int wave,
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
         float mx = -INFINITY;
-        float* out = a.heat + (size_t)p * a.nx * a.ny;
+        float* out = a.heat + (size_t)p * a.class_stride;
 #pragma unroll
         for (int rb = 0; rb < kRowBlocks; ++rb) {
             if (rb < t.nrb) {
@@ -449,7 +452,8 @@ struct Wide {
 static_assert(Wide<1>::TR == 16 * kDecodeSetRowBlocks[1] && Wide<3>::TR == 16 * kDecodeSetRowBlocks[2],
               "tile sets match the kernels");
 
-template <int PREC>
+// Z: volumes, the column operand also carries the third-axis table of the tile's slice.
+template <int PREC, bool Z>
 __global__ __launch_bounds__(256, Wide<PREC>::OCC) void k_decode16(DecodeArgs a) {
     using W = Wide<PREC>;
     constexpr int NS = W::NS, NSETS = W::NSETS, DEPTH = W::DEPTH, KB = W::KB, RBW = W::RBW, TR = W::TR;
@@ -498,6 +502,7 @@ __global__ __launch_bounds__(256, Wide<PREC>::OCC) void k_decode16(DecodeArgs a)
             ex_row[u] = reinterpret_cast<const f32x4*>(a.ex + (size_t)gcol * a.halfp + 2 * part16);
             oslot[u] = min(max(a.col_tx[gcol] - t.tx0, 0), 1);
         }
+        const f32x4* ez_row = Z ? reinterpret_cast<const f32x4*>(a.ez + (size_t)t.pad * a.halfp + 2 * part16) : nullptr;
         const int oks = (lane >> 5) & 1, ocls = (lane >> 4) & 1;  // this lane's staging item
         const f32x4* om_src = reinterpret_cast<const f32x4*>(
             a.omega_s + (size_t)(2 * (t.ty * a.tiles_x + min(t.tx0 + oks, a.tiles_x - 1)) + ocls) * a.halfp +
@@ -510,7 +515,7 @@ __global__ __launch_bounds__(256, Wide<PREC>::OCC) void k_decode16(DecodeArgs a)
         };
 
         u32x4 A[NSETS][RBW][2][NS];     // [set][block][32-real chunk][hi, lo]
-        f32x4 BX[B_PER_T];
+        f32x4 BX[B_PER_T], BZ;
 
         // Loads are issued without branches (blocks past the tile's last one reload a clamped row,
         // steps past the segment's last one reload its last step), so that the compiler can count
@@ -531,6 +536,7 @@ __global__ __launch_bounds__(256, Wide<PREC>::OCC) void k_decode16(DecodeArgs a)
             const size_t boff = (size_t)(kb0 + min(kk, n - 1)) * (KB / 2);
 #pragma unroll
             for (int u = 0; u < B_PER_T; ++u) BX[u] = ex_row[u][boff];
+            if (Z) BZ = ez_row[boff];
         };
         // column operand into LDS stage st: conj(Omega)/||w|| * Ex as (Re, -Im)
         auto bstore = [&](int st) {
@@ -539,7 +545,12 @@ __global__ __launch_bounds__(256, Wide<PREC>::OCC) void k_decode16(DecodeArgs a)
             for (int u = 0; u < B_PER_T; ++u) {
                 const int idx = tid + 256 * u;
                 const int c = idx / (KB / 2), part = idx % (KB / 2);
-                const f32x4 e = BX[u];
+                f32x4 e = BX[u];
+                if (Z) {  // Ex * Ez of the slice, two complex bins
+                    const f32x4 z = BZ;
+                    e = f32x4{__builtin_fmaf(e.x, z.x, -e.y * z.y), __builtin_fmaf(e.x, z.y, e.y * z.x),
+                              __builtin_fmaf(e.z, z.z, -e.w * z.w), __builtin_fmaf(e.z, z.w, e.w * z.z)};
+                }
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
                     const f32x4 o = *reinterpret_cast<const f32x4*>(&om_lds[st][(oslot[u] * 2 + p) * KB + 2 * part]);
@@ -640,7 +651,7 @@ __global__ __launch_bounds__(256, Wide<PREC>::OCC) void k_decode16(DecodeArgs a)
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
             float mx = -INFINITY;
-            float* out = a.heat + (size_t)p * a.nx * a.ny;
+            float* out = a.heat + (size_t)p * a.class_stride + (size_t)t.pad * a.nx * a.ny;
 #pragma unroll
             for (int j = 0; j < RBW; ++j)
                 if (j < nj)
@@ -722,7 +733,7 @@ __global__ __launch_bounds__(256) void k_decode_fix(DecodeArgs a) {
         const int row = t.row0 + r, col = t.col0 + c;
         if (r < 16 * t.nrb && row < t.row_end && c < t.ncol) {
             const float v = sum[j] * a.out_scale;
-            a.heat[(size_t)p * a.nx * a.ny + (size_t)row * a.nx + col] = v;
+            a.heat[(size_t)p * a.class_stride + (size_t)t.pad * a.nx * a.ny + (size_t)row * a.nx + col] = v;
             mx[p] = fmaxf(mx[p], v);
         }
     }
@@ -858,6 +869,8 @@ hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
     a.tiles_x = d.tiles_x;
     a.out_scale = d.out_scale;
     a.heat = d.heat;
+    a.class_stride = d.class_stride ? d.class_stride : (size_t)d.nx * d.ny;
+    a.ez = d.ez;
     a.hmax_u = d.hmax_u;
     a.partial = d.partial;
     a.ksteps = d.plan.ksteps;
@@ -866,10 +879,22 @@ hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
     const dim3 grid(d.plan.grid), block(256);
     profile_begin(kStageDecode, s);
     switch (precision) {
-        case 0: hipLaunchKernelGGL(k_decode<0>, grid, block, 0, s, a); break;
-        case 1: hipLaunchKernelGGL(k_decode16<1>, grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL(k_decode16<2>, grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL(k_decode16<3>, grid, block, 0, s, a); break;
+        case 0:
+            if (d.ez) return hipErrorInvalidValue;  // volumes run the 16-bit kernels
+            hipLaunchKernelGGL(k_decode<0>, grid, block, 0, s, a);
+            break;
+        case 1:
+            if (d.ez) hipLaunchKernelGGL((k_decode16<1, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_decode16<1, false>), grid, block, 0, s, a);
+            break;
+        case 2:
+            if (d.ez) hipLaunchKernelGGL((k_decode16<2, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_decode16<2, false>), grid, block, 0, s, a);
+            break;
+        case 3:
+            if (d.ez) hipLaunchKernelGGL((k_decode16<3, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_decode16<3, false>), grid, block, 0, s, a);
+            break;
         default: return hipErrorInvalidValue;
     }
     if (d.plan.steps_per_wg % d.plan.ksteps != 0 || d.plan.steps_per_wg < d.plan.ksteps) {

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 namespace vsaogm {
 
@@ -52,8 +53,36 @@ struct DTile {
     int col0;         // first grid column
     int ncol;         // columns of this tile (1..64)
     int tx0;          // tile column of its first column; 16-bit tiles span at most tx0, tx0 + 1
-    int pad;
+    int pad;          // slice of a volume (0 for maps)
 };
+
+// Rows of one band of decode work: its memories are those of tile row key_row (for volumes
+// tz * tiles_y + ty), its grid rows [row0, row1), in slice `slice` of a volume (0 for maps).
+struct DBand {
+    int key_row, row0, row1, slice;
+};
+// Work tiles of a tile set over the bands, the grid's columns with their tile columns tcol.
+std::vector<DTile> build_decode_tiles(const std::vector<DBand>& bands, const std::vector<int>& tcol, int nx,
+                                      int set);
+
+// ---- volumes (volume.hip) -------------------------------------------------------------
+struct Volume3Dev {
+    const double* cx;   // [tx] tile centres per axis
+    const double* cy;   // [ty]
+    const double* cz;   // [tz]
+    int tx, ty, tz;
+    double x0, y0, z0, wx, wy, wz;   // layout origin and tile widths
+};
+int encode3_ranges(int64_t n);  // point ranges of one encode (partial sums per range and memory)
+// Bucketing, encoding and bundling of n labelled points into omega [nkeys][halfp] (local frame).
+// rev: fp32 [halfp] (x, y, z, 0) revolutions per metre, 0 past half; rev_d: double [halfp][3].
+hipError_t launch_encode3(const float* xyz, const uint8_t* label, int64_t n, const Volume3Dev& V,
+                          const float4* rev, const double* rev_d, float4 max_rev, int nkeys, int half,
+                          int halfp, int* key, float4* loc, float4* loc_lo, float2* partial,
+                          unsigned long long* n_bad, float2* omega, hipStream_t s);
+// Ball entropy classification of a volume's heat [2][nz][ny][nx]; g is 2*nvox floats of scratch.
+hipError_t launch_classify3(const float* heat, const float* hmax, int nx, int ny, int nz, const int4* offsets,
+                            int n_emp, int n_occ, float rho, float* g, float* ogm, uint8_t* label, hipStream_t s);
 
 // ---- error text shared by every entry point (map.hip) -------------------------------
 void set_last_error(const char* msg);
@@ -132,6 +161,8 @@ struct DecodeLaunch {
     int halfp, nx, ny, tiles_x;
     float out_scale;        // 2 / D
     float* heat;
+    size_t class_stride = 0;   // floats between the class planes of heat (0: nx * ny)
+    const float2* ez = nullptr;  // volumes: [slices][halfp] third-axis table (16-bit kernels only)
     unsigned* hmax_u;       // zeroed by launch_norm
     float* hmax;
     float* partial;         // decode_partial_floats(precision, plan) floats

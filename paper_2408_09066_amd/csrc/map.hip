@@ -166,6 +166,55 @@ ProfileSlot g_profile[kNumStages];
 
 namespace vsaogm {
 void set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
+
+std::vector<DTile> build_decode_tiles(const std::vector<DBand>& bands, const std::vector<int>& tcol, int nx,
+                                      int set) {
+    // Work tiles: per band, its rows in blocks of 16 split evenly into groups of at most
+    // kDecodeSetRowBlocks blocks, times the grid's columns in slices of up to 64.
+    const int maxrb = kDecodeSetRowBlocks[set];
+    // column slices (the same for every band): 64 columns; for 16-bit operands cut short where
+    // a slice would reach a third tile column (its kernel stages two tiles' memories)
+    std::vector<std::pair<int, int>> slices;
+    for (int c = 0; c < nx;) {
+        int end = std::min(c + 64, nx);
+        if (set > 0 && tcol[end - 1] > tcol[c] + 1)
+            end = (int)(std::lower_bound(tcol.begin(), tcol.end(), tcol[c] + 2) - tcol.begin());
+        slices.emplace_back(c, end);
+        c = end;
+    }
+    std::vector<DTile> groups;  // row groups, columns unset
+    for (const DBand& bd : bands) {
+        const int nblocks = (bd.row1 - bd.row0 + 15) / 16;
+        const int ngroups = (nblocks + maxrb - 1) / maxrb;
+        int b0 = 0;
+        for (int gi = 0; gi < ngroups; ++gi) {
+            const int nb = nblocks / ngroups + (gi < nblocks % ngroups ? 1 : 0);
+            DTile d{};
+            d.ty = bd.key_row;
+            d.row0 = bd.row0 + 16 * b0;
+            d.row_end = bd.row1;
+            d.nrb = nb;
+            d.pad = bd.slice;
+            groups.push_back(d);
+            b0 += nb;
+        }
+    }
+    // order: blocks of kBlockRows row groups x kBlockCols slices, so that the workgroups
+    // resident on one XCD at a time work on tiles that share rows and columns
+    constexpr int kBlockRows = 4, kBlockCols = 8;
+    std::vector<DTile> tl;
+    for (size_t gb = 0; gb < groups.size(); gb += kBlockRows)
+        for (size_t sb = 0; sb < slices.size(); sb += kBlockCols)
+            for (size_t gi = gb; gi < std::min(groups.size(), gb + kBlockRows); ++gi)
+                for (size_t si = sb; si < std::min(slices.size(), sb + kBlockCols); ++si) {
+                    DTile d = groups[gi];
+                    d.col0 = slices[si].first;
+                    d.ncol = slices[si].second - slices[si].first;
+                    d.tx0 = tcol[d.col0];
+                    tl.push_back(d);
+                }
+    return tl;
+}
 void profile_begin(int stage, hipStream_t s) {
     if (g_profile[stage].begin) (void)hipEventRecord(g_profile[stage].begin, s);
 }
@@ -218,6 +267,39 @@ struct vsaogm_map {
         L.cy = d_cy.p;
         return L;
     }
+};
+
+// A volume (3-D map) and its one cached grid.
+struct Grid3Cache {
+    vsaogm_grid3_desc key{};
+    DevBuf<double> local_x, local_y, local_z;
+    DevBuf<int> col_tx;
+    DevBuf<DTile> tiles[kDecodeTileSets];
+    int ntiles[kDecodeTileSets] = {};
+    DevBuf<float2> ex32, ez32;                 // [nx][halfp], [nz][halfp]
+    DevBuf<uint16_t> ey_bf, ey_bf_lo, ey_h;    // [ny][2 halfp]
+};
+
+struct vsaogm_volume {
+    int device = 0, D = 0, half = 0, halfp = 0, tiles_x = 1, tiles_y = 1, tiles_z = 1, nkeys = 0, num_cus = 1;
+    double lay[6] = {};
+    std::vector<double> cx, cy, cz;
+    float max_rev[3] = {0.f, 0.f, 0.f};
+    DevBuf<double> d_cx, d_cy, d_cz;
+    DevBuf<float4> d_rev;                      // [halfp] revolutions per metre (x, y, z, 0)
+    DevBuf<double> d_rev_d;                    // [halfp][3]
+    DevBuf<double> d_theta_xy, d_theta_z;      // [half][2] rad/m: (x, y) and (z, 0) for the tables
+    DevBuf<float2> d_omega, d_omega_s;         // [nkeys][halfp]
+    DevBuf<float> d_scale;
+    DevBuf<unsigned> d_hmax_u;
+    DevBuf<unsigned long long> d_bad;
+    DevBuf<int> w_key;
+    DevBuf<float4> w_loc, w_loc_lo;
+    DevBuf<float2> w_partial;
+    int64_t cap_n = 0;
+    int cap_ranges = 0;
+    DevBuf<float> d_partial;                   // split-tile partial sums of the decode
+    std::unique_ptr<Grid3Cache> grid;
 };
 
 namespace {
@@ -322,54 +404,15 @@ GridCache* grid_cache(vsaogm_map* m, const vsaogm_grid_desc* g, hipStream_t s) {
     auto gc = std::make_unique<GridCache>();
     gc->nx = g->nx;
     gc->ny = g->ny;
-    // Work tiles: per tile band, its rows in blocks of 16 split evenly into groups of at most
-    // kDecodeSetRowBlocks blocks, times the grid's columns in slices of up to 64.
+    std::vector<DBand> bands;
+    for (int ty = 0; ty < m->tiles_y; ++ty) {
+        const int r0 = (int)(std::lower_bound(trow.begin(), trow.end(), ty) - trow.begin());
+        const int r1 = (int)(std::upper_bound(trow.begin(), trow.end(), ty) - trow.begin());
+        if (r0 < r1) bands.push_back(DBand{ty, r0, r1, 0});
+    }
     for (int set = 0; set < kDecodeTileSets; ++set) {
-        const int maxrb = kDecodeSetRowBlocks[set];
-        // column slices (the same for every band): 64 columns; for 16-bit operands cut short
-        // where a slice would reach a third tile column (its kernel stages two tiles' memories)
-        std::vector<std::pair<int, int>> slices;
-        for (int c = 0; c < g->nx;) {
-            int end = std::min(c + 64, g->nx);
-            if (set > 0 && tcol[end - 1] > tcol[c] + 1)
-                end = (int)(std::lower_bound(tcol.begin(), tcol.end(), tcol[c] + 2) - tcol.begin());
-            slices.emplace_back(c, end);
-            c = end;
-        }
-        std::vector<DTile> groups;  // row groups, columns unset
-        for (int ty = 0; ty < m->tiles_y; ++ty) {
-            const int r0 = (int)(std::lower_bound(trow.begin(), trow.end(), ty) - trow.begin());
-            const int r1 = (int)(std::upper_bound(trow.begin(), trow.end(), ty) - trow.begin());
-            if (r0 >= r1) continue;
-            const int nblocks = (r1 - r0 + 15) / 16;
-            const int ngroups = (nblocks + maxrb - 1) / maxrb;
-            int b0 = 0;
-            for (int gi = 0; gi < ngroups; ++gi) {
-                const int nb = nblocks / ngroups + (gi < nblocks % ngroups ? 1 : 0);
-                DTile d{};
-                d.ty = ty;
-                d.row0 = r0 + 16 * b0;
-                d.row_end = r1;
-                d.nrb = nb;
-                groups.push_back(d);
-                b0 += nb;
-            }
-        }
-        // order: blocks of kBlockRows row groups x kBlockCols slices, so that the workgroups
-        // resident on one XCD at a time work on tiles that share rows and columns
-        constexpr int kBlockRows = 4, kBlockCols = 8;
-        std::vector<DTile>& tl = gc->host_tiles[set];
-        for (size_t gb = 0; gb < groups.size(); gb += kBlockRows)
-            for (size_t sb = 0; sb < slices.size(); sb += kBlockCols)
-                for (size_t gi = gb; gi < std::min(groups.size(), gb + kBlockRows); ++gi)
-                    for (size_t si = sb; si < std::min(slices.size(), sb + kBlockCols); ++si) {
-                        DTile d = groups[gi];
-                        d.col0 = slices[si].first;
-                        d.ncol = slices[si].second - slices[si].first;
-                        d.tx0 = tcol[d.col0];
-                        tl.push_back(d);
-                    }
-        gc->ntiles[set] = (int)tl.size();
+        gc->host_tiles[set] = build_decode_tiles(bands, tcol, g->nx, set);
+        gc->ntiles[set] = (int)gc->host_tiles[set].size();
     }
     gc->tcol = tcol;
     gc->boxes.resize((size_t)m->tiles_x * m->tiles_y);
@@ -445,6 +488,95 @@ void check_grid(const vsaogm_grid_desc* g) {
     if ((int64_t)g->nx * g->ny > (int64_t)1 << 31) fail(VSAOGM_EINVAL, "grid too large");
     if (!is_finite(g->x0) || !is_finite(g->y0) || !is_finite(g->res) || !(g->res > 0))
         fail(VSAOGM_EINVAL, "grid origin must be finite and res > 0");
+}
+
+void check_grid3(const vsaogm_grid3_desc* g) {
+    if (!g) fail(VSAOGM_EINVAL, "grid is NULL");
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1) fail(VSAOGM_EINVAL, "grid nx, ny and nz must be >= 1");
+    if ((int64_t)g->nx * g->ny * g->nz > (int64_t)1 << 31) fail(VSAOGM_EINVAL, "grid too large");
+    if (!is_finite(g->x0) || !is_finite(g->y0) || !is_finite(g->z0) || !is_finite(g->res) || !(g->res > 0))
+        fail(VSAOGM_EINVAL, "grid origin must be finite and res > 0");
+}
+
+// Per-axis nearest centres of a volume grid, with the exact 3-D argmin confirmed wherever an
+// axis is close to a tie (as for plane maps).
+Grid3Cache* grid3_cache(vsaogm_volume* v, const vsaogm_grid3_desc* g, hipStream_t s) {
+    if (v->grid && std::memcmp(&v->grid->key, g, sizeof(*g)) == 0) return v->grid.get();
+    const int nx = g->nx, ny = g->ny, nz = g->nz;
+    std::vector<int> t[3];
+    std::vector<double> loc[3];
+    std::vector<char> tie[3];
+    const double o[3] = {g->x0, g->y0, g->z0};
+    const std::vector<double>* c[3] = {&v->cx, &v->cy, &v->cz};
+    const int nc[3] = {nx, ny, nz};
+    for (int a = 0; a < 3; ++a) {
+        t[a].resize(nc[a]);
+        loc[a].resize(nc[a]);
+        tie[a].assign(nc[a], 0);
+        for (int i = 0; i < nc[a]; ++i) {
+            const double val = o[a] + ((double)i + 0.5) * g->res;
+            t[a][i] = nearest_1d(*c[a], val);
+            loc[a][i] = val - (*c[a])[t[a][i]];
+            if (i > 0 && t[a][i] < t[a][i - 1]) fail(VSAOGM_EINVAL, "grid voxels are not ordered along an axis");
+            for (int u = 0; u < (int)c[a]->size(); ++u) {
+                if (u == t[a][i]) continue;
+                const double d1 = (val - (*c[a])[t[a][i]]) * (val - (*c[a])[t[a][i]]);
+                const double d2 = (val - (*c[a])[u]) * (val - (*c[a])[u]);
+                if (std::fabs(d2 - d1) <= 1e-9 * (d1 + d2) + 1e-300) tie[a][i] = 1;
+            }
+        }
+    }
+    for (int l = 0; l < nz; ++l)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                if (!tie[0][i] && !tie[1][j] && !tie[2][l]) continue;
+                const double x = g->x0 + ((double)i + 0.5) * g->res, y = g->y0 + ((double)j + 0.5) * g->res,
+                             z = g->z0 + ((double)l + 0.5) * g->res;
+                int best = 0;
+                double bd = INFINITY;
+                for (int b = 0; b < v->tiles_x * v->tiles_y * v->tiles_z; ++b) {
+                    const int tx = b % v->tiles_x, ty = (b / v->tiles_x) % v->tiles_y, tz = b / (v->tiles_x * v->tiles_y);
+                    const double dx = x - v->cx[tx], dy = y - v->cy[ty], dz = z - v->cz[tz];
+                    const double d = dx * dx + dy * dy + dz * dz;
+                    if (d < bd) {
+                        bd = d;
+                        best = b;
+                    }
+                }
+                if (best != (t[2][l] * v->tiles_y + t[1][j]) * v->tiles_x + t[0][i])
+                    fail(VSAOGM_EINVAL, "a voxel centre lies on a tile boundary in a way that does not "
+                                        "split into per-tile slabs");
+            }
+    auto gc = std::make_unique<Grid3Cache>();
+    gc->key = *g;
+    std::vector<DBand> bands;
+    for (int l = 0; l < nz; ++l)
+        for (int ty = 0; ty < v->tiles_y; ++ty) {
+            const int r0 = (int)(std::lower_bound(t[1].begin(), t[1].end(), ty) - t[1].begin());
+            const int r1 = (int)(std::upper_bound(t[1].begin(), t[1].end(), ty) - t[1].begin());
+            if (r0 < r1) bands.push_back(DBand{t[2][l] * v->tiles_y + ty, r0, r1, l});
+        }
+    for (int set = 1; set < kDecodeTileSets; ++set) {
+        std::vector<DTile> tl = build_decode_tiles(bands, t[0], nx, set);
+        gc->ntiles[set] = (int)tl.size();
+        gc->tiles[set].alloc(tl.size(), "volume tile list");
+        hip_check(hipMemcpy(gc->tiles[set].p, tl.data(), tl.size() * sizeof(DTile), hipMemcpyHostToDevice),
+                  "copy tile list");
+    }
+    gc->col_tx.alloc(nx, "column tiles");
+    hip_check(hipMemcpy(gc->col_tx.p, t[0].data(), nx * sizeof(int), hipMemcpyHostToDevice), "copy column tiles");
+    DevBuf<double>* lb[3] = {&gc->local_x, &gc->local_y, &gc->local_z};
+    for (int a = 0; a < 3; ++a) {
+        lb[a]->alloc(nc[a], "local coordinates");
+        hip_check(hipMemcpy(lb[a]->p, loc[a].data(), nc[a] * sizeof(double), hipMemcpyHostToDevice), "copy local");
+    }
+    gc->ex32.alloc((size_t)nx * v->halfp, "x location table");
+    gc->ez32.alloc((size_t)nz * v->halfp, "z location table");
+    hip_check(launch_table_f32(v->d_theta_xy.p, 0, gc->local_x.p, nx, v->half, v->halfp, gc->ex32.p, s), "x table");
+    hip_check(launch_table_f32(v->d_theta_z.p, 0, gc->local_z.p, nz, v->half, v->halfp, gc->ez32.p, s), "z table");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    v->grid = std::move(gc);
+    return v->grid.get();
 }
 
 }  // namespace
@@ -799,6 +931,246 @@ int vsaogm_profile_events(int32_t stage, void* begin_event, void* end_event) {
         if (stage < 0 || stage >= kNumStages) fail(VSAOGM_EINVAL, "unknown stage");
         g_profile[stage].begin = static_cast<hipEvent_t>(begin_event);
         g_profile[stage].end = static_cast<hipEvent_t>(end_event);
+    });
+}
+
+int vsaogm_volume_create(const vsaogm_volume_desc* d, vsaogm_volume** out) {
+    return guarded([&] {
+        if (!d || !out) fail(VSAOGM_EINVAL, "desc and out must not be NULL");
+        *out = nullptr;
+        const int D = d->dim;
+        if (D < 4 || (D & 1)) fail(VSAOGM_EINVAL, "dim must be even and >= 4");
+        if (D > (1 << 22)) fail(VSAOGM_EINVAL, "dim too large");
+        if (!d->theta) fail(VSAOGM_EINVAL, "theta is NULL");
+        const int tn[3] = {d->tiles_x, d->tiles_y, d->tiles_z};
+        for (int a = 0; a < 3; ++a)
+            if (tn[a] < 1 || tn[a] > kMaxTilesPerAxis) fail(VSAOGM_EINVAL, "tiles per axis must be in 1..64");
+        if (2 * tn[0] * tn[1] * tn[2] > kMaxKeys) fail(VSAOGM_EINVAL, "at most 4096 tiles");
+        const double box[6] = {d->x0, d->y0, d->z0, d->x1, d->y1, d->z1};
+        for (int a = 0; a < 3; ++a)
+            if (!is_finite(box[a]) || !is_finite(box[3 + a]) || !(box[3 + a] > box[a]))
+                fail(VSAOGM_EINVAL, "layout box must be finite with x1 > x0, y1 > y0 and z1 > z0");
+        int ndev = 0;
+        hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+        if (d->device < 0 || d->device >= ndev) fail(VSAOGM_EINVAL, "no such device");
+        const double* th = d->theta;
+        for (int k = 0; k < 3 * D; ++k)
+            if (!is_finite(th[k])) fail(VSAOGM_EINVAL, "theta must be finite");
+        const int half = D / 2;
+        for (int a = 0; a < 3; ++a) {
+            if (th[a] != 0.0 || th[3 * half + a] != 0.0) fail(VSAOGM_EINVAL, "theta[0] and theta[D/2] must be zero");
+            for (int k = 1; k < half; ++k)
+                if (th[3 * (D - k) + a] != -th[3 * k + a])
+                    fail(VSAOGM_EINVAL, "theta must be conjugate-symmetric: theta[D-k] = -theta[k]");
+        }
+        auto v = std::make_unique<vsaogm_volume>();
+        v->device = d->device;
+        v->D = D;
+        v->half = half;
+        v->halfp = (half + kBinPad - 1) / kBinPad * kBinPad;
+        v->tiles_x = tn[0];
+        v->tiles_y = tn[1];
+        v->tiles_z = tn[2];
+        v->nkeys = 2 * tn[0] * tn[1] * tn[2];
+        std::copy(box, box + 6, v->lay);
+        v->cx = centres(d->x0, d->x1, tn[0]);
+        v->cy = centres(d->y0, d->y1, tn[1]);
+        v->cz = centres(d->z0, d->z1, tn[2]);
+        std::vector<float4> rev(v->halfp, make_float4(0.f, 0.f, 0.f, 0.f));
+        std::vector<double> rev_d(3 * (size_t)v->halfp, 0.0), txy(2 * (size_t)half), tz(2 * (size_t)half, 0.0);
+        const double inv2pi = 1.0 / (2.0 * M_PI);
+        for (int k = 0; k < half; ++k) {
+            double r3[3];
+            for (int a = 0; a < 3; ++a) {
+                r3[a] = th[3 * k + a] * inv2pi;
+                rev_d[3 * k + a] = r3[a];
+                v->max_rev[a] = std::max(v->max_rev[a], (float)std::fabs(r3[a]));
+            }
+            rev[k] = make_float4((float)r3[0], (float)r3[1], (float)r3[2], 0.f);
+            txy[2 * k] = th[3 * k];
+            txy[2 * k + 1] = th[3 * k + 1];
+            tz[2 * k] = th[3 * k + 2];
+        }
+        DeviceGuard guard(v->device);
+        hip_check(hipDeviceGetAttribute(&v->num_cus, hipDeviceAttributeMultiprocessorCount, v->device),
+                  "device attribute");
+        if (v->num_cus < 1) v->num_cus = 1;
+        v->d_cx.alloc(tn[0], "tile centres x");
+        v->d_cy.alloc(tn[1], "tile centres y");
+        v->d_cz.alloc(tn[2], "tile centres z");
+        v->d_rev.alloc(v->halfp, "theta (rev, fp32)");
+        v->d_rev_d.alloc(3 * (size_t)v->halfp, "theta (rev, fp64)");
+        v->d_theta_xy.alloc(2 * (size_t)half, "theta xy");
+        v->d_theta_z.alloc(2 * (size_t)half, "theta z");
+        v->d_omega.alloc((size_t)v->nkeys * v->halfp, "memories");
+        v->d_omega_s.alloc((size_t)v->nkeys * v->halfp, "scaled memories");
+        v->d_scale.alloc(v->nkeys, "memory scales");
+        v->d_hmax_u.alloc(3, "class maxima");
+        v->d_bad.alloc(1, "rejected-label counter");
+        hip_check(hipMemcpy(v->d_cx.p, v->cx.data(), tn[0] * 8, hipMemcpyHostToDevice), "copy");
+        hip_check(hipMemcpy(v->d_cy.p, v->cy.data(), tn[1] * 8, hipMemcpyHostToDevice), "copy");
+        hip_check(hipMemcpy(v->d_cz.p, v->cz.data(), tn[2] * 8, hipMemcpyHostToDevice), "copy");
+        hip_check(hipMemcpy(v->d_rev.p, rev.data(), rev.size() * sizeof(float4), hipMemcpyHostToDevice), "copy");
+        hip_check(hipMemcpy(v->d_rev_d.p, rev_d.data(), rev_d.size() * 8, hipMemcpyHostToDevice), "copy");
+        hip_check(hipMemcpy(v->d_theta_xy.p, txy.data(), txy.size() * 8, hipMemcpyHostToDevice), "copy");
+        hip_check(hipMemcpy(v->d_theta_z.p, tz.data(), tz.size() * 8, hipMemcpyHostToDevice), "copy");
+        zero_async(v->d_omega.p, v->d_omega.n * sizeof(float2), nullptr);
+        zero_async(v->d_bad.p, sizeof(unsigned long long), nullptr);
+        hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        *out = v.release();
+    });
+}
+
+int vsaogm_volume_destroy(vsaogm_volume* v) {
+    return guarded([&] {
+        if (!v) return;
+        DeviceGuard guard(v->device);
+        (void)hipDeviceSynchronize();
+        delete v;
+    });
+}
+
+int vsaogm_volume_encode(vsaogm_volume* v, const float* xyz, const uint8_t* label, int64_t n,
+                         vsaogm_stream stream) {
+    return guarded([&] {
+        if (!v) fail(VSAOGM_EINVAL, "volume is NULL");
+        if (n < 0) fail(VSAOGM_EINVAL, "n must be >= 0");
+        if (n == 0) return;
+        if (!xyz || !label) fail(VSAOGM_EINVAL, "xyz and label must not be NULL");
+        DeviceGuard guard(v->device);
+        hipStream_t s = (hipStream_t)stream;
+        const int ranges = encode3_ranges(n);
+        if (n > v->cap_n || ranges > v->cap_ranges) {
+            const int64_t cap = std::max<int64_t>(n + n / 2, 4096);
+            const int cr = std::max(encode3_ranges(cap), ranges);
+            v->w_key.alloc_async(cap, s, "volume keys");
+            v->w_loc.alloc_async(cap, s, "volume local coordinates");
+            v->w_loc_lo.alloc_async(cap, s, "volume local residuals");
+            v->w_partial.alloc_async((size_t)cr * v->nkeys * v->halfp, s, "volume partial spectra");
+            v->cap_n = cap;
+            v->cap_ranges = cr;
+        }
+        Volume3Dev V{v->d_cx.p, v->d_cy.p, v->d_cz.p, v->tiles_x, v->tiles_y, v->tiles_z, v->lay[0], v->lay[1],
+                     v->lay[2], (v->lay[3] - v->lay[0]) / v->tiles_x, (v->lay[4] - v->lay[1]) / v->tiles_y,
+                     (v->lay[5] - v->lay[2]) / v->tiles_z};
+        hip_check(launch_encode3(xyz, label, n, V, v->d_rev.p, v->d_rev_d.p,
+                                 make_float4(v->max_rev[0], v->max_rev[1], v->max_rev[2], 0.f), v->nkeys, v->half,
+                                 v->halfp, v->w_key.p, v->w_loc.p, v->w_loc_lo.p, v->w_partial.p, v->d_bad.p,
+                                 v->d_omega.p, s),
+                  "volume encode");
+    });
+}
+
+int vsaogm_volume_take_rejected(vsaogm_volume* v, vsaogm_stream stream, int64_t* n_rejected) {
+    return guarded([&] {
+        if (!v || !n_rejected) fail(VSAOGM_EINVAL, "volume and n_rejected must not be NULL");
+        DeviceGuard guard(v->device);
+        hipStream_t s = (hipStream_t)stream;
+        unsigned long long c = 0;
+        hip_check(hipMemcpyAsync(&c, v->d_bad.p, sizeof(c), hipMemcpyDeviceToHost, s), "read counter");
+        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+        zero_async(v->d_bad.p, sizeof(c), s);
+        *n_rejected = (int64_t)c;
+    });
+}
+
+int vsaogm_volume_decode(vsaogm_volume* v, const vsaogm_grid3_desc* g, int32_t precision, float* heat,
+                         float* hmax, vsaogm_stream stream) {
+    return guarded([&] {
+        if (!v) fail(VSAOGM_EINVAL, "volume is NULL");
+        check_grid3(g);
+        if (!heat || !hmax) fail(VSAOGM_EINVAL, "heat and hmax must not be NULL");
+        if (precision != VSAOGM_BF16 && precision != VSAOGM_FP16 && precision != VSAOGM_BF16X3)
+            fail(VSAOGM_EINVAL, "volumes decode with VSAOGM_BF16, VSAOGM_FP16 or VSAOGM_BF16X3");
+        DeviceGuard guard(v->device);
+        hipStream_t s = (hipStream_t)stream;
+        Grid3Cache* gc = grid3_cache(v, g, s);
+        const size_t n16 = (size_t)g->ny * 2 * v->halfp;
+        const void* ey = nullptr;
+        const void* ey_lo = nullptr;
+        if (precision == VSAOGM_FP16) {
+            if (!gc->ey_h.p) {
+                gc->ey_h.alloc(n16, "y location table (fp16)");
+                hip_check(launch_table_split(v->d_theta_xy.p, 1, gc->local_y.p, g->ny, v->half, v->halfp, true,
+                                             gc->ey_h.p, nullptr, s), "y table");
+            }
+            ey = gc->ey_h.p;
+        } else {
+            if (!gc->ey_bf.p) {
+                gc->ey_bf.alloc(n16, "y location table (bf16)");
+                gc->ey_bf_lo.alloc(n16, "y location table (bf16 residual)");
+                hip_check(launch_table_split(v->d_theta_xy.p, 1, gc->local_y.p, g->ny, v->half, v->halfp, false,
+                                             gc->ey_bf.p, gc->ey_bf_lo.p, s), "y table");
+            }
+            ey = gc->ey_bf.p;
+            if (precision == VSAOGM_BF16X3) ey_lo = gc->ey_bf_lo.p;
+        }
+        const int set = decode_tile_set(precision);
+        DecodeLaunch d;
+        d.plan = decode_plan(precision, gc->ntiles[set], v->halfp, v->num_cus);
+        const size_t need = decode_partial_floats(precision, d.plan);
+        if (v->d_partial.n < need) v->d_partial.alloc_async(need, s, "decode partial sums");
+        hip_check(launch_norm(v->d_omega.p, v->nkeys, v->half, v->halfp, v->D, v->d_scale.p, v->d_omega_s.p,
+                              v->d_hmax_u.p, s),
+                  "norm launch");
+        d.tiles = gc->tiles[set].p;
+        d.ntiles = gc->ntiles[set];
+        d.col_tx = gc->col_tx.p;
+        d.ex = gc->ex32.p;
+        d.ey = ey;
+        d.ey_lo = ey_lo;
+        d.omega_s = v->d_omega_s.p;
+        d.halfp = v->halfp;
+        d.nx = g->nx;
+        d.ny = g->ny;
+        d.tiles_x = v->tiles_x;
+        d.out_scale = (float)(2.0 / (double)v->D);
+        d.heat = heat;
+        d.class_stride = (size_t)g->nx * g->ny * g->nz;
+        d.ez = gc->ez32.p;
+        d.hmax_u = v->d_hmax_u.p;
+        d.hmax = hmax;
+        d.partial = v->d_partial.p;
+        hip_check(launch_decode(precision, d, s), "volume decode launch");
+    });
+}
+
+int vsaogm_classify3(const vsaogm_grid3_desc* g, const float* heat, const float* hmax, int32_t r_occ,
+                     int32_t r_emp, float rho, float* ogm, uint8_t* label, int32_t device, vsaogm_stream stream) {
+    return guarded([&] {
+        check_grid3(g);
+        if (!heat || !hmax || !label) fail(VSAOGM_EINVAL, "heat, hmax and label must not be NULL");
+        if (r_occ < 0 || r_emp < 0 || r_occ > kMaxRadius || r_emp > kMaxRadius)
+            fail(VSAOGM_EINVAL, "radii must be in 0..24");
+        if (!is_finite(rho)) fail(VSAOGM_EINVAL, "rho must be finite");
+        DeviceGuard guard(device);
+        hipStream_t s = (hipStream_t)stream;
+        // ball offsets: class 0 (radius r_emp), then class 1 (radius r_occ)
+        std::vector<int4> off;
+        int n_emp = 0;
+        for (int p = 0; p < 2; ++p) {
+            const int r = p ? r_occ : r_emp;
+            for (int dz = -r; dz <= r; ++dz)
+                for (int dy = -r; dy <= r; ++dy)
+                    for (int dx = -r; dx <= r; ++dx)
+                        if (dx * dx + dy * dy + dz * dz <= r * r) off.push_back(make_int4(dx, dy, dz, 0));
+            if (p == 0) n_emp = (int)off.size();
+        }
+        const int n_occ = (int)off.size() - n_emp;
+        const size_t nvox = (size_t)g->nx * g->ny * g->nz;
+        void* scratch = nullptr;
+        const size_t off_bytes = (off.size() * sizeof(int4) + 255) / 256 * 256;
+        hip_check(hipMallocAsync(&scratch, off_bytes + 2 * nvox * sizeof(float), s), "classify scratch");
+        int4* d_off = static_cast<int4*>(scratch);
+        float* gbuf = reinterpret_cast<float*>(static_cast<char*>(scratch) + off_bytes);
+        hip_check(hipMemcpyAsync(d_off, off.data(), off.size() * sizeof(int4), hipMemcpyHostToDevice, s),
+                  "copy ball offsets");
+        const hipError_t e = launch_classify3(heat, hmax, g->nx, g->ny, g->nz, d_off, n_emp, n_occ, rho, gbuf, ogm,
+                                              label, s);
+        // the offsets are copied from this call's host vector: it must outlive the copy
+        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+        (void)hipFreeAsync(scratch, s);
+        hip_check(e, "classify launch");
     });
 }
 

@@ -26,6 +26,8 @@ EXPORTED = [
     "vsaogm_server_add_map", "vsaogm_server_get_map", "vsaogm_submit", "vsaogm_poll",
     "vsaogm_wait", "vsaogm_server_drain", "vsaogm_server_stats", "vsaogm_submit_many",
     "vsaogm_classify_ex", "vsaogm_decode_incremental", "vsaogm_request_bytes",
+    "vsaogm_volume_create", "vsaogm_volume_destroy", "vsaogm_volume_encode", "vsaogm_volume_take_rejected",
+    "vsaogm_volume_decode", "vsaogm_classify3",
 ]
 ACTIVATIONS = {"entropy": 0, "relu": 1, "tanh": 2, "sigmoid": 3}
 
@@ -47,6 +49,20 @@ class MapDesc(ctypes.Structure):
 class GridDesc(ctypes.Structure):
     _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double), ("res", ctypes.c_double),
                 ("nx", ctypes.c_int32), ("ny", ctypes.c_int32)]
+
+
+class VolumeDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("theta", ctypes.c_void_p),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("z0", ctypes.c_double),
+                ("x1", ctypes.c_double), ("y1", ctypes.c_double), ("z1", ctypes.c_double),
+                ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32), ("tiles_z", ctypes.c_int32),
+                ("device", ctypes.c_int32)]
+
+
+class Grid3Desc(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double), ("z0", ctypes.c_double),
+                ("res", ctypes.c_double), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32)]
 
 
 class ServerDesc(ctypes.Structure):
@@ -111,6 +127,12 @@ def load(path: str = LIB_PATH):
     L.vsaogm_server_drain.argtypes = [P]
     L.vsaogm_server_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.vsaogm_request_bytes.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(i64)]
+    L.vsaogm_volume_create.argtypes = [ctypes.POINTER(VolumeDesc), ctypes.POINTER(P)]
+    L.vsaogm_volume_destroy.argtypes = [P]
+    L.vsaogm_volume_encode.argtypes = [P, P, P, i64, P]
+    L.vsaogm_volume_take_rejected.argtypes = [P, P, ctypes.POINTER(i64)]
+    L.vsaogm_volume_decode.argtypes = [P, ctypes.POINTER(Grid3Desc), i32, P, P, P]
+    L.vsaogm_classify3.argtypes = [ctypes.POINTER(Grid3Desc), P, P, i32, i32, f32, P, P, i32, P]
     for name in EXPORTED:
         if name not in ("vsaogm_version", "vsaogm_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -245,6 +267,72 @@ def classify(heat, hmax, r_occ: int, r_emp: int, rho: float = 0.0, ogm=None, lab
                                         int(r_emp), float(rho), int(bool(normalize)),
                                         int(bool(square)), ACTIVATIONS[act], _ptr(ogm), _ptr(label),
                                         int(device), _stream(stream)))
+    return ogm, label
+
+
+def grid3_desc(grid, nx: int, ny: int, nz: int) -> Grid3Desc:
+    return Grid3Desc(float(grid[0]), float(grid[1]), float(grid[2]), float(grid[3]), int(nx), int(ny), int(nz))
+
+
+class Volume:
+    """2*tiles_x*tiles_y*tiles_z memory vectors of a 3-D map on one GPU."""
+
+    def __init__(self, theta: np.ndarray, layout: Sequence[float], tiles: Sequence[int], device: int = 0):
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        self.D = int(th.shape[0])
+        self.device = int(device)
+        d = VolumeDesc(self.D, th.ctypes.data, *[float(v) for v in layout], int(tiles[0]), int(tiles[1]),
+                       int(tiles[2]), self.device)
+        h = ctypes.c_void_p()
+        check(load().vsaogm_volume_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().vsaogm_volume_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def encode(self, xyz, label, stream=None):
+        assert xyz.is_contiguous() and label.is_contiguous() and xyz.shape[-1] == 3
+        check(load().vsaogm_volume_encode(self._h, _ptr(xyz), _ptr(label), int(xyz.shape[0]), _stream(stream)))
+
+    def take_rejected(self, stream=None) -> int:
+        n = ctypes.c_int64()
+        check(load().vsaogm_volume_take_rejected(self._h, _stream(stream), ctypes.byref(n)))
+        return int(n.value)
+
+    def decode(self, grid, nx: int, ny: int, nz: int, precision: str = "bf16x3", heat=None, hmax=None,
+               stream=None):
+        import torch
+        dev = torch.device("cuda", self.device)
+        if heat is None:
+            heat = torch.empty((2, nz, ny, nx), dtype=torch.float32, device=dev)
+        if hmax is None:
+            hmax = torch.empty(2, dtype=torch.float32, device=dev)
+        assert heat.is_contiguous() and tuple(heat.shape) == (2, nz, ny, nx)
+        g = grid3_desc(grid, nx, ny, nz)
+        check(load().vsaogm_volume_decode(self._h, ctypes.byref(g), PRECISIONS[precision], _ptr(heat), _ptr(hmax),
+                                          _stream(stream)))
+        return heat, hmax
+
+
+def classify3(heat, hmax, r_occ: int, r_emp: int, rho: float = 0.0, ogm=None, label=None, device: int = 0,
+              stream=None):
+    import torch
+    _, nz, ny, nx = heat.shape
+    if label is None:
+        label = torch.empty((nz, ny, nx), dtype=torch.uint8, device=heat.device)
+    if ogm is None:
+        ogm = torch.empty((nz, ny, nx), dtype=torch.float32, device=heat.device)
+    g = Grid3Desc(0.0, 0.0, 0.0, 1.0, int(nx), int(ny), int(nz))
+    check(load().vsaogm_classify3(ctypes.byref(g), _ptr(heat), _ptr(hmax), int(r_occ), int(r_emp), float(rho),
+                                  _ptr(ogm), _ptr(label), int(device), _stream(stream)))
     return ogm, label
 
 

@@ -1,0 +1,116 @@
+"""Volumes (3-D) on the GPU against the 3-D FP64 oracle.
+
+Bars as for plane maps: heatmaps within relative L2 1e-4 per class with the bf16 hi+lo operands
+(single-rounding bf16 / fp16 within their mantissa bounds), class maxima within 1e-4 and equal
+to the heatmap's own maxima, labels >= 99.9 % with every disagreement where the oracle's
+|OGM - rho| < 1e-3; ball-mask classification of the oracle's own similarities within 1e-4."""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_09066_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"bf16x3": 1e-4, "bf16": 2e-2, "fp16": 3e-3}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2408_09066_amd import native
+    native.load()
+    return torch
+
+
+def eight_tiles():
+    """room3d re-tiled 2 x 2 x 2 (two tile layers along z)."""
+    v = synth.volume("room3d")
+    v.tiles = (2, 2, 2)
+    v.name = "room3d_222"
+    return v
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_volume(name):
+    v = synth.volume("room3d") if name == "room3d" else eight_tiles()
+    return v, oracle.pipeline3(v)
+
+
+def gpu_volume(torch, v, precision):
+    from paper_2408_09066_amd import native
+    vol = native.Volume(v.theta, v.layout, v.tiles)
+    vol.encode(torch.from_numpy(v.xyz).cuda(), torch.from_numpy(v.label).cuda())
+    heat, hmax = vol.decode(v.grid, v.nx, v.ny, v.nz, precision)
+    ogm, lab = native.classify3(heat, hmax, v.r_occ, v.r_emp, v.rho)
+    torch.cuda.synchronize()
+    out = dict(heat=heat.cpu().numpy().astype(np.float64), hmax=hmax.cpu().numpy().astype(np.float64),
+               ogm=ogm.cpu().numpy().astype(np.float64), label=lab.cpu().numpy(), rejected=vol.take_rejected())
+    vol.close()
+    return out
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16", "fp16"])
+@pytest.mark.parametrize("name", ["room3d", "room3d_222"])
+def test_volume_pipeline_matches_oracle(torch_cuda, name, precision):
+    v, (om, P, m, H, ogm, lab) = oracle_volume(name)
+    g = gpu_volume(torch_cuda, v, precision)
+    assert g["rejected"] == 0
+    for psi in range(2):
+        e = np.linalg.norm(g["heat"][psi] - P[psi]) / np.linalg.norm(P[psi])
+        say(f"[gpu] volume {name} {precision} heat[{psi}] rel-L2 {e:.3e} max-abs {np.max(np.abs(g['heat'][psi] - P[psi])):.2e}")
+        assert e <= TOL[precision]
+        assert abs(g["hmax"][psi] - m[psi]) <= 2 * TOL[precision] * abs(m[psi])
+        assert g["hmax"][psi] == np.max(g["heat"][psi])
+    agree = float(np.mean(g["label"] == lab))
+    say(f"  labels agree {agree * 100:.4f}%")
+    if precision == "bf16x3":
+        bad = g["label"] != lab
+        assert agree >= 0.999
+        assert not bad.any() or np.max(np.abs(ogm[bad] - v.rho)) < 1e-3
+    else:
+        assert agree >= 0.98
+
+
+@pytest.mark.parametrize("radii", [(1, 1), (2, 1), (0, 3)])
+def test_classify3_on_oracle_heat(torch_cuda, radii):
+    from paper_2408_09066_amd import native
+    torch = torch_cuda
+    v, (om, P, m, H, ogm, lab) = oracle_volume("room3d")
+    P32 = P.astype(np.float32)
+    m_ref, _, ogm_ref, lab_ref = oracle.postprocess3(P32.astype(np.float64), radii[0], radii[1], 0.0)
+    o, l = native.classify3(torch.from_numpy(P32).cuda(), torch.from_numpy(m_ref.astype(np.float32)).cuda(),
+                            radii[0], radii[1], 0.0)
+    torch.cuda.synchronize()
+    o = o.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(o - ogm_ref)) < 1e-4
+    bad = l.cpu().numpy() != lab_ref
+    assert not bad.any() or np.max(np.abs(ogm_ref[bad])) < 1e-5
+
+
+def test_volume_errors(torch_cuda):
+    from paper_2408_09066_amd import native
+    torch = torch_cuda
+    v = synth.volume("room3d")
+    vol = native.Volume(v.theta, v.layout, v.tiles)
+    with pytest.raises(native.VsaogmError):
+        vol.decode(v.grid, v.nx, v.ny, v.nz, "fp32")
+    bad_theta = v.theta.copy()
+    bad_theta[3, 2] += 1.0
+    with pytest.raises(native.VsaogmError):
+        native.Volume(bad_theta, v.layout, v.tiles)
+    lab = v.label.copy()
+    lab[:5] = 7
+    vol.encode(torch.from_numpy(v.xyz).cuda(), torch.from_numpy(lab).cuda())
+    assert vol.take_rejected() == 5
+    vol.close()
