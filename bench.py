@@ -231,6 +231,60 @@ def heldout_accuracy(w, precision):
     return r
 
 
+def volume_benchmark(steps: int = 10, warmup: int = 2, precision: str = "bf16x3"):
+    """The 3-D extension at its benchmark size: one step = reset (memories zeroed), encode every
+    point, decode every voxel, classify with the ball mask."""
+    import torch
+    from paper_2408_09066_amd import native, synth
+    v = synth.volume("hall3d")
+    dev = torch.device("cuda", 0)
+    xyz = torch.from_numpy(v.xyz).to(dev)
+    lab = torch.from_numpy(v.label).to(dev)
+    heat = torch.empty((2, v.nz, v.ny, v.nx), dtype=torch.float32, device=dev)
+    hmax = torch.empty(2, dtype=torch.float32, device=dev)
+    ogm = torch.empty((v.nz, v.ny, v.nx), dtype=torch.float32, device=dev)
+    out = torch.empty((v.nz, v.ny, v.nx), dtype=torch.uint8, device=dev)
+    vol = native.Volume(v.theta, v.layout, v.tiles)
+    E = torch.cuda.Event
+    ev = {s_: [(E(enable_timing=True), E(enable_timing=True)) for _ in range(steps)] for s_ in native.STAGES}
+    for evs in ev.values():
+        for a, b in evs:
+            a.record()
+            b.record()
+
+    def step():
+        vol.reset()
+        vol.encode(xyz, lab)
+        vol.decode(v.grid, v.nx, v.ny, v.nz, precision, heat=heat, hmax=hmax)
+        native.classify3(heat, hmax, v.r_occ, v.r_emp, v.rho, ogm=ogm, label=out)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        for s_ in native.STAGES:
+            native.profile_events(s_, *ev[s_][i])
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    for s_ in native.STAGES:
+        native.profile_events(s_, None, None)
+    vol.close()
+    ms = {s_: float(np.mean([a.elapsed_time(b) for a, b in ev[s_]])) for s_ in native.STAGES}
+    nvox = v.nx * v.ny * v.nz
+    return {
+        "workload": (f"{v.name}: {v.n} points, D={v.D}, l={v.ell} m, {v.tiles[0]}x{v.tiles[1]}x{v.tiles[2]} tiles, "
+                     f"{v.nx}x{v.ny}x{v.nz} voxels at {v.grid[3]} m, ball r={v.r_occ}, {precision}"),
+        "ms_per_step": el / steps * 1e3,
+        "voxels_per_s": nvox * steps / el,
+        "points_per_s": v.n * steps / el,
+        "stage_ms": ms,
+        "encode_tcexp_per_s": v.n * (v.D // 2 - 1) / (ms["encode"] * 1e-3) / 1e12,
+        "decode_tflops_useful": 4.0 * v.D * nvox / (ms["decode"] * 1e-3) / 1e12,
+    }
+
+
 def stress_generate(n_updates: int, workers: int):
     """The large-map scenario and its first n_updates updates (host arrays), made before any
     GPU use: generation forks worker processes."""
@@ -329,6 +383,7 @@ def main() -> int:
                     help="also run the request-loop benchmark (256 updates of 16 maps)")
     ap.add_argument("--stress", type=int, default=200,
                     help="updates of the large-map stress run through the request loop (0 disables it)")
+    ap.add_argument("--volume", type=int, default=1, help="also run the 3-D benchmark")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
                     help="processes that generate the stress scans")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -458,6 +513,8 @@ def main() -> int:
     }
     m.close()
     result["accuracy"] = heldout_accuracy(w, args.precision)
+    if args.volume:
+        result["volume"] = volume_benchmark()
     if args.serving:
         result["serving"] = serving_benchmark()
     if stress_in is not None:

@@ -352,8 +352,13 @@ typedef struct {
 int vsaogm_volume_create(const vsaogm_volume_desc* desc, vsaogm_volume** out);
 int vsaogm_volume_destroy(vsaogm_volume* vol);
 
+/* Zero every memory of the volume (a fresh map of the same layout, cached grids kept).
+   Asynchronous on the stream; EINVAL for a NULL volume. */
+int vsaogm_volume_reset(vsaogm_volume* vol, vsaogm_stream stream);
+
 /* Algorithm 1 in 3-D: bundle n points (device float [n][3] world metres, device uint8 labels
-   0/1) into the memories; labels other than 0/1 are counted and skipped.  Asynchronous. */
+   0/1) into the memories; labels other than 0/1 are counted and skipped.  Asynchronous; work
+   buffers grow on demand.  EINVAL for n < 0, NULL pointers with n > 0, or n >= 2^31 - 2048. */
 int vsaogm_volume_encode(vsaogm_volume* vol, const float* xyz, const uint8_t* label, int64_t n,
                          vsaogm_stream stream);
 
@@ -370,7 +375,8 @@ int vsaogm_volume_decode(vsaogm_volume* vol, const vsaogm_grid3_desc* grid, int3
 
 /* Entropy classification of a volume (Algorithm 2 with a ball mask of radius r_occ for
    class 1 and r_emp for class 0, 0..24): ogm device float [nz][ny][nx] (or NULL), label
-   device uint8 [nz][ny][nx]. */
+   device uint8 [nz][ny][nx].  Asynchronous: a stream-ordered scratch of 2 nx ny nz floats
+   (the per-voxel entropy terms) is allocated and released on the stream. */
 int vsaogm_classify3(const vsaogm_grid3_desc* grid, const float* heat, const float* hmax,
                      int32_t r_occ, int32_t r_emp, float rho, float* ogm, uint8_t* label,
                      int32_t device, vsaogm_stream stream);

@@ -167,7 +167,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int* __restrict__ hist, i
             meta[1 + k] = e0;
             meta[1 + nkeys + k] = ne;
             meta[1 + 2 * nkeys + k] = cnt;
-            if (cnt > 0) version[k] += 1u;  // the memory changes: decodes of it are stale
+            if (version && cnt > 0) version[k] += 1u;  // the memory changes: decodes of it are stale
             for (int j = 0; j < ne; ++j) {
                 EChunk e;
                 e.key = k;
@@ -500,8 +500,7 @@ hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const
     const float2* xy2 = reinterpret_cast<const float2*>(xy);
     hipLaunchKernelGGL(k_assign, dim3(p.nchunks), dim3(kAssignChunk), nkeys * sizeof(int), s, xy2,
                        label, n, L, nkeys, p.nchunks, w.key, w.hist, w.n_bad);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), nkeys * sizeof(int), s, w.hist, p.nchunks, nkeys,
-                       p.echunk, w.table, w.meta, w.version);
+    launch_key_scan(w.hist, p.nchunks, nkeys, p.echunk, w.table, w.meta, w.version, s);
     if (4 * nkeys * (int)sizeof(int) <= 65536)
         hipLaunchKernelGGL(k_scatter<4>, dim3(p.nchunks), dim3(256), 4 * nkeys * sizeof(int), s, xy2, w.key,
                            n, L, nkeys, p.nchunks, bits_for(nkeys), w.hist, w.sorted, w.sorted_lo);
@@ -534,9 +533,20 @@ hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const
             break;
     }
     profile_end(kStageEncode, s);
-    hipLaunchKernelGGL(k_reduce, dim3((half + 255) / 256, nkeys), dim3(256), 0, s, w.partial,
-                       w.meta, nkeys, half, halfp, omega);
+    launch_key_reduce(w.partial, w.meta, nkeys, half, halfp, omega, s);
     return hipGetLastError();
+}
+
+void launch_key_scan(int* hist, int nchunks, int nkeys, int echunk, EChunk* table, int* meta, unsigned* version,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), nkeys * sizeof(int), s, hist, nchunks, nkeys, echunk,
+                       table, meta, version);
+}
+
+void launch_key_reduce(const float2* partial, const int* meta, int nkeys, int half, int halfp, float2* omega,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce, dim3((half + 255) / 256, nkeys), dim3(256), 0, s, partial, meta, nkeys, half,
+                       halfp, omega);
 }
 
 hipError_t launch_norm(const float2* omega, int nkeys, int half, int halfp, int D, float* scale,

@@ -73,16 +73,26 @@ struct Volume3Dev {
     int tx, ty, tz;
     double x0, y0, z0, wx, wy, wz;   // layout origin and tile widths
 };
-int encode3_ranges(int64_t n);  // point ranges of one encode (partial sums per range and memory)
+// Volume encode workspace: keys [n], local coordinates sorted by key (fp32 and residual,
+// (x, y, z, 0)) [n], histogram / table / meta / partial spectra as for planes (encode_plan).
+struct Encode3Work {
+    int* key;
+    float4* sorted;
+    float4* sorted_lo;
+    int* hist;
+    EChunk* table;
+    int* meta;
+    float2* partial;
+    unsigned long long* n_bad;
+};
 // Bucketing, encoding and bundling of n labelled points into omega [nkeys][halfp] (local frame).
 // rev: fp32 [halfp] (x, y, z, 0) revolutions per metre, 0 past half; rev_d: double [halfp][3].
 hipError_t launch_encode3(const float* xyz, const uint8_t* label, int64_t n, const Volume3Dev& V,
                           const float4* rev, const double* rev_d, float4 max_rev, int nkeys, int half,
-                          int halfp, int* key, float4* loc, float4* loc_lo, float2* partial,
-                          unsigned long long* n_bad, float2* omega, hipStream_t s);
+                          int halfp, const Encode3Work& w, float2* omega, hipStream_t s);
 // Ball entropy classification of a volume's heat [2][nz][ny][nx]; g is 2*nvox floats of scratch.
-hipError_t launch_classify3(const float* heat, const float* hmax, int nx, int ny, int nz, const int4* offsets,
-                            int n_emp, int n_occ, float rho, float* g, float* ogm, uint8_t* label, hipStream_t s);
+hipError_t launch_classify3(const float* heat, const float* hmax, int nx, int ny, int nz, int r_emp, int r_occ,
+                            float rho, float* g, float* ogm, uint8_t* label, hipStream_t s);
 
 // ---- error text shared by every entry point (map.hip) -------------------------------
 void set_last_error(const char* msg);
@@ -114,6 +124,16 @@ struct EncodePlan {
     int max_echunks;  // upper bound on work items: ceil(n / echunk) + nkeys
 };
 EncodePlan encode_plan(int64_t n, int halfp, int nkeys);
+
+// Shared by plane and volume encodes.  hist: key-major per-chunk key counts [nkeys][nchunks]
+// (+4 padding), turned in place into the stable counting sort's destination bases; then per
+// key its point count and work items of at most echunk points (table, meta as in EncodeWork;
+// version, if not NULL, is bumped for every key that received points).  One block.
+void launch_key_scan(int* hist, int nchunks, int nkeys, int echunk, EChunk* table, int* meta, unsigned* version,
+                     hipStream_t s);
+// omega[key] += the key's work-item partial spectra in work-item order.
+void launch_key_reduce(const float2* partial, const int* meta, int nkeys, int half, int halfp, float2* omega,
+                       hipStream_t s);
 
 hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const LayoutDev& L,
                          int nkeys, const float2* theta_rev, const double* theta_rev_d,

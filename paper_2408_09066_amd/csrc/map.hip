@@ -293,11 +293,12 @@ struct vsaogm_volume {
     DevBuf<float> d_scale;
     DevBuf<unsigned> d_hmax_u;
     DevBuf<unsigned long long> d_bad;
-    DevBuf<int> w_key;
-    DevBuf<float4> w_loc, w_loc_lo;
+    DevBuf<int> w_key, w_hist, w_meta;
+    DevBuf<float4> w_sorted, w_sorted_lo;
+    DevBuf<EChunk> w_table;
     DevBuf<float2> w_partial;
     int64_t cap_n = 0;
-    int cap_ranges = 0;
+    int cap_chunks = 0, cap_echunks = 0;
     DevBuf<float> d_partial;                   // split-tile partial sums of the decode
     std::unique_ptr<Grid3Cache> grid;
 };
@@ -1030,6 +1031,14 @@ int vsaogm_volume_destroy(vsaogm_volume* v) {
     });
 }
 
+int vsaogm_volume_reset(vsaogm_volume* v, vsaogm_stream stream) {
+    return guarded([&] {
+        if (!v) fail(VSAOGM_EINVAL, "volume is NULL");
+        DeviceGuard guard(v->device);
+        zero_async(v->d_omega.p, v->d_omega.n * sizeof(float2), (hipStream_t)stream);
+    });
+}
+
 int vsaogm_volume_encode(vsaogm_volume* v, const float* xyz, const uint8_t* label, int64_t n,
                          vsaogm_stream stream) {
     return guarded([&] {
@@ -1037,26 +1046,35 @@ int vsaogm_volume_encode(vsaogm_volume* v, const float* xyz, const uint8_t* labe
         if (n < 0) fail(VSAOGM_EINVAL, "n must be >= 0");
         if (n == 0) return;
         if (!xyz || !label) fail(VSAOGM_EINVAL, "xyz and label must not be NULL");
+        if (n > ((int64_t)1 << 31) - (int64_t)kAssignChunk * 2)
+            fail(VSAOGM_EINVAL, "n too large for one call");
         DeviceGuard guard(v->device);
         hipStream_t s = (hipStream_t)stream;
-        const int ranges = encode3_ranges(n);
-        if (n > v->cap_n || ranges > v->cap_ranges) {
+        const EncodePlan p = encode_plan(n, v->halfp, v->nkeys);
+        if (n > v->cap_n || p.nchunks > v->cap_chunks || p.max_echunks > v->cap_echunks) {
             const int64_t cap = std::max<int64_t>(n + n / 2, 4096);
-            const int cr = std::max(encode3_ranges(cap), ranges);
+            const EncodePlan q = encode_plan(cap, v->halfp, v->nkeys);
+            const int chunks = std::max(q.nchunks, p.nchunks), echunks = std::max(q.max_echunks, p.max_echunks);
             v->w_key.alloc_async(cap, s, "volume keys");
-            v->w_loc.alloc_async(cap, s, "volume local coordinates");
-            v->w_loc_lo.alloc_async(cap, s, "volume local residuals");
-            v->w_partial.alloc_async((size_t)cr * v->nkeys * v->halfp, s, "volume partial spectra");
+            v->w_sorted.alloc_async(cap, s, "volume sorted local coordinates");
+            v->w_sorted_lo.alloc_async(cap, s, "volume sorted residuals");
+            // + 4: the scan reads the histogram in aligned groups of four
+            v->w_hist.alloc_async((size_t)chunks * v->nkeys + 4, s, "volume histogram");
+            v->w_table.alloc_async(echunks, s, "volume work table");
+            v->w_partial.alloc_async((size_t)echunks * v->halfp, s, "volume partial spectra");
+            if (!v->w_meta.p) v->w_meta.alloc_async(1 + 3 * (size_t)v->nkeys, s, "volume encode meta");
             v->cap_n = cap;
-            v->cap_ranges = cr;
+            v->cap_chunks = chunks;
+            v->cap_echunks = echunks;
         }
         Volume3Dev V{v->d_cx.p, v->d_cy.p, v->d_cz.p, v->tiles_x, v->tiles_y, v->tiles_z, v->lay[0], v->lay[1],
                      v->lay[2], (v->lay[3] - v->lay[0]) / v->tiles_x, (v->lay[4] - v->lay[1]) / v->tiles_y,
                      (v->lay[5] - v->lay[2]) / v->tiles_z};
+        Encode3Work w{v->w_key.p, v->w_sorted.p, v->w_sorted_lo.p, v->w_hist.p, v->w_table.p, v->w_meta.p,
+                      v->w_partial.p, v->d_bad.p};
         hip_check(launch_encode3(xyz, label, n, V, v->d_rev.p, v->d_rev_d.p,
                                  make_float4(v->max_rev[0], v->max_rev[1], v->max_rev[2], 0.f), v->nkeys, v->half,
-                                 v->halfp, v->w_key.p, v->w_loc.p, v->w_loc_lo.p, v->w_partial.p, v->d_bad.p,
-                                 v->d_omega.p, s),
+                                 v->halfp, w, v->d_omega.p, s),
                   "volume encode");
     });
 }
@@ -1145,31 +1163,11 @@ int vsaogm_classify3(const vsaogm_grid3_desc* g, const float* heat, const float*
         if (!is_finite(rho)) fail(VSAOGM_EINVAL, "rho must be finite");
         DeviceGuard guard(device);
         hipStream_t s = (hipStream_t)stream;
-        // ball offsets: class 0 (radius r_emp), then class 1 (radius r_occ)
-        std::vector<int4> off;
-        int n_emp = 0;
-        for (int p = 0; p < 2; ++p) {
-            const int r = p ? r_occ : r_emp;
-            for (int dz = -r; dz <= r; ++dz)
-                for (int dy = -r; dy <= r; ++dy)
-                    for (int dx = -r; dx <= r; ++dx)
-                        if (dx * dx + dy * dy + dz * dz <= r * r) off.push_back(make_int4(dx, dy, dz, 0));
-            if (p == 0) n_emp = (int)off.size();
-        }
-        const int n_occ = (int)off.size() - n_emp;
         const size_t nvox = (size_t)g->nx * g->ny * g->nz;
-        void* scratch = nullptr;
-        const size_t off_bytes = (off.size() * sizeof(int4) + 255) / 256 * 256;
-        hip_check(hipMallocAsync(&scratch, off_bytes + 2 * nvox * sizeof(float), s), "classify scratch");
-        int4* d_off = static_cast<int4*>(scratch);
-        float* gbuf = reinterpret_cast<float*>(static_cast<char*>(scratch) + off_bytes);
-        hip_check(hipMemcpyAsync(d_off, off.data(), off.size() * sizeof(int4), hipMemcpyHostToDevice, s),
-                  "copy ball offsets");
-        const hipError_t e = launch_classify3(heat, hmax, g->nx, g->ny, g->nz, d_off, n_emp, n_occ, rho, gbuf, ogm,
-                                              label, s);
-        // the offsets are copied from this call's host vector: it must outlive the copy
-        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-        (void)hipFreeAsync(scratch, s);
+        float* gbuf = nullptr;
+        hip_check(hipMallocAsync((void**)&gbuf, 2 * nvox * sizeof(float), s), "classify scratch");
+        const hipError_t e = launch_classify3(heat, hmax, g->nx, g->ny, g->nz, r_emp, r_occ, rho, gbuf, ogm, label, s);
+        (void)hipFreeAsync(gbuf, s);
         hip_check(e, "classify launch");
     });
 }

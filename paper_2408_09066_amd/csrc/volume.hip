@@ -4,11 +4,14 @@
 // offsets dx^2 + dy^2 + dz^2 <= r^2.
 //
 //   k3_assign   nearest tile (exact double-precision argmin over the 3x3x3 neighbourhood of the
-//               per-axis guess, lowest index on ties), key 2*beta+psi, tile-local coordinates
-//   k3_encode   per (bin block, memory, range of points): sum of exp(2 pi i t) over the range's
-//               points of that memory, in point order (deterministic), t in revolutions; a range
-//               whose phases could exceed kWidePhaseRev forms and wraps them in double precision
-//   k3_reduce   memories += the ranges' partial sums, in range order
+//               per-axis guess, lowest index on ties), key 2*beta+psi, label check, per-chunk key
+//               histogram; the scan of the histogram into sort offsets and work items, and the
+//               final reduction, are the plane encoder's (encode.hip)
+//   k3_scatter  stable counting sort of the tile-local coordinates (and their rounding
+//               residuals) by key
+//   k3_encode   per (work item of one memory's sorted points, block of bins): sum of
+//               exp(2 pi i t), t in revolutions, two points per step; a work item whose phases
+//               could exceed kWidePhaseRev forms and wraps them in double precision
 //   k3_entropy  -Q ln Q with Q = (P / max P)^2 per voxel and class
 //   k3_classify ball sums of the entropy terms, softmax difference tanh((H1 - H0)/2), threshold
 // The similarity of every voxel is the same GEMM as for maps, per z slice, with the slice's
@@ -18,10 +21,6 @@
 namespace vsaogm {
 namespace {
 
-constexpr int kV3Threads = 256;
-constexpr int kV3Bpt = 4;          // bins per thread
-constexpr int kV3Range = 4096;     // points per encode range
-constexpr int kV3Stage = 1024;     // points staged in LDS at a time
 
 struct Layout3Dev {
     const double* cx;
@@ -58,126 +57,204 @@ __device__ int nearest_tile3(double x, double y, double z, const Layout3Dev& L) 
     return best;
 }
 
-__global__ __launch_bounds__(256) void k3_assign(const float* __restrict__ xyz, const uint8_t* __restrict__ label,
-                                                 int64_t n, Layout3Dev L, int* __restrict__ key,
-                                                 float4* __restrict__ loc, float4* __restrict__ loc_lo,
-                                                 unsigned long long* __restrict__ n_bad) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const double x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
-    const unsigned l = label[i];
-    int k = -1;
-    float4 hi = make_float4(0.f, 0.f, 0.f, 0.f), lo = hi;
-    if (l <= 1u) {
-        const int b = nearest_tile3(x, y, z, L);
-        k = 2 * b + (int)l;
-        const int tx = b % L.tx, ty = (b / L.tx) % L.ty, tz = b / (L.tx * L.ty);
-        const double lx = x - L.cx[tx], ly = y - L.cy[ty], lz = z - L.cz[tz];
-        hi = make_float4((float)lx, (float)ly, (float)lz, 0.f);
-        lo = make_float4((float)(lx - (double)hi.x), (float)(ly - (double)hi.y), (float)(lz - (double)hi.z), 0.f);
-    } else {
-        atomicAdd(n_bad, 1ull);
+// One point per thread, blocks of kAssignChunk points; hist[key][chunk] = the chunk's count.
+__global__ __launch_bounds__(kAssignChunk) void k3_assign(const float* __restrict__ xyz,
+                                                          const uint8_t* __restrict__ label, int64_t n,
+                                                          Layout3Dev L, int nkeys, int nchunks,
+                                                          int* __restrict__ key_out, int* __restrict__ hist,
+                                                          unsigned long long* __restrict__ n_bad) {
+    extern __shared__ int sh_hist[];
+    for (int k = threadIdx.x; k < nkeys; k += blockDim.x) sh_hist[k] = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * kAssignChunk + threadIdx.x;
+    if (i < n) {
+        const unsigned l = label[i];
+        int k = -1;
+        if (l <= 1u) k = 2 * nearest_tile3(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], L) + (int)l;
+        if (k < 0)
+            atomicAdd(n_bad, 1ull);
+        else
+            atomicAdd(&sh_hist[k], 1);
+        key_out[i] = k;
     }
-    key[i] = k;
-    loc[i] = hi;
-    loc_lo[i] = lo;
+    __syncthreads();
+    for (int k = threadIdx.x; k < nkeys; k += blockDim.x) hist[(size_t)k * nchunks + blockIdx.x] = sh_hist[k];
 }
 
-// Block (bin block, key, range): the range's points are staged in LDS; each matching point
-// (a uniform test) adds exp(2 pi i t) to the thread's kV3Bpt bins.
-__global__ __launch_bounds__(kV3Threads) void k3_encode(const int* __restrict__ key,
-                                                        const float4* __restrict__ loc,
-                                                        const float4* __restrict__ loc_lo, int64_t n,
-                                                        const float4* __restrict__ rev,
-                                                        const double* __restrict__ rev_d, float4 max_rev,
-                                                        int halfp, int nkeys, float2* __restrict__ partial) {
-    const int bb = blockIdx.x, kq = blockIdx.y, range = blockIdx.z;
-    const int64_t p0 = (int64_t)range * kV3Range, p1 = min(p0 + kV3Range, n);
-    __shared__ int sh_key[kV3Stage];
-    __shared__ float4 sh_loc[kV3Stage];
-    __shared__ float sh_max[kV3Threads / 64];
-
-    // largest phase (revolutions) the key's points of this range can reach
-    float bound = 0.f;
-    for (int64_t i = p0 + threadIdx.x; i < p1; i += kV3Threads)
-        if (key[i] == kq) {
-            const float4 v = loc[i];
-            bound = fmaxf(bound, fabsf(v.x) * max_rev.x + fabsf(v.y) * max_rev.y + fabsf(v.z) * max_rev.z);
+// Stable counting-sort scatter, one block of WAVES wavefronts per chunk of kAssignChunk points;
+// wave w takes the chunk's w-th part.  Each wave starts every key at the chunk's base plus the
+// counts of the earlier waves; within a round of 64 lanes, a point's rank among equal keys comes
+// from ballots over the key's bits.  The destination receives the tile-local coordinates,
+// formed in double precision and split into fp32 value and residual.
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k3_scatter(const float* __restrict__ xyz, const int* __restrict__ key,
+                                                         int64_t n, Layout3Dev L, int nkeys, int nchunks,
+                                                         int key_bits, const int* __restrict__ base,
+                                                         float4* __restrict__ sorted,
+                                                         float4* __restrict__ sorted_lo) {
+    extern __shared__ int run[];   // [WAVES][nkeys]
+    constexpr int Q = kAssignChunk / WAVES, R = Q / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t q0 = (int64_t)blockIdx.x * kAssignChunk + (int64_t)wave * Q;
+    int kk[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = q0 + r * 64 + lane;
+        kk[r] = (i < n) ? key[i] : -1;
+    }
+    for (int k = threadIdx.x; k < WAVES * nkeys; k += blockDim.x) run[k] = 0;
+    __syncthreads();
+    int* my = run + wave * nkeys;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (kk[r] >= 0) atomicAdd(&my[kk[r]], 1);
+    __syncthreads();
+    for (int k = threadIdx.x; k < nkeys; k += blockDim.x) {
+        int acc = base[(size_t)k * nchunks + blockIdx.x];
+        for (int w = 0; w < WAVES; ++w) {
+            const int c = run[w * nkeys + k];
+            run[w * nkeys + k] = acc;
+            acc += c;
         }
+    }
+    __syncthreads();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int k = kk[r];
+        const unsigned uk = (k < 0) ? (unsigned)nkeys : (unsigned)k;
+        uint64_t same = ~0ull;
+        for (int b = 0; b < key_bits; ++b) {
+            const bool bit = (uk >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            same &= bit ? m : ~m;
+        }
+        if (k >= 0) {
+            const int64_t i = q0 + r * 64 + lane;
+            const int dest = my[k] + __popcll(same & lt_mask);
+            const int b = k >> 1;
+            const int tx = b % L.tx, ty = (b / L.tx) % L.ty, tz = b / (L.tx * L.ty);
+            const double lx = (double)xyz[3 * i] - L.cx[tx], ly = (double)xyz[3 * i + 1] - L.cy[ty],
+                         lz = (double)xyz[3 * i + 2] - L.cz[tz];
+            const float fx = (float)lx, fy = (float)ly, fz = (float)lz;
+            sorted[dest] = make_float4(fx, fy, fz, 0.f);
+            sorted_lo[dest] = make_float4((float)(lx - (double)fx), (float)(ly - (double)fy), (float)(lz - (double)fz), 0.f);
+            if ((same & lt_mask) == 0) my[k] += __popcll(same);
+        }
+        __syncthreads();
+    }
+}
+
+// Partial spectrum of one work item (consecutive sorted points of one memory) for one block of
+// bins; thread t owns bins b0 + t + j kEncodeThreads, j < BPT.  Consecutive points go in pairs:
+//   exp(i a) + exp(i b) = 2 cos((a - b) / 2) exp(i (a + b) / 2),
+// three hardware sine/cosine evaluations per two points, with the pair's mid-point and
+// half-difference formed once in LDS for all bins.
+template <int BPT>
+__global__ __launch_bounds__(kEncodeThreads) void k3_encode(const float4* __restrict__ sorted,
+                                                            const float4* __restrict__ sorted_lo,
+                                                            const EChunk* __restrict__ table,
+                                                            const int* __restrict__ meta,
+                                                            const float4* __restrict__ rev,
+                                                            const double* __restrict__ rev_d, float4 max_rev,
+                                                            int halfp, float2* __restrict__ partial) {
+    const int c = blockIdx.x;
+    if (c >= meta[0]) return;
+    const EChunk e = table[c];
+    const int b0 = blockIdx.y * (kEncodeThreads * BPT) + threadIdx.x;
+    const float4* __restrict__ p = sorted + e.start;
+    __shared__ float sh_max[kEncodeThreads / 64];
+    __shared__ float4 sh_mid[kEncodeChunk / 2], sh_hd[kEncodeChunk / 2];
+
+    // largest phase (revolutions) any bin can reach on the work item's points
+    float bound = 0.f;
+    for (int q = threadIdx.x; q < e.len; q += kEncodeThreads) {
+        const float4 v = p[q];
+        bound = fmaxf(bound, fabsf(v.x) * max_rev.x + fabsf(v.y) * max_rev.y + fabsf(v.z) * max_rev.z);
+    }
     for (int off = 32; off > 0; off >>= 1) bound = fmaxf(bound, __shfl_xor(bound, off));
     if ((threadIdx.x & 63) == 0) sh_max[threadIdx.x >> 6] = bound;
     __syncthreads();
     float wmax = 0.f;
 #pragma unroll
-    for (int w = 0; w < kV3Threads / 64; ++w) wmax = fmaxf(wmax, sh_max[w]);
-    const bool wide = wmax > kWidePhaseRev;
+    for (int w = 0; w < kEncodeThreads / 64; ++w) wmax = fmaxf(wmax, sh_max[w]);
 
-    const int b0 = bb * (kV3Threads * kV3Bpt) + threadIdx.x;
-    float ax[kV3Bpt], ay[kV3Bpt], az[kV3Bpt], re[kV3Bpt], im[kV3Bpt];
+    float re[BPT], im[BPT];
 #pragma unroll
-    for (int j = 0; j < kV3Bpt; ++j) {
-        const int k = b0 + j * kV3Threads;
-        const float4 t = (k < halfp) ? rev[k] : make_float4(0.f, 0.f, 0.f, 0.f);
-        ax[j] = t.x;
-        ay[j] = t.y;
-        az[j] = t.z;
-        re[j] = im[j] = 0.f;
-    }
-    for (int64_t s0 = p0; s0 < p1; s0 += kV3Stage) {
-        const int m = (int)min((int64_t)kV3Stage, p1 - s0);
-        __syncthreads();  // the previous stage's reads are done
-        for (int q = threadIdx.x; q < m; q += kV3Threads) {
-            sh_key[q] = key[s0 + q];
-            sh_loc[q] = loc[s0 + q];
+    for (int j = 0; j < BPT; ++j) re[j] = im[j] = 0.f;
+    if (wmax <= kWidePhaseRev) {
+        float ax[BPT], ay[BPT], az[BPT];
+#pragma unroll
+        for (int j = 0; j < BPT; ++j) {
+            const int k = b0 + j * kEncodeThreads;
+            const float4 t = (k < halfp) ? rev[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+            ax[j] = t.x;
+            ay[j] = t.y;
+            az[j] = t.z;
+        }
+        const int npairs = e.len >> 1;
+        for (int q = threadIdx.x; q < npairs; q += kEncodeThreads) {
+            const float4 a = p[2 * q], b = p[2 * q + 1];
+            sh_mid[q] = make_float4(0.5f * (a.x + b.x), 0.5f * (a.y + b.y), 0.5f * (a.z + b.z), 0.f);
+            sh_hd[q] = make_float4(0.5f * (a.x - b.x), 0.5f * (a.y - b.y), 0.5f * (a.z - b.z), 0.f);
         }
         __syncthreads();
-        for (int q = 0; q < m; ++q) {
-            if (sh_key[q] != kq) continue;   // uniform over the block
-            const float4 v = sh_loc[q];
-            if (!wide) {
+#pragma unroll 2
+        for (int q = 0; q < npairs; ++q) {
+            const float4 m = sh_mid[q], d = sh_hd[q];
 #pragma unroll
-                for (int j = 0; j < kV3Bpt; ++j) {
-                    const float t = __builtin_fmaf(ax[j], v.x, __builtin_fmaf(ay[j], v.y, az[j] * v.z));
-                    re[j] += __builtin_amdgcn_cosf(t);
-                    im[j] += __builtin_amdgcn_sinf(t);
-                }
-            } else {
-                const float4 lo = loc_lo[s0 + q];
-                const double x = (double)v.x + (double)lo.x, y = (double)v.y + (double)lo.y,
-                             z = (double)v.z + (double)lo.z;
+            for (int j = 0; j < BPT; ++j) {
+                const float tm = __builtin_fmaf(ax[j], m.x, __builtin_fmaf(ay[j], m.y, az[j] * m.z));
+                const float td = __builtin_fmaf(ax[j], d.x, __builtin_fmaf(ay[j], d.y, az[j] * d.z));
+                const float cd = __builtin_amdgcn_cosf(td);
+                re[j] = __builtin_fmaf(cd, __builtin_amdgcn_cosf(tm), re[j]);
+                im[j] = __builtin_fmaf(cd, __builtin_amdgcn_sinf(tm), im[j]);
+            }
+        }
 #pragma unroll
-                for (int j = 0; j < kV3Bpt; ++j) {
-                    const int k = min(b0 + j * kV3Threads, halfp - 1);
-                    const double t = rev_d[3 * k] * x + rev_d[3 * k + 1] * y + rev_d[3 * k + 2] * z;
-                    const float r = (float)(t - rint(t));
-                    re[j] += __builtin_amdgcn_cosf(r);
-                    im[j] += __builtin_amdgcn_sinf(r);
-                }
+        for (int j = 0; j < BPT; ++j) {
+            re[j] *= 2.f;
+            im[j] *= 2.f;
+        }
+        if (e.len & 1) {
+            const float4 a = p[e.len - 1];
+#pragma unroll
+            for (int j = 0; j < BPT; ++j) {
+                const float t = __builtin_fmaf(ax[j], a.x, __builtin_fmaf(ay[j], a.y, az[j] * a.z));
+                re[j] += __builtin_amdgcn_cosf(t);
+                im[j] += __builtin_amdgcn_sinf(t);
+            }
+        }
+    } else {
+        // large arguments: phase formed and wrapped to [-1/2, 1/2] revolutions in double
+        // precision from the double-float local coordinates
+        const float4* __restrict__ plo = sorted_lo + e.start;
+        double ax[BPT], ay[BPT], az[BPT];
+#pragma unroll
+        for (int j = 0; j < BPT; ++j) {
+            const int k = min(b0 + j * kEncodeThreads, halfp - 1);
+            ax[j] = rev_d[3 * k];
+            ay[j] = rev_d[3 * k + 1];
+            az[j] = rev_d[3 * k + 2];
+        }
+        for (int q = 0; q < e.len; ++q) {
+            const float4 a = p[q], al = plo[q];
+            const double x = (double)a.x + (double)al.x, y = (double)a.y + (double)al.y,
+                         z = (double)a.z + (double)al.z;
+#pragma unroll
+            for (int j = 0; j < BPT; ++j) {
+                const double t = ax[j] * x + ay[j] * y + az[j] * z;
+                const float r = (float)(t - rint(t));
+                re[j] += __builtin_amdgcn_cosf(r);
+                im[j] += __builtin_amdgcn_sinf(r);
             }
         }
     }
-    float2* out = partial + ((size_t)range * nkeys + kq) * halfp;
 #pragma unroll
-    for (int j = 0; j < kV3Bpt; ++j) {
-        const int k = b0 + j * kV3Threads;
-        if (k < halfp) out[k] = make_float2(re[j], im[j]);
+    for (int j = 0; j < BPT; ++j) {
+        const int k = b0 + j * kEncodeThreads;
+        if (k < halfp) partial[(size_t)c * halfp + k] = make_float2(re[j], im[j]);
     }
-}
-
-__global__ __launch_bounds__(256) void k3_reduce(const float2* __restrict__ partial, int nranges, int nkeys,
-                                                 int half, int halfp, float2* __restrict__ omega) {
-    const int key = blockIdx.y;
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= half) return;
-    float sr = 0.f, si = 0.f;
-    for (int r = 0; r < nranges; ++r) {
-        const float2 v = partial[((size_t)r * nkeys + key) * halfp + k];
-        sr += v.x;
-        si += v.y;
-    }
-    float2* o = omega + (size_t)key * halfp + k;
-    const float2 w = *o;
-    *o = make_float2(w.x + sr, w.y + si);
 }
 
 __global__ __launch_bounds__(256) void k3_entropy(const float* __restrict__ heat, const float* __restrict__ hmax,
@@ -196,64 +273,93 @@ __global__ __launch_bounds__(256) void k3_entropy(const float* __restrict__ heat
     }
 }
 
-// Ball offsets of both classes: off[0 .. n_emp) class 0, off[n_emp .. n_emp + n_occ) class 1.
-__global__ __launch_bounds__(256) void k3_classify(const float* __restrict__ g, int nx, int ny, int nz,
-                                                   const int4* __restrict__ off, int n_emp, int n_occ,
-                                                   float rho, float* __restrict__ ogm, uint8_t* __restrict__ label) {
+// Sum of g over the ball |d| <= r around voxel (i, j, l), offsets visited with dz, then dy, then
+// dx increasing; voxels outside the volume contribute nothing.
+__device__ inline float ball_sum(const float* __restrict__ g, int i, int j, int l, int nx, int ny, int nz, int r) {
+    float s = 0.f;
+    const int r2 = r * r;
+    for (int dz = -r; dz <= r; ++dz) {
+        const int ll = l + dz;
+        for (int dy = -r; dy <= r; ++dy) {
+            const int jj = j + dy;
+            const int e2 = r2 - dz * dz - dy * dy;
+            if (e2 < 0 || ll < 0 || ll >= nz || jj < 0 || jj >= ny) continue;
+            const float* row = g + ((int64_t)ll * ny + jj) * nx;
+            for (int dx = -r; dx <= r; ++dx) {
+                const int ii = i + dx;
+                if (dx * dx <= e2 && ii >= 0 && ii < nx) s += row[ii];
+            }
+        }
+    }
+    return s;
+}
+
+// Class 0 sums over the ball of radius r_emp, class 1 over radius r_occ.
+__global__ __launch_bounds__(256) void k3_classify(const float* __restrict__ g, int nx, int ny, int nz, int r_emp,
+                                                   int r_occ, float rho, float* __restrict__ ogm,
+                                                   uint8_t* __restrict__ label) {
     const int64_t nvox = (int64_t)nx * ny * nz;
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (v >= nvox) return;
     const int i = (int)(v % nx), j = (int)((v / nx) % ny), l = (int)(v / ((int64_t)nx * ny));
-    float h[2] = {0.f, 0.f};
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-        const int o0 = p ? n_emp : 0, o1 = p ? n_emp + n_occ : n_emp;
-        const float* gp = g + p * nvox;
-        float s = 0.f;
-        for (int o = o0; o < o1; ++o) {
-            const int4 d = off[o];
-            const int ii = i + d.x, jj = j + d.y, ll = l + d.z;
-            if (ii < 0 || jj < 0 || ll < 0 || ii >= nx || jj >= ny || ll >= nz) continue;
-            s += gp[((int64_t)ll * ny + jj) * nx + ii];
-        }
-        h[p] = s;
-    }
-    const float o = tanhf(0.5f * (h[1] - h[0]));
+    const float h0 = ball_sum(g, i, j, l, nx, ny, nz, r_emp);
+    const float h1 = ball_sum(g + nvox, i, j, l, nx, ny, nz, r_occ);
+    const float o = tanhf(0.5f * (h1 - h0));
     if (ogm) ogm[v] = o;
     label[v] = (o >= rho) ? 1 : 0;
 }
 
-}  // namespace
+int key_bits_for(int v) {
+    int b = 0;
+    while ((1 << b) <= v) ++b;
+    return b;
+}
 
-int encode3_ranges(int64_t n) { return (int)((n + kV3Range - 1) / kV3Range); }
+}  // namespace
 
 hipError_t launch_encode3(const float* xyz, const uint8_t* label, int64_t n, const Volume3Dev& V,
                           const float4* rev, const double* rev_d, float4 max_rev, int nkeys, int half,
-                          int halfp, int* key, float4* loc, float4* loc_lo, float2* partial,
-                          unsigned long long* n_bad, float2* omega, hipStream_t s) {
+                          int halfp, const Encode3Work& w, float2* omega, hipStream_t s) {
     if (n <= 0) return hipSuccess;
+    const EncodePlan p = encode_plan(n, halfp, nkeys);
     Layout3Dev L{V.cx, V.cy, V.cz, V.tx, V.ty, V.tz, V.x0, V.y0, V.z0, V.wx, V.wy, V.wz};
-    hipLaunchKernelGGL(k3_assign, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xyz, label, n, L, key, loc,
-                       loc_lo, n_bad);
-    const int nranges = encode3_ranges(n);
-    const int binblocks = (halfp + kV3Threads * kV3Bpt - 1) / (kV3Threads * kV3Bpt);
+    hipLaunchKernelGGL(k3_assign, dim3(p.nchunks), dim3(kAssignChunk), nkeys * sizeof(int), s, xyz, label, n, L,
+                       nkeys, p.nchunks, w.key, w.hist, w.n_bad);
+    launch_key_scan(w.hist, p.nchunks, nkeys, p.echunk, w.table, w.meta, nullptr, s);
+    if (4 * nkeys * (int)sizeof(int) <= 65536)
+        hipLaunchKernelGGL(k3_scatter<4>, dim3(p.nchunks), dim3(256), 4 * nkeys * sizeof(int), s, xyz, w.key, n, L,
+                           nkeys, p.nchunks, key_bits_for(nkeys), w.hist, w.sorted, w.sorted_lo);
+    else
+        hipLaunchKernelGGL(k3_scatter<1>, dim3(p.nchunks), dim3(64), nkeys * sizeof(int), s, xyz, w.key, n, L,
+                           nkeys, p.nchunks, key_bits_for(nkeys), w.hist, w.sorted, w.sorted_lo);
+    const dim3 eg(p.max_echunks, p.binblocks);
     profile_begin(kStageEncode, s);
-    hipLaunchKernelGGL(k3_encode, dim3(binblocks, nkeys, nranges), dim3(kV3Threads), 0, s, key, loc, loc_lo, n, rev,
-                       rev_d, max_rev, halfp, nkeys, partial);
+    switch (p.bpt) {
+        case 1:
+            hipLaunchKernelGGL(k3_encode<1>, eg, dim3(kEncodeThreads), 0, s, w.sorted, w.sorted_lo, w.table, w.meta,
+                               rev, rev_d, max_rev, halfp, w.partial);
+            break;
+        case 2:
+            hipLaunchKernelGGL(k3_encode<2>, eg, dim3(kEncodeThreads), 0, s, w.sorted, w.sorted_lo, w.table, w.meta,
+                               rev, rev_d, max_rev, halfp, w.partial);
+            break;
+        default:
+            hipLaunchKernelGGL(k3_encode<4>, eg, dim3(kEncodeThreads), 0, s, w.sorted, w.sorted_lo, w.table, w.meta,
+                               rev, rev_d, max_rev, halfp, w.partial);
+            break;
+    }
     profile_end(kStageEncode, s);
-    hipLaunchKernelGGL(k3_reduce, dim3((half + 255) / 256, nkeys), dim3(256), 0, s, partial, nranges, nkeys, half,
-                       halfp, omega);
+    launch_key_reduce(w.partial, w.meta, nkeys, half, halfp, omega, s);
     return hipGetLastError();
 }
 
-hipError_t launch_classify3(const float* heat, const float* hmax, int nx, int ny, int nz, const int4* offsets,
-                            int n_emp, int n_occ, float rho, float* g, float* ogm, uint8_t* label, hipStream_t s) {
+hipError_t launch_classify3(const float* heat, const float* hmax, int nx, int ny, int nz, int r_emp, int r_occ,
+                            float rho, float* g, float* ogm, uint8_t* label, hipStream_t s) {
     const int64_t nvox = (int64_t)nx * ny * nz;
     const unsigned blocks = (unsigned)((nvox + 255) / 256);
     profile_begin(kStageClassify, s);
     hipLaunchKernelGGL(k3_entropy, dim3(blocks), dim3(256), 0, s, heat, hmax, nvox, g);
-    hipLaunchKernelGGL(k3_classify, dim3(blocks), dim3(256), 0, s, g, nx, ny, nz, offsets, n_emp, n_occ, rho, ogm,
-                       label);
+    hipLaunchKernelGGL(k3_classify, dim3(blocks), dim3(256), 0, s, g, nx, ny, nz, r_emp, r_occ, rho, ogm, label);
     profile_end(kStageClassify, s);
     return hipGetLastError();
 }

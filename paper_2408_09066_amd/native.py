@@ -26,8 +26,8 @@ EXPORTED = [
     "vsaogm_server_add_map", "vsaogm_server_get_map", "vsaogm_submit", "vsaogm_poll",
     "vsaogm_wait", "vsaogm_server_drain", "vsaogm_server_stats", "vsaogm_submit_many",
     "vsaogm_classify_ex", "vsaogm_decode_incremental", "vsaogm_request_bytes",
-    "vsaogm_volume_create", "vsaogm_volume_destroy", "vsaogm_volume_encode", "vsaogm_volume_take_rejected",
-    "vsaogm_volume_decode", "vsaogm_classify3",
+    "vsaogm_volume_create", "vsaogm_volume_destroy", "vsaogm_volume_reset", "vsaogm_volume_encode",
+    "vsaogm_volume_take_rejected", "vsaogm_volume_decode", "vsaogm_classify3",
 ]
 ACTIVATIONS = {"entropy": 0, "relu": 1, "tanh": 2, "sigmoid": 3}
 
@@ -129,6 +129,7 @@ def load(path: str = LIB_PATH):
     L.vsaogm_request_bytes.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(i64)]
     L.vsaogm_volume_create.argtypes = [ctypes.POINTER(VolumeDesc), ctypes.POINTER(P)]
     L.vsaogm_volume_destroy.argtypes = [P]
+    L.vsaogm_volume_reset.argtypes = [P, P]
     L.vsaogm_volume_encode.argtypes = [P, P, P, i64, P]
     L.vsaogm_volume_take_rejected.argtypes = [P, P, ctypes.POINTER(i64)]
     L.vsaogm_volume_decode.argtypes = [P, ctypes.POINTER(Grid3Desc), i32, P, P, P]
@@ -297,6 +298,9 @@ class Volume:
             self.close()
         except Exception:
             pass
+
+    def reset(self, stream=None):
+        check(load().vsaogm_volume_reset(self._h, _stream(stream)))
 
     def encode(self, xyz, label, stream=None):
         assert xyz.is_contiguous() and label.is_contiguous() and xyz.shape[-1] == 3

@@ -114,3 +114,58 @@ def test_volume_errors(torch_cuda):
     vol.encode(torch.from_numpy(v.xyz).cuda(), torch.from_numpy(lab).cuda())
     assert vol.take_rejected() == 5
     vol.close()
+
+
+def test_volume_reset(torch_cuda):
+    """A reset volume re-encoded with the same points decodes as a fresh one (same grid cache,
+    same kernels, so bit-identical)."""
+    from paper_2408_09066_amd import native
+    torch = torch_cuda
+    v = synth.volume("room3d")
+    xyz, lab = torch.from_numpy(v.xyz).cuda(), torch.from_numpy(v.label).cuda()
+    vol = native.Volume(v.theta, v.layout, v.tiles)
+    vol.encode(xyz, lab)
+    h1, m1 = vol.decode(v.grid, v.nx, v.ny, v.nz, "bf16x3")
+    h1, m1 = h1.clone(), m1.clone()
+    vol.encode(xyz[::2].contiguous(), lab[::2].contiguous())   # memories now differ
+    vol.reset()
+    vol.encode(xyz, lab)
+    h2, m2 = vol.decode(v.grid, v.nx, v.ny, v.nz, "bf16x3")
+    torch.cuda.synchronize()
+    assert torch.equal(h1, h2) and torch.equal(m1, m2)
+    vol.close()
+
+
+def test_volume_fullsize_sampled(torch_cuda):
+    """The 3-D benchmark volume (480 000 points, D = 4096, 128 x 128 x 32) at 1 000 seeded voxels of
+    one tile: the oracle encodes only that tile's points (its memories depend on nothing else)."""
+    from paper_2408_09066_amd import native
+    torch = torch_cuda
+    v = synth.volume("hall3d")
+    vol = native.Volume(v.theta, v.layout, v.tiles)
+    vol.encode(torch.from_numpy(v.xyz).cuda(), torch.from_numpy(v.label).cuda())
+    heat, hmax = vol.decode(v.grid, v.nx, v.ny, v.nz, "bf16x3")
+    torch.cuda.synchronize()
+    heat = heat.cpu().numpy()
+    hmax = hmax.cpu().numpy()
+    vol.close()
+    for p in range(2):
+        assert hmax[p] == heat[p].max()
+    beta = oracle.assign_tiles3(v.layout, v.tiles, v.xyz)
+    tile = int(np.argmin(np.bincount(beta, minlength=v.tiles[0] * v.tiles[1] * v.tiles[2])))
+    sel = beta == tile
+    omega, bad = oracle.encode3(v.theta, v.layout, v.tiles, v.xyz[sel], v.label[sel])
+    assert bad == 0
+    rng = np.random.default_rng(np.random.SeedSequence([2408, 32, 7]))
+    cand = rng.choice(v.nx * v.ny * v.nz, size=40_000, replace=False)
+    i, j, l = cand % v.nx, (cand // v.nx) % v.ny, cand // (v.nx * v.ny)
+    gx, gy, gz, res = v.grid
+    cb = oracle.assign_tiles3(v.layout, v.tiles, np.stack([gx + (i + .5) * res, gy + (j + .5) * res, gz + (l + .5) * res], 1))
+    cells = cand[cb == tile][:1000]
+    assert len(cells) == 1000
+    P = oracle.similarity3_cells(v.theta, v.layout, v.tiles, omega, v.grid, v.nx, v.ny, cells)
+    for p in range(2):
+        g = heat[p].reshape(-1)[cells].astype(np.float64)
+        e = np.linalg.norm(g - P[p]) / np.linalg.norm(P[p])
+        say(f"[gpu] hall3d tile {tile} heat[{p}] sampled rel-L2 {e:.3e}")
+        assert e <= 1e-4
