@@ -315,11 +315,12 @@ int vsaogm_server_stats(vsaogm_server* server, int64_t* completed, int64_t* peak
 int vsaogm_request_bytes(vsaogm_server* server, const vsaogm_request* req, int64_t* bytes);
 
 /*
- * Profiling hook: record the given HIP events (hipEvent_t) immediately before and
- * after every launch of one stage's main kernel, on the stream it is launched on:
+ * Profiling hook: the given HIP events (hipEvent_t) take the start and end times of
+ * every launch of one stage's main kernel(s), recorded by the kernel dispatches
+ * themselves (no marker packets are queued between kernels):
  *   stage 0  encode: the sin/cos-and-accumulate kernel,
- *   stage 1  decode: the similarity GEMM,
- *   stage 2  classify: the entropy / softmax / threshold kernel.
+ *   stage 1  decode: the similarity GEMM and, when the plan splits tiles, its fix-up,
+ *   stage 2  classify: the entropy / softmax / threshold kernel(s).
  * Passing NULL events turns the stage's recording off.  Process-wide; not for use
  * while other threads launch the same stage.
  */

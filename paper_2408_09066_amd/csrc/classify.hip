@@ -132,10 +132,9 @@ hipError_t launch_classify(const float* heat, const float* hmax, int nx, int ny,
     if (act != 0) r_occ = r_emp = 0;  // per-cell activations: the "disk" is the cell itself
     const int R = r_occ > r_emp ? r_occ : r_emp;
     const size_t lds = 2 * (size_t)(TX + 2 * R) * (TY + 2 * R) * sizeof(float);
-    profile_begin(kStageClassify, s);
-    hipLaunchKernelGGL(k_classify, dim3((nx + TX - 1) / TX, (ny + TY - 1) / TY), dim3(256), lds, s,
-                       heat, hmax, nx, ny, r_occ, r_emp, rho, normalize, square, act, ogm, label);
-    profile_end(kStageClassify, s);
+    hipExtLaunchKernelGGL(k_classify, dim3((nx + TX - 1) / TX, (ny + TY - 1) / TY), dim3(256), lds, s,
+                          profile_start(kStageClassify), profile_stop(kStageClassify), 0, heat, hmax, nx, ny,
+                          r_occ, r_emp, rho, normalize, square, act, ogm, label);
     return hipGetLastError();
 }
 

@@ -877,35 +877,40 @@ hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
     a.steps_per_wg = d.plan.steps_per_wg;
     a.total_steps = d.plan.total_steps;
     const dim3 grid(d.plan.grid), block(256);
-    profile_begin(kStageDecode, s);
+    // the GEMM records the stage's start event, and its stop event unless a fix-up follows
+    const bool fix = d.plan.steps_per_wg % d.plan.ksteps != 0 || d.plan.steps_per_wg < d.plan.ksteps;
+    const hipEvent_t e0 = profile_start(kStageDecode), e1 = profile_stop(kStageDecode);
+    const hipEvent_t g1 = fix ? nullptr : e1;
     switch (precision) {
         case 0:
             if (d.ez) return hipErrorInvalidValue;  // volumes run the 16-bit kernels
-            hipLaunchKernelGGL(k_decode<0>, grid, block, 0, s, a);
+            hipExtLaunchKernelGGL(k_decode<0>, grid, block, 0, s, e0, g1, 0, a);
             break;
         case 1:
-            if (d.ez) hipLaunchKernelGGL((k_decode16<1, true>), grid, block, 0, s, a);
-            else hipLaunchKernelGGL((k_decode16<1, false>), grid, block, 0, s, a);
+            if (d.ez) hipExtLaunchKernelGGL(k_decode16<1, true>, grid, block, 0, s, e0, g1, 0, a);
+            else hipExtLaunchKernelGGL(k_decode16<1, false>, grid, block, 0, s, e0, g1, 0, a);
             break;
         case 2:
-            if (d.ez) hipLaunchKernelGGL((k_decode16<2, true>), grid, block, 0, s, a);
-            else hipLaunchKernelGGL((k_decode16<2, false>), grid, block, 0, s, a);
+            if (d.ez) hipExtLaunchKernelGGL(k_decode16<2, true>, grid, block, 0, s, e0, g1, 0, a);
+            else hipExtLaunchKernelGGL(k_decode16<2, false>, grid, block, 0, s, e0, g1, 0, a);
             break;
         case 3:
-            if (d.ez) hipLaunchKernelGGL((k_decode16<3, true>), grid, block, 0, s, a);
-            else hipLaunchKernelGGL((k_decode16<3, false>), grid, block, 0, s, a);
+            if (d.ez) hipExtLaunchKernelGGL(k_decode16<3, true>, grid, block, 0, s, e0, g1, 0, a);
+            else hipExtLaunchKernelGGL(k_decode16<3, false>, grid, block, 0, s, e0, g1, 0, a);
             break;
         default: return hipErrorInvalidValue;
     }
-    if (d.plan.steps_per_wg % d.plan.ksteps != 0 || d.plan.steps_per_wg < d.plan.ksteps) {
+    if (fix) {
         if (precision == 0)
-            hipLaunchKernelGGL(k_decode_fix<kTileRows>, dim3((unsigned)d.ntiles * Fix<kTileRows>::PARTS), dim3(256), 0, s, a);
+            hipExtLaunchKernelGGL(k_decode_fix<kTileRows>, dim3((unsigned)d.ntiles * Fix<kTileRows>::PARTS),
+                                  dim3(256), 0, s, nullptr, e1, 0, a);
         else if (precision == 3)
-            hipLaunchKernelGGL(k_decode_fix<Wide<3>::TR>, dim3((unsigned)d.ntiles * Fix<Wide<3>::TR>::PARTS), dim3(256), 0, s, a);
+            hipExtLaunchKernelGGL(k_decode_fix<Wide<3>::TR>, dim3((unsigned)d.ntiles * Fix<Wide<3>::TR>::PARTS),
+                                  dim3(256), 0, s, nullptr, e1, 0, a);
         else
-            hipLaunchKernelGGL(k_decode_fix<Wide<1>::TR>, dim3((unsigned)d.ntiles * Fix<Wide<1>::TR>::PARTS), dim3(256), 0, s, a);
+            hipExtLaunchKernelGGL(k_decode_fix<Wide<1>::TR>, dim3((unsigned)d.ntiles * Fix<Wide<1>::TR>::PARTS),
+                                  dim3(256), 0, s, nullptr, e1, 0, a);
     }
-    profile_end(kStageDecode, s);
     if (d.hmax_u) hipLaunchKernelGGL(k_hmax_final, dim3(1), dim3(64), 0, s, d.hmax_u, d.hmax);
     return hipGetLastError();
 }

@@ -80,6 +80,8 @@ __global__ __launch_bounds__(kAssignChunk) void k_assign(const float2* __restric
 
 // Exclusive scan across a block of kScanThreads threads; returns the block total in *total.
 constexpr int kScanThreads = 1024;
+constexpr int kScanGroup = 16;     // histogram entries per thread and pass
+static_assert(kScanGroup <= kHistPad && kScanGroup % 4 == 0, "aligned group reads stay in the padding");
 __device__ int block_scan_excl(int v, int* sh_w, int* total) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int x = v;
@@ -115,34 +117,49 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int* __restrict__ hist, i
     __shared__ int sh_w[kScanThreads / 64];
     extern __shared__ int key_start[];   // [nkeys]
     const int64_t N = (int64_t)nkeys * nchunks;
-    // coalesced passes of kScanThreads * 4 entries (one aligned group of four per thread; the
+    // coalesced passes of kScanThreads * kScanGroup entries (one aligned group per thread; the
     // histogram buffer is padded so the last group stays in bounds); the next pass's group is
     // loaded before the current pass is scanned
-    constexpr int64_t PASS = (int64_t)kScanThreads * 4;
-    int carry = 0;
+    constexpr int G = kScanGroup;
+    constexpr int64_t PASS = (int64_t)kScanThreads * G;
     typedef int i32x4 __attribute__((ext_vector_type(4)));
-    i32x4 nxt = *reinterpret_cast<const i32x4*>(hist + min((int64_t)threadIdx.x * 4, N - 1) / 4 * 4);
+    auto load_group = [&](int64_t j, i32x4 (&dst)[G / 4]) {
+        const i32x4* src = reinterpret_cast<const i32x4*>(hist + min(j, N - 1) / G * G);
+#pragma unroll
+        for (int u = 0; u < G / 4; ++u) dst[u] = src[u];
+    };
+    int carry = 0;
+    i32x4 nxt[G / 4];
+    load_group((int64_t)threadIdx.x * G, nxt);
     for (int64_t base = 0; base < N; base += PASS) {
-        const int64_t j0 = base + (int64_t)threadIdx.x * 4;
-        i32x4 v = nxt;
+        const int64_t j0 = base + (int64_t)threadIdx.x * G;
+        int v[G];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (j0 + u >= N) v[u] = 0;
-        if (base + PASS < N) nxt = *reinterpret_cast<const i32x4*>(hist + min(j0 + PASS, N - 1) / 4 * 4);
+        for (int u = 0; u < G; ++u) v[u] = (j0 + u < N) ? nxt[u / 4][u % 4] : 0;
+        if (base + PASS < N) load_group(j0 + PASS, nxt);
+        int sum = 0;
+#pragma unroll
+        for (int u = 0; u < G; ++u) sum += v[u];
         int total;
-        int run = carry + block_scan_excl(v[0] + v[1] + v[2] + v[3], sh_w, &total);
-        i32x4 out;
+        int run = carry + block_scan_excl(sum, sh_w, &total);
+        if (j0 + G <= N) {
+            i32x4* dst = reinterpret_cast<i32x4*>(hist + j0);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            out[u] = run;
-            run += v[u];
-        }
-        if (j0 + 3 < N) {
-            *reinterpret_cast<i32x4*>(hist + j0) = out;
+            for (int q = 0; q < G / 4; ++q) {
+                i32x4 out;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    out[u] = run;
+                    run += v[4 * q + u];
+                }
+                dst[q] = out;
+            }
         } else {
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (j0 + u < N) hist[j0 + u] = out[u];
+            for (int u = 0; u < G; ++u) {
+                if (j0 + u < N) hist[j0 + u] = run;
+                run += v[u];
+            }
         }
         carry += total;
     }
@@ -359,36 +376,46 @@ __global__ __launch_bounds__(kEncodeThreads) void k_encode(
     }
 }
 
-// omega[key][k] += sum over the key's work items, in work-item order (deterministic).
+// omega[key][k] += sum over the key's work items.  Four groups of 64 threads per block of 64
+// bins: group g sums the items g, g + 4, g + 8, ... in order, eight loads in flight, and the four
+// group sums are added in a fixed order (deterministic).
 __global__ __launch_bounds__(256) void k_reduce(const float2* __restrict__ partial,
                                                 const int* __restrict__ meta, int nkeys, int half,
                                                 int halfp, float2* __restrict__ omega) {
+    __shared__ float2 sh[4][64];
     const int key = blockIdx.y;
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= half) return;
+    const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int k = blockIdx.x * 64 + lane;
     const int e0 = meta[1 + key], ne = meta[1 + nkeys + key];
-    if (ne == 0) return;
-    const float2* p = partial + (size_t)e0 * halfp + k;
+    if (ne == 0) return;   // uniform over the block
     float sr = 0.f, si = 0.f;
-    int c = 0;
-    for (; c + 8 <= ne; c += 8) {
-        float2 v[8];
+    if (k < half) {
+        const float2* p = partial + (size_t)e0 * halfp + k;
+        int c = g;
+        for (; c + 28 < ne; c += 32) {
+            float2 v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = p[(size_t)(c + u) * halfp];
+            for (int u = 0; u < 8; ++u) v[u] = p[(size_t)(c + 4 * u) * halfp];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            sr += v[u].x;
-            si += v[u].y;
+            for (int u = 0; u < 8; ++u) {
+                sr += v[u].x;
+                si += v[u].y;
+            }
+        }
+        for (; c < ne; c += 4) {
+            const float2 v = p[(size_t)c * halfp];
+            sr += v.x;
+            si += v.y;
         }
     }
-    for (; c < ne; ++c) {
-        const float2 v = p[(size_t)c * halfp];
-        sr += v.x;
-        si += v.y;
+    sh[g][lane] = make_float2(sr, si);
+    __syncthreads();
+    if (g == 0 && k < half) {
+        const float2 a = sh[0][lane], b = sh[1][lane], c = sh[2][lane], d = sh[3][lane];
+        float2* o = omega + (size_t)key * halfp + k;
+        const float2 w = *o;
+        *o = make_float2(w.x + ((a.x + b.x) + (c.x + d.x)), w.y + ((a.y + b.y) + (c.y + d.y)));
     }
-    float2* o = omega + (size_t)key * halfp + k;
-    const float2 w = *o;
-    *o = make_float2(w.x + sr, w.y + si);
 }
 
 // scale[key] = 1 / ||w|| with ||w||^2 = (2/D) sum_{k < D/2} |Omega_k|^2 (Parseval over the
@@ -509,30 +536,25 @@ hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const
                            n, L, nkeys, p.nchunks, bits_for(nkeys), w.hist, w.sorted, w.sorted_lo);
     const double2* rev_d = reinterpret_cast<const double2*>(theta_rev_d);
     const dim3 eg(p.max_echunks, p.binblocks);
-    profile_begin(kStageEncode, s);
+    const hipEvent_t e0 = profile_start(kStageEncode), e1 = profile_stop(kStageEncode);
     switch (p.bpt) {
         case 1:
-            hipLaunchKernelGGL(k_encode<1>, eg, dim3(kEncodeThreads), 0, s, w.sorted, w.sorted_lo,
-                               w.table, w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp,
-                               w.partial);
+            hipExtLaunchKernelGGL(k_encode<1>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo,
+                                  w.table, w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp, w.partial);
             break;
         case 2:
-            hipLaunchKernelGGL(k_encode<2>, eg, dim3(kEncodeThreads), 0, s, w.sorted, w.sorted_lo,
-                               w.table, w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp,
-                               w.partial);
+            hipExtLaunchKernelGGL(k_encode<2>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo,
+                                  w.table, w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp, w.partial);
             break;
         case 4:
-            hipLaunchKernelGGL(k_encode<4>, eg, dim3(kEncodeThreads), 0, s, w.sorted, w.sorted_lo,
-                               w.table, w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp,
-                               w.partial);
+            hipExtLaunchKernelGGL(k_encode<4>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo,
+                                  w.table, w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp, w.partial);
             break;
         default:
-            hipLaunchKernelGGL(k_encode<8>, eg, dim3(kEncodeThreads), 0, s, w.sorted, w.sorted_lo,
-                               w.table, w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp,
-                               w.partial);
+            hipExtLaunchKernelGGL(k_encode<8>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo,
+                                  w.table, w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp, w.partial);
             break;
     }
-    profile_end(kStageEncode, s);
     launch_key_reduce(w.partial, w.meta, nkeys, half, halfp, omega, s);
     return hipGetLastError();
 }
@@ -545,7 +567,7 @@ void launch_key_scan(int* hist, int nchunks, int nkeys, int echunk, EChunk* tabl
 
 void launch_key_reduce(const float2* partial, const int* meta, int nkeys, int half, int halfp, float2* omega,
                        hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3((half + 255) / 256, nkeys), dim3(256), 0, s, partial, meta, nkeys, half,
+    hipLaunchKernelGGL(k_reduce, dim3((half + 63) / 64, nkeys), dim3(256), 0, s, partial, meta, nkeys, half,
                        halfp, omega);
 }
 

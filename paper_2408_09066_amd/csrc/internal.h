@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <cstddef>
 #include <cstdint>
 #include <vector>
@@ -12,6 +13,7 @@ namespace vsaogm {
 constexpr int kMaxTilesPerAxis = 64;
 constexpr int kMaxKeys = 2 * kMaxTilesPerAxis * kMaxTilesPerAxis;  // 8192 memories
 constexpr int kAssignChunk = 1024;   // points per histogram / stable-scatter chunk
+constexpr int kHistPad = 16;         // entries of padding after a key histogram (aligned group reads)
 constexpr int kEncodeChunk = 1024;   // points per encode work item (even, so pairs never straddle)
 constexpr int kEncodeThreads = 256;
 constexpr int kEncodeBpt = 4;        // spectrum bins per encode thread
@@ -99,8 +101,11 @@ void set_last_error(const char* msg);
 
 // ---- profiling hook (map.hip) --------------------------------------------------------
 enum ProfileStage { kStageEncode = 0, kStageDecode = 1, kStageClassify = 2, kNumStages = 3 };
-void profile_begin(int stage, hipStream_t s);
-void profile_end(int stage, hipStream_t s);
+// The events a stage is being timed with (NULL when it is not): the stage's first kernel is
+// launched with the start event and its last with the stop event through hipExtLaunchKernelGGL,
+// so that the dispatches record them themselves (no marker packets between kernels).
+hipEvent_t profile_start(int stage);
+hipEvent_t profile_stop(int stage);
 
 // ---- encode (encode.hip) -----------------------------------------------------------
 struct EncodeWork {

@@ -215,12 +215,8 @@ std::vector<DTile> build_decode_tiles(const std::vector<DBand>& bands, const std
                 }
     return tl;
 }
-void profile_begin(int stage, hipStream_t s) {
-    if (g_profile[stage].begin) (void)hipEventRecord(g_profile[stage].begin, s);
-}
-void profile_end(int stage, hipStream_t s) {
-    if (g_profile[stage].end) (void)hipEventRecord(g_profile[stage].end, s);
-}
+hipEvent_t profile_start(int stage) { return g_profile[stage].begin; }
+hipEvent_t profile_stop(int stage) { return g_profile[stage].end; }
 }  // namespace vsaogm
 
 struct vsaogm_map {
@@ -344,8 +340,8 @@ void ensure_encode_workspace(vsaogm_map* m, int64_t n, hipStream_t s) {
     m->w_key.alloc_async(cap, s, "encode keys");
     m->w_sorted.alloc_async(cap, s, "encode sorted");
     m->w_sorted_lo.alloc_async(cap, s, "encode sorted residuals");
-    // + 4: the scan reads the histogram in aligned groups of four
-    m->w_hist.alloc_async((size_t)chunks * m->nkeys + 4, s, "encode histogram");
+    // the scan reads the histogram in aligned groups of kHistPad entries
+    m->w_hist.alloc_async((size_t)chunks * m->nkeys + kHistPad, s, "encode histogram");
     m->w_table.alloc_async(echunks, s, "encode table");
     m->w_partial.alloc_async((size_t)echunks * m->halfp, s, "encode partial spectra");
     if (!m->w_meta.p) m->w_meta.alloc_async(1 + 3 * (size_t)m->nkeys, s, "encode meta");
@@ -1058,8 +1054,8 @@ int vsaogm_volume_encode(vsaogm_volume* v, const float* xyz, const uint8_t* labe
             v->w_key.alloc_async(cap, s, "volume keys");
             v->w_sorted.alloc_async(cap, s, "volume sorted local coordinates");
             v->w_sorted_lo.alloc_async(cap, s, "volume sorted residuals");
-            // + 4: the scan reads the histogram in aligned groups of four
-            v->w_hist.alloc_async((size_t)chunks * v->nkeys + 4, s, "volume histogram");
+            // the scan reads the histogram in aligned groups of kHistPad entries
+            v->w_hist.alloc_async((size_t)chunks * v->nkeys + kHistPad, s, "volume histogram");
             v->w_table.alloc_async(echunks, s, "volume work table");
             v->w_partial.alloc_async((size_t)echunks * v->halfp, s, "volume partial spectra");
             if (!v->w_meta.p) v->w_meta.alloc_async(1 + 3 * (size_t)v->nkeys, s, "volume encode meta");

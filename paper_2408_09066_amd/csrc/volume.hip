@@ -333,22 +333,21 @@ hipError_t launch_encode3(const float* xyz, const uint8_t* label, int64_t n, con
         hipLaunchKernelGGL(k3_scatter<1>, dim3(p.nchunks), dim3(64), nkeys * sizeof(int), s, xyz, w.key, n, L,
                            nkeys, p.nchunks, key_bits_for(nkeys), w.hist, w.sorted, w.sorted_lo);
     const dim3 eg(p.max_echunks, p.binblocks);
-    profile_begin(kStageEncode, s);
+    const hipEvent_t e0 = profile_start(kStageEncode), e1 = profile_stop(kStageEncode);
     switch (p.bpt) {
         case 1:
-            hipLaunchKernelGGL(k3_encode<1>, eg, dim3(kEncodeThreads), 0, s, w.sorted, w.sorted_lo, w.table, w.meta,
-                               rev, rev_d, max_rev, halfp, w.partial);
+            hipExtLaunchKernelGGL(k3_encode<1>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo,
+                                  w.table, w.meta, rev, rev_d, max_rev, halfp, w.partial);
             break;
         case 2:
-            hipLaunchKernelGGL(k3_encode<2>, eg, dim3(kEncodeThreads), 0, s, w.sorted, w.sorted_lo, w.table, w.meta,
-                               rev, rev_d, max_rev, halfp, w.partial);
+            hipExtLaunchKernelGGL(k3_encode<2>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo,
+                                  w.table, w.meta, rev, rev_d, max_rev, halfp, w.partial);
             break;
         default:
-            hipLaunchKernelGGL(k3_encode<4>, eg, dim3(kEncodeThreads), 0, s, w.sorted, w.sorted_lo, w.table, w.meta,
-                               rev, rev_d, max_rev, halfp, w.partial);
+            hipExtLaunchKernelGGL(k3_encode<4>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo,
+                                  w.table, w.meta, rev, rev_d, max_rev, halfp, w.partial);
             break;
     }
-    profile_end(kStageEncode, s);
     launch_key_reduce(w.partial, w.meta, nkeys, half, halfp, omega, s);
     return hipGetLastError();
 }
@@ -357,10 +356,10 @@ hipError_t launch_classify3(const float* heat, const float* hmax, int nx, int ny
                             float rho, float* g, float* ogm, uint8_t* label, hipStream_t s) {
     const int64_t nvox = (int64_t)nx * ny * nz;
     const unsigned blocks = (unsigned)((nvox + 255) / 256);
-    profile_begin(kStageClassify, s);
-    hipLaunchKernelGGL(k3_entropy, dim3(blocks), dim3(256), 0, s, heat, hmax, nvox, g);
-    hipLaunchKernelGGL(k3_classify, dim3(blocks), dim3(256), 0, s, g, nx, ny, nz, r_emp, r_occ, rho, ogm, label);
-    profile_end(kStageClassify, s);
+    hipExtLaunchKernelGGL(k3_entropy, dim3(blocks), dim3(256), 0, s, profile_start(kStageClassify), nullptr, 0,
+                          heat, hmax, nvox, g);
+    hipExtLaunchKernelGGL(k3_classify, dim3(blocks), dim3(256), 0, s, nullptr, profile_stop(kStageClassify), 0, g,
+                          nx, ny, nz, r_emp, r_occ, rho, ogm, label);
     return hipGetLastError();
 }
 
