@@ -185,18 +185,29 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int* __restrict__ hist, i
             meta[1 + nkeys + k] = ne;
             meta[1 + 2 * nkeys + k] = cnt;
             if (version && cnt > 0) version[k] += 1u;  // the memory changes: decodes of it are stale
-            for (int j = 0; j < ne; ++j) {
-                EChunk e;
-                e.key = k;
-                e.start = start + j * echunk;
-                e.len = min(echunk, cnt - j * echunk);
-                e.pad = 0;
-                table[e0 + j] = e;
-            }
         }
         ec_carry += total;
     }
     if (threadIdx.x == 0) meta[0] = ec_carry;
+    __syncthreads();  // meta's first-item offsets are visible to the whole block
+    // the work table, one entry per thread: its key is the last whose first item is <= the entry
+    // (keys without items share their successor's offset and are passed over)
+    const int* e_first = meta + 1;
+    for (int idx = threadIdx.x; idx < ec_carry; idx += kScanThreads) {
+        int lo = 0, hi = nkeys;   // e_first[lo] <= idx < e_first[hi] (e_first[nkeys] taken as +inf)
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (e_first[mid] <= idx) lo = mid;
+            else hi = mid;
+        }
+        const int j = idx - e_first[lo];
+        EChunk e;
+        e.key = lo;
+        e.start = key_start[lo] + j * echunk;
+        e.len = min(echunk, meta[1 + 2 * nkeys + lo] - j * echunk);
+        e.pad = 0;
+        table[idx] = e;
+    }
 }
 
 // Stable counting-sort scatter: one block of WAVES wavefronts per chunk of kAssignChunk points,
