@@ -84,16 +84,32 @@ __global__ __launch_bounds__(256) void k_classify(const float* __restrict__ heat
     }
     const float m0 = hmax[0], m1 = hmax[1];
     const size_t plane = (size_t)nx * ny;
-    for (int idx = threadIdx.x; idx < 2 * W * H; idx += 256) {
-        const int p = idx / (W * H);
-        const int rem = idx - p * W * H;
-        const int yy = rem / W, xx = rem - yy * W;
-        const int gx = bx - R + xx, gy = by - R + yy;
-        const float m = p ? m1 : m0;
-        float v = 0.f;
-        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny)
-            v = cell_value(heat[p * plane + (size_t)gy * nx + gx], m, normalize, square, act);
-        sg[idx] = v;
+    // the block's cells and halo, both classes, kLoadBatch loads in flight per thread
+    constexpr int kLoadBatch = 8;
+    const int total = 2 * W * H;
+    for (int base = 0; base < total; base += 256 * kLoadBatch) {
+        float raw[kLoadBatch];
+        bool in[kLoadBatch];
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int idx = base + u * 256 + threadIdx.x;
+            const int p = idx / (W * H);
+            const int rem = idx - p * W * H;
+            const int yy = rem / W, xx = rem - yy * W;
+            const int gx = bx - R + xx, gy = by - R + yy;
+            in[u] = idx < total && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+            // outside the grid: a clamped in-bounds address, the value is discarded
+            const size_t off = in[u] ? (size_t)p * plane + (size_t)gy * nx + gx : 0;
+            raw[u] = heat[off];
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int idx = base + u * 256 + threadIdx.x;
+            if (idx < total) {
+                const float m = (idx >= W * H) ? m1 : m0;
+                sg[idx] = in[u] ? cell_value(raw[u], m, normalize, square, act) : 0.f;
+            }
+        }
     }
     __syncthreads();
     for (int c = threadIdx.x; c < TX * TY; c += 256) {

@@ -294,6 +294,37 @@ __device__ inline float ball_sum(const float* __restrict__ g, int i, int j, int 
     return s;
 }
 
+// The same sum for a radius known at compile time: straight-line code whose loads do not depend
+// on the running sum, so they can all be in flight together (addresses clamped into the
+// volume, values outside it masked to zero); same offset order.
+template <int R>
+__device__ inline float ball_sum_fixed(const float* __restrict__ g, int i, int j, int l, int nx, int ny, int nz) {
+    float s = 0.f;
+#pragma unroll
+    for (int dz = -R; dz <= R; ++dz)
+#pragma unroll
+        for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+            for (int dx = -R; dx <= R; ++dx)
+                if (dx * dx + dy * dy + dz * dz <= R * R) {   // compile-time after unrolling
+                    const int ii = i + dx, jj = j + dy, ll = l + dz;
+                    const bool in = ii >= 0 && ii < nx && jj >= 0 && jj < ny && ll >= 0 && ll < nz;
+                    const float x = g[in ? ((int64_t)ll * ny + jj) * nx + ii : 0];
+                    s += in ? x : 0.f;
+                }
+    return s;
+}
+
+__device__ inline float ball_sum_any(const float* __restrict__ g, int i, int j, int l, int nx, int ny, int nz,
+                                     int r) {
+    switch (r) {
+        case 0: return ball_sum_fixed<0>(g, i, j, l, nx, ny, nz);
+        case 1: return ball_sum_fixed<1>(g, i, j, l, nx, ny, nz);
+        case 2: return ball_sum_fixed<2>(g, i, j, l, nx, ny, nz);
+        default: return ball_sum(g, i, j, l, nx, ny, nz, r);
+    }
+}
+
 // Class 0 sums over the ball of radius r_emp, class 1 over radius r_occ.
 __global__ __launch_bounds__(256) void k3_classify(const float* __restrict__ g, int nx, int ny, int nz, int r_emp,
                                                    int r_occ, float rho, float* __restrict__ ogm,
@@ -302,8 +333,8 @@ __global__ __launch_bounds__(256) void k3_classify(const float* __restrict__ g, 
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (v >= nvox) return;
     const int i = (int)(v % nx), j = (int)((v / nx) % ny), l = (int)(v / ((int64_t)nx * ny));
-    const float h0 = ball_sum(g, i, j, l, nx, ny, nz, r_emp);
-    const float h1 = ball_sum(g + nvox, i, j, l, nx, ny, nz, r_occ);
+    const float h0 = ball_sum_any(g, i, j, l, nx, ny, nz, r_emp);
+    const float h1 = ball_sum_any(g + nvox, i, j, l, nx, ny, nz, r_occ);
     const float o = tanhf(0.5f * (h1 - h0));
     if (ogm) ogm[v] = o;
     label[v] = (o >= rho) ? 1 : 0;
