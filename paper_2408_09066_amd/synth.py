@@ -481,8 +481,9 @@ VOLUME_RECIPES: Dict[str, VolumeRecipe] = {
 }
 
 
-def volume(name: str) -> Volume:
-    rc = VOLUME_RECIPES[name]
+def volume(name: str, **changes) -> Volume:
+    """A recipe's volume; keyword arguments replace recipe fields (e.g. D, ell, tiles)."""
+    rc = dataclasses.replace(VOLUME_RECIPES[name], **changes)
     theta = make_theta3(rc.D, rc.ell, rng_for(rc.config_id, STREAM_THETA))
     rw = rng_for(rc.config_id, STREAM_WORLD)
     hx, hy, hz = rc.half

@@ -113,6 +113,63 @@ def test_volume_errors(torch_cuda):
     lab[:5] = 7
     vol.encode(torch.from_numpy(v.xyz).cuda(), torch.from_numpy(lab).cuda())
     assert vol.take_rejected() == 5
+    with pytest.raises(native.VsaogmError):
+        vol.decode(v.grid, 0, v.ny, v.nz, "bf16x3")                     # empty grid
+    with pytest.raises(native.VsaogmError):
+        vol.decode((v.grid[0], v.grid[1], v.grid[2], -0.1), v.nx, v.ny, v.nz, "bf16x3")   # negative res
+    heat, hmax = vol.decode(v.grid, v.nx, v.ny, v.nz, "bf16x3")
+    with pytest.raises(native.VsaogmError):
+        native.classify3(heat, hmax, 25, 1, 0.0)                          # radius above the maximum
+    torch.cuda.synchronize()
+    vol.close()
+
+
+def test_volume_wide_phases_and_padded_spectrum(torch_cuda):
+    """One tile over the room with l = 0.05 m: local phases beyond 64 revolutions take the
+    double-precision phase path of the encode; D = 200 pads the half spectrum (100 bins) to
+    128."""
+    v = synth.volume("room3d", D=200, ell=0.05, tiles=(1, 1, 1))
+    v.name = "room3d_wide"
+    centre = np.array(oracle.tile_center3(v.layout, v.tiles, 0))
+    rev_per_m = np.abs(v.theta[: v.D // 2]).max(axis=0) / (2 * np.pi)
+    reach = (np.abs(v.xyz.astype(np.float64) - centre) @ rev_per_m).max()
+    assert reach > 64.0          # the encode's single-precision bound is exceeded
+    _, P, m, H, ogm, lab = oracle.pipeline3(v)
+    g = gpu_volume(torch_cuda, v, "bf16x3")
+    for p in range(2):
+        e = np.linalg.norm(g["heat"][p] - P[p]) / np.linalg.norm(P[p])
+        say(f"[gpu] volume {v.name} heat[{p}] rel-L2 {e:.3e} (phase reach {reach:.0f} rev)")
+        assert e <= 1e-4
+    agree = float(np.mean(g["label"] == lab))
+    assert agree >= 0.999
+    bad = g["label"] != lab
+    assert not bad.any() or np.max(np.abs(ogm[bad] - v.rho)) < 1e-3
+
+
+def test_volume_empty_and_one_point(torch_cuda):
+    """An empty volume decodes to zero heat and maxima (OGM 0, occupied at rho = 0); one point
+    has unit self-similarity at its own voxel centre and leaves the other class empty."""
+    from paper_2408_09066_amd import native
+    torch = torch_cuda
+    v = synth.volume("room3d")
+    vol = native.Volume(v.theta, v.layout, v.tiles)
+    vol.encode(torch.zeros((0, 3), dtype=torch.float32, device="cuda"),
+               torch.zeros(0, dtype=torch.uint8, device="cuda"))
+    heat, hmax = vol.decode(v.grid, v.nx, v.ny, v.nz, "bf16x3")
+    ogm, lab = native.classify3(heat, hmax, v.r_occ, v.r_emp, 0.0)
+    torch.cuda.synchronize()
+    assert torch.all(heat == 0) and torch.all(hmax == 0)
+    assert torch.all(ogm == 0) and torch.all(lab == 1)
+    x0, y0, z0, res = v.grid
+    i, j, l = 5, 9, 3
+    c = [x0 + (i + 0.5) * res, y0 + (j + 0.5) * res, z0 + (l + 0.5) * res]
+    vol.encode(torch.tensor([c], dtype=torch.float32, device="cuda"),
+               torch.tensor([1], dtype=torch.uint8, device="cuda"))
+    heat, hmax = vol.decode(v.grid, v.nx, v.ny, v.nz, "bf16x3")
+    torch.cuda.synchronize()
+    assert abs(float(heat[1, l, j, i]) - 1.0) < 1e-5
+    assert abs(float(hmax[1]) - 1.0) < 1e-5
+    assert torch.all(heat[0] == 0)
     vol.close()
 
 
