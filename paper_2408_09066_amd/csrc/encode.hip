@@ -438,9 +438,9 @@ __global__ __launch_bounds__(kNormThreads) void k_norm(const float2* __restrict_
                                               float2* __restrict__ omega_s,
                                               unsigned* __restrict__ hmax_u) {
     const int key = blockIdx.x;
-    // the following similarity GEMM folds its maxima into hmax_u[0..1] and counts finished
-    // tiles in hmax_u[2]; they start from zero here
-    if (key == 0 && threadIdx.x < 3) hmax_u[threadIdx.x] = 0u;
+    // the following similarity GEMM folds its class maxima into hmax_u[0..1]; they start from
+    // zero here
+    if (key == 0 && threadIdx.x < 2) hmax_u[threadIdx.x] = 0u;
     const float2* w = omega + (size_t)key * halfp;
     double s = 0.0;
     for (int k = threadIdx.x; k < half; k += kNormThreads) {

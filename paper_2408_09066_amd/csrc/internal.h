@@ -146,7 +146,7 @@ hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const
                          const EncodeWork& w, float2* omega, hipStream_t s);
 
 // inv_norm[key] = 1/||w_key|| (0 for an empty memory) and omega_s = conj(Omega) * inv_norm.
-// Also zeroes hmax_u[0..2] (class maxima and finished-tile counter of the decode that follows).
+// Also zeroes hmax_u[0..1], the ordered class maxima of the decode that follows.
 hipError_t launch_norm(const float2* omega, int nkeys, int half, int halfp, int D, float* inv_norm,
                        float2* omega_s, unsigned* hmax_u, hipStream_t s);
 

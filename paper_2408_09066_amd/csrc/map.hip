@@ -237,7 +237,7 @@ struct vsaogm_map {
     DevBuf<float2> d_omega_s;           // [nkeys][halfp] conj(Omega)/||w|| for the decode
     DevBuf<float> d_partial;            // stream-K partial sums of the decode
     int num_cus = 0;
-    DevBuf<unsigned> d_hmax_u;          // [3] ordered class maxima, finished-block counter
+    DevBuf<unsigned> d_hmax_u;          // [2] ordered class maxima
     DevBuf<unsigned long long> d_bad;   // [1]
     DevBuf<unsigned> d_version;         // [nkeys] change counters of the memories
     unsigned* h_version = nullptr;      // pinned read-back of d_version
@@ -652,7 +652,7 @@ int vsaogm_map_create(const vsaogm_map_desc* d, vsaogm_map** out) {
         m->d_omega.alloc((size_t)m->nkeys * m->halfp, "memories");
         m->d_scale.alloc(m->nkeys, "memory scales");
         m->d_omega_s.alloc((size_t)m->nkeys * m->halfp, "scaled memories");
-        m->d_hmax_u.alloc(3, "class maxima");
+        m->d_hmax_u.alloc(2, "class maxima");
         m->d_bad.alloc(1, "rejected-label counter");
         m->d_version.alloc(m->nkeys, "memory versions");
         hip_check(hipHostMalloc((void**)&m->h_version, sizeof(unsigned) * m->nkeys, hipHostMallocDefault),
@@ -1002,7 +1002,7 @@ int vsaogm_volume_create(const vsaogm_volume_desc* d, vsaogm_volume** out) {
         v->d_omega.alloc((size_t)v->nkeys * v->halfp, "memories");
         v->d_omega_s.alloc((size_t)v->nkeys * v->halfp, "scaled memories");
         v->d_scale.alloc(v->nkeys, "memory scales");
-        v->d_hmax_u.alloc(3, "class maxima");
+        v->d_hmax_u.alloc(2, "class maxima");
         v->d_bad.alloc(1, "rejected-label counter");
         hip_check(hipMemcpy(v->d_cx.p, v->cx.data(), tn[0] * 8, hipMemcpyHostToDevice), "copy");
         hip_check(hipMemcpy(v->d_cy.p, v->cy.data(), tn[1] * 8, hipMemcpyHostToDevice), "copy");
