@@ -10,7 +10,8 @@ hi+lo operands, which meet the fp32 accuracy bar) and classifies the grid (entro
 difference, threshold).
 
 Timed: K plain steps (throughput), then K steps whose stage kernels carry HIP timing events
-(per-kernel durations for the rooflines, per-step latency).  Printed: one JSON line with the
+(per-kernel durations for the rooflines, per-step latency), then K replays of the step
+captured in a HIP graph (reported beside the eager figure).  Printed: one JSON line with the
 whole-step throughput (heatmap cells decoded per second), points encoded per second, per-update
 latency percentiles, the roofline of the dominant kernel, the FP64 CPU oracle timed on a bounded
 sample of the same workload, and the held-out accuracy, 3-D, request-loop and large-map
@@ -475,6 +476,22 @@ def main() -> int:
 
     elapsed = t1 - t0
     ms_step = elapsed / K * 1e3
+    # the same step captured once in a HIP graph and replayed (launch work leaves the host)
+    graph_ms = None
+    try:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        g.replay()
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(K):
+            g.replay()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - tg) / K * 1e3
+        del g
+    except RuntimeError as e:   # reported, not fatal: the eager figures above stand
+        print(f"graph capture failed: {e}", file=sys.stderr)
     lat = [a.elapsed_time(b) for a, b in step_ev]
     stage_ms = {s: float(np.mean([a.elapsed_time(b) for a, b in stage_ev[s]])) for s in native.STAGES}
     ncell = w.nx * w.ny
@@ -521,6 +538,7 @@ def main() -> int:
         },
         "points_per_s": w.n * K / elapsed,
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
+        "graph_ms_per_step": graph_ms,
         "stages": stages,
         "roofline": roof,
     }

@@ -44,6 +44,16 @@
  *     GPU finishes); the caller must keep inputs alive and outputs untouched
  *     until the stream reaches that point;
  *   - a map is not thread-safe; a server is safe for concurrent submit/poll.
+ *
+ * Graph capture.  Work buffers and a grid's tables are made on the first call
+ * that needs them (vsaogm_encode with more points than before, the first
+ * vsaogm_decode of a grid and precision); those calls may allocate and
+ * synchronise.  Once a map has run an update of a given point count, grid and
+ * precision, vsaogm_map_reset, vsaogm_encode, vsaogm_decode and
+ * vsaogm_classify for the same sizes launch kernels only (no allocation, no
+ * synchronisation, no memset), so a caller can capture such an update in a HIP
+ * graph on its stream and replay it for later scans of that size, copying the
+ * new points into the captured input buffers first.
  */
 #ifndef VSAOGM_H
 #define VSAOGM_H
