@@ -48,31 +48,32 @@ __device__ inline int nearest_tile(double x, double y, const LayoutDev& L) {
 }
 
 // One point per thread; blocks of kAssignChunk points.  hist is key-major:
-// hist[key][chunk] = number of the chunk's points with that key.
+// hist[key][chunk] = number of the chunk's points with that key.  The lanes of a wavefront
+// holding one key add their count with one LDS atomic (a chunk's points share few keys).
 __global__ __launch_bounds__(kAssignChunk) void k_assign(const float2* __restrict__ xy,
                                                          const uint8_t* __restrict__ label,
                                                          int64_t n, LayoutDev L, int nkeys,
-                                                         int nchunks, int* __restrict__ key_out,
+                                                         int nchunks, int key_bits, int* __restrict__ key_out,
                                                          int* __restrict__ hist,
                                                          unsigned long long* __restrict__ n_bad) {
     extern __shared__ int sh_hist[];
     for (int k = threadIdx.x; k < nkeys; k += blockDim.x) sh_hist[k] = 0;
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * kAssignChunk + threadIdx.x;
+    int key = -1;
     if (i < n) {
         const float2 p = xy[i];
         const unsigned l = label[i];
-        int key = -1;
         if (l <= 1u) {
             const int b = nearest_tile((double)p.x, (double)p.y, L);
             if (b >= 0) key = 2 * b + (int)l;
         }
-        if (key < 0)
-            atomicAdd(n_bad, 1ull);
-        else
-            atomicAdd(&sh_hist[key], 1);
+        if (key < 0) atomicAdd(n_bad, 1ull);
         key_out[i] = key;
     }
+    const int lane = threadIdx.x & 63;
+    const uint64_t same = same_value_lanes(key < 0 ? (unsigned)nkeys : (unsigned)key, key_bits);
+    if (key >= 0 && (same & ((1ull << lane) - 1ull)) == 0) atomicAdd(&sh_hist[key], __popcll(same));
     __syncthreads();
     for (int k = threadIdx.x; k < nkeys; k += blockDim.x)
         hist[(size_t)k * nchunks + blockIdx.x] = sh_hist[k];
@@ -228,20 +229,24 @@ __global__ __launch_bounds__(64 * WAVES) void k_scatter(const float2* __restrict
     constexpr int R = Q / 64;                         // rounds per wave
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t q0 = (int64_t)blockIdx.x * kAssignChunk + (int64_t)wave * Q;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int kk[R];
     float2 pp[R];
+    uint64_t same[R];   // lanes of the round with this lane's key
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t i = q0 + r * 64 + lane;
         kk[r] = (i < n) ? key[i] : -1;
         pp[r] = (i < n) ? xy[i] : make_float2(0.f, 0.f);
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r) same[r] = same_value_lanes(kk[r] < 0 ? (unsigned)nkeys : (unsigned)kk[r], key_bits);
     for (int k = threadIdx.x; k < WAVES * nkeys; k += blockDim.x) run[k] = 0;
     __syncthreads();
     int* my = run + wave * nkeys;
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-        if (kk[r] >= 0) atomicAdd(&my[kk[r]], 1);
+    for (int r = 0; r < R; ++r)   // one atomic per key and round
+        if (kk[r] >= 0 && (same[r] & lt_mask) == 0) atomicAdd(&my[kk[r]], __popcll(same[r]));
     __syncthreads();
     for (int k = threadIdx.x; k < nkeys; k += blockDim.x) {  // counts -> per-wave bases
         int acc = base[(size_t)k * nchunks + blockIdx.x];
@@ -252,19 +257,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_scatter(const float2* __restrict
         }
     }
     __syncthreads();
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int k = kk[r];
-        const unsigned uk = (k < 0) ? (unsigned)nkeys : (unsigned)k;
-        uint64_t same = ~0ull;
-        for (int b = 0; b < key_bits; ++b) {
-            const bool bit = (uk >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            same &= bit ? m : ~m;
-        }
         if (k >= 0) {
-            const int rank = __popcll(same & lt_mask);
+            const int rank = __popcll(same[r] & lt_mask);
             const int dest = my[k] + rank;
             const int beta = k >> 1;
             const int tx = beta % L.tiles_x, ty = beta / L.tiles_x;
@@ -273,7 +270,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_scatter(const float2* __restrict
             const float fx = (float)lx, fy = (float)ly;
             sorted[dest] = make_float2(fx, fy);
             sorted_lo[dest] = make_float2((float)(lx - (double)fx), (float)(ly - (double)fy));
-            if ((same & lt_mask) == 0) my[k] += __popcll(same);
+            if ((same[r] & lt_mask) == 0) my[k] += __popcll(same[r]);
         }
         __syncthreads();
     }
@@ -537,7 +534,7 @@ hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const
     const EncodePlan p = encode_plan(n, halfp, nkeys);
     const float2* xy2 = reinterpret_cast<const float2*>(xy);
     hipLaunchKernelGGL(k_assign, dim3(p.nchunks), dim3(kAssignChunk), nkeys * sizeof(int), s, xy2,
-                       label, n, L, nkeys, p.nchunks, w.key, w.hist, w.n_bad);
+                       label, n, L, nkeys, p.nchunks, bits_for(nkeys), w.key, w.hist, w.n_bad);
     launch_key_scan(w.hist, p.nchunks, nkeys, p.echunk, w.table, w.meta, w.version, s);
     if (4 * nkeys * (int)sizeof(int) <= 65536)
         hipLaunchKernelGGL(k_scatter<4>, dim3(p.nchunks), dim3(256), 4 * nkeys * sizeof(int), s, xy2, w.key,

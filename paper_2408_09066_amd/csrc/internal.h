@@ -23,6 +23,19 @@ constexpr int kMaxRadius = 24;       // largest disk radius of the entropy filte
 // phases; below it single precision keeps the phase error under ~4e-6 revolutions.
 constexpr float kWidePhaseRev = 64.0f;
 
+// Lanes of this wavefront holding the same value v < 2^bits as this lane, as a mask (one ballot
+// per bit).  Every lane of the wavefront must take part; the result includes inactive lanes
+// only if they are, so callers run it with the whole wavefront active.
+__device__ inline uint64_t same_value_lanes(unsigned v, int bits) {
+    uint64_t same = ~0ull;
+    for (int b = 0; b < bits; ++b) {
+        const bool bit = (v >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        same &= bit ? m : ~m;
+    }
+    return same;
+}
+
 // Tile layout as the kernels see it.  Centres are computed on the host in double
 // precision, cx[tx] = x0 + (tx + 0.5) * (x1 - x0) / tiles_x.
 struct LayoutDev {

@@ -57,26 +57,27 @@ __device__ int nearest_tile3(double x, double y, double z, const Layout3Dev& L) 
     return best;
 }
 
-// One point per thread, blocks of kAssignChunk points; hist[key][chunk] = the chunk's count.
+// One point per thread, blocks of kAssignChunk points; hist[key][chunk] = the chunk's count,
+// added with one LDS atomic per key and wavefront.
 __global__ __launch_bounds__(kAssignChunk) void k3_assign(const float* __restrict__ xyz,
                                                           const uint8_t* __restrict__ label, int64_t n,
-                                                          Layout3Dev L, int nkeys, int nchunks,
+                                                          Layout3Dev L, int nkeys, int nchunks, int key_bits,
                                                           int* __restrict__ key_out, int* __restrict__ hist,
                                                           unsigned long long* __restrict__ n_bad) {
     extern __shared__ int sh_hist[];
     for (int k = threadIdx.x; k < nkeys; k += blockDim.x) sh_hist[k] = 0;
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * kAssignChunk + threadIdx.x;
+    int k = -1;
     if (i < n) {
         const unsigned l = label[i];
-        int k = -1;
         if (l <= 1u) k = 2 * nearest_tile3(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], L) + (int)l;
-        if (k < 0)
-            atomicAdd(n_bad, 1ull);
-        else
-            atomicAdd(&sh_hist[k], 1);
+        if (k < 0) atomicAdd(n_bad, 1ull);
         key_out[i] = k;
     }
+    const int lane = threadIdx.x & 63;
+    const uint64_t same = same_value_lanes(k < 0 ? (unsigned)nkeys : (unsigned)k, key_bits);
+    if (k >= 0 && (same & ((1ull << lane) - 1ull)) == 0) atomicAdd(&sh_hist[k], __popcll(same));
     __syncthreads();
     for (int k = threadIdx.x; k < nkeys; k += blockDim.x) hist[(size_t)k * nchunks + blockIdx.x] = sh_hist[k];
 }
@@ -96,18 +97,22 @@ __global__ __launch_bounds__(64 * WAVES) void k3_scatter(const float* __restrict
     constexpr int Q = kAssignChunk / WAVES, R = Q / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t q0 = (int64_t)blockIdx.x * kAssignChunk + (int64_t)wave * Q;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int kk[R];
+    uint64_t same[R];   // lanes of the round with this lane's key
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t i = q0 + r * 64 + lane;
         kk[r] = (i < n) ? key[i] : -1;
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r) same[r] = same_value_lanes(kk[r] < 0 ? (unsigned)nkeys : (unsigned)kk[r], key_bits);
     for (int k = threadIdx.x; k < WAVES * nkeys; k += blockDim.x) run[k] = 0;
     __syncthreads();
     int* my = run + wave * nkeys;
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-        if (kk[r] >= 0) atomicAdd(&my[kk[r]], 1);
+    for (int r = 0; r < R; ++r)   // one atomic per key and round
+        if (kk[r] >= 0 && (same[r] & lt_mask) == 0) atomicAdd(&my[kk[r]], __popcll(same[r]));
     __syncthreads();
     for (int k = threadIdx.x; k < nkeys; k += blockDim.x) {
         int acc = base[(size_t)k * nchunks + blockIdx.x];
@@ -118,20 +123,12 @@ __global__ __launch_bounds__(64 * WAVES) void k3_scatter(const float* __restrict
         }
     }
     __syncthreads();
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int k = kk[r];
-        const unsigned uk = (k < 0) ? (unsigned)nkeys : (unsigned)k;
-        uint64_t same = ~0ull;
-        for (int b = 0; b < key_bits; ++b) {
-            const bool bit = (uk >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            same &= bit ? m : ~m;
-        }
         if (k >= 0) {
             const int64_t i = q0 + r * 64 + lane;
-            const int dest = my[k] + __popcll(same & lt_mask);
+            const int dest = my[k] + __popcll(same[r] & lt_mask);
             const int b = k >> 1;
             const int tx = b % L.tx, ty = (b / L.tx) % L.ty, tz = b / (L.tx * L.ty);
             const double lx = (double)xyz[3 * i] - L.cx[tx], ly = (double)xyz[3 * i + 1] - L.cy[ty],
@@ -139,7 +136,7 @@ __global__ __launch_bounds__(64 * WAVES) void k3_scatter(const float* __restrict
             const float fx = (float)lx, fy = (float)ly, fz = (float)lz;
             sorted[dest] = make_float4(fx, fy, fz, 0.f);
             sorted_lo[dest] = make_float4((float)(lx - (double)fx), (float)(ly - (double)fy), (float)(lz - (double)fz), 0.f);
-            if ((same & lt_mask) == 0) my[k] += __popcll(same);
+            if ((same[r] & lt_mask) == 0) my[k] += __popcll(same[r]);
         }
         __syncthreads();
     }
@@ -355,7 +352,7 @@ hipError_t launch_encode3(const float* xyz, const uint8_t* label, int64_t n, con
     const EncodePlan p = encode_plan(n, halfp, nkeys);
     Layout3Dev L{V.cx, V.cy, V.cz, V.tx, V.ty, V.tz, V.x0, V.y0, V.z0, V.wx, V.wy, V.wz};
     hipLaunchKernelGGL(k3_assign, dim3(p.nchunks), dim3(kAssignChunk), nkeys * sizeof(int), s, xyz, label, n, L,
-                       nkeys, p.nchunks, w.key, w.hist, w.n_bad);
+                       nkeys, p.nchunks, key_bits_for(nkeys), w.key, w.hist, w.n_bad);
     launch_key_scan(w.hist, p.nchunks, nkeys, p.echunk, w.table, w.meta, nullptr, s);
     if (4 * nkeys * (int)sizeof(int) <= 65536)
         hipLaunchKernelGGL(k3_scatter<4>, dim3(p.nchunks), dim3(256), 4 * nkeys * sizeof(int), s, xyz, w.key, n, L,
