@@ -598,9 +598,6 @@ int vsaogm_map_create(const vsaogm_map_desc* d, vsaogm_map** out) {
         if (!is_finite(d->x0) || !is_finite(d->x1) || !is_finite(d->y0) || !is_finite(d->y1) ||
             !(d->x1 > d->x0) || !(d->y1 > d->y0))
             fail(VSAOGM_EINVAL, "layout rectangle must be finite with x1 > x0 and y1 > y0");
-        int ndev = 0;
-        hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
-        if (d->device < 0 || d->device >= ndev) fail(VSAOGM_EINVAL, "no such device");
         const double* th = d->theta;
         for (int k = 0; k < 2 * D; ++k)
             if (!is_finite(th[k])) fail(VSAOGM_EINVAL, "theta must be finite");
@@ -611,6 +608,9 @@ int vsaogm_map_create(const vsaogm_map_desc* d, vsaogm_map** out) {
             for (int a = 0; a < 2; ++a)
                 if (th[2 * (D - k) + a] != -th[2 * k + a])
                     fail(VSAOGM_EINVAL, "theta must be conjugate-symmetric: theta[D-k] = -theta[k]");
+        int ndev = 0;   // arguments are checked before the device is touched
+        hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+        if (d->device < 0 || d->device >= ndev) fail(VSAOGM_EINVAL, "no such device");
 
         auto m = std::make_unique<vsaogm_map>();
         m->device = d->device;
@@ -947,9 +947,6 @@ int vsaogm_volume_create(const vsaogm_volume_desc* d, vsaogm_volume** out) {
         for (int a = 0; a < 3; ++a)
             if (!is_finite(box[a]) || !is_finite(box[3 + a]) || !(box[3 + a] > box[a]))
                 fail(VSAOGM_EINVAL, "layout box must be finite with x1 > x0, y1 > y0 and z1 > z0");
-        int ndev = 0;
-        hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
-        if (d->device < 0 || d->device >= ndev) fail(VSAOGM_EINVAL, "no such device");
         const double* th = d->theta;
         for (int k = 0; k < 3 * D; ++k)
             if (!is_finite(th[k])) fail(VSAOGM_EINVAL, "theta must be finite");
@@ -960,6 +957,9 @@ int vsaogm_volume_create(const vsaogm_volume_desc* d, vsaogm_volume** out) {
                 if (th[3 * (D - k) + a] != -th[3 * k + a])
                     fail(VSAOGM_EINVAL, "theta must be conjugate-symmetric: theta[D-k] = -theta[k]");
         }
+        int ndev = 0;   // arguments are checked before the device is touched
+        hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+        if (d->device < 0 || d->device >= ndev) fail(VSAOGM_EINVAL, "no such device");
         auto v = std::make_unique<vsaogm_volume>();
         v->device = d->device;
         v->D = D;
