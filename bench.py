@@ -20,6 +20,7 @@ sections.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -70,6 +71,17 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, budget_s: float):
     """Time the FP64 oracle on a bounded sample of the workload and scale to cells/s."""
     import oracle
@@ -106,6 +118,7 @@ def cpu_baseline(w, budget_s: float):
         "value": ncell / step,
         "unit": "cells/s",
         "cores": oracle.num_threads(),
+        "cpu_model": cpu_model(),
         "kind": "oracle",
         "sample": (f"encode of the first {n_enc} of {w.n} points ({t_enc:.2f} s), similarity at "
                    f"{n_dec} random cells of {ncell} ({t_dec:.2f} s), entropy/softmax/threshold on a "
@@ -516,8 +529,11 @@ def main() -> int:
         "classify": {"bound": "hbm", "achieved": cls_bytes / (stage_ms["classify"] * 1e-3) / 1e9,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "ms": stage_ms["classify"]},
     }
-    for v in stages.values():
+    for name, v in stages.items():
         v["frac"] = v["achieved"] / v["peak"]
+        tb = measured_traffic(name)     # HBM bytes per launch from the counters, if current
+        v["hbm_gbs"] = tb / (v["ms"] * 1e-3) / 1e9 if tb else None
+    stages["decode"]["issued_frac"] = stages["decode"]["frac"] * stages["decode"]["issued_per_useful"]
     dom = max(stages, key=lambda s: stages[s]["ms"])
     d = stages[dom]
     roof = {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
@@ -543,6 +559,12 @@ def main() -> int:
             "precision": args.precision,
         },
         "points_per_s": w.n * K / elapsed,
+        # cells/s of the similarity GEMM alone and of decode + classification (both classes'
+        # heatmaps, then the labelled map), from the same launches' timings
+        "gemm_cells_per_s": ncell / (stage_ms["decode"] * 1e-3),
+        "decode_classify_cells_per_s": ncell / ((stage_ms["decode"] + stage_ms["classify"]) * 1e-3),
+        "input_sha256": {k: hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+                         for k, a in (("xy", w.xy), ("label", w.label), ("theta", w.theta))},
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
         "graph_ms_per_step": graph_ms,
         "stages": stages,

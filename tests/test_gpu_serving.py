@@ -239,3 +239,45 @@ def test_local_requests_switching_grids(torch_cuda):
                           "label": lab.cpu().numpy()}, j)
     ref_map.close()
     srv.close()
+
+
+def test_request_stream_against_oracle(torch_cuda):
+    """The benchmark's request stream (16 maps, 256 updates): every update of its two cheapest
+    maps (D = 2048, the smallest grids), served interleaved in stream order, against the FP64
+    oracle's memories accumulated update by update: whole heatmaps within the fp32 bar, labels
+    >= 99.9 % with every disagreement within 1e-3 of the threshold."""
+    say("[gpu] request stream vs oracle")
+    from paper_2408_09066_amd import native
+    maps, reqs = synth.serving_stream()
+    small = sorted((m.side, i) for i, m in enumerate(maps) if m.D == 2048)[:2]
+    chosen = [i for _, i in small]
+    srv = native.Server(max_inflight=8)
+    ids = {i: srv.add_map(maps[i].theta, maps[i].layout, maps[i].tiles) for i in chosen}
+    tickets = []
+    for q in reqs:
+        if q.map_id in ids:
+            spec = maps[q.map_id]
+            t, out = srv.submit(ids[q.map_id], q.xy, q.label, spec.grid, spec.side, spec.side, 3, 3, 0.0,
+                                "bf16x3", want=("label", "ogm", "heat"))
+            tickets.append((q, t, out))
+    omega = {i: None for i in chosen}
+    worst, n = 0.0, 0
+    for q, t, out in tickets:
+        assert srv.wait(t)["status"] == 0
+        spec = maps[q.map_id]
+        omega[q.map_id], bad = oracle.encode(spec.theta, spec.layout, spec.tiles, q.xy, q.label,
+                                             omega=omega[q.map_id])
+        assert bad == 0
+        P = oracle.similarity(spec.theta, spec.layout, spec.tiles, omega[q.map_id], spec.grid, spec.side,
+                              spec.side)
+        _, _, ogm, lab = oracle.postprocess(P, 3, 3, 0.0)
+        for p in range(2):
+            e = float(np.linalg.norm(out["heat"][p] - P[p]) / np.linalg.norm(P[p]))
+            worst = max(worst, e)
+            assert e <= 1e-4, (q.map_id, p, e)
+        flips = out["label"] != lab
+        assert float(np.mean(~flips)) >= 0.999
+        assert not flips.any() or float(np.max(np.abs(ogm[flips]))) < 1e-3
+        n += 1
+    srv.close()
+    say(f"  {n} updates of maps {chosen}: worst heat rel-L2 {worst:.2e}")
