@@ -71,6 +71,26 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
 
 
+def measured_hbm_copy_gbs() -> float:
+    """Device-to-device copy of 1 GiB (bytes read plus bytes written per second): the HBM rate
+    a streaming kernel can reach on this device, beside the 8 TB/s of the datasheet."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    reps = 5
+    t = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * 4 * n * reps / dt / 1e9
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -114,6 +134,19 @@ def cpu_baseline(w, budget_s: float):
     oracle.postprocess(P, w.r_occ, w.r_emp, w.rho)
     t_cls = time.perf_counter() - t
     step = t_enc * (w.n / n_enc) + t_dec * (ncell / n_dec) + t_cls * (ncell / (sub * sub))
+    # the same kinds of work on one host thread, on smaller samples (about budget/4 seconds)
+    threads = oracle.num_threads()
+    oracle.set_threads(1)
+    n1 = min(w.n, max(64, int(n_enc * (budget_s / 8) / max(t_enc * threads, 1e-6))))
+    t = time.perf_counter()
+    om1, _ = oracle.encode(w.theta, w.layout, w.tiles, w.xy[:n1], w.label[:n1])
+    t_enc1 = time.perf_counter() - t
+    c1 = cells[:max(16, int(n_dec * (budget_s / 8) / max(t_dec * threads, 1e-6)))]
+    t = time.perf_counter()
+    oracle.similarity_cells(w.theta, w.layout, w.tiles, om1, w.grid, w.nx, c1)
+    t_dec1 = time.perf_counter() - t
+    oracle.set_threads(threads)
+    step1 = t_enc1 * (w.n / n1) + t_dec1 * (ncell / len(c1)) + t_cls * threads * (ncell / (sub * sub))
     return {
         "value": ncell / step,
         "unit": "cells/s",
@@ -125,6 +158,9 @@ def cpu_baseline(w, budget_s: float):
                    f"{sub}x{sub} sub-grid ({t_cls:.2f} s); scaled to one full update "
                    f"({step:.1f} s)"),
         "points_per_s": n_enc / t_enc,
+        "single_thread": {"value": ncell / step1, "points_per_s": n1 / t_enc1,
+                          "sample": f"encode of {n1} points ({t_enc1:.2f} s), similarity at {len(c1)} cells "
+                                    f"({t_dec1:.2f} s), post-processing scaled from the threaded run"},
     }
 
 
@@ -571,6 +607,7 @@ def main() -> int:
         "roofline": roof,
     }
     m.close()
+    result["measured_peaks"] = {"hbm_copy_gbs": measured_hbm_copy_gbs(), "datasheet_hbm_gbs": PEAK_HBM_GBS}
     result["accuracy"] = heldout_accuracy(w, args.precision)
     if args.volume:
         result["volume"] = volume_benchmark()

@@ -57,6 +57,7 @@ def lib():
         L.vo_fuse.argtypes = [i32, i64, i32, P, P, P, P]
         L.vo_postprocess_ex.argtypes = [P, i32, i32, i32, i32, f64, i32, i32, i32, P, P, P, P]
         L.vo_num_threads.restype = i32
+        L.vo_set_threads.argtypes = [i32]
         L.vo3_tile_center.argtypes = [P, P, i32, P, P, P]
         L.vo3_assign_tile.argtypes = [P, P, f64, f64, f64]
         L.vo3_assign_tile.restype = i32
@@ -82,6 +83,11 @@ def _lay(layout, tiles):
 
 def num_threads() -> int:
     return int(lib().vo_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Host threads of the following calls (for timing; results do not depend on it)."""
+    lib().vo_set_threads(int(n))
 
 
 def num_memories(tiles) -> int:

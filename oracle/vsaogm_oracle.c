@@ -402,6 +402,16 @@ int32_t vo_num_threads(void)
 #endif
 }
 
+/* Host threads the following oracle calls use (timing only; results do not depend on it). */
+void vo_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /*
  * ---------------------------------------------------------------------------
  * Three dimensions (the 3-D extension named as future work in Sec. V; the
