@@ -14,7 +14,7 @@ constexpr int kMaxTilesPerAxis = 64;
 constexpr int kMaxKeys = 2 * kMaxTilesPerAxis * kMaxTilesPerAxis;  // 8192 memories
 constexpr int kAssignChunk = 1024;   // points per histogram / stable-scatter chunk
 constexpr int kHistPad = 16;         // entries of padding after a key histogram (aligned group reads)
-constexpr int kEncodeChunk = 1024;   // points per encode work item (even, so pairs never straddle)
+constexpr int kEncodeChunk = 512;    // points per encode work item (even, so pairs never straddle)
 constexpr int kEncodeThreads = 256;
 constexpr int kEncodeBpt = 4;        // spectrum bins per encode thread
 constexpr int kBinPad = 64;          // stored half spectra are padded to a multiple of this

@@ -173,12 +173,13 @@ struct Slot {
 
 // Bytes a request holds while it runs: its inputs and outputs on the device plus the map's
 // working buffers for its points (sorted coordinates, keys, partial spectra) and grid.
-int64_t footprint_of(const vsaogm_request& r, int32_t dim) {
+int64_t footprint_of(const vsaogm_request& r, int32_t dim, int64_t nkeys) {
     const int64_t n = r.n, cells = (int64_t)r.grid.nx * r.grid.ny;
     const int64_t halfp = ((int64_t)dim / 2 + 63) / 64 * 64;
     const int64_t inputs = n * 9;
     const int64_t outputs = cells * 13 + 8;
-    const int64_t encode_ws = n * 20 + (n / 64 + 1024) * halfp * 8;
+    // work items hold at least 64 points, plus one partial item per memory
+    const int64_t encode_ws = n * 20 + (n / 64 + 1 + nkeys) * halfp * 8;
     const int64_t decode_ws = (int64_t)256 * 2 * 2 * 256 * 64 * 4;  // stream-K partial sums (upper bound)
     return inputs + outputs + encode_ws + decode_ws;
 }
@@ -191,6 +192,7 @@ struct vsaogm_server {
     int max_inflight = 4, max_queue = 1024;
     std::vector<vsaogm_map*> maps;
     std::vector<int32_t> map_dim;
+    std::vector<int64_t> map_keys;
     std::vector<char> map_busy;
     // heat kept per map for VSAOGM_REQUEST_LOCAL (only the map's own running request uses it)
     struct LocalHeat {
@@ -428,6 +430,7 @@ int vsaogm_server_add_map(vsaogm_server* s, const vsaogm_map_desc* d, int32_t* m
         std::lock_guard<std::mutex> lk(s->mu);
         s->maps.push_back(m);
         s->map_dim.push_back(dd.dim);
+        s->map_keys.push_back(2 * (int64_t)dd.tiles_x * dd.tiles_y);
         s->map_busy.push_back(0);
         s->local_heat.push_back(std::make_unique<vsaogm_server::LocalHeat>());
         *map_id = (int32_t)s->maps.size() - 1;
@@ -461,7 +464,7 @@ std::unique_ptr<Request> prepare(vsaogm_server* s, const vsaogm_request* r) {
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (r->map_id < 0 || r->map_id >= (int32_t)s->maps.size()) throw Fail(VSAOGM_ENOTFOUND, "unknown map");
-        q->footprint = footprint_of(*r, s->map_dim[r->map_id]);
+        q->footprint = footprint_of(*r, s->map_dim[r->map_id], s->map_keys[r->map_id]);
     }
     if (q->footprint > s->budget) throw Fail(VSAOGM_EINVAL, "request exceeds the memory budget");
     if (r->n > 0) {
@@ -597,7 +600,7 @@ int vsaogm_request_bytes(vsaogm_server* s, const vsaogm_request* r, int64_t* byt
     if (!s || !r || !bytes) return VSAOGM_EINVAL;
     std::lock_guard<std::mutex> lk(s->mu);
     if (r->map_id < 0 || r->map_id >= (int32_t)s->maps.size()) return VSAOGM_ENOTFOUND;
-    *bytes = footprint_of(*r, s->map_dim[r->map_id]);
+    *bytes = footprint_of(*r, s->map_dim[r->map_id], s->map_keys[r->map_id]);
     return VSAOGM_OK;
 }
 
