@@ -89,6 +89,23 @@ __device__ inline uint16_t f16_bits(float f) {
     return __builtin_bit_cast(uint16_t, h);
 }
 
+// (re, im) of one bin into a 16-bit table at element o (re) and o + 1 (im); lo, if given, takes
+// the rounding residuals (split form).
+__device__ inline void store16(const double (&v)[2], size_t o, int fp16, uint16_t* __restrict__ hi,
+                               uint16_t* __restrict__ lo) {
+    for (int q = 0; q < 2; ++q) {
+        if (fp16) {
+            const uint16_t h = f16_bits((float)v[q]);
+            hi[o + q] = h;
+            if (lo) lo[o + q] = f16_bits((float)(v[q] - (double)__builtin_bit_cast(_Float16, h)));
+        } else {
+            const uint16_t h = bf16_bits((float)v[q]);
+            hi[o + q] = h;
+            if (lo) lo[o + q] = bf16_bits((float)(v[q] - (double)bf16_value(h)));
+        }
+    }
+}
+
 // 16-bit tables [c][2*halfp] (re, im per bin); lo holds the rounding residual (split form).
 __global__ __launch_bounds__(256) void k_table_16(const double* __restrict__ theta_rad, int axis,
                                                   const double* __restrict__ local, int half,
@@ -99,17 +116,26 @@ __global__ __launch_bounds__(256) void k_table_16(const double* __restrict__ the
     if (k >= halfp) return;
     double v[2] = {0.0, 0.0};
     if (k < half) sincos(theta_rad[2 * k + axis] * local[c], &v[1], &v[0]);
-    for (int q = 0; q < 2; ++q) {
-        const size_t o = (size_t)c * 2 * halfp + 2 * k + q;
-        if (fp16) {
-            const uint16_t h = f16_bits((float)v[q]);
-            hi[o] = h;
-            if (lo) lo[o] = f16_bits((float)(v[q] - (double)__builtin_bit_cast(_Float16, h)));
-        } else {
-            const uint16_t h = bf16_bits((float)v[q]);
-            hi[o] = h;
-            if (lo) lo[o] = bf16_bits((float)(v[q] - (double)bf16_value(h)));
-        }
+    store16(v, (size_t)c * 2 * halfp + 2 * k, fp16, hi, lo);
+}
+
+// Joint (z, y) rows of a volume, one block per row r of the row space: voxel plane offset
+// row_map[r] = slice * ny + y, spectrum exp(i (Theta_y[k] y + Theta_z[k] z)) with the phase
+// formed in double precision from the tile-local coordinates.
+__global__ __launch_bounds__(256) void k_table_yz_16(const double* __restrict__ theta_xy,
+                                                     const double* __restrict__ theta_z,
+                                                     const double* __restrict__ local_y,
+                                                     const double* __restrict__ local_z,
+                                                     const int* __restrict__ row_map, int ny, int half,
+                                                     int halfp, int fp16, uint16_t* __restrict__ hi,
+                                                     uint16_t* __restrict__ lo) {
+    const int r = blockIdx.x;
+    const int rm = row_map[r];
+    const double y = local_y[rm % ny], z = local_z[rm / ny];
+    for (int k = threadIdx.x; k < halfp; k += 256) {
+        double v[2] = {0.0, 0.0};
+        if (k < half) sincos(theta_xy[2 * k + 1] * y + theta_z[2 * k] * z, &v[1], &v[0]);
+        store16(v, (size_t)r * 2 * halfp + 2 * k, fp16, hi, lo);
     }
 }
 
@@ -140,10 +166,10 @@ struct DecodeArgs {
     const float2* omega_s;     // [nkeys][halfp] conj(Omega) / ||w|| (0 for an empty memory)
     int halfp, nx, ny, tiles_x;
     float out_scale;           // 2 / D
-    float* heat;               // [2][slices][ny][nx]: class planes class_stride apart, a tile's
-                               // slice (DTile::pad) nx*ny further
+    float* heat;               // [2][slices][ny][nx]: class planes class_stride apart
     size_t class_stride;
-    const float2* ez;          // [slices][halfp] third-axis table (volumes), else null
+    const int* row_map;        // volumes: voxel plane offset (slice * ny + y) of every row of the
+                               // joint (z, y) row space; null for maps
     unsigned* hmax_u;          // [2] ordered maxima (zeroed by the norm kernel)
     float* partial;            // [grid][2][2][kTileRows][kTileCols]
     int ksteps;                // K steps per tile
@@ -452,7 +478,8 @@ struct Wide {
 static_assert(Wide<1>::TR == 16 * kDecodeSetRowBlocks[1] && Wide<3>::TR == 16 * kDecodeSetRowBlocks[2],
               "tile sets match the kernels");
 
-// Z: volumes, the column operand also carries the third-axis table of the tile's slice.
+// Z: volumes; rows are the joint (z, y) rows of the volume (the row operand is their joint table)
+// and row_map places them in the heat planes.
 template <int PREC, bool Z>
 __global__ __launch_bounds__(256, Wide<PREC>::OCC) void k_decode16(DecodeArgs a) {
     using W = Wide<PREC>;
@@ -502,7 +529,6 @@ __global__ __launch_bounds__(256, Wide<PREC>::OCC) void k_decode16(DecodeArgs a)
             ex_row[u] = reinterpret_cast<const f32x4*>(a.ex + (size_t)gcol * a.halfp + 2 * part16);
             oslot[u] = min(max(a.col_tx[gcol] - t.tx0, 0), 1);
         }
-        const f32x4* ez_row = Z ? reinterpret_cast<const f32x4*>(a.ez + (size_t)t.pad * a.halfp + 2 * part16) : nullptr;
         const int oks = (lane >> 5) & 1, ocls = (lane >> 4) & 1;  // this lane's staging item
         const f32x4* om_src = reinterpret_cast<const f32x4*>(
             a.omega_s + (size_t)(2 * (t.ty * a.tiles_x + min(t.tx0 + oks, a.tiles_x - 1)) + ocls) * a.halfp +
@@ -515,7 +541,7 @@ __global__ __launch_bounds__(256, Wide<PREC>::OCC) void k_decode16(DecodeArgs a)
         };
 
         u32x4 A[NSETS][RBW][2][NS];     // [set][block][32-real chunk][hi, lo]
-        f32x4 BX[B_PER_T], BZ;
+        f32x4 BX[B_PER_T];
 
         // Loads are issued without branches (blocks past the tile's last one reload a clamped row,
         // steps past the segment's last one reload its last step), so that the compiler can count
@@ -536,7 +562,6 @@ __global__ __launch_bounds__(256, Wide<PREC>::OCC) void k_decode16(DecodeArgs a)
             const size_t boff = (size_t)(kb0 + min(kk, n - 1)) * (KB / 2);
 #pragma unroll
             for (int u = 0; u < B_PER_T; ++u) BX[u] = ex_row[u][boff];
-            if (Z) BZ = ez_row[boff];
         };
         // column operand into LDS stage st: conj(Omega)/||w|| * Ex as (Re, -Im)
         auto bstore = [&](int st) {
@@ -546,11 +571,6 @@ __global__ __launch_bounds__(256, Wide<PREC>::OCC) void k_decode16(DecodeArgs a)
                 const int idx = tid + 256 * u;
                 const int c = idx / (KB / 2), part = idx % (KB / 2);
                 f32x4 e = BX[u];
-                if (Z) {  // Ex * Ez of the slice, two complex bins
-                    const f32x4 z = BZ;
-                    e = f32x4{__builtin_fmaf(e.x, z.x, -e.y * z.y), __builtin_fmaf(e.x, z.y, e.y * z.x),
-                              __builtin_fmaf(e.z, z.z, -e.w * z.w), __builtin_fmaf(e.z, z.w, e.w * z.z)};
-                }
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
                     const f32x4 o = *reinterpret_cast<const f32x4*>(&om_lds[st][(oslot[u] * 2 + p) * KB + 2 * part]);
@@ -651,7 +671,7 @@ __global__ __launch_bounds__(256, Wide<PREC>::OCC) void k_decode16(DecodeArgs a)
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
             float mx = -INFINITY;
-            float* out = a.heat + (size_t)p * a.class_stride + (size_t)t.pad * a.nx * a.ny;
+            float* out = a.heat + (size_t)p * a.class_stride;
 #pragma unroll
             for (int j = 0; j < RBW; ++j)
                 if (j < nj)
@@ -664,7 +684,7 @@ __global__ __launch_bounds__(256, Wide<PREC>::OCC) void k_decode16(DecodeArgs a)
                                 const int row = t.row0 + r, col = t.col0 + c;
                                 if (row < t.row_end && c < t.ncol) {
                                     const float v = acc[j][p][cb][e] * a.out_scale;
-                                    out[(size_t)row * a.nx + col] = v;
+                                    out[(size_t)(Z ? a.row_map[row] : row) * a.nx + col] = v;
                                     mx = fmaxf(mx, v);
                                 }
                             } else {
@@ -733,7 +753,8 @@ __global__ __launch_bounds__(256) void k_decode_fix(DecodeArgs a) {
         const int row = t.row0 + r, col = t.col0 + c;
         if (r < 16 * t.nrb && row < t.row_end && c < t.ncol) {
             const float v = sum[j] * a.out_scale;
-            a.heat[(size_t)p * a.class_stride + (size_t)t.pad * a.nx * a.ny + (size_t)row * a.nx + col] = v;
+            const size_t orow = a.row_map ? (size_t)a.row_map[row] : (size_t)row;
+            a.heat[(size_t)p * a.class_stride + orow * a.nx + col] = v;
             mx[p] = fmaxf(mx[p], v);
         }
     }
@@ -808,6 +829,15 @@ hipError_t launch_table_f32(const double* theta_rad, int axis, const double* loc
     return hipGetLastError();
 }
 
+hipError_t launch_table_yz_split(const double* theta_xy, const double* theta_z, const double* local_y,
+                                 const double* local_z, const int* row_map, int nrows, int ny, int half, int halfp,
+                                 bool fp16, uint16_t* hi, uint16_t* lo, hipStream_t s) {
+    if (nrows > 0)
+        hipLaunchKernelGGL(k_table_yz_16, dim3((unsigned)nrows), dim3(256), 0, s, theta_xy, theta_z, local_y, local_z,
+                           row_map, ny, half, halfp, fp16 ? 1 : 0, hi, lo);
+    return hipGetLastError();
+}
+
 hipError_t launch_table_split(const double* theta_rad, int axis, const double* local, int ncells,
                               int half, int halfp, bool fp16, void* hi, void* lo, hipStream_t s) {
     hipLaunchKernelGGL(k_table_16, dim3((halfp + 255) / 256, ncells), dim3(256), 0, s, theta_rad,
@@ -870,7 +900,7 @@ hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
     a.out_scale = d.out_scale;
     a.heat = d.heat;
     a.class_stride = d.class_stride ? d.class_stride : (size_t)d.nx * d.ny;
-    a.ez = d.ez;
+    a.row_map = d.row_map;
     a.hmax_u = d.hmax_u;
     a.partial = d.partial;
     a.ksteps = d.plan.ksteps;
@@ -883,19 +913,19 @@ hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
     const hipEvent_t g1 = fix ? nullptr : e1;
     switch (precision) {
         case 0:
-            if (d.ez) return hipErrorInvalidValue;  // volumes run the 16-bit kernels
+            if (d.row_map) return hipErrorInvalidValue;  // volumes run the 16-bit kernels
             hipExtLaunchKernelGGL(k_decode<0>, grid, block, 0, s, e0, g1, 0, a);
             break;
         case 1:
-            if (d.ez) hipExtLaunchKernelGGL(k_decode16<1, true>, grid, block, 0, s, e0, g1, 0, a);
+            if (d.row_map) hipExtLaunchKernelGGL(k_decode16<1, true>, grid, block, 0, s, e0, g1, 0, a);
             else hipExtLaunchKernelGGL(k_decode16<1, false>, grid, block, 0, s, e0, g1, 0, a);
             break;
         case 2:
-            if (d.ez) hipExtLaunchKernelGGL(k_decode16<2, true>, grid, block, 0, s, e0, g1, 0, a);
+            if (d.row_map) hipExtLaunchKernelGGL(k_decode16<2, true>, grid, block, 0, s, e0, g1, 0, a);
             else hipExtLaunchKernelGGL(k_decode16<2, false>, grid, block, 0, s, e0, g1, 0, a);
             break;
         case 3:
-            if (d.ez) hipExtLaunchKernelGGL(k_decode16<3, true>, grid, block, 0, s, e0, g1, 0, a);
+            if (d.row_map) hipExtLaunchKernelGGL(k_decode16<3, true>, grid, block, 0, s, e0, g1, 0, a);
             else hipExtLaunchKernelGGL(k_decode16<3, false>, grid, block, 0, s, e0, g1, 0, a);
             break;
         default: return hipErrorInvalidValue;

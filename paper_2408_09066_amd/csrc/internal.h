@@ -68,13 +68,13 @@ struct DTile {
     int col0;         // first grid column
     int ncol;         // columns of this tile (1..64)
     int tx0;          // tile column of its first column; 16-bit tiles span at most tx0, tx0 + 1
-    int pad;          // slice of a volume (0 for maps)
+    int pad;          // unused (keeps the record 32 bytes)
 };
 
 // Rows of one band of decode work: its memories are those of tile row key_row (for volumes
-// tz * tiles_y + ty), its grid rows [row0, row1), in slice `slice` of a volume (0 for maps).
+// tz * tiles_y + ty), its rows [row0, row1) (grid rows of a map; joint (z, y) rows of a volume).
 struct DBand {
-    int key_row, row0, row1, slice;
+    int key_row, row0, row1;
 };
 // Work tiles of a tile set over the bands, the grid's columns with their tile columns tcol.
 std::vector<DTile> build_decode_tiles(const std::vector<DBand>& bands, const std::vector<int>& tcol, int nx,
@@ -175,6 +175,11 @@ hipError_t launch_bump_versions(unsigned* version, int nkeys, hipStream_t s);
 hipError_t launch_table_f32(const double* theta_rad, int axis, const double* local, int ncells,
                             int half, int halfp, float2* tab, hipStream_t s);
 // Same table split into bf16 (or fp16) hi and lo parts: [c][2*halfp] hi, then lo.
+// Joint (z, y) table of a volume, 16-bit [nrows][2 halfp] (+ residual when lo is given): row r is
+// the voxel plane offset row_map[r] = slice * ny + y.  theta_xy [half][2], theta_z [half][2] rad/m.
+hipError_t launch_table_yz_split(const double* theta_xy, const double* theta_z, const double* local_y,
+                                 const double* local_z, const int* row_map, int nrows, int ny, int half, int halfp,
+                                 bool fp16, uint16_t* hi, uint16_t* lo, hipStream_t s);
 hipError_t launch_table_split(const double* theta_rad, int axis, const double* local, int ncells,
                               int half, int halfp, bool fp16, void* hi, void* lo, hipStream_t s);
 
@@ -200,7 +205,7 @@ struct DecodeLaunch {
     float out_scale;        // 2 / D
     float* heat;
     size_t class_stride = 0;   // floats between the class planes of heat (0: nx * ny)
-    const float2* ez = nullptr;  // volumes: [slices][halfp] third-axis table (16-bit kernels only)
+    const int* row_map = nullptr;  // volumes: voxel plane offset of every joint (z, y) row (16-bit kernels only)
     unsigned* hmax_u;       // zeroed by launch_norm
     float* hmax;
     float* partial;         // decode_partial_floats(precision, plan) floats

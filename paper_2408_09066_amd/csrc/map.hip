@@ -194,7 +194,7 @@ std::vector<DTile> build_decode_tiles(const std::vector<DBand>& bands, const std
             d.row0 = bd.row0 + 16 * b0;
             d.row_end = bd.row1;
             d.nrb = nb;
-            d.pad = bd.slice;
+            d.pad = 0;
             groups.push_back(d);
             b0 += nb;
         }
@@ -272,8 +272,10 @@ struct Grid3Cache {
     DevBuf<int> col_tx;
     DevBuf<DTile> tiles[kDecodeTileSets];
     int ntiles[kDecodeTileSets] = {};
-    DevBuf<float2> ex32, ez32;                 // [nx][halfp], [nz][halfp]
-    DevBuf<uint16_t> ey_bf, ey_bf_lo, ey_h;    // [ny][2 halfp]
+    DevBuf<float2> ex32;                       // [nx][halfp]
+    int nrows = 0;                             // joint (z, y) rows = nz * ny
+    DevBuf<int> row_map;                       // [nrows] voxel plane offset slice * ny + y
+    DevBuf<uint16_t> eyz_bf, eyz_bf_lo, eyz_h; // [nrows][2 halfp] joint (z, y) tables
 };
 
 struct vsaogm_volume {
@@ -405,7 +407,7 @@ GridCache* grid_cache(vsaogm_map* m, const vsaogm_grid_desc* g, hipStream_t s) {
     for (int ty = 0; ty < m->tiles_y; ++ty) {
         const int r0 = (int)(std::lower_bound(trow.begin(), trow.end(), ty) - trow.begin());
         const int r1 = (int)(std::upper_bound(trow.begin(), trow.end(), ty) - trow.begin());
-        if (r0 < r1) bands.push_back(DBand{ty, r0, r1, 0});
+        if (r0 < r1) bands.push_back(DBand{ty, r0, r1});
     }
     for (int set = 0; set < kDecodeTileSets; ++set) {
         gc->host_tiles[set] = build_decode_tiles(bands, tcol, g->nx, set);
@@ -546,13 +548,28 @@ Grid3Cache* grid3_cache(vsaogm_volume* v, const vsaogm_grid3_desc* g, hipStream_
             }
     auto gc = std::make_unique<Grid3Cache>();
     gc->key = *g;
+    // joint (z, y) rows grouped by tile block: for each (tz, ty), its slices, and in each slice
+    // its grid rows; every block is one band (its rows share the memories of (tz, ty))
     std::vector<DBand> bands;
-    for (int l = 0; l < nz; ++l)
+    std::vector<int> row_map;
+    row_map.reserve((size_t)nz * ny);
+    for (int tz = 0; tz < v->tiles_z; ++tz) {
+        const int l0 = (int)(std::lower_bound(t[2].begin(), t[2].end(), tz) - t[2].begin());
+        const int l1 = (int)(std::upper_bound(t[2].begin(), t[2].end(), tz) - t[2].begin());
         for (int ty = 0; ty < v->tiles_y; ++ty) {
-            const int r0 = (int)(std::lower_bound(t[1].begin(), t[1].end(), ty) - t[1].begin());
-            const int r1 = (int)(std::upper_bound(t[1].begin(), t[1].end(), ty) - t[1].begin());
-            if (r0 < r1) bands.push_back(DBand{t[2][l] * v->tiles_y + ty, r0, r1, l});
+            const int y0 = (int)(std::lower_bound(t[1].begin(), t[1].end(), ty) - t[1].begin());
+            const int y1 = (int)(std::upper_bound(t[1].begin(), t[1].end(), ty) - t[1].begin());
+            if (l0 >= l1 || y0 >= y1) continue;
+            const int r0 = (int)row_map.size();
+            for (int l = l0; l < l1; ++l)
+                for (int y = y0; y < y1; ++y) row_map.push_back(l * ny + y);
+            bands.push_back(DBand{tz * v->tiles_y + ty, r0, (int)row_map.size()});
         }
+    }
+    gc->nrows = (int)row_map.size();   // every voxel row once: the axes split into per-tile slabs
+    gc->row_map.alloc(row_map.size(), "volume row map");
+    hip_check(hipMemcpy(gc->row_map.p, row_map.data(), row_map.size() * sizeof(int), hipMemcpyHostToDevice),
+              "copy row map");
     for (int set = 1; set < kDecodeTileSets; ++set) {
         std::vector<DTile> tl = build_decode_tiles(bands, t[0], nx, set);
         gc->ntiles[set] = (int)tl.size();
@@ -568,9 +585,7 @@ Grid3Cache* grid3_cache(vsaogm_volume* v, const vsaogm_grid3_desc* g, hipStream_
         hip_check(hipMemcpy(lb[a]->p, loc[a].data(), nc[a] * sizeof(double), hipMemcpyHostToDevice), "copy local");
     }
     gc->ex32.alloc((size_t)nx * v->halfp, "x location table");
-    gc->ez32.alloc((size_t)nz * v->halfp, "z location table");
     hip_check(launch_table_f32(v->d_theta_xy.p, 0, gc->local_x.p, nx, v->half, v->halfp, gc->ex32.p, s), "x table");
-    hip_check(launch_table_f32(v->d_theta_z.p, 0, gc->local_z.p, nz, v->half, v->halfp, gc->ez32.p, s), "z table");
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     v->grid = std::move(gc);
     return v->grid.get();
@@ -1099,25 +1114,24 @@ int vsaogm_volume_decode(vsaogm_volume* v, const vsaogm_grid3_desc* g, int32_t p
         DeviceGuard guard(v->device);
         hipStream_t s = (hipStream_t)stream;
         Grid3Cache* gc = grid3_cache(v, g, s);
-        const size_t n16 = (size_t)g->ny * 2 * v->halfp;
+        const size_t n16 = (size_t)gc->nrows * 2 * v->halfp;
         const void* ey = nullptr;
         const void* ey_lo = nullptr;
+        auto table = [&](DevBuf<uint16_t>& hi, DevBuf<uint16_t>* lo, bool fp16, const char* what) {
+            hi.alloc(n16, what);
+            if (lo) lo->alloc(n16, what);
+            hip_check(launch_table_yz_split(v->d_theta_xy.p, v->d_theta_z.p, gc->local_y.p, gc->local_z.p,
+                                            gc->row_map.p, gc->nrows, g->ny, v->half, v->halfp, fp16, hi.p,
+                                            lo ? lo->p : nullptr, s),
+                      what);
+        };
         if (precision == VSAOGM_FP16) {
-            if (!gc->ey_h.p) {
-                gc->ey_h.alloc(n16, "y location table (fp16)");
-                hip_check(launch_table_split(v->d_theta_xy.p, 1, gc->local_y.p, g->ny, v->half, v->halfp, true,
-                                             gc->ey_h.p, nullptr, s), "y table");
-            }
-            ey = gc->ey_h.p;
+            if (!gc->eyz_h.p) table(gc->eyz_h, nullptr, true, "joint (z, y) table (fp16)");
+            ey = gc->eyz_h.p;
         } else {
-            if (!gc->ey_bf.p) {
-                gc->ey_bf.alloc(n16, "y location table (bf16)");
-                gc->ey_bf_lo.alloc(n16, "y location table (bf16 residual)");
-                hip_check(launch_table_split(v->d_theta_xy.p, 1, gc->local_y.p, g->ny, v->half, v->halfp, false,
-                                             gc->ey_bf.p, gc->ey_bf_lo.p, s), "y table");
-            }
-            ey = gc->ey_bf.p;
-            if (precision == VSAOGM_BF16X3) ey_lo = gc->ey_bf_lo.p;
+            if (!gc->eyz_bf.p) table(gc->eyz_bf, &gc->eyz_bf_lo, false, "joint (z, y) table (bf16 hi + lo)");
+            ey = gc->eyz_bf.p;
+            if (precision == VSAOGM_BF16X3) ey_lo = gc->eyz_bf_lo.p;
         }
         const int set = decode_tile_set(precision);
         DecodeLaunch d;
@@ -1141,7 +1155,7 @@ int vsaogm_volume_decode(vsaogm_volume* v, const vsaogm_grid3_desc* g, int32_t p
         d.out_scale = (float)(2.0 / (double)v->D);
         d.heat = heat;
         d.class_stride = (size_t)g->nx * g->ny * g->nz;
-        d.ez = gc->ez32.p;
+        d.row_map = gc->row_map.p;
         d.hmax_u = v->d_hmax_u.p;
         d.hmax = hmax;
         d.partial = v->d_partial.p;

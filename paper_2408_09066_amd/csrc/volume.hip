@@ -14,8 +14,9 @@
 //               could exceed kWidePhaseRev forms and wraps them in double precision
 //   k3_entropy  -Q ln Q with Q = (P / max P)^2 per voxel and class
 //   k3_classify ball sums of the entropy terms, softmax difference tanh((H1 - H0)/2), threshold
-// The similarity of every voxel is the same GEMM as for maps, per z slice, with the slice's
-// third-axis table folded into the column operand (decode.hip).
+// The similarity of every voxel is the same GEMM as for maps: its rows are the volume's joint
+// (z, y) rows, with a cached table of exp(i (Theta_y y + Theta_z z)) as the row operand
+// (decode.hip).
 #include "internal.h"
 
 namespace vsaogm {
