@@ -153,6 +153,20 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _tensor(t, dtype: str, shape, name: str):
+    """Check that t is a contiguous device tensor of the given dtype ("float32", "uint8") and
+    shape; the kernels read and write it through a raw pointer."""
+    if t is None or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if str(t.dtype) != "torch." + dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
 def _ptr(t) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr() if t is not None else 0)
 
@@ -199,9 +213,8 @@ class Map:
     def encode(self, xy, label, stream=None):
         """xy: float32 [n][2] cuda tensor, label: uint8 [n] cuda tensor."""
         n = int(xy.shape[0])
-        assert xy.is_cuda and label.is_cuda and xy.is_contiguous() and label.is_contiguous()
-        assert str(xy.dtype) == "torch.float32" and str(label.dtype) == "torch.uint8"
-        assert tuple(xy.shape) == (n, 2) and tuple(label.shape) == (n,)
+        _tensor(xy, "float32", (n, 2), "xy")
+        _tensor(label, "uint8", (n,), "label")
         check(load().vsaogm_encode(self._h, _ptr(xy), _ptr(label), n, _stream(stream)))
 
     def take_rejected(self, stream=None) -> int:
@@ -217,7 +230,8 @@ class Map:
             heat = torch.empty((2, ny, nx), dtype=torch.float32, device=dev)
         if hmax is None:
             hmax = torch.empty(2, dtype=torch.float32, device=dev)
-        assert heat.is_contiguous() and tuple(heat.shape) == (2, ny, nx)
+        _tensor(heat, "float32", (2, ny, nx), "heat")
+        _tensor(hmax, "float32", (2,), "hmax")
         g = grid_desc(grid, nx, ny)
         check(load().vsaogm_decode(self._h, ctypes.byref(g), PRECISIONS[precision], _ptr(heat),
                                    _ptr(hmax), _stream(stream)))
@@ -229,7 +243,8 @@ class Map:
         import torch
         if hmax is None:
             hmax = torch.empty(2, dtype=torch.float32, device=torch.device("cuda", self.device))
-        assert heat.is_contiguous() and tuple(heat.shape) == (2, ny, nx)
+        _tensor(heat, "float32", (2, ny, nx), "heat")
+        _tensor(hmax, "float32", (2,), "hmax")
         g = grid_desc(grid, nx, ny)
         check(load().vsaogm_decode_incremental(self._h, ctypes.byref(g), PRECISIONS[precision],
                                                _ptr(heat), _ptr(hmax), _stream(stream)))
@@ -241,6 +256,7 @@ class Map:
         if out is None:
             out = torch.empty((self.n_memories, self.D // 2 + 1, 2), dtype=torch.float32,
                               device=torch.device("cuda", self.device))
+        _tensor(out, "float32", (self.n_memories, self.D // 2 + 1, 2), "out")
         check(load().vsaogm_memories(self._h, _ptr(out), _stream(stream)))
         return out
 
@@ -258,6 +274,10 @@ def classify(heat, hmax, r_occ: int, r_emp: int, rho: float = 0.0, ogm=None, lab
         label = torch.empty((ny, nx), dtype=torch.uint8, device=dev)
     if ogm is None:
         ogm = torch.empty((ny, nx), dtype=torch.float32, device=dev)
+    _tensor(heat, "float32", (2, ny, nx), "heat")
+    _tensor(hmax, "float32", (2,), "hmax")
+    _tensor(ogm, "float32", (ny, nx), "ogm")
+    _tensor(label, "uint8", (ny, nx), "label")
     g = GridDesc(0.0, 0.0, 1.0, int(nx), int(ny))
     if normalize and square and act == "entropy":
         check(load().vsaogm_classify(ctypes.byref(g), _ptr(heat), _ptr(hmax), int(r_occ),
@@ -303,8 +323,10 @@ class Volume:
         check(load().vsaogm_volume_reset(self._h, _stream(stream)))
 
     def encode(self, xyz, label, stream=None):
-        assert xyz.is_contiguous() and label.is_contiguous() and xyz.shape[-1] == 3
-        check(load().vsaogm_volume_encode(self._h, _ptr(xyz), _ptr(label), int(xyz.shape[0]), _stream(stream)))
+        n = int(xyz.shape[0])
+        _tensor(xyz, "float32", (n, 3), "xyz")
+        _tensor(label, "uint8", (n,), "label")
+        check(load().vsaogm_volume_encode(self._h, _ptr(xyz), _ptr(label), n, _stream(stream)))
 
     def take_rejected(self, stream=None) -> int:
         n = ctypes.c_int64()
@@ -319,7 +341,8 @@ class Volume:
             heat = torch.empty((2, nz, ny, nx), dtype=torch.float32, device=dev)
         if hmax is None:
             hmax = torch.empty(2, dtype=torch.float32, device=dev)
-        assert heat.is_contiguous() and tuple(heat.shape) == (2, nz, ny, nx)
+        _tensor(heat, "float32", (2, nz, ny, nx), "heat")
+        _tensor(hmax, "float32", (2,), "hmax")
         g = grid3_desc(grid, nx, ny, nz)
         check(load().vsaogm_volume_decode(self._h, ctypes.byref(g), PRECISIONS[precision], _ptr(heat), _ptr(hmax),
                                           _stream(stream)))
@@ -334,6 +357,10 @@ def classify3(heat, hmax, r_occ: int, r_emp: int, rho: float = 0.0, ogm=None, la
         label = torch.empty((nz, ny, nx), dtype=torch.uint8, device=heat.device)
     if ogm is None:
         ogm = torch.empty((nz, ny, nx), dtype=torch.float32, device=heat.device)
+    _tensor(heat, "float32", (2, nz, ny, nx), "heat")
+    _tensor(hmax, "float32", (2,), "hmax")
+    _tensor(ogm, "float32", (nz, ny, nx), "ogm")
+    _tensor(label, "uint8", (nz, ny, nx), "label")
     g = Grid3Desc(0.0, 0.0, 0.0, 1.0, int(nx), int(ny), int(nz))
     check(load().vsaogm_classify3(ctypes.byref(g), _ptr(heat), _ptr(hmax), int(r_occ), int(r_emp), float(rho),
                                   _ptr(ogm), _ptr(label), int(device), _stream(stream)))

@@ -137,3 +137,28 @@ def test_stress_updates_are_independent_of_generation_order():
     # each update draws from its own sub-stream: update 2 alone equals update 2 in sequence
     xy2, lb2 = sc.update(2)
     assert np.array_equal(xy2, ups[2][0]) and np.array_equal(lb2, ups[2][1])
+
+
+def test_binding_rejects_wrong_tensors_before_the_library():
+    """The binding checks device, dtype, shape and layout of every tensor it passes on."""
+    torch = pytest.importorskip("torch")
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    from paper_2408_09066_amd import native
+    heat = torch.zeros((2, 4, 5), dtype=torch.float32)
+    hmax = torch.zeros(2, dtype=torch.float32)
+    with pytest.raises(ValueError, match="device tensor"):
+        native.classify(heat, hmax, 1, 1)                        # host memory
+    with pytest.raises(ValueError):
+        native.classify3(heat.reshape(2, 1, 4, 5).double(), hmax, 1, 1)   # wrong dtype (and host)
+    t = native._tensor
+    fake = type("T", (), {"is_cuda": True, "dtype": "torch.float64", "shape": (2, 4, 5),
+                          "is_contiguous": lambda self: True})()
+    with pytest.raises(ValueError, match="float32"):
+        t(fake, "float32", (2, 4, 5), "heat")
+    fake.dtype = "torch.float32"
+    with pytest.raises(ValueError, match="shape"):
+        t(fake, "float32", (2, 5, 4), "heat")
+    fake.is_contiguous = lambda: False
+    with pytest.raises(ValueError, match="contiguous"):
+        t(fake, "float32", (2, 4, 5), "heat")
