@@ -386,8 +386,8 @@ int vsaogm_volume_decode(vsaogm_volume* vol, const vsaogm_grid3_desc* grid, int3
 
 /* Entropy classification of a volume (Algorithm 2 with a ball mask of radius r_occ for
    class 1 and r_emp for class 0, 0..24): ogm device float [nz][ny][nx] (or NULL), label
-   device uint8 [nz][ny][nx].  Asynchronous: a stream-ordered scratch of 2 nx ny nz floats
-   (the per-voxel entropy terms) is allocated and released on the stream. */
+   device uint8 [nz][ny][nx].  Asynchronous.  Radii up to 4 run in one kernel; larger radii
+   allocate and release a stream-ordered scratch of 2 nx ny nz floats (the entropy terms). */
 int vsaogm_classify3(const vsaogm_grid3_desc* grid, const float* heat, const float* hmax,
                      int32_t r_occ, int32_t r_emp, float rho, float* ogm, uint8_t* label,
                      int32_t device, vsaogm_stream stream);

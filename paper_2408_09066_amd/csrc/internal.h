@@ -105,7 +105,10 @@ struct Encode3Work {
 hipError_t launch_encode3(const float* xyz, const uint8_t* label, int64_t n, const Volume3Dev& V,
                           const float4* rev, const double* rev_d, float4 max_rev, int nkeys, int half,
                           int halfp, const Encode3Work& w, float2* omega, hipStream_t s);
-// Ball entropy classification of a volume's heat [2][nz][ny][nx]; g is 2*nvox floats of scratch.
+// Ball entropy classification of a volume's heat [2][nz][ny][nx].  Radii up to
+// kClassify3TiledRadius run in one kernel through LDS (g unused, may be NULL); larger radii need g,
+// 2*nvox floats of scratch.
+constexpr int kClassify3TiledRadius = 4;
 hipError_t launch_classify3(const float* heat, const float* hmax, int nx, int ny, int nz, int r_emp, int r_occ,
                             float rho, float* g, float* ogm, uint8_t* label, hipStream_t s);
 

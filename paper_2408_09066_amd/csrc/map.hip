@@ -1174,10 +1174,11 @@ int vsaogm_classify3(const vsaogm_grid3_desc* g, const float* heat, const float*
         DeviceGuard guard(device);
         hipStream_t s = (hipStream_t)stream;
         const size_t nvox = (size_t)g->nx * g->ny * g->nz;
-        float* gbuf = nullptr;
-        hip_check(hipMallocAsync((void**)&gbuf, 2 * nvox * sizeof(float), s), "classify scratch");
+        float* gbuf = nullptr;   // entropy scratch, only for radii beyond the tiled kernel's
+        if (std::max(r_occ, r_emp) > kClassify3TiledRadius)
+            hip_check(hipMallocAsync((void**)&gbuf, 2 * nvox * sizeof(float), s), "classify scratch");
         const hipError_t e = launch_classify3(heat, hmax, g->nx, g->ny, g->nz, r_emp, r_occ, rho, gbuf, ogm, label, s);
-        (void)hipFreeAsync(gbuf, s);
+        if (gbuf) (void)hipFreeAsync(gbuf, s);
         hip_check(e, "classify launch");
     });
 }

@@ -12,8 +12,10 @@
 //   k3_encode   per (work item of one memory's sorted points, block of bins): sum of
 //               exp(2 pi i t), t in revolutions, two points per step; a work item whose phases
 //               could exceed kWidePhaseRev forms and wraps them in double precision
-//   k3_entropy  -Q ln Q with Q = (P / max P)^2 per voxel and class
-//   k3_classify ball sums of the entropy terms, softmax difference tanh((H1 - H0)/2), threshold
+//   k3_classify_tiled  radii <= kClassify3TiledRadius: per 8x8x8 block, -Q ln Q with
+//               Q = (P / max P)^2 of the block and its halo into LDS, ball sums there, softmax
+//               difference tanh((H1 - H0)/2), threshold
+//   k3_entropy, k3_classify  larger radii: the same in two passes through a scratch buffer
 // The similarity of every voxel is the same GEMM as for maps: its rows are the volume's joint
 // (z, y) rows, with a cached table of exp(i (Theta_y y + Theta_z z)) as the row operand
 // (decode.hip).
@@ -255,19 +257,89 @@ __global__ __launch_bounds__(kEncodeThreads) void k3_encode(const float4* __rest
     }
 }
 
+// Entropy term -Q ln Q of one similarity, Q = (P / max P)^2 (0 when the class maximum is not
+// positive or Q is 0).
+__device__ inline float entropy_term(float h, float m) {
+    if (!(m > 0.f)) return 0.f;
+    const float q = (h / m) * (h / m);
+    return (q > 0.f) ? -q * __logf(q) : 0.f;
+}
+
 __global__ __launch_bounds__(256) void k3_entropy(const float* __restrict__ heat, const float* __restrict__ hmax,
                                                   int64_t nvox, float* __restrict__ g) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= nvox) return;
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-        const float m = hmax[p];
-        float v = 0.f;
-        if (m > 0.f) {
-            const float q = (heat[p * nvox + i] / m) * (heat[p * nvox + i] / m);
-            v = (q > 0.f) ? -q * __logf(q) : 0.f;
+    for (int p = 0; p < 2; ++p) g[p * nvox + i] = entropy_term(heat[p * nvox + i], hmax[p]);
+}
+
+// Radii up to R in one kernel: a block of kB3^3 voxels computes the entropy terms of its voxels
+// and a halo of R into LDS (zero outside the volume, which excludes those neighbours), then sums
+// each voxel's balls there (offsets with dz, then dy, then dx increasing).
+constexpr int kB3 = 8;
+template <int R>
+__global__ __launch_bounds__(256) void k3_classify_tiled(const float* __restrict__ heat,
+                                                         const float* __restrict__ hmax, int nx, int ny, int nz,
+                                                         int r_emp, int r_occ, float rho,
+                                                         float* __restrict__ ogm, uint8_t* __restrict__ label) {
+    constexpr int W = kB3 + 2 * R, W3 = W * W * W;
+    __shared__ float sg[2 * W3];
+    const int bx = blockIdx.x * kB3, by = blockIdx.y * kB3, bz = blockIdx.z * kB3;
+    const int64_t nvox = (int64_t)nx * ny * nz;
+    const float m0 = hmax[0], m1 = hmax[1];
+    constexpr int kLoadBatch = 8;   // loads in flight per thread
+    for (int base = 0; base < 2 * W3; base += 256 * kLoadBatch) {
+        float raw[kLoadBatch];
+        bool in[kLoadBatch];
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int idx = base + u * 256 + threadIdx.x;
+            const int p = idx >= W3, rem = idx - p * W3;
+            const int gx = bx - R + rem % W, gy = by - R + (rem / W) % W, gz = bz - R + rem / (W * W);
+            in[u] = idx < 2 * W3 && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+            raw[u] = heat[in[u] ? p * nvox + ((int64_t)gz * ny + gy) * nx + gx : 0];
         }
-        g[p * nvox + i] = v;
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int idx = base + u * 256 + threadIdx.x;
+            if (idx < 2 * W3) sg[idx] = in[u] ? entropy_term(raw[u], idx >= W3 ? m1 : m0) : 0.f;
+        }
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < kB3 * kB3 * kB3; c += 256) {
+        const int cx = c % kB3, cy = (c / kB3) % kB3, cz = c / (kB3 * kB3);
+        const int gx = bx + cx, gy = by + cy, gz = bz + cz;
+        if (gx >= nx || gy >= ny || gz >= nz) continue;
+        float h[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int r = p ? r_occ : r_emp;
+            const float* ctr = sg + p * W3 + ((cz + R) * W + (cy + R)) * W + (cx + R);
+            float sum = 0.f;
+            if (r == R) {   // the ball of the tile's radius: offsets known at compile time
+#pragma unroll
+                for (int dz = -R; dz <= R; ++dz)
+#pragma unroll
+                    for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+                        for (int dx = -R; dx <= R; ++dx)
+                            if (dx * dx + dy * dy + dz * dz <= R * R) sum += ctr[(dz * W + dy) * W + dx];
+            } else {
+                for (int dz = -r; dz <= r; ++dz)
+                    for (int dy = -r; dy <= r; ++dy) {
+                        const int e2 = r * r - dz * dz - dy * dy;
+                        if (e2 < 0) continue;
+                        const float* row = ctr + (dz * W + dy) * W;
+                        for (int dx = -r; dx <= r; ++dx)
+                            if (dx * dx <= e2) sum += row[dx];
+                    }
+            }
+            h[p] = sum;
+        }
+        const float o = tanhf(0.5f * (h[1] - h[0]));
+        const int64_t v = ((int64_t)gz * ny + gy) * nx + gx;
+        if (ogm) ogm[v] = o;
+        label[v] = (o >= rho) ? 1 : 0;
     }
 }
 
@@ -383,12 +455,26 @@ hipError_t launch_encode3(const float* xyz, const uint8_t* label, int64_t n, con
 
 hipError_t launch_classify3(const float* heat, const float* hmax, int nx, int ny, int nz, int r_emp, int r_occ,
                             float rho, float* g, float* ogm, uint8_t* label, hipStream_t s) {
+    const int R = r_emp > r_occ ? r_emp : r_occ;
+    const hipEvent_t e0 = profile_start(kStageClassify), e1 = profile_stop(kStageClassify);
+    if (R <= kClassify3TiledRadius) {
+        const dim3 grid((nx + kB3 - 1) / kB3, (ny + kB3 - 1) / kB3, (nz + kB3 - 1) / kB3);
+        const dim3 block(256);
+        switch (R) {
+            case 0: hipExtLaunchKernelGGL(k3_classify_tiled<0>, grid, block, 0, s, e0, e1, 0, heat, hmax, nx, ny, nz, r_emp, r_occ, rho, ogm, label); break;
+            case 1: hipExtLaunchKernelGGL(k3_classify_tiled<1>, grid, block, 0, s, e0, e1, 0, heat, hmax, nx, ny, nz, r_emp, r_occ, rho, ogm, label); break;
+            case 2: hipExtLaunchKernelGGL(k3_classify_tiled<2>, grid, block, 0, s, e0, e1, 0, heat, hmax, nx, ny, nz, r_emp, r_occ, rho, ogm, label); break;
+            case 3: hipExtLaunchKernelGGL(k3_classify_tiled<3>, grid, block, 0, s, e0, e1, 0, heat, hmax, nx, ny, nz, r_emp, r_occ, rho, ogm, label); break;
+            default: hipExtLaunchKernelGGL(k3_classify_tiled<4>, grid, block, 0, s, e0, e1, 0, heat, hmax, nx, ny, nz, r_emp, r_occ, rho, ogm, label); break;
+        }
+        return hipGetLastError();
+    }
+    if (!g) return hipErrorInvalidValue;   // larger radii need the entropy scratch
     const int64_t nvox = (int64_t)nx * ny * nz;
     const unsigned blocks = (unsigned)((nvox + 255) / 256);
-    hipExtLaunchKernelGGL(k3_entropy, dim3(blocks), dim3(256), 0, s, profile_start(kStageClassify), nullptr, 0,
-                          heat, hmax, nvox, g);
-    hipExtLaunchKernelGGL(k3_classify, dim3(blocks), dim3(256), 0, s, nullptr, profile_stop(kStageClassify), 0, g,
-                          nx, ny, nz, r_emp, r_occ, rho, ogm, label);
+    hipExtLaunchKernelGGL(k3_entropy, dim3(blocks), dim3(256), 0, s, e0, nullptr, 0, heat, hmax, nvox, g);
+    hipExtLaunchKernelGGL(k3_classify, dim3(blocks), dim3(256), 0, s, nullptr, e1, 0, g, nx, ny, nz, r_emp, r_occ,
+                          rho, ogm, label);
     return hipGetLastError();
 }
 

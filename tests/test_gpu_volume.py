@@ -82,7 +82,7 @@ def test_volume_pipeline_matches_oracle(torch_cuda, name, precision):
         assert agree >= 0.98
 
 
-@pytest.mark.parametrize("radii", [(1, 1), (2, 1), (0, 3)])
+@pytest.mark.parametrize("radii", [(1, 1), (2, 1), (0, 3), (5, 2)])   # (5, 2): the two-pass path
 def test_classify3_on_oracle_heat(torch_cuda, radii):
     from paper_2408_09066_amd import native
     torch = torch_cuda
