@@ -129,6 +129,8 @@ def test_self_similarity_is_one():
     cx, cy = grid[0] + 7.5 * grid[2], grid[1] + 12.5 * grid[2]
     xy = np.array([[cx, cy]], dtype=np.float32)
     omega, _ = oracle.encode(th, layout, tiles, xy, np.array([1], np.uint8))
+    # one point: every bin of its memory is a unit phasor, and the memory has unit length
+    assert np.max(np.abs(np.hypot(omega[1, :, 0], omega[1, :, 1]) - 1.0)) < 1e-12
     assert abs(oracle.norm(omega[1]) - 1.0) < 1e-13
     cells = np.array([12 * 20 + 7])
     P = oracle.similarity_cells(th, layout, tiles, omega, grid, 20, cells)
@@ -274,6 +276,9 @@ def test_entropy_closed_forms():
     P[1, 5, 5] = 2.0                       # class 1: Q = 1 at one cell, 0 elsewhere
     m, H, ogm, lab = oracle.postprocess(P, r_occ=r, r_emp=r, rho=0.0)
     assert m[0] == 1.0 and m[1] == 2.0
+    # Q = (P / max P)^2 is exactly 1 at each class's argmax, so its entropy term there is 0
+    _, H0, _, _ = oracle.postprocess(P, r_occ=0, r_emp=0, rho=0.0)
+    assert H0[0, 0, 0] == 0.0 and H0[1, 5, 5] == 0.0
     assert abs(H[0, 10, 10] - 29 / math.e) < 1e-12
     assert np.all(H[1] == 0.0)
     # corner (0, 0) with r = 1 sees itself and 2 in-grid neighbours; itself has Q = 1
