@@ -35,10 +35,14 @@ if ROOT not in sys.path:
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0}
-# Issue-limited complex-exponential rate of the encode kernel: 256 CUs x 2.4 GHz x 64 lanes
-# per clock, over 6 issue slots per complex exponential (per pair of points and bin: 4 phase
-# FMA/MUL, 2 accumulate FMA, 3 half-rate transcendentals of 2 slots each = 12 slots).
-PEAK_CEXP_TPS = 256 * 2.4e9 * 64 / 6 / 1e12
+# Issue-limited complex-exponential rate of the encode kernels: 256 CUs x 2.4 GHz x 64 lanes per
+# clock (a wave64 VALU instruction holds a 16-lane SIMD for 4 clocks), one issue slot per VALU
+# instruction.  Per pair of points and bin the plane kernel issues 4 phase MUL/FMA, 3
+# transcendentals and 2 accumulate FMA: 9 slots for two complex exponentials; the volume kernel
+# 6 phase MUL/FMA (three coordinates), 3 transcendentals and 2 FMA: 11 slots.  Transcendentals
+# alone issue at half that rate, so these are upper bounds the kernels cannot quite reach.
+PEAK_CEXP_TPS = 256 * 2.4e9 * 64 / 4.5 / 1e12
+PEAK_CEXP3_TPS = 256 * 2.4e9 * 64 / 5.5 / 1e12
 
 
 # HBM bytes per launch of a stage's main kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE counters
@@ -344,6 +348,7 @@ def volume_benchmark(steps: int = 10, warmup: int = 2, precision: str = "bf16x3"
         "points_per_s": v.n * steps / el,
         "stage_ms": ms,
         "encode_tcexp_per_s": v.n * (v.D // 2 - 1) / (ms["encode"] * 1e-3) / 1e12,
+        "encode_frac": v.n * (v.D // 2 - 1) / (ms["encode"] * 1e-3) / 1e12 / PEAK_CEXP3_TPS,
         "decode_tflops_useful": 4.0 * v.D * nvox / (ms["decode"] * 1e-3) / 1e12,
     }
 

@@ -13,7 +13,7 @@
 namespace vsaogm {
 namespace {
 
-constexpr int TX = 64, TY = 16;
+constexpr int TX = 32, TY = 16;
 
 // Disk sum around the LDS element at `centre` (row pitch W) for a radius known at compile
 // time: straight-line reads at constant offsets within each row.

@@ -545,24 +545,13 @@ hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const
     const double2* rev_d = reinterpret_cast<const double2*>(theta_rev_d);
     const dim3 eg(p.max_echunks, p.binblocks);
     const hipEvent_t e0 = profile_start(kStageEncode), e1 = profile_stop(kStageEncode);
-    switch (p.bpt) {
-        case 1:
-            hipExtLaunchKernelGGL(k_encode<1>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo,
-                                  w.table, w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp, w.partial);
-            break;
-        case 2:
-            hipExtLaunchKernelGGL(k_encode<2>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo,
-                                  w.table, w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp, w.partial);
-            break;
-        case 4:
-            hipExtLaunchKernelGGL(k_encode<4>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo,
-                                  w.table, w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp, w.partial);
-            break;
-        default:
-            hipExtLaunchKernelGGL(k_encode<8>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo,
-                                  w.table, w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp, w.partial);
-            break;
-    }
+    static_assert(kEncodeBpt == 2, "instantiations below");
+    if (p.bpt == 1)
+        hipExtLaunchKernelGGL(k_encode<1>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo, w.table,
+                              w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp, w.partial);
+    else
+        hipExtLaunchKernelGGL(k_encode<2>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo, w.table,
+                              w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp, w.partial);
     launch_key_reduce(w.partial, w.meta, nkeys, half, halfp, omega, s);
     return hipGetLastError();
 }

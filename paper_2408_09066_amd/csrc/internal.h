@@ -16,7 +16,7 @@ constexpr int kAssignChunk = 1024;   // points per histogram / stable-scatter ch
 constexpr int kHistPad = 16;         // entries of padding after a key histogram (aligned group reads)
 constexpr int kEncodeChunk = 512;    // points per encode work item (even, so pairs never straddle)
 constexpr int kEncodeThreads = 256;
-constexpr int kEncodeBpt = 4;        // spectrum bins per encode thread
+constexpr int kEncodeBpt = 2;        // spectrum bins per encode thread (at most)
 constexpr int kBinPad = 64;          // stored half spectra are padded to a multiple of this
 constexpr int kMaxRadius = 24;       // largest disk radius of the entropy filter
 // A phase bound (revolutions) above which a chunk is encoded with double-precision

@@ -435,20 +435,13 @@ hipError_t launch_encode3(const float* xyz, const uint8_t* label, int64_t n, con
                            nkeys, p.nchunks, key_bits_for(nkeys), w.hist, w.sorted, w.sorted_lo);
     const dim3 eg(p.max_echunks, p.binblocks);
     const hipEvent_t e0 = profile_start(kStageEncode), e1 = profile_stop(kStageEncode);
-    switch (p.bpt) {
-        case 1:
-            hipExtLaunchKernelGGL(k3_encode<1>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo,
-                                  w.table, w.meta, rev, rev_d, max_rev, halfp, w.partial);
-            break;
-        case 2:
-            hipExtLaunchKernelGGL(k3_encode<2>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo,
-                                  w.table, w.meta, rev, rev_d, max_rev, halfp, w.partial);
-            break;
-        default:
-            hipExtLaunchKernelGGL(k3_encode<4>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo,
-                                  w.table, w.meta, rev, rev_d, max_rev, halfp, w.partial);
-            break;
-    }
+    static_assert(kEncodeBpt == 2, "instantiations below");
+    if (p.bpt == 1)
+        hipExtLaunchKernelGGL(k3_encode<1>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo, w.table,
+                              w.meta, rev, rev_d, max_rev, halfp, w.partial);
+    else
+        hipExtLaunchKernelGGL(k3_encode<2>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo, w.table,
+                              w.meta, rev, rev_d, max_rev, halfp, w.partial);
     launch_key_reduce(w.partial, w.meta, nkeys, half, halfp, omega, s);
     return hipGetLastError();
 }
