@@ -452,26 +452,30 @@ __global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeAr
     }
 }
 
-// 16-bit operand formats.  Work tiles of 4*RBW row blocks x 64 columns x 2 classes.  The
-// waves split the rows (wave w owns row blocks w, w+4, ...) and read their row operand -- the
+// 16-bit operand formats.  Work tiles of NW*RBW row blocks x 64 columns x 2 classes.  The
+// waves split the rows (wave w owns row blocks w, w+NW, ...) and read their row operand -- the
 // location table, already in the MFMA input format -- straight from global memory into
 // registers, DEPTH K steps ahead; only the column operand, which needs the memory factor
-// applied, goes through LDS (its sources are loaded one step ahead), where all four waves read
-// it.  So LDS carries one operand instead of two, and each wave reads only its own rows' table
-// data.  256-row tiles, one workgroup per CU (the accumulators take the AGPRs).
+// applied, goes through LDS (its sources are loaded one step ahead), where every wave reads it.
+// So LDS carries one operand instead of two, and each wave reads only its own rows' table data.
+// 256-row tiles, one workgroup of eight waves per CU: two waves per SIMD, so that one wave's
+// matrix instructions run while the other forms, stores or waits for operands (with four waves,
+// one per SIMD and the accumulators in AGPRs, every step serialised those phases).
 template <int PREC>
 struct Wide {
     static constexpr bool kSplit = (PREC == 3);
-    static constexpr int RBW = 4;                       // row blocks per wave
+    static constexpr int NW = 8;                        // waves per workgroup (two per SIMD)
+    static constexpr int NT = 64 * NW;                  // threads per workgroup
+    static constexpr int RBW = 16 / NW;                 // row blocks per wave
     static constexpr int OCC = 1;                       // workgroups per CU
-    static constexpr int TR = 64 * RBW;                 // tile rows
+    static constexpr int TR = 16 * NW * RBW;            // tile rows
     static constexpr int NS = kSplit ? 2 : 1;           // hi (+ lo) parts
     static constexpr int DEPTH = 1;                     // K steps the row operand is loaded ahead
     static constexpr int NSETS = DEPTH + 1;             // register sets in rotation
     static constexpr int KB = 32;                       // complex bins per K step
     static constexpr int BROWS = 2 * kTileCols;         // LDS rows: class-major columns
     static constexpr int BSTAGE = NS * BROWS * kRowPitchBytes;
-    static constexpr int B_PER_T = kTileCols * KB / 2 / 256;  // f32x4 units per thread
+    static constexpr int B_PER_T = kTileCols * KB / 2 / NT;  // f32x4 units per thread
     static constexpr int OSTAGE = 2 * 2 * KB;           // float2: [key slot][class][bin]
 };
 
@@ -481,10 +485,10 @@ static_assert(Wide<1>::TR == 16 * kDecodeSetRowBlocks[1] && Wide<3>::TR == 16 * 
 // Z: volumes; rows are the joint (z, y) rows of the volume (the row operand is their joint table)
 // and row_map places them in the heat planes.
 template <int PREC, bool Z>
-__global__ __launch_bounds__(256, Wide<PREC>::OCC) void k_decode16(DecodeArgs a) {
+__global__ __launch_bounds__(Wide<PREC>::NT, Wide<PREC>::OCC) void k_decode16(DecodeArgs a) {
     using W = Wide<PREC>;
     constexpr int NS = W::NS, NSETS = W::NSETS, DEPTH = W::DEPTH, KB = W::KB, RBW = W::RBW, TR = W::TR;
-    constexpr int B_PER_T = W::B_PER_T;
+    constexpr int B_PER_T = W::B_PER_T, NW = W::NW, NT = W::NT;
     __shared__ __attribute__((aligned(16))) unsigned char smem[2 * W::BSTAGE];
     __shared__ __attribute__((aligned(16))) float2 om_lds[2][W::OSTAGE];
 
@@ -508,13 +512,13 @@ __global__ __launch_bounds__(256, Wide<PREC>::OCC) void k_decode16(DecodeArgs a)
         const int n = kb1 - kb0;
         // row blocks of this wave present in the tile (wave-uniform, kept in a scalar register)
         const int wv = __builtin_amdgcn_readfirstlane(wave);
-        const int nj = __builtin_amdgcn_readfirstlane((t.nrb > wv) ? min((t.nrb - wv + 3) / 4, RBW) : 0);
+        const int nj = __builtin_amdgcn_readfirstlane((t.nrb > wv) ? min((t.nrb - wv + NW - 1) / NW, RBW) : 0);
 
         // row operand addresses: row i16 of each owned block, K offset 8*g within a 32-real chunk
         size_t arow[RBW];
 #pragma unroll
         for (int j = 0; j < RBW; ++j) {
-            const int row = min(t.row0 + 16 * (wave + 4 * j) + i16, t.row_end - 1);
+            const int row = min(t.row0 + 16 * (wave + NW * j) + i16, t.row_end - 1);
             arow[j] = (size_t)row * pitch + 8 * g;
         }
         // column operand sources: the x table per column; the memories of the (at most two)
@@ -524,7 +528,7 @@ __global__ __launch_bounds__(256, Wide<PREC>::OCC) void k_decode16(DecodeArgs a)
         const int part16 = tid % (KB / 2);
 #pragma unroll
         for (int u = 0; u < B_PER_T; ++u) {
-            const int c = (tid + 256 * u) / (KB / 2);
+            const int c = (tid + NT * u) / (KB / 2);
             const int gcol = min(t.col0 + c, a.nx - 1);
             ex_row[u] = reinterpret_cast<const f32x4*>(a.ex + (size_t)gcol * a.halfp + 2 * part16);
             oslot[u] = min(max(a.col_tx[gcol] - t.tx0, 0), 1);
@@ -568,7 +572,7 @@ __global__ __launch_bounds__(256, Wide<PREC>::OCC) void k_decode16(DecodeArgs a)
             unsigned char* Bs = smem + st * W::BSTAGE;
 #pragma unroll
             for (int u = 0; u < B_PER_T; ++u) {
-                const int idx = tid + 256 * u;
+                const int idx = tid + NT * u;
                 const int c = idx / (KB / 2), part = idx % (KB / 2);
                 f32x4 e = BX[u];
 #pragma unroll
@@ -679,7 +683,7 @@ __global__ __launch_bounds__(256, Wide<PREC>::OCC) void k_decode16(DecodeArgs a)
                     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
-                            const int r = 16 * (wave + 4 * j) + 4 * g + e, c = 16 * cb + i16;
+                            const int r = 16 * (wave + NW * j) + 4 * g + e, c = 16 * cb + i16;
                             if (whole) {
                                 const int row = t.row0 + r, col = t.col0 + c;
                                 if (row < t.row_end && c < t.ncol) {
@@ -906,7 +910,7 @@ hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
     a.ksteps = d.plan.ksteps;
     a.steps_per_wg = d.plan.steps_per_wg;
     a.total_steps = d.plan.total_steps;
-    const dim3 grid(d.plan.grid), block(256);
+    const dim3 grid(d.plan.grid), block(256), block16(Wide<1>::NT);
     // the GEMM records the stage's start event, and its stop event unless a fix-up follows
     const bool fix = d.plan.steps_per_wg % d.plan.ksteps != 0 || d.plan.steps_per_wg < d.plan.ksteps;
     const hipEvent_t e0 = profile_start(kStageDecode), e1 = profile_stop(kStageDecode);
@@ -917,16 +921,16 @@ hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
             hipExtLaunchKernelGGL(k_decode<0>, grid, block, 0, s, e0, g1, 0, a);
             break;
         case 1:
-            if (d.row_map) hipExtLaunchKernelGGL(k_decode16<1, true>, grid, block, 0, s, e0, g1, 0, a);
-            else hipExtLaunchKernelGGL(k_decode16<1, false>, grid, block, 0, s, e0, g1, 0, a);
+            if (d.row_map) hipExtLaunchKernelGGL(k_decode16<1, true>, grid, block16, 0, s, e0, g1, 0, a);
+            else hipExtLaunchKernelGGL(k_decode16<1, false>, grid, block16, 0, s, e0, g1, 0, a);
             break;
         case 2:
-            if (d.row_map) hipExtLaunchKernelGGL(k_decode16<2, true>, grid, block, 0, s, e0, g1, 0, a);
-            else hipExtLaunchKernelGGL(k_decode16<2, false>, grid, block, 0, s, e0, g1, 0, a);
+            if (d.row_map) hipExtLaunchKernelGGL(k_decode16<2, true>, grid, block16, 0, s, e0, g1, 0, a);
+            else hipExtLaunchKernelGGL(k_decode16<2, false>, grid, block16, 0, s, e0, g1, 0, a);
             break;
         case 3:
-            if (d.row_map) hipExtLaunchKernelGGL(k_decode16<3, true>, grid, block, 0, s, e0, g1, 0, a);
-            else hipExtLaunchKernelGGL(k_decode16<3, false>, grid, block, 0, s, e0, g1, 0, a);
+            if (d.row_map) hipExtLaunchKernelGGL(k_decode16<3, true>, grid, block16, 0, s, e0, g1, 0, a);
+            else hipExtLaunchKernelGGL(k_decode16<3, false>, grid, block16, 0, s, e0, g1, 0, a);
             break;
         default: return hipErrorInvalidValue;
     }
