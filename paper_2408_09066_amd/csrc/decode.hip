@@ -36,6 +36,7 @@ namespace vsaogm {
 namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
@@ -452,27 +453,33 @@ __global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeAr
     }
 }
 
-// 16-bit operand formats.  Work tiles of NW*RBW row blocks x 64 columns x 2 classes.  The
-// waves split the rows (wave w owns row blocks w, w+NW, ...) and read their row operand -- the
+// 16-bit operand formats.  Work tiles of 256 rows x 64 columns x 2 classes on the 32x32x16
+// matrix instructions (the 16x16x32 form of the same formats issues at about half their rate on
+// gfx950).  Each of the NW waves owns one block of 32 consecutive rows and both 32-column blocks
+// of the tile, for both classes (four 32x32 accumulators).  A wave reads its row operand -- the
 // location table, already in the MFMA input format -- straight from global memory into
 // registers, DEPTH K steps ahead; only the column operand, which needs the memory factor
 // applied, goes through LDS (its sources are loaded one step ahead), where every wave reads it.
 // So LDS carries one operand instead of two, and each wave reads only its own rows' table data.
-// 256-row tiles, one workgroup of eight waves per CU: two waves per SIMD, so that one wave's
-// matrix instructions run while the other forms, stores or waits for operands (with four waves,
-// one per SIMD and the accumulators in AGPRs, every step serialised those phases).
+// One workgroup of eight waves per CU: two waves per SIMD, so that one wave's matrix
+// instructions run while the other forms, stores or waits for operands.
+//
+// Lane layout of v_mfma_f32_32x32x16 (16-bit inputs): lane l holds eight consecutive K elements
+// 8*(l/32) .. +7 of row (A) / column (B) l%32; output register v of lane l is row
+// 8*(v/4) + 4*(l/32) + v%4, column l%32.  A K step (64 reals) is four 16-real chunks.
 template <int PREC>
 struct Wide {
     static constexpr bool kSplit = (PREC == 3);
     static constexpr int NW = 8;                        // waves per workgroup (two per SIMD)
     static constexpr int NT = 64 * NW;                  // threads per workgroup
-    static constexpr int RBW = 16 / NW;                 // row blocks per wave
+    static constexpr int WR = 32;                       // rows per wave
     static constexpr int OCC = 1;                       // workgroups per CU
-    static constexpr int TR = 16 * NW * RBW;            // tile rows
+    static constexpr int TR = WR * NW;                  // tile rows
     static constexpr int NS = kSplit ? 2 : 1;           // hi (+ lo) parts
     static constexpr int DEPTH = 1;                     // K steps the row operand is loaded ahead
     static constexpr int NSETS = DEPTH + 1;             // register sets in rotation
     static constexpr int KB = 32;                       // complex bins per K step
+    static constexpr int NCH = 2 * KB / 16;             // 16-real MFMA chunks per K step
     static constexpr int BROWS = 2 * kTileCols;         // LDS rows: class-major columns
     static constexpr int BSTAGE = NS * BROWS * kRowPitchBytes;
     static constexpr int B_PER_T = kTileCols * KB / 2 / NT;  // f32x4 units per thread
@@ -482,18 +489,27 @@ struct Wide {
 static_assert(Wide<1>::TR == 16 * kDecodeSetRowBlocks[1] && Wide<3>::TR == 16 * kDecodeSetRowBlocks[2],
               "tile sets match the kernels");
 
+template <int PREC>
+__device__ inline v16f mfma32(u32x4 x, u32x4 y, v16f c) {
+    if constexpr (PREC == 2)
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, x), __builtin_bit_cast(v8h, y), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, x), __builtin_bit_cast(v8bf, y), c, 0,
+                                                       0, 0);
+}
+
 // Z: volumes; rows are the joint (z, y) rows of the volume (the row operand is their joint table)
 // and row_map places them in the heat planes.
 template <int PREC, bool Z>
 __global__ __launch_bounds__(Wide<PREC>::NT, Wide<PREC>::OCC) void k_decode16(DecodeArgs a) {
     using W = Wide<PREC>;
-    constexpr int NS = W::NS, NSETS = W::NSETS, DEPTH = W::DEPTH, KB = W::KB, RBW = W::RBW, TR = W::TR;
-    constexpr int B_PER_T = W::B_PER_T, NW = W::NW, NT = W::NT;
+    constexpr int NS = W::NS, NSETS = W::NSETS, DEPTH = W::DEPTH, KB = W::KB, NCH = W::NCH, TR = W::TR;
+    constexpr int B_PER_T = W::B_PER_T, NT = W::NT;
     __shared__ __attribute__((aligned(16))) unsigned char smem[2 * W::BSTAGE];
     __shared__ __attribute__((aligned(16))) float2 om_lds[2][W::OSTAGE];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int g = lane >> 4, i16 = lane & 15;
+    const int h = lane >> 5, l32 = lane & 31;
     const int wg = xcd_local_index(blockIdx.x, gridDim.x);
     const long long it0 = (long long)wg * a.steps_per_wg;
     const long long it1 = min(it0 + a.steps_per_wg, a.total_steps);
@@ -510,17 +526,13 @@ __global__ __launch_bounds__(Wide<PREC>::NT, Wide<PREC>::OCC) void k_decode16(De
         it = (long long)ti * a.ksteps + kb1;
         const DTile t = a.tiles[ti];
         const int n = kb1 - kb0;
-        // row blocks of this wave present in the tile (wave-uniform, kept in a scalar register)
+        // does this wave's 32-row block hold any row of the tile (wave-uniform)
         const int wv = __builtin_amdgcn_readfirstlane(wave);
-        const int nj = __builtin_amdgcn_readfirstlane((t.nrb > wv) ? min((t.nrb - wv + NW - 1) / NW, RBW) : 0);
+        const bool active = t.nrb > 2 * wv;
 
-        // row operand addresses: row i16 of each owned block, K offset 8*g within a 32-real chunk
-        size_t arow[RBW];
-#pragma unroll
-        for (int j = 0; j < RBW; ++j) {
-            const int row = min(t.row0 + 16 * (wave + NW * j) + i16, t.row_end - 1);
-            arow[j] = (size_t)row * pitch + 8 * g;
-        }
+        // row operand address: row l32 of the wave's block, K offset 8*h within a 16-real chunk
+        const int arow_idx = min(t.row0 + W::WR * wave + l32, t.row_end - 1);
+        const size_t arow = (size_t)arow_idx * pitch + 8 * h;
         // column operand sources: the x table per column; the memories of the (at most two)
         // tile columns of the slice are staged in LDS, two K steps ahead, by the first wave
         const f32x4* ex_row[B_PER_T];
@@ -544,23 +556,21 @@ __global__ __launch_bounds__(Wide<PREC>::NT, Wide<PREC>::OCC) void k_decode16(De
                 *reinterpret_cast<f32x4*>(&om_lds[st][(oks * 2 + ocls) * KB + 2 * part16]) = OM;
         };
 
-        u32x4 A[NSETS][RBW][2][NS];     // [set][block][32-real chunk][hi, lo]
+        u32x4 A[NSETS][NCH][NS];     // [set][16-real chunk][hi, lo]
         f32x4 BX[B_PER_T];
 
-        // Loads are issued without branches (blocks past the tile's last one reload a clamped row,
+        // Loads are issued without branches (rows past the tile's last one reload a clamped row,
         // steps past the segment's last one reload its last step), so that the compiler can count
         // them exactly and waits only for the data a step actually consumes.
         auto load_a = [&](auto SET, int kk) {  // row operand of K step kb0 + kk into set SET
             constexpr int S = decltype(SET)::value;
             const int kb = kb0 + min(kk, n - 1);
 #pragma unroll
-            for (int j = 0; j < RBW; ++j)
-#pragma unroll
-                    for (int ch = 0; ch < 2; ++ch) {
-                        const size_t off = arow[j] + (size_t)kb * (2 * KB) + 32 * ch;
-                        A[S][j][ch][0] = *reinterpret_cast<const u32x4*>(ey_hi + off);
-                        if (W::kSplit) A[S][j][ch][NS - 1] = *reinterpret_cast<const u32x4*>(ey_lo + off);
-                    }
+            for (int ch = 0; ch < NCH; ++ch) {
+                const size_t off = arow + (size_t)kb * (2 * KB) + 16 * ch;
+                A[S][ch][0] = *reinterpret_cast<const u32x4*>(ey_hi + off);
+                if (W::kSplit) A[S][ch][NS - 1] = *reinterpret_cast<const u32x4*>(ey_lo + off);
+            }
         };
         auto load_b = [&](int kk) {  // column operand sources of K step kb0 + kk
             const size_t boff = (size_t)(kb0 + min(kk, n - 1)) * (KB / 2);
@@ -596,13 +606,13 @@ __global__ __launch_bounds__(Wide<PREC>::NT, Wide<PREC>::OCC) void k_decode16(De
             }
         };
 
-        v4f acc[RBW][2][4];
+        v16f acc[2][2];   // [column block][class]
 #pragma unroll
-        for (int j = 0; j < RBW; ++j)
+        for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
             for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb) acc[j][p][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+                for (int e = 0; e < 16; ++e) acc[cb][p][e] = 0.f;
 
         // one K step from register set SET: loads for step kk + DEPTH go out first, then the
         // MFMAs of step kk (column operand from LDS stage kk & 1), then step kk + 1's column
@@ -614,35 +624,29 @@ __global__ __launch_bounds__(Wide<PREC>::NT, Wide<PREC>::OCC) void k_decode16(De
             load_a(std::integral_constant<int, (S + DEPTH) % NSETS>{}, kk + DEPTH);
             const unsigned char* Bs = smem + (kk & 1) * W::BSTAGE;
 #pragma unroll
-            for (int ch = 0; ch < 2; ++ch) {
-                u32x4 bh[4][2], bl[4][2];
+            for (int ch = 0; ch < NCH; ++ch) {
+                u32x4 bh[2][2], bl[2][2];
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb)
+                for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
                     for (int p = 0; p < 2; ++p) {
-                        const unsigned char* src = Bs + (p * kTileCols + 16 * cb + i16) * kRowPitchBytes + 64 * ch + 16 * g;
+                        const unsigned char* src = Bs + (p * kTileCols + 32 * cb + l32) * kRowPitchBytes + 32 * ch + 16 * h;
                         bh[cb][p] = *reinterpret_cast<const u32x4*>(src);
                         if (W::kSplit) bl[cb][p] = *reinterpret_cast<const u32x4*>(src + W::BROWS * kRowPitchBytes);
                     }
                 constexpr int NTERM = W::kSplit ? 3 : 1;
+                if (active) {
 #pragma unroll
-                for (int term = 0; term < NTERM; ++term)
+                    for (int term = 0; term < NTERM; ++term)
 #pragma unroll
-                    for (int j = 0; j < RBW; ++j)
-                        if (j < nj)
+                        for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-                            for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-                                for (int p = 0; p < 2; ++p) {
-                                    const u32x4 x = (term == 2) ? A[S][j][ch][NS - 1] : A[S][j][ch][0];
-                                    const u32x4 y = (term == 1) ? bl[cb][p] : bh[cb][p];
-                                    if (PREC == 2)
-                                        acc[j][p][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                                            __builtin_bit_cast(v8h, x), __builtin_bit_cast(v8h, y), acc[j][p][cb], 0, 0, 0);
-                                    else
-                                        acc[j][p][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                            __builtin_bit_cast(v8bf, x), __builtin_bit_cast(v8bf, y), acc[j][p][cb], 0, 0, 0);
-                                }
+                            for (int p = 0; p < 2; ++p) {
+                                const u32x4 x = (term == 2) ? A[S][ch][NS - 1] : A[S][ch][0];
+                                const u32x4 y = (term == 1) ? bl[cb][p] : bh[cb][p];
+                                acc[cb][p] = mfma32<PREC>(x, y, acc[cb][p]);
+                            }
+                }
             }
             bstore((kk + 1) & 1);  // past the segment's end: a stage nobody reads
             store_om(kk & 1);      // memories of step kk + 2, into the stage step kk's used
@@ -676,25 +680,24 @@ __global__ __launch_bounds__(Wide<PREC>::NT, Wide<PREC>::OCC) void k_decode16(De
         for (int p = 0; p < 2; ++p) {
             float mx = -INFINITY;
             float* out = a.heat + (size_t)p * a.class_stride;
+            if (active) {
 #pragma unroll
-            for (int j = 0; j < RBW; ++j)
-                if (j < nj)
+                for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-                    for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const int r = 16 * (wave + NW * j) + 4 * g + e, c = 16 * cb + i16;
-                            if (whole) {
-                                const int row = t.row0 + r, col = t.col0 + c;
-                                if (row < t.row_end && c < t.ncol) {
-                                    const float v = acc[j][p][cb][e] * a.out_scale;
-                                    out[(size_t)(Z ? a.row_map[row] : row) * a.nx + col] = v;
-                                    mx = fmaxf(mx, v);
-                                }
-                            } else {
-                                part[((size_t)p * TR + r) * kTileCols + c] = acc[j][p][cb][e];
+                    for (int v = 0; v < 16; ++v) {
+                        const int r = W::WR * wave + 8 * (v >> 2) + 4 * h + (v & 3), c = 32 * cb + l32;
+                        if (whole) {
+                            const int row = t.row0 + r, col = t.col0 + c;
+                            if (row < t.row_end && c < t.ncol) {
+                                const float val = acc[cb][p][v] * a.out_scale;
+                                out[(size_t)(Z ? a.row_map[row] : row) * a.nx + col] = val;
+                                mx = fmaxf(mx, val);
                             }
+                        } else {
+                            part[((size_t)p * TR + r) * kTileCols + c] = acc[cb][p][v];
                         }
+                    }
+            }
             if (whole) {
                 for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
                 if (lane == 0 && mx > -INFINITY && a.hmax_u) atomicMax(a.hmax_u + p, order_key(mx));
