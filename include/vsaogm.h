@@ -124,8 +124,10 @@ int vsaogm_map_reset(vsaogm_map* map, vsaogm_stream stream);
 /*
  * Algorithm 1: bundle n labelled points into the map's memories.
  *   xy    dev float32 [n][2], world metres
- *   label dev uint8 [n], 1 = occupied, 0 = empty; any other value is not
- *         bundled and is counted (see vsaogm_map_take_rejected)
+ *   label dev uint8 [n], 1 = occupied, 0 = empty; any other value names no
+ *         memory of Algorithm 1 (classes are 0 and 1 only): such a point is not
+ *         bundled and is counted, and vsaogm_map_take_rejected reports the count
+ *         (the check runs on the device, so the call stays asynchronous)
  * Memories accumulate across calls.  n == 0 is a no-op.  Returns EINVAL for
  * n < 0 or NULL pointers with n > 0.  Work buffers grow on demand (a growth
  * synchronises the stream once).
@@ -206,7 +208,9 @@ int vsaogm_classify_ex(const vsaogm_grid_desc* grid, const float* heat, const fl
                        vsaogm_stream stream);
 
 /*
- * Read the memories back in the paper's frame: out dev float32
+ * The bundled memories of eq. bundling as Algorithm 1 leaves them (memory 2*beta+psi holds
+ * the sum of the class-psi points of tile beta, 2-D encoding equation), read back in the
+ * paper's frame: out dev float32
  * [2R][D/2+1][2] (re, im), out[key][k] = sum over the key's points of
  * exp(i*(Theta[k][0]*x + Theta[k][1]*y)), k = 0..D/2 (the other bins are the
  * complex conjugates, bin D-k = conj(bin k)).

@@ -162,3 +162,17 @@ def test_binding_rejects_wrong_tensors_before_the_library():
     fake.is_contiguous = lambda: False
     with pytest.raises(ValueError, match="contiguous"):
         t(fake, "float32", (2, 4, 5), "heat")
+
+
+def test_rejected_labels_contract(lib):
+    """A label outside {0, 1} names no memory of Algorithm 1: the encode skips and counts such
+    points on the device (asynchronously) and vsaogm_map_take_rejected reports the count; the
+    header states it, and the count query validates its arguments before any device work."""
+    native, L = lib
+    with open(os.path.join(ROOT, "include", "vsaogm.h")) as fh:
+        hdr = fh.read()
+    assert "vsaogm_map_take_rejected reports the count" in hdr
+    v = ctypes.c_int64(-1)
+    assert L.vsaogm_map_take_rejected(None, None, ctypes.byref(v)) == native.EINVAL
+    assert L.vsaogm_volume_take_rejected(None, None, ctypes.byref(v)) == native.EINVAL
+    assert L.vsaogm_last_error()
