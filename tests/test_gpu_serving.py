@@ -281,3 +281,78 @@ def test_request_stream_against_oracle(torch_cuda):
         n += 1
     srv.close()
     say(f"  {n} updates of maps {chosen}: worst heat rel-L2 {worst:.2e}")
+
+
+FULL_HEAT_MAX_WORK = 2.0e9   # cells x D above which the oracle checks sampled cells only
+SAMPLED_CELLS = 4000
+
+
+def test_request_stream_random_requests_against_oracle(torch_cuda):
+    """The benchmark's whole request stream (16 maps, 256 updates of uneven scans and grids) served
+    through the loop, and 32 seeded random requests of it checked against the FP64 oracle's
+    memories accumulated update by update in stream order: maps of every D, the largest grid
+    (916 x 916 cells) and the largest D = 8192 grid (829 x 829).  Where the oracle's whole map
+    costs at most 2e9 cell-bins it is computed in full and the heatmaps (rel-L2 <= 1e-4) and
+    labels (>= 99.9 %, every disagreement within 1e-3 of the threshold) are compared in full;
+    above that, 4000 seeded random cells of the heatmaps are compared (rel-L2 <= 1e-4)."""
+    say("[gpu] request stream, 32 random requests vs oracle")
+    from paper_2408_09066_amd import native
+    maps, reqs = synth.serving_stream()
+    rng = np.random.default_rng(np.random.SeedSequence([2408, 4, 32]))
+    chosen = set(rng.choice(len(reqs), size=32, replace=False).tolist())
+    big = max(range(len(maps)), key=lambda i: maps[i].side)
+    big8 = max((i for i in range(len(maps)) if maps[i].D == 8192), key=lambda i: maps[i].side)
+    assert any(reqs[i].map_id == big for i in chosen) and any(reqs[i].map_id == big8 for i in chosen)
+    assert {maps[reqs[i].map_id].D for i in chosen} == {2048, 4096, 8192}
+    srv = native.Server(max_inflight=8)
+    ids = [srv.add_map(m.theta, m.layout, m.tiles) for m in maps]
+    tickets = []
+    for j, q in enumerate(reqs):
+        spec = maps[q.map_id]
+        want = ("label", "heat") if j in chosen else ("label",)
+        t, out = srv.submit(ids[q.map_id], q.xy, q.label, spec.grid, spec.side, spec.side, 3, 3, 0.0, "bf16x3",
+                            want=want)
+        tickets.append((t, out))
+    res = [srv.wait(t) for t, _ in tickets]
+    assert all(r["status"] == 0 for r in res)
+    srv.close()
+    say("  served 256 updates")
+    last = {}
+    for j in sorted(chosen):
+        last[reqs[j].map_id] = j
+    omega = {}
+    worst, full, sampled = 0.0, 0, 0
+    for j, q in enumerate(reqs):
+        if q.map_id not in last or j > last[q.map_id]:
+            continue
+        spec = maps[q.map_id]
+        omega[q.map_id], bad = oracle.encode(spec.theta, spec.layout, spec.tiles, q.xy, q.label,
+                                             omega=omega.get(q.map_id))
+        assert bad == 0
+        if j not in chosen:
+            continue
+        out = tickets[j][1]
+        n = spec.side
+        if n * n * spec.D <= FULL_HEAT_MAX_WORK:
+            P = oracle.similarity(spec.theta, spec.layout, spec.tiles, omega[q.map_id], spec.grid, n, n)
+            _, _, ogm, lab = oracle.postprocess(P, 3, 3, 0.0)
+            for p in range(2):
+                e = float(np.linalg.norm(out["heat"][p] - P[p]) / np.linalg.norm(P[p]))
+                worst = max(worst, e)
+                assert e <= 1e-4, (j, q.map_id, p, e)
+            flips = out["label"] != lab
+            assert float(np.mean(~flips)) >= 0.999, j
+            assert not flips.any() or float(np.max(np.abs(ogm[flips]))) < 1e-3, j
+            full += 1
+        else:
+            cells = np.random.default_rng(np.random.SeedSequence([2408, 4, 33, j])).choice(
+                n * n, size=SAMPLED_CELLS, replace=False)
+            P = oracle.similarity_cells(spec.theta, spec.layout, spec.tiles, omega[q.map_id], spec.grid, n, cells)
+            for p in range(2):
+                g = out["heat"][p].reshape(-1)[cells].astype(np.float64)
+                e = float(np.linalg.norm(g - P[p]) / np.linalg.norm(P[p]))
+                worst = max(worst, e)
+                assert e <= 1e-4, (j, q.map_id, p, e)
+            sampled += 1
+        say(f"  request {j}: map {q.map_id} D={spec.D} {n}x{n} checked")
+    say(f"  {full} requests in full, {sampled} at sampled cells; worst heat rel-L2 {worst:.2e}")
