@@ -396,6 +396,23 @@ int vsaogm_classify3(const vsaogm_grid3_desc* grid, const float* heat, const flo
                      int32_t r_occ, int32_t r_emp, float rho, float* ogm, uint8_t* label,
                      int32_t device, vsaogm_stream stream);
 
+/*
+ * vsaogm_classify3 for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same arguments,
+ * kernels and results, but the entropy terms of radii above 4 go to a fixed scratch array the
+ * library holds on each device it runs on (16 MiB, kept until the process ends) instead of a
+ * stream-ordered allocation.  Radii above 4 require nx * ny * nz <= 2097152 voxels (EINVAL
+ * otherwise, before any device work); radii up to 4 use no scratch and have no size limit.
+ * No call allocates or frees device memory.  All calls on one device share its scratch, and the
+ * scratch keeps the last call's contents (every voxel's entropy terms are written before they
+ * are read, so nothing needs clearing): calls that overlap on one device, on different streams
+ * or threads, race and must be serialised by the caller.  The first call on a device looks up
+ * that device's scratch address (no allocation).
+ */
+int vsaogm_classify3_noalloc(const vsaogm_grid3_desc* grid, const float* heat, const float* hmax,
+                             int32_t r_occ, int32_t r_emp, float rho, float* ogm, uint8_t* label,
+                             int32_t device, vsaogm_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

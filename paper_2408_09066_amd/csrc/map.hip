@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -1180,6 +1181,61 @@ int vsaogm_classify3(const vsaogm_grid3_desc* g, const float* heat, const float*
         const hipError_t e = launch_classify3(heat, hmax, g->nx, g->ny, g->nz, r_emp, r_occ, rho, gbuf, ogm, label, s);
         if (gbuf) (void)hipFreeAsync(gbuf, s);
         hip_check(e, "classify launch");
+    });
+}
+
+}  // extern "C"
+
+// ---- allocation-free volume classification -------------------------------------------------
+// vsaogm_classify3_noalloc keeps the entropy terms of the two-pass path (radii above the tiled
+// kernel's) in this file-scope device array instead of a stream-ordered allocation.  Host code
+// never uses the array's name as an address: each device's copy is found once with
+// hipGetSymbolAddress (with that device current) and the kernels receive that pointer.
+namespace {
+constexpr int64_t kNoAllocVoxels = int64_t(1) << 21;   // 2 floats per voxel: 16 MiB per device
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kNoAllocMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) float scratch[2 * kNoAllocVoxels];
+
+namespace {
+// The calling thread's current device must be `device`.
+float* scratch_on_device(int device) {
+    if (device < 0 || device >= kNoAllocMaxDevices) fail(VSAOGM_EINVAL, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "scratch symbol address");
+        if (!ptr) fail(VSAOGM_EDEVICE, "scratch symbol address is NULL");
+        g_scratch_ptr[device] = static_cast<float*>(ptr);
+    }
+    return g_scratch_ptr[device];
+}
+}  // namespace
+
+extern "C" {
+
+int vsaogm_classify3_noalloc(const vsaogm_grid3_desc* g, const float* heat, const float* hmax, int32_t r_occ,
+                             int32_t r_emp, float rho, float* ogm, uint8_t* label, int32_t device,
+                             vsaogm_stream stream) {
+    return guarded([&] {
+        check_grid3(g);
+        if (!heat || !hmax || !label) fail(VSAOGM_EINVAL, "heat, hmax and label must not be NULL");
+        if (r_occ < 0 || r_emp < 0 || r_occ > kMaxRadius || r_emp > kMaxRadius)
+            fail(VSAOGM_EINVAL, "radii must be in 0..24");
+        if (!is_finite(rho)) fail(VSAOGM_EINVAL, "rho must be finite");
+        const int64_t nvox = (int64_t)g->nx * g->ny * g->nz;
+        const bool two_pass = std::max(r_occ, r_emp) > kClassify3TiledRadius;
+        if (two_pass && nvox > kNoAllocVoxels)
+            fail(VSAOGM_EINVAL, "vsaogm_classify3_noalloc: radii above 4 need nx*ny*nz <= 2097152 voxels "
+                                "(the fixed scratch holds 2 floats per voxel)");
+        DeviceGuard guard(device);
+        hipStream_t s = (hipStream_t)stream;
+        float* gbuf = two_pass ? scratch_on_device(device) : nullptr;
+        hip_check(launch_classify3(heat, hmax, g->nx, g->ny, g->nz, r_emp, r_occ, rho, gbuf, ogm, label, s),
+                  "classify launch");
     });
 }
 

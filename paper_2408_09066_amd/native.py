@@ -28,6 +28,7 @@ EXPORTED = [
     "vsaogm_classify_ex", "vsaogm_decode_incremental", "vsaogm_request_bytes",
     "vsaogm_volume_create", "vsaogm_volume_destroy", "vsaogm_volume_reset", "vsaogm_volume_encode",
     "vsaogm_volume_take_rejected", "vsaogm_volume_decode", "vsaogm_classify3",
+    "vsaogm_classify3_noalloc",
 ]
 ACTIVATIONS = {"entropy": 0, "relu": 1, "tanh": 2, "sigmoid": 3}
 
@@ -134,6 +135,7 @@ def load(path: str = LIB_PATH):
     L.vsaogm_volume_take_rejected.argtypes = [P, P, ctypes.POINTER(i64)]
     L.vsaogm_volume_decode.argtypes = [P, ctypes.POINTER(Grid3Desc), i32, P, P, P]
     L.vsaogm_classify3.argtypes = [ctypes.POINTER(Grid3Desc), P, P, i32, i32, f32, P, P, i32, P]
+    L.vsaogm_classify3_noalloc.argtypes = [ctypes.POINTER(Grid3Desc), P, P, i32, i32, f32, P, P, i32, P]
     for name in EXPORTED:
         if name not in ("vsaogm_version", "vsaogm_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -350,7 +352,8 @@ class Volume:
 
 
 def classify3(heat, hmax, r_occ: int, r_emp: int, rho: float = 0.0, ogm=None, label=None, device: int = 0,
-              stream=None):
+              stream=None, noalloc: bool = False):
+    """noalloc: call vsaogm_classify3_noalloc (fixed per-device scratch, no device allocation)."""
     import torch
     _, nz, ny, nx = heat.shape
     if label is None:
@@ -362,8 +365,9 @@ def classify3(heat, hmax, r_occ: int, r_emp: int, rho: float = 0.0, ogm=None, la
     _tensor(ogm, "float32", (nz, ny, nx), "ogm")
     _tensor(label, "uint8", (nz, ny, nx), "label")
     g = Grid3Desc(0.0, 0.0, 0.0, 1.0, int(nx), int(ny), int(nz))
-    check(load().vsaogm_classify3(ctypes.byref(g), _ptr(heat), _ptr(hmax), int(r_occ), int(r_emp), float(rho),
-                                  _ptr(ogm), _ptr(label), int(device), _stream(stream)))
+    fn = load().vsaogm_classify3_noalloc if noalloc else load().vsaogm_classify3
+    check(fn(ctypes.byref(g), _ptr(heat), _ptr(hmax), int(r_occ), int(r_emp), float(rho), _ptr(ogm), _ptr(label),
+             int(device), _stream(stream)))
     return ogm, label
 
 

@@ -176,3 +176,17 @@ def test_rejected_labels_contract(lib):
     assert L.vsaogm_map_take_rejected(None, None, ctypes.byref(v)) == native.EINVAL
     assert L.vsaogm_volume_take_rejected(None, None, ctypes.byref(v)) == native.EINVAL
     assert L.vsaogm_last_error()
+
+
+def test_noalloc_classify3_rejects_volumes_beyond_its_scratch(lib):
+    """The allocation-free volume classification refuses, before any device work, a volume whose
+    entropy terms would not fit its fixed scratch (radii above 4 need 2 floats per voxel, at most
+    2^21 voxels), and accepts the argument checks of vsaogm_classify3 otherwise."""
+    native, L = lib
+    g = native.Grid3Desc(0.0, 0.0, 0.0, 1.0, 256, 128, 65)        # 2 129 920 voxels
+    fake = ctypes.c_void_p(4096)                                  # never dereferenced: refused first
+    rc = L.vsaogm_classify3_noalloc(ctypes.byref(g), fake, fake, 5, 3, 0.0, None, fake, 0, None)
+    assert rc == native.EINVAL
+    assert b"2097152" in L.vsaogm_last_error()
+    assert L.vsaogm_classify3_noalloc(None, fake, fake, 5, 3, 0.0, None, fake, 0, None) == native.EINVAL
+    assert L.vsaogm_classify3_noalloc(ctypes.byref(g), fake, fake, 25, 3, 0.0, None, fake, 0, None) == native.EINVAL
