@@ -1,21 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the VSA-OGM hot path on one MI355X.
 
-One step is one full map update of the "world40" workload, with every input already resident
-in HBM: 50 lidar scans of 1080 beams in a 40 m x 40 m world, 54 000 occupied beam ends and
-540 000 empty samples (594 000 points), D = 8192, l = 0.1 m, 4 x 4 tiles (32 memories),
-an 800 x 800 grid at 0.05 m and disk radius 3.  The step resets the memories, encodes and
-bundles every point, decodes both class heatmaps (the similarity GEMM, by default with bf16
-hi+lo operands, which meet the fp32 accuracy bar) and classifies the grid (entropy, softmax
-difference, threshold).
+Headline (one JSON line): the large-map configuration "stress200" -- a 200 m x 200 m world with
+400 obstacles mapped by a random walk of 1 080-beam scans, D = 16384, l = 0.1 m, 16 x 16 tiles
+(512 memories), a 4000 x 4000 grid at 0.05 m, disk radius 3 and the similarity contraction in
+bf16 hi+lo operands (which meet the fp32 accuracy bar).  One step is one incremental map update
+with its inputs already resident in HBM: encode and bundle the update's 118 800 points (10
+poses x 1 080 beams x (1 hit + 10 empty samples)) into the map's memories, decode both class
+heatmaps over the whole grid, classify every cell (entropy, softmax difference, threshold).
+The memories accumulate from step to step, as the map of a moving robot does.
 
-Timed: K plain steps (throughput), then K steps whose stage kernels carry HIP timing events
-(per-kernel durations for the rooflines, per-step latency), then K replays of the step
-captured in a HIP graph (reported beside the eager figure).  Printed: one JSON line with the
-whole-step throughput (heatmap cells decoded per second), points encoded per second, per-update
-latency percentiles, the roofline of the dominant kernel, the FP64 CPU oracle timed on a bounded
-sample of the same workload, and the held-out accuracy, 3-D, request-loop and large-map
-sections.
+Timed: K plain steps (throughput: cells decoded per second, points encoded per second), then K
+steps whose stage kernels carry HIP timing events (per-kernel durations for the rooflines,
+per-update latency percentiles).  Sections beside it: the same step through the request loop
+(host inputs, labels returned per update: PCIe-inclusive), the 40 m world of the plain method in
+fp32 and bf16 hi+lo, the request-loop benchmark (256 updates of 16 uneven maps against the plain
+per-request fp32 path), the 3-D extension, held-out accuracy, and the FP64 CPU oracle timed on a
+bounded sample of the headline workload.
 """
 from __future__ import annotations
 
@@ -32,27 +33,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X published peaks
+# MI355X published peaks: HBM3E bandwidth, dense matrix rates per operand type, fp32 vector rate
 PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0}
-# Issue-limited complex-exponential rate of the encode kernels: 256 CUs x 2.4 GHz x 64 lanes per
-# clock (a wave64 VALU instruction holds a 16-lane SIMD for 4 clocks), one issue slot per VALU
-# instruction.  Per pair of points and bin the plane kernel issues 4 phase MUL/FMA, 3
-# transcendentals and 2 accumulate FMA: 9 slots for two complex exponentials; the volume kernel
-# 6 phase MUL/FMA (three coordinates), 3 transcendentals and 2 FMA: 11 slots.  Transcendentals
-# alone issue at half that rate, so these are upper bounds the kernels cannot quite reach.
-PEAK_CEXP_TPS = 256 * 2.4e9 * 64 / 4.5 / 1e12
-PEAK_CEXP3_TPS = 256 * 2.4e9 * 64 / 5.5 / 1e12
+PEAK_FP32_TFLOPS = 157.3
+# Algorithmic work of the encode per point and spectrum bin: the phase Theta_x x + Theta_y y
+# (two fused multiply-adds, 4 flops), one sine and one cosine (1 op each), and the accumulation
+# of the real and imaginary parts (2 adds): 8 ops, priced against the fp32 vector rate (which
+# counts a fused multiply-add as 2).  A 3-D point adds one fused multiply-add (10 ops).
+ENCODE_OPS_PER_BIN = 8
+ENCODE3_OPS_PER_BIN = 10
+# Context only (not a peak): the VALU issue bound of the pair-form encode kernels, 256 CUs x
+# 2.4 GHz x 64 lanes / (issue slots per complex exponential): 4.5 for planes, 5.5 for volumes.
+ISSUE_CEXP_TPS = 256 * 2.4e9 * 64 / 4.5 / 1e12
+ISSUE_CEXP3_TPS = 256 * 2.4e9 * 64 / 5.5 / 1e12
 
 
 # HBM bytes per launch of a stage's main kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE counters
-# (scaled by what they read for a device-to-device copy of known size), valid only for the kernel
-# sources they were taken on.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "world40_hbm_traffic.json")
+# of an earlier profiled run (scaled by what they read for a device-to-device copy of known size),
+# one file per workload; a figure is used only while the kernel sources it was taken on are
+# unchanged (SHA-256 recorded with it).
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.json")
 
 
 def source_digest(files):
-    import hashlib
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
@@ -60,9 +65,9 @@ def source_digest(files):
     return h.hexdigest()
 
 
-def measured_traffic(stage):
+def measured_traffic(workload, stage):
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file(workload)) as fh:
             rec = json.load(fh).get(stage)
     except (OSError, ValueError):
         return None
@@ -106,65 +111,76 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(w, budget_s: float):
-    """Time the FP64 oracle on a bounded sample of the workload and scale to cells/s."""
+def cpu_baseline(sc, xy, label, budget_s: float):
+    """The FP64 oracle on a bounded sample of one update of the headline workload, scaled to one
+    whole update (cells/s): encode a prefix of the update's points, the similarity at random
+    cells, and the entropy / softmax / threshold post-processing of a sub-grid of the oracle's own
+    heat; the same kinds of work on one host thread beside it."""
     import oracle
     oracle.lib()
     rng = np.random.default_rng(np.random.SeedSequence([2408, 99]))
+    n = len(xy)
+    ncell = sc.nx * sc.ny
     # encode: a prefix of the points, sized from a short probe to about budget/2 seconds
-    probe = 500
+    probe = 200
     t = time.perf_counter()
-    oracle.encode(w.theta, w.layout, w.tiles, w.xy[:probe], w.label[:probe])
+    oracle.encode(sc.theta, sc.layout, sc.tiles, xy[:probe], label[:probe])
     dt = max(time.perf_counter() - t, 1e-6)
-    n_enc = int(min(w.n, max(probe, probe * (0.5 * budget_s) / dt)))
+    n_enc = int(min(n, max(probe, probe * (0.5 * budget_s) / dt)))
     t = time.perf_counter()
-    omega, _ = oracle.encode(w.theta, w.layout, w.tiles, w.xy[:n_enc], w.label[:n_enc])
+    omega, _ = oracle.encode(sc.theta, sc.layout, sc.tiles, xy[:n_enc], label[:n_enc])
     t_enc = time.perf_counter() - t
-    # decode: random cells, sized to about budget/3 seconds
-    ncell = w.nx * w.ny
-    cells = rng.choice(ncell, size=64, replace=False)
+    # similarity at random cells, sized to about budget/3 seconds
+    cells = rng.choice(ncell, size=32, replace=False)
     t = time.perf_counter()
-    oracle.similarity_cells(w.theta, w.layout, w.tiles, omega, w.grid, w.nx, cells)
+    oracle.similarity_cells(sc.theta, sc.layout, sc.tiles, omega, sc.grid, sc.nx, cells)
     dt = max(time.perf_counter() - t, 1e-6)
-    n_dec = int(min(ncell, max(64, 64 * (budget_s / 3) / dt)))
+    n_dec = int(min(ncell, max(32, 32 * (budget_s / 3) / dt)))
     cells = rng.choice(ncell, size=n_dec, replace=False)
     t = time.perf_counter()
-    oracle.similarity_cells(w.theta, w.layout, w.tiles, omega, w.grid, w.nx, cells)
+    oracle.similarity_cells(sc.theta, sc.layout, sc.tiles, omega, sc.grid, sc.nx, cells)
     t_dec = time.perf_counter() - t
-    # post-processing: a 200 x 200 sub-grid of synthetic similarity values
-    sub = 200
-    P = rng.normal(0.0, 0.1, size=(2, sub, sub))
+    # post-processing of the oracle's heat of a 40 x 40 sub-grid around the first pose
+    sub = 40
+    px, py = sc.poses[0]
+    gx, gy, res = sc.grid
+    i0 = int(min(max((px - gx) / res - sub // 2, 0), sc.nx - sub))
+    j0 = int(min(max((py - gy) / res - sub // 2, 0), sc.ny - sub))
+    sub_grid = (gx + i0 * res, gy + j0 * res, res)
+    P = oracle.similarity(sc.theta, sc.layout, sc.tiles, omega, sub_grid, sub, sub)
     t = time.perf_counter()
-    oracle.postprocess(P, w.r_occ, w.r_emp, w.rho)
-    t_cls = time.perf_counter() - t
-    step = t_enc * (w.n / n_enc) + t_dec * (ncell / n_dec) + t_cls * (ncell / (sub * sub))
-    # the same kinds of work on one host thread, on smaller samples (about budget/4 seconds)
+    oracle.postprocess(P, sc.r, sc.r, 0.0)
+    t_cls = max(time.perf_counter() - t, 1e-6)
+    step = t_enc * (n / n_enc) + t_dec * (ncell / n_dec) + t_cls * (ncell / (sub * sub))
     threads = oracle.num_threads()
     oracle.set_threads(1)
-    n1 = min(w.n, max(64, int(n_enc * (budget_s / 8) / max(t_enc * threads, 1e-6))))
+    n1 = min(n, max(16, int(n_enc * (budget_s / 8) / max(t_enc * threads, 1e-6))))
     t = time.perf_counter()
-    om1, _ = oracle.encode(w.theta, w.layout, w.tiles, w.xy[:n1], w.label[:n1])
+    om1, _ = oracle.encode(sc.theta, sc.layout, sc.tiles, xy[:n1], label[:n1])
     t_enc1 = time.perf_counter() - t
-    c1 = cells[:max(16, int(n_dec * (budget_s / 8) / max(t_dec * threads, 1e-6)))]
+    c1 = cells[:max(8, int(n_dec * (budget_s / 8) / max(t_dec * threads, 1e-6)))]
     t = time.perf_counter()
-    oracle.similarity_cells(w.theta, w.layout, w.tiles, om1, w.grid, w.nx, c1)
+    oracle.similarity_cells(sc.theta, sc.layout, sc.tiles, om1, sc.grid, sc.nx, c1)
     t_dec1 = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.postprocess(P, sc.r, sc.r, 0.0)
+    t_cls1 = max(time.perf_counter() - t, 1e-6)
     oracle.set_threads(threads)
-    step1 = t_enc1 * (w.n / n1) + t_dec1 * (ncell / len(c1)) + t_cls * threads * (ncell / (sub * sub))
+    step1 = t_enc1 * (n / n1) + t_dec1 * (ncell / len(c1)) + t_cls1 * (ncell / (sub * sub))
     return {
         "value": ncell / step,
         "unit": "cells/s",
-        "cores": oracle.num_threads(),
+        "cores": threads,
         "cpu_model": cpu_model(),
         "kind": "oracle",
-        "sample": (f"encode of the first {n_enc} of {w.n} points ({t_enc:.2f} s), similarity at "
-                   f"{n_dec} random cells of {ncell} ({t_dec:.2f} s), entropy/softmax/threshold on a "
-                   f"{sub}x{sub} sub-grid ({t_cls:.2f} s); scaled to one full update "
-                   f"({step:.1f} s)"),
+        "sample": (f"one {n}-point update of {sc.name}: encode of its first {n_enc} points ({t_enc:.2f} s), "
+                   f"similarity at {n_dec} random cells of {ncell} ({t_dec:.2f} s), entropy/softmax/threshold "
+                   f"of the oracle's heat on a {sub}x{sub} sub-grid ({t_cls * 1e3:.1f} ms); scaled to one whole "
+                   f"update ({step:.0f} s)"),
         "points_per_s": n_enc / t_enc,
-        "single_thread": {"value": ncell / step1, "points_per_s": n1 / t_enc1,
+        "single_thread": {"value": ncell / step1, "points_per_s": n1 / t_enc1, "cores": 1,
                           "sample": f"encode of {n1} points ({t_enc1:.2f} s), similarity at {len(c1)} cells "
-                                    f"({t_dec1:.2f} s), post-processing scaled from the threaded run"},
+                                    f"({t_dec1:.2f} s), the same sub-grid post-processing"},
     }
 
 
@@ -348,7 +364,9 @@ def volume_benchmark(steps: int = 10, warmup: int = 2, precision: str = "bf16x3"
         "points_per_s": v.n * steps / el,
         "stage_ms": ms,
         "encode_tcexp_per_s": v.n * (v.D // 2 - 1) / (ms["encode"] * 1e-3) / 1e12,
-        "encode_frac": v.n * (v.D // 2 - 1) / (ms["encode"] * 1e-3) / 1e12 / PEAK_CEXP3_TPS,
+        "encode_tflops": ENCODE3_OPS_PER_BIN * v.n * (v.D // 2 - 1) / (ms["encode"] * 1e-3) / 1e12,
+        "encode_frac": ENCODE3_OPS_PER_BIN * v.n * (v.D // 2 - 1) / (ms["encode"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+        "encode_issue_bound_frac": v.n * (v.D // 2 - 1) / (ms["encode"] * 1e-3) / 1e12 / ISSUE_CEXP3_TPS,
         "decode_tflops_useful": 4.0 * v.D * nvox / (ms["decode"] * 1e-3) / 1e12,
     }
 
@@ -436,24 +454,153 @@ def stress_benchmark(sc, ups, precision: str = "bf16x3", load: float = 0.8):
     }
 
 
+def stage_rooflines(workload, stage_ms, n_points, D, ncell, precision):
+    """Per-stage rooflines of one update: algorithmic work per launch / measured launch time,
+    against the published peak of the unit that bounds the stage."""
+    half = D // 2
+    cexp = n_points * (half - 1)
+    enc_ops = ENCODE_OPS_PER_BIN * cexp
+    dec_flop = 4.0 * D * ncell            # 2 classes x D reals x (mul + add) per cell
+    cls_bytes = 13.0 * ncell              # 2 x 4 B heat in; 4 B ogm + 1 B label out
+    st = {
+        "encode": {"bound": "alu", "achieved": enc_ops / (stage_ms["encode"] * 1e-3) / 1e12,
+                   "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "ms": stage_ms["encode"],
+                   "algorithmic": f"{ENCODE_OPS_PER_BIN} ops x {n_points} points x {half - 1} bins",
+                   "tcexp_per_s": cexp / (stage_ms["encode"] * 1e-3) / 1e12,
+                   "issue_bound_frac": cexp / (stage_ms["encode"] * 1e-3) / 1e12 / ISSUE_CEXP_TPS},
+        "decode": {"bound": "mfma", "achieved": dec_flop / (stage_ms["decode"] * 1e-3) / 1e12,
+                   "peak": PEAK_MFMA_TFLOPS[precision], "unit": "TFLOP/s", "ms": stage_ms["decode"],
+                   "algorithmic": f"4 D flop x {ncell} cells (D = {D}), useful",
+                   # MFMA work issued per useful flop (the split form multiplies three products)
+                   "issued_per_useful": 3 if precision == "bf16x3" else 1},
+        "classify": {"bound": "hbm", "achieved": cls_bytes / (stage_ms["classify"] * 1e-3) / 1e9,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "ms": stage_ms["classify"],
+                     "algorithmic": f"13 B x {ncell} cells"},
+    }
+    for name, v in st.items():
+        v["frac"] = v["achieved"] / v["peak"]
+        tb = measured_traffic(workload, name)
+        v["traffic"] = tb
+        v["hbm_gbs"] = tb / (v["ms"] * 1e-3) / 1e9 if tb else None
+    st["decode"]["issued_frac"] = st["decode"]["frac"] * st["decode"]["issued_per_useful"]
+    return st
+
+
+def timed_steps(step, steps: int, warmup: int, graph: bool = False):
+    """warmup untimed steps; K steps for the throughput; K steps whose stage kernels record HIP
+    events (per-kernel durations; per-step latency); optionally K replays of one step captured in
+    a HIP graph.  Returns (seconds of the K plain steps, stage ms means, step latencies ms, graph
+    ms per step or None)."""
+    import torch
+    from paper_2408_09066_amd import native
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    E = torch.cuda.Event
+    step_ev = [(E(enable_timing=True), E(enable_timing=True)) for _ in range(steps)]
+    stage_ev = {s_: [(E(enable_timing=True), E(enable_timing=True)) for _ in range(steps)] for s_ in native.STAGES}
+    # torch creates an event on its first record: record each once so that its handle exists
+    # before the library's kernels record it
+    for evs in stage_ev.values():
+        for a, b in evs:
+            a.record()
+            b.record()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # a timed kernel completion delays the next kernel by a few microseconds, so these are not
+    # the steps the throughput is taken from
+    for i in range(steps):
+        for s_ in native.STAGES:
+            native.profile_events(s_, *stage_ev[s_][i])
+        step_ev[i][0].record()
+        step()
+        step_ev[i][1].record()
+    torch.cuda.synchronize()
+    for s_ in native.STAGES:
+        native.profile_events(s_, None, None)
+    lat = [a.elapsed_time(b) for a, b in step_ev]
+    stage_ms = {s_: float(np.mean([a.elapsed_time(b) for a, b in stage_ev[s_]])) for s_ in native.STAGES}
+    graph_ms = None
+    if graph:
+        try:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                step()
+            g.replay()
+            torch.cuda.synchronize()
+            tg = time.perf_counter()
+            for _ in range(steps):
+                g.replay()
+            torch.cuda.synchronize()
+            graph_ms = (time.perf_counter() - tg) / steps * 1e3
+            del g
+        except RuntimeError as e:   # reported, not fatal: the eager figures stand
+            print(f"graph capture failed: {e}", file=sys.stderr)
+    return elapsed, stage_ms, lat, graph_ms
+
+
+def world40_benchmark(precision: str, steps: int, warmup: int):
+    """The plain method at real size: one step = reset + encode all 594 000 points + decode the
+    800 x 800 grid + classify (inputs resident in HBM)."""
+    import torch
+    from paper_2408_09066_amd import native, synth
+    w = synth.workload("world40")
+    dev = torch.device("cuda", 0)
+    xy = torch.from_numpy(w.xy).to(dev)
+    lab = torch.from_numpy(w.label).to(dev)
+    heat = torch.empty((2, w.ny, w.nx), dtype=torch.float32, device=dev)
+    hmax = torch.empty(2, dtype=torch.float32, device=dev)
+    ogm = torch.empty((w.ny, w.nx), dtype=torch.float32, device=dev)
+    out_lab = torch.empty((w.ny, w.nx), dtype=torch.uint8, device=dev)
+    m = native.Map(w.theta, w.layout, w.tiles, device=0)
+
+    def step():
+        m.reset()
+        m.encode(xy, lab)
+        m.decode(w.grid, w.nx, w.ny, precision, heat=heat, hmax=hmax)
+        native.classify(heat, hmax, w.r_occ, w.r_emp, w.rho, ogm=ogm, label=out_lab)
+
+    elapsed, stage_ms, lat, graph_ms = timed_steps(step, steps, warmup, graph=True)
+    m.close()
+    ncell = w.nx * w.ny
+    st = stage_rooflines("world40", stage_ms, w.n, w.D, ncell, precision)
+    return {
+        "workload": (f"{w.name}: {w.n} points ({int(w.label.sum())} occupied), D={w.D}, l={w.ell} m, "
+                     f"{w.tiles[0]}x{w.tiles[1]} tiles, {w.nx}x{w.ny} grid at {w.grid[2]} m, disk r={w.r_occ}; "
+                     "step = reset + encode all points + decode + classify"),
+        "precision": precision,
+        "ms_per_step": elapsed / steps * 1e3,
+        "cells_per_s": ncell * steps / elapsed,
+        "points_per_s": w.n * steps / elapsed,
+        "gemm_cells_per_s": ncell / (stage_ms["decode"] * 1e-3),
+        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
+        "graph_ms_per_step": graph_ms,
+        "stages": st,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="world40")
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "fp16", "bf16x3"],
-                    help="operands of the similarity contraction; bf16x3 (hi+lo split) meets the fp32 "
-                         "accuracy bar")
+                    help="operands of the headline's similarity contraction; bf16x3 (hi+lo split) meets "
+                         "the fp32 accuracy bar")
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle work for the CPU baseline (0 disables it)")
+    ap.add_argument("--world40", type=int, default=1, help="also run the 40 m world (fp32 and bf16 hi+lo)")
     ap.add_argument("--serving", type=int, default=1,
                     help="also run the request-loop benchmark (256 updates of 16 maps)")
     ap.add_argument("--stress", type=int, default=200,
-                    help="updates of the large-map stress run through the request loop (0 disables it)")
+                    help="updates of the large map served through the request loop (0 disables it)")
     ap.add_argument("--volume", type=int, default=1, help="also run the 3-D benchmark")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
-                    help="processes that generate the stress scans")
+                    help="processes that generate the scans")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 512 MiB device to device three times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -474,111 +621,54 @@ def main() -> int:
               "(the hot path here is the single-GPU kernel set)", file=sys.stderr)
         return 2
 
-    stress_in = stress_generate(args.stress, args.workers) if args.stress > 0 else None
+    # scans are generated before any GPU use (generation forks worker processes)
+    n_head = args.warmup + 2 * args.steps
+    sc, ups, gen_s = stress_generate(max(n_head, args.stress), args.workers)
 
     import torch
-    from paper_2408_09066_amd import native, synth
+    from paper_2408_09066_amd import native
 
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         return 1
     native.load()
     torch.cuda.set_device(0)
-    w = synth.workload(args.workload)
     dev = torch.device("cuda", 0)
-    xy = torch.from_numpy(w.xy).to(dev)
-    lab = torch.from_numpy(w.label).to(dev)
-    heat = torch.empty((2, w.ny, w.nx), dtype=torch.float32, device=dev)
+
+    # ---- headline: incremental updates of the large map, inputs resident in HBM
+    dev_ups = [(torch.from_numpy(xy).to(dev), torch.from_numpy(lb).to(dev)) for xy, lb in ups[:n_head]]
+    heat = torch.empty((2, sc.ny, sc.nx), dtype=torch.float32, device=dev)
     hmax = torch.empty(2, dtype=torch.float32, device=dev)
-    ogm = torch.empty((w.ny, w.nx), dtype=torch.float32, device=dev)
-    out_lab = torch.empty((w.ny, w.nx), dtype=torch.uint8, device=dev)
-    m = native.Map(w.theta, w.layout, w.tiles, device=0)
+    ogm = torch.empty((sc.ny, sc.nx), dtype=torch.float32, device=dev)
+    out_lab = torch.empty((sc.ny, sc.nx), dtype=torch.uint8, device=dev)
+    m = native.Map(sc.theta, sc.layout, sc.tiles, device=0)
+    nxt = [0]
 
     def step():
-        m.reset()
-        m.encode(xy, lab)
-        m.decode(w.grid, w.nx, w.ny, args.precision, heat=heat, hmax=hmax)
-        native.classify(heat, hmax, w.r_occ, w.r_emp, w.rho, ogm=ogm, label=out_lab)
+        xy, lb = dev_ups[nxt[0] % len(dev_ups)]
+        nxt[0] += 1
+        m.encode(xy, lb)
+        m.decode(sc.grid, sc.nx, sc.ny, args.precision, heat=heat, hmax=hmax)
+        native.classify(heat, hmax, sc.r, sc.r, 0.0, ogm=ogm, label=out_lab)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
+    free0, total = torch.cuda.mem_get_info()
+    elapsed, stage_ms, lat, _ = timed_steps(step, args.steps, args.warmup)
+    free1, _ = torch.cuda.mem_get_info()
+    m.close()
+    del dev_ups
     K = args.steps
-    E = torch.cuda.Event
-    step_ev = [(E(enable_timing=True), E(enable_timing=True)) for _ in range(K)]
-    stage_ev = {s: [(E(enable_timing=True), E(enable_timing=True)) for _ in range(K)]
-                for s in native.STAGES}
-    # torch creates an event on its first record; record each once so that its handle
-    # exists before the library records it around the stage's kernel
-    for evs in stage_ev.values():
-        for a, b in evs:
-            a.record()
-            b.record()
-    # K plain steps give the throughput; K more with timing events give per-kernel durations and
-    # per-step latency (a timed kernel completion delays the next kernel by a few microseconds, so
-    # the instrumented steps are not the ones the throughput is taken from)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(K):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for i in range(K):
-        for s in native.STAGES:
-            native.profile_events(s, *stage_ev[s][i])
-        step_ev[i][0].record()
-        step()
-        step_ev[i][1].record()
-    torch.cuda.synchronize()
-    for s in native.STAGES:
-        native.profile_events(s, None, None)
-
-    elapsed = t1 - t0
-    ms_step = elapsed / K * 1e3
-    # the same step captured once in a HIP graph and replayed (launch work leaves the host)
-    graph_ms = None
-    try:
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            step()
-        g.replay()
-        torch.cuda.synchronize()
-        tg = time.perf_counter()
-        for _ in range(K):
-            g.replay()
-        torch.cuda.synchronize()
-        graph_ms = (time.perf_counter() - tg) / K * 1e3
-        del g
-    except RuntimeError as e:   # reported, not fatal: the eager figures above stand
-        print(f"graph capture failed: {e}", file=sys.stderr)
-    lat = [a.elapsed_time(b) for a, b in step_ev]
-    stage_ms = {s: float(np.mean([a.elapsed_time(b) for a, b in stage_ev[s]])) for s in native.STAGES}
-    ncell = w.nx * w.ny
-    half = w.D // 2
-    enc_cexp = w.n * (half - 1)
-    dec_flop = 4.0 * w.D * ncell
-    cls_bytes = 13.0 * ncell
-    stages = {
-        "encode": {"bound": "alu", "achieved": enc_cexp / (stage_ms["encode"] * 1e-3) / 1e12,
-                   "peak": PEAK_CEXP_TPS, "unit": "Tcexp/s", "ms": stage_ms["encode"]},
-        "decode": {"bound": "mfma", "achieved": dec_flop / (stage_ms["decode"] * 1e-3) / 1e12,
-                   "peak": PEAK_MFMA_TFLOPS[args.precision], "unit": "TFLOP/s",
-                   "ms": stage_ms["decode"],
-                   # MFMA work issued per useful flop (the split form multiplies three products)
-                   "issued_per_useful": 3 if args.precision == "bf16x3" else 1},
-        "classify": {"bound": "hbm", "achieved": cls_bytes / (stage_ms["classify"] * 1e-3) / 1e9,
-                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "ms": stage_ms["classify"]},
-    }
-    for name, v in stages.items():
-        v["frac"] = v["achieved"] / v["peak"]
-        tb = measured_traffic(name)     # HBM bytes per launch from the counters, if current
-        v["hbm_gbs"] = tb / (v["ms"] * 1e-3) / 1e9 if tb else None
-    stages["decode"]["issued_frac"] = stages["decode"]["frac"] * stages["decode"]["issued_per_useful"]
-    dom = max(stages, key=lambda s: stages[s]["ms"])
+    ncell = sc.nx * sc.ny
+    npts = sc.points_per_update
+    stages = stage_rooflines(sc.name, stage_ms, npts, sc.D, ncell, args.precision)
+    dom = max(stages, key=lambda s_: stages[s_]["ms"])
     d = stages[dom]
     roof = {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
-            "frac": d["frac"], "traffic": measured_traffic(dom), "kernel": dom}
+            "frac": d["frac"], "traffic": d["traffic"], "kernel": dom,
+            "traffic_source": (f"rocprofv3 FETCH_SIZE / WRITE_SIZE of an earlier profiled run on these kernel "
+                               f"sources ({os.path.relpath(traffic_file(sc.name), ROOT)}), copy-calibrated"
+                               if d["traffic"] else "no counter run on these kernel sources")}
+    if dom == "decode":
+        roof["issued_frac"] = d["issued_frac"]
 
     result = {
         "metric": "heatmap cells decoded/sec + points encoded/sec; p50/p99 map-update latency",
@@ -587,43 +677,47 @@ def main() -> int:
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": elapsed / K * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else f"f32 ({args.precision} similarity operands)",
         "data": "synthetic",
         "config": {
-            "workload": (f"{w.name}: {w.n} points ({int(w.label.sum())} occupied), D={w.D}, "
-                         f"l={w.ell} m, {w.tiles[0]}x{w.tiles[1]} tiles, {w.nx}x{w.ny} grid at "
-                         f"{w.grid[2]} m, disk r={w.r_occ}"),
+            "workload": (f"{sc.name}: 200 m x 200 m world, {len(sc.world.rects)} rectangles + "
+                         f"{len(sc.world.circles)} circles; one step = one incremental map update of "
+                         f"{sc.poses_per_update} poses x {sc.beams} beams x (1 + {sc.empties}) = {npts} points "
+                         f"(resident in HBM), D={sc.D}, l={sc.ell} m, {sc.tiles[0]}x{sc.tiles[1]} tiles, "
+                         f"{sc.nx}x{sc.ny} grid at {sc.grid[2]} m decoded in full, disk r={sc.r}"),
             "precision": args.precision,
         },
-        "points_per_s": w.n * K / elapsed,
-        # cells/s of the similarity GEMM alone and of decode + classification (both classes'
-        # heatmaps, then the labelled map), from the same launches' timings
+        "points_per_s": npts * K / elapsed,
+        # cells/s of the similarity GEMM alone and of decode + classification, from the same
+        # launches' timings
         "gemm_cells_per_s": ncell / (stage_ms["decode"] * 1e-3),
         "decode_classify_cells_per_s": ncell / ((stage_ms["decode"] + stage_ms["classify"]) * 1e-3),
-        "input_sha256": {k: hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
-                         for k, a in (("xy", w.xy), ("label", w.label), ("theta", w.theta))},
-        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
-        "graph_ms_per_step": graph_ms,
+        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99),
+                       "what": "device time of one update (encode + decode + classify), HIP events"},
+        "hbm_bytes_map_and_buffers": int(free0 - free1),
+        "input_sha256": {"theta": hashlib.sha256(np.ascontiguousarray(sc.theta).tobytes()).hexdigest(),
+                         "update0_xy": hashlib.sha256(np.ascontiguousarray(ups[0][0]).tobytes()).hexdigest()},
+        "generation_s": gen_s,
         "stages": stages,
         "roofline": roof,
     }
-    m.close()
     result["measured_peaks"] = {"hbm_copy_gbs": measured_hbm_copy_gbs(), "datasheet_hbm_gbs": PEAK_HBM_GBS}
-    result["accuracy"] = heldout_accuracy(w, args.precision)
+    if args.world40:
+        result["world40"] = {p_: world40_benchmark(p_, K, args.warmup) for p_ in ("fp32", "bf16x3")}
+        from paper_2408_09066_amd import synth
+        result["world40"]["accuracy"] = heldout_accuracy(synth.workload("world40"), "bf16x3")
     if args.volume:
         result["volume"] = volume_benchmark()
     if args.serving:
         result["serving"] = serving_benchmark()
-    if stress_in is not None:
-        sc, ups, gen_s = stress_in
-        result["stress"] = stress_benchmark(sc, ups)
-        result["stress"]["generation_s"] = gen_s
+    if args.stress > 0:
+        result["stress_serving"] = stress_benchmark(sc, ups[:args.stress])
     if args.cpu_budget > 0:
-        result["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+        result["cpu_baseline"] = cpu_baseline(sc, ups[0][0], ups[0][1], args.cpu_budget)
     print(json.dumps(result), flush=True)
     return 0
 
