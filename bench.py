@@ -184,7 +184,8 @@ def cpu_baseline(sc, xy, label, budget_s: float):
     }
 
 
-def serving_benchmark(n_requests: int = 256, slots: int = 8, precision: str = "bf16x3"):
+def serving_benchmark(n_requests: int = 256, slots: int = 8, precision: str = "bf16x3", max_batch: int = 0,
+                      plain: bool = True):
     """256 map updates of 16 uneven maps: plain per-request fp32 path vs the request loop.
 
     Plain path: one update at a time through the map API (copy in, encode, fp32 decode,
@@ -231,7 +232,7 @@ def serving_benchmark(n_requests: int = 256, slots: int = 8, precision: str = "b
     plain_ups = len(reqs) / plain_total
 
     # ---- request loop
-    srv = native.Server(max_inflight=slots)
+    srv = native.Server(max_inflight=slots, max_batch=max_batch)
     ids = [srv.add_map(m.theta, m.layout, m.tiles) for m in maps]
 
     def submit(q):

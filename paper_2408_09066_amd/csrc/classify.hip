@@ -60,17 +60,19 @@ __device__ inline float cell_value(float p, float m, int normalize, int square, 
     }
 }
 
-__global__ __launch_bounds__(256) void k_classify(const float* __restrict__ heat,
-                                                  const float* __restrict__ hmax, int nx, int ny,
-                                                  int r_occ, int r_emp, float rho, int normalize,
-                                                  int square, int act,
-                                                  float* __restrict__ ogm,
-                                                  uint8_t* __restrict__ label) {
-    extern __shared__ float sg[];
+// One block of TX x TY cells, block column bxi and row byi; m0, m1 the class maxima.
+__device__ __attribute__((always_inline)) inline void classify_body(const float* __restrict__ heat_, float m0, float m1,
+                                                                    int nx, int ny, int r_occ, int r_emp, float rho,
+                                                                    int normalize, int square, int act,
+                                                                    float* __restrict__ ogm_, uint8_t* __restrict__ label_,
+                                                                    int bxi, int byi, float* sg /* LDS */) {
+    gmem<float>* __restrict__ heat = as_global(heat_);
+    gmem_rw<float>* __restrict__ ogm = ogm_ ? as_global_rw(ogm_) : nullptr;
+    gmem_rw<uint8_t>* __restrict__ label = as_global_rw(label_);
     const int R = max(r_occ, r_emp);
     const int W = TX + 2 * R, H = TY + 2 * R;
     __shared__ int half_w[2][2 * kMaxRadius + 1];
-    const int bx = blockIdx.x * TX, by = blockIdx.y * TY;
+    const int bx = bxi * TX, by = byi * TY;
     if (threadIdx.x < 2 * (2 * kMaxRadius + 1)) {
         const int p = threadIdx.x / (2 * kMaxRadius + 1);
         const int dy = threadIdx.x % (2 * kMaxRadius + 1) - kMaxRadius;
@@ -82,7 +84,6 @@ __global__ __launch_bounds__(256) void k_classify(const float* __restrict__ heat
         }
         half_w[p][dy + kMaxRadius] = w;
     }
-    const float m0 = hmax[0], m1 = hmax[1];
     const size_t plane = (size_t)nx * ny;
     // the block's cells and halo, both classes, kLoadBatch loads in flight per thread
     constexpr int kLoadBatch = 8;
@@ -140,7 +141,48 @@ __global__ __launch_bounds__(256) void k_classify(const float* __restrict__ heat
     }
 }
 
+__global__ __launch_bounds__(256) void k_classify(const float* __restrict__ heat,
+                                                  const float* __restrict__ hmax, int nx, int ny,
+                                                  int r_occ, int r_emp, float rho, int normalize,
+                                                  int square, int act,
+                                                  float* __restrict__ ogm,
+                                                  uint8_t* __restrict__ label) {
+    extern __shared__ float sg[];
+    classify_body(heat, hmax[0], hmax[1], nx, ny, r_occ, r_emp, rho, normalize, square, act, ogm, label, blockIdx.x,
+                  blockIdx.y, sg);
+}
+
+// Batched: the blocks of request r are [block0[r], block0[r + 1]), numbered block column
+// fastest; the class maxima come from the ordered maxima of the request's decode, and the
+// request's first block also writes them out as floats.
+__global__ __launch_bounds__(256) void k_classify_b(const ClassifyReq* __restrict__ qs,
+                                                    const int* __restrict__ block0, int nq) {
+    extern __shared__ float sg[];
+    const int r = batch_job(block0, nq, blockIdx.x);
+    const ClassifyReq q = qs[r];
+    const int b = blockIdx.x - block0[r];
+    const int gx = (q.nx + TX - 1) / TX;
+    const float m0 = order_value(as_global(q.hmax_u)[0]), m1 = order_value(as_global(q.hmax_u)[1]);
+    if (b == 0 && threadIdx.x == 0 && q.hmax_out) {
+        gmem_rw<float>* ho = as_global_rw(q.hmax_out);
+        ho[0] = m0;
+        ho[1] = m1;
+    }
+    classify_body(q.heat, m0, m1, q.nx, q.ny, q.r_occ, q.r_emp, q.rho, 1, 1, 0, q.ogm, q.label, b % gx, b / gx, sg);
+}
+
 }  // namespace
+
+int classify_blocks(int nx, int ny) { return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY); }
+
+hipError_t launch_classify_batch(const ClassifyReq* reqs, const int* block0, int nreq, int total_blocks, int max_radius,
+                                 hipStream_t s) {
+    if (total_blocks == 0) return hipSuccess;
+    const size_t lds = 2 * (size_t)(TX + 2 * max_radius) * (TY + 2 * max_radius) * sizeof(float);
+    hipExtLaunchKernelGGL(k_classify_b, dim3(total_blocks), dim3(256), lds, s, profile_start(kStageClassify),
+                          profile_stop(kStageClassify), 0, reqs, block0, nreq);
+    return hipGetLastError();
+}
 
 hipError_t launch_classify(const float* heat, const float* hmax, int nx, int ny, int r_occ,
                            int r_emp, float rho, int normalize, int square, int act, float* ogm,

@@ -28,6 +28,7 @@
 // would evict the location tables of every resident workgroup.  Every store folds the class
 // maxima (eq. non-linearities) into order-preserving unsigned atomics; a one-block kernel
 // converts them once all stores are done.
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.h"
@@ -140,15 +141,6 @@ __global__ __launch_bounds__(256) void k_table_yz_16(const double* __restrict__ 
     }
 }
 
-// Monotone map float -> unsigned so that unsigned max = float max.
-__device__ inline unsigned order_key(float f) {
-    unsigned u = __float_as_uint(f);
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ inline float order_value(unsigned u) {
-    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
-}
-
 // Logical index of workgroup b of n when consecutive hardware indices land on different XCDs
 // (round-robin over kXcds): XCD x receives the logical range [x*n/kXcds, (x+1)*n/kXcds).
 constexpr int kXcds = 8;
@@ -174,9 +166,41 @@ struct DecodeArgs {
     unsigned* hmax_u;          // [2] ordered maxima (zeroed by the norm kernel)
     float* partial;            // [grid][2][2][kTileRows][kTileCols]
     int ksteps;                // K steps per tile
-    int steps_per_wg;          // L
-    long long total_steps;     // ntiles * ksteps
+    int steps_per_wg;          // fp32 kernel: L, stream-K iterations per workgroup
+    long long total_steps;     // fp32 kernel: ntiles * ksteps
+    // 16-bit kernels: work units (a K range of one tile), in K order within a tile; tile t's
+    // units are tile_u0[t] .. tile_u0[t + 1] - 1 and workgroup w runs units wg_u0[w] ..
+    // wg_u0[w + 1] - 1 (one, or two where its range crosses a tile border).
+    const DUnit* units;
+    int nunits;
+    const int* tile_u0;
+    const int* wg_u0;
+    int nwg;
+    // Batched launches (16-bit kernels): tiles of several requests, tile t belonging to request
+    // reqs[t.pad], whose fields replace the per-request ones above.  Null for one request.
+    const DecodeReq* reqs;
 };
+
+// The per-request view of a batched launch for tile t (unchanged for a single request).
+__device__ inline void apply_request(DecodeArgs& r, const DTile& t) {
+    if (!r.reqs) return;
+    const DecodeReq q = r.reqs[t.pad];
+    r.col_tx = q.col_tx;
+    r.ex = q.ex;
+    r.ey = q.ey;
+    r.ey_lo = q.ey_lo;
+    r.omega_s = q.omega_s;
+    r.halfp = q.halfp;
+    r.nx = q.nx;
+    r.ny = q.ny;
+    r.tiles_x = q.tiles_x;
+    r.out_scale = q.out_scale;
+    r.heat = q.heat;
+    r.class_stride = q.class_stride;
+    r.row_map = q.row_map;
+    r.hmax_u = q.hmax_u;
+    r.ksteps = q.ksteps;
+}
 
 // Operand formats: FP32 (0), BF16 (1), FP16 (2), BF16 hi+lo (3).
 template <int PREC>
@@ -501,7 +525,7 @@ __device__ inline v16f mfma32(u32x4 x, u32x4 y, v16f c) {
 // Z: volumes; rows are the joint (z, y) rows of the volume (the row operand is their joint table)
 // and row_map places them in the heat planes.
 template <int PREC, bool Z>
-__global__ __launch_bounds__(Wide<PREC>::NT, Wide<PREC>::OCC) void k_decode16(DecodeArgs a) {
+__global__ __launch_bounds__(Wide<PREC>::NT, Wide<PREC>::OCC) void k_decode16(DecodeArgs ab) {
     using W = Wide<PREC>;
     constexpr int NS = W::NS, NSETS = W::NSETS, DEPTH = W::DEPTH, KB = W::KB, NCH = W::NCH, TR = W::TR;
     constexpr int B_PER_T = W::B_PER_T, NT = W::NT;
@@ -511,20 +535,20 @@ __global__ __launch_bounds__(Wide<PREC>::NT, Wide<PREC>::OCC) void k_decode16(De
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, l32 = lane & 31;
     const int wg = xcd_local_index(blockIdx.x, gridDim.x);
-    const long long it0 = (long long)wg * a.steps_per_wg;
-    const long long it1 = min(it0 + a.steps_per_wg, a.total_steps);
-    const int first_tile = (int)(it0 / a.ksteps);
-    const uint16_t* ey_hi = static_cast<const uint16_t*>(a.ey);
-    const uint16_t* ey_lo = static_cast<const uint16_t*>(a.ey_lo);
-    const size_t pitch = 2 * (size_t)a.halfp;  // 16-bit elements per table row
-
-    long long it = it0;
-    while (it < it1) {
-        const int ti = (int)(it / a.ksteps);
-        const int kb0 = (int)(it - (long long)ti * a.ksteps);
-        const int kb1 = (int)min((long long)a.ksteps, it1 - (long long)ti * a.ksteps);
-        it = (long long)ti * a.ksteps + kb1;
-        const DTile t = a.tiles[ti];
+    if (wg >= ab.nwg) return;   // grid padding (uniform over the workgroup)
+    const int u_end = ab.wg_u0[wg + 1];
+    for (int ui = ab.wg_u0[wg]; ui < u_end; ++ui) {
+        const DUnit unit = ab.units[ui];
+        const int ti = unit.tile, kb0 = unit.kb0, kb1 = unit.kb1;
+        const DTile t = ab.tiles[ti];
+        DecodeArgs a = ab;
+        apply_request(a, t);
+        const int ks = a.ksteps;
+        // the tables are global memory (the pointers of a batched launch come from a descriptor,
+        // so the address space is stated for the compiler)
+        const gmem<uint16_t>* ey_hi = as_global(static_cast<const uint16_t*>(a.ey));
+        const gmem<uint16_t>* ey_lo = as_global(static_cast<const uint16_t*>(a.ey_lo));
+        const size_t pitch = 2 * (size_t)a.halfp;  // 16-bit elements per table row
         const int n = kb1 - kb0;
         // does this wave's 32-row block hold any row of the tile (wave-uniform)
         const int wv = __builtin_amdgcn_readfirstlane(wave);
@@ -535,20 +559,20 @@ __global__ __launch_bounds__(Wide<PREC>::NT, Wide<PREC>::OCC) void k_decode16(De
         const size_t arow = (size_t)arow_idx * pitch + 8 * h;
         // column operand sources: the x table per column; the memories of the (at most two)
         // tile columns of the slice are staged in LDS, two K steps ahead, by the first wave
-        const f32x4* ex_row[B_PER_T];
+        const gmem<f32x4>* ex_row[B_PER_T];
         int oslot[B_PER_T];
         const int part16 = tid % (KB / 2);
 #pragma unroll
         for (int u = 0; u < B_PER_T; ++u) {
             const int c = (tid + NT * u) / (KB / 2);
             const int gcol = min(t.col0 + c, a.nx - 1);
-            ex_row[u] = reinterpret_cast<const f32x4*>(a.ex + (size_t)gcol * a.halfp + 2 * part16);
-            oslot[u] = min(max(a.col_tx[gcol] - t.tx0, 0), 1);
+            ex_row[u] = as_global(reinterpret_cast<const f32x4*>(a.ex + (size_t)gcol * a.halfp + 2 * part16));
+            oslot[u] = min(max(as_global(a.col_tx)[gcol] - t.tx0, 0), 1);
         }
         const int oks = (lane >> 5) & 1, ocls = (lane >> 4) & 1;  // this lane's staging item
-        const f32x4* om_src = reinterpret_cast<const f32x4*>(
+        const gmem<f32x4>* om_src = as_global(reinterpret_cast<const f32x4*>(
             a.omega_s + (size_t)(2 * (t.ty * a.tiles_x + min(t.tx0 + oks, a.tiles_x - 1)) + ocls) * a.halfp +
-            2 * part16);
+            2 * part16));
         f32x4 OM;
         auto load_om = [&](int kk) { OM = om_src[(size_t)(kb0 + min(kk, n - 1)) * (KB / 2)]; };
         auto store_om = [&](int st) {
@@ -568,8 +592,8 @@ __global__ __launch_bounds__(Wide<PREC>::NT, Wide<PREC>::OCC) void k_decode16(De
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
                 const size_t off = arow + (size_t)kb * (2 * KB) + 16 * ch;
-                A[S][ch][0] = *reinterpret_cast<const u32x4*>(ey_hi + off);
-                if (W::kSplit) A[S][ch][NS - 1] = *reinterpret_cast<const u32x4*>(ey_lo + off);
+                A[S][ch][0] = *reinterpret_cast<const gmem<u32x4>*>(ey_hi + off);
+                if (W::kSplit) A[S][ch][NS - 1] = *reinterpret_cast<const gmem<u32x4>*>(ey_lo + off);
             }
         };
         auto load_b = [&](int kk) {  // column operand sources of K step kb0 + kk
@@ -673,13 +697,12 @@ __global__ __launch_bounds__(Wide<PREC>::NT, Wide<PREC>::OCC) void k_decode16(De
         if (kk < n) step(std::integral_constant<int, 0>{}, kk);
         if (NSETS > 2 && kk + 1 < n) step(std::integral_constant<int, 1>{}, kk + 1);
 
-        const bool whole = (kb0 == 0 && kb1 == a.ksteps);
-        const int slot = (ti == first_tile) ? 0 : 1;
-        float* part = a.partial + ((size_t)wg * 2 + slot) * 2 * TR * kTileCols;
+        const bool whole = (kb0 == 0 && kb1 == ks);
+        gmem_rw<float>* part = as_global_rw(a.partial + (size_t)ui * 2 * TR * kTileCols);
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
             float mx = -INFINITY;
-            float* out = a.heat + (size_t)p * a.class_stride;
+            gmem_rw<float>* out = as_global_rw(a.heat + (size_t)p * a.class_stride);
             if (active) {
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb)
@@ -690,7 +713,7 @@ __global__ __launch_bounds__(Wide<PREC>::NT, Wide<PREC>::OCC) void k_decode16(De
                             const int row = t.row0 + r, col = t.col0 + c;
                             if (row < t.row_end && c < t.ncol) {
                                 const float val = acc[cb][p][v] * a.out_scale;
-                                out[(size_t)(Z ? a.row_map[row] : row) * a.nx + col] = val;
+                                out[(size_t)(Z ? as_global(a.row_map)[row] : row) * a.nx + col] = val;
                                 mx = fmaxf(mx, val);
                             }
                         } else {
@@ -719,29 +742,40 @@ struct Fix {
 };
 
 template <int TR>
-__global__ __launch_bounds__(256) void k_decode_fix(DecodeArgs a) {
+__global__ __launch_bounds__(256) void k_decode_fix(DecodeArgs ab) {
     using X = Fix<TR>;
     constexpr int PER_TILE = X::PER_TILE, PARTS = X::PARTS, PER = X::PER;
     const int ti = blockIdx.x / PARTS, partk = blockIdx.x % PARTS;
-    const long long t0 = (long long)ti * a.ksteps;
-    const int w_first = (int)(t0 / a.steps_per_wg);
-    const int w_last = (int)((t0 + a.ksteps - 1) / a.steps_per_wg);
-    if (w_first == w_last) return;  // whole tile, stored by the GEMM
-    const DTile t = a.tiles[ti];
+    // segments of the tile: its work units (16-bit kernels, one partial block per unit), or the
+    // workgroups whose stream-K ranges cover it (fp32 kernel, two partial blocks per workgroup)
+    int w_first, w_last;
+    if (ab.units) {
+        w_first = ab.tile_u0[ti];
+        w_last = ab.tile_u0[ti + 1] - 1;
+    } else {
+        const long long t0 = (long long)ti * ab.ksteps;
+        w_first = (int)(t0 / ab.steps_per_wg);
+        w_last = (int)((t0 + ab.ksteps - 1) / ab.steps_per_wg);
+    }
+    if (w_first >= w_last) return;  // whole tile, stored by the GEMM
+    const DTile t = ab.tiles[ti];
+    DecodeArgs a = ab;
+    apply_request(a, t);
     float sum[PER];
 #pragma unroll
     for (int j = 0; j < PER; ++j) sum[j] = 0.f;
     // segments in workgroup order, four at a time so that their loads are in flight together
     // (a segment past the last one reloads the last and adds nothing)
     auto seg = [&](int w) {
-        const int slot = ((long long)w * a.steps_per_wg / a.ksteps == ti) ? 0 : 1;
-        return a.partial + ((size_t)w * 2 + slot) * PER_TILE + partk * (PER_TILE / PARTS);
+        if (ab.units) return as_global(a.partial + (size_t)w * PER_TILE + partk * (PER_TILE / PARTS));
+        const int slot = ((long long)w * ab.steps_per_wg / ab.ksteps == ti) ? 0 : 1;
+        return as_global(a.partial + ((size_t)w * 2 + slot) * PER_TILE + partk * (PER_TILE / PARTS));
     };
     for (int w = w_first; w <= w_last; w += 4) {
         float v[4][PER];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const float* src = seg(min(w + q, w_last));
+            const gmem<float>* src = seg(min(w + q, w_last));
 #pragma unroll
             for (int j = 0; j < PER; ++j) v[q][j] = src[threadIdx.x + 256 * j];
         }
@@ -760,8 +794,8 @@ __global__ __launch_bounds__(256) void k_decode_fix(DecodeArgs a) {
         const int row = t.row0 + r, col = t.col0 + c;
         if (r < 16 * t.nrb && row < t.row_end && c < t.ncol) {
             const float v = sum[j] * a.out_scale;
-            const size_t orow = a.row_map ? (size_t)a.row_map[row] : (size_t)row;
-            a.heat[(size_t)p * a.class_stride + orow * a.nx + col] = v;
+            const size_t orow = a.row_map ? (size_t)as_global(a.row_map)[row] : (size_t)row;
+            as_global_rw(a.heat)[(size_t)p * a.class_stride + orow * a.nx + col] = v;
             mx[p] = fmaxf(mx[p], v);
         }
     }
@@ -913,9 +947,19 @@ hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
     a.ksteps = d.plan.ksteps;
     a.steps_per_wg = d.plan.steps_per_wg;
     a.total_steps = d.plan.total_steps;
-    const dim3 grid(d.plan.grid), block(256), block16(Wide<1>::NT);
+    a.units = precision == 0 ? nullptr : d.units;
+    a.nunits = d.nunits;
+    a.tile_u0 = d.tile_u0;
+    a.wg_u0 = d.wg_u0;
+    a.nwg = d.nwg;
+    a.reqs = nullptr;
+    if (precision != 0 && (!d.units || !d.wg_u0 || d.nunits < 1 || d.nwg < 1))
+        return d.ntiles == 0 ? hipSuccess : hipErrorInvalidValue;
+    const dim3 grid(precision == 0 ? d.plan.grid : (unsigned)((d.nwg + kXcds - 1) / kXcds * kXcds)), block(256),
+        block16(Wide<1>::NT);
     // the GEMM records the stage's start event, and its stop event unless a fix-up follows
-    const bool fix = d.plan.steps_per_wg % d.plan.ksteps != 0 || d.plan.steps_per_wg < d.plan.ksteps;
+    const bool fix = precision == 0 ? (d.plan.steps_per_wg % d.plan.ksteps != 0 || d.plan.steps_per_wg < d.plan.ksteps)
+                                    : d.any_split;
     const hipEvent_t e0 = profile_start(kStageDecode), e1 = profile_stop(kStageDecode);
     const hipEvent_t g1 = fix ? nullptr : e1;
     switch (precision) {
@@ -949,6 +993,71 @@ hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
                                   dim3(256), 0, s, nullptr, e1, 0, a);
     }
     if (d.hmax_u) hipLaunchKernelGGL(k_hmax_final, dim3(1), dim3(64), 0, s, d.hmax_u, d.hmax);
+    return hipGetLastError();
+}
+
+// Shortest K range of a workgroup when tiles are split (longer ranges amortise the unit's
+// prologue, epilogue and partial-sum traffic).
+constexpr int kMinUnitSteps = 16;
+
+void decode_units(int ntiles, int ksteps, int num_cus, int tile_base, int unit_base, std::vector<DUnit>& units,
+                  std::vector<int>& tile_u0, std::vector<int>& wg_u0) {
+    // Whole tiles when there are enough of them to occupy every CU.  Otherwise the request's
+    // ntiles * ksteps K steps are cut into equal consecutive ranges, one per workgroup, about one
+    // per CU (at least kMinUnitSteps steps each); a range that crosses a tile border is two
+    // units of the same workgroup.  The cut depends on the request alone, so its tiles' sums
+    // (partials added in unit order) are the same whatever else shares the launch.
+    const int slots = Wide<1>::OCC * num_cus;
+    const long long total = (long long)ntiles * ksteps;
+    long long L = ksteps;
+    if (ntiles > 0 && ntiles < slots)
+        L = std::min<long long>(ksteps, std::max<long long>((total + slots - 1) / slots, kMinUnitSteps));
+    int u = unit_base, cur = -1;
+    for (long long it0 = 0; it0 < total; it0 += L) {
+        const long long it1 = std::min(total, it0 + L);
+        wg_u0.push_back(u);
+        for (long long it = it0; it < it1;) {
+            const int t = (int)(it / ksteps);
+            const int kb0 = (int)(it - (long long)t * ksteps);
+            const int kb1 = (int)std::min<long long>(ksteps, it1 - (long long)t * ksteps);
+            for (; cur < t; ++cur) tile_u0.push_back(u);   // tile t starts at this unit
+            units.push_back(DUnit{tile_base + t, kb0, kb1, 0});
+            ++u;
+            it = (long long)t * ksteps + kb1;
+        }
+    }
+    for (; cur + 1 < ntiles; ++cur) tile_u0.push_back(u);   // no K steps: tiles without units
+}
+
+size_t decode_unit_partial_floats(int nunits) { return (size_t)nunits * 2 * Wide<1>::TR * kTileCols; }
+
+hipError_t launch_decode_batch(int precision, const DecodeBatch& b, hipStream_t s) {
+    if (precision < 1 || precision > 3) return hipErrorInvalidValue;
+    if (b.ntiles == 0 || b.nunits == 0 || b.nwg == 0) return hipSuccess;
+    DecodeArgs a{};
+    a.tiles = b.tiles;
+    a.ntiles = b.ntiles;
+    a.partial = b.partial;
+    a.units = b.units;
+    a.nunits = b.nunits;
+    a.tile_u0 = b.tile_u0;
+    a.wg_u0 = b.wg_u0;
+    a.nwg = b.nwg;
+    a.reqs = b.reqs;
+    const dim3 grid((unsigned)((b.nwg + kXcds - 1) / kXcds * kXcds)), block16(Wide<1>::NT);
+    const hipEvent_t e0 = profile_start(kStageDecode), e1 = profile_stop(kStageDecode);
+    const hipEvent_t g1 = b.any_split ? nullptr : e1;
+    switch (precision) {
+        case 1: hipExtLaunchKernelGGL(k_decode16<1, false>, grid, block16, 0, s, e0, g1, 0, a); break;
+        case 2: hipExtLaunchKernelGGL(k_decode16<2, false>, grid, block16, 0, s, e0, g1, 0, a); break;
+        default: hipExtLaunchKernelGGL(k_decode16<3, false>, grid, block16, 0, s, e0, g1, 0, a); break;
+    }
+    if (b.any_split) {
+        constexpr int TR = Wide<1>::TR;
+        static_assert(Wide<3>::TR == TR, "one fix-up geometry for the 16-bit formats");
+        hipExtLaunchKernelGGL(k_decode_fix<TR>, dim3((unsigned)b.ntiles * Fix<TR>::PARTS), dim3(256), 0, s, nullptr,
+                              e1, 0, a);
+    }
     return hipGetLastError();
 }
 

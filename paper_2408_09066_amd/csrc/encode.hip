@@ -33,10 +33,10 @@ __device__ inline int nearest_tile(double x, double y, const LayoutDev& L) {
     int best = -1;
     double bd = INFINITY;
     for (int j = j0; j <= j1; ++j) {
-        double dy = __dsub_rn(y, L.cy[j]);
+        double dy = __dsub_rn(y, as_global(L.cy)[j]);
         double dy2 = __dmul_rn(dy, dy);
         for (int i = i0; i <= i1; ++i) {
-            double dx = __dsub_rn(x, L.cx[i]);
+            double dx = __dsub_rn(x, as_global(L.cx)[i]);
             double d2 = __dadd_rn(__dmul_rn(dx, dx), dy2);
             if (d2 < bd) {
                 bd = d2;
@@ -50,33 +50,37 @@ __device__ inline int nearest_tile(double x, double y, const LayoutDev& L) {
 // One point per thread; blocks of kAssignChunk points.  hist is key-major:
 // hist[key][chunk] = number of the chunk's points with that key.  The lanes of a wavefront
 // holding one key add their count with one LDS atomic (a chunk's points share few keys).
-__global__ __launch_bounds__(kAssignChunk) void k_assign(const float2* __restrict__ xy,
-                                                         const uint8_t* __restrict__ label,
-                                                         int64_t n, LayoutDev L, int nkeys,
-                                                         int nchunks, int key_bits, int* __restrict__ key_out,
-                                                         int* __restrict__ hist,
-                                                         unsigned long long* __restrict__ n_bad) {
-    extern __shared__ int sh_hist[];
-    for (int k = threadIdx.x; k < nkeys; k += blockDim.x) sh_hist[k] = 0;
+__device__ inline void assign_body(const EncodeReq& q, int bid, int* sh_hist) {
+    for (int k = threadIdx.x; k < q.nkeys; k += blockDim.x) sh_hist[k] = 0;
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * kAssignChunk + threadIdx.x;
+    const int64_t i = (int64_t)bid * kAssignChunk + threadIdx.x;
     int key = -1;
-    if (i < n) {
-        const float2 p = xy[i];
-        const unsigned l = label[i];
+    if (i < q.n) {
+        const float2 p = as_global(q.xy)[i];
+        const unsigned l = as_global(q.label)[i];
         if (l <= 1u) {
-            const int b = nearest_tile((double)p.x, (double)p.y, L);
+            const int b = nearest_tile((double)p.x, (double)p.y, q.L);
             if (b >= 0) key = 2 * b + (int)l;
         }
-        if (key < 0) atomicAdd(n_bad, 1ull);
-        key_out[i] = key;
+        if (key < 0) atomicAdd(as_global_rw(q.n_bad), 1ull);
+        as_global_rw(q.key)[i] = key;
     }
     const int lane = threadIdx.x & 63;
-    const uint64_t same = same_value_lanes(key < 0 ? (unsigned)nkeys : (unsigned)key, key_bits);
+    const uint64_t same = same_value_lanes(key < 0 ? (unsigned)q.nkeys : (unsigned)key, q.key_bits);
     if (key >= 0 && (same & ((1ull << lane) - 1ull)) == 0) atomicAdd(&sh_hist[key], __popcll(same));
     __syncthreads();
-    for (int k = threadIdx.x; k < nkeys; k += blockDim.x)
-        hist[(size_t)k * nchunks + blockIdx.x] = sh_hist[k];
+    for (int k = threadIdx.x; k < q.nkeys; k += blockDim.x)
+        as_global_rw(q.hist)[(size_t)k * q.nchunks + bid] = sh_hist[k];
+}
+__global__ __launch_bounds__(kAssignChunk) void k_assign(EncodeReq q) {
+    extern __shared__ int sh_hist[];
+    assign_body(q, blockIdx.x, sh_hist);
+}
+__global__ __launch_bounds__(kAssignChunk) void k_assign_b(const EncodeReq* __restrict__ qs, const int* __restrict__ b0,
+                                                           int nq) {
+    extern __shared__ int sh_hist[];
+    const int r = batch_job(b0, nq, blockIdx.x);
+    assign_body(qs[r], blockIdx.x - b0[r], sh_hist);
 }
 
 // Exclusive scan across a block of kScanThreads threads; returns the block total in *total.
@@ -110,13 +114,13 @@ __device__ int block_scan_excl(int v, int* sh_w, int* total) {
 // One block.  The key-major histogram becomes, by one flat exclusive scan, the destination
 // base of every (key, chunk) -- the stable counting sort's offsets.  Then per key: point
 // count, encode work items and their table.
-__global__ __launch_bounds__(kScanThreads) void k_scan(int* __restrict__ hist, int nchunks,
-                                                       int nkeys, int echunk,
-                                                       EChunk* __restrict__ table,
-                                                       int* __restrict__ meta,
-                                                       unsigned* __restrict__ version) {
+__device__ inline void scan_body(const EncodeReq& q, int* key_start /* LDS [nkeys] */) {
     __shared__ int sh_w[kScanThreads / 64];
-    extern __shared__ int key_start[];   // [nkeys]
+    gmem_rw<int>* __restrict__ hist = as_global_rw(q.hist);
+    const int nchunks = q.nchunks, nkeys = q.nkeys, echunk = q.echunk;
+    gmem_rw<EChunk>* __restrict__ table = as_global_rw(q.table);
+    gmem_rw<int>* __restrict__ meta = as_global_rw(q.meta);
+    gmem_rw<unsigned>* __restrict__ version = q.version ? as_global_rw(q.version) : nullptr;
     const int64_t N = (int64_t)nkeys * nchunks;
     // coalesced passes of kScanThreads * kScanGroup entries (one aligned group per thread; the
     // histogram buffer is padded so the last group stays in bounds); the next pass's group is
@@ -210,6 +214,15 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int* __restrict__ hist, i
         table[idx] = e;
     }
 }
+__global__ __launch_bounds__(kScanThreads) void k_scan(EncodeReq q) {
+    extern __shared__ int key_start[];
+    scan_body(q, key_start);
+}
+__global__ __launch_bounds__(kScanThreads) void k_scan_b(const EncodeReq* __restrict__ qs, const int* __restrict__ b0,
+                                                         int nq) {
+    extern __shared__ int key_start[];
+    scan_body(qs[batch_job(b0, nq, blockIdx.x)], key_start);
+}
 
 // Stable counting-sort scatter: one block of WAVES wavefronts per chunk of kAssignChunk points,
 // wave w taking the chunk's w-th part in order (four waves; one when the per-wave key tables
@@ -218,17 +231,19 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int* __restrict__ hist, i
 // wave, a point's slot is its key's running base plus the number of earlier lanes of the same
 // round with the same key (lanes are matched bit by bit with ballots).
 template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_scatter(const float2* __restrict__ xy,
-                                                const int* __restrict__ key, int64_t n,
-                                                LayoutDev L, int nkeys, int nchunks, int key_bits,
-                                                const int* __restrict__ base,
-                                                float2* __restrict__ sorted,
-                                                float2* __restrict__ sorted_lo) {
-    extern __shared__ int run[];  // [WAVES][nkeys]
+__device__ inline void scatter_body(const EncodeReq& q, int bid, int* run /* LDS [WAVES][nkeys] */) {
+    gmem<float2>* __restrict__ xy = as_global(q.xy);
+    gmem<int>* __restrict__ key = as_global(q.key);
+    const int64_t n = q.n;
+    const LayoutDev& L = q.L;
+    const int nkeys = q.nkeys, nchunks = q.nchunks, key_bits = q.key_bits;
+    gmem<int>* __restrict__ base = as_global(q.hist);
+    gmem_rw<float2>* __restrict__ sorted = as_global_rw(q.sorted);
+    gmem_rw<float2>* __restrict__ sorted_lo = as_global_rw(q.sorted_lo);
     constexpr int Q = kAssignChunk / WAVES;           // points per wave
     constexpr int R = Q / 64;                         // rounds per wave
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t q0 = (int64_t)blockIdx.x * kAssignChunk + (int64_t)wave * Q;
+    const int64_t q0 = (int64_t)bid * kAssignChunk + (int64_t)wave * Q;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int kk[R];
     float2 pp[R];
@@ -237,7 +252,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_scatter(const float2* __restrict
     for (int r = 0; r < R; ++r) {
         const int64_t i = q0 + r * 64 + lane;
         kk[r] = (i < n) ? key[i] : -1;
-        pp[r] = (i < n) ? xy[i] : make_float2(0.f, 0.f);
+        pp[r] = make_float2(0.f, 0.f);
+        if (i < n) pp[r] = xy[i];
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) same[r] = same_value_lanes(kk[r] < 0 ? (unsigned)nkeys : (unsigned)kk[r], key_bits);
@@ -249,7 +265,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_scatter(const float2* __restrict
         if (kk[r] >= 0 && (same[r] & lt_mask) == 0) atomicAdd(&my[kk[r]], __popcll(same[r]));
     __syncthreads();
     for (int k = threadIdx.x; k < nkeys; k += blockDim.x) {  // counts -> per-wave bases
-        int acc = base[(size_t)k * nchunks + blockIdx.x];
+        int acc = base[(size_t)k * nchunks + bid];
         for (int w = 0; w < WAVES; ++w) {
             const int c = run[w * nkeys + k];
             run[w * nkeys + k] = acc;
@@ -265,8 +281,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_scatter(const float2* __restrict
             const int dest = my[k] + rank;
             const int beta = k >> 1;
             const int tx = beta % L.tiles_x, ty = beta / L.tiles_x;
-            const double lx = (double)pp[r].x - L.cx[tx];
-            const double ly = (double)pp[r].y - L.cy[ty];
+            const double lx = (double)pp[r].x - as_global(L.cx)[tx];
+            const double ly = (double)pp[r].y - as_global(L.cy)[ty];
             const float fx = (float)lx, fy = (float)ly;
             sorted[dest] = make_float2(fx, fy);
             sorted_lo[dest] = make_float2((float)(lx - (double)fx), (float)(ly - (double)fy));
@@ -275,20 +291,37 @@ __global__ __launch_bounds__(64 * WAVES) void k_scatter(const float2* __restrict
         __syncthreads();
     }
 }
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_scatter(EncodeReq q) {
+    extern __shared__ int run[];
+    scatter_body<WAVES>(q, blockIdx.x, run);
+}
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_scatter_b(const EncodeReq* __restrict__ qs,
+                                                          const int* __restrict__ b0, int nq) {
+    extern __shared__ int run[];
+    const int r = batch_job(b0, nq, blockIdx.x);
+    scatter_body<WAVES>(qs[r], blockIdx.x - b0[r], run);
+}
 
 // Partial spectra of one work item for one block of bins.  Thread t owns bins
 // b0 + t + j*256, j < BPT; the points are read as wave-uniform (scalar) loads.
+// Blocks are numbered work item fastest: block bid is work item bid % max_echunks of bin block
+// bid / max_echunks.
 template <int BPT>
-__global__ __launch_bounds__(kEncodeThreads) void k_encode(
-    const float2* __restrict__ sorted, const float2* __restrict__ sorted_lo,
-    const EChunk* __restrict__ table, const int* __restrict__ meta,
-    const float2* __restrict__ rev, const double2* __restrict__ rev_d, float max_rev_x,
-    float max_rev_y, int halfp, float2* __restrict__ partial) {
-    const int c = blockIdx.x;
-    if (c >= meta[0]) return;
-    const EChunk e = table[c];
-    const int b0 = blockIdx.y * (kEncodeThreads * BPT) + threadIdx.x;
-    const float2* __restrict__ p = sorted + e.start;
+__device__ inline void encode_body(const EncodeReq& q, int bid) {
+    gmem<float2>* __restrict__ sorted = as_global(q.sorted);
+    gmem<float2>* __restrict__ sorted_lo = as_global(q.sorted_lo);
+    gmem<float2>* __restrict__ rev = as_global(q.rev);
+    gmem<double2>* __restrict__ rev_d = as_global(q.rev_d);
+    const float max_rev_x = q.max_rev_x, max_rev_y = q.max_rev_y;
+    const int halfp = q.halfp;
+    gmem_rw<float2>* __restrict__ partial = as_global_rw(q.partial);
+    const int c = bid % q.max_echunks;
+    if (c >= as_global(q.meta)[0]) return;
+    const EChunk e = as_global(q.table)[c];
+    const int b0 = (bid / q.max_echunks) * (kEncodeThreads * BPT) + threadIdx.x;
+    gmem<float2>* __restrict__ p = sorted + e.start;
 
     // Largest phase (revolutions) any bin can reach on this work item's points.
     __shared__ float sh_max[kEncodeThreads / 64];
@@ -314,7 +347,8 @@ __global__ __launch_bounds__(kEncodeThreads) void k_encode(
 #pragma unroll
         for (int j = 0; j < BPT; ++j) {
             const int k = b0 + j * kEncodeThreads;
-            float2 t = (k < halfp) ? rev[k] : make_float2(0.f, 0.f);
+            float2 t = make_float2(0.f, 0.f);
+            if (k < halfp) t = rev[k];
             ax[j] = t.x;
             ay[j] = t.y;
         }
@@ -360,11 +394,12 @@ __global__ __launch_bounds__(kEncodeThreads) void k_encode(
 #pragma unroll
         for (int j = 0; j < BPT; ++j) {
             const int k = b0 + j * kEncodeThreads;
-            double2 t = (k < halfp) ? rev_d[k] : make_double2(0.0, 0.0);
+            double2 t = make_double2(0.0, 0.0);
+            if (k < halfp) t = rev_d[k];
             ax[j] = t.x;
             ay[j] = t.y;
         }
-        const float2* __restrict__ plo = sorted_lo + e.start;
+        gmem<float2>* __restrict__ plo = sorted_lo + e.start;
         for (int q = 0; q < e.len; ++q) {
             const float2 a = p[q], al = plo[q];
             const double x = (double)a.x + (double)al.x, y = (double)a.y + (double)al.y;
@@ -383,22 +418,37 @@ __global__ __launch_bounds__(kEncodeThreads) void k_encode(
         if (k < halfp) partial[(size_t)c * halfp + k] = make_float2(re[j], im[j]);
     }
 }
+template <int BPT>
+__global__ __launch_bounds__(kEncodeThreads) void k_encode(EncodeReq q) {
+    encode_body<BPT>(q, blockIdx.x);
+}
+template <int BPT>
+__global__ __launch_bounds__(kEncodeThreads) void k_encode_b(const EncodeReq* __restrict__ qs,
+                                                             const int* __restrict__ b0, int nq) {
+    const int r = batch_job(b0, nq, blockIdx.x);
+    encode_body<BPT>(qs[r], blockIdx.x - b0[r]);
+}
 
 // omega[key][k] += sum over the key's work items.  Four groups of 64 threads per block of 64
 // bins: group g sums the items g, g + 4, g + 8, ... in order, eight loads in flight, and the four
 // group sums are added in a fixed order (deterministic).
-__global__ __launch_bounds__(256) void k_reduce(const float2* __restrict__ partial,
-                                                const int* __restrict__ meta, int nkeys, int half,
-                                                int halfp, float2* __restrict__ omega) {
+// Blocks are numbered bin block fastest: block bid is bins 64 * (bid % ceil(half / 64)) .. of key
+// bid / ceil(half / 64).
+__device__ inline void reduce_body(const EncodeReq& q, int bid) {
+    gmem<float2>* __restrict__ partial = as_global(q.partial);
+    gmem<int>* __restrict__ meta = as_global(q.meta);
+    const int nkeys = q.nkeys, half = q.half, halfp = q.halfp;
+    gmem_rw<float2>* __restrict__ omega = as_global_rw(q.omega);
     __shared__ float2 sh[4][64];
-    const int key = blockIdx.y;
+    const int bblocks = (half + 63) / 64;
+    const int key = bid / bblocks;
     const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int k = blockIdx.x * 64 + lane;
+    const int k = (bid % bblocks) * 64 + lane;
     const int e0 = meta[1 + key], ne = meta[1 + nkeys + key];
     if (ne == 0) return;   // uniform over the block
     float sr = 0.f, si = 0.f;
     if (k < half) {
-        const float2* p = partial + (size_t)e0 * halfp + k;
+        gmem<float2>* p = partial + (size_t)e0 * halfp + k;
         int c = g;
         for (; c + 28 < ne; c += 32) {
             float2 v[8];
@@ -420,25 +470,32 @@ __global__ __launch_bounds__(256) void k_reduce(const float2* __restrict__ parti
     __syncthreads();
     if (g == 0 && k < half) {
         const float2 a = sh[0][lane], b = sh[1][lane], c = sh[2][lane], d = sh[3][lane];
-        float2* o = omega + (size_t)key * halfp + k;
+        gmem_rw<float2>* o = omega + (size_t)key * halfp + k;
         const float2 w = *o;
         *o = make_float2(w.x + ((a.x + b.x) + (c.x + d.x)), w.y + ((a.y + b.y) + (c.y + d.y)));
     }
+}
+__global__ __launch_bounds__(256) void k_reduce(EncodeReq q) { reduce_body(q, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_reduce_b(const EncodeReq* __restrict__ qs, const int* __restrict__ b0,
+                                                  int nq) {
+    const int r = batch_job(b0, nq, blockIdx.x);
+    reduce_body(qs[r], blockIdx.x - b0[r]);
 }
 
 // scale[key] = 1 / ||w|| with ||w||^2 = (2/D) sum_{k < D/2} |Omega_k|^2 (Parseval over the
 // conjugate-symmetric spectrum; bins 0 and D/2 both equal the point count), 0 for an empty
 // memory (eq. vector-normalization); omega_s[key] = conj(Omega[key]) * scale[key].
 constexpr int kNormThreads = 1024;
-__global__ __launch_bounds__(kNormThreads) void k_norm(const float2* __restrict__ omega, int half,
-                                              int halfp, int D, float* __restrict__ scale,
-                                              float2* __restrict__ omega_s,
-                                              unsigned* __restrict__ hmax_u) {
-    const int key = blockIdx.x;
+__device__ inline void norm_body(const EncodeReq& q, int key) {
+    gmem<float2>* __restrict__ omega = as_global(q.omega);
+    const int half = q.half, halfp = q.halfp, D = q.D;
+    gmem_rw<float>* __restrict__ scale = as_global_rw(q.scale);
+    gmem_rw<float2>* __restrict__ omega_s = as_global_rw(q.omega_s);
+    gmem_rw<unsigned>* __restrict__ hmax_u = as_global_rw(q.hmax_u);
     // the following similarity GEMM folds its class maxima into hmax_u[0..1]; they start from
     // zero here
     if (key == 0 && threadIdx.x < 2) hmax_u[threadIdx.x] = 0u;
-    const float2* w = omega + (size_t)key * halfp;
+    gmem<float2>* w = omega + (size_t)key * halfp;
     double s = 0.0;
     for (int k = threadIdx.x; k < half; k += kNormThreads) {
         double re = w[k].x, im = w[k].y;
@@ -460,8 +517,14 @@ __global__ __launch_bounds__(kNormThreads) void k_norm(const float2* __restrict_
     __syncthreads();
     // conj(Omega) / ||w|| for the similarity GEMM (padding bins stay zero)
     const float inv = sh_inv;
-    float2* o = omega_s + (size_t)key * halfp;
+    gmem_rw<float2>* o = omega_s + (size_t)key * halfp;
     for (int k = threadIdx.x; k < halfp; k += kNormThreads) o[k] = make_float2(w[k].x * inv, -w[k].y * inv);
+}
+__global__ __launch_bounds__(kNormThreads) void k_norm(EncodeReq q) { norm_body(q, blockIdx.x); }
+__global__ __launch_bounds__(kNormThreads) void k_norm_b(const EncodeReq* __restrict__ qs, const int* __restrict__ b0,
+                                                         int nq) {
+    const int r = batch_job(b0, nq, blockIdx.x);
+    norm_body(qs[r], blockIdx.x - b0[r]);
 }
 
 // Paper-frame export: out[key][k] = exp(i*Theta[k].mu_beta) * Omega_local[key][k] for
@@ -526,53 +589,140 @@ EncodePlan encode_plan(int64_t n, int halfp, int nkeys) {
     return p;
 }
 
+// The request of one map's encode chain (everything but the spectra-side fields of a norm).
+EncodeReq encode_req(const float* xy, const uint8_t* label, int64_t n, const LayoutDev& L, int nkeys,
+                     const float2* theta_rev, const double* theta_rev_d, float max_rev_x, float max_rev_y,
+                     int half, int halfp, const EncodeWork& w, float2* omega) {
+    const EncodePlan p = encode_plan(n, halfp, nkeys);
+    EncodeReq q{};
+    q.xy = reinterpret_cast<const float2*>(xy);
+    q.label = label;
+    q.n = n;
+    q.L = L;
+    q.nkeys = nkeys;
+    q.key_bits = bits_for(nkeys);
+    q.nchunks = p.nchunks;
+    q.echunk = p.echunk;
+    q.max_echunks = p.max_echunks;
+    q.binblocks = p.binblocks;
+    q.bpt = p.bpt;
+    q.key = w.key;
+    q.hist = w.hist;
+    q.table = w.table;
+    q.meta = w.meta;
+    q.sorted = w.sorted;
+    q.sorted_lo = w.sorted_lo;
+    q.partial = w.partial;
+    q.n_bad = w.n_bad;
+    q.version = w.version;
+    q.rev = theta_rev;
+    q.rev_d = reinterpret_cast<const double2*>(theta_rev_d);
+    q.max_rev_x = max_rev_x;
+    q.max_rev_y = max_rev_y;
+    q.half = half;
+    q.halfp = halfp;
+    q.omega = omega;
+    return q;
+}
+
 hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const LayoutDev& L,
                          int nkeys, const float2* theta_rev, const double* theta_rev_d,
                          float max_rev_x, float max_rev_y, int half, int halfp,
                          const EncodeWork& w, float2* omega, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const EncodePlan p = encode_plan(n, halfp, nkeys);
-    const float2* xy2 = reinterpret_cast<const float2*>(xy);
-    hipLaunchKernelGGL(k_assign, dim3(p.nchunks), dim3(kAssignChunk), nkeys * sizeof(int), s, xy2,
-                       label, n, L, nkeys, p.nchunks, bits_for(nkeys), w.key, w.hist, w.n_bad);
-    launch_key_scan(w.hist, p.nchunks, nkeys, p.echunk, w.table, w.meta, w.version, s);
+    const EncodeReq q = encode_req(xy, label, n, L, nkeys, theta_rev, theta_rev_d, max_rev_x, max_rev_y, half,
+                                   halfp, w, omega);
+    hipLaunchKernelGGL(k_assign, dim3(q.nchunks), dim3(kAssignChunk), nkeys * sizeof(int), s, q);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), nkeys * sizeof(int), s, q);
     if (4 * nkeys * (int)sizeof(int) <= 65536)
-        hipLaunchKernelGGL(k_scatter<4>, dim3(p.nchunks), dim3(256), 4 * nkeys * sizeof(int), s, xy2, w.key,
-                           n, L, nkeys, p.nchunks, bits_for(nkeys), w.hist, w.sorted, w.sorted_lo);
+        hipLaunchKernelGGL(k_scatter<4>, dim3(q.nchunks), dim3(256), 4 * nkeys * sizeof(int), s, q);
     else
-        hipLaunchKernelGGL(k_scatter<1>, dim3(p.nchunks), dim3(64), nkeys * sizeof(int), s, xy2, w.key,
-                           n, L, nkeys, p.nchunks, bits_for(nkeys), w.hist, w.sorted, w.sorted_lo);
-    const double2* rev_d = reinterpret_cast<const double2*>(theta_rev_d);
-    const dim3 eg(p.max_echunks, p.binblocks);
+        hipLaunchKernelGGL(k_scatter<1>, dim3(q.nchunks), dim3(64), nkeys * sizeof(int), s, q);
+    const dim3 eg((unsigned)q.max_echunks * q.binblocks);
     const hipEvent_t e0 = profile_start(kStageEncode), e1 = profile_stop(kStageEncode);
     static_assert(kEncodeBpt == 2, "instantiations below");
-    if (p.bpt == 1)
-        hipExtLaunchKernelGGL(k_encode<1>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo, w.table,
-                              w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp, w.partial);
+    if (q.bpt == 1)
+        hipExtLaunchKernelGGL(k_encode<1>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, q);
     else
-        hipExtLaunchKernelGGL(k_encode<2>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo, w.table,
-                              w.meta, theta_rev, rev_d, max_rev_x, max_rev_y, halfp, w.partial);
-    launch_key_reduce(w.partial, w.meta, nkeys, half, halfp, omega, s);
+        hipExtLaunchKernelGGL(k_encode<2>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, q);
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((half + 63) / 64 * nkeys)), dim3(256), 0, s, q);
     return hipGetLastError();
 }
 
 void launch_key_scan(int* hist, int nchunks, int nkeys, int echunk, EChunk* table, int* meta, unsigned* version,
                      hipStream_t s) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), nkeys * sizeof(int), s, hist, nchunks, nkeys, echunk,
-                       table, meta, version);
+    EncodeReq q{};
+    q.hist = hist;
+    q.nchunks = nchunks;
+    q.nkeys = nkeys;
+    q.echunk = echunk;
+    q.table = table;
+    q.meta = meta;
+    q.version = version;
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), nkeys * sizeof(int), s, q);
 }
 
 void launch_key_reduce(const float2* partial, const int* meta, int nkeys, int half, int halfp, float2* omega,
                        hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3((half + 63) / 64, nkeys), dim3(256), 0, s, partial, meta, nkeys, half,
-                       halfp, omega);
+    EncodeReq q{};
+    q.partial = const_cast<float2*>(partial);
+    q.meta = const_cast<int*>(meta);
+    q.nkeys = nkeys;
+    q.half = half;
+    q.halfp = halfp;
+    q.omega = omega;
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((half + 63) / 64 * nkeys)), dim3(256), 0, s, q);
 }
 
 hipError_t launch_norm(const float2* omega, int nkeys, int half, int halfp, int D, float* scale,
                        float2* omega_s, unsigned* hmax_u, hipStream_t s) {
-    hipLaunchKernelGGL(k_norm, dim3(nkeys), dim3(kNormThreads), 0, s, omega, half, halfp, D, scale, omega_s,
-                       hmax_u);
+    EncodeReq q{};
+    q.omega = const_cast<float2*>(omega);
+    q.half = half;
+    q.halfp = halfp;
+    q.D = D;
+    q.scale = scale;
+    q.omega_s = omega_s;
+    q.hmax_u = hmax_u;
+    hipLaunchKernelGGL(k_norm, dim3(nkeys), dim3(kNormThreads), 0, s, q);
     return hipGetLastError();
+}
+
+hipError_t launch_encode_batch(const EncodeBatch& b, hipStream_t s) {
+    const int nq = b.nreq;
+    auto b0 = [&](int stage) { return b.block0 + (size_t)stage * (nq + 1); };
+    if (b.blocks[0] > 0) {
+        hipLaunchKernelGGL(k_assign_b, dim3(b.blocks[0]), dim3(kAssignChunk), b.max_keys * sizeof(int), s, b.reqs,
+                           b0(0), nq);
+        hipLaunchKernelGGL(k_scan_b, dim3(b.blocks[1]), dim3(kScanThreads), b.max_keys * sizeof(int), s, b.reqs,
+                           b0(1), nq);
+        if (4 * b.max_keys * (int)sizeof(int) <= 65536)
+            hipLaunchKernelGGL(k_scatter_b<4>, dim3(b.blocks[2]), dim3(256), 4 * b.max_keys * sizeof(int), s, b.reqs,
+                               b0(2), nq);
+        else
+            hipLaunchKernelGGL(k_scatter_b<1>, dim3(b.blocks[2]), dim3(64), b.max_keys * sizeof(int), s, b.reqs,
+                               b0(2), nq);
+        const hipEvent_t e0 = profile_start(kStageEncode), e1 = profile_stop(kStageEncode);
+        if (b.bpt == 1)
+            hipExtLaunchKernelGGL(k_encode_b<1>, dim3(b.blocks[3]), dim3(kEncodeThreads), 0, s, e0, e1, 0, b.reqs,
+                                  b0(3), nq);
+        else
+            hipExtLaunchKernelGGL(k_encode_b<2>, dim3(b.blocks[3]), dim3(kEncodeThreads), 0, s, e0, e1, 0, b.reqs,
+                                  b0(3), nq);
+        hipLaunchKernelGGL(k_reduce_b, dim3(b.blocks[4]), dim3(256), 0, s, b.reqs, b0(4), nq);
+    }
+    if (b.blocks[5] > 0) hipLaunchKernelGGL(k_norm_b, dim3(b.blocks[5]), dim3(kNormThreads), 0, s, b.reqs, b0(5), nq);
+    return hipGetLastError();
+}
+
+void encode_batch_blocks(const EncodeReq& q, int out[kEncodeStages]) {
+    const bool enc = q.n > 0;
+    out[0] = enc ? q.nchunks : 0;
+    out[1] = enc ? 1 : 0;
+    out[2] = enc ? q.nchunks : 0;
+    out[3] = enc ? q.max_echunks * q.binblocks : 0;
+    out[4] = enc ? (q.half + 63) / 64 * q.nkeys : 0;
+    out[5] = q.nkeys;
 }
 
 hipError_t launch_memories_export(const float2* omega, const double* theta_rad, const LayoutDev& L,

@@ -8,6 +8,8 @@
 #include <cstdint>
 #include <vector>
 
+#include "vsaogm.h"
+
 namespace vsaogm {
 
 constexpr int kMaxTilesPerAxis = 64;
@@ -34,6 +36,39 @@ __device__ inline uint64_t same_value_lanes(unsigned v, int bits) {
         same &= bit ? m : ~m;
     }
     return same;
+}
+
+// Pointers into global memory (address space 1), so that loads and stores through pointers
+// read from a descriptor (batched launches) still compile to global, not flat, instructions.
+// The qualifier only exists in the device pass; the host pass parses the same bodies with plain
+// pointers (it compiles no device code).
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using gmem = const __attribute__((address_space(1))) T;
+template <class T>
+using gmem_rw = __attribute__((address_space(1))) T;
+#else
+template <class T>
+using gmem = const T;
+template <class T>
+using gmem_rw = T;
+#endif
+template <class T>
+__device__ inline gmem<T>* as_global(const T* p) {
+    return (gmem<T>*)p;
+}
+template <class T>
+__device__ inline gmem_rw<T>* as_global_rw(T* p) {
+    return (gmem_rw<T>*)p;
+}
+
+// Monotone map float -> unsigned so that unsigned max = float max (class maxima by atomicMax).
+__device__ inline unsigned order_key(float f) {
+    unsigned u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float order_value(unsigned u) {
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
 }
 
 // Tile layout as the kernels see it.  Centres are computed on the host in double
@@ -112,6 +147,32 @@ constexpr int kClassify3TiledRadius = 4;
 hipError_t launch_classify3(const float* heat, const float* hmax, int nx, int ny, int nz, int r_emp, int r_occ,
                             float rho, float* g, float* ogm, uint8_t* label, hipStream_t s);
 
+// ---- batched map updates (map.hip) ------------------------------------------------------
+// One whole map update: bundle n points into the map, decode its grid, classify it.  Device
+// pointers; ogm may be null.
+struct UpdateItem {
+    vsaogm_map* map;
+    const float* xy;
+    const uint8_t* label;
+    int64_t n;
+    vsaogm_grid_desc grid;
+    int32_t r_occ, r_emp;
+    float rho;
+    float* heat;        // [2][ny][nx]
+    float* hmax;        // [2]
+    float* ogm;         // [ny][nx] or null
+    uint8_t* label_out; // [ny][nx]
+};
+struct UpdateBatchWork;   // staging and device buffers of one in-flight batch
+UpdateBatchWork* update_batch_work_create();
+void update_batch_work_destroy(UpdateBatchWork* w);
+// count updates of distinct maps on one device as one launch per stage (precision: a 16-bit
+// format), asynchronously on s.  Results equal the same updates through vsaogm_encode,
+// vsaogm_decode and vsaogm_classify up to the order of the similarity's fp32 accumulation (the
+// stream-K split of the K loop depends on the batch).  w must not be reused before s passes the
+// batch.  Returns a vsaogm_status (message in vsaogm_last_error).
+int run_update_batch(const UpdateItem* items, int count, int precision, hipStream_t s, UpdateBatchWork* w);
+
 // ---- error text shared by every entry point (map.hip) -------------------------------
 void set_last_error(const char* msg);
 
@@ -135,6 +196,61 @@ struct EncodeWork {
     unsigned long long* n_bad;
     unsigned* version;   // [nkeys] bumped for every memory that receives points
 };
+
+// Everything one map's encode chain (assign, scan, scatter, encode, reduce) and its memory norm
+// need: the kernels take it by value for one map, or read it from a device array in a batched
+// launch that covers the encodes of several maps (one request each) with one dispatch per stage.
+struct EncodeReq {
+    const float2* xy;                 // [n] world metres
+    const uint8_t* label;             // [n]
+    int64_t n;
+    LayoutDev L;
+    int nkeys, key_bits;
+    int nchunks, echunk, max_echunks, binblocks, bpt;   // encode_plan
+    int* key;
+    int* hist;
+    EChunk* table;
+    int* meta;
+    float2* sorted;
+    float2* sorted_lo;
+    float2* partial;
+    unsigned long long* n_bad;
+    unsigned* version;
+    const float2* rev;
+    const double2* rev_d;
+    float max_rev_x, max_rev_y;
+    int half, halfp, D;
+    float2* omega;                    // [nkeys][halfp] local-frame memories
+    float* scale;                     // norm: [nkeys] 1/||w||
+    float2* omega_s;                  // norm: [nkeys][halfp] conj(Omega)/||w||
+    unsigned* hmax_u;                 // norm: [2] ordered class maxima, zeroed
+};
+
+// Batched launches: job r covers blocks [block0[r], block0[r+1]) of a stage's grid; the job of
+// block b is the last r with block0[r] <= b (jobs with no blocks are passed over).
+__device__ inline int batch_job(const int* __restrict__ block0, int njobs, int b) {
+    int lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (block0[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Stages of a batched encode: assign, scan, scatter, encode, reduce, norm.
+constexpr int kEncodeStages = 6;
+struct EncodeBatch {
+    const EncodeReq* reqs;            // device [nreq]
+    const int* block0;                // device [kEncodeStages][nreq + 1] block prefixes
+    int nreq;
+    int blocks[kEncodeStages];        // total blocks per stage
+    int max_keys;                     // largest nkeys (dynamic LDS)
+    int bpt;                          // bins per encode thread, the same for every request
+};
+hipError_t launch_encode_batch(const EncodeBatch& b, hipStream_t s);
+// Blocks of each stage for one request (0 for the encode stages when it has no points).
+void encode_batch_blocks(const EncodeReq& q, int out[kEncodeStages]);
 
 // Launch geometry of one encode, shared by the host (buffer sizing) and the launcher.
 struct EncodePlan {
@@ -160,6 +276,10 @@ hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const
                          int nkeys, const float2* theta_rev, const double* theta_rev_d,
                          float max_rev_x, float max_rev_y, int half, int halfp,
                          const EncodeWork& w, float2* omega, hipStream_t s);
+// The request launch_encode runs (the norm fields are left for the caller).
+EncodeReq encode_req(const float* xy, const uint8_t* label, int64_t n, const LayoutDev& L, int nkeys,
+                     const float2* theta_rev, const double* theta_rev_d, float max_rev_x, float max_rev_y,
+                     int half, int halfp, const EncodeWork& w, float2* omega);
 
 // inv_norm[key] = 1/||w_key|| (0 for an empty memory) and omega_s = conj(Omega) * inv_norm.
 // Also zeroes hmax_u[0..1], the ordered class maxima of the decode that follows.
@@ -186,6 +306,26 @@ hipError_t launch_table_yz_split(const double* theta_xy, const double* theta_z, 
 hipError_t launch_table_split(const double* theta_rad, int axis, const double* local, int ncells,
                               int half, int halfp, bool fp16, void* hi, void* lo, hipStream_t s);
 
+struct DUnit {
+    int tile, kb0, kb1, pad;
+};
+
+// One request of a batched similarity GEMM (the per-map, per-grid fields of a decode).
+struct DecodeReq {
+    const int* col_tx;
+    const float2* ex;
+    const void* ey;
+    const void* ey_lo;
+    const float2* omega_s;
+    int halfp, nx, ny, tiles_x;
+    float out_scale;
+    float* heat;
+    size_t class_stride;
+    const int* row_map;
+    unsigned* hmax_u;
+    int ksteps;
+};
+
 // Stream-K launch geometry of the similarity GEMM.
 struct DecodePlan {
     int ksteps;            // K steps per tile
@@ -194,6 +334,30 @@ struct DecodePlan {
     long long total_steps; // tiles * ksteps
 };
 DecodePlan decode_plan(int precision, int ntiles, int halfp, int num_cus);
+// Work units of the 16-bit similarity GEMM: a K range of one tile; each workgroup runs one
+// unit, or two where its K range crosses a tile border.  A request's units depend only on its
+// own tile count and K steps, so its fp32 accumulation order is the same whether it is decoded
+// alone or in a batch.  Appends the units of tiles tile_base .. tile_base + ntiles - 1
+// (numbered from unit_base), each tile's first unit and each workgroup's first unit; the caller
+// appends the closing entries of tile_u0 and wg_u0.
+void decode_units(int ntiles, int ksteps, int num_cus, int tile_base, int unit_base, std::vector<DUnit>& units,
+                  std::vector<int>& tile_u0, std::vector<int>& wg_u0);
+size_t decode_unit_partial_floats(int nunits);   // partial sums of split tiles
+
+// A batched 16-bit similarity GEMM: tiles of several requests (DTile::pad = request index).
+struct DecodeBatch {
+    const DTile* tiles;        // device [ntiles]
+    int ntiles;
+    const DecodeReq* reqs;     // device [requests]
+    const DUnit* units;        // device [nunits]
+    int nunits;
+    const int* tile_u0;        // device [ntiles + 1]
+    const int* wg_u0;          // device [nwg + 1]
+    int nwg;                   // workgroups of the GEMM
+    float* partial;            // decode_unit_partial_floats(nunits) when any_split
+    bool any_split;            // some tile has several units (a fix-up pass runs)
+};
+hipError_t launch_decode_batch(int precision, const DecodeBatch& b, hipStream_t s);
 size_t decode_partial_floats(int precision, const DecodePlan& plan);  // 0 when no tile is split
 
 struct DecodeLaunch {
@@ -211,8 +375,14 @@ struct DecodeLaunch {
     const int* row_map = nullptr;  // volumes: voxel plane offset of every joint (z, y) row (16-bit kernels only)
     unsigned* hmax_u;       // zeroed by launch_norm
     float* hmax;
-    float* partial;         // decode_partial_floats(precision, plan) floats
-    DecodePlan plan;
+    float* partial;         // fp32: decode_partial_floats(precision, plan); 16-bit: decode_unit_partial_floats
+    DecodePlan plan;        // fp32 kernel
+    const DUnit* units = nullptr;   // 16-bit kernels: work units (decode_units), each tile's
+    int nunits = 0;                 // first unit [ntiles + 1] and each workgroup's [nwg + 1]
+    const int* tile_u0 = nullptr;
+    const int* wg_u0 = nullptr;
+    int nwg = 0;
+    bool any_split = false;
 };
 // Similarity GEMM over the tile list (precision: 0 fp32, 1 bf16, 2 fp16, 3 bf16 hi+lo).
 // With hmax_u == nullptr no class maxima are folded and hmax is not written.
@@ -228,6 +398,19 @@ hipError_t launch_region_max(const float* heat, int nx, int ny, const RegionBox*
                              float* region_max, int nregions, float* hmax, hipStream_t s);
 
 // ---- classify (classify.hip) -------------------------------------------------------
+// One request of a batched classification (entropy decoding, Sec. III-B defaults).
+struct ClassifyReq {
+    const float* heat;         // [2][ny][nx]
+    const unsigned* hmax_u;    // [2] ordered class maxima of the decode
+    float* hmax_out;           // [2] the maxima as floats, or null
+    int nx, ny, r_occ, r_emp;
+    float rho;
+    float* ogm;                // [ny][nx] or null
+    uint8_t* label;            // [ny][nx]
+};
+int classify_blocks(int nx, int ny);
+hipError_t launch_classify_batch(const ClassifyReq* reqs, const int* block0, int nreq, int total_blocks, int max_radius,
+                                 hipStream_t s);
 // act: 0 entropy (disk radii used), 1 ReLU, 2 tanh, 3 sigmoid (per cell)
 hipError_t launch_classify(const float* heat, const float* hmax, int nx, int ny, int r_occ,
                            int r_emp, float rho, int normalize, int square, int act, float* ogm,

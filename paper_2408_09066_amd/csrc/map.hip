@@ -103,6 +103,60 @@ struct DevBuf {
     }
 };
 
+// Work units of the 16-bit GEMM over one tile list (decode_units): the host copy, and the device
+// copy the kernels read.
+struct UnitPlan {
+    std::vector<DUnit> units;
+    std::vector<int> tile_u0, wg_u0;   // [ntiles + 1], [workgroups + 1]
+    void build(int ntiles, int ksteps, int num_cus) {
+        units.clear();
+        tile_u0.clear();
+        wg_u0.clear();
+        decode_units(ntiles, ksteps, num_cus, 0, 0, units, tile_u0, wg_u0);
+        tile_u0.push_back((int)units.size());
+        wg_u0.push_back((int)units.size());
+    }
+    int nwg() const { return (int)wg_u0.size() - 1; }
+};
+struct DevUnits {
+    DevBuf<DUnit> units;
+    DevBuf<int> tile_u0, wg_u0;
+    void upload(const UnitPlan& h) {
+        units.alloc(h.units.size(), "decode work units");
+        tile_u0.alloc(h.tile_u0.size(), "decode tile units");
+        wg_u0.alloc(h.wg_u0.size(), "decode workgroup units");
+        hip_check(hipMemcpy(units.p, h.units.data(), h.units.size() * sizeof(DUnit), hipMemcpyHostToDevice),
+                  "copy units");
+        hip_check(hipMemcpy(tile_u0.p, h.tile_u0.data(), h.tile_u0.size() * sizeof(int), hipMemcpyHostToDevice),
+                  "copy tile units");
+        hip_check(hipMemcpy(wg_u0.p, h.wg_u0.data(), h.wg_u0.size() * sizeof(int), hipMemcpyHostToDevice),
+                  "copy workgroup units");
+    }
+    // stream-ordered; h must stay unchanged until the stream has passed the copies
+    void upload_async(const UnitPlan& h, hipStream_t s) {
+        if (units.n < h.units.size()) units.alloc_async(h.units.size(), s, "decode work units");
+        if (tile_u0.n < h.tile_u0.size()) tile_u0.alloc_async(h.tile_u0.size(), s, "decode tile units");
+        if (wg_u0.n < h.wg_u0.size()) wg_u0.alloc_async(h.wg_u0.size(), s, "decode workgroup units");
+        hip_check(hipMemcpyAsync(units.p, h.units.data(), h.units.size() * sizeof(DUnit), hipMemcpyHostToDevice, s),
+                  "copy units");
+        hip_check(hipMemcpyAsync(tile_u0.p, h.tile_u0.data(), h.tile_u0.size() * sizeof(int),
+                                 hipMemcpyHostToDevice, s),
+                  "copy tile units");
+        hip_check(hipMemcpyAsync(wg_u0.p, h.wg_u0.data(), h.wg_u0.size() * sizeof(int), hipMemcpyHostToDevice, s),
+                  "copy workgroup units");
+    }
+};
+// The 16-bit GEMM's work units of a decode; returns the partial-sum floats it needs.
+size_t set_units(DecodeLaunch& d, const UnitPlan& h, const DevUnits& dv, int ntiles) {
+    d.units = dv.units.p;
+    d.nunits = (int)h.units.size();
+    d.tile_u0 = dv.tile_u0.p;
+    d.wg_u0 = dv.wg_u0.p;
+    d.nwg = h.nwg();
+    d.any_split = d.nunits > ntiles;   // every tile has a unit, so some tile has several
+    return d.any_split ? decode_unit_partial_floats(d.nunits) : 0;
+}
+
 __global__ void k_zero_words(unsigned* p, size_t n) {
     size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (i < n) p[i] = 0u;
@@ -141,6 +195,9 @@ struct GridCache {
     DevBuf<DTile> tiles[kDecodeTileSets];
     int ntiles[kDecodeTileSets] = {};
     std::vector<DTile> host_tiles[kDecodeTileSets];
+    // work units of the 16-bit GEMM per tile set
+    UnitPlan uplan[kDecodeTileSets];
+    DevUnits dunits[kDecodeTileSets];
     DevBuf<int> col_tx;              // [nx] tile column of every grid column
     DevBuf<float2> ex32, ey32;       // fp32 tables [n][halfp]
     DevBuf<uint16_t> ey_bf, ey_bf_lo, ey_h;  // 16-bit y tables [ny][2*halfp], built on first use
@@ -154,8 +211,10 @@ struct GridCache {
     DevBuf<float> region_max;                // [tiles][2]
     DevBuf<DTile> inc_tiles;
     DevBuf<RegionBox> inc_boxes;
+    DevUnits inc_dunits;
     std::vector<DTile> inc_tiles_host;
     std::vector<RegionBox> inc_boxes_host;
+    UnitPlan inc_uplan;
 };
 
 struct ProfileSlot {
@@ -273,6 +332,8 @@ struct Grid3Cache {
     DevBuf<int> col_tx;
     DevBuf<DTile> tiles[kDecodeTileSets];
     int ntiles[kDecodeTileSets] = {};
+    UnitPlan uplan[kDecodeTileSets];           // work units of the 16-bit GEMM
+    DevUnits dunits[kDecodeTileSets];
     DevBuf<float2> ex32;                       // [nx][halfp]
     int nrows = 0;                             // joint (z, y) rows = nz * ny
     DevBuf<int> row_map;                       // [nrows] voxel plane offset slice * ny + y
@@ -428,6 +489,10 @@ GridCache* grid_cache(vsaogm_map* m, const vsaogm_grid_desc* g, hipStream_t s) {
             gc->boxes[b.beta] = b;
         }
     gc->seen.assign(m->nkeys, 0u);
+    for (int set = 1; set < kDecodeTileSets; ++set) {
+        gc->uplan[set].build(gc->ntiles[set], m->halfp / 32, m->num_cus);
+        gc->dunits[set].upload(gc->uplan[set]);
+    }
     for (int set = 0; set < kDecodeTileSets; ++set)
         gc->tiles[set].alloc(gc->host_tiles[set].size(), "decode tile list");
     gc->col_tx.alloc(g->nx, "column tiles");
@@ -577,6 +642,8 @@ Grid3Cache* grid3_cache(vsaogm_volume* v, const vsaogm_grid3_desc* g, hipStream_
         gc->tiles[set].alloc(tl.size(), "volume tile list");
         hip_check(hipMemcpy(gc->tiles[set].p, tl.data(), tl.size() * sizeof(DTile), hipMemcpyHostToDevice),
                   "copy tile list");
+        gc->uplan[set].build((int)tl.size(), v->halfp / 32, v->num_cus);
+        gc->dunits[set].upload(gc->uplan[set]);
     }
     gc->col_tx.alloc(nx, "column tiles");
     hip_check(hipMemcpy(gc->col_tx.p, t[0].data(), nx * sizeof(int), hipMemcpyHostToDevice), "copy column tiles");
@@ -592,7 +659,241 @@ Grid3Cache* grid3_cache(vsaogm_volume* v, const vsaogm_grid3_desc* g, hipStream_
     return v->grid.get();
 }
 
+EncodeWork map_work(vsaogm_map* m) {
+    EncodeWork w;
+    w.key = m->w_key.p;
+    w.sorted = m->w_sorted.p;
+    w.sorted_lo = m->w_sorted_lo.p;
+    w.hist = m->w_hist.p;
+    w.table = m->w_table.p;
+    w.meta = m->w_meta.p;
+    w.partial = m->w_partial.p;
+    w.n_bad = m->d_bad.p;
+    w.version = m->d_version.p;
+    return w;
+}
+
 }  // namespace
+
+// ---- batched map updates ---------------------------------------------------------------
+// Several whole map updates (one per map) run as one launch per stage: the per-request
+// descriptors, block prefixes and the concatenated decode tile list are packed into one staging
+// block and copied to the device with one copy, then encode (assign, scan, scatter, encode,
+// reduce), norm, the similarity GEMM (+ fix-up) and the classification each cover every request.
+namespace vsaogm {
+
+struct UpdateBatchWork {
+    DevBuf<unsigned char> d_meta;
+    unsigned char* h_meta = nullptr;
+    size_t h_cap = 0;
+    DevBuf<float> d_partial;
+    ~UpdateBatchWork() {
+        if (h_meta) (void)hipHostFree(h_meta);
+    }
+};
+
+UpdateBatchWork* update_batch_work_create() { return new UpdateBatchWork(); }
+void update_batch_work_destroy(UpdateBatchWork* w) { delete w; }
+
+int run_update_batch(const UpdateItem* items, int count, int precision, hipStream_t s, UpdateBatchWork* w) {
+    return guarded([&] {
+        if (!items || count < 1 || !w) fail(VSAOGM_EINVAL, "batch: items, count >= 1 and workspace required");
+        if (precision < VSAOGM_BF16 || precision > VSAOGM_BF16X3)
+            fail(VSAOGM_EINVAL, "batch: the batched similarity runs the 16-bit formats");
+        const int device = items[0].map ? items[0].map->device : 0;
+        for (int i = 0; i < count; ++i) {
+            const UpdateItem& it = items[i];
+            if (!it.map) fail(VSAOGM_EINVAL, "batch: map is NULL");
+            if (it.map->device != device) fail(VSAOGM_EINVAL, "batch: maps on different devices");
+            for (int j = 0; j < i; ++j)
+                if (items[j].map == it.map) fail(VSAOGM_EINVAL, "batch: a map appears twice");
+            check_grid(&it.grid);
+            if (it.n < 0) fail(VSAOGM_EINVAL, "batch: n must be >= 0");
+            if (it.n > 0 && (!it.xy || !it.label)) fail(VSAOGM_EINVAL, "batch: xy and label must not be NULL");
+            if (it.n > ((int64_t)1 << 31) - (int64_t)kAssignChunk * 2) fail(VSAOGM_EINVAL, "batch: n too large");
+            if (!it.heat || !it.hmax || !it.label_out) fail(VSAOGM_EINVAL, "batch: heat, hmax and label required");
+            if (it.r_occ < 0 || it.r_emp < 0 || it.r_occ > kMaxRadius || it.r_emp > kMaxRadius)
+                fail(VSAOGM_EINVAL, "batch: radii must be in 0..24");
+            if (!is_finite(it.rho)) fail(VSAOGM_EINVAL, "batch: rho must be finite");
+        }
+        DeviceGuard guard(device);
+        const int set = decode_tile_set(precision);
+        std::vector<EncodeReq> eq(count);
+        std::vector<DecodeReq> dq(count);
+        std::vector<ClassifyReq> cq(count);
+        std::vector<DTile> tiles;
+        std::vector<DUnit> units;
+        std::vector<int> tile_u0, wg_u0;
+        int num_cus = 1, max_r = 0;
+        for (int i = 0; i < count; ++i) {
+            const UpdateItem& it = items[i];
+            vsaogm_map* m = it.map;
+            num_cus = m->num_cus;
+            if (it.n > 0) ensure_encode_workspace(m, it.n, s);
+            GridCache* gc = grid_cache(m, &it.grid, s);
+            const void* ey_lo = nullptr;
+            const void* ey = y_table(m, gc, precision, &ey_lo, s);
+            EncodeReq q = encode_req(it.xy, it.label, it.n, m->layout(), m->nkeys, m->d_rev.p, m->d_rev_d.p,
+                                     m->max_rev_x, m->max_rev_y, m->half, m->halfp, map_work(m), m->d_omega.p);
+            q.D = m->D;
+            q.scale = m->d_scale.p;
+            q.omega_s = m->d_omega_s.p;
+            q.hmax_u = m->d_hmax_u.p;
+            eq[i] = q;
+            DecodeReq& d = dq[i];
+            d.col_tx = gc->col_tx.p;
+            d.ex = gc->ex32.p;
+            d.ey = ey;
+            d.ey_lo = ey_lo;
+            d.omega_s = m->d_omega_s.p;
+            d.halfp = m->halfp;
+            d.nx = it.grid.nx;
+            d.ny = it.grid.ny;
+            d.tiles_x = m->tiles_x;
+            d.out_scale = (float)(2.0 / (double)m->D);
+            d.heat = it.heat;
+            d.class_stride = (size_t)it.grid.nx * it.grid.ny;
+            d.row_map = nullptr;
+            d.hmax_u = m->d_hmax_u.p;
+            d.ksteps = m->halfp / 32;
+            ClassifyReq& c = cq[i];
+            c.heat = it.heat;
+            c.hmax_u = m->d_hmax_u.p;
+            c.hmax_out = it.hmax;
+            c.nx = it.grid.nx;
+            c.ny = it.grid.ny;
+            c.r_occ = it.r_occ;
+            c.r_emp = it.r_emp;
+            c.rho = it.rho;
+            c.ogm = it.ogm;
+            c.label = it.label_out;
+            max_r = std::max(max_r, std::max(it.r_occ, it.r_emp));
+            // the request's own units (as vsaogm_decode runs them), renumbered into the batch
+            const int tile_base = (int)tiles.size(), unit_base = (int)units.size();
+            for (DTile t : gc->host_tiles[set]) {
+                t.pad = i;
+                tiles.push_back(t);
+            }
+            const UnitPlan& up = gc->uplan[set];
+            for (DUnit u : up.units) {
+                u.tile += tile_base;
+                units.push_back(u);
+            }
+            for (size_t t = 0; t + 1 < up.tile_u0.size(); ++t) tile_u0.push_back(up.tile_u0[t] + unit_base);
+            for (size_t g = 0; g + 1 < up.wg_u0.size(); ++g) wg_u0.push_back(up.wg_u0[g] + unit_base);
+        }
+        // encode groups by bins per thread (the encode kernel's template argument)
+        std::vector<int> order;
+        int ngroup[3] = {0, 0, 0};
+        for (int g = 1; g <= 2; ++g)
+            for (int i = 0; i < count; ++i)
+                if (eq[i].bpt == g) {
+                    order.push_back(i);
+                    ++ngroup[g];
+                }
+        if ((int)order.size() != count) fail(VSAOGM_EDEVICE, "batch: unexpected encode geometry");
+        std::vector<EncodeReq> eq_sorted(count);
+        for (int j = 0; j < count; ++j) eq_sorted[j] = eq[order[j]];
+        // block prefixes: per group [kEncodeStages][n_g + 1]; classification [count + 1]
+        std::vector<int> enc_b0;
+        EncodeBatch eb[3] = {};
+        size_t enc_b0_off[3] = {0, 0, 0};
+        int first = 0;
+        for (int g = 1; g <= 2; ++g) {
+            const int ng = ngroup[g];
+            eb[g].nreq = ng;
+            eb[g].bpt = g;
+            enc_b0_off[g] = enc_b0.size();
+            if (ng == 0) continue;
+            std::vector<int> pre((size_t)kEncodeStages * (ng + 1), 0);
+            for (int j = 0; j < ng; ++j) {
+                int b[kEncodeStages];
+                encode_batch_blocks(eq_sorted[first + j], b);
+                for (int st = 0; st < kEncodeStages; ++st) pre[(size_t)st * (ng + 1) + j + 1] = pre[(size_t)st * (ng + 1) + j] + b[st];
+                eb[g].max_keys = std::max(eb[g].max_keys, eq_sorted[first + j].nkeys);
+            }
+            for (int st = 0; st < kEncodeStages; ++st) eb[g].blocks[st] = pre[(size_t)st * (ng + 1) + ng];
+            enc_b0.insert(enc_b0.end(), pre.begin(), pre.end());
+            first += ng;
+        }
+        std::vector<int> cls_b0(count + 1, 0);
+        for (int i = 0; i < count; ++i) cls_b0[i + 1] = cls_b0[i] + classify_blocks(cq[i].nx, cq[i].ny);
+        tile_u0.push_back((int)units.size());
+        wg_u0.push_back((int)units.size());
+        const bool any_split = units.size() > tiles.size();
+        (void)num_cus;
+
+        // one staging block: encode requests, encode prefixes, decode requests, classify requests,
+        // classify prefixes, tiles, work units, first units of tiles and workgroups (each
+        // 16-byte aligned)
+        size_t off = 0;
+        auto place = [&](size_t bytes) {
+            const size_t o = off;
+            off = (off + bytes + 15) / 16 * 16;
+            return o;
+        };
+        const size_t o_eq = place(sizeof(EncodeReq) * count);
+        const size_t o_eb0 = place(sizeof(int) * enc_b0.size());
+        const size_t o_dq = place(sizeof(DecodeReq) * count);
+        const size_t o_cq = place(sizeof(ClassifyReq) * count);
+        const size_t o_cb0 = place(sizeof(int) * cls_b0.size());
+        const size_t o_t = place(sizeof(DTile) * std::max<size_t>(tiles.size(), 1));
+        const size_t o_u = place(sizeof(DUnit) * std::max<size_t>(units.size(), 1));
+        const size_t o_ti = place(sizeof(int) * tile_u0.size());
+        const size_t o_wi = place(sizeof(int) * wg_u0.size());
+        const size_t bytes = off;
+        if (w->h_cap < bytes) {
+            if (w->h_meta) (void)hipHostFree(w->h_meta);
+            w->h_meta = nullptr;
+            w->h_cap = 0;
+            size_t cap = 1 << 16;
+            while (cap < bytes) cap *= 2;
+            hip_check(hipHostMalloc((void**)&w->h_meta, cap, hipHostMallocDefault), "batch staging");
+            w->h_cap = cap;
+        }
+        if (w->d_meta.n < bytes) w->d_meta.alloc_async(std::max<size_t>(bytes, w->h_cap), s, "batch descriptors");
+        unsigned char* h = w->h_meta;
+        std::memcpy(h + o_eq, eq_sorted.data(), sizeof(EncodeReq) * count);
+        std::memcpy(h + o_eb0, enc_b0.data(), sizeof(int) * enc_b0.size());
+        std::memcpy(h + o_dq, dq.data(), sizeof(DecodeReq) * count);
+        std::memcpy(h + o_cq, cq.data(), sizeof(ClassifyReq) * count);
+        std::memcpy(h + o_cb0, cls_b0.data(), sizeof(int) * cls_b0.size());
+        if (!tiles.empty()) std::memcpy(h + o_t, tiles.data(), sizeof(DTile) * tiles.size());
+        if (!units.empty()) std::memcpy(h + o_u, units.data(), sizeof(DUnit) * units.size());
+        std::memcpy(h + o_ti, tile_u0.data(), sizeof(int) * tile_u0.size());
+        std::memcpy(h + o_wi, wg_u0.data(), sizeof(int) * wg_u0.size());
+        const size_t partial = decode_unit_partial_floats((int)units.size());
+        if (any_split && w->d_partial.n < partial) w->d_partial.alloc_async(partial, s, "batch partial sums");
+        unsigned char* dm = w->d_meta.p;
+        hip_check(hipMemcpyAsync(dm, h, bytes, hipMemcpyHostToDevice, s), "copy batch descriptors");
+        const EncodeReq* d_eq = reinterpret_cast<const EncodeReq*>(dm + o_eq);
+        int done = 0;
+        for (int g = 1; g <= 2; ++g) {
+            if (eb[g].nreq == 0) continue;
+            eb[g].reqs = d_eq + done;
+            eb[g].block0 = reinterpret_cast<const int*>(dm + o_eb0) + enc_b0_off[g];
+            hip_check(launch_encode_batch(eb[g], s), "batched encode");
+            done += eb[g].nreq;
+        }
+        DecodeBatch db;
+        db.tiles = reinterpret_cast<const DTile*>(dm + o_t);
+        db.ntiles = (int)tiles.size();
+        db.reqs = reinterpret_cast<const DecodeReq*>(dm + o_dq);
+        db.units = reinterpret_cast<const DUnit*>(dm + o_u);
+        db.nunits = (int)units.size();
+        db.tile_u0 = reinterpret_cast<const int*>(dm + o_ti);
+        db.wg_u0 = reinterpret_cast<const int*>(dm + o_wi);
+        db.nwg = (int)wg_u0.size() - 1;
+        db.partial = w->d_partial.p;
+        db.any_split = any_split;
+        hip_check(launch_decode_batch(precision, db, s), "batched decode");
+        hip_check(launch_classify_batch(reinterpret_cast<const ClassifyReq*>(dm + o_cq),
+                                        reinterpret_cast<const int*>(dm + o_cb0), count, cls_b0[count], max_r, s),
+                  "batched classify");
+    });
+}
+
+}  // namespace vsaogm
 
 extern "C" {
 
@@ -773,7 +1074,8 @@ int vsaogm_decode(vsaogm_map* m, const vsaogm_grid_desc* g, int32_t precision, f
         const int set = decode_tile_set(precision);
         DecodeLaunch d;
         d.plan = decode_plan(precision, gc->ntiles[set], m->halfp, m->num_cus);
-        const size_t need = decode_partial_floats(precision, d.plan);
+        size_t need = decode_partial_floats(precision, d.plan);
+        if (precision != VSAOGM_FP32) need = set_units(d, gc->uplan[set], gc->dunits[set], gc->ntiles[set]);
         if (m->d_partial.n < need) m->d_partial.alloc_async(need, s, "decode partial sums");
         hip_check(launch_norm(m->d_omega.p, m->nkeys, m->half, m->halfp, m->D, m->d_scale.p,
                               m->d_omega_s.p, m->d_hmax_u.p, s),
@@ -854,7 +1156,12 @@ int vsaogm_decode_incremental(vsaogm_map* m, const vsaogm_grid_desc* g, int32_t 
         if (!tl.empty()) {
             DecodeLaunch d;
             d.plan = decode_plan(precision, (int)tl.size(), m->halfp, m->num_cus);
-            const size_t need = decode_partial_floats(precision, d.plan);
+            size_t need = decode_partial_floats(precision, d.plan);
+            if (precision != VSAOGM_FP32) {
+                gc->inc_uplan.build((int)tl.size(), m->halfp / 32, m->num_cus);
+                gc->inc_dunits.upload_async(gc->inc_uplan, s);
+                need = set_units(d, gc->inc_uplan, gc->inc_dunits, (int)tl.size());
+            }
             if (m->d_partial.n < need) m->d_partial.alloc_async(need, s, "decode partial sums");
             hip_check(launch_norm(m->d_omega.p, m->nkeys, m->half, m->halfp, m->D, m->d_scale.p,
                                   m->d_omega_s.p, m->d_hmax_u.p, s),
@@ -1137,7 +1444,7 @@ int vsaogm_volume_decode(vsaogm_volume* v, const vsaogm_grid3_desc* g, int32_t p
         const int set = decode_tile_set(precision);
         DecodeLaunch d;
         d.plan = decode_plan(precision, gc->ntiles[set], v->halfp, v->num_cus);
-        const size_t need = decode_partial_floats(precision, d.plan);
+        const size_t need = set_units(d, gc->uplan[set], gc->dunits[set], gc->ntiles[set]);
         if (v->d_partial.n < need) v->d_partial.alloc_async(need, s, "decode partial sums");
         hip_check(launch_norm(v->d_omega.p, v->nkeys, v->half, v->halfp, v->D, v->d_scale.p, v->d_omega_s.p,
                               v->d_hmax_u.p, s),

@@ -1,43 +1,35 @@
 // Request server for map updates (vsaogm_server_* / vsaogm_submit / vsaogm_poll).
 //
-// Worker threads (up to four) own the device side, each a share of the execution slots.  Each
-// slot is a HIP stream with its own device and pinned host buffers; a request admitted to a
-// slot runs its whole update there:
-// one host-to-device copy of the points (staged by submit in pooled pinned memory), encode into its map (Algorithm 1), decode of its grid
+// The scheduling (tickets, per-map order, admission by device bytes and execution slots,
+// batching) is the device-free core of server_core.h; this file is its HIP executor and the C
+// ABI.  Each execution slot is a HIP stream with its own device and pinned staging buffers.  A
+// batch of admitted requests of distinct maps runs as one launch per stage (run_update_batch):
+// one host-to-device copy of all the batch's points (gathered from the pinned blocks submit
+// staged them in), encode into each map (Algorithm 1), norm and decode of each request's grid
 // (eqs. vector-normalization, loc-query), classification (Algorithm 2, eqs. softmax, psd,
-// classification) and device-to-host copies of the outputs, closed by an event.  Slots run
-// concurrently, so updates of different maps overlap on the GPU; a map is bound to at most one
-// slot at a time and its requests are admitted in submission order.  Admission is first come,
-// first served against a device-memory budget: a request that does not fit blocks the ones
-// behind it until running requests finish and release their bytes.
+// classification), one device-to-host copy of the outputs, closed by an event.  Requests with
+// the fp32 contraction or with localized decoding run alone in a slot through the map API.
+// Slots run concurrently, so batches overlap on the GPU; a map is in at most one batch at a time
+// and its requests run in submission order.  A request's results do not depend on the other
+// requests of its batch: every kernel works per request, and the similarity's work split
+// (decode_units) depends on the request alone.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <atomic>
-#include <chrono>
-#include <condition_variable>
 #include <cstring>
-#include <deque>
 #include <memory>
 #include <mutex>
 #include <stdexcept>
 #include <string>
-#include <thread>
-#include <unordered_map>
-#include <unordered_set>
 #include <vector>
 
 #include "internal.h"
+#include "server_core.h"
 #include "vsaogm.h"
 
 namespace {
 
-int64_t now_ns() {
-    return std::chrono::duration_cast<std::chrono::nanoseconds>(
-               std::chrono::steady_clock::now().time_since_epoch())
-        .count();
-}
-
+using vsaogm::CoreRequest;
 
 struct Fail : std::runtime_error {
     int code;
@@ -138,25 +130,47 @@ struct PinnedPool {
     }
 };
 
-struct Request {
-    uint64_t ticket = 0;
-    vsaogm_request r{};
-    void* in = nullptr;       // pinned [n][2] float32 points, then [n] labels
-    size_t in_cap = 0;
-    int64_t footprint = 0;
-    vsaogm_result res{};
-    bool done = false;
+// The heat a map keeps for VSAOGM_REQUEST_LOCAL requests (only its own running request uses it).
+struct LocalHeat {
+    DevMem heat;
+    vsaogm_grid_desc grid{};
 };
 
-// Output block on the device and in pinned memory: maxima, labels, map, heatmaps, each
-// 256-byte aligned; one copy brings back the prefix holding what the request asked for.
+// What the executor needs of one request: its arguments, the map (captured under the server
+// lock at submit), the staged inputs and the results handed back.
+struct Payload {
+    vsaogm_request r{};
+    vsaogm_map* map = nullptr;
+    LocalHeat* local = nullptr;
+    void* in = nullptr;       // pinned [n][2] float32 points, then [n] labels
+    size_t in_cap = 0;
+    float hmax[2] = {0.f, 0.f};
+};
+
+// Bytes a request holds while it runs: its inputs and outputs on the device plus the map's
+// working buffers for its points (sorted coordinates, keys, partial spectra) and the similarity's
+// partial sums.
+int64_t footprint_of(const vsaogm_request& r, int32_t dim, int64_t nkeys) {
+    const int64_t n = r.n, cells = (int64_t)r.grid.nx * r.grid.ny;
+    const int64_t halfp = ((int64_t)dim / 2 + 63) / 64 * 64;
+    const int64_t inputs = n * 9;
+    const int64_t outputs = cells * 13 + 8;
+    // work items hold at least 64 points, plus one partial item per memory
+    const int64_t encode_ws = n * 20 + (n / 64 + 1 + nkeys) * halfp * 8;
+    const int64_t decode_ws = (int64_t)256 * 2 * 2 * 256 * 64 * 4;  // split-tile partial sums (upper bound)
+    return inputs + outputs + encode_ws + decode_ws;
+}
+
+size_t up256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Output block of one request run alone: maxima, labels, map, heatmaps, each 256-byte aligned;
+// one copy brings back the prefix holding what the request asked for.
 struct OutLayout {
     size_t lab, ogm, heat, end_lab, end_ogm, end_heat;
     explicit OutLayout(int64_t cells) {
-        auto up = [](size_t v) { return (v + 255) / 256 * 256; };
         lab = 256;
-        ogm = up(lab + cells);
-        heat = up(ogm + cells * 4);
+        ogm = up256(lab + cells);
+        heat = up256(ogm + cells * 4);
         end_lab = lab + cells;
         end_ogm = ogm + cells * 4;
         end_heat = heat + cells * 8;
@@ -166,77 +180,112 @@ struct OutLayout {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    Request* req = nullptr;
     DevMem d_in, d_out;
-    HostMem h_out;
+    HostMem h_in, h_out;
+    vsaogm::UpdateBatchWork* work = nullptr;
+    // layout of the current batch's outputs (section-major: maxima, labels, maps, heatmaps)
+    std::vector<size_t> o_hmax, o_lab, o_ogm, o_heat;
+    size_t back = 0;
+    bool single = false;
 };
 
-// Bytes a request holds while it runs: its inputs and outputs on the device plus the map's
-// working buffers for its points (sorted coordinates, keys, partial spectra) and grid.
-int64_t footprint_of(const vsaogm_request& r, int32_t dim, int64_t nkeys) {
-    const int64_t n = r.n, cells = (int64_t)r.grid.nx * r.grid.ny;
-    const int64_t halfp = ((int64_t)dim / 2 + 63) / 64 * 64;
-    const int64_t inputs = n * 9;
-    const int64_t outputs = cells * 13 + 8;
-    // work items hold at least 64 points, plus one partial item per memory
-    const int64_t encode_ws = n * 20 + (n / 64 + 1 + nkeys) * halfp * 8;
-    const int64_t decode_ws = (int64_t)256 * 2 * 2 * 256 * 64 * 4;  // stream-K partial sums (upper bound)
-    return inputs + outputs + encode_ws + decode_ws;
-}
+class HipExecutor : public vsaogm::Executor {
+public:
+    HipExecutor(int device, int nslots, PinnedPool* pool) : device_(device), pool_(pool), slots_(nslots) {}
+    ~HipExecutor() override {
+        (void)hipSetDevice(device_);
+        for (auto& s : slots_) {
+            if (s.stream) (void)hipStreamSynchronize(s.stream);
+            if (s.work) vsaogm::update_batch_work_destroy(s.work);
+            if (s.done) (void)hipEventDestroy(s.done);
+            if (s.stream) (void)hipStreamDestroy(s.stream);
+        }
+    }
+    void init() {
+        for (auto& s : slots_) {
+            check_hip(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking), "create stream");
+            check_hip(hipEventCreateWithFlags(&s.done, hipEventDisableTiming), "create event");
+            s.work = vsaogm::update_batch_work_create();
+        }
+    }
 
-}  // namespace
+    int launch(int si, const std::vector<CoreRequest*>& batch) override {
+        thread_local int cur = -1;
+        if (cur != device_) {
+            (void)hipSetDevice(device_);
+            cur = device_;
+        }
+        Slot& s = slots_[si];
+        int rc = VSAOGM_OK;
+        try {
+            const Payload* f = static_cast<const Payload*>(batch.front()->payload);
+            const bool single = batch.size() == 1 && ((f->r.flags & VSAOGM_REQUEST_LOCAL) || f->r.precision == VSAOGM_FP32);
+            s.single = single;
+            if (single) launch_single(s, *static_cast<Payload*>(batch.front()->payload));
+            else launch_batch(s, batch);
+        } catch (const Fail& e) {
+            rc = e.code;
+        } catch (const std::exception&) {
+            rc = VSAOGM_EDEVICE;
+        }
+        // the event closes whatever was enqueued, so that completion waits for it
+        if (hipEventRecord(s.done, s.stream) != hipSuccess && rc == VSAOGM_OK) rc = VSAOGM_EDEVICE;
+        if (rc != VSAOGM_OK) (void)hipEventSynchronize(s.done);
+        return rc;
+    }
 
-struct vsaogm_server {
-    int device = 0;
-    int64_t budget = 0, used = 0, peak = 0;
-    int max_inflight = 4, max_queue = 1024;
-    std::vector<vsaogm_map*> maps;
-    std::vector<int32_t> map_dim;
-    std::vector<int64_t> map_keys;
-    std::vector<char> map_busy;
-    // heat kept per map for VSAOGM_REQUEST_LOCAL (only the map's own running request uses it)
-    struct LocalHeat {
-        DevMem heat;
-        vsaogm_grid_desc grid{};
-    };
-    std::vector<std::unique_ptr<LocalHeat>> local_heat;
-    std::deque<Request*> pending;
-    std::unordered_map<uint64_t, std::unique_ptr<Request>> tickets;
-    std::vector<Slot> slots;
-    std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    bool stop = false;
-    uint64_t next_ticket = 1;
-    int64_t completed = 0;
-    int inflight = 0;
+    int query(int si) override {
+        const hipError_t e = hipEventQuery(slots_[si].done);
+        if (e == hipErrorNotReady) return vsaogm::kCoreAgain;
+        return e == hipSuccess ? VSAOGM_OK : VSAOGM_EDEVICE;
+    }
 
-    int nworkers = 1;
-    std::vector<std::thread> workers;
-    PinnedPool pool;
+    void complete(int si, const std::vector<CoreRequest*>& batch, int status) override {
+        Slot& s = slots_[si];
+        const unsigned char* h = static_cast<const unsigned char*>(s.h_out.p);
+        for (size_t i = 0; i < batch.size(); ++i) {
+            CoreRequest* q = batch[i];
+            Payload* p = static_cast<Payload*>(q->payload);
+            if (status == VSAOGM_OK) {
+                const vsaogm_request& r = p->r;
+                const int64_t cells = (int64_t)r.grid.nx * r.grid.ny;
+                std::memcpy(p->hmax, h + s.o_hmax[i], 8);
+                if (r.label_out) std::memcpy(r.label_out, h + s.o_lab[i], cells);
+                if (r.ogm) std::memcpy(r.ogm, h + s.o_ogm[i], cells * 4);
+                if (r.heat) std::memcpy(r.heat, h + s.o_heat[i], cells * 8);
+            }
+            q->status = status;
+            q->result[0] = p->hmax[0];
+            q->result[1] = p->hmax[1];
+            release(q);
+        }
+    }
 
-    void run(int w);
-    void launch(Slot& s, int slot_index);
-    void finish(Slot& s);
-};
+    void release(CoreRequest* q) override {
+        Payload* p = static_cast<Payload*>(q->payload);
+        if (!p) return;
+        if (p->in) pool_->put(p->in, p->in_cap);
+        delete p;
+        q->payload = nullptr;
+    }
 
-void vsaogm_server::launch(Slot& s, int slot_index) {
-    Request* q = s.req;
-    const vsaogm_request& r = q->r;
-    q->res.slot = slot_index;
-    q->res.t_start_ns = now_ns();
-    int rc = VSAOGM_OK;
-    try {
+private:
+    void launch_single(Slot& s, Payload& p) {
+        const vsaogm_request& r = p.r;
         const int64_t n = r.n, cells = (int64_t)r.grid.nx * r.grid.ny;
         const OutLayout L(cells);
-        const size_t back = r.heat ? L.end_heat : (r.ogm ? L.end_ogm : (r.label_out ? L.end_lab : 8));
+        s.back = r.heat ? L.end_heat : (r.ogm ? L.end_ogm : (r.label_out ? L.end_lab : 8));
+        s.o_hmax.assign(1, 0);
+        s.o_lab.assign(1, L.lab);
+        s.o_ogm.assign(1, L.ogm);
+        s.o_heat.assign(1, L.heat);
         s.d_in.ensure(std::max<int64_t>(n, 1) * 9, s.stream, "slot inputs");
         s.d_out.ensure(L.end_heat, s.stream, "slot outputs");
-        s.h_out.ensure(back, "slot pinned outputs");
+        s.h_out.ensure(s.back, "slot pinned outputs");
         unsigned char* din = static_cast<unsigned char*>(s.d_in.p);
         unsigned char* dout = static_cast<unsigned char*>(s.d_out.p);
-        if (n > 0)
-            check_hip(hipMemcpyAsync(din, q->in, n * 9, hipMemcpyHostToDevice, s.stream), "copy inputs");
-        vsaogm_map* m = maps[r.map_id];
+        if (n > 0) check_hip(hipMemcpyAsync(din, p.in, n * 9, hipMemcpyHostToDevice, s.stream), "copy inputs");
+        vsaogm_map* m = p.map;
         auto call = [&](int code) {
             if (code != VSAOGM_OK) throw Fail(code, vsaogm_last_error());
         };
@@ -244,7 +293,7 @@ void vsaogm_server::launch(Slot& s, int slot_index) {
         float* heat = reinterpret_cast<float*>(dout + L.heat);
         call(vsaogm_encode(m, reinterpret_cast<float*>(din), din + n * 8, n, s.stream));
         if (r.flags & VSAOGM_REQUEST_LOCAL) {
-            LocalHeat& lh = *local_heat[r.map_id];
+            LocalHeat& lh = *p.local;
             const bool same = lh.heat.p && lh.grid.nx == r.grid.nx && lh.grid.ny == r.grid.ny &&
                               lh.grid.x0 == r.grid.x0 && lh.grid.y0 == r.grid.y0 && lh.grid.res == r.grid.res;
             if (!same) {
@@ -264,103 +313,167 @@ void vsaogm_server::launch(Slot& s, int slot_index) {
         } else {
             call(vsaogm_decode(m, &r.grid, r.precision, heat, hmax, s.stream));
         }
-        call(vsaogm_classify(&r.grid, heat, hmax, r.r_occ, r.r_emp, r.rho,
-                             reinterpret_cast<float*>(dout + L.ogm), dout + L.lab, device, s.stream));
-        check_hip(hipMemcpyAsync(s.h_out.p, dout, back, hipMemcpyDeviceToHost, s.stream), "copy outputs");
-    } catch (const Fail& e) {
-        rc = e.code;
-    } catch (const std::exception&) {
-        rc = VSAOGM_EDEVICE;
+        call(vsaogm_classify(&r.grid, heat, hmax, r.r_occ, r.r_emp, r.rho, reinterpret_cast<float*>(dout + L.ogm),
+                             dout + L.lab, device_, s.stream));
+        check_hip(hipMemcpyAsync(s.h_out.p, dout, s.back, hipMemcpyDeviceToHost, s.stream), "copy outputs");
     }
-    q->res.status = rc;
-    if (hipEventRecord(s.done, s.stream) != hipSuccess && q->res.status == VSAOGM_OK)
-        q->res.status = VSAOGM_EDEVICE;
+
+    void launch_batch(Slot& s, const std::vector<CoreRequest*>& batch) {
+        const size_t count = batch.size();
+        // inputs: per request [n][2] points then [n] labels, 256-byte aligned
+        std::vector<size_t> o_in(count);
+        size_t in_bytes = 0;
+        bool want_lab = false, want_ogm = false, want_heat = false;
+        size_t cells_total = 0;
+        for (size_t i = 0; i < count; ++i) {
+            const Payload* p = static_cast<const Payload*>(batch[i]->payload);
+            o_in[i] = in_bytes;
+            in_bytes += up256((size_t)p->r.n * 9);
+            want_lab = want_lab || p->r.label_out;
+            want_ogm = want_ogm || p->r.ogm;
+            want_heat = want_heat || p->r.heat;
+            cells_total += (size_t)p->r.grid.nx * p->r.grid.ny;
+        }
+        // outputs, section-major so that one copy brings back what any request asked for
+        s.o_hmax.resize(count);
+        s.o_lab.resize(count);
+        s.o_ogm.resize(count);
+        s.o_heat.resize(count);
+        size_t o = 0;
+        for (size_t i = 0; i < count; ++i) s.o_hmax[i] = o, o += 16;
+        o = up256(o);
+        for (size_t i = 0; i < count; ++i) {
+            const Payload* p = static_cast<const Payload*>(batch[i]->payload);
+            s.o_lab[i] = o;
+            o = up256(o + (size_t)p->r.grid.nx * p->r.grid.ny);
+        }
+        const size_t end_lab = o;
+        for (size_t i = 0; i < count; ++i) {
+            const Payload* p = static_cast<const Payload*>(batch[i]->payload);
+            s.o_ogm[i] = o;
+            o = up256(o + (size_t)p->r.grid.nx * p->r.grid.ny * 4);
+        }
+        const size_t end_ogm = o;
+        for (size_t i = 0; i < count; ++i) {
+            const Payload* p = static_cast<const Payload*>(batch[i]->payload);
+            s.o_heat[i] = o;
+            o = up256(o + (size_t)p->r.grid.nx * p->r.grid.ny * 8);
+        }
+        const size_t end_heat = o;
+        (void)cells_total;
+        s.back = want_heat ? end_heat : (want_ogm ? end_ogm : (want_lab ? end_lab : 16 * count));
+        s.d_in.ensure(std::max<size_t>(in_bytes, 256), s.stream, "batch inputs");
+        s.d_out.ensure(end_heat, s.stream, "batch outputs");
+        s.h_in.ensure(std::max<size_t>(in_bytes, 256), "batch pinned inputs");
+        s.h_out.ensure(s.back, "batch pinned outputs");
+        unsigned char* hin = static_cast<unsigned char*>(s.h_in.p);
+        unsigned char* din = static_cast<unsigned char*>(s.d_in.p);
+        unsigned char* dout = static_cast<unsigned char*>(s.d_out.p);
+        std::vector<vsaogm::UpdateItem> items(count);
+        int precision = VSAOGM_BF16X3;
+        for (size_t i = 0; i < count; ++i) {
+            const Payload* p = static_cast<const Payload*>(batch[i]->payload);
+            const vsaogm_request& r = p->r;
+            if (r.n > 0) std::memcpy(hin + o_in[i], p->in, (size_t)r.n * 9);
+            vsaogm::UpdateItem& it = items[i];
+            it.map = p->map;
+            it.xy = reinterpret_cast<const float*>(din + o_in[i]);
+            it.label = din + o_in[i] + (size_t)r.n * 8;
+            it.n = r.n;
+            it.grid = r.grid;
+            it.r_occ = r.r_occ;
+            it.r_emp = r.r_emp;
+            it.rho = r.rho;
+            it.heat = reinterpret_cast<float*>(dout + s.o_heat[i]);
+            it.hmax = reinterpret_cast<float*>(dout + s.o_hmax[i]);
+            it.ogm = want_ogm ? reinterpret_cast<float*>(dout + s.o_ogm[i]) : nullptr;
+            it.label_out = dout + s.o_lab[i];
+            precision = r.precision;
+        }
+        if (in_bytes > 0) check_hip(hipMemcpyAsync(din, hin, in_bytes, hipMemcpyHostToDevice, s.stream), "copy inputs");
+        const int rc = vsaogm::run_update_batch(items.data(), (int)count, precision, s.stream, s.work);
+        if (rc != VSAOGM_OK) throw Fail(rc, vsaogm_last_error());
+        check_hip(hipMemcpyAsync(s.h_out.p, dout, s.back, hipMemcpyDeviceToHost, s.stream), "copy outputs");
+    }
+
+    int device_;
+    PinnedPool* pool_;
+    std::vector<Slot> slots_;
+};
+
+}  // namespace
+
+struct vsaogm_server {
+    int device = 0;
+    int64_t budget = 0;
+    std::mutex mu;                          // guards the map tables below
+    std::vector<vsaogm_map*> maps;
+    std::vector<int32_t> map_dim;
+    std::vector<int64_t> map_keys;
+    std::vector<std::unique_ptr<LocalHeat>> local_heat;
+    PinnedPool pool;
+    std::unique_ptr<HipExecutor> exec;
+    std::unique_ptr<vsaogm::Scheduler> sched;
+};
+
+namespace {
+
+// Requests one batch takes when the descriptor does not say (distinct maps, one precision).
+constexpr int kMaxDefaultBatch = 8;
+
+// Validate one request and stage its inputs in pinned memory.
+std::unique_ptr<CoreRequest> prepare(vsaogm_server* s, const vsaogm_request* r) {
+    if (!r) throw Fail(VSAOGM_EINVAL, "request must not be NULL");
+    if (r->n < 0) throw Fail(VSAOGM_EINVAL, "n must be >= 0");
+    if (r->n > 0 && (!r->xy || !r->label)) throw Fail(VSAOGM_EINVAL, "xy and label must not be NULL");
+    if (r->grid.nx < 1 || r->grid.ny < 1 || !(r->grid.res > 0)) throw Fail(VSAOGM_EINVAL, "invalid grid");
+    if (r->precision < VSAOGM_FP32 || r->precision > VSAOGM_BF16X3) throw Fail(VSAOGM_EINVAL, "unknown precision");
+    if (r->r_occ < 0 || r->r_emp < 0 || r->r_occ > 24 || r->r_emp > 24)
+        throw Fail(VSAOGM_EINVAL, "disk radii must be in 0..24");
+    auto p = std::make_unique<Payload>();
+    p->r = *r;
+    auto q = std::make_unique<CoreRequest>();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (r->map_id < 0 || r->map_id >= (int32_t)s->maps.size()) throw Fail(VSAOGM_ENOTFOUND, "unknown map");
+        p->map = s->maps[r->map_id];
+        p->local = s->local_heat[r->map_id].get();
+        q->bytes = footprint_of(*r, s->map_dim[r->map_id], s->map_keys[r->map_id]);
+    }
+    if (q->bytes > s->budget) throw Fail(VSAOGM_EINVAL, "request exceeds the memory budget");
+    q->map = r->map_id;
+    q->precision = r->precision;
+    q->batchable = r->precision != VSAOGM_FP32 && !(r->flags & VSAOGM_REQUEST_LOCAL);
+    if (r->n > 0) {
+        auto blk = s->pool.get((size_t)r->n * 9);
+        p->in = blk.first;
+        p->in_cap = blk.second;
+        std::memcpy(p->in, r->xy, (size_t)r->n * 8);
+        std::memcpy(static_cast<unsigned char*>(p->in) + r->n * 8, r->label, (size_t)r->n);
+    }
+    p->r.xy = nullptr;
+    p->r.label = nullptr;
+    q->payload = p.release();
+    return q;
 }
 
-void vsaogm_server::finish(Slot& s) {
-    Request* q = s.req;
-    const vsaogm_request& r = q->r;
-    if (q->res.status == VSAOGM_OK) {
-        const int64_t cells = (int64_t)r.grid.nx * r.grid.ny;
-        const OutLayout L(cells);
-        const unsigned char* h = static_cast<const unsigned char*>(s.h_out.p);
-        std::memcpy(q->res.hmax, h, 8);
-        if (r.label_out) std::memcpy(r.label_out, h + L.lab, cells);
-        if (r.ogm) std::memcpy(r.ogm, h + L.ogm, cells * 4);
-        if (r.heat) std::memcpy(r.heat, h + L.heat, cells * 8);
-    }
-    if (q->in) pool.put(q->in, q->in_cap);
-    q->in = nullptr;
-    q->res.t_done_ns = now_ns();
+void drop(vsaogm_server* s, std::unique_ptr<CoreRequest>& q) {
+    if (q && q->payload) s->exec->release(q.get());
 }
 
-void vsaogm_server::run(int w) {
-    (void)hipSetDevice(device);
-    std::vector<int> free_slots;
-    for (int i = (int)slots.size() - 1; i >= 0; --i)
-        if (i % nworkers == w) free_slots.push_back(i);
-    for (;;) {
-        bool progressed = false;
-        // completions of this worker's slots
-        for (int i = w; i < (int)slots.size(); i += nworkers) {
-            Slot& s = slots[i];
-            if (!s.req) continue;
-            const hipError_t e = hipEventQuery(s.done);
-            if (e == hipErrorNotReady) continue;
-            if (e != hipSuccess && s.req->res.status == VSAOGM_OK) s.req->res.status = VSAOGM_EDEVICE;
-            finish(s);
-            {
-                std::lock_guard<std::mutex> lk(mu);
-                used -= s.req->footprint;
-                map_busy[s.req->r.map_id] = 0;
-                s.req->done = true;
-                ++completed;
-                --inflight;
-            }
-            cv_done.notify_all();
-            cv_work.notify_all();  // a map or budget freed up for the other workers
-            s.req = nullptr;
-            free_slots.push_back(i);
-            progressed = true;
-        }
-        // admissions, first come first served: a request whose map is busy waits (and so do
-        // later requests of that map); a request that does not fit the budget stops admission
-        std::vector<std::pair<int, Request*>> to_launch;
-        {
-            std::unique_lock<std::mutex> lk(mu);
-            if (stop && pending.empty() && inflight == 0) break;
-            std::unordered_set<int32_t> blocked;
-            for (auto it = pending.begin(); it != pending.end() && !free_slots.empty();) {
-                Request* q = *it;
-                const int32_t mid = q->r.map_id;
-                if (map_busy[mid] || blocked.count(mid)) {
-                    blocked.insert(mid);
-                    ++it;
-                    continue;
-                }
-                if (used + q->footprint > budget) break;
-                used += q->footprint;
-                peak = std::max(peak, used);
-                map_busy[mid] = 1;
-                ++inflight;
-                const int si = free_slots.back();
-                free_slots.pop_back();
-                slots[si].req = q;
-                to_launch.emplace_back(si, q);
-                it = pending.erase(it);
-            }
-            if (to_launch.empty() && !progressed) {
-                // nothing to do right now: sleep until a submit or a completion, or a short
-                // timeout while this worker's slots run (they are polled every 20 us)
-                bool mine = false;
-                for (int i = w; i < (int)slots.size(); i += nworkers) mine = mine || slots[i].req;
-                cv_work.wait_for(lk, std::chrono::microseconds(mine ? 20 : 2000));
-                continue;
-            }
-        }
-        for (auto& [si, q] : to_launch) launch(slots[si], si);
-    }
+vsaogm_result to_result(const CoreRequest& q) {
+    vsaogm_result r{};
+    r.status = q.status;
+    r.slot = q.slot;
+    r.t_submit_ns = q.t_submit_ns;
+    r.t_start_ns = q.t_start_ns;
+    r.t_done_ns = q.t_done_ns;
+    r.hmax[0] = q.result[0];
+    r.hmax[1] = q.result[1];
+    return r;
 }
+
+}  // namespace
 
 extern "C" {
 
@@ -370,28 +483,29 @@ int vsaogm_server_create(const vsaogm_server_desc* d, vsaogm_server** out) {
         *out = nullptr;
         if (d->max_inflight < 1 || d->max_inflight > 32) throw Fail(VSAOGM_EINVAL, "max_inflight must be 1..32");
         if (d->max_queue < 1) throw Fail(VSAOGM_EINVAL, "max_queue must be >= 1");
+        if (d->max_batch > 64) throw Fail(VSAOGM_EINVAL, "max_batch must be <= 64");
         int ndev = 0;
         check_hip(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
         if (d->device < 0 || d->device >= ndev) throw Fail(VSAOGM_EINVAL, "no such device");
         check_hip(hipSetDevice(d->device), "hipSetDevice");
         auto s = std::make_unique<vsaogm_server>();
         s->device = d->device;
-        s->max_inflight = d->max_inflight;
-        s->max_queue = d->max_queue;
         s->budget = d->hbm_budget_bytes;
         if (s->budget <= 0) {
             size_t free_b = 0, total_b = 0;
             check_hip(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
             s->budget = (int64_t)(free_b / 4);
         }
-        s->slots.resize(d->max_inflight);
-        for (auto& sl : s->slots) {
-            check_hip(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking), "create stream");
-            check_hip(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming), "create event");
-        }
-        vsaogm_server* raw = s.get();
-        raw->nworkers = std::min(d->max_inflight, 4);
-        for (int w = 0; w < raw->nworkers; ++w) raw->workers.emplace_back([raw, w] { raw->run(w); });
+        s->exec = std::make_unique<HipExecutor>(d->device, d->max_inflight, &s->pool);
+        s->exec->init();
+        vsaogm::SchedulerConfig cfg;
+        cfg.slots = d->max_inflight;
+        cfg.max_queue = d->max_queue;
+        cfg.max_batch = d->max_batch > 0 ? d->max_batch : kMaxDefaultBatch;
+        cfg.workers = std::min(d->max_inflight, 4);
+        cfg.budget = s->budget;
+        s->sched = std::make_unique<vsaogm::Scheduler>(cfg, s->exec.get());
+        s->sched->start();
         *out = s.release();
     });
 }
@@ -399,22 +513,11 @@ int vsaogm_server_create(const vsaogm_server_desc* d, vsaogm_server** out) {
 int vsaogm_server_destroy(vsaogm_server* s) {
     if (!s) return VSAOGM_OK;
     return guard([&] {
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->stop = true;
-        }
-        s->cv_work.notify_all();
-        for (auto& t : s->workers)
-            if (t.joinable()) t.join();
+        s->sched->stop();
+        s->sched.reset();
         (void)hipSetDevice(s->device);
-        for (auto& sl : s->slots) {
-            if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-        }
+        s->exec.reset();
         for (auto* m : s->maps) vsaogm_map_destroy(m);
-        for (auto& sl : s->slots) {
-            if (sl.done) (void)hipEventDestroy(sl.done);
-            if (sl.stream) (void)hipStreamDestroy(sl.stream);
-        }
         delete s;
     });
 }
@@ -431,9 +534,10 @@ int vsaogm_server_add_map(vsaogm_server* s, const vsaogm_map_desc* d, int32_t* m
         s->maps.push_back(m);
         s->map_dim.push_back(dd.dim);
         s->map_keys.push_back(2 * (int64_t)dd.tiles_x * dd.tiles_y);
-        s->map_busy.push_back(0);
-        s->local_heat.push_back(std::make_unique<vsaogm_server::LocalHeat>());
+        s->local_heat.push_back(std::make_unique<LocalHeat>());
+        const int id = s->sched->add_map();
         *map_id = (int32_t)s->maps.size() - 1;
+        if (id != *map_id) throw Fail(VSAOGM_EDEVICE, "map tables out of step");
     });
 }
 
@@ -446,80 +550,25 @@ int vsaogm_server_get_map(vsaogm_server* s, int32_t map_id, vsaogm_map** out) {
     });
 }
 
-}  // extern "C"
-
-namespace {
-
-// Validate one request and stage its inputs in pinned memory (no server lock held).
-std::unique_ptr<Request> prepare(vsaogm_server* s, const vsaogm_request* r) {
-    if (!r) throw Fail(VSAOGM_EINVAL, "request must not be NULL");
-    if (r->n < 0) throw Fail(VSAOGM_EINVAL, "n must be >= 0");
-    if (r->n > 0 && (!r->xy || !r->label)) throw Fail(VSAOGM_EINVAL, "xy and label must not be NULL");
-    if (r->grid.nx < 1 || r->grid.ny < 1 || !(r->grid.res > 0)) throw Fail(VSAOGM_EINVAL, "invalid grid");
-    if (r->precision < VSAOGM_FP32 || r->precision > VSAOGM_BF16X3) throw Fail(VSAOGM_EINVAL, "unknown precision");
-    if (r->r_occ < 0 || r->r_emp < 0 || r->r_occ > 24 || r->r_emp > 24)
-        throw Fail(VSAOGM_EINVAL, "disk radii must be in 0..24");
-    auto q = std::make_unique<Request>();
-    q->r = *r;
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        if (r->map_id < 0 || r->map_id >= (int32_t)s->maps.size()) throw Fail(VSAOGM_ENOTFOUND, "unknown map");
-        q->footprint = footprint_of(*r, s->map_dim[r->map_id], s->map_keys[r->map_id]);
-    }
-    if (q->footprint > s->budget) throw Fail(VSAOGM_EINVAL, "request exceeds the memory budget");
-    if (r->n > 0) {
-        auto blk = s->pool.get((size_t)r->n * 9);
-        q->in = blk.first;
-        q->in_cap = blk.second;
-        std::memcpy(q->in, r->xy, (size_t)r->n * 8);
-        std::memcpy(static_cast<unsigned char*>(q->in) + r->n * 8, r->label, (size_t)r->n);
-    }
-    q->r.xy = nullptr;
-    q->r.label = nullptr;
-    q->res.status = VSAOGM_EAGAIN;
-    q->res.slot = -1;
-    return q;
-}
-
-// Queue a prepared request (server lock held); false when the queue is full.
-bool enqueue_locked(vsaogm_server* s, std::unique_ptr<Request>& q, uint64_t* ticket) {
-    if ((int)s->pending.size() >= s->max_queue) return false;
-    q->ticket = s->next_ticket++;
-    q->res.t_submit_ns = now_ns();
-    *ticket = q->ticket;
-    s->pending.push_back(q.get());
-    s->tickets.emplace(q->ticket, std::move(q));
-    return true;
-}
-
-}  // namespace
-
-extern "C" {
-
 int vsaogm_submit(vsaogm_server* s, const vsaogm_request* r, uint64_t* ticket) {
     return guard([&] {
         if (!s || !r || !ticket) throw Fail(VSAOGM_EINVAL, "server, request and ticket must not be NULL");
         auto q = prepare(s, r);
-        bool ok;
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            ok = enqueue_locked(s, q, ticket);
+        const int rc = s->sched->submit(q, ticket);
+        if (rc != VSAOGM_OK) {
+            drop(s, q);
+            throw Fail(rc, rc == VSAOGM_EBUSY ? "queue full" : "request refused");
         }
-        if (!ok) {
-            if (q->in) s->pool.put(q->in, q->in_cap);
-            throw Fail(VSAOGM_EBUSY, "queue full");
-        }
-        s->cv_work.notify_all();
     });
 }
 
 int vsaogm_submit_many(vsaogm_server* s, const vsaogm_request* reqs, int32_t count, uint64_t* tickets,
                        int32_t* n_queued) {
-    int32_t queued = 0;
+    int queued = 0;
     const int rc = guard([&] {
         if (!s || (!reqs && count > 0) || (!tickets && count > 0))
             throw Fail(VSAOGM_EINVAL, "server, requests and tickets must not be NULL");
-        std::vector<std::unique_ptr<Request>> qs;
+        std::vector<std::unique_ptr<CoreRequest>> qs;
         qs.reserve(count > 0 ? count : 0);
         int err = VSAOGM_OK;
         std::string msg;
@@ -532,67 +581,44 @@ int vsaogm_submit_many(vsaogm_server* s, const vsaogm_request* reqs, int32_t cou
                 break;
             }
         }
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            for (auto& q : qs) {
-                if (!enqueue_locked(s, q, tickets + queued)) {
-                    err = VSAOGM_EBUSY;
-                    msg = "queue full";
-                    break;
-                }
-                ++queued;
-            }
-        }
-        for (auto& q : qs)
-            if (q && q->in) s->pool.put(q->in, q->in_cap);  // the ones not queued
-        if (queued) s->cv_work.notify_all();
+        std::vector<std::unique_ptr<CoreRequest>*> ptrs;
+        for (auto& q : qs) ptrs.push_back(&q);
+        const int rc2 = s->sched->submit_many(ptrs, tickets, &queued);
+        for (auto& q : qs) drop(s, q);   // the ones not queued (queued ones were moved out)
+        if (rc2 != VSAOGM_OK) throw Fail(rc2, rc2 == VSAOGM_EBUSY ? "queue full" : "request refused");
         if (err != VSAOGM_OK) throw Fail(err, msg);
     });
     if (n_queued) *n_queued = queued;
     return rc;
 }
 
-static int poll_locked(vsaogm_server* s, uint64_t ticket, vsaogm_result* out) {
-    auto it = s->tickets.find(ticket);
-    if (it == s->tickets.end()) {
-        vsaogm::set_last_error("unknown or retired ticket");
-        return VSAOGM_ENOTFOUND;
-    }
-    if (!it->second->done) return VSAOGM_EAGAIN;
-    if (out) *out = it->second->res;
-    s->tickets.erase(it);
-    return VSAOGM_OK;
-}
-
 int vsaogm_poll(vsaogm_server* s, uint64_t ticket, vsaogm_result* out) {
     if (!s) return VSAOGM_EINVAL;
-    std::lock_guard<std::mutex> lk(s->mu);
-    return poll_locked(s, ticket, out);
+    CoreRequest q;
+    const int rc = s->sched->poll(ticket, &q);
+    if (rc == VSAOGM_OK && out) *out = to_result(q);
+    if (rc == VSAOGM_ENOTFOUND) vsaogm::set_last_error("unknown or retired ticket");
+    return rc;
 }
 
 int vsaogm_wait(vsaogm_server* s, uint64_t ticket, vsaogm_result* out) {
     if (!s) return VSAOGM_EINVAL;
-    std::unique_lock<std::mutex> lk(s->mu);
-    for (;;) {
-        const int rc = poll_locked(s, ticket, out);
-        if (rc != VSAOGM_EAGAIN) return rc;
-        s->cv_done.wait(lk);
-    }
+    CoreRequest q;
+    const int rc = s->sched->wait(ticket, &q);
+    if (rc == VSAOGM_OK && out) *out = to_result(q);
+    if (rc == VSAOGM_ENOTFOUND) vsaogm::set_last_error("unknown or retired ticket");
+    return rc;
 }
 
 int vsaogm_server_drain(vsaogm_server* s) {
     if (!s) return VSAOGM_EINVAL;
-    std::unique_lock<std::mutex> lk(s->mu);
-    s->cv_done.wait(lk, [&] { return s->pending.empty() && s->inflight == 0; });
+    s->sched->drain();
     return VSAOGM_OK;
 }
 
 int vsaogm_server_stats(vsaogm_server* s, int64_t* completed, int64_t* peak_bytes, int64_t* budget_bytes) {
     if (!s) return VSAOGM_EINVAL;
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (completed) *completed = s->completed;
-    if (peak_bytes) *peak_bytes = s->peak;
-    if (budget_bytes) *budget_bytes = s->budget;
+    s->sched->stats(completed, peak_bytes, budget_bytes, nullptr);
     return VSAOGM_OK;
 }
 

@@ -68,7 +68,7 @@ class Grid3Desc(ctypes.Structure):
 
 class ServerDesc(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
-                ("max_queue", ctypes.c_int32), ("device", ctypes.c_int32)]
+                ("max_queue", ctypes.c_int32), ("device", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -399,9 +399,9 @@ class Server:
     """The request loop of the C ABI: submit map updates, poll for their results."""
 
     def __init__(self, device: int = 0, max_inflight: int = 4, max_queue: int = 1024,
-                 hbm_budget_bytes: int = 0):
+                 hbm_budget_bytes: int = 0, max_batch: int = 0):
         L = load()
-        d = ServerDesc(int(hbm_budget_bytes), int(max_inflight), int(max_queue), int(device))
+        d = ServerDesc(int(hbm_budget_bytes), int(max_inflight), int(max_queue), int(device), int(max_batch))
         h = ctypes.c_void_p()
         check(L.vsaogm_server_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
