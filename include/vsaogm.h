@@ -166,7 +166,10 @@ int vsaogm_decode(vsaogm_map* map, const vsaogm_grid_desc* grid, int32_t precisi
  * decodes every cell.  hmax is the maximum over all cells (the map keeps per-tile maxima).
  * A recomputed cell equals vsaogm_decode's value up to the order of the fp32 accumulation
  * (the reduction over frequencies is split among workgroups by the number of tiles decoded).
- * Synchronises the stream once, to read which memories changed.  Errors as vsaogm_decode.
+ * Asynchronous: which memories changed, the tiles to recompute and the split of their work
+ * are found by a kernel on the stream (memory versions on the device), so the host never
+ * waits; only the first call for a grid synchronises once, as vsaogm_decode does.  Errors as
+ * vsaogm_decode.
  */
 int vsaogm_decode_incremental(vsaogm_map* map, const vsaogm_grid_desc* grid, int32_t precision,
                               float* heat, float* hmax, vsaogm_stream stream);

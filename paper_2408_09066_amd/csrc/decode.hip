@@ -179,7 +179,19 @@ struct DecodeArgs {
     // Batched launches (16-bit kernels): tiles of several requests, tile t belonging to request
     // reqs[t.pad], whose fields replace the per-request ones above.  Null for one request.
     const DecodeReq* reqs;
+    // Localized decode: [0] tiles, [1] 16-bit workgroups, [3] fp32 steps per workgroup, written
+    // on the device by the plan kernel (the grids are upper bounds).  Null: the fields above.
+    const int* dyn;
 };
+
+// Launch width and logical index of this workgroup when the real workgroup count n comes from
+// the device: the first round_up(n, kXcds) workgroups are spread over the XCDs as usual, the
+// rest of the (upper-bound) grid leaves at once (returns -1).
+__device__ inline int dyn_wg_index(int n) {
+    const int n8 = (n + kXcds - 1) / kXcds * kXcds;
+    if ((int)blockIdx.x >= n8) return -1;
+    return xcd_local_index(blockIdx.x, n8);
+}
 
 // The per-request view of a batched launch for tile t (unchanged for a single request).
 __device__ inline void apply_request(DecodeArgs& r, const DTile& t) {
@@ -257,9 +269,18 @@ __global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeAr
     // Workgroups are dispatched round-robin over the XCDs; give each XCD a contiguous share of
     // the iteration space, so that its resident workgroups work on neighbouring tiles (the
     // same row group of a band) and share those rows' table lines in the XCD's L2.
-    const int wg = xcd_local_index(blockIdx.x, gridDim.x);
-    const long long it0 = (long long)wg * a.steps_per_wg;
-    const long long it1 = min(it0 + a.steps_per_wg, a.total_steps);
+    long long steps_per_wg = a.steps_per_wg, total_steps = a.total_steps;
+    int wg;
+    if (a.dyn) {
+        steps_per_wg = a.dyn[3];
+        total_steps = (long long)a.dyn[0] * a.ksteps;
+        wg = dyn_wg_index((int)((total_steps + steps_per_wg - 1) / steps_per_wg));
+        if (wg < 0) return;
+    } else {
+        wg = xcd_local_index(blockIdx.x, gridDim.x);
+    }
+    const long long it0 = (long long)wg * steps_per_wg;
+    const long long it1 = min(it0 + steps_per_wg, total_steps);
     const int first_tile = (int)(it0 / a.ksteps);
 
     // A: 128-byte rows, 8 units of 16 bytes; B: 64 columns x KB complex, units of 2 complex
@@ -534,8 +555,8 @@ __global__ __launch_bounds__(Wide<PREC>::NT, Wide<PREC>::OCC) void k_decode16(De
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, l32 = lane & 31;
-    const int wg = xcd_local_index(blockIdx.x, gridDim.x);
-    if (wg >= ab.nwg) return;   // grid padding (uniform over the workgroup)
+    const int wg = ab.dyn ? dyn_wg_index(ab.dyn[1]) : xcd_local_index(blockIdx.x, gridDim.x);
+    if (wg < 0 || wg >= (ab.dyn ? ab.dyn[1] : ab.nwg)) return;   // grid padding (uniform over the workgroup)
     const int u_end = ab.wg_u0[wg + 1];
     for (int ui = ab.wg_u0[wg]; ui < u_end; ++ui) {
         const DUnit unit = ab.units[ui];
@@ -746,6 +767,8 @@ __global__ __launch_bounds__(256) void k_decode_fix(DecodeArgs ab) {
     using X = Fix<TR>;
     constexpr int PER_TILE = X::PER_TILE, PARTS = X::PARTS, PER = X::PER;
     const int ti = blockIdx.x / PARTS, partk = blockIdx.x % PARTS;
+    if (ti >= (ab.dyn ? ab.dyn[0] : ab.ntiles)) return;   // localized decode: fewer tiles than the grid
+    const long long steps_per_wg = ab.dyn ? ab.dyn[3] : ab.steps_per_wg;
     // segments of the tile: its work units (16-bit kernels, one partial block per unit), or the
     // workgroups whose stream-K ranges cover it (fp32 kernel, two partial blocks per workgroup)
     int w_first, w_last;
@@ -754,8 +777,8 @@ __global__ __launch_bounds__(256) void k_decode_fix(DecodeArgs ab) {
         w_last = ab.tile_u0[ti + 1] - 1;
     } else {
         const long long t0 = (long long)ti * ab.ksteps;
-        w_first = (int)(t0 / ab.steps_per_wg);
-        w_last = (int)((t0 + ab.ksteps - 1) / ab.steps_per_wg);
+        w_first = (int)(t0 / steps_per_wg);
+        w_last = (int)((t0 + ab.ksteps - 1) / steps_per_wg);
     }
     if (w_first >= w_last) return;  // whole tile, stored by the GEMM
     const DTile t = ab.tiles[ti];
@@ -768,7 +791,7 @@ __global__ __launch_bounds__(256) void k_decode_fix(DecodeArgs ab) {
     // (a segment past the last one reloads the last and adds nothing)
     auto seg = [&](int w) {
         if (ab.units) return as_global(a.partial + (size_t)w * PER_TILE + partk * (PER_TILE / PARTS));
-        const int slot = ((long long)w * ab.steps_per_wg / ab.ksteps == ti) ? 0 : 1;
+        const int slot = ((long long)w * steps_per_wg / ab.ksteps == ti) ? 0 : 1;
         return as_global(a.partial + ((size_t)w * 2 + slot) * PER_TILE + partk * (PER_TILE / PARTS));
     };
     for (int w = w_first; w <= w_last; w += 4) {
@@ -816,7 +839,9 @@ __global__ __launch_bounds__(256) void k_decode_fix(DecodeArgs ab) {
 // One block per listed region: maxima of both classes over the region's cells.
 __global__ __launch_bounds__(256) void k_region_max(const float* __restrict__ heat, int nx, int ny,
                                                     const RegionBox* __restrict__ boxes,
+                                                    const int* __restrict__ nboxes_dev,
                                                     float* __restrict__ region_max) {
+    if (nboxes_dev && (int)blockIdx.x >= *nboxes_dev) return;
     const RegionBox b = boxes[blockIdx.x];
     const int w = b.col1 - b.col0, h = b.row1 - b.row0;
     float mx[2] = {-INFINITY, -INFINITY};
@@ -920,13 +945,23 @@ size_t decode_partial_floats(int precision, const DecodePlan& p) {
 hipError_t launch_region_max(const float* heat, int nx, int ny, const RegionBox* boxes, int nboxes,
                              float* region_max, int nregions, float* hmax, hipStream_t s) {
     if (nboxes > 0)
-        hipLaunchKernelGGL(k_region_max, dim3(nboxes), dim3(256), 0, s, heat, nx, ny, boxes, region_max);
+        hipLaunchKernelGGL(k_region_max, dim3(nboxes), dim3(256), 0, s, heat, nx, ny, boxes,
+                           static_cast<const int*>(nullptr), region_max);
+    hipLaunchKernelGGL(k_region_final, dim3(1), dim3(256), 0, s, region_max, nregions, hmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_region_max_dyn(const float* heat, int nx, int ny, const RegionBox* boxes, const int* nboxes_dev,
+                                 int max_boxes, float* region_max, int nregions, float* hmax, hipStream_t s) {
+    if (max_boxes > 0)
+        hipLaunchKernelGGL(k_region_max, dim3(max_boxes), dim3(256), 0, s, heat, nx, ny, boxes, nboxes_dev,
+                           region_max);
     hipLaunchKernelGGL(k_region_final, dim3(1), dim3(256), 0, s, region_max, nregions, hmax);
     return hipGetLastError();
 }
 
 hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
-    DecodeArgs a;
+    DecodeArgs a{};
     a.tiles = d.tiles;
     a.ntiles = d.ntiles;
     a.col_tx = d.col_tx;
@@ -953,13 +988,18 @@ hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
     a.wg_u0 = d.wg_u0;
     a.nwg = d.nwg;
     a.reqs = nullptr;
-    if (precision != 0 && (!d.units || !d.wg_u0 || d.nunits < 1 || d.nwg < 1))
+    a.dyn = d.dyn;
+    if (precision != 0 && (!d.units || !d.wg_u0 || d.nwg < 1 || (!d.dyn && d.nunits < 1)))
         return d.ntiles == 0 ? hipSuccess : hipErrorInvalidValue;
     const dim3 grid(precision == 0 ? d.plan.grid : (unsigned)((d.nwg + kXcds - 1) / kXcds * kXcds)), block(256),
         block16(Wide<1>::NT);
     // the GEMM records the stage's start event, and its stop event unless a fix-up follows
-    const bool fix = precision == 0 ? (d.plan.steps_per_wg % d.plan.ksteps != 0 || d.plan.steps_per_wg < d.plan.ksteps)
-                                    : d.any_split;
+    // (a localized decode does not know on the host whether a tile is split: its fix-up always
+    // runs, over at most fix_tiles tiles, and leaves at once where nothing is split)
+    const bool fix = d.dyn ? true
+                           : precision == 0 ? (d.plan.steps_per_wg % d.plan.ksteps != 0 || d.plan.steps_per_wg < d.plan.ksteps)
+                                            : d.any_split;
+    const unsigned fix_tiles = (unsigned)(d.dyn ? d.fix_tiles : d.ntiles);
     const hipEvent_t e0 = profile_start(kStageDecode), e1 = profile_stop(kStageDecode);
     const hipEvent_t g1 = fix ? nullptr : e1;
     switch (precision) {
@@ -983,13 +1023,13 @@ hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
     }
     if (fix) {
         if (precision == 0)
-            hipExtLaunchKernelGGL(k_decode_fix<kTileRows>, dim3((unsigned)d.ntiles * Fix<kTileRows>::PARTS),
+            hipExtLaunchKernelGGL(k_decode_fix<kTileRows>, dim3(fix_tiles * Fix<kTileRows>::PARTS),
                                   dim3(256), 0, s, nullptr, e1, 0, a);
         else if (precision == 3)
-            hipExtLaunchKernelGGL(k_decode_fix<Wide<3>::TR>, dim3((unsigned)d.ntiles * Fix<Wide<3>::TR>::PARTS),
+            hipExtLaunchKernelGGL(k_decode_fix<Wide<3>::TR>, dim3(fix_tiles * Fix<Wide<3>::TR>::PARTS),
                                   dim3(256), 0, s, nullptr, e1, 0, a);
         else
-            hipExtLaunchKernelGGL(k_decode_fix<Wide<1>::TR>, dim3((unsigned)d.ntiles * Fix<Wide<1>::TR>::PARTS),
+            hipExtLaunchKernelGGL(k_decode_fix<Wide<1>::TR>, dim3(fix_tiles * Fix<Wide<1>::TR>::PARTS),
                                   dim3(256), 0, s, nullptr, e1, 0, a);
     }
     if (d.hmax_u) hipLaunchKernelGGL(k_hmax_final, dim3(1), dim3(64), 0, s, d.hmax_u, d.hmax);
@@ -1044,6 +1084,7 @@ hipError_t launch_decode_batch(int precision, const DecodeBatch& b, hipStream_t 
     a.wg_u0 = b.wg_u0;
     a.nwg = b.nwg;
     a.reqs = b.reqs;
+    a.dyn = nullptr;
     const dim3 grid((unsigned)((b.nwg + kXcds - 1) / kXcds * kXcds)), block16(Wide<1>::NT);
     const hipEvent_t e0 = profile_start(kStageDecode), e1 = profile_stop(kStageDecode);
     const hipEvent_t g1 = b.any_split ? nullptr : e1;
@@ -1060,5 +1101,132 @@ hipError_t launch_decode_batch(int precision, const DecodeBatch& b, hipStream_t 
     }
     return hipGetLastError();
 }
+
+namespace {
+
+constexpr int kPlanThreads = 1024;
+constexpr int kMaxRegions = kMaxTilesPerAxis * kMaxTilesPerAxis;
+
+// Exclusive prefix sum of v over the block (kPlanThreads threads); *total = the block's sum.
+__device__ inline int plan_scan(int v, int* s_w, int* total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int i = 0; i < kPlanThreads / 64; ++i) {
+        const int t = s_w[i];
+        if (i < w) off += t;
+        tot += t;
+    }
+    __syncthreads();   // s_w is reused by the next scan
+    *total = tot;
+    return off + x - v;
+}
+
+// One block: changed regions (memory versions against the last localized decode), the tiles
+// touching them and the boxes of those regions, compacted in list order, then the 16-bit
+// GEMM's work units over the changed tiles (the cut decode_units makes: equal consecutive
+// K ranges per workgroup, two units where a range crosses a tile border) and the fp32
+// kernel's steps per workgroup.
+__global__ __launch_bounds__(kPlanThreads) void k_inc_plan(IncPlan a) {
+    __shared__ unsigned char dirty[kMaxRegions];
+    __shared__ int s_w[kPlanThreads / 64];
+    const int tid = threadIdx.x;
+    for (int b = tid; b < a.nregions; b += kPlanThreads) {
+        const unsigned v0 = a.version[2 * b], v1 = a.version[2 * b + 1];
+        dirty[b] = (a.all || v0 != a.seen[2 * b] || v1 != a.seen[2 * b + 1]) ? 1 : 0;
+        a.seen[2 * b] = v0;
+        a.seen[2 * b + 1] = v1;
+    }
+    __syncthreads();
+    int n = 0;   // changed tiles so far (uniform)
+    for (int c0 = 0; c0 < a.ntiles; c0 += kPlanThreads) {
+        const int i = c0 + tid;
+        int f = 0;
+        DTile t{};
+        if (i < a.ntiles) {
+            t = a.tiles[i];
+            const int tx0 = a.col_tx[t.col0], tx1 = a.col_tx[t.col0 + t.ncol - 1];
+            for (int tx = tx0; tx <= tx1 && !f; ++tx) f = dirty[t.ty * a.tiles_x + tx];
+        }
+        int tot;
+        const int pos = plan_scan(f, s_w, &tot);
+        if (f) a.out_tiles[n + pos] = t;
+        n += tot;
+    }
+    int nb = 0;   // changed regions
+    for (int c0 = 0; c0 < a.nregions; c0 += kPlanThreads) {
+        const int b = c0 + tid;
+        const int f = b < a.nregions ? dirty[b] : 0;
+        int tot;
+        const int pos = plan_scan(f, s_w, &tot);
+        if (f) a.out_boxes[nb + pos] = a.boxes[b];
+        nb += tot;
+    }
+    const long long ks = a.ksteps16, total = (long long)n * ks;
+    long long L = ks;
+    if (n > 0 && n < a.slots16)
+        L = min(ks, max((total + a.slots16 - 1) / a.slots16, (long long)kMinUnitSteps));
+    const int nwg = total > 0 ? (int)((total + L - 1) / L) : 0;
+    int crossed = 0;   // workgroups so far whose range crosses a tile border
+    for (int c0 = 0; c0 < nwg; c0 += kPlanThreads) {
+        const int w = c0 + tid;
+        long long it0 = 0, it1 = 0;
+        int t = 0, c = 0;
+        if (w < nwg) {
+            it0 = (long long)w * L;
+            it1 = min(total, it0 + L);
+            t = (int)(it0 / ks);
+            c = ((it1 - 1) / ks != t) ? 1 : 0;   // L <= ks: at most one border inside
+        }
+        int tot;
+        const int pos = plan_scan(c, s_w, &tot);
+        if (w < nwg) {
+            const int u = w + crossed + pos;
+            const int kb0 = (int)(it0 - (long long)t * ks);
+            a.wg_u0[w] = u;
+            if (kb0 == 0) a.tile_u0[t] = u;
+            if (c) {
+                a.units[u] = DUnit{t, kb0, (int)ks, 0};
+                a.units[u + 1] = DUnit{t + 1, 0, (int)(it1 - (long long)(t + 1) * ks), 0};
+                a.tile_u0[t + 1] = u + 1;
+            } else {
+                a.units[u] = DUnit{t, kb0, (int)(it1 - (long long)t * ks), 0};
+            }
+        }
+        crossed += tot;
+    }
+    if (tid == 0) {
+        const int nunits = nwg + crossed;
+        a.wg_u0[nwg] = nunits;
+        a.tile_u0[n] = nunits;
+        const long long total32 = (long long)n * a.ksteps32;
+        long long L32 = (total32 + a.slots32 - 1) / a.slots32;
+        if (L32 < 4) L32 = 4;   // the fp32 plan's shortest range (decode_plan)
+        a.dyn[0] = n;
+        a.dyn[1] = nwg;
+        a.dyn[2] = nb;
+        a.dyn[3] = (int)L32;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_inc_plan(const IncPlan& p, hipStream_t s) {
+    if (p.nregions < 1 || p.nregions > kMaxRegions || p.ntiles < 0 || p.ksteps16 < 1 || p.ksteps32 < 1 ||
+        p.slots16 < 1 || p.slots32 < 1)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_inc_plan, dim3(1), dim3(kPlanThreads), 0, s, p);
+    return hipGetLastError();
+}
+
+int decode_slots16(int num_cus) { return Wide<1>::OCC * num_cus; }
+int decode_slots32(int num_cus) { return kDecodeOccupancy<0> * num_cus; }
 
 }  // namespace vsaogm

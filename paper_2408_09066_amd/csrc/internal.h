@@ -383,6 +383,10 @@ struct DecodeLaunch {
     const int* wg_u0 = nullptr;
     int nwg = 0;
     bool any_split = false;
+    // Localized decode: the counts come from the device (an IncPlan's dyn) and ntiles, nwg and
+    // plan.grid are upper bounds for the grids; fix_tiles bounds the tiles a fix-up may touch.
+    const int* dyn = nullptr;
+    int fix_tiles = 0;
 };
 // Similarity GEMM over the tile list (precision: 0 fp32, 1 bf16, 2 fp16, 3 bf16 hi+lo).
 // With hmax_u == nullptr no class maxima are folded and hmax is not written.
@@ -396,6 +400,36 @@ struct RegionBox {
 };
 hipError_t launch_region_max(const float* heat, int nx, int ny, const RegionBox* boxes, int nboxes,
                              float* region_max, int nregions, float* hmax, hipStream_t s);
+// Same with the listed regions' count read on the device (*nboxes_dev <= max_boxes).
+hipError_t launch_region_max_dyn(const float* heat, int nx, int ny, const RegionBox* boxes, const int* nboxes_dev,
+                                 int max_boxes, float* region_max, int nregions, float* hmax, hipStream_t s);
+
+// Plan of a localized decode, made on the device so that the host never waits for the memory
+// versions: the regions whose memories changed since the last localized decode (or all),
+// the tiles touching them and the GEMM's work units over those tiles (the cut of
+// decode_units for the 16-bit kernels; steps per workgroup for the fp32 kernel).
+struct IncPlan {
+    const unsigned* version;   // [2 nregions] memory versions
+    unsigned* seen;            // [2 nregions] versions at the last localized decode (updated)
+    int all;                   // every region counts as changed
+    int nregions, tiles_x;
+    const DTile* tiles;        // the grid's full tile list [ntiles]
+    int ntiles;
+    const int* col_tx;         // tile column of every grid column
+    const RegionBox* boxes;    // [nregions] cell range of every region
+    int ksteps16, ksteps32;    // K steps per tile of the 16-bit and fp32 kernels
+    int slots16, slots32;      // resident workgroups of the 16-bit and fp32 kernels
+    DTile* out_tiles;          // [ntiles] changed tiles
+    RegionBox* out_boxes;      // [nregions] changed regions
+    DUnit* units;              // [ntiles + slots16] 16-bit work units
+    int* tile_u0;              // [ntiles + 1]
+    int* wg_u0;                // [max(ntiles, slots16) + 1]
+    int* dyn;                  // [4]: changed tiles, 16-bit workgroups, changed regions, fp32 steps per workgroup
+};
+hipError_t launch_inc_plan(const IncPlan& p, hipStream_t s);
+// Resident workgroups of the 16-bit and fp32 GEMMs on num_cus CUs (the plans' slot counts).
+int decode_slots16(int num_cus);
+int decode_slots32(int num_cus);
 
 // ---- classify (classify.hip) -------------------------------------------------------
 // One request of a batched classification (entropy decoding, Sec. III-B defaults).

@@ -201,20 +201,19 @@ struct GridCache {
     DevBuf<int> col_tx;              // [nx] tile column of every grid column
     DevBuf<float2> ex32, ey32;       // fp32 tables [n][halfp]
     DevBuf<uint16_t> ey_bf, ey_bf_lo, ey_h;  // 16-bit y tables [ny][2*halfp], built on first use
-    // incremental decoding state
+    // localized decoding state (planned on the device: IncPlan)
     std::vector<int> tcol;                   // tile column of every grid column
     std::vector<RegionBox> boxes;            // [tiles] cell range of every tile (row0 == row1: none)
-    std::vector<unsigned> seen;              // memory versions at the last incremental decode
+    DevBuf<RegionBox> d_boxes;
+    DevBuf<unsigned> d_seen;                 // memory versions at the last localized decode
     const float* inc_heat = nullptr;         // heat buffer of that decode
     int inc_precision = -1;                  // and its operand precision
     bool inc_valid = false;
     DevBuf<float> region_max;                // [tiles][2]
-    DevBuf<DTile> inc_tiles;
-    DevBuf<RegionBox> inc_boxes;
-    DevUnits inc_dunits;
-    std::vector<DTile> inc_tiles_host;
-    std::vector<RegionBox> inc_boxes_host;
-    UnitPlan inc_uplan;
+    DevBuf<DTile> inc_tiles;                 // changed tiles, regions and the GEMM's work units
+    DevBuf<RegionBox> inc_boxes;             // (capacities for the whole tile list)
+    DevBuf<DUnit> inc_units;
+    DevBuf<int> inc_tile_u0, inc_wg_u0, inc_dyn;
 };
 
 struct ProfileSlot {
@@ -300,7 +299,6 @@ struct vsaogm_map {
     DevBuf<unsigned> d_hmax_u;          // [2] ordered class maxima
     DevBuf<unsigned long long> d_bad;   // [1]
     DevBuf<unsigned> d_version;         // [nkeys] change counters of the memories
-    unsigned* h_version = nullptr;      // pinned read-back of d_version
 
     // encode workspace
     int64_t cap_n = 0;
@@ -488,7 +486,6 @@ GridCache* grid_cache(vsaogm_map* m, const vsaogm_grid_desc* g, hipStream_t s) {
             if (b.row0 >= b.row1 || b.col0 >= b.col1) b.row0 = b.row1 = b.col0 = b.col1 = 0;
             gc->boxes[b.beta] = b;
         }
-    gc->seen.assign(m->nkeys, 0u);
     for (int set = 1; set < kDecodeTileSets; ++set) {
         gc->uplan[set].build(gc->ntiles[set], m->halfp / 32, m->num_cus);
         gc->dunits[set].upload(gc->uplan[set]);
@@ -972,8 +969,6 @@ int vsaogm_map_create(const vsaogm_map_desc* d, vsaogm_map** out) {
         m->d_hmax_u.alloc(2, "class maxima");
         m->d_bad.alloc(1, "rejected-label counter");
         m->d_version.alloc(m->nkeys, "memory versions");
-        hip_check(hipHostMalloc((void**)&m->h_version, sizeof(unsigned) * m->nkeys, hipHostMallocDefault),
-                  "pinned versions");
         hip_check(hipMemcpy(m->d_cx.p, m->cx.data(), m->cx.size() * 8, hipMemcpyHostToDevice), "copy");
         hip_check(hipMemcpy(m->d_cy.p, m->cy.data(), m->cy.size() * 8, hipMemcpyHostToDevice), "copy");
         hip_check(hipMemcpy(m->d_rev.p, rev.data(), rev.size() * sizeof(float2), hipMemcpyHostToDevice),
@@ -993,7 +988,6 @@ int vsaogm_map_destroy(vsaogm_map* m) {
     return guarded([&] {
         DeviceGuard guard(m->device);
         (void)hipDeviceSynchronize();
-        if (m->h_version) (void)hipHostFree(m->h_version);
         delete m;
     });
 }
@@ -1114,78 +1108,101 @@ int vsaogm_decode_incremental(vsaogm_map* m, const vsaogm_grid_desc* g, int32_t 
         const void* ey = y_table(m, gc, precision, &ey_lo, s);
         const int nregions = m->tiles_x * m->tiles_y;
         if (!gc->region_max.p) gc->region_max.alloc_async(2 * (size_t)nregions, s, "region maxima");
-        // which memories changed since this grid was last decoded incrementally
-        hip_check(hipMemcpyAsync(m->h_version, m->d_version.p, sizeof(unsigned) * m->nkeys,
-                                 hipMemcpyDeviceToHost, s),
-                  "read versions");
-        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-        std::vector<char> dirty(nregions, 0);
+        const int set = decode_tile_set(precision);
+        const int N = gc->ntiles[set];
+        const int slots16 = decode_slots16(m->num_cus), slots32 = decode_slots32(m->num_cus);
+        if (!gc->d_seen.p) {
+            gc->d_seen.alloc_async(m->nkeys, s, "seen versions");
+            gc->d_boxes.alloc_async(nregions, s, "region boxes");
+            hip_check(hipMemcpyAsync(gc->d_boxes.p, gc->boxes.data(), sizeof(RegionBox) * nregions,
+                                     hipMemcpyHostToDevice, s),
+                      "copy region boxes");
+            gc->inc_boxes.alloc_async(nregions, s, "changed regions");
+            gc->inc_dyn.alloc_async(4, s, "localized decode counts");
+        }
+        // capacities for every tile of the largest tile set
+        int nmax = 0;
+        for (int t = 0; t < kDecodeTileSets; ++t) nmax = std::max(nmax, gc->ntiles[t]);
+        if (gc->inc_tiles.n < (size_t)std::max(nmax, 1)) {
+            gc->inc_tiles.alloc_async(std::max(nmax, 1), s, "changed tiles");
+            gc->inc_units.alloc_async((size_t)nmax + slots16, s, "localized work units");
+            gc->inc_tile_u0.alloc_async((size_t)nmax + 1, s, "localized tile units");
+            gc->inc_wg_u0.alloc_async((size_t)std::max(nmax, slots16) + 1, s, "localized workgroup units");
+        }
         const bool all = !gc->inc_valid || gc->inc_heat != heat || gc->inc_precision != precision;
-        for (int b = 0; b < nregions; ++b)
-            dirty[b] = all || m->h_version[2 * b] != gc->seen[2 * b] ||
-                       m->h_version[2 * b + 1] != gc->seen[2 * b + 1];
-        std::copy(m->h_version, m->h_version + m->nkeys, gc->seen.begin());
         gc->inc_valid = true;
         gc->inc_heat = heat;
         gc->inc_precision = precision;
-        std::vector<DTile>& tl = gc->inc_tiles_host;
-        std::vector<RegionBox>& bx = gc->inc_boxes_host;
-        tl.clear();
-        bx.clear();
-        const int set = decode_tile_set(precision);
-        for (const DTile& t : gc->host_tiles[set]) {
-            const int tx0 = gc->tcol[t.col0], tx1 = gc->tcol[t.col0 + t.ncol - 1];
-            bool d = false;
-            for (int tx = tx0; tx <= tx1 && !d; ++tx) d = dirty[t.ty * m->tiles_x + tx];
-            if (d) tl.push_back(t);
+        // which memories changed since this grid's last localized decode, the tiles to decode
+        // and the GEMM's work units: planned on the device, so nothing here waits for it
+        IncPlan ip;
+        ip.version = m->d_version.p;
+        ip.seen = gc->d_seen.p;
+        ip.all = all ? 1 : 0;
+        ip.nregions = nregions;
+        ip.tiles_x = m->tiles_x;
+        ip.tiles = gc->tiles[set].p;
+        ip.ntiles = N;
+        ip.col_tx = gc->col_tx.p;
+        ip.boxes = gc->d_boxes.p;
+        ip.ksteps16 = m->halfp / 32;
+        ip.ksteps32 = m->halfp / 16;
+        ip.slots16 = slots16;
+        ip.slots32 = slots32;
+        ip.out_tiles = gc->inc_tiles.p;
+        ip.out_boxes = gc->inc_boxes.p;
+        ip.units = gc->inc_units.p;
+        ip.tile_u0 = gc->inc_tile_u0.p;
+        ip.wg_u0 = gc->inc_wg_u0.p;
+        ip.dyn = gc->inc_dyn.p;
+        hip_check(launch_inc_plan(ip, s), "localized decode plan");
+        // partial sums: 16-bit, split tiles only when fewer tiles than slots (at most two units
+        // per workgroup); fp32, two blocks per workgroup of at most slots32 workgroups
+        DecodeLaunch d;
+        d.plan = decode_plan(precision, N, m->halfp, m->num_cus);
+        size_t need;
+        if (precision != VSAOGM_FP32) {
+            need = decode_unit_partial_floats(2 * slots16);
+            d.units = gc->inc_units.p;
+            d.nunits = 0;   // read on the device
+            d.tile_u0 = gc->inc_tile_u0.p;
+            d.wg_u0 = gc->inc_wg_u0.p;
+            d.nwg = std::max(N, slots16);
+            d.fix_tiles = std::min(N, slots16);
+        } else {
+            d.plan.grid = slots32;
+            d.plan.steps_per_wg = 0;   // read on the device
+            DecodePlan worst{};   // at most slots32 workgroups, each with split tiles
+            worst.ksteps = 2;
+            worst.steps_per_wg = 1;
+            worst.grid = slots32;
+            need = decode_partial_floats(precision, worst);
+            d.fix_tiles = N;
         }
-        for (int b = 0; b < nregions; ++b)
-            if (dirty[b]) bx.push_back(gc->boxes[b]);
-        if (gc->inc_tiles.n < tl.size())
-            gc->inc_tiles.alloc_async(gc->host_tiles[set].size(), s, "incremental tiles");
-        if (gc->inc_boxes.n < bx.size()) gc->inc_boxes.alloc_async(nregions, s, "incremental regions");
-        // the host vectors stay untouched until this stream passes the copies: the next
-        // incremental decode of this grid synchronises the stream before refilling them
-        if (!tl.empty())
-            hip_check(hipMemcpyAsync(gc->inc_tiles.p, tl.data(), tl.size() * sizeof(DTile), hipMemcpyHostToDevice, s),
-                      "copy tiles");
-        if (!bx.empty())
-            hip_check(hipMemcpyAsync(gc->inc_boxes.p, bx.data(), bx.size() * sizeof(RegionBox),
-                                     hipMemcpyHostToDevice, s),
-                      "copy regions");
-        if (!tl.empty()) {
-            DecodeLaunch d;
-            d.plan = decode_plan(precision, (int)tl.size(), m->halfp, m->num_cus);
-            size_t need = decode_partial_floats(precision, d.plan);
-            if (precision != VSAOGM_FP32) {
-                gc->inc_uplan.build((int)tl.size(), m->halfp / 32, m->num_cus);
-                gc->inc_dunits.upload_async(gc->inc_uplan, s);
-                need = set_units(d, gc->inc_uplan, gc->inc_dunits, (int)tl.size());
-            }
-            if (m->d_partial.n < need) m->d_partial.alloc_async(need, s, "decode partial sums");
-            hip_check(launch_norm(m->d_omega.p, m->nkeys, m->half, m->halfp, m->D, m->d_scale.p,
-                                  m->d_omega_s.p, m->d_hmax_u.p, s),
-                      "norm launch");
-            d.tiles = gc->inc_tiles.p;
-            d.ntiles = (int)tl.size();
-            d.col_tx = gc->col_tx.p;
-            d.ex = gc->ex32.p;
-            d.ey = ey;
-            d.ey_lo = ey_lo;
-            d.omega_s = m->d_omega_s.p;
-            d.halfp = m->halfp;
-            d.nx = g->nx;
-            d.ny = g->ny;
-            d.tiles_x = m->tiles_x;
-            d.out_scale = (float)(2.0 / (double)m->D);
-            d.heat = heat;
-            d.hmax_u = nullptr;
-            d.hmax = hmax;
-            d.partial = m->d_partial.p;
-            hip_check(launch_decode(precision, d, s), "decode launch");
-        }
-        hip_check(launch_region_max(heat, g->nx, g->ny, gc->inc_boxes.p, (int)bx.size(), gc->region_max.p,
-                                    nregions, hmax, s),
+        if (m->d_partial.n < need) m->d_partial.alloc_async(need, s, "decode partial sums");
+        hip_check(launch_norm(m->d_omega.p, m->nkeys, m->half, m->halfp, m->D, m->d_scale.p, m->d_omega_s.p,
+                              m->d_hmax_u.p, s),
+                  "norm launch");
+        d.dyn = gc->inc_dyn.p;
+        d.tiles = gc->inc_tiles.p;
+        d.ntiles = N;
+        d.col_tx = gc->col_tx.p;
+        d.ex = gc->ex32.p;
+        d.ey = ey;
+        d.ey_lo = ey_lo;
+        d.omega_s = m->d_omega_s.p;
+        d.halfp = m->halfp;
+        d.nx = g->nx;
+        d.ny = g->ny;
+        d.tiles_x = m->tiles_x;
+        d.out_scale = (float)(2.0 / (double)m->D);
+        d.heat = heat;
+        d.hmax_u = nullptr;
+        d.hmax = hmax;
+        d.partial = m->d_partial.p;
+        if (N > 0) hip_check(launch_decode(precision, d, s), "decode launch");
+        hip_check(launch_region_max_dyn(heat, g->nx, g->ny, gc->inc_boxes.p, gc->inc_dyn.p + 2, nregions,
+                                        gc->region_max.p, nregions, hmax, s),
                   "region maxima");
     });
 }

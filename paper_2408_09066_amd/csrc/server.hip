@@ -181,7 +181,7 @@ struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     DevMem d_in, d_out;
-    HostMem h_in, h_out;
+    HostMem h_out;
     vsaogm::UpdateBatchWork* work = nullptr;
     // layout of the current batch's outputs (section-major: maxima, labels, maps, heatmaps)
     std::vector<size_t> o_hmax, o_lab, o_ogm, o_heat;
@@ -364,9 +364,7 @@ private:
         s.back = want_heat ? end_heat : (want_ogm ? end_ogm : (want_lab ? end_lab : 16 * count));
         s.d_in.ensure(std::max<size_t>(in_bytes, 256), s.stream, "batch inputs");
         s.d_out.ensure(end_heat, s.stream, "batch outputs");
-        s.h_in.ensure(std::max<size_t>(in_bytes, 256), "batch pinned inputs");
         s.h_out.ensure(s.back, "batch pinned outputs");
-        unsigned char* hin = static_cast<unsigned char*>(s.h_in.p);
         unsigned char* din = static_cast<unsigned char*>(s.d_in.p);
         unsigned char* dout = static_cast<unsigned char*>(s.d_out.p);
         std::vector<vsaogm::UpdateItem> items(count);
@@ -374,7 +372,10 @@ private:
         for (size_t i = 0; i < count; ++i) {
             const Payload* p = static_cast<const Payload*>(batch[i]->payload);
             const vsaogm_request& r = p->r;
-            if (r.n > 0) std::memcpy(hin + o_in[i], p->in, (size_t)r.n * 9);
+            // from the request's pinned block (returned to the pool only after the slot's work ended)
+            if (r.n > 0)
+                check_hip(hipMemcpyAsync(din + o_in[i], p->in, (size_t)r.n * 9, hipMemcpyHostToDevice, s.stream),
+                          "copy inputs");
             vsaogm::UpdateItem& it = items[i];
             it.map = p->map;
             it.xy = reinterpret_cast<const float*>(din + o_in[i]);
@@ -390,7 +391,6 @@ private:
             it.label_out = dout + s.o_lab[i];
             precision = r.precision;
         }
-        if (in_bytes > 0) check_hip(hipMemcpyAsync(din, hin, in_bytes, hipMemcpyHostToDevice, s.stream), "copy inputs");
         const int rc = vsaogm::run_update_batch(items.data(), (int)count, precision, s.stream, s.work);
         if (rc != VSAOGM_OK) throw Fail(rc, vsaogm_last_error());
         check_hip(hipMemcpyAsync(s.h_out.p, dout, s.back, hipMemcpyDeviceToHost, s.stream), "copy outputs");
@@ -568,25 +568,17 @@ int vsaogm_submit_many(vsaogm_server* s, const vsaogm_request* reqs, int32_t cou
     const int rc = guard([&] {
         if (!s || (!reqs && count > 0) || (!tickets && count > 0))
             throw Fail(VSAOGM_EINVAL, "server, requests and tickets must not be NULL");
-        std::vector<std::unique_ptr<CoreRequest>> qs;
-        qs.reserve(count > 0 ? count : 0);
-        int err = VSAOGM_OK;
-        std::string msg;
+        // each request is queued as soon as it is staged, so that the workers start on the first
+        // ones while the later ones are copied
         for (int32_t i = 0; i < count; ++i) {
-            try {
-                qs.push_back(prepare(s, reqs + i));
-            } catch (const Fail& e) {
-                err = e.code;
-                msg = e.what();
-                break;
+            std::unique_ptr<CoreRequest> q = prepare(s, reqs + i);
+            const int rc2 = s->sched->submit(q, tickets + i);
+            if (rc2 != VSAOGM_OK) {
+                drop(s, q);   // not queued: still ours
+                throw Fail(rc2, rc2 == VSAOGM_EBUSY ? "queue full" : "request refused");
             }
+            ++queued;
         }
-        std::vector<std::unique_ptr<CoreRequest>*> ptrs;
-        for (auto& q : qs) ptrs.push_back(&q);
-        const int rc2 = s->sched->submit_many(ptrs, tickets, &queued);
-        for (auto& q : qs) drop(s, q);   // the ones not queued (queued ones were moved out)
-        if (rc2 != VSAOGM_OK) throw Fail(rc2, rc2 == VSAOGM_EBUSY ? "queue full" : "request refused");
-        if (err != VSAOGM_OK) throw Fail(err, msg);
     });
     if (n_queued) *n_queued = queued;
     return rc;

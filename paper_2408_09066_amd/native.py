@@ -468,9 +468,10 @@ class Server:
         self._keep[t.value] = out
         return int(t.value), out
 
-    def submit_many(self, items, want=("label",)):
-        """Queue a list of requests with one call.  items: dicts with keys map_id, xy, label,
-        grid, nx, ny, r_occ, r_emp and optionally rho, precision, local.  Returns [(ticket, outputs)]."""
+    def prepare_many(self, items, want=("label",)):
+        """Build the request structs and output arrays of a list of requests (no server call).
+        items: dicts with keys map_id, xy, label, grid, nx, ny, r_occ, r_emp and optionally rho,
+        precision, local.  Returns an object for submit_prepared."""
         n = len(items)
         arr = (Request * n)()
         keep, outs = [], []
@@ -494,7 +495,13 @@ class Server:
                              out["label"].ctypes.data if "label" in out else None,
                              out["heat"].ctypes.data if "heat" in out else None,
                              REQUEST_LOCAL if it.get("local") else 0)
-        tk = (ctypes.c_uint64 * n)()
+        return (n, arr, keep, outs)
+
+    def submit_prepared(self, prepared):
+        """Queue requests built by prepare_many with one call (inputs are staged by the server
+        before it returns).  Returns [(ticket, outputs)]."""
+        n, arr, _keep, outs = prepared
+        tk = (ctypes.c_uint64 * max(n, 1))()
         nq = ctypes.c_int32()
         rc = load().vsaogm_submit_many(self._h, arr, n, tk, ctypes.byref(nq))
         res = []
@@ -503,6 +510,11 @@ class Server:
             res.append((int(tk[i]), outs[i]))
         check(rc)
         return res
+
+    def submit_many(self, items, want=("label",)):
+        """Queue a list of requests with one call (prepare_many + submit_prepared).
+        Returns [(ticket, outputs)]."""
+        return self.submit_prepared(self.prepare_many(items, want))
 
     def poll(self, ticket: int):
         """None while running; else a dict with status, slot, times (ns) and maxima."""

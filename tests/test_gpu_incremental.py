@@ -156,3 +156,52 @@ def test_incremental_equals_full(torch_cuda, name, precision):
     assert same(heat2, ref) and same(hmax, ref_max)
     other.close()
     m.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "bf16x3"])
+def test_incremental_many_tiles(torch_cuda, precision):
+    """A 2560 x 2560 grid of 10 x 10 memory tiles (400 GEMM tiles of 256 x 64 cells): updates
+    that touch 7 tile rows (about 280 GEMM tiles, whole tiles per workgroup), two neighbouring
+    tiles (a few tiles split over workgroups, ranges crossing tile borders) and none.  The
+    plan is made on the device; every result equals a full decode up to accumulation order."""
+    say(f"[gpu] incremental decode, many tiles, {precision}")
+    from paper_2408_09066_amd import native
+    torch = torch_cuda
+    rng = np.random.default_rng(2408)
+    D, res, side, T = 512, 0.05, 2560, 10
+    half = side * res / 2.0
+    layout = (-half, -half, half, half)
+    grid = (-half, -half, res)
+    theta = synth.make_theta(D, 0.25, rng)
+    m = native.Map(theta, layout, (T, T))
+    heat = torch.empty((2, side, side), dtype=torch.float32, device="cuda")
+    hmax = torch.empty(2, dtype=torch.float32, device="cuda")
+
+    def points(x0, y0, x1, y1, n):
+        xy = np.stack([rng.uniform(x0, x1, n), rng.uniform(y0, y1, n)], 1).astype(np.float32)
+        lb = rng.integers(0, 2, n).astype(np.uint8)
+        return torch.from_numpy(xy).cuda(), torch.from_numpy(lb).cuda()
+
+    def check_full(tag):
+        ref, ref_max = m.decode(grid, side, side, precision)
+        torch.cuda.synchronize()
+        d = torch_max_abs(heat, ref)
+        say(f"  {tag}: max-abs vs full decode {d:.2e}")
+        assert d <= ORDER_TOL and same(hmax, ref_max)
+
+    m.encode(*points(-half, -half, half, half, 20000))
+    heat.fill_(float("nan"))
+    m.decode_incremental(grid, side, side, heat, precision, hmax)
+    check_full("first call (all tiles)")
+    tile = 2 * half / T
+    m.encode(*points(-half, -half + 2 * tile, half, -half + 9 * tile, 30000))   # tile rows 2..8
+    m.decode_incremental(grid, side, side, heat, precision, hmax)
+    check_full("7 tile rows")
+    m.encode(*points(-half + 3 * tile, -half + 5 * tile, -half + 5 * tile, -half + 6 * tile, 5000))
+    m.decode_incremental(grid, side, side, heat, precision, hmax)
+    check_full("2 tiles")
+    heat[:, 0, 0] = SENTINEL
+    m.decode_incremental(grid, side, side, heat, precision, hmax)
+    torch.cuda.synchronize()
+    assert torch.all(heat[:, 0, 0] == SENTINEL)
+    m.close()
