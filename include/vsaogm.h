@@ -239,11 +239,22 @@ int vsaogm_fuse(vsaogm_map* dst, const vsaogm_map* src, vsaogm_stream stream);
  * maps overlap on the device, while updates of one map run in submission
  * order (memories are state).  A request's result does not depend on which
  * other requests share the device with it.
+ *
+ * Memory budget: a request is admitted only if the bytes of the requests in
+ * flight (each charged its buffers plus a bound on what its run can add to its
+ * map: a new grid's tables, workspace growth), of every map as it stands and of
+ * the slots' buffers stay within hbm_budget_bytes.  When nothing runs and the
+ * first waiting request still does not fit, the server releases what the maps
+ * rebuild on demand (cached grids, workspaces; never memories) and tries again;
+ * a request that does not fit even then completes with VSAOGM_ENOMEM.  The
+ * accounting is the library's own: the device allocator may round blocks up.
  * ------------------------------------------------------------------------- */
 
 typedef struct {
-    int64_t hbm_budget_bytes; /* device bytes for in-flight request buffers;
-                                 <= 0 means a quarter of the free memory */
+    int64_t hbm_budget_bytes; /* device bytes the server may hold: its maps (memories,
+                                 workspaces, cached grid tables), its slots' buffers and
+                                 the requests in flight; <= 0 means a quarter of the free
+                                 memory */
     int32_t max_inflight;     /* execution slots (streams), 1..32 */
     int32_t max_queue;        /* pending requests before submit returns EBUSY */
     int32_t device;           /* HIP device ordinal */
@@ -287,7 +298,8 @@ int vsaogm_server_create(const vsaogm_server_desc* desc, vsaogm_server** out);
 int vsaogm_server_destroy(vsaogm_server* server);
 
 /* Create a map owned by the server (desc->device is ignored: the server's
-   device is used).  *map_id receives its id (0, 1, ...). */
+   device is used).  *map_id receives its id (0, 1, ...).  ENOMEM when the new
+   map's own buffers do not fit the memory budget beside what the server holds. */
 int vsaogm_server_add_map(vsaogm_server* server, const vsaogm_map_desc* desc, int32_t* map_id);
 
 /* The server-owned map (for vsaogm_memories, vsaogm_decode or vsaogm_fuse after vsaogm_server_drain).
@@ -325,12 +337,20 @@ int vsaogm_wait(vsaogm_server* server, uint64_t ticket, vsaogm_result* result);
 /* Block until every submitted request has completed. */
 int vsaogm_server_drain(vsaogm_server* server);
 
-/* Counters: requests completed, peak bytes of the budget in use, budget. */
+/* Counters: requests completed, peak bytes of the budget in use (maps, slots and
+   requests in flight), budget. */
 int vsaogm_server_stats(vsaogm_server* server, int64_t* completed, int64_t* peak_bytes,
                         int64_t* budget_bytes);
 
-/* Device bytes a request holds from admission to completion (what admission checks against
-   the budget).  ENOTFOUND for an unknown map. */
+/* The budget's bytes now: charged to requests in flight, resident in the maps (as last
+   reported), held by the slots' buffers; and how many times the server released the maps'
+   rebuildable buffers to admit a request.  Any pointer may be NULL. */
+int vsaogm_server_memory(vsaogm_server* server, int64_t* in_flight, int64_t* resident, int64_t* fixed,
+                         int64_t* reclaims);
+
+/* Device bytes a request holds from admission to completion for its own buffers (admission
+   adds a bound on what its run can add to its map, and checks the sum against the budget
+   beside the maps' and slots' bytes).  ENOTFOUND for an unknown map. */
 int vsaogm_request_bytes(vsaogm_server* server, const vsaogm_request* req, int64_t* bytes);
 
 /*

@@ -1226,6 +1226,12 @@ hipError_t launch_inc_plan(const IncPlan& p, hipStream_t s) {
     return hipGetLastError();
 }
 
+size_t decode_partial_floats_max(int num_cus) {
+    const size_t u16 = decode_unit_partial_floats(2 * decode_slots16(num_cus));
+    const size_t f32 = (size_t)decode_slots32(num_cus) * 2 * 2 * kTileRows * kTileCols;
+    return std::max(u16, f32);
+}
+
 int decode_slots16(int num_cus) { return Wide<1>::OCC * num_cus; }
 int decode_slots32(int num_cus) { return kDecodeOccupancy<0> * num_cus; }
 

@@ -166,6 +166,8 @@ struct UpdateItem {
 struct UpdateBatchWork;   // staging and device buffers of one in-flight batch
 UpdateBatchWork* update_batch_work_create();
 void update_batch_work_destroy(UpdateBatchWork* w);
+int64_t update_batch_work_bytes(const UpdateBatchWork* w);   // device bytes it holds
+void update_batch_work_trim(UpdateBatchWork* w);             // release them (nothing in flight)
 // count updates of distinct maps on one device as one launch per stage (precision: a 16-bit
 // format), asynchronously on s.  Results equal the same updates through vsaogm_encode,
 // vsaogm_decode and vsaogm_classify up to the order of the similarity's fp32 accumulation (the
@@ -430,6 +432,19 @@ hipError_t launch_inc_plan(const IncPlan& p, hipStream_t s);
 // Resident workgroups of the 16-bit and fp32 GEMMs on num_cus CUs (the plans' slot counts).
 int decode_slots16(int num_cus);
 int decode_slots32(int num_cus);
+// Largest partial-sum block any decode of a map needs (full or localized, any precision).
+size_t decode_partial_floats_max(int num_cus);
+
+// ---- device memory of a map (the request loop's budget) ----------------------------------
+// Bytes of device memory the map holds now: memories, workspaces, partial sums, every cached
+// grid (tables, tile lists, localized-decode state).
+int64_t map_resident_bytes(const vsaogm_map* m);
+// Upper bound on the bytes one update (n points, decode of grid g at precision, localized or
+// not) can add to map_resident_bytes: a new grid cache or table format, workspace growth.
+int64_t map_growth_bytes(const vsaogm_map* m, const vsaogm_grid_desc* g, int precision, int64_t n, bool local);
+// Release what the map rebuilds on demand (grid caches, encode workspace, partial sums); the
+// memories stay.  The caller makes sure no work on the map is in flight.
+void map_trim(vsaogm_map* m);
 
 // ---- classify (classify.hip) -------------------------------------------------------
 // One request of a batched classification (entropy decoding, Sec. III-B defaults).

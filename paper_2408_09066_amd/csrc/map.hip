@@ -679,6 +679,114 @@ EncodeWork map_work(vsaogm_map* m) {
 // reduce), norm, the similarity GEMM (+ fix-up) and the classification each cover every request.
 namespace vsaogm {
 
+namespace {
+template <class T>
+int64_t nbytes(const DevBuf<T>& b) {
+    return b.p ? (int64_t)std::max<size_t>(b.n, 1) * (int64_t)sizeof(T) : 0;
+}
+
+// Every device buffer of a cached grid (keep in step with GridCache).
+int64_t grid_bytes(const GridCache& g) {
+    int64_t b = nbytes(g.local_x) + nbytes(g.local_y) + nbytes(g.col_tx) + nbytes(g.ex32) + nbytes(g.ey32) +
+                nbytes(g.ey_bf) + nbytes(g.ey_bf_lo) + nbytes(g.ey_h) + nbytes(g.d_boxes) + nbytes(g.d_seen) +
+                nbytes(g.region_max) + nbytes(g.inc_tiles) + nbytes(g.inc_boxes) + nbytes(g.inc_units) +
+                nbytes(g.inc_tile_u0) + nbytes(g.inc_wg_u0) + nbytes(g.inc_dyn);
+    for (int t = 0; t < kDecodeTileSets; ++t)
+        b += nbytes(g.tiles[t]) + nbytes(g.dunits[t].units) + nbytes(g.dunits[t].tile_u0) +
+             nbytes(g.dunits[t].wg_u0);
+    return b;
+}
+
+// Bytes of a 16-bit y table or of an fp32 table of n cells.
+int64_t table16_bytes(const vsaogm_map* m, int n) { return (int64_t)n * 2 * m->halfp * 2; }
+int64_t table32_bytes(const vsaogm_map* m, int n) { return (int64_t)n * m->halfp * 8; }
+
+int64_t y_tables_bytes(const vsaogm_map* m, int ny, int precision) {
+    switch (precision) {
+        case VSAOGM_FP32: return table32_bytes(m, ny);
+        case VSAOGM_FP16: return table16_bytes(m, ny);
+        default: return 2 * table16_bytes(m, ny);   // bf16 hi + residual, built together
+    }
+}
+}  // namespace
+
+int64_t map_resident_bytes(const vsaogm_map* m) {
+    int64_t b = nbytes(m->d_cx) + nbytes(m->d_cy) + nbytes(m->d_rev) + nbytes(m->d_rev_d) + nbytes(m->d_theta) +
+                nbytes(m->d_omega) + nbytes(m->d_scale) + nbytes(m->d_omega_s) + nbytes(m->d_partial) +
+                nbytes(m->d_hmax_u) + nbytes(m->d_bad) + nbytes(m->d_version) + nbytes(m->w_key) +
+                nbytes(m->w_hist) + nbytes(m->w_meta) + nbytes(m->w_sorted) + nbytes(m->w_sorted_lo) +
+                nbytes(m->w_partial) + nbytes(m->w_table);
+    for (const auto& kv : m->grids) b += grid_bytes(*kv.second);
+    return b;
+}
+
+int64_t map_growth_bytes(const vsaogm_map* m, const vsaogm_grid_desc* g, int precision, int64_t n, bool local) {
+    int64_t b = 0;
+    // encode workspace (ensure_encode_workspace): a new block replaces the old in stream order,
+    // so both are counted while the old one may still be in use
+    const EncodePlan p = encode_plan(n, m->halfp, m->nkeys);
+    if (n > m->cap_n || p.nchunks > m->cap_chunks || p.max_echunks > m->cap_echunks) {
+        const int64_t cap = std::max<int64_t>(n + n / 2, 4096);
+        const EncodePlan q = encode_plan(cap, m->halfp, m->nkeys);
+        const int64_t chunks = std::max(q.nchunks, p.nchunks), echunks = std::max(q.max_echunks, p.max_echunks);
+        b += cap * (4 + 8 + 8) + (chunks * m->nkeys + kHistPad) * 4 + echunks * (int64_t)sizeof(EChunk) +
+             echunks * m->halfp * 8 + (1 + 3 * (int64_t)m->nkeys) * 4;
+    }
+    // partial sums: at most the largest block any decode uses
+    const int64_t partial = (int64_t)decode_partial_floats_max(m->num_cus) * 4;
+    if (nbytes(m->d_partial) < partial) b += partial;
+    // grid: the whole cache when new, else the table of a precision not built yet
+    const GridKey key{g->x0, g->y0, g->res, g->nx, g->ny};
+    auto it = m->grids.find(key);
+    const GridCache* gc = it == m->grids.end() ? nullptr : it->second.get();
+    if (!gc) {
+        // tiles per set: bands of at least 16 rows (plus one per tile row), 64 columns
+        // (plus one per tile column); units at most two per tile plus one per slot
+        const int64_t tiles = ((int64_t)g->ny / 16 + 1 + m->tiles_y) * ((int64_t)g->nx / 64 + 1 + m->tiles_x);
+        const int64_t slots = std::max(decode_slots16(m->num_cus), decode_slots32(m->num_cus));
+        const int64_t per_set = tiles * (int64_t)sizeof(DTile) + (2 * tiles + slots) * (int64_t)sizeof(DUnit) +
+                                (2 * tiles + slots + 2) * 4;
+        b += kDecodeTileSets * per_set + ((int64_t)g->nx + g->ny) * 12 + table32_bytes(m, g->nx) +
+             y_tables_bytes(m, g->ny, precision);
+        if (local) {
+            const int64_t nreg = (int64_t)m->tiles_x * m->tiles_y;
+            b += nreg * (int64_t)(2 * sizeof(RegionBox) + 8 + 8) + tiles * (int64_t)(sizeof(DTile) + sizeof(DUnit)) +
+                 (2 * tiles + 2 * slots + 8) * 4 + slots * (int64_t)sizeof(DUnit);
+        }
+    } else {
+        const bool have = precision == VSAOGM_FP32 ? gc->ey32.p != nullptr
+                          : precision == VSAOGM_FP16 ? gc->ey_h.p != nullptr
+                                                     : gc->ey_bf.p != nullptr && gc->ey_bf_lo.p != nullptr;
+        if (!have) b += y_tables_bytes(m, g->ny, precision);
+        if (local && !gc->d_seen.p) {
+            int nmax = 0;
+            for (int t = 0; t < kDecodeTileSets; ++t) nmax = std::max(nmax, gc->ntiles[t]);
+            const int64_t nreg = (int64_t)m->tiles_x * m->tiles_y;
+            const int64_t slots = decode_slots16(m->num_cus);
+            b += nreg * (int64_t)(2 * sizeof(RegionBox) + 8 + 8) + nmax * (int64_t)(sizeof(DTile) + sizeof(DUnit)) +
+                 (2 * nmax + 2 * slots + 8) * 4 + slots * (int64_t)sizeof(DUnit);
+        }
+    }
+    return b;
+}
+
+void map_trim(vsaogm_map* m) {
+    DeviceGuard guard(m->device);
+    hip_check(hipDeviceSynchronize(), "trim: synchronise");
+    m->grids.clear();
+    m->d_partial.release();
+    m->w_key.release();
+    m->w_hist.release();
+    m->w_meta.release();
+    m->w_sorted.release();
+    m->w_sorted_lo.release();
+    m->w_partial.release();
+    m->w_table.release();
+    m->cap_n = 0;
+    m->cap_chunks = 0;
+    m->cap_echunks = 0;
+}
+
 struct UpdateBatchWork {
     DevBuf<unsigned char> d_meta;
     unsigned char* h_meta = nullptr;
@@ -691,6 +799,11 @@ struct UpdateBatchWork {
 
 UpdateBatchWork* update_batch_work_create() { return new UpdateBatchWork(); }
 void update_batch_work_destroy(UpdateBatchWork* w) { delete w; }
+int64_t update_batch_work_bytes(const UpdateBatchWork* w) { return nbytes(w->d_meta) + nbytes(w->d_partial); }
+void update_batch_work_trim(UpdateBatchWork* w) {
+    w->d_meta.release();
+    w->d_partial.release();
+}
 
 int run_update_batch(const UpdateItem* items, int count, int precision, hipStream_t s, UpdateBatchWork* w) {
     return guarded([&] {

@@ -16,7 +16,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <stdexcept>
@@ -68,14 +70,21 @@ struct DevMem {
         if (p) check_hip(hipFreeAsync(p, s), what);
         p = nullptr;
         bytes = 0;
-        size_t cap = 1 << 21;
-        while (cap < need) cap *= 2;
+        const size_t cap = round_up(need);
         check_hip(hipMallocAsync(&p, cap, s), what);
         bytes = cap;
     }
-    ~DevMem() {
+    // 2 MiB granules, so that a block exceeds what was asked for by less than one granule
+    static size_t round_up(size_t need) { return (need + kGranule - 1) / kGranule * kGranule; }
+    static constexpr size_t kGranule = size_t(1) << 21;
+    // the block ensure(need) would hold (0 if the current one suffices)
+    size_t growth(size_t need) const { return need <= bytes ? 0 : round_up(need); }
+    void release() {
         if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
     }
+    ~DevMem() { release(); }
 };
 
 struct HostMem {
@@ -158,7 +167,8 @@ int64_t footprint_of(const vsaogm_request& r, int32_t dim, int64_t nkeys) {
     // work items hold at least 64 points, plus one partial item per memory
     const int64_t encode_ws = n * 20 + (n / 64 + 1 + nkeys) * halfp * 8;
     const int64_t decode_ws = (int64_t)256 * 2 * 2 * 256 * 64 * 4;  // split-tile partial sums (upper bound)
-    return inputs + outputs + encode_ws + decode_ws;
+    // the slot's input and output blocks are rounded up to 2 MiB granules
+    return inputs + outputs + encode_ws + decode_ws + 2 * ((int64_t)1 << 21);
 }
 
 size_t up256(size_t v) { return (v + 255) / 256 * 256; }
@@ -187,11 +197,14 @@ struct Slot {
     std::vector<size_t> o_hmax, o_lab, o_ogm, o_heat;
     size_t back = 0;
     bool single = false;
+    int64_t counted = 0;   // device bytes of this slot counted in the executor's fixed bytes
 };
 
 class HipExecutor : public vsaogm::Executor {
 public:
-    HipExecutor(int device, int nslots, PinnedPool* pool) : device_(device), pool_(pool), slots_(nslots) {}
+    // trim_maps: release what every map rebuilds on demand and report each one's bytes after
+    HipExecutor(int device, int nslots, PinnedPool* pool, std::function<void(std::vector<int64_t>*)> trim_maps)
+        : device_(device), pool_(pool), slots_(nslots), trim_maps_(std::move(trim_maps)) {}
     ~HipExecutor() override {
         (void)hipSetDevice(device_);
         for (auto& s : slots_) {
@@ -231,7 +244,40 @@ public:
         // the event closes whatever was enqueued, so that completion waits for it
         if (hipEventRecord(s.done, s.stream) != hipSuccess && rc == VSAOGM_OK) rc = VSAOGM_EDEVICE;
         if (rc != VSAOGM_OK) (void)hipEventSynchronize(s.done);
+        count_slot(s);
         return rc;
+    }
+
+    void admission(const CoreRequest* q, int64_t* resident_now, int64_t* growth) override {
+        const Payload* p = static_cast<const Payload*>(q->payload);
+        const vsaogm_request& r = p->r;
+        const bool local = (r.flags & VSAOGM_REQUEST_LOCAL) != 0;
+        *resident_now = map_bytes(*p);
+        int64_t g = vsaogm::map_growth_bytes(p->map, &r.grid, r.precision, r.n, local);
+        if (local) {
+            const LocalHeat& lh = *p->local;
+            const bool same = lh.heat.p && lh.grid.nx == r.grid.nx && lh.grid.ny == r.grid.ny;
+            if (!same) g += (int64_t)lh.heat.growth((size_t)r.grid.nx * r.grid.ny * 8);
+        }
+        *growth = g;
+    }
+
+    int64_t fixed_bytes() override { return fixed_.load(); }
+
+    void reclaim(std::vector<int64_t>* resident) override {
+        (void)hipSetDevice(device_);
+        for (auto& s : slots_) {
+            (void)hipStreamSynchronize(s.stream);
+            s.d_in.release();
+            s.d_out.release();
+            vsaogm::update_batch_work_trim(s.work);
+            count_slot(s);
+        }
+        try {
+            trim_maps_(resident);
+        } catch (const std::exception&) {
+            // a map that could not be trimmed keeps its bytes (entries stay -1: unchanged)
+        }
     }
 
     int query(int si) override {
@@ -257,6 +303,7 @@ public:
             q->status = status;
             q->result[0] = p->hmax[0];
             q->result[1] = p->hmax[1];
+            q->resident_after = map_bytes(*p);   // the map is still this batch's alone
             release(q);
         }
     }
@@ -270,6 +317,16 @@ public:
     }
 
 private:
+    static int64_t map_bytes(const Payload& p) {
+        return vsaogm::map_resident_bytes(p.map) + (int64_t)p.local->heat.bytes;
+    }
+    // device bytes a slot keeps between batches (its streams' buffers and batch workspace)
+    void count_slot(Slot& s) {
+        const int64_t b = (int64_t)s.d_in.bytes + (int64_t)s.d_out.bytes + vsaogm::update_batch_work_bytes(s.work);
+        fixed_ += b - s.counted;
+        s.counted = b;
+    }
+
     void launch_single(Slot& s, Payload& p) {
         const vsaogm_request& r = p.r;
         const int64_t n = r.n, cells = (int64_t)r.grid.nx * r.grid.ny;
@@ -399,6 +456,8 @@ private:
     int device_;
     PinnedPool* pool_;
     std::vector<Slot> slots_;
+    std::function<void(std::vector<int64_t>*)> trim_maps_;
+    std::atomic<int64_t> fixed_{0};
 };
 
 }  // namespace
@@ -496,7 +555,17 @@ int vsaogm_server_create(const vsaogm_server_desc* d, vsaogm_server** out) {
             check_hip(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
             s->budget = (int64_t)(free_b / 4);
         }
-        s->exec = std::make_unique<HipExecutor>(d->device, d->max_inflight, &s->pool);
+        vsaogm_server* sp = s.get();
+        s->exec = std::make_unique<HipExecutor>(d->device, d->max_inflight, &s->pool, [sp](std::vector<int64_t>* res) {
+            // nothing is in flight: trim every map (the local heat buffers are rebuilt too)
+            std::lock_guard<std::mutex> lk(sp->mu);
+            for (size_t m = 0; m < sp->maps.size(); ++m) {
+                vsaogm::map_trim(sp->maps[m]);
+                sp->local_heat[m]->heat.release();
+                sp->local_heat[m]->grid = vsaogm_grid_desc{};
+                if (m < res->size()) (*res)[m] = vsaogm::map_resident_bytes(sp->maps[m]);
+            }
+        });
         s->exec->init();
         vsaogm::SchedulerConfig cfg;
         cfg.slots = d->max_inflight;
@@ -535,7 +604,15 @@ int vsaogm_server_add_map(vsaogm_server* s, const vsaogm_map_desc* d, int32_t* m
         s->map_dim.push_back(dd.dim);
         s->map_keys.push_back(2 * (int64_t)dd.tiles_x * dd.tiles_y);
         s->local_heat.push_back(std::make_unique<LocalHeat>());
-        const int id = s->sched->add_map();
+        const int id = s->sched->add_map(vsaogm::map_resident_bytes(m));
+        if (id < 0) {
+            s->maps.pop_back();
+            s->map_dim.pop_back();
+            s->map_keys.pop_back();
+            s->local_heat.pop_back();
+            vsaogm_map_destroy(m);
+            throw Fail(VSAOGM_ENOMEM, "the map's memories do not fit the server's memory budget");
+        }
         *map_id = (int32_t)s->maps.size() - 1;
         if (id != *map_id) throw Fail(VSAOGM_EDEVICE, "map tables out of step");
     });
@@ -611,6 +688,13 @@ int vsaogm_server_drain(vsaogm_server* s) {
 int vsaogm_server_stats(vsaogm_server* s, int64_t* completed, int64_t* peak_bytes, int64_t* budget_bytes) {
     if (!s) return VSAOGM_EINVAL;
     s->sched->stats(completed, peak_bytes, budget_bytes, nullptr);
+    return VSAOGM_OK;
+}
+
+int vsaogm_server_memory(vsaogm_server* s, int64_t* in_flight, int64_t* resident, int64_t* fixed,
+                         int64_t* reclaims) {
+    if (!s) return VSAOGM_EINVAL;
+    s->sched->memory(in_flight, resident, fixed, reclaims);
     return VSAOGM_OK;
 }
 

@@ -8,7 +8,15 @@
 // flight, or an earlier request still pending, waits (updates of one map run in submission
 // order: memories are state); requests of other maps pass it.  A request that does not fit the
 // remaining budget stops admission (first come, first served: nothing behind it is admitted
-// until running requests release their bytes).  Requests of distinct maps with the same
+// until running requests release their bytes).
+//
+// Budget.  The bytes counted against it are those of the requests in flight (each charged its
+// transient bytes plus an upper bound on what its run can add to its map's resident memory,
+// asked of the executor at admission, when the map is idle), the resident bytes of every map
+// (reported at admission and at completion) and the executor's fixed buffers.  When nothing
+// is in flight and the first waiting request still does not fit, the executor is asked once to
+// reclaim what the maps rebuild on demand; if it still does not fit, it completes with
+// kCoreNomem without running.  Requests of distinct maps with the same
 // precision and the batchable flag are admitted together into one batch of at most max_batch;
 // a request that is not batchable runs alone in its slot.
 #pragma once
@@ -49,6 +57,8 @@ struct CoreRequest {
     int64_t t_submit_ns = 0, t_start_ns = 0, t_done_ns = 0;
     float result[2] = {0.f, 0.f}; // values the executor reports with the status (class maxima)
     void* payload = nullptr;     // the executor's view of the request (inputs, outputs)
+    int64_t charge = 0;          // bytes held against the budget while in flight
+    int64_t resident_after = -1; // the map's resident bytes after the run (set by complete)
 };
 
 // Runs batches on execution slots.  launch() enqueues the batch's work on the slot and returns
@@ -63,8 +73,20 @@ public:
     virtual int launch(int slot, const std::vector<CoreRequest*>& batch) = 0;
     virtual int query(int slot) = 0;
     virtual void complete(int slot, const std::vector<CoreRequest*>& batch, int status) = 0;
-    // called when the request is dropped without running (server shut down with it pending)
+    // called when the request is dropped without running (server shut down with it pending,
+    // or refused for memory)
     virtual void release(CoreRequest*) {}
+    // At admission (scheduler lock held, the request's map idle): the map's resident bytes now
+    // (-1: unchanged) and an upper bound on what the request's run can add to them.
+    virtual void admission(const CoreRequest*, int64_t* resident_now, int64_t* growth) {
+        *resident_now = -1;
+        *growth = 0;
+    }
+    // Device bytes of the executor's own buffers (read under the scheduler lock; thread-safe).
+    virtual int64_t fixed_bytes() { return 0; }
+    // Nothing in flight: release what can be rebuilt on demand; resident[m] = map m's bytes
+    // after (entries left at -1 are unchanged).
+    virtual void reclaim(std::vector<int64_t>* resident) { (void)resident; }
 };
 
 struct SchedulerConfig {
@@ -99,9 +121,14 @@ public:
         threads_.clear();
     }
 
-    int add_map() {
+    // A new map holding resident bytes already; -1 (and no map) if they do not fit the budget.
+    int add_map(int64_t resident = 0) {
         std::lock_guard<std::mutex> lk(mu_);
+        if (resident_ + resident + ex_->fixed_bytes() > cfg_.budget) return -1;
         map_busy_.push_back(0);
+        map_resident_.push_back(resident);
+        resident_ += resident;
+        peak_ = std::max(peak_, used_ + resident_ + ex_->fixed_bytes());
         return (int)map_busy_.size() - 1;
     }
     int num_maps() {
@@ -169,14 +196,26 @@ public:
         std::unique_lock<std::mutex> lk(mu_);
         cv_done_.wait(lk, [&] { return pending_.empty() && inflight_ == 0; });
     }
-    void stats(int64_t* completed, int64_t* peak, int64_t* budget, int64_t* batches) {
+    void stats(int64_t* completed, int64_t* peak, int64_t* budget, int64_t* batches, int64_t* resident = nullptr,
+               int64_t* reclaims = nullptr) {
         std::lock_guard<std::mutex> lk(mu_);
         if (completed) *completed = completed_;
         if (peak) *peak = peak_;
         if (budget) *budget = cfg_.budget;
         if (batches) *batches = batches_;
+        if (resident) *resident = resident_;
+        if (reclaims) *reclaims = reclaims_;
     }
     int64_t budget() const { return cfg_.budget; }
+    // Bytes counted against the budget now: in-flight charges, maps' resident bytes, the
+    // executor's fixed buffers; and how many reclaims ran.
+    void memory(int64_t* in_flight, int64_t* resident, int64_t* fixed, int64_t* reclaims) {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (in_flight) *in_flight = used_;
+        if (resident) *resident = resident_;
+        if (fixed) *fixed = ex_->fixed_bytes();
+        if (reclaims) *reclaims = reclaims_;
+    }
 
 private:
     struct SlotState {
@@ -199,6 +238,7 @@ private:
     // Admission for one free slot (lock held): the batch to launch there, possibly empty.
     std::vector<CoreRequest*> admit_locked() {
         std::vector<CoreRequest*> batch;
+        if (reclaiming_) return batch;
         std::unordered_set<int32_t> blocked;   // maps with an earlier request still waiting
         for (auto it = pending_.begin(); it != pending_.end();) {
             CoreRequest* q = *it;
@@ -216,9 +256,35 @@ private:
                     continue;
                 }
             }
-            if (used_ + q->bytes > cfg_.budget) break;   // first come, first served
-            used_ += q->bytes;
-            peak_ = std::max(peak_, used_);
+            int64_t now = -1, grow = 0;
+            ex_->admission(q, &now, &grow);
+            if (now >= 0) {
+                resident_ += now - map_resident_[q->map];
+                map_resident_[q->map] = now;
+            }
+            const int64_t charge = q->bytes + std::max<int64_t>(grow, 0);
+            const int64_t fixed = ex_->fixed_bytes();
+            if (used_ + resident_ + fixed + charge > cfg_.budget) {   // first come, first served
+                if (inflight_ == 0 && batch.empty()) {
+                    if (!reclaimed_) {
+                        want_reclaim_ = true;   // the worker reclaims outside the lock
+                    } else {
+                        // cannot fit even with everything reclaimed: refuse it
+                        it = pending_.erase(it);
+                        q->status = kCoreNomem;
+                        q->t_start_ns = q->t_done_ns = steady_ns();
+                        q->done = true;
+                        ++completed_;
+                        ex_->release(q);
+                        refused_ = true;
+                        continue;
+                    }
+                }
+                break;
+            }
+            q->charge = charge;
+            used_ += charge;
+            peak_ = std::max(peak_, used_ + resident_ + fixed);
             map_busy_[q->map] = 1;
             ++inflight_;
             batch.push_back(q);
@@ -253,7 +319,12 @@ private:
                     for (CoreRequest* q : s.batch) {
                         if (q->status == kCoreAgain) q->status = st;
                         q->t_done_ns = t;
-                        used_ -= q->bytes;
+                        used_ -= q->charge;
+                        if (q->resident_after >= 0) {
+                            resident_ += q->resident_after - map_resident_[q->map];
+                            map_resident_[q->map] = q->resident_after;
+                        }
+                        reclaimed_ = false;   // progress: a later blockage may reclaim again
                         map_busy_[q->map] = 0;
                         q->done = true;
                         ++completed_;
@@ -268,11 +339,22 @@ private:
                 progressed = true;
             }
             std::vector<std::pair<int, std::vector<CoreRequest*>>> to_launch;
+            bool reclaim = false;
             {
                 std::unique_lock<std::mutex> lk(mu_);
                 if (stopping_ && pending_.empty() && inflight_ == 0) break;
                 while (!free_slots.empty()) {
                     std::vector<CoreRequest*> b = admit_locked();
+                    if (refused_) {
+                        refused_ = false;
+                        cv_done_.notify_all();
+                    }
+                    if (want_reclaim_ && inflight_ == 0 && !reclaiming_) {
+                        want_reclaim_ = false;
+                        reclaiming_ = true;   // no admission anywhere until it is done
+                        reclaim = true;
+                        break;
+                    }
                     if (b.empty()) break;
                     const int si = free_slots.back();
                     free_slots.pop_back();
@@ -281,7 +363,7 @@ private:
                     slots_[si].batch = b;
                     to_launch.emplace_back(si, std::move(b));
                 }
-                if (to_launch.empty() && !progressed) {
+                if (to_launch.empty() && !progressed && !reclaim) {
                     bool mine = false;
                     for (int i = s0; i < s1; ++i) mine = mine || !slots_[i].batch.empty();
                     // a system-clock deadline (pthread_cond_timedwait), which thread sanitizers
@@ -296,6 +378,24 @@ private:
                 for (CoreRequest* q : b) q->t_start_ns = t;
                 slots_[si].launch_status = ex_->launch(si, b);
             }
+            if (reclaim) {
+                std::vector<int64_t> res;
+                {
+                    std::lock_guard<std::mutex> lk(mu_);
+                    res.assign(map_resident_.size(), -1);
+                }
+                ex_->reclaim(&res);
+                std::lock_guard<std::mutex> lk(mu_);
+                for (size_t m = 0; m < res.size() && m < map_resident_.size(); ++m)
+                    if (res[m] >= 0) {
+                        resident_ += res[m] - map_resident_[m];
+                        map_resident_[m] = res[m];
+                    }
+                ++reclaims_;
+                reclaimed_ = true;
+                reclaiming_ = false;
+                cv_work_.notify_all();
+            }
         }
     }
 
@@ -309,9 +409,11 @@ private:
     std::deque<CoreRequest*> pending_;
     std::unordered_map<uint64_t, std::unique_ptr<CoreRequest>> tickets_;
     std::vector<char> map_busy_;
+    std::vector<int64_t> map_resident_;
     uint64_t next_ticket_ = 1;
-    int64_t used_ = 0, peak_ = 0, completed_ = 0, batches_ = 0;
+    int64_t used_ = 0, resident_ = 0, peak_ = 0, completed_ = 0, batches_ = 0, reclaims_ = 0;
     int inflight_ = 0;
+    bool want_reclaim_ = false, reclaiming_ = false, reclaimed_ = false, refused_ = false;
 };
 
 }  // namespace vsaogm

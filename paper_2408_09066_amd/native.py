@@ -24,7 +24,7 @@ EXPORTED = [
     "vsaogm_decode", "vsaogm_classify", "vsaogm_memories", "vsaogm_fuse",
     "vsaogm_profile_events", "vsaogm_server_create", "vsaogm_server_destroy",
     "vsaogm_server_add_map", "vsaogm_server_get_map", "vsaogm_submit", "vsaogm_poll",
-    "vsaogm_wait", "vsaogm_server_drain", "vsaogm_server_stats", "vsaogm_submit_many",
+    "vsaogm_wait", "vsaogm_server_drain", "vsaogm_server_stats", "vsaogm_server_memory", "vsaogm_submit_many",
     "vsaogm_classify_ex", "vsaogm_decode_incremental", "vsaogm_request_bytes",
     "vsaogm_volume_create", "vsaogm_volume_destroy", "vsaogm_volume_reset", "vsaogm_volume_encode",
     "vsaogm_volume_take_rejected", "vsaogm_volume_decode", "vsaogm_classify3",
@@ -127,6 +127,7 @@ def load(path: str = LIB_PATH):
     L.vsaogm_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
     L.vsaogm_server_drain.argtypes = [P]
     L.vsaogm_server_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.vsaogm_server_memory.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.vsaogm_request_bytes.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(i64)]
     L.vsaogm_volume_create.argtypes = [ctypes.POINTER(VolumeDesc), ctypes.POINTER(P)]
     L.vsaogm_volume_destroy.argtypes = [P]
@@ -551,3 +552,9 @@ class Server:
         c, p, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         check(load().vsaogm_server_stats(self._h, ctypes.byref(c), ctypes.byref(p), ctypes.byref(b)))
         return {"completed": c.value, "peak_bytes": p.value, "budget_bytes": b.value}
+
+    def memory(self):
+        """Budget bytes now: in flight, resident in the maps, the slots' fixed buffers; reclaims."""
+        v = [ctypes.c_int64() for _ in range(4)]
+        check(load().vsaogm_server_memory(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("in_flight", "resident", "fixed", "reclaims"), (x.value for x in v)))

@@ -289,11 +289,137 @@ void test_budget_blocks_later_requests() {
     s.stop();
 }
 
+// Maps that cache grids: each request decodes one of a few grids; a grid not yet cached costs
+// kGrid resident bytes from its run on.  The executor tracks the bytes it really holds (maps'
+// resident bytes plus in-flight transient buffers) and checks them against the budget at every
+// launch; reclaim drops every cached grid.
+class CachingExecutor : public Executor {
+public:
+    static constexpr int64_t kBase = 100, kGrid = 300;
+    CachingExecutor(int slots, int nmaps, int64_t budget)
+        : cached_(nmaps), running_(slots), budget_(budget) {}
+
+    struct Req {
+        int map, grid;
+        int64_t transient;
+        bool ran = false;
+    };
+    int64_t resident_of(int m) const { return kBase + (int64_t)cached_[m].size() * kGrid; }
+
+    void admission(const CoreRequest* q, int64_t* now, int64_t* growth) override {
+        std::lock_guard<std::mutex> lk(mu_);
+        const Req* r = static_cast<const Req*>(q->payload);
+        *now = resident_of(r->map);
+        *growth = cached_[r->map].count(r->grid) ? 0 : kGrid;
+    }
+    int launch(int slot, const std::vector<CoreRequest*>& batch) override {
+        std::lock_guard<std::mutex> lk(mu_);
+        for (CoreRequest* q : batch) {
+            Req* r = static_cast<Req*>(q->payload);
+            cached_[r->map].insert(r->grid);   // the run builds the grid's tables
+            transient_ += r->transient;
+            r->ran = true;
+        }
+        running_[slot] = batch.size();
+        int64_t held = transient_;
+        for (size_t m = 0; m < cached_.size(); ++m) held += resident_of((int)m);
+        peak_held = std::max(peak_held, held);
+        if (held > budget_) over_budget = true;
+        return kCoreOk;
+    }
+    int query(int) override { return kCoreOk; }
+    void complete(int, const std::vector<CoreRequest*>& batch, int status) override {
+        std::lock_guard<std::mutex> lk(mu_);
+        for (CoreRequest* q : batch) {
+            Req* r = static_cast<Req*>(q->payload);
+            transient_ -= r->transient;
+            q->status = status;
+            q->resident_after = resident_of(r->map);
+            delete r;
+            q->payload = nullptr;
+        }
+    }
+    void release(CoreRequest* q) override {
+        delete static_cast<Req*>(q->payload);
+        q->payload = nullptr;
+        ++released;
+    }
+    void reclaim(std::vector<int64_t>* res) override {
+        std::lock_guard<std::mutex> lk(mu_);
+        ++reclaims;
+        for (size_t m = 0; m < cached_.size(); ++m) {
+            cached_[m].clear();
+            if (m < res->size()) (*res)[m] = resident_of((int)m);
+        }
+    }
+
+    std::mutex mu_;
+    std::vector<std::set<int>> cached_;
+    std::vector<size_t> running_;
+    int64_t budget_, transient_ = 0, peak_held = 0;
+    int reclaims = 0, released = 0;
+    bool over_budget = false;
+};
+
+std::unique_ptr<CoreRequest> make_cached(int map, int grid, int64_t transient) {
+    auto q = std::make_unique<CoreRequest>();
+    q->map = map;
+    q->bytes = transient;
+    q->precision = 3;
+    q->batchable = true;
+    q->payload = new CachingExecutor::Req{map, grid, transient};
+    return q;
+}
+
+// Resident bytes count against the budget, grid caches are reclaimed when nothing runs and the
+// next request does not fit, and a request too large even then completes with kCoreNomem.
+void test_resident_bytes_and_reclaim() {
+    SchedulerConfig cfg;
+    cfg.slots = 4;
+    cfg.workers = 2;
+    cfg.max_batch = 2;
+    cfg.poll_us = 1;
+    const int nmaps = 4;
+    cfg.budget = nmaps * CachingExecutor::kBase + 3 * CachingExecutor::kGrid + 200;   // 4 maps, 3 grids
+    CachingExecutor ex(cfg.slots, nmaps, cfg.budget);
+    Scheduler s(cfg, &ex);
+    for (int m = 0; m < nmaps; ++m) CHECK(s.add_map(CachingExecutor::kBase) == m);
+    CHECK(s.add_map(cfg.budget) == -1);   // a map as large as the budget does not fit beside them
+    s.start();
+    std::mt19937 rng(5);
+    std::vector<uint64_t> tickets;
+    std::vector<int> expect;
+    for (int i = 0; i < 200; ++i) {
+        const bool huge = (i == 120);
+        const int m = (int)(rng() % nmaps), g = (int)(rng() % 5);
+        auto q = make_cached(m, g, huge ? cfg.budget - nmaps * CachingExecutor::kBase : 20 + (int64_t)(rng() % 60));
+        uint64_t t = 0;
+        CHECK(s.submit(q, &t) == kCoreOk);
+        tickets.push_back(t);
+        expect.push_back(huge ? kCoreNomem : kCoreOk);
+    }
+    for (size_t i = 0; i < tickets.size(); ++i) {
+        CoreRequest r;
+        CHECK(s.wait(tickets[i], &r) == kCoreOk);
+        CHECK(r.status == expect[i]);
+    }
+    int64_t completed = 0, peak = 0, budget = 0, batches = 0, resident = 0, reclaims = 0;
+    s.stats(&completed, &peak, &budget, &batches, &resident, &reclaims);
+    CHECK(completed == 200);
+    CHECK(peak <= budget);
+    CHECK(reclaims >= 1 && reclaims == ex.reclaims);
+    CHECK(ex.released == 1);   // the refused one
+    CHECK(!ex.over_budget);
+    CHECK(ex.peak_held <= cfg.budget);
+    s.stop();
+}
+
 int main() {
     test_stream_order_batches_budget();
     test_backpressure_and_refusals();
     test_injected_failures();
     test_budget_blocks_later_requests();
+    test_resident_bytes_and_reclaim();
     if (g_failures) {
         std::fprintf(stderr, "%d check(s) failed\n", g_failures);
         return 1;

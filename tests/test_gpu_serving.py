@@ -107,18 +107,76 @@ def test_alone_and_in_the_mix_agree(torch_cuda, stream):
 
 
 def test_tight_budget_still_completes(torch_cuda, stream):
-    """Admission waits for memory: a budget for about one request at a time still finishes."""
+    """Admission waits for memory: a budget for the maps' own buffers and about one request at
+    a time (no room for every grid's tables at once) still finishes, and the server's count
+    stays within it."""
     say("[gpu] tight budget")
     maps, reqs = stream
     from paper_2408_09066_amd import native
     probe = native.Server(max_inflight=1)
     ids = [probe.add_map(m.theta, m.layout, m.tiles) for m in maps]
-    budget = max(probe.request_bytes(ids[q.map_id], q.xy.shape[0], maps[q.map_id].grid, maps[q.map_id].side,
-                                     maps[q.map_id].side) for q in reqs[:12]) + 4096
+    base = probe.memory()["resident"]
+    one = max(probe.request_bytes(ids[q.map_id], q.xy.shape[0], maps[q.map_id].grid, maps[q.map_id].side,
+                                  maps[q.map_id].side) for q in reqs[:12])
     probe.close()
+    budget = base + 2 * one + (256 << 20)
     res, st = served(maps, reqs[:12], "fp32", max_inflight=4, budget=budget)
     assert st["completed"] == 12
     assert st["peak_bytes"] <= budget
+
+
+def test_budget_bounds_device_memory(torch_cuda):
+    """What the server holds on the device -- maps, cached grids, workspaces, slot buffers,
+    requests in flight -- stays within its budget, measured as the drop of the device's free
+    memory, over a stream that decodes three grid sizes per map (more grid tables than the
+    budget holds: the server must release cached grids to go on)."""
+    say("[gpu] budget bounds device memory")
+    torch = torch_cuda
+    from paper_2408_09066_amd import native
+    rng = np.random.default_rng(9066)
+    D, T, res = 8192, 2, 0.05
+    sides = (1200, 1500, 1800)
+    nmaps = 4
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0, _ = torch.cuda.mem_get_info()
+    probe = native.Server(max_inflight=4)
+    half = max(sides) * res / 2.0
+    layout = (-half, -half, half, half)
+    thetas = [synth.make_theta(D, 0.25, rng) for _ in range(nmaps)]
+    for th in thetas:
+        probe.add_map(th, layout, (T, T))
+    base = probe.memory()["resident"]
+    probe.close()
+    budget = base + (1 << 30)
+    srv = native.Server(max_inflight=4, hbm_budget_bytes=budget)
+    ids = [srv.add_map(th, layout, (T, T)) for th in thetas]
+    items = []
+    for i in range(36):
+        side = sides[i % 3]
+        h = side * res / 2.0
+        n = 20000
+        xy = np.stack([rng.uniform(-h, h, n), rng.uniform(-h, h, n)], 1).astype(np.float32)
+        lb = rng.integers(0, 2, n).astype(np.uint8)
+        items.append({"map_id": ids[(i // 3) % nmaps], "xy": xy, "label": lb, "grid": (-h, -h, res),
+                      "nx": side, "ny": side, "r_occ": 2, "r_emp": 2,
+                      "precision": ("bf16x3", "fp32", "bf16")[(i // 2) % 3]})
+    tk = srv.submit_many(items)
+    out = [srv.wait(t) for t, _ in tk]
+    assert all(r["status"] == 0 for r in out)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    mem = srv.memory()
+    st = srv.stats()
+    held = free0 - free1
+    say(f"  budget {budget / 2**20:.0f} MiB, peak counted {st['peak_bytes'] / 2**20:.0f} MiB, device drop "
+        f"{held / 2**20:.0f} MiB, reclaims {mem['reclaims']}, resident {mem['resident'] / 2**20:.0f} MiB, "
+        f"fixed {mem['fixed'] / 2**20:.0f} MiB")
+    assert st["peak_bytes"] <= budget
+    assert mem["reclaims"] >= 1
+    # the allocator rounds blocks up and the runtime holds its own queues and events
+    assert held <= budget + (128 << 20)
+    srv.close()
 
 
 def test_served_update_matches_oracle(torch_cuda):
