@@ -170,7 +170,7 @@ struct DecodeArgs {
     long long total_steps;     // fp32 kernel: ntiles * ksteps
     // 16-bit kernels: work units (a K range of one tile), in K order within a tile; tile t's
     // units are tile_u0[t] .. tile_u0[t + 1] - 1 and workgroup w runs units wg_u0[w] ..
-    // wg_u0[w + 1] - 1 (one, or two where its range crosses a tile border).
+    // wg_u0[w + 1] - 1; a unit that is not a whole tile writes partial block unit.part.
     const DUnit* units;
     int nunits;
     const int* tile_u0;
@@ -719,7 +719,7 @@ __global__ __launch_bounds__(Wide<PREC>::NT, Wide<PREC>::OCC) void k_decode16(De
         if (NSETS > 2 && kk + 1 < n) step(std::integral_constant<int, 1>{}, kk + 1);
 
         const bool whole = (kb0 == 0 && kb1 == ks);
-        gmem_rw<float>* part = as_global_rw(a.partial + (size_t)ui * 2 * TR * kTileCols);
+        gmem_rw<float>* part = as_global_rw(a.partial + (size_t)unit.part * 2 * TR * kTileCols);
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
             float mx = -INFINITY;
@@ -790,7 +790,7 @@ __global__ __launch_bounds__(256) void k_decode_fix(DecodeArgs ab) {
     // segments in workgroup order, four at a time so that their loads are in flight together
     // (a segment past the last one reloads the last and adds nothing)
     auto seg = [&](int w) {
-        if (ab.units) return as_global(a.partial + (size_t)w * PER_TILE + partk * (PER_TILE / PARTS));
+        if (ab.units) return as_global(a.partial + (size_t)ab.units[w].part * PER_TILE + partk * (PER_TILE / PARTS));
         const int slot = ((long long)w * steps_per_wg / ab.ksteps == ti) ? 0 : 1;
         return as_global(a.partial + ((size_t)w * 2 + slot) * PER_TILE + partk * (PER_TILE / PARTS));
     };
@@ -1040,36 +1040,48 @@ hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s) {
 // prologue, epilogue and partial-sum traffic).
 constexpr int kMinUnitSteps = 16;
 
+// K steps per workgroup for n tiles of ks steps on slots resident workgroups: whole tiles when
+// there are at least slots of them and the last round of workgroups is at least 90 % full;
+// otherwise equal consecutive ranges, about one per slot (at least kMinUnitSteps steps, at most
+// one tile when the tiles are fewer than the slots).
+__host__ __device__ inline long long unit_range(long long n, long long ks, long long slots) {
+    if (n <= 0) return ks;
+    const long long rounds = (n + slots - 1) / slots;
+    if (n >= slots && 10 * n >= 9 * rounds * slots) return ks;
+    long long L = (n * ks + slots - 1) / slots;
+    if (L < kMinUnitSteps) L = kMinUnitSteps;
+    if (n < slots && L > ks) L = ks;
+    return L;
+}
+
 void decode_units(int ntiles, int ksteps, int num_cus, int tile_base, int unit_base, std::vector<DUnit>& units,
                   std::vector<int>& tile_u0, std::vector<int>& wg_u0) {
-    // Whole tiles when there are enough of them to occupy every CU.  Otherwise the request's
-    // ntiles * ksteps K steps are cut into equal consecutive ranges, one per workgroup, about one
-    // per CU (at least kMinUnitSteps steps each); a range that crosses a tile border is two
-    // units of the same workgroup.  The cut depends on the request alone, so its tiles' sums
+    // The request's ntiles * ksteps K steps are cut into consecutive ranges, one per workgroup
+    // (unit_range); a range is one unit per tile it touches.  Only a range's first and last
+    // units can be parts of a tile; they write partial blocks 2w and 2w + 1 (w: the
+    // workgroup within the request).  The cut depends on the request alone, so its tiles' sums
     // (partials added in unit order) are the same whatever else shares the launch.
     const int slots = Wide<1>::OCC * num_cus;
-    const long long total = (long long)ntiles * ksteps;
-    long long L = ksteps;
-    if (ntiles > 0 && ntiles < slots)
-        L = std::min<long long>(ksteps, std::max<long long>((total + slots - 1) / slots, kMinUnitSteps));
-    int u = unit_base, cur = -1;
-    for (long long it0 = 0; it0 < total; it0 += L) {
+    const long long ks = ksteps, total = (long long)ntiles * ks;
+    const long long L = unit_range(ntiles, ks, slots);
+    int u = unit_base, cur = -1, w = 0;
+    for (long long it0 = 0; it0 < total; it0 += L, ++w) {
         const long long it1 = std::min(total, it0 + L);
         wg_u0.push_back(u);
         for (long long it = it0; it < it1;) {
-            const int t = (int)(it / ksteps);
-            const int kb0 = (int)(it - (long long)t * ksteps);
-            const int kb1 = (int)std::min<long long>(ksteps, it1 - (long long)t * ksteps);
+            const int t = (int)(it / ks);
+            const int kb0 = (int)(it - (long long)t * ks);
+            const int kb1 = (int)std::min<long long>(ks, it1 - (long long)t * ks);
             for (; cur < t; ++cur) tile_u0.push_back(u);   // tile t starts at this unit
-            units.push_back(DUnit{tile_base + t, kb0, kb1, 0});
+            units.push_back(DUnit{tile_base + t, kb0, kb1, 2 * w + (it == it0 ? 0 : 1)});
             ++u;
-            it = (long long)t * ksteps + kb1;
+            it = (long long)t * ks + kb1;
         }
     }
     for (; cur + 1 < ntiles; ++cur) tile_u0.push_back(u);   // no K steps: tiles without units
 }
 
-size_t decode_unit_partial_floats(int nunits) { return (size_t)nunits * 2 * Wide<1>::TR * kTileCols; }
+size_t decode_unit_partial_floats(int nblocks) { return (size_t)nblocks * 2 * Wide<1>::TR * kTileCols; }
 
 hipError_t launch_decode_batch(int precision, const DecodeBatch& b, hipStream_t s) {
     if (precision < 1 || precision > 3) return hipErrorInvalidValue;
@@ -1170,40 +1182,36 @@ __global__ __launch_bounds__(kPlanThreads) void k_inc_plan(IncPlan a) {
         nb += tot;
     }
     const long long ks = a.ksteps16, total = (long long)n * ks;
-    long long L = ks;
-    if (n > 0 && n < a.slots16)
-        L = min(ks, max((total + a.slots16 - 1) / a.slots16, (long long)kMinUnitSteps));
+    const long long L = unit_range(n, ks, a.slots16);
     const int nwg = total > 0 ? (int)((total + L - 1) / L) : 0;
-    int crossed = 0;   // workgroups so far whose range crosses a tile border
+    int extra = 0;   // units so far beyond one per workgroup (tile borders inside ranges)
     for (int c0 = 0; c0 < nwg; c0 += kPlanThreads) {
         const int w = c0 + tid;
         long long it0 = 0, it1 = 0;
-        int t = 0, c = 0;
+        int t0 = 0, pieces = 0;
         if (w < nwg) {
             it0 = (long long)w * L;
             it1 = min(total, it0 + L);
-            t = (int)(it0 / ks);
-            c = ((it1 - 1) / ks != t) ? 1 : 0;   // L <= ks: at most one border inside
+            t0 = (int)(it0 / ks);
+            pieces = (int)((it1 - 1) / ks) - t0 + 1;
         }
         int tot;
-        const int pos = plan_scan(c, s_w, &tot);
+        const int pos = plan_scan(pieces > 0 ? pieces - 1 : 0, s_w, &tot);
         if (w < nwg) {
-            const int u = w + crossed + pos;
-            const int kb0 = (int)(it0 - (long long)t * ks);
+            const int u = w + extra + pos;
             a.wg_u0[w] = u;
-            if (kb0 == 0) a.tile_u0[t] = u;
-            if (c) {
-                a.units[u] = DUnit{t, kb0, (int)ks, 0};
-                a.units[u + 1] = DUnit{t + 1, 0, (int)(it1 - (long long)(t + 1) * ks), 0};
-                a.tile_u0[t + 1] = u + 1;
-            } else {
-                a.units[u] = DUnit{t, kb0, (int)(it1 - (long long)t * ks), 0};
+            for (int j = 0; j < pieces; ++j) {
+                const int t = t0 + j;
+                const int kb0 = j == 0 ? (int)(it0 - (long long)t0 * ks) : 0;
+                const int kb1 = (int)min(ks, it1 - (long long)t * ks);
+                if (kb0 == 0) a.tile_u0[t] = u + j;
+                a.units[u + j] = DUnit{t, kb0, kb1, 2 * w + (j == 0 ? 0 : 1)};
             }
         }
-        crossed += tot;
+        extra += tot;
     }
     if (tid == 0) {
-        const int nunits = nwg + crossed;
+        const int nunits = nwg + extra;
         a.wg_u0[nwg] = nunits;
         a.tile_u0[n] = nunits;
         const long long total32 = (long long)n * a.ksteps32;

@@ -309,7 +309,8 @@ hipError_t launch_table_split(const double* theta_rad, int axis, const double* l
                               int half, int halfp, bool fp16, void* hi, void* lo, hipStream_t s);
 
 struct DUnit {
-    int tile, kb0, kb1, pad;
+    int tile, kb0, kb1;
+    int part;   // partial-sum block, used when the unit is not a whole tile
 };
 
 // One request of a batched similarity GEMM (the per-map, per-grid fields of a decode).
@@ -336,15 +337,17 @@ struct DecodePlan {
     long long total_steps; // tiles * ksteps
 };
 DecodePlan decode_plan(int precision, int ntiles, int halfp, int num_cus);
-// Work units of the 16-bit similarity GEMM: a K range of one tile; each workgroup runs one
-// unit, or two where its K range crosses a tile border.  A request's units depend only on its
-// own tile count and K steps, so its fp32 accumulation order is the same whether it is decoded
-// alone or in a batch.  Appends the units of tiles tile_base .. tile_base + ntiles - 1
-// (numbered from unit_base), each tile's first unit and each workgroup's first unit; the caller
-// appends the closing entries of tile_u0 and wg_u0.
+// Work units of the 16-bit similarity GEMM: a K range of one tile.  Each workgroup runs a
+// range of consecutive K steps of the request (whole tiles, or equal ranges when that balances
+// the CUs better), one unit per tile the range touches; a unit that is part of a tile writes
+// partial block DUnit::part (2w or 2w + 1 for the request's workgroup w).  A request's units
+// depend only on its own tile count and K steps, so its fp32 accumulation order is the same
+// whether it is decoded alone or in a batch.  Appends the units of tiles tile_base ..
+// tile_base + ntiles - 1 (numbered from unit_base), each tile's first unit and each
+// workgroup's first unit; the caller appends the closing entries of tile_u0 and wg_u0.
 void decode_units(int ntiles, int ksteps, int num_cus, int tile_base, int unit_base, std::vector<DUnit>& units,
                   std::vector<int>& tile_u0, std::vector<int>& wg_u0);
-size_t decode_unit_partial_floats(int nunits);   // partial sums of split tiles
+size_t decode_unit_partial_floats(int nblocks);   // partial-sum blocks of split tiles
 
 // A batched 16-bit similarity GEMM: tiles of several requests (DTile::pad = request index).
 struct DecodeBatch {
@@ -356,7 +359,7 @@ struct DecodeBatch {
     const int* tile_u0;        // device [ntiles + 1]
     const int* wg_u0;          // device [nwg + 1]
     int nwg;                   // workgroups of the GEMM
-    float* partial;            // decode_unit_partial_floats(nunits) when any_split
+    float* partial;            // decode_unit_partial_floats(partial blocks) when any_split
     bool any_split;            // some tile has several units (a fix-up pass runs)
 };
 hipError_t launch_decode_batch(int precision, const DecodeBatch& b, hipStream_t s);

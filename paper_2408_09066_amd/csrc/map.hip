@@ -154,7 +154,7 @@ size_t set_units(DecodeLaunch& d, const UnitPlan& h, const DevUnits& dv, int nti
     d.wg_u0 = dv.wg_u0.p;
     d.nwg = h.nwg();
     d.any_split = d.nunits > ntiles;   // every tile has a unit, so some tile has several
-    return d.any_split ? decode_unit_partial_floats(d.nunits) : 0;
+    return d.any_split ? decode_unit_partial_floats(2 * d.nwg) : 0;   // blocks 2w, 2w + 1
 }
 
 __global__ void k_zero_words(unsigned* p, size_t n) {
@@ -834,6 +834,7 @@ int run_update_batch(const UpdateItem* items, int count, int precision, hipStrea
         std::vector<DTile> tiles;
         std::vector<DUnit> units;
         std::vector<int> tile_u0, wg_u0;
+        int pblocks = 0;   // partial-sum blocks of the requests with split tiles
         int num_cus = 1, max_r = 0;
         for (int i = 0; i < count; ++i) {
             const UpdateItem& it = items[i];
@@ -885,10 +886,13 @@ int run_update_batch(const UpdateItem* items, int count, int precision, hipStrea
                 tiles.push_back(t);
             }
             const UnitPlan& up = gc->uplan[set];
+            const bool split = up.units.size() > gc->host_tiles[set].size();
             for (DUnit u : up.units) {
                 u.tile += tile_base;
+                u.part += pblocks;   // partial blocks of the request's workgroups, after the others'
                 units.push_back(u);
             }
+            if (split) pblocks += 2 * up.nwg();
             for (size_t t = 0; t + 1 < up.tile_u0.size(); ++t) tile_u0.push_back(up.tile_u0[t] + unit_base);
             for (size_t g = 0; g + 1 < up.wg_u0.size(); ++g) wg_u0.push_back(up.wg_u0[g] + unit_base);
         }
@@ -972,7 +976,7 @@ int run_update_batch(const UpdateItem* items, int count, int precision, hipStrea
         if (!units.empty()) std::memcpy(h + o_u, units.data(), sizeof(DUnit) * units.size());
         std::memcpy(h + o_ti, tile_u0.data(), sizeof(int) * tile_u0.size());
         std::memcpy(h + o_wi, wg_u0.data(), sizeof(int) * wg_u0.size());
-        const size_t partial = decode_unit_partial_floats((int)units.size());
+        const size_t partial = decode_unit_partial_floats(pblocks);
         if (any_split && w->d_partial.n < partial) w->d_partial.alloc_async(partial, s, "batch partial sums");
         unsigned char* dm = w->d_meta.p;
         hip_check(hipMemcpyAsync(dm, h, bytes, hipMemcpyHostToDevice, s), "copy batch descriptors");
@@ -1281,7 +1285,7 @@ int vsaogm_decode_incremental(vsaogm_map* m, const vsaogm_grid_desc* g, int32_t 
             d.tile_u0 = gc->inc_tile_u0.p;
             d.wg_u0 = gc->inc_wg_u0.p;
             d.nwg = std::max(N, slots16);
-            d.fix_tiles = std::min(N, slots16);
+            d.fix_tiles = N;   // with more changed tiles than slots, any of them can be split
         } else {
             d.plan.grid = slots32;
             d.plan.steps_per_wg = 0;   // read on the device

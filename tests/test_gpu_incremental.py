@@ -160,15 +160,16 @@ def test_incremental_equals_full(torch_cuda, name, precision):
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16", "bf16x3"])
 def test_incremental_many_tiles(torch_cuda, precision):
-    """A 2560 x 2560 grid of 10 x 10 memory tiles (400 GEMM tiles of 256 x 64 cells): updates
-    that touch 7 tile rows (about 280 GEMM tiles, whole tiles per workgroup), two neighbouring
-    tiles (a few tiles split over workgroups, ranges crossing tile borders) and none.  The
-    plan is made on the device; every result equals a full decode up to accumulation order."""
+    """A 2560 x 2560 grid of 10 x 10 memory tiles (400 GEMM tiles of 256 x 64 cells), D = 1536
+    (24 K steps per tile): updates that touch 7 tile rows (about 280 GEMM tiles, more than the
+    workgroups: ranges of 27 steps that split tiles anywhere in the list, also past the 256th),
+    two neighbouring tiles (a few tiles split over many workgroups) and none.  The plan is made
+    on the device; every result equals a full decode up to accumulation order."""
     say(f"[gpu] incremental decode, many tiles, {precision}")
     from paper_2408_09066_amd import native
     torch = torch_cuda
     rng = np.random.default_rng(2408)
-    D, res, side, T = 512, 0.05, 2560, 10
+    D, res, side, T = 1536, 0.05, 2560, 10
     half = side * res / 2.0
     layout = (-half, -half, half, half)
     grid = (-half, -half, res)
