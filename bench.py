@@ -587,58 +587,11 @@ def world40_benchmark(precision: str, steps: int, warmup: int):
     }
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "fp16", "bf16x3"],
-                    help="operands of the headline's similarity contraction; bf16x3 (hi+lo split) meets "
-                         "the fp32 accuracy bar")
-    ap.add_argument("--cpu-budget", type=float, default=12.0,
-                    help="seconds of oracle work for the CPU baseline (0 disables it)")
-    ap.add_argument("--world40", type=int, default=1, help="also run the 40 m world (fp32 and bf16 hi+lo)")
-    ap.add_argument("--serving", type=int, default=1,
-                    help="also run the request-loop benchmark (256 updates of 16 maps)")
-    ap.add_argument("--stress", type=int, default=200,
-                    help="updates of the large map served through the request loop (0 disables it)")
-    ap.add_argument("--volume", type=int, default=1, help="also run the 3-D benchmark")
-    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
-                    help="processes that generate the scans")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only copy 512 MiB device to device three times (reference for HBM byte counters)")
-    args = ap.parse_args()
-
-    if args.copy_calibration:
-        import torch
-        n = 512 << 20
-        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}), flush=True)
-        return 0
-
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the hot path here is the single-GPU kernel set)", file=sys.stderr)
-        return 2
-
-    # scans are generated before any GPU use (generation forks worker processes)
-    n_head = args.warmup + 2 * args.steps
-    sc, ups, gen_s = stress_generate(max(n_head, args.stress), args.workers)
-
+def headline(args, sc, ups, gen_s, n_head):
+    """The large-map update step, timed: the bench line's headline fields."""
     import torch
     from paper_2408_09066_amd import native
-
-    if not torch.cuda.is_available():
-        print("no GPU visible", file=sys.stderr)
-        return 1
-    native.load()
-    torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
-
     # ---- headline: incremental updates of the large map, inputs resident in HBM
     dev_ups = [(torch.from_numpy(xy).to(dev), torch.from_numpy(lb).to(dev)) for xy, lb in ups[:n_head]]
     heat = torch.empty((2, sc.ny, sc.nx), dtype=torch.float32, device=dev)
@@ -709,6 +662,71 @@ def main() -> int:
         "stages": stages,
         "roofline": roof,
     }
+    return result
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "fp16", "bf16x3"],
+                    help="operands of the headline's similarity contraction; bf16x3 (hi+lo split) meets "
+                         "the fp32 accuracy bar")
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of oracle work for the CPU baseline (0 disables it)")
+    ap.add_argument("--headline", type=int, default=1,
+                    help="run the headline (0: only the other sections, for profiling them)")
+    ap.add_argument("--world40", type=int, default=1, help="also run the 40 m world (fp32 and bf16 hi+lo)")
+    ap.add_argument("--serving", type=int, default=1,
+                    help="also run the request-loop benchmark (256 updates of 16 maps)")
+    ap.add_argument("--stress", type=int, default=200,
+                    help="updates of the large map served through the request loop (0 disables it)")
+    ap.add_argument("--volume", type=int, default=1, help="also run the 3-D benchmark")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="processes that generate the scans")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 512 MiB device to device three times (reference for HBM byte counters)")
+    args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        n = 512 << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}), flush=True)
+        return 0
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the hot path here is the single-GPU kernel set)", file=sys.stderr)
+        return 2
+
+    # scans are generated before any GPU use (generation forks worker processes)
+    n_head = args.warmup + 2 * args.steps
+    sc, ups, gen_s = stress_generate(max(n_head, args.stress), args.workers)
+
+    import torch
+    from paper_2408_09066_amd import native
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    native.load()
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+
+    K = args.steps
+    if args.headline:
+        result = headline(args, sc, ups, gen_s, n_head)
+    else:
+        # a run of the other sections alone (for profiling them): no headline figure
+        result = {"metric": "heatmap cells decoded/sec + points encoded/sec; p50/p99 map-update latency",
+                  "value": None, "unit": "cells/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+                  "note": "headline not run (--headline 0)"}
     result["measured_peaks"] = {"hbm_copy_gbs": measured_hbm_copy_gbs(), "datasheet_hbm_gbs": PEAK_HBM_GBS}
     if args.world40:
         result["world40"] = {p_: world40_benchmark(p_, K, args.warmup) for p_ in ("fp32", "bf16x3")}
