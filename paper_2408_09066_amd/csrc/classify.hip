@@ -85,31 +85,42 @@ __device__ __attribute__((always_inline)) inline void classify_body(const float*
         half_w[p][dy + kMaxRadius] = w;
     }
     const size_t plane = (size_t)nx * ny;
-    // the block's cells and halo, both classes, kLoadBatch loads in flight per thread
+    // the block's cells and halo, both classes, kLoadBatch loads in flight per thread; element
+    // idx = class * W * H + yy * W + xx, walked in steps of 256 without integer division (one
+    // per thread to start; W >= 32 and H >= 16, so a step moves at most 8 rows and wraps the
+    // class at most once)
     constexpr int kLoadBatch = 8;
     const int total = 2 * W * H;
+    const int sy = 256 / W, sx = 256 - sy * W;
+    int cp = 0, cyy = threadIdx.x / W, cxx = threadIdx.x - (threadIdx.x / W) * W;
     for (int base = 0; base < total; base += 256 * kLoadBatch) {
         float raw[kLoadBatch];
         bool in[kLoadBatch];
+        int cls[kLoadBatch];
 #pragma unroll
         for (int u = 0; u < kLoadBatch; ++u) {
             const int idx = base + u * 256 + threadIdx.x;
-            const int p = idx / (W * H);
-            const int rem = idx - p * W * H;
-            const int yy = rem / W, xx = rem - yy * W;
-            const int gx = bx - R + xx, gy = by - R + yy;
+            const int gx = bx - R + cxx, gy = by - R + cyy;
             in[u] = idx < total && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+            cls[u] = cp;
             // outside the grid: a clamped in-bounds address, the value is discarded
-            const size_t off = in[u] ? (size_t)p * plane + (size_t)gy * nx + gx : 0;
+            const size_t off = in[u] ? (size_t)cp * plane + (size_t)gy * nx + gx : 0;
             raw[u] = heat[off];
+            cxx += sx;
+            cyy += sy;
+            if (cxx >= W) {
+                cxx -= W;
+                ++cyy;
+            }
+            if (cyy >= H) {
+                cyy -= H;
+                ++cp;
+            }
         }
 #pragma unroll
         for (int u = 0; u < kLoadBatch; ++u) {
             const int idx = base + u * 256 + threadIdx.x;
-            if (idx < total) {
-                const float m = (idx >= W * H) ? m1 : m0;
-                sg[idx] = in[u] ? cell_value(raw[u], m, normalize, square, act) : 0.f;
-            }
+            if (idx < total) sg[idx] = in[u] ? cell_value(raw[u], cls[u] ? m1 : m0, normalize, square, act) : 0.f;
         }
     }
     __syncthreads();
