@@ -843,13 +843,12 @@ __global__ __launch_bounds__(256) void k_region_max(const float* __restrict__ he
                                                     float* __restrict__ region_max) {
     if (nboxes_dev && (int)blockIdx.x >= *nboxes_dev) return;
     const RegionBox b = boxes[blockIdx.x];
-    const int w = b.col1 - b.col0, h = b.row1 - b.row0;
     float mx[2] = {-INFINITY, -INFINITY};
-    for (int e = threadIdx.x; e < w * h; e += 256) {
-        const int r = b.row0 + e / w, c = b.col0 + e % w;
+    // rows one after another, the block's threads across each row (no per-cell division)
+    for (int r = b.row0; r < b.row1; ++r)
+        for (int c = b.col0 + (int)threadIdx.x; c < b.col1; c += 256)
 #pragma unroll
-        for (int p = 0; p < 2; ++p) mx[p] = fmaxf(mx[p], heat[(size_t)p * nx * ny + (size_t)r * nx + c]);
-    }
+            for (int p = 0; p < 2; ++p) mx[p] = fmaxf(mx[p], heat[(size_t)p * nx * ny + (size_t)r * nx + c]);
     __shared__ float sh[2][4];
 #pragma unroll
     for (int p = 0; p < 2; ++p) {

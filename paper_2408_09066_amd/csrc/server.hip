@@ -154,7 +154,20 @@ struct Payload {
     void* in = nullptr;       // pinned [n][2] float32 points, then [n] labels
     size_t in_cap = 0;
     float hmax[2] = {0.f, 0.f};
+    // outputs in pinned host memory: copied there from the device directly, not staged
+    bool pin_ogm = false, pin_label = false, pin_heat = false;
 };
+
+// Host memory the device can copy into directly (allocated pinned, e.g. hipHostMalloc).
+bool is_pinned_host(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();   // pageable memory may report an error: not pinned
+        return false;
+    }
+    return a.type == hipMemoryTypeHost;
+}
 
 // Bytes a request holds while it runs: its inputs and outputs on the device plus the map's
 // working buffers for its points (sorted coordinates, keys, partial spectra) and the similarity's
@@ -296,9 +309,9 @@ public:
                 const vsaogm_request& r = p->r;
                 const int64_t cells = (int64_t)r.grid.nx * r.grid.ny;
                 std::memcpy(p->hmax, h + s.o_hmax[i], 8);
-                if (r.label_out) std::memcpy(r.label_out, h + s.o_lab[i], cells);
-                if (r.ogm) std::memcpy(r.ogm, h + s.o_ogm[i], cells * 4);
-                if (r.heat) std::memcpy(r.heat, h + s.o_heat[i], cells * 8);
+                if (r.label_out && !p->pin_label) std::memcpy(r.label_out, h + s.o_lab[i], cells);
+                if (r.ogm && !p->pin_ogm) std::memcpy(r.ogm, h + s.o_ogm[i], cells * 4);
+                if (r.heat && !p->pin_heat) std::memcpy(r.heat, h + s.o_heat[i], cells * 8);
             }
             q->status = status;
             q->result[0] = p->hmax[0];
@@ -331,7 +344,8 @@ private:
         const vsaogm_request& r = p.r;
         const int64_t n = r.n, cells = (int64_t)r.grid.nx * r.grid.ny;
         const OutLayout L(cells);
-        s.back = r.heat ? L.end_heat : (r.ogm ? L.end_ogm : (r.label_out ? L.end_lab : 8));
+        const bool st_heat = r.heat && !p.pin_heat, st_ogm = r.ogm && !p.pin_ogm, st_lab = r.label_out && !p.pin_label;
+        s.back = st_heat ? L.end_heat : (st_ogm ? L.end_ogm : (st_lab ? L.end_lab : 8));
         s.o_hmax.assign(1, 0);
         s.o_lab.assign(1, L.lab);
         s.o_ogm.assign(1, L.ogm);
@@ -373,6 +387,19 @@ private:
         call(vsaogm_classify(&r.grid, heat, hmax, r.r_occ, r.r_emp, r.rho, reinterpret_cast<float*>(dout + L.ogm),
                              dout + L.lab, device_, s.stream));
         check_hip(hipMemcpyAsync(s.h_out.p, dout, s.back, hipMemcpyDeviceToHost, s.stream), "copy outputs");
+        copy_pinned(s, p, dout + L.lab, dout + L.ogm, dout + L.heat, cells);
+    }
+
+    // outputs the caller holds in pinned memory go there straight from the device
+    void copy_pinned(Slot& s, const Payload& p, const unsigned char* lab, const unsigned char* ogm,
+                     const unsigned char* heat, int64_t cells) {
+        const vsaogm_request& r = p.r;
+        if (r.label_out && p.pin_label)
+            check_hip(hipMemcpyAsync(r.label_out, lab, (size_t)cells, hipMemcpyDeviceToHost, s.stream), "copy labels");
+        if (r.ogm && p.pin_ogm)
+            check_hip(hipMemcpyAsync(r.ogm, ogm, (size_t)cells * 4, hipMemcpyDeviceToHost, s.stream), "copy map");
+        if (r.heat && p.pin_heat)
+            check_hip(hipMemcpyAsync(r.heat, heat, (size_t)cells * 8, hipMemcpyDeviceToHost, s.stream), "copy heat");
     }
 
     void launch_batch(Slot& s, const std::vector<CoreRequest*>& batch) {
@@ -380,15 +407,17 @@ private:
         // inputs: per request [n][2] points then [n] labels, 256-byte aligned
         std::vector<size_t> o_in(count);
         size_t in_bytes = 0;
-        bool want_lab = false, want_ogm = false, want_heat = false;
+        bool want_lab = false, want_ogm = false, want_heat = false;   // staged through h_out
+        bool want_ogm_dev = false;                                     // the map computed at all
         size_t cells_total = 0;
         for (size_t i = 0; i < count; ++i) {
             const Payload* p = static_cast<const Payload*>(batch[i]->payload);
             o_in[i] = in_bytes;
             in_bytes += up256((size_t)p->r.n * 9);
-            want_lab = want_lab || p->r.label_out;
-            want_ogm = want_ogm || p->r.ogm;
-            want_heat = want_heat || p->r.heat;
+            want_lab = want_lab || (p->r.label_out && !p->pin_label);
+            want_ogm = want_ogm || (p->r.ogm && !p->pin_ogm);
+            want_heat = want_heat || (p->r.heat && !p->pin_heat);
+            want_ogm_dev = want_ogm_dev || p->r.ogm;
             cells_total += (size_t)p->r.grid.nx * p->r.grid.ny;
         }
         // outputs, section-major so that one copy brings back what any request asked for
@@ -444,13 +473,18 @@ private:
             it.rho = r.rho;
             it.heat = reinterpret_cast<float*>(dout + s.o_heat[i]);
             it.hmax = reinterpret_cast<float*>(dout + s.o_hmax[i]);
-            it.ogm = want_ogm ? reinterpret_cast<float*>(dout + s.o_ogm[i]) : nullptr;
+            it.ogm = want_ogm_dev ? reinterpret_cast<float*>(dout + s.o_ogm[i]) : nullptr;
             it.label_out = dout + s.o_lab[i];
             precision = r.precision;
         }
         const int rc = vsaogm::run_update_batch(items.data(), (int)count, precision, s.stream, s.work);
         if (rc != VSAOGM_OK) throw Fail(rc, vsaogm_last_error());
         check_hip(hipMemcpyAsync(s.h_out.p, dout, s.back, hipMemcpyDeviceToHost, s.stream), "copy outputs");
+        for (size_t i = 0; i < count; ++i) {
+            const Payload* p = static_cast<const Payload*>(batch[i]->payload);
+            copy_pinned(s, *p, dout + s.o_lab[i], dout + s.o_ogm[i], dout + s.o_heat[i],
+                        (int64_t)p->r.grid.nx * p->r.grid.ny);
+        }
     }
 
     int device_;
@@ -491,6 +525,9 @@ std::unique_ptr<CoreRequest> prepare(vsaogm_server* s, const vsaogm_request* r) 
         throw Fail(VSAOGM_EINVAL, "disk radii must be in 0..24");
     auto p = std::make_unique<Payload>();
     p->r = *r;
+    p->pin_label = is_pinned_host(r->label_out);
+    p->pin_ogm = is_pinned_host(r->ogm);
+    p->pin_heat = is_pinned_host(r->heat);
     auto q = std::make_unique<CoreRequest>();
     {
         std::lock_guard<std::mutex> lk(s->mu);

@@ -66,6 +66,20 @@ class Grid3Desc(ctypes.Structure):
                 ("nz", ctypes.c_int32)]
 
 
+def _host_out(shape, dtype):
+    """Output array for a served update: in pinned memory (torch's caching host allocator) when
+    a device is present, so that the server copies results into it straight from the device;
+    the returned array keeps its memory alive."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            tdt = {np.dtype(np.uint8): torch.uint8, np.dtype(np.float32): torch.float32}[np.dtype(dtype)]
+            return torch.empty(shape, dtype=tdt, pin_memory=True).numpy()
+    except (ImportError, RuntimeError):
+        pass
+    return np.empty(shape, dtype=dtype)
+
+
 class ServerDesc(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
                 ("max_queue", ctypes.c_int32), ("device", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
@@ -446,11 +460,11 @@ class Server:
         label = np.ascontiguousarray(label, dtype=np.uint8).reshape(-1)
         out = {}
         if "label" in want:
-            out["label"] = np.empty((ny, nx), dtype=np.uint8)
+            out["label"] = _host_out((ny, nx), np.uint8)
         if "ogm" in want:
-            out["ogm"] = np.empty((ny, nx), dtype=np.float32)
+            out["ogm"] = _host_out((ny, nx), np.float32)
         if "heat" in want:
-            out["heat"] = np.empty((2, ny, nx), dtype=np.float32)
+            out["heat"] = _host_out((2, ny, nx), np.float32)
         req = Request(int(map_id), xy.ctypes.data, label.ctypes.data, int(xy.shape[0]),
                       grid_desc(grid, nx, ny), PRECISIONS[precision], int(r_occ), int(r_emp),
                       float(rho),
@@ -482,11 +496,11 @@ class Server:
             nx, ny = int(it["nx"]), int(it["ny"])
             out = {}
             if "label" in want:
-                out["label"] = np.empty((ny, nx), dtype=np.uint8)
+                out["label"] = _host_out((ny, nx), np.uint8)
             if "ogm" in want:
-                out["ogm"] = np.empty((ny, nx), dtype=np.float32)
+                out["ogm"] = _host_out((ny, nx), np.float32)
             if "heat" in want:
-                out["heat"] = np.empty((2, ny, nx), dtype=np.float32)
+                out["heat"] = _host_out((2, ny, nx), np.float32)
             keep.append((xy, lab))
             outs.append(out)
             arr[i] = Request(int(it["map_id"]), xy.ctypes.data, lab.ctypes.data, int(xy.shape[0]),
