@@ -259,7 +259,7 @@ typedef struct {
     int32_t max_queue;        /* pending requests before submit returns EBUSY */
     int32_t device;           /* HIP device ordinal */
     int32_t max_batch;        /* requests of distinct maps run as one batch (one launch per
-                                 stage), 1..64; <= 0 means 8 */
+                                 stage), 1..64; <= 0 means 2 */
 } vsaogm_server_desc;
 
 typedef struct {

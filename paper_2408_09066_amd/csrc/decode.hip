@@ -782,6 +782,13 @@ __global__ __launch_bounds__(256) void k_decode_fix(DecodeArgs ab) {
     }
     if (w_first >= w_last) return;  // whole tile, stored by the GEMM
     const DTile t = ab.tiles[ti];
+    // a part of rows at or past the tile's last row block holds nothing to add (parts of whole
+    // rows of one class: rows r0 .. r0 + PART_ROWS - 1)
+    constexpr int PART_ROWS = PER_TILE / PARTS / kTileCols;
+    if constexpr (TR % PART_ROWS == 0) {
+        const int r0 = (partk * PART_ROWS) % TR;
+        if (r0 >= 16 * t.nrb) return;
+    }
     DecodeArgs a = ab;
     apply_request(a, t);
     float sum[PER];

@@ -55,9 +55,9 @@ def direct(torch, maps, reqs, precision):
     return outs
 
 
-def served(maps, reqs, precision, only_map=None, max_inflight=4, budget=0, local=False):
+def served(maps, reqs, precision, only_map=None, max_inflight=4, budget=0, local=False, max_batch=0):
     from paper_2408_09066_amd import native
-    srv = native.Server(max_inflight=max_inflight, hbm_budget_bytes=budget)
+    srv = native.Server(max_inflight=max_inflight, hbm_budget_bytes=budget, max_batch=max_batch)
     ids = [srv.add_map(m.theta, m.layout, m.tiles) for m in maps]
     tickets = []
     for i, q in enumerate(reqs):
@@ -98,7 +98,7 @@ def test_alone_and_in_the_mix_agree(torch_cuda, stream):
     """A map's updates give the same bits alone on the server and mixed with other maps'."""
     say("[gpu] alone vs in the mix")
     maps, reqs = stream
-    mix, _ = served(maps, reqs, "bf16x3", max_inflight=8)
+    mix, _ = served(maps, reqs, "bf16x3", max_inflight=8, max_batch=8)   # batches of up to 8 maps
     for mid in range(len(maps)):
         alone, _ = served(maps, reqs, "bf16x3", only_map=mid, max_inflight=1)
         for i, (out, r) in alone.items():
