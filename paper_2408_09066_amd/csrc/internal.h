@@ -152,8 +152,10 @@ hipError_t launch_classify3(const float* heat, const float* hmax, int nx, int ny
 // pointers; ogm may be null.
 struct UpdateItem {
     vsaogm_map* map;
-    const float* xy;
+    const float* xy;          // device inputs, or
     const uint8_t* label;
+    const void* host_in;      // pinned host [n][2] float32 points then [n] labels, staged with
+                              // the batch's descriptors (one copy for the batch)
     int64_t n;
     vsaogm_grid_desc grid;
     int32_t r_occ, r_emp;

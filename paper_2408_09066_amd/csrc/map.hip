@@ -819,7 +819,8 @@ int run_update_batch(const UpdateItem* items, int count, int precision, hipStrea
                 if (items[j].map == it.map) fail(VSAOGM_EINVAL, "batch: a map appears twice");
             check_grid(&it.grid);
             if (it.n < 0) fail(VSAOGM_EINVAL, "batch: n must be >= 0");
-            if (it.n > 0 && (!it.xy || !it.label)) fail(VSAOGM_EINVAL, "batch: xy and label must not be NULL");
+            if (it.n > 0 && !it.host_in && (!it.xy || !it.label))
+                fail(VSAOGM_EINVAL, "batch: xy and label (or host_in) must not be NULL");
             if (it.n > ((int64_t)1 << 31) - (int64_t)kAssignChunk * 2) fail(VSAOGM_EINVAL, "batch: n too large");
             if (!it.heat || !it.hmax || !it.label_out) fail(VSAOGM_EINVAL, "batch: heat, hmax and label required");
             if (it.r_occ < 0 || it.r_emp < 0 || it.r_occ > kMaxRadius || it.r_emp > kMaxRadius)
@@ -955,6 +956,10 @@ int run_update_batch(const UpdateItem* items, int count, int precision, hipStrea
         const size_t o_u = place(sizeof(DUnit) * std::max<size_t>(units.size(), 1));
         const size_t o_ti = place(sizeof(int) * tile_u0.size());
         const size_t o_wi = place(sizeof(int) * wg_u0.size());
+        // inputs given in pinned host memory travel with the descriptors
+        std::vector<size_t> o_in(count, 0);
+        for (int i = 0; i < count; ++i)
+            if (items[i].host_in && items[i].n > 0) o_in[i] = place((size_t)items[i].n * 9);
         const size_t bytes = off;
         if (w->h_cap < bytes) {
             if (w->h_meta) (void)hipHostFree(w->h_meta);
@@ -967,6 +972,14 @@ int run_update_batch(const UpdateItem* items, int count, int precision, hipStrea
         }
         if (w->d_meta.n < bytes) w->d_meta.alloc_async(std::max<size_t>(bytes, w->h_cap), s, "batch descriptors");
         unsigned char* h = w->h_meta;
+        unsigned char* dm = w->d_meta.p;
+        for (int j = 0; j < count; ++j) {
+            const UpdateItem& it = items[order[j]];
+            if (!it.host_in || it.n <= 0) continue;
+            std::memcpy(h + o_in[order[j]], it.host_in, (size_t)it.n * 9);
+            eq_sorted[j].xy = reinterpret_cast<const float2*>(dm + o_in[order[j]]);
+            eq_sorted[j].label = dm + o_in[order[j]] + (size_t)it.n * 8;
+        }
         std::memcpy(h + o_eq, eq_sorted.data(), sizeof(EncodeReq) * count);
         std::memcpy(h + o_eb0, enc_b0.data(), sizeof(int) * enc_b0.size());
         std::memcpy(h + o_dq, dq.data(), sizeof(DecodeReq) * count);
@@ -978,7 +991,6 @@ int run_update_batch(const UpdateItem* items, int count, int precision, hipStrea
         std::memcpy(h + o_wi, wg_u0.data(), sizeof(int) * wg_u0.size());
         const size_t partial = decode_unit_partial_floats(pblocks);
         if (any_split && w->d_partial.n < partial) w->d_partial.alloc_async(partial, s, "batch partial sums");
-        unsigned char* dm = w->d_meta.p;
         hip_check(hipMemcpyAsync(dm, h, bytes, hipMemcpyHostToDevice, s), "copy batch descriptors");
         const EncodeReq* d_eq = reinterpret_cast<const EncodeReq*>(dm + o_eq);
         int done = 0;

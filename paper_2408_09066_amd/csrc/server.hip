@@ -99,7 +99,13 @@ struct HostMem {
         while (cap < need) cap *= 2;
         check_hip(hipHostMalloc(&p, cap, hipHostMallocDefault), what);
         bytes = cap;
+        dev = nullptr;
+        if (hipHostGetDevicePointer(&dev, p, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            dev = nullptr;
+        }
     }
+    void* dev = nullptr;   // the block's device address (kernels write results into it), or null
     ~HostMem() {
         if (p) (void)hipHostFree(p);
     }
@@ -154,9 +160,53 @@ struct Payload {
     void* in = nullptr;       // pinned [n][2] float32 points, then [n] labels
     size_t in_cap = 0;
     float hmax[2] = {0.f, 0.f};
-    // outputs in pinned host memory: copied there from the device directly, not staged
+    // outputs in pinned host memory: copied there from the device directly, not staged; their
+    // device addresses (null where the runtime gives none: a copy call then)
     bool pin_ogm = false, pin_label = false, pin_heat = false;
+    void* dev_ogm = nullptr;
+    void* dev_label = nullptr;
+    void* dev_heat = nullptr;
 };
+
+// The device address of pinned host memory, or null.
+void* device_address(void* host) {
+    void* d = nullptr;
+    if (!host || hipHostGetDevicePointer(&d, host, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return d;
+}
+
+// Results of a batch written into pinned host buffers by one launch: segment k copies bytes[k]
+// from src[k] (device) to dst[k] (device address of pinned host memory), 16 KiB per block.
+constexpr int kMaxOutSegs = 32;
+constexpr size_t kOutChunk = 16384;
+struct OutSegs {
+    const unsigned char* src[kMaxOutSegs];
+    unsigned char* dst[kMaxOutSegs];
+    unsigned long long bytes[kMaxOutSegs];
+    int n;
+};
+
+__global__ __launch_bounds__(256) void k_results_to_host(OutSegs sg) {
+    const int k = blockIdx.y;
+    if (k >= sg.n) return;
+    const size_t nb = sg.bytes[k];
+    const size_t c0 = (size_t)blockIdx.x * kOutChunk;
+    if (c0 >= nb) return;
+    const size_t c1 = c0 + kOutChunk < nb ? c0 + kOutChunk : nb;
+    const unsigned char* src = sg.src[k];
+    unsigned char* dst = sg.dst[k];
+    if ((((uintptr_t)src | (uintptr_t)dst) & 15) == 0) {
+        const size_t w0 = c0 / 16, w1 = c1 / 16;
+        for (size_t w = w0 + threadIdx.x; w < w1; w += 256)
+            reinterpret_cast<uint4*>(dst)[w] = reinterpret_cast<const uint4*>(src)[w];
+        for (size_t b = w1 * 16 + threadIdx.x; b < c1; b += 256) dst[b] = src[b];
+    } else {
+        for (size_t b = c0 + threadIdx.x; b < c1; b += 256) dst[b] = src[b];
+    }
+}
 
 // Host memory the device can copy into directly (allocated pinned, e.g. hipHostMalloc).
 bool is_pinned_host(const void* p) {
@@ -404,16 +454,11 @@ private:
 
     void launch_batch(Slot& s, const std::vector<CoreRequest*>& batch) {
         const size_t count = batch.size();
-        // inputs: per request [n][2] points then [n] labels, 256-byte aligned
-        std::vector<size_t> o_in(count);
-        size_t in_bytes = 0;
         bool want_lab = false, want_ogm = false, want_heat = false;   // staged through h_out
         bool want_ogm_dev = false;                                     // the map computed at all
         size_t cells_total = 0;
         for (size_t i = 0; i < count; ++i) {
             const Payload* p = static_cast<const Payload*>(batch[i]->payload);
-            o_in[i] = in_bytes;
-            in_bytes += up256((size_t)p->r.n * 9);
             want_lab = want_lab || (p->r.label_out && !p->pin_label);
             want_ogm = want_ogm || (p->r.ogm && !p->pin_ogm);
             want_heat = want_heat || (p->r.heat && !p->pin_heat);
@@ -448,24 +493,21 @@ private:
         const size_t end_heat = o;
         (void)cells_total;
         s.back = want_heat ? end_heat : (want_ogm ? end_ogm : (want_lab ? end_lab : 16 * count));
-        s.d_in.ensure(std::max<size_t>(in_bytes, 256), s.stream, "batch inputs");
         s.d_out.ensure(end_heat, s.stream, "batch outputs");
         s.h_out.ensure(s.back, "batch pinned outputs");
-        unsigned char* din = static_cast<unsigned char*>(s.d_in.p);
         unsigned char* dout = static_cast<unsigned char*>(s.d_out.p);
         std::vector<vsaogm::UpdateItem> items(count);
         int precision = VSAOGM_BF16X3;
         for (size_t i = 0; i < count; ++i) {
             const Payload* p = static_cast<const Payload*>(batch[i]->payload);
             const vsaogm_request& r = p->r;
-            // from the request's pinned block (returned to the pool only after the slot's work ended)
-            if (r.n > 0)
-                check_hip(hipMemcpyAsync(din + o_in[i], p->in, (size_t)r.n * 9, hipMemcpyHostToDevice, s.stream),
-                          "copy inputs");
+            // the request's pinned block travels with the batch's descriptors (it goes back to
+            // the pool only after the slot's work ended)
             vsaogm::UpdateItem& it = items[i];
             it.map = p->map;
-            it.xy = reinterpret_cast<const float*>(din + o_in[i]);
-            it.label = din + o_in[i] + (size_t)r.n * 8;
+            it.xy = nullptr;
+            it.label = nullptr;
+            it.host_in = r.n > 0 ? p->in : nullptr;
             it.n = r.n;
             it.grid = r.grid;
             it.r_occ = r.r_occ;
@@ -479,11 +521,46 @@ private:
         }
         const int rc = vsaogm::run_update_batch(items.data(), (int)count, precision, s.stream, s.work);
         if (rc != VSAOGM_OK) throw Fail(rc, vsaogm_last_error());
-        check_hip(hipMemcpyAsync(s.h_out.p, dout, s.back, hipMemcpyDeviceToHost, s.stream), "copy outputs");
-        for (size_t i = 0; i < count; ++i) {
+        // results: what is staged comes back with one copy; pinned outputs (and the maxima, when
+        // nothing is staged) are written by one kernel where the runtime gave device addresses
+        OutSegs sg{};
+        size_t max_bytes = 0;
+        bool direct = true;
+        auto add = [&](const unsigned char* src, void* dst, size_t n) {
+            if (!dst || sg.n >= kMaxOutSegs) return false;
+            sg.src[sg.n] = src;
+            sg.dst[sg.n] = static_cast<unsigned char*>(dst);
+            sg.bytes[sg.n] = n;
+            ++sg.n;
+            max_bytes = std::max(max_bytes, n);
+            return true;
+        };
+        const bool staged = want_lab || want_ogm || want_heat;
+        if (staged) check_hip(hipMemcpyAsync(s.h_out.p, dout, s.back, hipMemcpyDeviceToHost, s.stream), "copy outputs");
+        else direct = add(dout, s.h_out.dev, 16 * count);
+        for (size_t i = 0; i < count && direct; ++i) {
             const Payload* p = static_cast<const Payload*>(batch[i]->payload);
-            copy_pinned(s, *p, dout + s.o_lab[i], dout + s.o_ogm[i], dout + s.o_heat[i],
-                        (int64_t)p->r.grid.nx * p->r.grid.ny);
+            const vsaogm_request& r = p->r;
+            const size_t cells = (size_t)r.grid.nx * r.grid.ny;
+            if (r.label_out && p->pin_label) direct = direct && add(dout + s.o_lab[i], p->dev_label, cells);
+            if (r.ogm && p->pin_ogm) direct = direct && add(dout + s.o_ogm[i], p->dev_ogm, cells * 4);
+            if (r.heat && p->pin_heat) direct = direct && add(dout + s.o_heat[i], p->dev_heat, cells * 8);
+        }
+        if (direct) {
+            if (sg.n > 0) {
+                const dim3 grid((unsigned)((max_bytes + kOutChunk - 1) / kOutChunk), (unsigned)sg.n);
+                hipLaunchKernelGGL(k_results_to_host, grid, dim3(256), 0, s.stream, sg);
+                check_hip(hipGetLastError(), "results to host");
+            }
+        } else {
+            // a buffer without a device address, or too many: copy calls
+            if (!staged) check_hip(hipMemcpyAsync(s.h_out.p, dout, 16 * count, hipMemcpyDeviceToHost, s.stream),
+                                   "copy maxima");
+            for (size_t i = 0; i < count; ++i) {
+                const Payload* p = static_cast<const Payload*>(batch[i]->payload);
+                copy_pinned(s, *p, dout + s.o_lab[i], dout + s.o_ogm[i], dout + s.o_heat[i],
+                            (int64_t)p->r.grid.nx * p->r.grid.ny);
+            }
         }
     }
 
@@ -529,6 +606,9 @@ std::unique_ptr<CoreRequest> prepare(vsaogm_server* s, const vsaogm_request* r) 
     p->pin_label = is_pinned_host(r->label_out);
     p->pin_ogm = is_pinned_host(r->ogm);
     p->pin_heat = is_pinned_host(r->heat);
+    if (p->pin_label) p->dev_label = device_address(r->label_out);
+    if (p->pin_ogm) p->dev_ogm = device_address(r->ogm);
+    if (p->pin_heat) p->dev_heat = device_address(r->heat);
     auto q = std::make_unique<CoreRequest>();
     {
         std::lock_guard<std::mutex> lk(s->mu);
