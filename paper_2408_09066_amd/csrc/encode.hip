@@ -320,6 +320,8 @@ __device__ inline void encode_body(const EncodeReq& q, int bid) {
     const int c = bid % q.max_echunks;
     if (c >= as_global(q.meta)[0]) return;
     const EChunk e = as_global(q.table)[c];
+    // the only work item of its memory: its sums go straight into the memory (below)
+    const bool alone = q.direct_single && as_global(q.meta)[1 + q.nkeys + e.key] == 1;
     const int b0 = (bid / q.max_echunks) * (kEncodeThreads * BPT) + threadIdx.x;
     gmem<float2>* __restrict__ p = sorted + e.start;
 
@@ -412,6 +414,19 @@ __device__ inline void encode_body(const EncodeReq& q, int bid) {
             }
         }
     }
+    if (alone) {
+        // what the reduction would add for one work item: w + (0 + s), bins below half only
+        gmem_rw<float2>* __restrict__ w = as_global_rw(q.omega) + (size_t)e.key * halfp;
+#pragma unroll
+        for (int j = 0; j < BPT; ++j) {
+            const int k = b0 + j * kEncodeThreads;
+            if (k < q.half) {
+                const float2 o = w[k];
+                w[k] = make_float2(o.x + (0.f + re[j]), o.y + (0.f + im[j]));
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
         const int k = b0 + j * kEncodeThreads;
@@ -445,7 +460,7 @@ __device__ inline void reduce_body(const EncodeReq& q, int bid) {
     const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int k = (bid % bblocks) * 64 + lane;
     const int e0 = meta[1 + key], ne = meta[1 + nkeys + key];
-    if (ne == 0) return;   // uniform over the block
+    if (ne == 0 || (ne == 1 && q.direct_single)) return;   // uniform over the block (one work item: the encode added it)
     float sr = 0.f, si = 0.f;
     if (k < half) {
         gmem<float2>* p = partial + (size_t)e0 * halfp + k;
@@ -621,6 +636,7 @@ EncodeReq encode_req(const float* xy, const uint8_t* label, int64_t n, const Lay
     q.max_rev_y = max_rev_y;
     q.half = half;
     q.halfp = halfp;
+    q.direct_single = 1;
     q.omega = omega;
     return q;
 }

@@ -224,6 +224,9 @@ struct EncodeReq {
     const double2* rev_d;
     float max_rev_x, max_rev_y;
     int half, halfp, D;
+    // the encode adds the sums of a memory that has one work item straight into it (the
+    // reduction then skips that memory); 0 where the encode writes every work item's partials
+    int direct_single;
     float2* omega;                    // [nkeys][halfp] local-frame memories
     float* scale;                     // norm: [nkeys] 1/||w||
     float2* omega_s;                  // norm: [nkeys][halfp] conj(Omega)/||w||
