@@ -728,8 +728,15 @@ def main() -> int:
     dev = torch.device("cuda", 0)
 
     K = args.steps
+    t_start = time.perf_counter()
+
+    def done(section):
+        # one line per finished section on stderr (the JSON line alone goes to stdout)
+        print(f"[bench] {section} done at {time.perf_counter() - t_start:.1f} s", file=sys.stderr, flush=True)
+
     if args.headline:
         result = headline(args, sc, ups, gen_s, n_head)
+        done("headline")
     else:
         # a run of the other sections alone (for profiling them): no headline figure
         result = {"metric": "heatmap cells decoded/sec + points encoded/sec; p50/p99 map-update latency",
@@ -737,17 +744,25 @@ def main() -> int:
                   "note": "headline not run (--headline 0)"}
     result["measured_peaks"] = {"hbm_copy_gbs": measured_hbm_copy_gbs(), "datasheet_hbm_gbs": PEAK_HBM_GBS}
     if args.world40:
-        result["world40"] = {p_: world40_benchmark(p_, K, args.warmup) for p_ in ("fp32", "bf16x3")}
+        result["world40"] = {}
+        for p_ in ("fp32", "bf16x3"):
+            result["world40"][p_] = world40_benchmark(p_, K, args.warmup)
+            done(f"world40 {p_}")
         from paper_2408_09066_amd import synth
         result["world40"]["accuracy"] = heldout_accuracy(synth.workload("world40"), "bf16x3")
+        done("world40 accuracy")
     if args.volume:
         result["volume"] = volume_benchmark()
+        done("volume")
     if args.serving:
         result["serving"] = serving_benchmark()
+        done("serving")
     if args.stress > 0:
         result["stress_serving"] = stress_benchmark(sc, ups[:args.stress])
+        done("stress serving")
     if args.cpu_budget > 0:
         result["cpu_baseline"] = cpu_baseline(sc, ups[0][0], ups[0][1], args.cpu_budget)
+        done("cpu baseline")
     print(json.dumps(result), flush=True)
     return 0
 
