@@ -843,19 +843,38 @@ __global__ __launch_bounds__(256) void k_decode_fix(DecodeArgs ab) {
     }
 }
 
-// One block per listed region: maxima of both classes over the region's cells.
+// Maxima of both classes over the listed regions' cells, folded into their ordered maxima
+// (order_key; 0 = no cell seen: the localized plan zeroes the entries of the regions it lists).
+// Block (region, stripe): kRegionStripes blocks share a region's rows; the block's threads run
+// across each row, four rows' loads in flight.
+constexpr int kRegionStripes = 16;
 __global__ __launch_bounds__(256) void k_region_max(const float* __restrict__ heat, int nx, int ny,
                                                     const RegionBox* __restrict__ boxes,
                                                     const int* __restrict__ nboxes_dev,
-                                                    float* __restrict__ region_max) {
-    if (nboxes_dev && (int)blockIdx.x >= *nboxes_dev) return;
+                                                    unsigned* __restrict__ region_u) {
+    if ((int)blockIdx.x >= *nboxes_dev) return;
     const RegionBox b = boxes[blockIdx.x];
+    const int h = b.row1 - b.row0, sh_rows = (h + kRegionStripes - 1) / kRegionStripes;
+    const int r0 = b.row0 + (int)blockIdx.y * sh_rows, r1 = min(b.row1, r0 + sh_rows);
+    const size_t plane = (size_t)nx * ny;
     float mx[2] = {-INFINITY, -INFINITY};
-    // rows one after another, the block's threads across each row (no per-cell division)
-    for (int r = b.row0; r < b.row1; ++r)
-        for (int c = b.col0 + (int)threadIdx.x; c < b.col1; c += 256)
+    for (int c = b.col0 + (int)threadIdx.x; c < b.col1; c += 256) {
+        int r = r0;
+        for (; r + 4 <= r1; r += 4) {
+            float v[2][4];
 #pragma unroll
-            for (int p = 0; p < 2; ++p) mx[p] = fmaxf(mx[p], heat[(size_t)p * nx * ny + (size_t)r * nx + c]);
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int p = 0; p < 2; ++p) v[p][u] = heat[(size_t)p * plane + (size_t)(r + u) * nx + c];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int p = 0; p < 2; ++p) mx[p] = fmaxf(mx[p], v[p][u]);
+        }
+        for (; r < r1; ++r)
+#pragma unroll
+            for (int p = 0; p < 2; ++p) mx[p] = fmaxf(mx[p], heat[(size_t)p * plane + (size_t)r * nx + c]);
+    }
     __shared__ float sh[2][4];
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
@@ -864,28 +883,32 @@ __global__ __launch_bounds__(256) void k_region_max(const float* __restrict__ he
         if ((threadIdx.x & 63) == 0) sh[p][threadIdx.x >> 6] = m;
     }
     __syncthreads();
-    if (threadIdx.x < 2)
-        region_max[2 * b.beta + threadIdx.x] =
-            fmaxf(fmaxf(sh[threadIdx.x][0], sh[threadIdx.x][1]), fmaxf(sh[threadIdx.x][2], sh[threadIdx.x][3]));
+    if (threadIdx.x < 2) {
+        const float m = fmaxf(fmaxf(sh[threadIdx.x][0], sh[threadIdx.x][1]), fmaxf(sh[threadIdx.x][2], sh[threadIdx.x][3]));
+        if (m > -INFINITY) atomicMax(region_u + 2 * b.beta + threadIdx.x, order_key(m));
+    }
 }
 
-__global__ __launch_bounds__(256) void k_region_final(const float* __restrict__ region_max, int nregions,
+// hmax over all regions (a region with no cell counts as -inf).
+__global__ __launch_bounds__(256) void k_region_final(const unsigned* __restrict__ region_u, int nregions,
                                                       float* __restrict__ hmax) {
-    float mx[2] = {-INFINITY, -INFINITY};
+    unsigned mx[2] = {0u, 0u};
     for (int i = threadIdx.x; i < nregions; i += 256) {
-        mx[0] = fmaxf(mx[0], region_max[2 * i]);
-        mx[1] = fmaxf(mx[1], region_max[2 * i + 1]);
+        mx[0] = max(mx[0], region_u[2 * i]);
+        mx[1] = max(mx[1], region_u[2 * i + 1]);
     }
-    __shared__ float sh[2][4];
+    __shared__ unsigned sh[2][4];
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
-        float m = mx[p];
-        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+        unsigned m = mx[p];
+        for (int off = 32; off > 0; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off));
         if ((threadIdx.x & 63) == 0) sh[p][threadIdx.x >> 6] = m;
     }
     __syncthreads();
-    if (threadIdx.x < 2)
-        hmax[threadIdx.x] = fmaxf(fmaxf(sh[threadIdx.x][0], sh[threadIdx.x][1]), fmaxf(sh[threadIdx.x][2], sh[threadIdx.x][3]));
+    if (threadIdx.x < 2) {
+        const unsigned m = max(max(sh[threadIdx.x][0], sh[threadIdx.x][1]), max(sh[threadIdx.x][2], sh[threadIdx.x][3]));
+        hmax[threadIdx.x] = m ? order_value(m) : -INFINITY;
+    }
 }
 
 __global__ void k_hmax_final(const unsigned* __restrict__ hmax_u, float* __restrict__ hmax) {
@@ -948,21 +971,12 @@ size_t decode_partial_floats(int precision, const DecodePlan& p) {
     return (size_t)p.grid * 2 * 2 * tr * kTileCols;
 }
 
-hipError_t launch_region_max(const float* heat, int nx, int ny, const RegionBox* boxes, int nboxes,
-                             float* region_max, int nregions, float* hmax, hipStream_t s) {
-    if (nboxes > 0)
-        hipLaunchKernelGGL(k_region_max, dim3(nboxes), dim3(256), 0, s, heat, nx, ny, boxes,
-                           static_cast<const int*>(nullptr), region_max);
-    hipLaunchKernelGGL(k_region_final, dim3(1), dim3(256), 0, s, region_max, nregions, hmax);
-    return hipGetLastError();
-}
-
 hipError_t launch_region_max_dyn(const float* heat, int nx, int ny, const RegionBox* boxes, const int* nboxes_dev,
-                                 int max_boxes, float* region_max, int nregions, float* hmax, hipStream_t s) {
+                                 int max_boxes, unsigned* region_u, int nregions, float* hmax, hipStream_t s) {
     if (max_boxes > 0)
-        hipLaunchKernelGGL(k_region_max, dim3(max_boxes), dim3(256), 0, s, heat, nx, ny, boxes, nboxes_dev,
-                           region_max);
-    hipLaunchKernelGGL(k_region_final, dim3(1), dim3(256), 0, s, region_max, nregions, hmax);
+        hipLaunchKernelGGL(k_region_max, dim3(max_boxes, kRegionStripes), dim3(256), 0, s, heat, nx, ny, boxes,
+                           nboxes_dev, region_u);
+    hipLaunchKernelGGL(k_region_final, dim3(1), dim3(256), 0, s, region_u, nregions, hmax);
     return hipGetLastError();
 }
 
@@ -1184,7 +1198,11 @@ __global__ __launch_bounds__(kPlanThreads) void k_inc_plan(IncPlan a) {
         const int f = b < a.nregions ? dirty[b] : 0;
         int tot;
         const int pos = plan_scan(f, s_w, &tot);
-        if (f) a.out_boxes[nb + pos] = a.boxes[b];
+        if (f) {
+            a.out_boxes[nb + pos] = a.boxes[b];
+            a.region_u[2 * b] = 0u;   // their maxima are taken again after the decode
+            a.region_u[2 * b + 1] = 0u;
+        }
         nb += tot;
     }
     const long long ks = a.ksteps16, total = (long long)n * ks;

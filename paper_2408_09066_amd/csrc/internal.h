@@ -402,17 +402,15 @@ struct DecodeLaunch {
 // With hmax_u == nullptr no class maxima are folded and hmax is not written.
 hipError_t launch_decode(int precision, const DecodeLaunch& d, hipStream_t s);
 
-// Per-region class maxima of a heatmap: region_max[beta][psi] = max over the region's cells
-// (rows [row0, row1) x cols [col0, col1) of each listed region; -inf if it has none), then
-// hmax[psi] = max over all nregions regions.
+// Per-region class maxima of a heatmap, for localized decoding: the ordered maxima (order_key)
+// region_u[beta][psi] of the *nboxes_dev listed regions (max_boxes at most) are raised to the
+// maxima of their cells (the entries start from 0, which no cell value maps to), then
+// hmax[psi] = max over all nregions regions (-inf if none has a cell).
 struct RegionBox {
     int beta, row0, row1, col0, col1, pad[3];
 };
-hipError_t launch_region_max(const float* heat, int nx, int ny, const RegionBox* boxes, int nboxes,
-                             float* region_max, int nregions, float* hmax, hipStream_t s);
-// Same with the listed regions' count read on the device (*nboxes_dev <= max_boxes).
 hipError_t launch_region_max_dyn(const float* heat, int nx, int ny, const RegionBox* boxes, const int* nboxes_dev,
-                                 int max_boxes, float* region_max, int nregions, float* hmax, hipStream_t s);
+                                 int max_boxes, unsigned* region_u, int nregions, float* hmax, hipStream_t s);
 
 // Plan of a localized decode, made on the device so that the host never waits for the memory
 // versions: the regions whose memories changed since the last localized decode (or all),
@@ -431,6 +429,7 @@ struct IncPlan {
     int slots16, slots32;      // resident workgroups of the 16-bit and fp32 kernels
     DTile* out_tiles;          // [ntiles] changed tiles
     RegionBox* out_boxes;      // [nregions] changed regions
+    unsigned* region_u;        // [nregions][2] ordered region maxima: the changed regions' zeroed
     DUnit* units;              // [ntiles + slots16] 16-bit work units
     int* tile_u0;              // [ntiles + 1]
     int* wg_u0;                // [max(ntiles, slots16) + 1]

@@ -209,7 +209,7 @@ struct GridCache {
     const float* inc_heat = nullptr;         // heat buffer of that decode
     int inc_precision = -1;                  // and its operand precision
     bool inc_valid = false;
-    DevBuf<float> region_max;                // [tiles][2]
+    DevBuf<unsigned> region_max;             // [tiles][2] ordered maxima (order_key)
     DevBuf<DTile> inc_tiles;                 // changed tiles, regions and the GEMM's work units
     DevBuf<RegionBox> inc_boxes;             // (capacities for the whole tile list)
     DevBuf<DUnit> inc_units;
@@ -1284,6 +1284,7 @@ int vsaogm_decode_incremental(vsaogm_map* m, const vsaogm_grid_desc* g, int32_t 
         ip.tile_u0 = gc->inc_tile_u0.p;
         ip.wg_u0 = gc->inc_wg_u0.p;
         ip.dyn = gc->inc_dyn.p;
+        ip.region_u = gc->region_max.p;
         hip_check(launch_inc_plan(ip, s), "localized decode plan");
         // partial sums: 16-bit, split tiles only when fewer tiles than slots (at most two units
         // per workgroup); fp32, two blocks per workgroup of at most slots32 workgroups

@@ -434,10 +434,35 @@ private:
         } else {
             call(vsaogm_decode(m, &r.grid, r.precision, heat, hmax, s.stream));
         }
-        call(vsaogm_classify(&r.grid, heat, hmax, r.r_occ, r.r_emp, r.rho, reinterpret_cast<float*>(dout + L.ogm),
-                             dout + L.lab, device_, s.stream));
+        // the map of values only when the caller asked for it
+        call(vsaogm_classify(&r.grid, heat, hmax, r.r_occ, r.r_emp, r.rho,
+                             r.ogm ? reinterpret_cast<float*>(dout + L.ogm) : nullptr, dout + L.lab, device_,
+                             s.stream));
         check_hip(hipMemcpyAsync(s.h_out.p, dout, s.back, hipMemcpyDeviceToHost, s.stream), "copy outputs");
-        copy_pinned(s, p, dout + L.lab, dout + L.ogm, dout + L.heat, cells);
+        // pinned outputs: one kernel writes them through their device addresses (copy calls
+        // where the runtime gave none)
+        OutSegs sg{};
+        bool direct = true;
+        size_t max_bytes = 0;
+        auto add = [&](const unsigned char* src, void* dst, size_t bytes) {
+            if (!dst) return false;
+            sg.src[sg.n] = src;
+            sg.dst[sg.n] = static_cast<unsigned char*>(dst);
+            sg.bytes[sg.n] = bytes;
+            ++sg.n;
+            max_bytes = std::max(max_bytes, bytes);
+            return true;
+        };
+        if (r.label_out && p.pin_label) direct = add(dout + L.lab, p.dev_label, (size_t)cells) && direct;
+        if (r.ogm && p.pin_ogm) direct = add(dout + L.ogm, p.dev_ogm, (size_t)cells * 4) && direct;
+        if (r.heat && p.pin_heat) direct = add(dout + L.heat, p.dev_heat, (size_t)cells * 8) && direct;
+        if (!direct) {
+            copy_pinned(s, p, dout + L.lab, dout + L.ogm, dout + L.heat, cells);
+        } else if (sg.n > 0) {
+            const dim3 grid((unsigned)((max_bytes + kOutChunk - 1) / kOutChunk), (unsigned)sg.n);
+            hipLaunchKernelGGL(k_results_to_host, grid, dim3(256), 0, s.stream, sg);
+            check_hip(hipGetLastError(), "results to host");
+        }
     }
 
     // outputs the caller holds in pinned memory go there straight from the device
