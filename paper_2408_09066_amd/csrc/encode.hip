@@ -8,7 +8,8 @@
 // the same local frame, so the factor cancels exactly in every similarity, while the phases
 // stay small enough for single precision.
 //
-// Pipeline (all on the stream, no host synchronisation):
+// Pipeline (all on the stream, no host synchronisation; the bodies of k_assign, k_scatter and
+// k_encode are bundle.h's, shared with volumes, on PlaneGeom):
 //   k_assign   nearest tile (exact double-precision argmin, lowest index on ties), key,
 //              label check, per-chunk key histogram
 //   k_scan     per-key totals and exclusive bases, encode work table
@@ -17,7 +18,7 @@
 //              hardware v_sin/v_cos, two points per step:
 //                exp(i a) + exp(i b) = 2 cos((a-b)/2) exp(i (a+b)/2)
 //   k_reduce   fixed-order sum of the work items' partial spectra into the memories
-#include "internal.h"
+#include "bundle.h"
 
 namespace vsaogm {
 namespace {
@@ -47,40 +48,52 @@ __device__ inline int nearest_tile(double x, double y, const LayoutDev& L) {
     return best;
 }
 
-// One point per thread; blocks of kAssignChunk points.  hist is key-major:
-// hist[key][chunk] = number of the chunk's points with that key.  The lanes of a wavefront
-// holding one key add their count with one LDS atomic (a chunk's points share few keys).
-__device__ inline void assign_body(const EncodeReq& q, int bid, int* sh_hist) {
-    for (int k = threadIdx.x; k < q.nkeys; k += blockDim.x) sh_hist[k] = 0;
-    __syncthreads();
-    const int64_t i = (int64_t)bid * kAssignChunk + threadIdx.x;
-    int key = -1;
-    if (i < q.n) {
-        const float2 p = as_global(q.xy)[i];
-        const unsigned l = as_global(q.label)[i];
-        if (l <= 1u) {
-            const int b = nearest_tile((double)p.x, (double)p.y, q.L);
-            if (b >= 0) key = 2 * b + (int)l;
-        }
-        if (key < 0) atomicAdd(as_global_rw(q.n_bad), 1ull);
-        as_global_rw(q.key)[i] = key;
+// The plane: points (x, y), tiles numbered beta = ty * tiles_x + tx, pairs kept in LDS as
+// (mid-point x, y, half-difference x, y).
+struct PlaneGeom {
+    using Src = float2;
+    using Pt = float2;
+    using Rev = float2;
+    using RevD = double2;
+    using Pair = float4;
+    __device__ static float2 src0() { return make_float2(0.f, 0.f); }
+    __device__ static float2 load(const EncodeReq& q, int64_t i) { return as_global(q.xy)[i]; }
+    __device__ static int nearest(const EncodeReq& q, float2 p) { return nearest_tile((double)p.x, (double)p.y, q.L); }
+    __device__ static void local(const EncodeReq& q, int beta, float2 s, float2& h, float2& l) {
+        const int tx = beta % q.L.tiles_x, ty = beta / q.L.tiles_x;
+        const double lx = (double)s.x - as_global(q.L.cx)[tx];
+        const double ly = (double)s.y - as_global(q.L.cy)[ty];
+        const float fx = (float)lx, fy = (float)ly;
+        h = make_float2(fx, fy);
+        l = make_float2((float)(lx - (double)fx), (float)(ly - (double)fy));
     }
-    const int lane = threadIdx.x & 63;
-    const uint64_t same = same_value_lanes(key < 0 ? (unsigned)q.nkeys : (unsigned)key, q.key_bits);
-    if (key >= 0 && (same & ((1ull << lane) - 1ull)) == 0) atomicAdd(&sh_hist[key], __popcll(same));
-    __syncthreads();
-    for (int k = threadIdx.x; k < q.nkeys; k += blockDim.x)
-        as_global_rw(q.hist)[(size_t)k * q.nchunks + bid] = sh_hist[k];
-}
+    __device__ static float reach(float2 v, float2 m) { return fabsf(v.x) * m.x + fabsf(v.y) * m.y; }
+    __device__ static float4 pair(float2 a, float2 b) {
+        return make_float4(0.5f * (a.x + b.x), 0.5f * (a.y + b.y), 0.5f * (a.x - b.x), 0.5f * (a.y - b.y));
+    }
+    __device__ static float mid(float2 r, float4 pr) { return __builtin_fmaf(r.x, pr.x, r.y * pr.y); }
+    __device__ static float half(float2 r, float4 pr) { return __builtin_fmaf(r.x, pr.z, r.y * pr.w); }
+    __device__ static float phase(float2 r, float2 p) { return __builtin_fmaf(r.x, p.x, r.y * p.y); }
+    __device__ static double wide(double2 r, float2 h, float2 l) {
+        const double x = (double)h.x + (double)l.x, y = (double)h.y + (double)l.y;
+        return __fma_rn(r.x, x, r.y * y);
+    }
+    __device__ static float2 rev0() { return make_float2(0.f, 0.f); }
+    __device__ static float2 rev(const EncodeReq& q, int k) { return as_global(q.rev)[k]; }
+    __device__ static double2 rev_d0() { return make_double2(0.0, 0.0); }
+    __device__ static double2 rev_d(const EncodeReq& q, int k) { return as_global(q.rev_d)[k]; }
+    __device__ static float2 max_rev(const EncodeReq& q) { return make_float2(q.max_rev_x, q.max_rev_y); }
+};
+
 __global__ __launch_bounds__(kAssignChunk) void k_assign(EncodeReq q) {
     extern __shared__ int sh_hist[];
-    assign_body(q, blockIdx.x, sh_hist);
+    assign_points<PlaneGeom>(q, blockIdx.x, sh_hist);
 }
 __global__ __launch_bounds__(kAssignChunk) void k_assign_b(const EncodeReq* __restrict__ qs, const int* __restrict__ b0,
                                                            int nq) {
     extern __shared__ int sh_hist[];
     const int r = batch_job(b0, nq, blockIdx.x);
-    assign_body(qs[r], blockIdx.x - b0[r], sh_hist);
+    assign_points<PlaneGeom>(qs[r], blockIdx.x - b0[r], sh_hist);
 }
 
 // Exclusive scan across a block of kScanThreads threads; returns the block total in *total.
@@ -224,224 +237,28 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_b(const EncodeReq* __rest
     scan_body(qs[batch_job(b0, nq, blockIdx.x)], key_start);
 }
 
-// Stable counting-sort scatter: one block of WAVES wavefronts per chunk of kAssignChunk points,
-// wave w taking the chunk's w-th part in order (four waves; one when the per-wave key tables
-// would not fit the LDS of a workgroup).  The waves' key counts give each wave its
-// own running base per key (the chunk's base plus the counts of the earlier quarters); within a
-// wave, a point's slot is its key's running base plus the number of earlier lanes of the same
-// round with the same key (lanes are matched bit by bit with ballots).
-template <int WAVES>
-__device__ inline void scatter_body(const EncodeReq& q, int bid, int* run /* LDS [WAVES][nkeys] */) {
-    gmem<float2>* __restrict__ xy = as_global(q.xy);
-    gmem<int>* __restrict__ key = as_global(q.key);
-    const int64_t n = q.n;
-    const LayoutDev& L = q.L;
-    const int nkeys = q.nkeys, nchunks = q.nchunks, key_bits = q.key_bits;
-    gmem<int>* __restrict__ base = as_global(q.hist);
-    gmem_rw<float2>* __restrict__ sorted = as_global_rw(q.sorted);
-    gmem_rw<float2>* __restrict__ sorted_lo = as_global_rw(q.sorted_lo);
-    constexpr int Q = kAssignChunk / WAVES;           // points per wave
-    constexpr int R = Q / 64;                         // rounds per wave
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t q0 = (int64_t)bid * kAssignChunk + (int64_t)wave * Q;
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int kk[R];
-    float2 pp[R];
-    uint64_t same[R];   // lanes of the round with this lane's key
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t i = q0 + r * 64 + lane;
-        kk[r] = (i < n) ? key[i] : -1;
-        pp[r] = make_float2(0.f, 0.f);
-        if (i < n) pp[r] = xy[i];
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) same[r] = same_value_lanes(kk[r] < 0 ? (unsigned)nkeys : (unsigned)kk[r], key_bits);
-    for (int k = threadIdx.x; k < WAVES * nkeys; k += blockDim.x) run[k] = 0;
-    __syncthreads();
-    int* my = run + wave * nkeys;
-#pragma unroll
-    for (int r = 0; r < R; ++r)   // one atomic per key and round
-        if (kk[r] >= 0 && (same[r] & lt_mask) == 0) atomicAdd(&my[kk[r]], __popcll(same[r]));
-    __syncthreads();
-    for (int k = threadIdx.x; k < nkeys; k += blockDim.x) {  // counts -> per-wave bases
-        int acc = base[(size_t)k * nchunks + bid];
-        for (int w = 0; w < WAVES; ++w) {
-            const int c = run[w * nkeys + k];
-            run[w * nkeys + k] = acc;
-            acc += c;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int k = kk[r];
-        if (k >= 0) {
-            const int rank = __popcll(same[r] & lt_mask);
-            const int dest = my[k] + rank;
-            const int beta = k >> 1;
-            const int tx = beta % L.tiles_x, ty = beta / L.tiles_x;
-            const double lx = (double)pp[r].x - as_global(L.cx)[tx];
-            const double ly = (double)pp[r].y - as_global(L.cy)[ty];
-            const float fx = (float)lx, fy = (float)ly;
-            sorted[dest] = make_float2(fx, fy);
-            sorted_lo[dest] = make_float2((float)(lx - (double)fx), (float)(ly - (double)fy));
-            if ((same[r] & lt_mask) == 0) my[k] += __popcll(same[r]);
-        }
-        __syncthreads();
-    }
-}
 template <int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_scatter(EncodeReq q) {
     extern __shared__ int run[];
-    scatter_body<WAVES>(q, blockIdx.x, run);
+    scatter_points<WAVES, PlaneGeom>(q, blockIdx.x, run);
 }
 template <int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_scatter_b(const EncodeReq* __restrict__ qs,
                                                           const int* __restrict__ b0, int nq) {
     extern __shared__ int run[];
     const int r = batch_job(b0, nq, blockIdx.x);
-    scatter_body<WAVES>(qs[r], blockIdx.x - b0[r], run);
+    scatter_points<WAVES, PlaneGeom>(qs[r], blockIdx.x - b0[r], run);
 }
 
-// Partial spectra of one work item for one block of bins.  Thread t owns bins
-// b0 + t + j*256, j < BPT; the points are read as wave-uniform (scalar) loads.
-// Blocks are numbered work item fastest: block bid is work item bid % max_echunks of bin block
-// bid / max_echunks.
-template <int BPT>
-__device__ inline void encode_body(const EncodeReq& q, int bid) {
-    gmem<float2>* __restrict__ sorted = as_global(q.sorted);
-    gmem<float2>* __restrict__ sorted_lo = as_global(q.sorted_lo);
-    gmem<float2>* __restrict__ rev = as_global(q.rev);
-    gmem<double2>* __restrict__ rev_d = as_global(q.rev_d);
-    const float max_rev_x = q.max_rev_x, max_rev_y = q.max_rev_y;
-    const int halfp = q.halfp;
-    gmem_rw<float2>* __restrict__ partial = as_global_rw(q.partial);
-    const int c = bid % q.max_echunks;
-    if (c >= as_global(q.meta)[0]) return;
-    const EChunk e = as_global(q.table)[c];
-    // the only work item of its memory: its sums go straight into the memory (below)
-    const bool alone = q.direct_single && as_global(q.meta)[1 + q.nkeys + e.key] == 1;
-    const int b0 = (bid / q.max_echunks) * (kEncodeThreads * BPT) + threadIdx.x;
-    gmem<float2>* __restrict__ p = sorted + e.start;
-
-    // Largest phase (revolutions) any bin can reach on this work item's points.
-    __shared__ float sh_max[kEncodeThreads / 64];
-    __shared__ float4 sh_pair[kEncodeChunk / 2];
-    float bound = 0.f;
-    for (int q = threadIdx.x; q < e.len; q += kEncodeThreads) {
-        float2 v = p[q];
-        bound = fmaxf(bound, fabsf(v.x) * max_rev_x + fabsf(v.y) * max_rev_y);
-    }
-    for (int off = 32; off > 0; off >>= 1) bound = fmaxf(bound, __shfl_xor(bound, off));
-    if ((threadIdx.x & 63) == 0) sh_max[threadIdx.x >> 6] = bound;
-    __syncthreads();
-    float wmax = 0.f;
-#pragma unroll
-    for (int w = 0; w < kEncodeThreads / 64; ++w) wmax = fmaxf(wmax, sh_max[w]);
-
-    float re[BPT], im[BPT];
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) re[j] = im[j] = 0.f;
-
-    if (wmax <= kWidePhaseRev) {
-        float ax[BPT], ay[BPT];
-#pragma unroll
-        for (int j = 0; j < BPT; ++j) {
-            const int k = b0 + j * kEncodeThreads;
-            float2 t = make_float2(0.f, 0.f);
-            if (k < halfp) t = rev[k];
-            ax[j] = t.x;
-            ay[j] = t.y;
-        }
-        // pair mid-points and half-differences, formed once per pair for all bins
-        const int npairs = e.len >> 1;
-        for (int q = threadIdx.x; q < npairs; q += kEncodeThreads) {
-            const float2 a = p[2 * q], b = p[2 * q + 1];
-            sh_pair[q] = make_float4(0.5f * (a.x + b.x), 0.5f * (a.y + b.y), 0.5f * (a.x - b.x),
-                                     0.5f * (a.y - b.y));
-        }
-        __syncthreads();
-#pragma unroll 2
-        for (int q = 0; q < npairs; ++q) {
-            const float4 pq = sh_pair[q];
-            const float mx = pq.x, my = pq.y, dx = pq.z, dy = pq.w;
-#pragma unroll
-            for (int j = 0; j < BPT; ++j) {
-                const float tm = __builtin_fmaf(ax[j], mx, ay[j] * my);
-                const float td = __builtin_fmaf(ax[j], dx, ay[j] * dy);
-                const float cd = __builtin_amdgcn_cosf(td);
-                re[j] = __builtin_fmaf(cd, __builtin_amdgcn_cosf(tm), re[j]);
-                im[j] = __builtin_fmaf(cd, __builtin_amdgcn_sinf(tm), im[j]);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < BPT; ++j) {
-            re[j] *= 2.f;
-            im[j] *= 2.f;
-        }
-        if (e.len & 1) {
-            const float2 a = p[e.len - 1];
-#pragma unroll
-            for (int j = 0; j < BPT; ++j) {
-                const float t = __builtin_fmaf(ax[j], a.x, ay[j] * a.y);
-                re[j] += __builtin_amdgcn_cosf(t);
-                im[j] += __builtin_amdgcn_sinf(t);
-            }
-        }
-    } else {
-        // Large arguments: the phase is formed and wrapped to [-1/2, 1/2] revolutions in
-        // double precision, from the double-float local coordinates.
-        double ax[BPT], ay[BPT];
-#pragma unroll
-        for (int j = 0; j < BPT; ++j) {
-            const int k = b0 + j * kEncodeThreads;
-            double2 t = make_double2(0.0, 0.0);
-            if (k < halfp) t = rev_d[k];
-            ax[j] = t.x;
-            ay[j] = t.y;
-        }
-        gmem<float2>* __restrict__ plo = sorted_lo + e.start;
-        for (int q = 0; q < e.len; ++q) {
-            const float2 a = p[q], al = plo[q];
-            const double x = (double)a.x + (double)al.x, y = (double)a.y + (double)al.y;
-#pragma unroll
-            for (int j = 0; j < BPT; ++j) {
-                const double t = __fma_rn(ax[j], x, ay[j] * y);
-                const float r = (float)(t - rint(t));
-                re[j] += __builtin_amdgcn_cosf(r);
-                im[j] += __builtin_amdgcn_sinf(r);
-            }
-        }
-    }
-    if (alone) {
-        // what the reduction would add for one work item: w + (0 + s), bins below half only
-        gmem_rw<float2>* __restrict__ w = as_global_rw(q.omega) + (size_t)e.key * halfp;
-#pragma unroll
-        for (int j = 0; j < BPT; ++j) {
-            const int k = b0 + j * kEncodeThreads;
-            if (k < q.half) {
-                const float2 o = w[k];
-                w[k] = make_float2(o.x + (0.f + re[j]), o.y + (0.f + im[j]));
-            }
-        }
-        return;
-    }
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) {
-        const int k = b0 + j * kEncodeThreads;
-        if (k < halfp) partial[(size_t)c * halfp + k] = make_float2(re[j], im[j]);
-    }
-}
 template <int BPT>
 __global__ __launch_bounds__(kEncodeThreads) void k_encode(EncodeReq q) {
-    encode_body<BPT>(q, blockIdx.x);
+    encode_points<BPT, PlaneGeom>(q, blockIdx.x);
 }
 template <int BPT>
 __global__ __launch_bounds__(kEncodeThreads) void k_encode_b(const EncodeReq* __restrict__ qs,
                                                              const int* __restrict__ b0, int nq) {
     const int r = batch_job(b0, nq, blockIdx.x);
-    encode_body<BPT>(qs[r], blockIdx.x - b0[r]);
+    encode_points<BPT, PlaneGeom>(qs[r], blockIdx.x - b0[r]);
 }
 
 // omega[key][k] += sum over the key's work items.  Four groups of 64 threads per block of 64
@@ -678,9 +495,10 @@ void launch_key_scan(int* hist, int nchunks, int nkeys, int echunk, EChunk* tabl
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), nkeys * sizeof(int), s, q);
 }
 
-void launch_key_reduce(const float2* partial, const int* meta, int nkeys, int half, int halfp, float2* omega,
-                       hipStream_t s) {
+void launch_key_reduce(const float2* partial, const int* meta, int nkeys, int half, int halfp, int direct_single,
+                       float2* omega, hipStream_t s) {
     EncodeReq q{};
+    q.direct_single = direct_single;
     q.partial = const_cast<float2*>(partial);
     q.meta = const_cast<int*>(meta);
     q.nkeys = nkeys;

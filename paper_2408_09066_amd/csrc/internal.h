@@ -275,9 +275,10 @@ EncodePlan encode_plan(int64_t n, int halfp, int nkeys);
 // version, if not NULL, is bumped for every key that received points).  One block.
 void launch_key_scan(int* hist, int nchunks, int nkeys, int echunk, EChunk* table, int* meta, unsigned* version,
                      hipStream_t s);
-// omega[key] += the key's work-item partial spectra in work-item order.
-void launch_key_reduce(const float2* partial, const int* meta, int nkeys, int half, int halfp, float2* omega,
-                       hipStream_t s);
+// omega[key] += the key's work-item partial spectra in work-item order.  With direct_single, keys
+// with exactly one work item are skipped (their encode added its sums into omega itself).
+void launch_key_reduce(const float2* partial, const int* meta, int nkeys, int half, int halfp, int direct_single,
+                       float2* omega, hipStream_t s);
 
 hipError_t launch_encode(const float* xy, const uint8_t* label, int64_t n, const LayoutDev& L,
                          int nkeys, const float2* theta_rev, const double* theta_rev_d,

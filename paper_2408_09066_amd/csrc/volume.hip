@@ -3,15 +3,12 @@
 // numbered beta = (tz * ty_n + ty) * tx_n + tx; the entropy window is the ball of integer voxel
 // offsets dx^2 + dy^2 + dz^2 <= r^2.
 //
-//   k3_assign   nearest tile (exact double-precision argmin over the 3x3x3 neighbourhood of the
-//               per-axis guess, lowest index on ties), key 2*beta+psi, label check, per-chunk key
-//               histogram; the scan of the histogram into sort offsets and work items, and the
-//               final reduction, are the plane encoder's (encode.hip)
-//   k3_scatter  stable counting sort of the tile-local coordinates (and their rounding
-//               residuals) by key
-//   k3_encode   per (work item of one memory's sorted points, block of bins): sum of
-//               exp(2 pi i t), t in revolutions, two points per step; a work item whose phases
-//               could exceed kWidePhaseRev forms and wraps them in double precision
+//   k3_assign, k3_scatter, k3_encode   the map's encode stages (bundle.h) on VolumeGeom: nearest
+//               tile (exact double-precision argmin over the 3x3x3 neighbourhood of the per-axis
+//               guess, lowest index on ties), key 2*beta+psi, per-chunk key histogram; stable
+//               counting sort of the tile-local coordinates; per (work item, block of bins) sum of
+//               exp(2 pi i t), two points per step.  The scan of the histogram into sort offsets
+//               and work items, and the final reduction, are the map encoder's (encode.hip)
 //   k3_classify_tiled  radii <= kClassify3TiledRadius: per 8x8x8 block, -Q ln Q with
 //               Q = (P / max P)^2 of the block and its halo into LDS, ball sums there, softmax
 //               difference tanh((H1 - H0)/2), threshold
@@ -19,7 +16,7 @@
 // The similarity of every voxel is the same GEMM as for maps: its rows are the volume's joint
 // (z, y) rows, with a cached table of exp(i (Theta_y y + Theta_z z)) as the row operand
 // (decode.hip).
-#include "internal.h"
+#include "bundle.h"
 
 namespace vsaogm {
 namespace {
@@ -60,201 +57,97 @@ __device__ int nearest_tile3(double x, double y, double z, const Layout3Dev& L) 
     return best;
 }
 
-// One point per thread, blocks of kAssignChunk points; hist[key][chunk] = the chunk's count,
-// added with one LDS atomic per key and wavefront.
-__global__ __launch_bounds__(kAssignChunk) void k3_assign(const float* __restrict__ xyz,
-                                                          const uint8_t* __restrict__ label, int64_t n,
-                                                          Layout3Dev L, int nkeys, int nchunks, int key_bits,
-                                                          int* __restrict__ key_out, int* __restrict__ hist,
-                                                          unsigned long long* __restrict__ n_bad) {
+// The encode of a volume, as one record that the shared bodies read (member names as for a map's
+// encode).
+struct EncodeReq3 {
+    const float* xyz;               // [n][3] world metres
+    const uint8_t* label;           // [n]
+    int64_t n;
+    Layout3Dev L;
+    int nkeys, key_bits, nchunks, max_echunks;
+    int* key;
+    int* hist;
+    EChunk* table;
+    int* meta;
+    float4* sorted;                 // [n] local (x, y, z, 0)
+    float4* sorted_lo;              // [n] rounding residuals
+    float2* partial;
+    unsigned long long* n_bad;
+    const float4* rev;              // [halfp] (x, y, z, 0) revolutions per metre
+    const double* rev_d;            // [halfp][3]
+    float4 max_rev;
+    int half, halfp;
+    int direct_single;              // as for maps: a memory with one work item is written directly
+    float2* omega;
+};
+
+struct D3 {
+    double x, y, z;
+};
+struct Pair3 {
+    float4 m, d;   // mid-point, half-difference (w unused)
+};
+
+// The volume: points (x, y, z), tiles numbered beta = (tz * ty_n + ty) * tx_n + tx.
+struct VolumeGeom {
+    using Src = float3;
+    using Pt = float4;
+    using Rev = float4;
+    using RevD = D3;
+    using Pair = Pair3;
+    __device__ static float3 src0() { return make_float3(0.f, 0.f, 0.f); }
+    __device__ static float3 load(const EncodeReq3& q, int64_t i) {
+        gmem<float>* __restrict__ p = as_global(q.xyz) + 3 * i;
+        return make_float3(p[0], p[1], p[2]);
+    }
+    __device__ static int nearest(const EncodeReq3& q, float3 p) { return nearest_tile3(p.x, p.y, p.z, q.L); }
+    __device__ static void local(const EncodeReq3& q, int beta, float3 s, float4& h, float4& l) {
+        const Layout3Dev& L = q.L;
+        const int tx = beta % L.tx, ty = (beta / L.tx) % L.ty, tz = beta / (L.tx * L.ty);
+        const double lx = (double)s.x - as_global(L.cx)[tx], ly = (double)s.y - as_global(L.cy)[ty],
+                     lz = (double)s.z - as_global(L.cz)[tz];
+        const float fx = (float)lx, fy = (float)ly, fz = (float)lz;
+        h = make_float4(fx, fy, fz, 0.f);
+        l = make_float4((float)(lx - (double)fx), (float)(ly - (double)fy), (float)(lz - (double)fz), 0.f);
+    }
+    __device__ static float reach(float4 v, float4 m) {
+        return fabsf(v.x) * m.x + fabsf(v.y) * m.y + fabsf(v.z) * m.z;
+    }
+    __device__ static Pair3 pair(float4 a, float4 b) {
+        return Pair3{make_float4(0.5f * (a.x + b.x), 0.5f * (a.y + b.y), 0.5f * (a.z + b.z), 0.f),
+                     make_float4(0.5f * (a.x - b.x), 0.5f * (a.y - b.y), 0.5f * (a.z - b.z), 0.f)};
+    }
+    __device__ static float phase(float4 r, float4 p) {
+        return __builtin_fmaf(r.x, p.x, __builtin_fmaf(r.y, p.y, r.z * p.z));
+    }
+    __device__ static float mid(float4 r, const Pair3& pr) { return phase(r, pr.m); }
+    __device__ static float half(float4 r, const Pair3& pr) { return phase(r, pr.d); }
+    __device__ static double wide(const D3& r, float4 h, float4 l) {
+        const double x = (double)h.x + (double)l.x, y = (double)h.y + (double)l.y, z = (double)h.z + (double)l.z;
+        return r.x * x + r.y * y + r.z * z;
+    }
+    __device__ static float4 rev0() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+    __device__ static float4 rev(const EncodeReq3& q, int k) { return as_global(q.rev)[k]; }
+    __device__ static D3 rev_d0() { return D3{0.0, 0.0, 0.0}; }
+    __device__ static D3 rev_d(const EncodeReq3& q, int k) {
+        gmem<double>* __restrict__ p = as_global(q.rev_d) + 3 * k;
+        return D3{p[0], p[1], p[2]};
+    }
+    __device__ static float4 max_rev(const EncodeReq3& q) { return q.max_rev; }
+};
+
+__global__ __launch_bounds__(kAssignChunk) void k3_assign(EncodeReq3 q) {
     extern __shared__ int sh_hist[];
-    for (int k = threadIdx.x; k < nkeys; k += blockDim.x) sh_hist[k] = 0;
-    __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * kAssignChunk + threadIdx.x;
-    int k = -1;
-    if (i < n) {
-        const unsigned l = label[i];
-        if (l <= 1u) k = 2 * nearest_tile3(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], L) + (int)l;
-        if (k < 0) atomicAdd(n_bad, 1ull);
-        key_out[i] = k;
-    }
-    const int lane = threadIdx.x & 63;
-    const uint64_t same = same_value_lanes(k < 0 ? (unsigned)nkeys : (unsigned)k, key_bits);
-    if (k >= 0 && (same & ((1ull << lane) - 1ull)) == 0) atomicAdd(&sh_hist[k], __popcll(same));
-    __syncthreads();
-    for (int k = threadIdx.x; k < nkeys; k += blockDim.x) hist[(size_t)k * nchunks + blockIdx.x] = sh_hist[k];
+    assign_points<VolumeGeom>(q, blockIdx.x, sh_hist);
 }
-
-// Stable counting-sort scatter, one block of WAVES wavefronts per chunk of kAssignChunk points;
-// wave w takes the chunk's w-th part.  Each wave starts every key at the chunk's base plus the
-// counts of the earlier waves; within a round of 64 lanes, a point's rank among equal keys comes
-// from ballots over the key's bits.  The destination receives the tile-local coordinates,
-// formed in double precision and split into fp32 value and residual.
 template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k3_scatter(const float* __restrict__ xyz, const int* __restrict__ key,
-                                                         int64_t n, Layout3Dev L, int nkeys, int nchunks,
-                                                         int key_bits, const int* __restrict__ base,
-                                                         float4* __restrict__ sorted,
-                                                         float4* __restrict__ sorted_lo) {
+__global__ __launch_bounds__(64 * WAVES) void k3_scatter(EncodeReq3 q) {
     extern __shared__ int run[];   // [WAVES][nkeys]
-    constexpr int Q = kAssignChunk / WAVES, R = Q / 64;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t q0 = (int64_t)blockIdx.x * kAssignChunk + (int64_t)wave * Q;
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int kk[R];
-    uint64_t same[R];   // lanes of the round with this lane's key
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t i = q0 + r * 64 + lane;
-        kk[r] = (i < n) ? key[i] : -1;
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) same[r] = same_value_lanes(kk[r] < 0 ? (unsigned)nkeys : (unsigned)kk[r], key_bits);
-    for (int k = threadIdx.x; k < WAVES * nkeys; k += blockDim.x) run[k] = 0;
-    __syncthreads();
-    int* my = run + wave * nkeys;
-#pragma unroll
-    for (int r = 0; r < R; ++r)   // one atomic per key and round
-        if (kk[r] >= 0 && (same[r] & lt_mask) == 0) atomicAdd(&my[kk[r]], __popcll(same[r]));
-    __syncthreads();
-    for (int k = threadIdx.x; k < nkeys; k += blockDim.x) {
-        int acc = base[(size_t)k * nchunks + blockIdx.x];
-        for (int w = 0; w < WAVES; ++w) {
-            const int c = run[w * nkeys + k];
-            run[w * nkeys + k] = acc;
-            acc += c;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int k = kk[r];
-        if (k >= 0) {
-            const int64_t i = q0 + r * 64 + lane;
-            const int dest = my[k] + __popcll(same[r] & lt_mask);
-            const int b = k >> 1;
-            const int tx = b % L.tx, ty = (b / L.tx) % L.ty, tz = b / (L.tx * L.ty);
-            const double lx = (double)xyz[3 * i] - L.cx[tx], ly = (double)xyz[3 * i + 1] - L.cy[ty],
-                         lz = (double)xyz[3 * i + 2] - L.cz[tz];
-            const float fx = (float)lx, fy = (float)ly, fz = (float)lz;
-            sorted[dest] = make_float4(fx, fy, fz, 0.f);
-            sorted_lo[dest] = make_float4((float)(lx - (double)fx), (float)(ly - (double)fy), (float)(lz - (double)fz), 0.f);
-            if ((same[r] & lt_mask) == 0) my[k] += __popcll(same[r]);
-        }
-        __syncthreads();
-    }
+    scatter_points<WAVES, VolumeGeom>(q, blockIdx.x, run);
 }
-
-// Partial spectrum of one work item (consecutive sorted points of one memory) for one block of
-// bins; thread t owns bins b0 + t + j kEncodeThreads, j < BPT.  Consecutive points go in pairs:
-//   exp(i a) + exp(i b) = 2 cos((a - b) / 2) exp(i (a + b) / 2),
-// three hardware sine/cosine evaluations per two points, with the pair's mid-point and
-// half-difference formed once in LDS for all bins.
 template <int BPT>
-__global__ __launch_bounds__(kEncodeThreads) void k3_encode(const float4* __restrict__ sorted,
-                                                            const float4* __restrict__ sorted_lo,
-                                                            const EChunk* __restrict__ table,
-                                                            const int* __restrict__ meta,
-                                                            const float4* __restrict__ rev,
-                                                            const double* __restrict__ rev_d, float4 max_rev,
-                                                            int halfp, float2* __restrict__ partial) {
-    const int c = blockIdx.x;
-    if (c >= meta[0]) return;
-    const EChunk e = table[c];
-    const int b0 = blockIdx.y * (kEncodeThreads * BPT) + threadIdx.x;
-    const float4* __restrict__ p = sorted + e.start;
-    __shared__ float sh_max[kEncodeThreads / 64];
-    __shared__ float4 sh_mid[kEncodeChunk / 2], sh_hd[kEncodeChunk / 2];
-
-    // largest phase (revolutions) any bin can reach on the work item's points
-    float bound = 0.f;
-    for (int q = threadIdx.x; q < e.len; q += kEncodeThreads) {
-        const float4 v = p[q];
-        bound = fmaxf(bound, fabsf(v.x) * max_rev.x + fabsf(v.y) * max_rev.y + fabsf(v.z) * max_rev.z);
-    }
-    for (int off = 32; off > 0; off >>= 1) bound = fmaxf(bound, __shfl_xor(bound, off));
-    if ((threadIdx.x & 63) == 0) sh_max[threadIdx.x >> 6] = bound;
-    __syncthreads();
-    float wmax = 0.f;
-#pragma unroll
-    for (int w = 0; w < kEncodeThreads / 64; ++w) wmax = fmaxf(wmax, sh_max[w]);
-
-    float re[BPT], im[BPT];
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) re[j] = im[j] = 0.f;
-    if (wmax <= kWidePhaseRev) {
-        float ax[BPT], ay[BPT], az[BPT];
-#pragma unroll
-        for (int j = 0; j < BPT; ++j) {
-            const int k = b0 + j * kEncodeThreads;
-            const float4 t = (k < halfp) ? rev[k] : make_float4(0.f, 0.f, 0.f, 0.f);
-            ax[j] = t.x;
-            ay[j] = t.y;
-            az[j] = t.z;
-        }
-        const int npairs = e.len >> 1;
-        for (int q = threadIdx.x; q < npairs; q += kEncodeThreads) {
-            const float4 a = p[2 * q], b = p[2 * q + 1];
-            sh_mid[q] = make_float4(0.5f * (a.x + b.x), 0.5f * (a.y + b.y), 0.5f * (a.z + b.z), 0.f);
-            sh_hd[q] = make_float4(0.5f * (a.x - b.x), 0.5f * (a.y - b.y), 0.5f * (a.z - b.z), 0.f);
-        }
-        __syncthreads();
-#pragma unroll 2
-        for (int q = 0; q < npairs; ++q) {
-            const float4 m = sh_mid[q], d = sh_hd[q];
-#pragma unroll
-            for (int j = 0; j < BPT; ++j) {
-                const float tm = __builtin_fmaf(ax[j], m.x, __builtin_fmaf(ay[j], m.y, az[j] * m.z));
-                const float td = __builtin_fmaf(ax[j], d.x, __builtin_fmaf(ay[j], d.y, az[j] * d.z));
-                const float cd = __builtin_amdgcn_cosf(td);
-                re[j] = __builtin_fmaf(cd, __builtin_amdgcn_cosf(tm), re[j]);
-                im[j] = __builtin_fmaf(cd, __builtin_amdgcn_sinf(tm), im[j]);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < BPT; ++j) {
-            re[j] *= 2.f;
-            im[j] *= 2.f;
-        }
-        if (e.len & 1) {
-            const float4 a = p[e.len - 1];
-#pragma unroll
-            for (int j = 0; j < BPT; ++j) {
-                const float t = __builtin_fmaf(ax[j], a.x, __builtin_fmaf(ay[j], a.y, az[j] * a.z));
-                re[j] += __builtin_amdgcn_cosf(t);
-                im[j] += __builtin_amdgcn_sinf(t);
-            }
-        }
-    } else {
-        // large arguments: phase formed and wrapped to [-1/2, 1/2] revolutions in double
-        // precision from the double-float local coordinates
-        const float4* __restrict__ plo = sorted_lo + e.start;
-        double ax[BPT], ay[BPT], az[BPT];
-#pragma unroll
-        for (int j = 0; j < BPT; ++j) {
-            const int k = min(b0 + j * kEncodeThreads, halfp - 1);
-            ax[j] = rev_d[3 * k];
-            ay[j] = rev_d[3 * k + 1];
-            az[j] = rev_d[3 * k + 2];
-        }
-        for (int q = 0; q < e.len; ++q) {
-            const float4 a = p[q], al = plo[q];
-            const double x = (double)a.x + (double)al.x, y = (double)a.y + (double)al.y,
-                         z = (double)a.z + (double)al.z;
-#pragma unroll
-            for (int j = 0; j < BPT; ++j) {
-                const double t = ax[j] * x + ay[j] * y + az[j] * z;
-                const float r = (float)(t - rint(t));
-                re[j] += __builtin_amdgcn_cosf(r);
-                im[j] += __builtin_amdgcn_sinf(r);
-            }
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) {
-        const int k = b0 + j * kEncodeThreads;
-        if (k < halfp) partial[(size_t)c * halfp + k] = make_float2(re[j], im[j]);
-    }
+__global__ __launch_bounds__(kEncodeThreads) void k3_encode(EncodeReq3 q) {
+    encode_points<BPT, VolumeGeom>(q, blockIdx.x);
 }
 
 // Entropy term -Q ln Q of one similarity, Q = (P / max P)^2 (0 when the class maximum is not
@@ -423,26 +316,44 @@ hipError_t launch_encode3(const float* xyz, const uint8_t* label, int64_t n, con
                           int halfp, const Encode3Work& w, float2* omega, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const EncodePlan p = encode_plan(n, halfp, nkeys);
-    Layout3Dev L{V.cx, V.cy, V.cz, V.tx, V.ty, V.tz, V.x0, V.y0, V.z0, V.wx, V.wy, V.wz};
-    hipLaunchKernelGGL(k3_assign, dim3(p.nchunks), dim3(kAssignChunk), nkeys * sizeof(int), s, xyz, label, n, L,
-                       nkeys, p.nchunks, key_bits_for(nkeys), w.key, w.hist, w.n_bad);
+    EncodeReq3 q{};
+    q.xyz = xyz;
+    q.label = label;
+    q.n = n;
+    q.L = Layout3Dev{V.cx, V.cy, V.cz, V.tx, V.ty, V.tz, V.x0, V.y0, V.z0, V.wx, V.wy, V.wz};
+    q.nkeys = nkeys;
+    q.key_bits = key_bits_for(nkeys);
+    q.nchunks = p.nchunks;
+    q.max_echunks = p.max_echunks;
+    q.key = w.key;
+    q.hist = w.hist;
+    q.table = w.table;
+    q.meta = w.meta;
+    q.sorted = w.sorted;
+    q.sorted_lo = w.sorted_lo;
+    q.partial = w.partial;
+    q.n_bad = w.n_bad;
+    q.rev = rev;
+    q.rev_d = rev_d;
+    q.max_rev = max_rev;
+    q.half = half;
+    q.halfp = halfp;
+    q.direct_single = 1;
+    q.omega = omega;
+    hipLaunchKernelGGL(k3_assign, dim3(p.nchunks), dim3(kAssignChunk), nkeys * sizeof(int), s, q);
     launch_key_scan(w.hist, p.nchunks, nkeys, p.echunk, w.table, w.meta, nullptr, s);
     if (4 * nkeys * (int)sizeof(int) <= 65536)
-        hipLaunchKernelGGL(k3_scatter<4>, dim3(p.nchunks), dim3(256), 4 * nkeys * sizeof(int), s, xyz, w.key, n, L,
-                           nkeys, p.nchunks, key_bits_for(nkeys), w.hist, w.sorted, w.sorted_lo);
+        hipLaunchKernelGGL(k3_scatter<4>, dim3(p.nchunks), dim3(256), 4 * nkeys * sizeof(int), s, q);
     else
-        hipLaunchKernelGGL(k3_scatter<1>, dim3(p.nchunks), dim3(64), nkeys * sizeof(int), s, xyz, w.key, n, L,
-                           nkeys, p.nchunks, key_bits_for(nkeys), w.hist, w.sorted, w.sorted_lo);
-    const dim3 eg(p.max_echunks, p.binblocks);
+        hipLaunchKernelGGL(k3_scatter<1>, dim3(p.nchunks), dim3(64), nkeys * sizeof(int), s, q);
+    const unsigned eblocks = (unsigned)p.max_echunks * (unsigned)p.binblocks;
     const hipEvent_t e0 = profile_start(kStageEncode), e1 = profile_stop(kStageEncode);
     static_assert(kEncodeBpt == 2, "instantiations below");
     if (p.bpt == 1)
-        hipExtLaunchKernelGGL(k3_encode<1>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo, w.table,
-                              w.meta, rev, rev_d, max_rev, halfp, w.partial);
+        hipExtLaunchKernelGGL(k3_encode<1>, dim3(eblocks), dim3(kEncodeThreads), 0, s, e0, e1, 0, q);
     else
-        hipExtLaunchKernelGGL(k3_encode<2>, eg, dim3(kEncodeThreads), 0, s, e0, e1, 0, w.sorted, w.sorted_lo, w.table,
-                              w.meta, rev, rev_d, max_rev, halfp, w.partial);
-    launch_key_reduce(w.partial, w.meta, nkeys, half, halfp, omega, s);
+        hipExtLaunchKernelGGL(k3_encode<2>, dim3(eblocks), dim3(kEncodeThreads), 0, s, e0, e1, 0, q);
+    launch_key_reduce(w.partial, w.meta, nkeys, half, halfp, 1, omega, s);
     return hipGetLastError();
 }
 
