@@ -108,36 +108,53 @@ __device__ inline void store16(const double (&v)[2], size_t o, int fp16, uint16_
     }
 }
 
-// 16-bit tables [c][2*halfp] (re, im per bin); lo holds the rounding residual (split form).
+// 16-bit row tables are stored in the operand order of v_mfma_f32_32x32x16: rows in blocks of
+// 32, and for every block, K step (32 bins = 64 reals, re and im interleaved) and 16-real chunk of
+// the step, one contiguous 1 KB fragment whose 16-byte piece l holds reals 8 (l / 32) .. + 7 of
+// the chunk for row l % 32 of the block.  A wavefront's operand load is then 1 KB of consecutive
+// bytes (a row-major table would touch 32 lines and use 32 bytes of each).  Element e of row r:
+__device__ inline size_t frag16(int r, int e, int ksteps) {
+    const int b = r >> 5, rr = r & 31;
+    const int kb = e >> 6, ch = (e >> 4) & 3, h = (e >> 3) & 1, j = e & 7;
+    return ((((size_t)b * ksteps + kb) * 4 + ch) * 64 + rr + 32 * h) * 8 + j;
+}
+
+// 16-bit tables of nrows rows (re, im per bin, in the order above); lo holds the rounding
+// residual (split form).  One block per row of the table, which has rows16(nrows) rows: the
+// rows past nrows are zero.
 __global__ __launch_bounds__(256) void k_table_16(const double* __restrict__ theta_rad, int axis,
-                                                  const double* __restrict__ local, int half,
+                                                  const double* __restrict__ local, int nrows, int half,
                                                   int halfp, int fp16, uint16_t* __restrict__ hi,
                                                   uint16_t* __restrict__ lo) {
-    const int c = blockIdx.y;
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= halfp) return;
-    double v[2] = {0.0, 0.0};
-    if (k < half) sincos(theta_rad[2 * k + axis] * local[c], &v[1], &v[0]);
-    store16(v, (size_t)c * 2 * halfp + 2 * k, fp16, hi, lo);
+    const int r = blockIdx.x, ks = halfp / 32;
+    for (int k = threadIdx.x; k < halfp; k += 256) {
+        double v[2] = {0.0, 0.0};
+        if (r < nrows && k < half) sincos(theta_rad[2 * k + axis] * local[r], &v[1], &v[0]);
+        store16(v, frag16(r, 2 * k, ks), fp16, hi, lo);
+    }
 }
 
 // Joint (z, y) rows of a volume, one block per row r of the row space: voxel plane offset
 // row_map[r] = slice * ny + y, spectrum exp(i (Theta_y[k] y + Theta_z[k] z)) with the phase
-// formed in double precision from the tile-local coordinates.
+// formed in double precision from the tile-local coordinates.  Same order and padding as above.
 __global__ __launch_bounds__(256) void k_table_yz_16(const double* __restrict__ theta_xy,
                                                      const double* __restrict__ theta_z,
                                                      const double* __restrict__ local_y,
                                                      const double* __restrict__ local_z,
-                                                     const int* __restrict__ row_map, int ny, int half,
-                                                     int halfp, int fp16, uint16_t* __restrict__ hi,
+                                                     const int* __restrict__ row_map, int nrows, int ny,
+                                                     int half, int halfp, int fp16, uint16_t* __restrict__ hi,
                                                      uint16_t* __restrict__ lo) {
-    const int r = blockIdx.x;
-    const int rm = row_map[r];
-    const double y = local_y[rm % ny], z = local_z[rm / ny];
+    const int r = blockIdx.x, ks = halfp / 32;
+    double y = 0.0, z = 0.0;
+    if (r < nrows) {
+        const int rm = row_map[r];
+        y = local_y[rm % ny];
+        z = local_z[rm / ny];
+    }
     for (int k = threadIdx.x; k < halfp; k += 256) {
         double v[2] = {0.0, 0.0};
-        if (k < half) sincos(theta_xy[2 * k + 1] * y + theta_z[2 * k] * z, &v[1], &v[0]);
-        store16(v, (size_t)r * 2 * halfp + 2 * k, fp16, hi, lo);
+        if (r < nrows && k < half) sincos(theta_xy[2 * k + 1] * y + theta_z[2 * k] * z, &v[1], &v[0]);
+        store16(v, frag16(r, 2 * k, ks), fp16, hi, lo);
     }
 }
 
@@ -214,13 +231,8 @@ __device__ inline void apply_request(DecodeArgs& r, const DTile& t) {
     r.ksteps = q.ksteps;
 }
 
-// Operand formats: FP32 (0), BF16 (1), FP16 (2), BF16 hi+lo (3).
-template <int PREC>
-struct Fmt {
-    static constexpr bool kSplit = (PREC == 3);
-    static constexpr bool k16 = (PREC != 0);
-    static constexpr int KB = k16 ? 32 : 16;  // complex bins per K step (128-byte rows)
-};
+// Operand formats: FP32 (0), BF16 (1), FP16 (2), BF16 hi+lo (3).  k_decode below takes FP32
+// operands; the 16-bit formats run k_decode16.
 
 __device__ inline void store_tile(const DecodeArgs& a, const DTile& t, int wave, int lane,
                                   const v4f (&acc)[2][kRowBlocks]) {
@@ -249,18 +261,16 @@ __device__ inline void store_tile(const DecodeArgs& a, const DTile& t, int wave,
     }
 }
 
-// Workgroups resident per CU: two for the single-product formats; the split form needs more
-// registers than two waves per SIMD allow, so it runs one.
-template <int PREC>
-constexpr int kDecodeOccupancy = (PREC == 3) ? 1 : 2;
+// Workgroups of the fp32 kernel resident per CU.
+constexpr int kDecodeOccupancy32 = 2;
 
+// FP32 operands (PREC 0 only).
 template <int PREC>
-__global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeArgs a) {
-    using F = Fmt<PREC>;
-    constexpr int KB = F::KB;
-    constexpr int NSPLIT = F::kSplit ? 2 : 1;
-    // LDS, two stages: A rows [kTileRows], B rows [2 classes][kTileCols], each
-    // kRowPitchBytes, hi (+ lo).
+__global__ __launch_bounds__(256, kDecodeOccupancy32) void k_decode(DecodeArgs a) {
+    static_assert(PREC == 0, "the 16-bit formats run k_decode16");
+    constexpr int KB = 16;    // complex bins per K step (128-byte rows)
+    constexpr int NSPLIT = 1;
+    // LDS, two stages: A rows [kTileRows], B rows [2 classes][kTileCols], each kRowPitchBytes.
     constexpr int STAGE = NSPLIT * (kTileRows + 2 * kTileCols) * kRowPitchBytes;
     __shared__ __attribute__((aligned(16))) unsigned char smem[2 * STAGE];
 
@@ -325,17 +335,8 @@ __global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeAr
                 if (idx >= A_UNITS_MAX) break;  // only the last unit round is partial
                 const int r = idx >> 3, part = idx & 7;
                 const int grow = min(t.row0 + min(r, nrows - 1), t.row_end - 1);
-                if (PREC == 0) {
-                    const float2* src = static_cast<const float2*>(a.ey) + (size_t)grow * a.halfp +
-                                        (size_t)kb * KB + 2 * part;
-                    ra[u * NSPLIT] = *reinterpret_cast<const u32x4*>(src);
-                } else {
-                    const size_t off = (size_t)grow * 2 * a.halfp + (size_t)kb * KB * 2 + 8 * part;
-                    ra[u * NSPLIT] = *reinterpret_cast<const u32x4*>(static_cast<const uint16_t*>(a.ey) + off);
-                    if (F::kSplit)
-                        ra[u * NSPLIT + NSPLIT - 1] =
-                            *reinterpret_cast<const u32x4*>(static_cast<const uint16_t*>(a.ey_lo) + off);
-                }
+                const float2* src = static_cast<const float2*>(a.ey) + (size_t)grow * a.halfp + (size_t)kb * KB + 2 * part;
+                ra[u * NSPLIT] = *reinterpret_cast<const u32x4*>(src);
             }
 #pragma unroll
             for (int u = 0; u < B_PER_T; ++u) {
@@ -347,7 +348,7 @@ __global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeAr
         };
 
         // Registers of one K step into LDS stage `st`; the column operand becomes
-        // conj(Omega)/||w|| * Ex written as (Re, -Im), rounded to the operand format.
+        // conj(Omega)/||w|| * Ex written as (Re, -Im).
         auto lstore = [&](int st) {
             unsigned char* As = smem + st * STAGE;
             unsigned char* Bs = As + NSPLIT * kTileRows * kRowPitchBytes;
@@ -374,17 +375,7 @@ __global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeAr
                     const float r2 = __builtin_fmaf(o.z, e.z, -o.w * e.w);
                     const float r3 = -__builtin_fmaf(o.z, e.w, o.w * e.z);
                     unsigned char* dst = Bs + (p * kTileCols + c) * kRowPitchBytes;
-                    if (PREC == 0) {
-                        *reinterpret_cast<f32x4*>(dst + 16 * part) = f32x4{r0, r1, r2, r3};
-                    } else if (PREC == 2) {
-                        *reinterpret_cast<u32x2*>(dst + 8 * part) = u32x2{pack_f16(r0, r1), pack_f16(r2, r3)};
-                    } else {
-                        const uint32_t h01 = pack_bf16(r0, r1), h23 = pack_bf16(r2, r3);
-                        *reinterpret_cast<u32x2*>(dst + 8 * part) = u32x2{h01, h23};
-                        if (F::kSplit)
-                            *reinterpret_cast<u32x2*>(dst + 2 * kTileCols * kRowPitchBytes + 8 * part) =
-                                u32x2{pack_bf16_lo(r0, r1, h01), pack_bf16_lo(r2, r3, h23)};
-                    }
+                    *reinterpret_cast<f32x4*>(dst + 16 * part) = f32x4{r0, r1, r2, r3};
                 }
             }
         };
@@ -410,7 +401,7 @@ __global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeAr
             const int bcol = 16 * wave + i16;
             // MFMAs are issued with the row-block loop innermost so that consecutive
             // instructions update different accumulators (no back-to-back dependency).
-            if (PREC == 0) {
+            {
                 float b[2][8];
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
@@ -437,43 +428,6 @@ __global__ __launch_bounds__(256, kDecodeOccupancy<PREC>) void k_decode(DecodeAr
 #pragma unroll
                             for (int p = 0; p < 2; ++p)
                                 acc[p][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rb][s], b[p][s], acc[p][rb], 0, 0, 0);
-            } else {
-#pragma unroll
-                for (int ch = 0; ch < 2; ++ch) {  // two 32-real halves of the 64-real K step
-                    u32x4 bh[2], bl[2];
-#pragma unroll
-                    for (int p = 0; p < 2; ++p) {
-                        const unsigned char* src = Bs + (p * kTileCols + bcol) * kRowPitchBytes + 64 * ch + 16 * g;
-                        bh[p] = *reinterpret_cast<const u32x4*>(src);
-                        if (F::kSplit) bl[p] = *reinterpret_cast<const u32x4*>(src + 2 * kTileCols * kRowPitchBytes);
-                    }
-                    u32x4 ah[kRowBlocks], al[kRowBlocks];
-#pragma unroll
-                    for (int rb = 0; rb < kRowBlocks; ++rb) {
-                        if (rb < t.nrb) {
-                            const unsigned char* src = As + (16 * rb + i16) * kRowPitchBytes + 64 * ch + 16 * g;
-                            ah[rb] = *reinterpret_cast<const u32x4*>(src);
-                            if (F::kSplit) al[rb] = *reinterpret_cast<const u32x4*>(src + kTileRows * kRowPitchBytes);
-                        }
-                    }
-                    constexpr int NTERM = F::kSplit ? 3 : 1;
-#pragma unroll
-                    for (int term = 0; term < NTERM; ++term)
-#pragma unroll
-                        for (int rb = 0; rb < kRowBlocks; ++rb)
-                            if (rb < t.nrb)
-#pragma unroll
-                                for (int p = 0; p < 2; ++p) {
-                                    const u32x4 x = (term == 2) ? al[rb] : ah[rb];
-                                    const u32x4 y = (term == 1) ? bl[p] : bh[p];
-                                    if (PREC == 2)
-                                        acc[p][rb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                                            __builtin_bit_cast(v8h, x), __builtin_bit_cast(v8h, y), acc[p][rb], 0, 0, 0);
-                                    else
-                                        acc[p][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                            __builtin_bit_cast(v8bf, x), __builtin_bit_cast(v8bf, y), acc[p][rb], 0, 0, 0);
-                                }
-                }
             }
             if (more) lstore(st ^ 1);
             __syncthreads();
@@ -531,6 +485,7 @@ struct Wide {
     static constexpr int OSTAGE = 2 * 2 * KB;           // float2: [key slot][class][bin]
 };
 
+static_assert(Wide<1>::KB == 32 && Wide<1>::NCH == 4 && Wide<1>::WR == 32, "the row tables' operand order (frag16)");
 static_assert(Wide<1>::TR == 16 * kDecodeSetRowBlocks[1] && Wide<3>::TR == 16 * kDecodeSetRowBlocks[2],
               "tile sets match the kernels");
 
@@ -569,15 +524,16 @@ __global__ __launch_bounds__(Wide<PREC>::NT, Wide<PREC>::OCC) void k_decode16(De
         // so the address space is stated for the compiler)
         const gmem<uint16_t>* ey_hi = as_global(static_cast<const uint16_t*>(a.ey));
         const gmem<uint16_t>* ey_lo = as_global(static_cast<const uint16_t*>(a.ey_lo));
-        const size_t pitch = 2 * (size_t)a.halfp;  // 16-bit elements per table row
         const int n = kb1 - kb0;
         // does this wave's 32-row block hold any row of the tile (wave-uniform)
         const int wv = __builtin_amdgcn_readfirstlane(wave);
         const bool active = t.nrb > 2 * wv;
 
-        // row operand address: row l32 of the wave's block, K offset 8*h within a 16-real chunk
+        // row operand: row l32 of the wave's block (clamped to the tile's last row), K offset 8*h
+        // within a 16-real chunk, in the table's operand order (chunk ch of step kb of the row's
+        // 32-row block is the 1 KB at (kb * NCH + ch) * 512 elements from the block's first)
         const int arow_idx = min(t.row0 + W::WR * wave + l32, t.row_end - 1);
-        const size_t arow = (size_t)arow_idx * pitch + 8 * h;
+        const size_t arow = ((size_t)(arow_idx >> 5) * ks * NCH * 64 + (arow_idx & 31) + 32 * h) * 8;
         // column operand sources: the x table per column; the memories of the (at most two)
         // tile columns of the slice are staged in LDS, two K steps ahead, by the first wave
         const gmem<f32x4>* ex_row[B_PER_T];
@@ -612,7 +568,7 @@ __global__ __launch_bounds__(Wide<PREC>::NT, Wide<PREC>::OCC) void k_decode16(De
             const int kb = kb0 + min(kk, n - 1);
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
-                const size_t off = arow + (size_t)kb * (2 * KB) + 16 * ch;
+                const size_t off = arow + ((size_t)kb * NCH + ch) * 512;
                 A[S][ch][0] = *reinterpret_cast<const gmem<u32x4>*>(ey_hi + off);
                 if (W::kSplit) A[S][ch][NS - 1] = *reinterpret_cast<const gmem<u32x4>*>(ey_lo + off);
             }
@@ -928,16 +884,16 @@ hipError_t launch_table_yz_split(const double* theta_xy, const double* theta_z, 
                                  const double* local_z, const int* row_map, int nrows, int ny, int half, int halfp,
                                  bool fp16, uint16_t* hi, uint16_t* lo, hipStream_t s) {
     if (nrows > 0)
-        hipLaunchKernelGGL(k_table_yz_16, dim3((unsigned)nrows), dim3(256), 0, s, theta_xy, theta_z, local_y, local_z,
-                           row_map, ny, half, halfp, fp16 ? 1 : 0, hi, lo);
+        hipLaunchKernelGGL(k_table_yz_16, dim3((unsigned)rows16(nrows)), dim3(256), 0, s, theta_xy, theta_z, local_y,
+                           local_z, row_map, nrows, ny, half, halfp, fp16 ? 1 : 0, hi, lo);
     return hipGetLastError();
 }
 
 hipError_t launch_table_split(const double* theta_rad, int axis, const double* local, int ncells,
                               int half, int halfp, bool fp16, void* hi, void* lo, hipStream_t s) {
-    hipLaunchKernelGGL(k_table_16, dim3((halfp + 255) / 256, ncells), dim3(256), 0, s, theta_rad,
-                       axis, local, half, halfp, fp16 ? 1 : 0, static_cast<uint16_t*>(hi),
-                       static_cast<uint16_t*>(lo));
+    if (ncells > 0)
+        hipLaunchKernelGGL(k_table_16, dim3((unsigned)rows16(ncells)), dim3(256), 0, s, theta_rad, axis, local,
+                           ncells, half, halfp, fp16 ? 1 : 0, static_cast<uint16_t*>(hi), static_cast<uint16_t*>(lo));
     return hipGetLastError();
 }
 
@@ -946,7 +902,7 @@ DecodePlan decode_plan(int precision, int ntiles, int halfp, int num_cus) {
     const int kb = precision == 0 ? 16 : 32;
     p.ksteps = halfp / kb;
     const long long total = (long long)ntiles * p.ksteps;
-    const int occ = precision == 0 ? kDecodeOccupancy<0> : Wide<1>::OCC;
+    const int occ = precision == 0 ? kDecodeOccupancy32 : Wide<1>::OCC;
     const int slots = occ * num_cus;
     const long long rounds = (ntiles + slots - 1) / slots;
     if (precision != 0 && ntiles >= slots && (double)ntiles >= 0.9 * (double)(rounds * slots)) {
@@ -1265,6 +1221,6 @@ size_t decode_partial_floats_max(int num_cus) {
 }
 
 int decode_slots16(int num_cus) { return Wide<1>::OCC * num_cus; }
-int decode_slots32(int num_cus) { return kDecodeOccupancy<0> * num_cus; }
+int decode_slots32(int num_cus) { return kDecodeOccupancy32 * num_cus; }
 
 }  // namespace vsaogm

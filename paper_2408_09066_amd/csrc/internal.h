@@ -305,14 +305,20 @@ hipError_t launch_bump_versions(unsigned* version, int nkeys, hipStream_t s);
 // half <= k < halfp; computed in double precision.  Stored as fp32 complex pairs.
 hipError_t launch_table_f32(const double* theta_rad, int axis, const double* local, int ncells,
                             int half, int halfp, float2* tab, hipStream_t s);
-// Same table split into bf16 (or fp16) hi and lo parts: [c][2*halfp] hi, then lo.
-// Joint (z, y) table of a volume, 16-bit [nrows][2 halfp] (+ residual when lo is given): row r is
-// the voxel plane offset row_map[r] = slice * ny + y.  theta_xy [half][2], theta_z [half][2] rad/m.
+// Same table split into bf16 (or fp16) hi and lo parts, hi and lo tables of rows16(ncells) x
+// 2*halfp elements each, in the matrix-core operand order of the 16-bit decode (decode.hip); the
+// rows past ncells are zero.
+// Joint (z, y) table of a volume, 16-bit, rows16(nrows) x 2 halfp (+ residual when lo is given),
+// same order: row r is the voxel plane offset row_map[r] = slice * ny + y.  theta_xy [half][2],
+// theta_z [half][2] rad/m.
 hipError_t launch_table_yz_split(const double* theta_xy, const double* theta_z, const double* local_y,
                                  const double* local_z, const int* row_map, int nrows, int ny, int half, int halfp,
                                  bool fp16, uint16_t* hi, uint16_t* lo, hipStream_t s);
 hipError_t launch_table_split(const double* theta_rad, int axis, const double* local, int ncells,
                               int half, int halfp, bool fp16, void* hi, void* lo, hipStream_t s);
+
+// Rows of a 16-bit row table of n rows (whole blocks of 32).
+__host__ __device__ constexpr int rows16(int n) { return (n + 31) / 32 * 32; }
 
 struct DUnit {
     int tile, kb0, kb1;

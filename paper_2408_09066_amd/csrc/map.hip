@@ -200,7 +200,7 @@ struct GridCache {
     DevUnits dunits[kDecodeTileSets];
     DevBuf<int> col_tx;              // [nx] tile column of every grid column
     DevBuf<float2> ex32, ey32;       // fp32 tables [n][halfp]
-    DevBuf<uint16_t> ey_bf, ey_bf_lo, ey_h;  // 16-bit y tables [ny][2*halfp], built on first use
+    DevBuf<uint16_t> ey_bf, ey_bf_lo, ey_h;  // 16-bit y tables (rows16(ny) x 2*halfp, operand order), built on first use
     // localized decoding state (planned on the device: IncPlan)
     std::vector<int> tcol;                   // tile column of every grid column
     std::vector<RegionBox> boxes;            // [tiles] cell range of every tile (row0 == row1: none)
@@ -335,7 +335,7 @@ struct Grid3Cache {
     DevBuf<float2> ex32;                       // [nx][halfp]
     int nrows = 0;                             // joint (z, y) rows = nz * ny
     DevBuf<int> row_map;                       // [nrows] voxel plane offset slice * ny + y
-    DevBuf<uint16_t> eyz_bf, eyz_bf_lo, eyz_h; // [nrows][2 halfp] joint (z, y) tables
+    DevBuf<uint16_t> eyz_bf, eyz_bf_lo, eyz_h; // joint (z, y) tables, rows16(nrows) x 2 halfp, operand order
 };
 
 struct vsaogm_volume {
@@ -516,7 +516,7 @@ GridCache* grid_cache(vsaogm_map* m, const vsaogm_grid_desc* g, hipStream_t s) {
 // The y table in the operand format of the requested precision (built on first use).
 const void* y_table(vsaogm_map* m, GridCache* gc, int precision, const void** lo, hipStream_t s) {
     *lo = nullptr;
-    const size_t n16 = (size_t)gc->ny * 2 * m->halfp;
+    const size_t n16 = (size_t)rows16(gc->ny) * 2 * m->halfp;
     switch (precision) {
         case VSAOGM_FP32:
             if (!gc->ey32.p) {
@@ -698,7 +698,7 @@ int64_t grid_bytes(const GridCache& g) {
 }
 
 // Bytes of a 16-bit y table or of an fp32 table of n cells.
-int64_t table16_bytes(const vsaogm_map* m, int n) { return (int64_t)n * 2 * m->halfp * 2; }
+int64_t table16_bytes(const vsaogm_map* m, int n) { return (int64_t)rows16(n) * 2 * m->halfp * 2; }
 int64_t table32_bytes(const vsaogm_map* m, int n) { return (int64_t)n * m->halfp * 8; }
 
 int64_t y_tables_bytes(const vsaogm_map* m, int ny, int precision) {
@@ -1569,7 +1569,7 @@ int vsaogm_volume_decode(vsaogm_volume* v, const vsaogm_grid3_desc* g, int32_t p
         DeviceGuard guard(v->device);
         hipStream_t s = (hipStream_t)stream;
         Grid3Cache* gc = grid3_cache(v, g, s);
-        const size_t n16 = (size_t)gc->nrows * 2 * v->halfp;
+        const size_t n16 = (size_t)rows16(gc->nrows) * 2 * v->halfp;
         const void* ey = nullptr;
         const void* ey_lo = nullptr;
         auto table = [&](DevBuf<uint16_t>& hi, DevBuf<uint16_t>* lo, bool fp16, const char* what) {
