@@ -199,8 +199,9 @@ def serving_benchmark(n_requests: int = 256, slots: int = 8, precision: str = "b
     execution slots and the bf16 hi+lo decode (fp32-level accuracy).  Both paths first run the
     whole stream WARM_PASSES times untimed, then TIMED_PASSES timed passes, of which the median
     is reported.  Throughput is measured with every request queued at once; latency percentiles
-    with Poisson arrivals at 0.5x, 1x and 2x the plain path's throughput (for the plain path
-    from its measured per-request service times, one queue)."""
+    with Poisson arrivals at 0.5x, 1x and 2x the plain path's throughput, measured on both paths
+    (the plain path serves the arrivals one at a time in arrival order, each as soon as it has
+    arrived and the previous one is done)."""
     import torch
     from paper_2408_09066_amd import native, synth
 
@@ -211,31 +212,29 @@ def serving_benchmark(n_requests: int = 256, slots: int = 8, precision: str = "b
     # ---- plain per-request path
     objs = [native.Map(m.theta, m.layout, m.tiles) for m in maps]
 
+    def plain_one(q):
+        spec, o = maps[q.map_id], objs[q.map_id]
+        xy = torch.from_numpy(q.xy).to(dev)
+        lb = torch.from_numpy(q.label).to(dev)
+        o.encode(xy, lb)
+        heat, hmax = o.decode(spec.grid, spec.side, spec.side, "fp32")
+        _, lab = native.classify(heat, hmax, R, R, 0.0)
+        out = lab.cpu().numpy()
+        torch.cuda.synchronize()
+        return out
+
     def plain_pass():
-        service, labels = [], []
         t_all = time.perf_counter()
-        for q in reqs:
-            spec, o = maps[q.map_id], objs[q.map_id]
-            t0 = time.perf_counter()
-            xy = torch.from_numpy(q.xy).to(dev)
-            lb = torch.from_numpy(q.label).to(dev)
-            o.encode(xy, lb)
-            heat, hmax = o.decode(spec.grid, spec.side, spec.side, "fp32")
-            _, lab = native.classify(heat, hmax, R, R, 0.0)
-            labels.append(lab.cpu().numpy())
-            torch.cuda.synchronize()
-            service.append(time.perf_counter() - t0)
-        return time.perf_counter() - t_all, service, labels
+        labels = [plain_one(q) for q in reqs]
+        return time.perf_counter() - t_all, labels
 
     for _ in range(WARM_PASSES):
         plain_pass()
     # median of the timed passes; memories accumulate pass after pass, so labels are compared
     # between the last passes of both paths (the same updates applied the same number of times)
     runs = [plain_pass() for _ in range(TIMED_PASSES)]
-    plain_total, service, _ = sorted(runs, key=lambda r: r[0])[TIMED_PASSES // 2]
-    plain_labels = runs[-1][2]
-    for o in objs:
-        o.close()
+    plain_total = sorted(r[0] for r in runs)[TIMED_PASSES // 2]
+    plain_labels = runs[-1][1]
     plain_ups = len(reqs) / plain_total
 
     # ---- request loop
@@ -275,10 +274,13 @@ def serving_benchmark(n_requests: int = 256, slots: int = 8, precision: str = "b
     for mult in (0.5, 1.0, 2.0):
         qps = mult * plain_ups
         arr = arrivals / qps
-        fin, last = [], 0.0
-        for a_, sv in zip(arr, service):
-            last = max(a_, last) + sv
-            fin.append(last - a_)
+        fin = []   # plain path, measured: arrival to labels on the host
+        t0 = time.perf_counter()
+        for q, a_ in zip(reqs, arr):
+            while time.perf_counter() - t0 < a_:
+                pass
+            plain_one(q)
+            fin.append(time.perf_counter() - t0 - a_)
         t0 = time.perf_counter()
         tk = []
         for q, a_ in zip(reqs, arr):
@@ -292,6 +294,8 @@ def serving_benchmark(n_requests: int = 256, slots: int = 8, precision: str = "b
                            "plain_ms": {"p50": percentile(fin, 50) * 1e3, "p99": percentile(fin, 99) * 1e3}}
     stats = srv.stats()
     srv.close()
+    for o in objs:
+        o.close()
     return {
         "workload": (f"{len(reqs)} updates of {len(maps)} maps: D in {{2048,4096,8192}}, 1-16 tiles, "
                      f"grid sides {min(m.side for m in maps)}-{max(m.side for m in maps)} at 0.05 m, "
