@@ -18,6 +18,7 @@
  *                    probabilistic signed difference (eq. psd) and the
  *                    threshold rho (eq. classification).
  *   vsaogm_fuse      Sec. III-B "Multi-Map Fusion" (Algorithm 3).
+ *   vsaogm_fuse_many the same for N agents in one pass.
  *   vsaogm_submit /  a request loop that runs whole map updates
  *   vsaogm_poll      (encode + decode + classify) for many maps at once.
  *
@@ -227,6 +228,16 @@ int vsaogm_memories(const vsaogm_map* map, float* out, vsaogm_stream stream);
  * into concurrently.
  */
 int vsaogm_fuse(vsaogm_map* dst, const vsaogm_map* src, vsaogm_stream stream);
+
+/*
+ * Algorithm 3 for N agents: dst's memories += srcs[0]'s + ... + srcs[n-1]'s, key by key,
+ * added in source order in one pass over dst (one launch per 16 sources), so the result is
+ * bit-identical to n vsaogm_fuse calls in that order.  srcs: host array of n map handles
+ * (n >= 0; n = 0 leaves dst unchanged); every source must satisfy vsaogm_fuse's conditions
+ * against dst (EINVAL otherwise, nothing launched); a source may appear more than once, dst
+ * not at all.  Async on stream; the sources must not be encoded into concurrently.
+ */
+int vsaogm_fuse_many(vsaogm_map* dst, const vsaogm_map* const* srcs, int32_t n, vsaogm_stream stream);
 
 /* ---------------------------------------------------------------------------
  * Serving: a request loop for map updates of many maps.

@@ -399,6 +399,22 @@ __global__ __launch_bounds__(256) void k_add(float2* __restrict__ dst,
     }
 }
 
+// Algorithm 3 over several agents in one pass: dst[i] += src[0][i], then src[1][i], ... in
+// source order, the additions (and so the rounding) of that many pairwise k_add launches.
+struct FuseSources {
+    const float2* p[kFuseSources];
+};
+__global__ __launch_bounds__(256) void k_add_many(float2* __restrict__ dst, FuseSources src, int nsrc, size_t n) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float2 a = dst[i];
+    for (int j = 0; j < nsrc; ++j) {
+        const float2 b = as_global(src.p[j])[i];
+        a = make_float2(a.x + b.x, a.y + b.y);
+    }
+    dst[i] = a;
+}
+
 int bits_for(int v) {
     int b = 0;
     while ((1 << b) <= v) ++b;
@@ -568,6 +584,17 @@ hipError_t launch_memories_export(const float2* omega, const double* theta_rad, 
 
 hipError_t launch_bump_versions(unsigned* version, int nkeys, hipStream_t s) {
     hipLaunchKernelGGL(k_bump, dim3((nkeys + 255) / 256), dim3(256), 0, s, version, nkeys);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_many(float2* dst, const float2* const* srcs, int nsrc, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    for (int j0 = 0; j0 < nsrc; j0 += kFuseSources) {   // chunks in source order
+        FuseSources f{};
+        const int m = std::min(kFuseSources, nsrc - j0);
+        for (int j = 0; j < m; ++j) f.p[j] = srcs[j0 + j];
+        hipLaunchKernelGGL(k_add_many, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, f, m, n);
+    }
     return hipGetLastError();
 }
 

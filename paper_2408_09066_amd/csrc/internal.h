@@ -298,6 +298,10 @@ hipError_t launch_memories_export(const float2* omega, const double* theta_rad, 
                                   int nkeys, int half, int halfp, float* out, hipStream_t s);
 
 hipError_t launch_add(float2* dst, const float2* src, size_t n, hipStream_t s);
+// dst[i] += srcs[0][i] + ... in source order (as nsrc pairwise launch_add calls would add), one
+// launch per kFuseSources sources.
+constexpr int kFuseSources = 16;
+hipError_t launch_add_many(float2* dst, const float2* const* srcs, int nsrc, size_t n, hipStream_t s);
 hipError_t launch_bump_versions(unsigned* version, int nkeys, hipStream_t s);
 
 // ---- decode (decode.hip) -----------------------------------------------------------

@@ -1393,6 +1393,30 @@ int vsaogm_fuse(vsaogm_map* dst, const vsaogm_map* src, vsaogm_stream stream) {
     });
 }
 
+int vsaogm_fuse_many(vsaogm_map* dst, const vsaogm_map* const* srcs, int32_t n, vsaogm_stream stream) {
+    return guarded([&] {
+        if (!dst) fail(VSAOGM_EINVAL, "dst must not be NULL");
+        if (n < 0 || (n > 0 && !srcs)) fail(VSAOGM_EINVAL, "srcs must hold n >= 0 maps");
+        std::vector<const float2*> p((size_t)n);
+        for (int j = 0; j < n; ++j) {
+            const vsaogm_map* src = srcs[j];
+            if (!src) fail(VSAOGM_EINVAL, "a source map is NULL");
+            if (src == dst) fail(VSAOGM_EINVAL, "cannot fuse a map into itself");
+            if (dst->device != src->device) fail(VSAOGM_EINVAL, "maps live on different devices");
+            if (dst->D != src->D || dst->theta != src->theta)
+                fail(VSAOGM_EINVAL, "maps must share the axis vectors (same Theta)");
+            if (dst->tiles_x != src->tiles_x || dst->tiles_y != src->tiles_y || dst->x0 != src->x0 ||
+                dst->y0 != src->y0 || dst->x1 != src->x1 || dst->y1 != src->y1)
+                fail(VSAOGM_EINVAL, "maps must share the tiling of the global frame");
+            p[(size_t)j] = src->d_omega.p;
+        }
+        if (n == 0) return;
+        DeviceGuard guard(dst->device);
+        hip_check(launch_add_many(dst->d_omega.p, p.data(), n, dst->d_omega.n, (hipStream_t)stream), "fuse launch");
+        hip_check(launch_bump_versions(dst->d_version.p, dst->nkeys, (hipStream_t)stream), "versions");
+    });
+}
+
 int vsaogm_profile_events(int32_t stage, void* begin_event, void* end_event) {
     return guarded([&] {
         if (stage < 0 || stage >= kNumStages) fail(VSAOGM_EINVAL, "unknown stage");

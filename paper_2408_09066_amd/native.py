@@ -21,7 +21,7 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16x3": 3}
 EXPORTED = [
     "vsaogm_version", "vsaogm_last_error", "vsaogm_map_create", "vsaogm_map_destroy",
     "vsaogm_map_info", "vsaogm_map_reset", "vsaogm_encode", "vsaogm_map_take_rejected",
-    "vsaogm_decode", "vsaogm_classify", "vsaogm_memories", "vsaogm_fuse",
+    "vsaogm_decode", "vsaogm_classify", "vsaogm_memories", "vsaogm_fuse", "vsaogm_fuse_many",
     "vsaogm_profile_events", "vsaogm_server_create", "vsaogm_server_destroy",
     "vsaogm_server_add_map", "vsaogm_server_get_map", "vsaogm_submit", "vsaogm_poll",
     "vsaogm_wait", "vsaogm_server_drain", "vsaogm_server_stats", "vsaogm_server_memory", "vsaogm_submit_many",
@@ -129,6 +129,7 @@ def load(path: str = LIB_PATH):
     L.vsaogm_classify_ex.argtypes = [ctypes.POINTER(GridDesc), P, P, i32, i32, f32, i32, i32, i32,
                                      P, P, i32, P]
     L.vsaogm_fuse.argtypes = [P, P, P]
+    L.vsaogm_fuse_many.argtypes = [P, ctypes.POINTER(P), ctypes.c_int32, P]
     L.vsaogm_profile_events.argtypes = [i32, P, P]
     L.vsaogm_server_create.argtypes = [ctypes.POINTER(ServerDesc), ctypes.POINTER(P)]
     L.vsaogm_server_destroy.argtypes = [P]
@@ -279,6 +280,10 @@ class Map:
 
     def fuse_from(self, other: "Map", stream=None):
         check(load().vsaogm_fuse(self._h, other._h, _stream(stream)))
+
+    def fuse_many(self, others: Sequence["Map"], stream=None):
+        hs = (ctypes.c_void_p * max(len(others), 1))(*[o._h for o in others])
+        check(load().vsaogm_fuse_many(self._h, hs, len(others), _stream(stream)))
 
 
 def classify(heat, hmax, r_occ: int, r_emp: int, rho: float = 0.0, ogm=None, label=None,

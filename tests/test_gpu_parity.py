@@ -188,6 +188,63 @@ def test_fusion_is_union(torch_cuda):
         mm.close()
 
 
+def test_fusion_many_agents(torch_cuda):
+    """Algorithm 3 over N agents in one pass: the same bits as N pairwise fusions in that order,
+    the union's memories against the oracle, more than one launch's worth of sources, a repeated
+    source, no sources, and refused sources leaving the destination untouched."""
+    say("[gpu] fusion of N agents mini4x4")
+    from paper_2408_09066_amd import native
+    torch = torch_cuda
+    w, (om, P, m, H, ogm, lab) = oracle_result("mini4x4")
+    xy = torch.from_numpy(w.xy).cuda()
+    lb = torch.from_numpy(w.label).cuda()
+    n = xy.shape[0]
+    cuts = [0, n // 5, 2 * n // 5, 3 * n // 5, 4 * n // 5, n]
+    agents = []
+    for i in range(5):
+        a = native.Map(w.theta, w.layout, w.tiles)
+        a.encode(xy[cuts[i]:cuts[i + 1]].contiguous(), lb[cuts[i]:cuts[i + 1]].contiguous())
+        agents.append(a)
+    seq = native.Map(w.theta, w.layout, w.tiles)
+    many = native.Map(w.theta, w.layout, w.tiles)
+    for a in agents:
+        seq.fuse_from(a)
+    many.fuse_many(agents)
+    m_seq, m_many = seq.memories().cpu().numpy(), many.memories().cpu().numpy()
+    assert np.array_equal(m_seq.view(np.uint32), m_many.view(np.uint32))
+    half = w.D // 2
+    got = m_many.astype(np.float64)
+    for key in range(om.shape[0]):
+        assert rel_l2(got[key], om[key, :half + 1, :]) <= MEM_TOL, key
+    heat, _ = many.decode(w.grid, w.nx, w.ny)
+    torch.cuda.synchronize()
+    for psi in range(2):
+        assert rel_l2(heat.cpu().numpy().astype(np.float64)[psi], P[psi]) <= HEAT_TOL
+    # 17 sources (two launches, a repeated source) and no sources
+    seq.reset()
+    many.reset()
+    srcs = [agents[i % 5] for i in range(17)]
+    for a in srcs:
+        seq.fuse_from(a)
+    many.fuse_many(srcs)
+    many.fuse_many([])
+    m_seq, m_many = seq.memories().cpu().numpy(), many.memories().cpu().numpy()
+    assert np.array_equal(m_seq.view(np.uint32), m_many.view(np.uint32))
+    # refused: the destination among the sources, a different Theta; nothing is added
+    bad_theta = w.theta.copy()
+    bad_theta[1] *= 1.0000001
+    bad_theta[-1] = -bad_theta[1]
+    c = native.Map(bad_theta, w.layout, w.tiles)
+    with pytest.raises(native.VsaogmError):
+        many.fuse_many([agents[0], many])
+    with pytest.raises(native.VsaogmError):
+        many.fuse_many([agents[0], c])
+    after = many.memories().cpu().numpy()
+    assert np.array_equal(after.view(np.uint32), m_many.view(np.uint32))
+    for mm in agents + [seq, many, c]:
+        mm.close()
+
+
 def test_edge_cases(torch_cuda):
     say("[gpu] edge cases")
     from paper_2408_09066_amd import native
