@@ -46,11 +46,13 @@ __device__ inline float disk_sum_fast(int r, const float* centre, int W) {
 }
 
 // Pre-softmax value of one cell of one class (decoding of Sec. III-B and its ablation of
-// Sec. IV-B): q = P (/ max P if normalising) (squared if squaring), then -q ln q (entropy, to be
-// summed over the disk; 0 for q <= 0) or the per-cell activation ReLU / tanh / sigmoid.
-__device__ inline float cell_value(float p, float m, int normalize, int square, int act) {
+// Sec. IV-B): q = P (/ max P if normalising, as P times the block's reciprocal inv_m of the class
+// maximum, 0 when the maximum is not positive) (squared if squaring), then -q ln q (entropy, to
+// be summed over the disk; 0 for q <= 0) or the per-cell activation ReLU / tanh / sigmoid.
+__device__ inline float recip_max(float m) { return (m > 0.f) ? 1.f / m : 0.f; }
+__device__ inline float cell_value(float p, float inv_m, int normalize, int square, int act) {
     float q = p;
-    if (normalize) q = (m > 0.f) ? p / m : 0.f;
+    if (normalize) q = p * inv_m;
     if (square) q = q * q;
     switch (act) {
         case 0: return (q > 0.f) ? -q * __logf(q) : 0.f;
@@ -85,6 +87,7 @@ __device__ __attribute__((always_inline)) inline void classify_body(const float*
         half_w[p][dy + kMaxRadius] = w;
     }
     const size_t plane = (size_t)nx * ny;
+    const float inv0 = recip_max(m0), inv1 = recip_max(m1);
     // the block's cells and halo, both classes, kLoadBatch loads in flight per thread; element
     // idx = class * W * H + yy * W + xx, walked in steps of 256 without integer division (one
     // per thread to start; W >= 32 and H >= 16, so a step moves at most 8 rows and wraps the
@@ -120,7 +123,7 @@ __device__ __attribute__((always_inline)) inline void classify_body(const float*
 #pragma unroll
         for (int u = 0; u < kLoadBatch; ++u) {
             const int idx = base + u * 256 + threadIdx.x;
-            if (idx < total) sg[idx] = in[u] ? cell_value(raw[u], cls[u] ? m1 : m0, normalize, square, act) : 0.f;
+            if (idx < total) sg[idx] = in[u] ? cell_value(raw[u], cls[u] ? inv1 : inv0, normalize, square, act) : 0.f;
         }
     }
     __syncthreads();
