@@ -371,9 +371,9 @@ __global__ __launch_bounds__(256, kDecodeOccupancy32) void k_decode(DecodeArgs a
                     const f32x4 o = ro[u][p];
                     // (o.x + i o.y)(e.x + i e.y) -> (Re, -Im)
                     const float r0 = __builtin_fmaf(o.x, e.x, -o.y * e.y);
-                    const float r1 = -__builtin_fmaf(o.x, e.y, o.y * e.x);
+                    const float r1 = __builtin_fmaf(-o.x, e.y, -o.y * e.x);   // -(o.x e.y + o.y e.x), same bits
                     const float r2 = __builtin_fmaf(o.z, e.z, -o.w * e.w);
-                    const float r3 = -__builtin_fmaf(o.z, e.w, o.w * e.z);
+                    const float r3 = __builtin_fmaf(-o.z, e.w, -o.w * e.z);
                     unsigned char* dst = Bs + (p * kTileCols + c) * kRowPitchBytes;
                     *reinterpret_cast<f32x4*>(dst + 16 * part) = f32x4{r0, r1, r2, r3};
                 }
@@ -590,9 +590,9 @@ __global__ __launch_bounds__(Wide<PREC>::NT, Wide<PREC>::OCC) void k_decode16(De
                 for (int p = 0; p < 2; ++p) {
                     const f32x4 o = *reinterpret_cast<const f32x4*>(&om_lds[st][(oslot[u] * 2 + p) * KB + 2 * part]);
                     const float r0 = __builtin_fmaf(o.x, e.x, -o.y * e.y);
-                    const float r1 = -__builtin_fmaf(o.x, e.y, o.y * e.x);
+                    const float r1 = __builtin_fmaf(-o.x, e.y, -o.y * e.x);   // -(o.x e.y + o.y e.x), same bits
                     const float r2 = __builtin_fmaf(o.z, e.z, -o.w * e.w);
-                    const float r3 = -__builtin_fmaf(o.z, e.w, o.w * e.z);
+                    const float r3 = __builtin_fmaf(-o.z, e.w, -o.w * e.z);
                     unsigned char* dst = Bs + (p * kTileCols + c) * kRowPitchBytes + 8 * part;
                     if (PREC == 2) {
                         *reinterpret_cast<u32x2*>(dst) = u32x2{pack_f16(r0, r1), pack_f16(r2, r3)};
