@@ -245,6 +245,40 @@ def test_fusion_many_agents(torch_cuda):
         mm.close()
 
 
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16", "fp16"])
+def test_small_and_ragged_grids_16bit(torch_cuda, precision):
+    """The 16-bit row tables are stored in blocks of 32 rows: grids whose row count is not a
+    multiple of 32, whose tile bands start inside a block, a single cell, and a grid narrower
+    than one column slice, each against the oracle's similarity of the same memories."""
+    say(f"[gpu] small and ragged grids {precision}")
+    from paper_2408_09066_amd import native
+    torch = torch_cuda
+    w, (om, P, m, H, ogm, lab) = oracle_result("mini4x4")
+    mp = native.Map(w.theta, w.layout, w.tiles)
+    mp.encode(torch.from_numpy(w.xy).cuda(), torch.from_numpy(w.label).cuda())
+    x0, y0, res = w.grid
+    cases = [((x0, y0, res), 1, 1), ((x0 + 0.35, y0 + 0.95, res), 3, 5),
+             ((x0 + 1.05, y0 + 2.15, res), 70, 33), ((x0 + 0.25, y0 + 0.45, res), 65, 97),
+             ((x0, y0 + 0.05, 0.17), 41, 93)]
+    # every cell within tol of the map's peak magnitude; the map-level relative L2 bar where a
+    # grid has enough cells for it to mean one (for a single cell it is that cell's relative error)
+    tol = LOOSE_TOL.get(precision, HEAT_TOL)
+    peak = [float(np.max(np.abs(P[psi]))) for psi in range(2)]
+    for grid, nx, ny in cases:
+        heat, hmax = mp.decode(grid, nx, ny, precision)
+        torch.cuda.synchronize()
+        ref = oracle.similarity(w.theta, w.layout, w.tiles, om, grid, nx, ny)
+        got = heat.cpu().numpy().astype(np.float64)
+        for psi in range(2):
+            mab = float(np.max(np.abs(got[psi] - ref[psi])))
+            assert mab <= tol * peak[psi], (grid, nx, ny, psi, mab)
+            if nx * ny >= 256:
+                e = rel_l2(got[psi], ref[psi])
+                assert e <= tol, (grid, nx, ny, psi, e)
+            assert hmax.cpu().numpy()[psi] == np.max(got[psi])
+    mp.close()
+
+
 def test_edge_cases(torch_cuda):
     say("[gpu] edge cases")
     from paper_2408_09066_amd import native
