@@ -226,3 +226,34 @@ def test_volume_fullsize_sampled(torch_cuda):
         e = np.linalg.norm(g - P[p]) / np.linalg.norm(P[p])
         say(f"[gpu] hall3d tile {tile} heat[{p}] sampled rel-L2 {e:.3e}")
         assert e <= 1e-4
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16", "fp16"])
+def test_volume_ragged_grids(torch_cuda, precision):
+    """The joint (z, y) row table is stored in blocks of 32 rows: volumes whose joint row count
+    is not a multiple of 32 and whose (z, y) bands start inside a block, and a single voxel,
+    each against the oracle's similarity of the same memories (every voxel within the format's
+    bar of the volume's peak magnitude; relative L2 where the grid has at least 256 voxels)."""
+    from paper_2408_09066_amd import native
+    torch = torch_cuda
+    v, (om, P, m, H, ogm, lab) = oracle_volume("room3d_222")
+    vol = native.Volume(v.theta, v.layout, v.tiles)
+    vol.encode(torch.from_numpy(v.xyz).cuda(), torch.from_numpy(v.label).cuda())
+    x0, y0, z0, res = v.grid
+    cases = [((x0 + 0.013, y0 + 0.031, z0 + 0.017, res), 13, 21, 5),
+             ((x0 + 0.11, y0 + 0.07, z0 + 0.05, 0.9 * res), 29, 7, 11),
+             ((x0, y0, z0, res), 1, 1, 1)]
+    peak = [float(np.max(np.abs(P[psi]))) for psi in range(2)]
+    for grid, nx, ny, nz in cases:
+        heat, hmax = vol.decode(grid, nx, ny, nz, precision)
+        torch.cuda.synchronize()
+        ref = oracle.similarity3(v.theta, v.layout, v.tiles, om, grid, nx, ny, nz)
+        got = heat.cpu().numpy().astype(np.float64)
+        for psi in range(2):
+            mab = float(np.max(np.abs(got[psi] - ref[psi])))
+            say(f"[gpu] volume grid {nx}x{ny}x{nz} {precision} heat[{psi}] max-abs {mab:.2e}")
+            assert mab <= TOL[precision] * peak[psi], (grid, psi, mab)
+            if nx * ny * nz >= 256:
+                assert np.linalg.norm(got[psi] - ref[psi]) / np.linalg.norm(ref[psi]) <= TOL[precision]
+            assert hmax.cpu().numpy()[psi] == np.max(got[psi])
+    vol.close()
