@@ -91,52 +91,80 @@ __device__ inline uint16_t f16_bits(float f) {
     return __builtin_bit_cast(uint16_t, h);
 }
 
-// (re, im) of one bin into a 16-bit table at element o (re) and o + 1 (im); lo, if given, takes
-// the rounding residuals (split form).
-__device__ inline void store16(const double (&v)[2], size_t o, int fp16, uint16_t* __restrict__ hi,
-                               uint16_t* __restrict__ lo) {
-    for (int q = 0; q < 2; ++q) {
-        if (fp16) {
-            const uint16_t h = f16_bits((float)v[q]);
-            hi[o + q] = h;
-            if (lo) lo[o + q] = f16_bits((float)(v[q] - (double)__builtin_bit_cast(_Float16, h)));
-        } else {
-            const uint16_t h = bf16_bits((float)v[q]);
-            hi[o + q] = h;
-            if (lo) lo[o + q] = bf16_bits((float)(v[q] - (double)bf16_value(h)));
-        }
-    }
-}
-
 // 16-bit row tables are stored in the operand order of v_mfma_f32_32x32x16: rows in blocks of
 // 32, and for every block, K step (32 bins = 64 reals, re and im interleaved) and 16-real chunk of
 // the step, one contiguous 1 KB fragment whose 16-byte piece l holds reals 8 (l / 32) .. + 7 of
 // the chunk for row l % 32 of the block.  A wavefront's operand load is then 1 KB of consecutive
-// bytes (a row-major table would touch 32 lines and use 32 bytes of each).  Element e of row r:
-__device__ inline size_t frag16(int r, int e, int ksteps) {
-    const int b = r >> 5, rr = r & 31;
-    const int kb = e >> 6, ch = (e >> 4) & 3, h = (e >> 3) & 1, j = e & 7;
-    return ((((size_t)b * ksteps + kb) * 4 + ch) * 64 + rr + 32 * h) * 8 + j;
+// bytes (a row-major table would touch 32 lines and use 32 bytes of each).  Element e of row r
+// (K step kb = e / 64, chunk ch = (e / 16) % 4, half h = (e / 8) % 2, j = e % 8) sits at
+//   (((r / 32) * ksteps + kb) * 4 + ch) * 512 + ((r % 32) + 32 h) * 8 + j.
+
+// Eight table values (four bins, re and im) of one lane's 16-byte piece, rounded to the 16-bit
+// format (hi) and, for the split form, the rounding residuals (lo).
+__device__ inline void pack16x8(const double (&v)[8], int fp16, uint32_t (&h)[4], uint32_t (&l)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint16_t hb[2], lb[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const double x = v[2 * q + u];
+            if (fp16) {
+                hb[u] = f16_bits((float)x);
+                lb[u] = f16_bits((float)(x - (double)__builtin_bit_cast(_Float16, hb[u])));
+            } else {
+                hb[u] = bf16_bits((float)x);
+                lb[u] = bf16_bits((float)(x - (double)bf16_value(hb[u])));
+            }
+        }
+        h[q] = (uint32_t)hb[0] | ((uint32_t)hb[1] << 16);
+        l[q] = (uint32_t)lb[0] | ((uint32_t)lb[1] << 16);
+    }
+}
+
+// Block (K step kb, 32-row block b) of a 16-bit table: thread t writes lane t % 64 of chunk t / 64,
+// i.e. bins kb*32 + 8*(t/64) + 4*h .. + 3 of row 32*b + l % 32 (h = l / 32), as one 16-byte store,
+// so each wavefront writes one whole 1 KB fragment.
+struct Frag16Lane {
+    int r, k0;
+    size_t off;   // element offset of the lane's 16-byte piece
+};
+__device__ inline Frag16Lane frag16_lane(int ks) {
+    const int kb = blockIdx.x, b = blockIdx.y, ch = threadIdx.x >> 6, l = threadIdx.x & 63;
+    Frag16Lane f;
+    f.r = 32 * b + (l & 31);
+    f.k0 = kb * 32 + 8 * ch + 4 * (l >> 5);
+    f.off = (((size_t)b * ks + kb) * 4 + ch) * 512 + (size_t)l * 8;
+    return f;
+}
+__device__ inline void store16x8(const double (&v)[8], size_t off, int fp16, uint16_t* __restrict__ hi,
+                                 uint16_t* __restrict__ lo) {
+    uint32_t h[4], l[4];
+    pack16x8(v, fp16, h, l);
+    *reinterpret_cast<uint4*>(hi + off) = make_uint4(h[0], h[1], h[2], h[3]);
+    if (lo) *reinterpret_cast<uint4*>(lo + off) = make_uint4(l[0], l[1], l[2], l[3]);
 }
 
 // 16-bit tables of nrows rows (re, im per bin, in the order above); lo holds the rounding
-// residual (split form).  One block per row of the table, which has rows16(nrows) rows: the
-// rows past nrows are zero.
+// residual (split form).  Grid (K steps, rows16(nrows) / 32); rows past nrows are zero.
 __global__ __launch_bounds__(256) void k_table_16(const double* __restrict__ theta_rad, int axis,
                                                   const double* __restrict__ local, int nrows, int half,
                                                   int halfp, int fp16, uint16_t* __restrict__ hi,
                                                   uint16_t* __restrict__ lo) {
-    const int r = blockIdx.x, ks = halfp / 32;
-    for (int k = threadIdx.x; k < halfp; k += 256) {
-        double v[2] = {0.0, 0.0};
-        if (r < nrows && k < half) sincos(theta_rad[2 * k + axis] * local[r], &v[1], &v[0]);
-        store16(v, frag16(r, 2 * k, ks), fp16, hi, lo);
+    const Frag16Lane f = frag16_lane(halfp / 32);
+    double v[8];
+    const double c = f.r < nrows ? local[f.r] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int k = f.k0 + i;
+        v[2 * i] = v[2 * i + 1] = 0.0;
+        if (f.r < nrows && k < half) sincos(theta_rad[2 * k + axis] * c, &v[2 * i + 1], &v[2 * i]);
     }
+    store16x8(v, f.off, fp16, hi, lo);
 }
 
-// Joint (z, y) rows of a volume, one block per row r of the row space: voxel plane offset
-// row_map[r] = slice * ny + y, spectrum exp(i (Theta_y[k] y + Theta_z[k] z)) with the phase
-// formed in double precision from the tile-local coordinates.  Same order and padding as above.
+// Joint (z, y) rows of a volume, row r of the row space being voxel plane offset
+// row_map[r] = slice * ny + y: spectrum exp(i (Theta_y[k] y + Theta_z[k] z)) with the phase
+// formed in double precision from the tile-local coordinates.  Same order, grid and padding.
 __global__ __launch_bounds__(256) void k_table_yz_16(const double* __restrict__ theta_xy,
                                                      const double* __restrict__ theta_z,
                                                      const double* __restrict__ local_y,
@@ -144,18 +172,21 @@ __global__ __launch_bounds__(256) void k_table_yz_16(const double* __restrict__ 
                                                      const int* __restrict__ row_map, int nrows, int ny,
                                                      int half, int halfp, int fp16, uint16_t* __restrict__ hi,
                                                      uint16_t* __restrict__ lo) {
-    const int r = blockIdx.x, ks = halfp / 32;
+    const Frag16Lane f = frag16_lane(halfp / 32);
     double y = 0.0, z = 0.0;
-    if (r < nrows) {
-        const int rm = row_map[r];
+    if (f.r < nrows) {
+        const int rm = row_map[f.r];
         y = local_y[rm % ny];
         z = local_z[rm / ny];
     }
-    for (int k = threadIdx.x; k < halfp; k += 256) {
-        double v[2] = {0.0, 0.0};
-        if (r < nrows && k < half) sincos(theta_xy[2 * k + 1] * y + theta_z[2 * k] * z, &v[1], &v[0]);
-        store16(v, frag16(r, 2 * k, ks), fp16, hi, lo);
+    double v[8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int k = f.k0 + i;
+        v[2 * i] = v[2 * i + 1] = 0.0;
+        if (f.r < nrows && k < half) sincos(theta_xy[2 * k + 1] * y + theta_z[2 * k] * z, &v[2 * i + 1], &v[2 * i]);
     }
+    store16x8(v, f.off, fp16, hi, lo);
 }
 
 // Logical index of workgroup b of n when consecutive hardware indices land on different XCDs
@@ -485,7 +516,7 @@ struct Wide {
     static constexpr int OSTAGE = 2 * 2 * KB;           // float2: [key slot][class][bin]
 };
 
-static_assert(Wide<1>::KB == 32 && Wide<1>::NCH == 4 && Wide<1>::WR == 32, "the row tables' operand order (frag16)");
+static_assert(Wide<1>::KB == 32 && Wide<1>::NCH == 4 && Wide<1>::WR == 32, "the row tables' operand order (k_table_16)");
 static_assert(Wide<1>::TR == 16 * kDecodeSetRowBlocks[1] && Wide<3>::TR == 16 * kDecodeSetRowBlocks[2],
               "tile sets match the kernels");
 
@@ -884,16 +915,17 @@ hipError_t launch_table_yz_split(const double* theta_xy, const double* theta_z, 
                                  const double* local_z, const int* row_map, int nrows, int ny, int half, int halfp,
                                  bool fp16, uint16_t* hi, uint16_t* lo, hipStream_t s) {
     if (nrows > 0)
-        hipLaunchKernelGGL(k_table_yz_16, dim3((unsigned)rows16(nrows)), dim3(256), 0, s, theta_xy, theta_z, local_y,
-                           local_z, row_map, nrows, ny, half, halfp, fp16 ? 1 : 0, hi, lo);
+        hipLaunchKernelGGL(k_table_yz_16, dim3((unsigned)(halfp / 32), (unsigned)(rows16(nrows) / 32)), dim3(256), 0, s,
+                           theta_xy, theta_z, local_y, local_z, row_map, nrows, ny, half, halfp, fp16 ? 1 : 0, hi, lo);
     return hipGetLastError();
 }
 
 hipError_t launch_table_split(const double* theta_rad, int axis, const double* local, int ncells,
                               int half, int halfp, bool fp16, void* hi, void* lo, hipStream_t s) {
     if (ncells > 0)
-        hipLaunchKernelGGL(k_table_16, dim3((unsigned)rows16(ncells)), dim3(256), 0, s, theta_rad, axis, local,
-                           ncells, half, halfp, fp16 ? 1 : 0, static_cast<uint16_t*>(hi), static_cast<uint16_t*>(lo));
+        hipLaunchKernelGGL(k_table_16, dim3((unsigned)(halfp / 32), (unsigned)(rows16(ncells) / 32)), dim3(256), 0, s,
+                           theta_rad, axis, local, ncells, half, halfp, fp16 ? 1 : 0, static_cast<uint16_t*>(hi),
+                           static_cast<uint16_t*>(lo));
     return hipGetLastError();
 }
 
