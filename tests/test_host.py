@@ -90,6 +90,14 @@ def test_calls_on_null_handles_return_einval(lib):
     assert L.vsaogm_volume_encode(None, None, None, 5, None) == native.EINVAL
     assert L.vsaogm_volume_reset(None, None) == native.EINVAL
     assert L.vsaogm_fuse(None, None, None) == native.EINVAL
+    assert L.vsaogm_fuse_many(None, None, 0, None) == native.EINVAL
+    srcs = (ctypes.c_void_p * 2)(None, None)
+    # a non-null handle is never dereferenced before its arguments are checked: n < 0, a missing
+    # source array and a null source are refused first
+    fake = ctypes.c_void_p(1)
+    assert L.vsaogm_fuse_many(fake, None, -1, None) == native.EINVAL
+    assert L.vsaogm_fuse_many(fake, None, 2, None) == native.EINVAL
+    assert L.vsaogm_fuse_many(fake, srcs, 2, None) == native.EINVAL
     assert L.vsaogm_classify(None, None, None, 1, 1, 0.0, None, None, 0, None) == native.EINVAL
     assert L.vsaogm_classify3(None, None, None, 1, 1, 0.0, None, None, 0, None) == native.EINVAL
     assert L.vsaogm_last_error()
